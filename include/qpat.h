@@ -1,0 +1,196 @@
+/*
+ * qpat.h - C ABI of the MI355X k-space acoustic operator library (libqpat.so).
+ *
+ * The library computes the discrete acoustic forward operator H_a of
+ * Javaherian & Holman, "Direct quantitative photoacoustic tomography for
+ * realistic acoustic media" (arXiv 1810.11685), Section 3.3.3 and Definition 4
+ * (k-space PSTD solve of eqs num-vel, num-rho, num-p, num-m with the two-step
+ * additive source of eq s1), and its discretise-then-adjoint H_a^* (Section
+ * 3.3.4, Lemma 2), on a 2-D grid, in FP32, with hand-written HIP kernels for
+ * gfx950.
+ *
+ * Conventions shared by every entry point
+ *  - Fields are row-major [ny][nx] float arrays, x fastest.  Node (j, i) sits at
+ *    x = (i - nx/2) dx, y = (j - ny/2) dy (centre node at the origin).
+ *  - Sensor data are time-major [nt][ns] (Definition 4): row m holds
+ *    P_m = M p_m, m = 0 .. nt-1.
+ *  - A batch of B vectors of the same plan is laid out contiguously:
+ *    fields [B][ny][nx], data [B][nt][ns].
+ *  - Device pointers are HIP device memory owned by the caller; the library
+ *    never frees them.  Host pointers are read during the call only.
+ *  - `stream` is a hipStream_t (NULL = default stream).  Calls enqueue work on
+ *    it and return without waiting for the device; no hidden device-wide
+ *    synchronisation.  A plan is not re-entrant: calls that use one plan from
+ *    several streams at once race on its work buffers.
+ *  - Every call returns a qpat_status.  Argument checks happen on the host
+ *    before any device work; a failing check enqueues nothing.  The message of
+ *    the last failure of the calling thread is in qpat_last_error().
+ *  - Readings of points the paper leaves open (PML profile, staggered density,
+ *    sensor interpolation, Nyquist bin, sinc convention, alpha0 units) are
+ *    listed with the parameters below.
+ */
+#ifndef QPAT_H
+#define QPAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  QPAT_OK = 0,
+  QPAT_E_INVALID = 1,     /* bad argument (null pointer, bad size, non-positive medium, ...) */
+  QPAT_E_UNSUPPORTED = 2, /* grid size not 2^a or 3*2^a in [8, 2048], y odd with loss, mixed batch */
+  QPAT_E_UNSTABLE = 3,    /* dt above the k-space stability bound for c_ref < max(c0) */
+  QPAT_E_HIP = 4,         /* a HIP runtime call failed (message has the HIP error) */
+  QPAT_E_OOM = 5          /* device or pinned host allocation failed */
+} qpat_status;
+
+typedef struct qpat_plan_s* qpat_plan;
+typedef struct qpat_batch_s* qpat_batch;
+typedef void* qpat_stream; /* hipStream_t */
+
+/*
+ * Problem parameters (host struct, copied by qpat_plan_create).
+ *  nx, ny      grid nodes (each 2^a or 3*2^a, 8 <= n <= 2048); the PML lies
+ *              inside this grid.
+ *  dx, dy, dt  grid spacing [m] and time step [s].
+ *  nt          number of time samples (the loop runs n = -1 .. nt-2).
+ *  c_ref       reference speed of the k-space correction sinc(c_ref k dt/2),
+ *              eq grr [m/s].  The stability bound is checked against max(c0).
+ *  pml_size    PML thickness in cells on every side (0 = none); profile
+ *              sigma = pml_alpha (c_ref/dx) (xi/pml_size)^4 [1/s], A = exp(-sigma dt/2)
+ *              (eq dis-pml); velocities use it at half-node positions.
+ *  pml_alpha   PML maximum attenuation in nepers per cell.
+ *  alpha0_db   power-law absorption prefactor in dB MHz^-y cm^-1 (0 = lossless);
+ *              tau and eta follow eq Twelve after conversion to Np (rad/s)^-y m^-1.
+ *  y           power-law exponent (y != 1 when alpha0_db > 0).
+ *  ns          number of point sensors.
+ *  sensor_xy   host [ns][2] (x, y) positions in metres; each must lie inside the
+ *              node grid; M interpolates bilinearly from the 4 nearest nodes.
+ */
+typedef struct {
+  int32_t nx, ny;
+  double dx, dy, dt;
+  int32_t nt;
+  double c_ref;
+  int32_t pml_size;
+  double pml_alpha;
+  double alpha0_db;
+  double y;
+  int32_t ns;
+  const double* sensor_xy;
+} qpat_params;
+
+/* Spectral operators for qpat_apply (Section 3.3.2): k-space staggered
+ * gradients of eq grr and the fractional Laplacians Y_dis, Y_abs. */
+typedef enum {
+  QPAT_OP_DX_PLUS = 0,  /* d/dx^+ : F^-1 { i kx e^{+i kx dx/2} sinc(c_ref k dt/2) F } */
+  QPAT_OP_DX_MINUS = 1, /* d/dx^- */
+  QPAT_OP_DY_PLUS = 2,  /* d/dy^+ */
+  QPAT_OP_DY_MINUS = 3, /* d/dy^- */
+  QPAT_OP_YDIS = 4,     /* F^-1 { |k|^(y-1) F }, 0 at k = 0 */
+  QPAT_OP_YABS = 5      /* F^-1 { |k|^(y-2) F }, 0 at k = 0 */
+} qpat_op;
+
+/* Host-only check of a parameter set (no device work, no allocation).
+ * Returns QPAT_E_INVALID / QPAT_E_UNSUPPORTED for bad sizes or values. */
+qpat_status qpat_validate(const qpat_params* prm);
+
+/* Build a plan: validates `prm` and the medium, derives every medium diagonal,
+ * multiplier, PML profile and sensor tap in FP64 on the host, rounds them to
+ * FP32 and uploads them (synchronously) to the current HIP device.
+ *  c0, rho0  host [ny][nx] sound speed [m/s] and ambient density [kg/m^3],
+ *            all > 0 and finite.
+ * Returns QPAT_E_UNSTABLE when dt exceeds 2 asin(c_ref/max c0)/(c_ref k_max)
+ * with c_ref < max c0.  On failure *out is NULL. */
+qpat_status qpat_plan_create(const qpat_params* prm, const double* c0, const double* rho0,
+                             qpat_plan* out);
+void qpat_plan_destroy(qpat_plan plan);
+
+/* Forward operator H_a (Definition 4): p0 [B][ny][nx] -> data [B][nt][ns].
+ * `batch` vectors run in one set of launches. */
+qpat_status qpat_forward(qpat_plan plan, const float* p0, float* data, int32_t batch,
+                         qpat_stream stream);
+
+/* Adjoint H_a^* (Lemma 2): residual [B][nt][ns] -> gradient in p0 [B][ny][nx]. */
+qpat_status qpat_adjoint(qpat_plan plan, const float* res, float* grad, int32_t batch,
+                         qpat_stream stream);
+
+/* Jacobian-vector product.  H_a is linear in p0 (eq acoust_map), so J v = H_a v. */
+qpat_status qpat_jv(qpat_plan plan, const float* v, float* data, int32_t batch,
+                    qpat_stream stream);
+
+/* Gauss-Newton normal operator J^T J v = H_a^* H_a v (Section 4, eq apj):
+ * v [B][ny][nx] -> out [B][ny][nx]; the intermediate data stay in plan memory. */
+qpat_status qpat_jtjv(qpat_plan plan, const float* v, float* out, int32_t batch,
+                      qpat_stream stream);
+
+/* One spectral operator on B fields: in [B][ny][nx] -> out [B][ny][nx]. */
+qpat_status qpat_apply(qpat_plan plan, int32_t op, const float* in, float* out, int32_t batch,
+                       qpat_stream stream);
+
+/* Wavefield checkpointing.  The stacked state z_m = (v_x, v_y at t_{m-1/2},
+ * rho_x, rho_y, p at t_m) of the paper's eq t is stored at m = 0, K, 2K, ...
+ * A checkpoint buffer holds [B][ceil(nt/K)][5][ny][nx] floats.
+ *  qpat_ckpt_bytes     size in bytes of that buffer.
+ *  qpat_forward_ckpt   qpat_forward that also fills `ckpt` (device, caller-owned).
+ *  qpat_replay         recomputes the states of segment `seg` from its checkpoint:
+ *                      states [B][cnt][5][ny][nx] for m = seg*K .. seg*K+cnt-1,
+ *                      cnt = min(K, nt - seg*K); bitwise equal to the states of
+ *                      the uninterrupted forward run.  p0 is needed again because
+ *                      the source of eq s1 is also injected at iterate n = 0.
+ * Memory is O(nt/K) for the checkpoints plus O(K) for one replayed segment. */
+qpat_status qpat_ckpt_bytes(qpat_plan plan, int32_t interval, int32_t batch, size_t* bytes);
+qpat_status qpat_forward_ckpt(qpat_plan plan, const float* p0, float* data, int32_t interval,
+                              float* ckpt, int32_t batch, qpat_stream stream);
+qpat_status qpat_replay(qpat_plan plan, const float* p0, const float* ckpt, int32_t interval,
+                        int32_t seg, float* states, int32_t batch, qpat_stream stream);
+
+/* Launch shape of the FFT passes: rows per row-pass block and spectrum columns
+ * per column-pass block (powers of two dividing ny and nx/2).  qpat_tune times
+ * the candidates on `stream` for `batch` vectors (it runs short forward
+ * solves, synchronising the stream) and keeps the fastest; results are cached
+ * per (nx, ny, batch, lossy) in the file named by QPAT_TUNE_CACHE, if set. */
+qpat_status qpat_set_tiles(qpat_plan plan, int32_t rows, int32_t cols);
+qpat_status qpat_get_tiles(qpat_plan plan, int32_t* rows, int32_t* cols);
+qpat_status qpat_tune(qpat_plan plan, int32_t batch, qpat_stream stream);
+
+/* hipGraph mode: when enabled, the kernel sequence of a forward / adjoint /
+ * jtjv call is captured into a hipGraph on first use and replayed on later
+ * calls with the same operation, batch and buffer addresses. */
+qpat_status qpat_set_graph(qpat_plan plan, int32_t enable);
+
+/* Uneven-grid batch: plans of different sizes (and numbers of time steps)
+ * advanced together, one launch per phase for all of them.  All plans must be
+ * lossy or all lossless (else QPAT_E_UNSUPPORTED).  The batch keeps references
+ * to the plans, which must outlive it.  Pointer arrays are host arrays of `count` device
+ * pointers laid out as for the single-plan calls with B = 1. */
+qpat_status qpat_batch_create(const qpat_plan* plans, int32_t count, qpat_batch* out);
+void qpat_batch_destroy(qpat_batch batch);
+qpat_status qpat_batch_forward(qpat_batch batch, const float* const* p0, float* const* data,
+                               qpat_stream stream);
+qpat_status qpat_batch_adjoint(qpat_batch batch, const float* const* res, float* const* grad,
+                               qpat_stream stream);
+qpat_status qpat_batch_jtjv(qpat_batch batch, const float* const* v, float* const* out,
+                            qpat_stream stream);
+qpat_status qpat_batch_set_graph(qpat_batch batch, int32_t enable);
+
+/* Inner product with FP64 accumulation of two device float vectors of length
+ * n; the result is written to *out (device double).  Deterministic: a fixed
+ * block partition reduced in a fixed order (wavefront shuffles, then LDS). */
+qpat_status qpat_dot(const float* a, const float* b, int64_t n, double* out, qpat_stream stream);
+
+/* Plan introspection: sizes and the device bytes the plan holds. */
+qpat_status qpat_plan_info(qpat_plan plan, int32_t* nx, int32_t* ny, int32_t* nt, int32_t* ns,
+                           size_t* device_bytes);
+
+const char* qpat_status_string(qpat_status status);
+const char* qpat_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QPAT_H */

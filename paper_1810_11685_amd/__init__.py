@@ -1,0 +1,9 @@
+"""MI355X (gfx950) k-space acoustic forward / adjoint operators of direct QPAT
+(Javaherian & Holman, arXiv 1810.11685), as hand-written HIP kernels behind a
+C ABI (include/qpat.h), with a thin torch binding."""
+from ._lib import EXPORTED, LIB_PATH, QpatError, lib
+from .ops import Batch, Plan, dot, make_params, validate
+from .autograd import AcousticForward, acoustic, replay_states
+
+__all__ = ["Plan", "Batch", "dot", "validate", "make_params", "acoustic", "AcousticForward",
+           "replay_states", "QpatError", "lib", "LIB_PATH", "EXPORTED"]

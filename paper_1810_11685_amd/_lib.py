@@ -1,0 +1,101 @@
+"""ctypes declarations of the C ABI in include/qpat.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import torch  # noqa: F401  (loads torch's HIP runtime first so libqpat binds to the same one)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqpat.so")
+
+c_int32 = ctypes.c_int32
+c_double = ctypes.c_double
+c_void_p = ctypes.c_void_p
+c_size_t = ctypes.c_size_t
+c_int64 = ctypes.c_int64
+
+
+class QpatParams(ctypes.Structure):
+    _fields_ = [
+        ("nx", c_int32), ("ny", c_int32),
+        ("dx", c_double), ("dy", c_double), ("dt", c_double),
+        ("nt", c_int32),
+        ("c_ref", c_double),
+        ("pml_size", c_int32),
+        ("pml_alpha", c_double),
+        ("alpha0_db", c_double),
+        ("y", c_double),
+        ("ns", c_int32),
+        ("sensor_xy", ctypes.POINTER(c_double)),
+    ]
+
+
+STATUS = {0: "QPAT_OK", 1: "QPAT_E_INVALID", 2: "QPAT_E_UNSUPPORTED", 3: "QPAT_E_UNSTABLE",
+          4: "QPAT_E_HIP", 5: "QPAT_E_OOM"}
+
+# name -> (restype, argtypes)
+_SIGS = {
+    "qpat_validate": (c_int32, [ctypes.POINTER(QpatParams)]),
+    "qpat_plan_create": (c_int32, [ctypes.POINTER(QpatParams), c_void_p, c_void_p, ctypes.POINTER(c_void_p)]),
+    "qpat_plan_destroy": (None, [c_void_p]),
+    "qpat_forward": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_void_p]),
+    "qpat_adjoint": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_void_p]),
+    "qpat_jv": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_void_p]),
+    "qpat_jtjv": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_void_p]),
+    "qpat_apply": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_int32, c_void_p]),
+    "qpat_ckpt_bytes": (c_int32, [c_void_p, c_int32, c_int32, ctypes.POINTER(c_size_t)]),
+    "qpat_forward_ckpt": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_int32, c_void_p]),
+    "qpat_replay": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_void_p, c_int32, c_void_p]),
+    "qpat_set_tiles": (c_int32, [c_void_p, c_int32, c_int32]),
+    "qpat_get_tiles": (c_int32, [c_void_p, ctypes.POINTER(c_int32), ctypes.POINTER(c_int32)]),
+    "qpat_tune": (c_int32, [c_void_p, c_int32, c_void_p]),
+    "qpat_set_graph": (c_int32, [c_void_p, c_int32]),
+    "qpat_batch_create": (c_int32, [ctypes.POINTER(c_void_p), c_int32, ctypes.POINTER(c_void_p)]),
+    "qpat_batch_destroy": (None, [c_void_p]),
+    "qpat_batch_forward": (c_int32, [c_void_p, ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p), c_void_p]),
+    "qpat_batch_adjoint": (c_int32, [c_void_p, ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p), c_void_p]),
+    "qpat_batch_jtjv": (c_int32, [c_void_p, ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p), c_void_p]),
+    "qpat_batch_set_graph": (c_int32, [c_void_p, c_int32]),
+    "qpat_dot": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_void_p]),
+    "qpat_plan_info": (c_int32, [c_void_p, ctypes.POINTER(c_int32), ctypes.POINTER(c_int32),
+                                 ctypes.POINTER(c_int32), ctypes.POINTER(c_int32), ctypes.POINTER(c_size_t)]),
+    "qpat_status_string": (ctypes.c_char_p, [c_int32]),
+    "qpat_last_error": (ctypes.c_char_p, []),
+}
+
+EXPORTED = tuple(_SIGS)
+
+_lock = threading.Lock()
+_lib = None
+
+
+class QpatError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where}: {STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded libqpat.so.  Raises if it has not been built: there is no
+    fallback implementation."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                                   "`python -m paper_1810_11685_amd.build` (hipcc, gfx950)")
+            L = ctypes.CDLL(LIB_PATH)
+            for name, (res, args) in _SIGS.items():
+                f = getattr(L, name)
+                f.restype = res
+                f.argtypes = args
+            _lib = L
+        return _lib
+
+
+def check(status: int, where: str) -> None:
+    if status != 0:
+        msg = lib().qpat_last_error()
+        raise QpatError(status, where, msg.decode() if msg else "")

@@ -1,0 +1,662 @@
+// HIP kernels of the k-space acoustic operator for gfx950 (MI355X).
+//
+// Every spectral operator F^-1 diag(m) F of Section 3.3.2 (staggered
+// gradients of eq grr, fractional Laplacians Y_dis and Y_abs) is split into
+//   row pass  : inverse row FFTs of the previous spectra, the pointwise update
+//               of eqs num-vel / num-rho / num-p (or their transposes), and the
+//               forward row FFTs of the next fields, all on rows held in LDS;
+//   column pass: forward column FFT, multiplier(s), inverse column FFT, on a
+//               tile of spectrum columns held in LDS.
+// Two real fields share one complex row FFT (z = a + i b); spectra are stored
+// as half spectra [ny][nx/2] with the (real) DC and Nyquist columns packed as
+// the real and imaginary parts of column 0.  FFTs are radix-2/3/4/8 Stockham
+// passes between two LDS buffers; inverse transforms use conj(FFT(conj(.))).
+// The 1/(nx ny) normalisation is folded into the multiplier tables.
+//
+// A launch covers any number of problems ("items", possibly of different
+// sizes): block b reads (item, tile) from a block map built on the host, which
+// places consecutive tiles of one item on the same XCD.
+#include "qpat_internal.hpp"
+
+namespace qpat {
+
+// ---------------------------------------------------------------- complex
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+__device__ __forceinline__ float2 mul_mi(float2 a) { return make_float2(a.y, -a.x); }  // -i * a
+
+// ---------------------------------------------------------------- butterflies (forward DFT)
+template <int R> __device__ __forceinline__ void bfly(float2* v);
+
+template <> __device__ __forceinline__ void bfly<2>(float2* v) {
+  const float2 a = v[0], b = v[1];
+  v[0] = cadd(a, b);
+  v[1] = csub(a, b);
+}
+
+template <> __device__ __forceinline__ void bfly<3>(float2* v) {
+  const float s = 0.86602540378443864676f;  // sin(pi/3)
+  const float2 t1 = cadd(v[1], v[2]);
+  const float2 t2 = make_float2(v[0].x - 0.5f * t1.x, v[0].y - 0.5f * t1.y);
+  const float2 t3 = mul_mi(cscale(csub(v[1], v[2]), s));
+  v[0] = cadd(v[0], t1);
+  v[1] = cadd(t2, t3);
+  v[2] = csub(t2, t3);
+}
+
+template <> __device__ __forceinline__ void bfly<4>(float2* v) {
+  const float2 t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+  const float2 t2 = cadd(v[1], v[3]), t3 = mul_mi(csub(v[1], v[3]));
+  v[0] = cadd(t0, t2);
+  v[2] = csub(t0, t2);
+  v[1] = cadd(t1, t3);
+  v[3] = csub(t1, t3);
+}
+
+template <> __device__ __forceinline__ void bfly<8>(float2* v) {
+  const float c = 0.70710678118654752440f;
+  float2 e[4] = {v[0], v[2], v[4], v[6]};
+  float2 o[4] = {v[1], v[3], v[5], v[7]};
+  bfly<4>(e);
+  bfly<4>(o);
+  const float2 o1 = make_float2(c * (o[1].x + o[1].y), c * (o[1].y - o[1].x));   // W8^1
+  const float2 o2 = mul_mi(o[2]);                                               // W8^2
+  const float2 o3 = make_float2(c * (o[3].y - o[3].x), -c * (o[3].x + o[3].y)); // W8^3
+  v[0] = cadd(e[0], o[0]);
+  v[4] = csub(e[0], o[0]);
+  v[1] = cadd(e[1], o1);
+  v[5] = csub(e[1], o1);
+  v[2] = cadd(e[2], o2);
+  v[6] = csub(e[2], o2);
+  v[3] = cadd(e[3], o3);
+  v[7] = csub(e[3], o3);
+}
+
+// One Stockham stage for butterfly j: reads src[j + r nb], twiddles by
+// W_{Ns R}^{k r} (k = j mod Ns), writes dst[(j - k) R + k + r Ns].
+template <int R>
+__device__ __forceinline__ void stockham(const float2* src, float2* dst, int j, int nb, int Ns,
+                                         int tws, const float2* __restrict__ tw) {
+  float2 v[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) v[r] = src[j + r * nb];
+  const int k = j % Ns;
+  if (Ns > 1) {
+#pragma unroll
+    for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw[k * r * tws]);
+  }
+  bfly<R>(v);
+  const int base = (j - k) * R + k;
+#pragma unroll
+  for (int r = 0; r < R; ++r) dst[base + r * Ns] = v[r];
+}
+
+// Forward FFT of `nlines` lines of length n (line stride ls) held in LDS
+// buffer a, using b as the ping-pong partner.  All threads of the block take
+// part; returns the buffer that holds the result.  The caller must have
+// synchronised after writing the input; the routine ends synchronised.
+__device__ float2* fft_lines(float2* a, float2* b, int nlines, int n, int ls, uint32_t rad, int nst,
+                             const float2* __restrict__ tw) {
+  int Ns = 1;
+  for (int s = 0; s < nst; ++s) {
+    const int R = (rad >> (4 * s)) & 15;
+    const int nb = n / R;
+    const int tws = n / (Ns * R);
+    const int total = nlines * nb;
+    for (int it = threadIdx.x; it < total; it += blockDim.x) {
+      const int line = it / nb;
+      const int j = it - line * nb;
+      const float2* src = a + line * ls;
+      float2* dst = b + line * ls;
+      if (R == 8)
+        stockham<8>(src, dst, j, nb, Ns, tws, tw);
+      else if (R == 4)
+        stockham<4>(src, dst, j, nb, Ns, tws, tw);
+      else if (R == 2)
+        stockham<2>(src, dst, j, nb, Ns, tws, tw);
+      else
+        stockham<3>(src, dst, j, nb, Ns, tws, tw);
+    }
+    __syncthreads();
+    float2* t = a;
+    a = b;
+    b = t;
+    Ns *= R;
+  }
+  return a;
+}
+
+// ---------------------------------------------------------------- packing
+// Conjugated inverse-FFT input of the pair (A, B) of packed half-spectrum
+// rows: Z = A + iB with Hermitian completion; writes Z[k] and Z[n-k].
+__device__ __forceinline__ void build_inv(float2* L, float2 A, float2 B, int k, int nx, int nxh) {
+  if (k == 0) {
+    L[0] = make_float2(A.x, -B.x);
+    L[nxh] = make_float2(A.y, -B.y);
+  } else {
+    L[k] = make_float2(A.x - B.y, -(A.y + B.x));
+    L[nx - k] = make_float2(A.x + B.y, -(B.x - A.y));
+  }
+}
+
+// Split the FFT Z of a + i b into the packed half spectra A (of a), B (of b).
+__device__ __forceinline__ void unpack(const float2* L, int k, int nx, int nxh, float2& A, float2& B) {
+  if (k == 0) {
+    const float2 z0 = L[0], zn = L[nxh];
+    A = make_float2(z0.x, zn.x);
+    B = make_float2(z0.y, zn.y);
+  } else {
+    const float2 zk = L[k], zm = L[nx - k];
+    A = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
+    B = make_float2(0.5f * (zk.y + zm.y), 0.5f * (zm.x - zk.x));
+  }
+}
+
+__device__ __forceinline__ float2* other(float2* r, float2* a, float2* b) { return r == a ? b : a; }
+
+// line j <- rows y0+j of (s0, s1)
+__device__ __forceinline__ void load_pair_lines(float2* buf, const float2* __restrict__ s0,
+                                                const float2* __restrict__ s1, int y0, int nlines,
+                                                int nx, int nxh) {
+  for (int it = threadIdx.x; it < nlines * nxh; it += blockDim.x) {
+    const int j = it / nxh, k = it - j * nxh;
+    const size_t off = size_t(y0 + j) * nxh + k;
+    build_inv(buf + j * nx, s0[off], s1[off], k, nx, nxh);
+  }
+}
+
+// line l <- rows (y0+2l, y0+2l+1) of s0
+__device__ __forceinline__ void load_rowpair_lines(float2* buf, const float2* __restrict__ s0, int y0,
+                                                   int nlines, int nx, int nxh) {
+  for (int it = threadIdx.x; it < nlines * nxh; it += blockDim.x) {
+    const int l = it / nxh, k = it - l * nxh;
+    const size_t off = size_t(y0 + 2 * l) * nxh + k;
+    build_inv(buf + l * nx, s0[off], s0[off + nxh], k, nx, nxh);
+  }
+}
+
+__device__ __forceinline__ void store_pair_spectra(const float2* buf, float2* __restrict__ s0,
+                                                   float2* __restrict__ s1, int y0, int nlines, int nx,
+                                                   int nxh) {
+  for (int it = threadIdx.x; it < nlines * nxh; it += blockDim.x) {
+    const int j = it / nxh, k = it - j * nxh;
+    float2 A, B;
+    unpack(buf + j * nx, k, nx, nxh, A, B);
+    const size_t off = size_t(y0 + j) * nxh + k;
+    s0[off] = A;
+    s1[off] = B;
+  }
+}
+
+__device__ __forceinline__ void store_rowpair_spectra(const float2* buf, float2* __restrict__ s0, int y0,
+                                                      int nlines, int nx, int nxh) {
+  for (int it = threadIdx.x; it < nlines * nxh; it += blockDim.x) {
+    const int l = it / nxh, k = it - l * nxh;
+    float2 A, B;
+    unpack(buf + l * nx, k, nx, nxh, A, B);
+    const size_t off = size_t(y0 + 2 * l) * nxh + k;
+    s0[off] = A;
+    s0[off + nxh] = B;
+  }
+}
+
+// Row-pair LDS layout: row y0+j lives in component (j & 1) of line j >> 1.
+__device__ __forceinline__ float& pcomp(float2* buf, int j, int x, int nx) {
+  float2* e = buf + (j >> 1) * nx + x;
+  return (j & 1) ? e->y : e->x;
+}
+
+// Forward sensor partials for rows y0 .. y0+rt-1 (bilinear taps, eq num-m).
+__device__ __forceinline__ void sensor_partials(const Medium& M, float2* buf, int y0, int rt,
+                                                float* __restrict__ part, int m) {
+  const int e0 = M.tap_off[y0], e1 = M.tap_off[y0 + rt];
+  for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+    const Tap t = M.taps[e];
+    const int j = t.y - y0;
+    const float v = t.wl * pcomp(buf, j, t.ixl, M.nx) + t.wr * pcomp(buf, j, t.ixr, M.nx);
+    part[(size_t(m) * M.ns + t.s) * 2 + t.slot] = v;
+  }
+}
+
+// Adjoint sensor scatter M^T r for rows y0 .. y0+rt-1, one thread per row so
+// taps hitting the same node are added in a fixed order.
+__device__ __forceinline__ void sensor_scatter(const Medium& M, float2* buf, int y0, int rt,
+                                               const float* __restrict__ res, int m) {
+  const int r = threadIdx.x;
+  if (r < rt) {
+    const int e0 = M.tap_off[y0 + r], e1 = M.tap_off[y0 + r + 1];
+    for (int e = e0; e < e1; ++e) {
+      const Tap t = M.taps[e];
+      const float rv = res[size_t(m) * M.ns + t.s];
+      pcomp(buf, r, t.ixl, M.nx) += t.wl * rv;
+      pcomp(buf, r, t.ixr, M.nx) += t.wr * rv;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- row pass
+template <int MODE>
+__global__ void __launch_bounds__(kBlock)
+row_kernel(const Item* __restrict__ items, const IO* __restrict__ io, const int2* __restrict__ map,
+           int n, int flags) {
+  extern __shared__ float2 lds[];
+  const int2 bm = map[blockIdx.x];
+  if (bm.x < 0) return;
+  const Medium& M = items[bm.x].m;
+  const Work& W = items[bm.x].w;
+  const IO& X = io[bm.x];
+  if (n > M.nt - 2) return;  // this problem has finished (uneven batches)
+  const int nx = M.nx, nxh = M.nxh, rt = M.rt;
+  const int y0 = bm.y * rt;
+  float2* bufA = lds;
+  float2* bufB = lds + rt * nx;
+  const int tot = rt * nx;
+
+  if constexpr (MODE == RM_F1) {
+    // eq num-vel: v_i = A_i (A_i v_i - dt/rho_i d/dr_i^+ p)
+    load_pair_lines(bufA, W.s0, W.s1, y0, rt, nx, nxh);
+    __syncthreads();
+    float2* r = fft_lines(bufA, bufB, rt, nx, nx, M.radx, M.nstx, M.twx);
+    float2* o = other(r, bufA, bufB);
+    const bool first = (n == 0);
+    for (int it = threadIdx.x; it < tot; it += blockDim.x) {
+      const int j = it / nx, x = it - j * nx, y = y0 + j;
+      const size_t idx = size_t(y) * nx + x;
+      const float2 z = r[it];
+      const float gx = z.x, gy = -z.y;
+      const float vxo = first ? 0.f : W.f0[idx], vyo = first ? 0.f : W.f1[idx];
+      const float ax = M.avx[x], ay = M.avy[y];
+      const float vx = ax * (ax * vxo - M.bx[idx] * gx);
+      const float vy = ay * (ay * vyo - M.by[idx] * gy);
+      W.f0[idx] = vx;
+      W.f1[idx] = vy;
+      o[it] = make_float2(vx, vy);
+    }
+    __syncthreads();
+    r = fft_lines(o, other(o, bufA, bufB), rt, nx, nx, M.radx, M.nstx, M.twx);
+    store_pair_spectra(r, W.s0, W.s1, y0, rt, nx, nxh);
+  } else if constexpr (MODE == RM_F2 || MODE == RM_F2L) {
+    // eq num-rho with the additive source of eq s1 (dt s = p0 / (2 d c^2), d = 2)
+    const bool skip = (n == -1);  // v^{-1/2} = 0 and rho^{-1} = 0
+    float2* r = nullptr;
+    float2* o = bufA;
+    if (!skip) {
+      load_pair_lines(bufA, W.s0, W.s1, y0, rt, nx, nxh);
+      __syncthreads();
+      r = fft_lines(bufA, bufB, rt, nx, nx, M.radx, M.nstx, M.twx);
+      o = other(r, bufA, bufB);
+    }
+    const bool inject = (n <= 0);
+    const float dt = M.dt;
+    for (int it = threadIdx.x; it < tot; it += blockDim.x) {
+      const int j = it / nx, x = it - j * nx, y = y0 + j;
+      const size_t idx = size_t(y) * nx + x;
+      float ex = 0.f, ey = 0.f, rxo = 0.f, ryo = 0.f;
+      if (!skip) {
+        const float2 z = r[it];
+        ex = z.x;
+        ey = -z.y;
+        rxo = W.f2[idx];
+        ryo = W.f3[idx];
+      } else {
+        W.f0[idx] = 0.f;  // the state z_0 holds v^{-1/2} = 0
+        W.f1[idx] = 0.f;
+      }
+      const float ax = M.arx[x], ay = M.ary[y], r0 = M.rho0[idx];
+      const float src = inject ? X.in[idx] * (0.25f / M.c2[idx]) : 0.f;
+      const float rx = ax * (ax * rxo - dt * r0 * ex) + src;
+      const float ry = ay * (ay * ryo - dt * r0 * ey) + src;
+      W.f2[idx] = rx;
+      W.f3[idx] = ry;
+      if constexpr (MODE == RM_F2) {
+        // S = sum_i rho_i and u = rho0 sum_i A_i d/dr_i^- v_i feed eq num-p
+        o[it] = make_float2(rx + ry, r0 * (ax * ex + ay * ey));
+      } else {
+        const float p = M.c2[idx] * (rx + ry);
+        pcomp(o, j, x, nx) = p;
+        if (flags & FL_STORE_P) W.q[idx] = p;
+      }
+    }
+    __syncthreads();
+    if constexpr (MODE == RM_F2) {
+      r = fft_lines(o, other(o, bufA, bufB), rt, nx, nx, M.radx, M.nstx, M.twx);
+      store_pair_spectra(r, W.s0, W.s1, y0, rt, nx, nxh);
+    } else {
+      if (!(flags & FL_NO_SENSORS)) sensor_partials(M, o, y0, rt, W.part, n + 1);
+      r = fft_lines(o, other(o, bufA, bufB), rt / 2, nx, nx, M.radx, M.nstx, M.twx);
+      store_rowpair_spectra(r, W.s0, y0, rt / 2, nx, nxh);
+    }
+  } else if constexpr (MODE == RM_F3) {
+    // eq num-p: p = c^2 (S - eta Y_dis S + tau Y_abs u)
+    load_pair_lines(bufA, W.s0, W.s1, y0, rt, nx, nxh);
+    __syncthreads();
+    float2* r = fft_lines(bufA, bufB, rt, nx, nx, M.radx, M.nstx, M.twx);
+    float2* o = other(r, bufA, bufB);
+    for (int it = threadIdx.x; it < tot; it += blockDim.x) {
+      const int j = it / nx, x = it - j * nx, y = y0 + j;
+      const size_t idx = size_t(y) * nx + x;
+      const float2 z = r[it];
+      const float S = W.f2[idx] + W.f3[idx];
+      const float p = M.c2[idx] * S - M.c2eta[idx] * z.x + M.c2tau[idx] * (-z.y);
+      pcomp(o, j, x, nx) = p;
+      if (flags & FL_STORE_P) W.q[idx] = p;
+    }
+    __syncthreads();
+    if (!(flags & FL_NO_SENSORS)) sensor_partials(M, o, y0, rt, W.part, n + 1);
+    r = fft_lines(o, other(o, bufA, bufB), rt / 2, nx, nx, M.radx, M.nstx, M.twx);
+    store_rowpair_spectra(r, W.s0, y0, rt / 2, nx, nxh);
+  } else if constexpr (MODE == RM_A1 || MODE == RM_A1L) {
+    // transpose of eqs num-m and num-p: p* += M^T r_{n+1}; q = c^2 p*
+    const bool first = (n == M.nt - 2);
+    const int half = rt / 2;
+    float2* r = bufA;
+    if (!first) {
+      load_rowpair_lines(bufA, W.s0, y0, half, nx, nxh);
+      __syncthreads();
+      r = fft_lines(bufA, bufB, half, nx, nx, M.radx, M.nstx, M.twx);
+      // p* = -(grad_x^- g_x + grad_y^- g_y): negate the (conjugated) inverse
+      for (int it = threadIdx.x; it < half * nx; it += blockDim.x) {
+        const float2 z = r[it];
+        r[it] = make_float2(-z.x, z.y);
+      }
+    } else {
+      for (int it = threadIdx.x; it < half * nx; it += blockDim.x) r[it] = make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    sensor_scatter(M, r, y0, rt, X.in, n + 1);
+    __syncthreads();
+    float2* o = other(r, bufA, bufB);
+    const float dt = M.dt;
+    for (int it = threadIdx.x; it < tot; it += blockDim.x) {
+      const int j = it / nx, x = it - j * nx, y = y0 + j;
+      const size_t idx = size_t(y) * nx + x;
+      const float pb = pcomp(r, j, x, nx);
+      if constexpr (MODE == RM_A1) {
+        W.q[idx] = M.c2[idx] * pb;
+        o[it] = make_float2(M.c2eta[idx] * pb, M.c2tau[idx] * pb);
+      } else {
+        // lossless: S* = q, u* = 0, then the transposed mass update
+        const float q = M.c2[idx] * pb;
+        const float rbx = (first ? 0.f : W.f2[idx]) + q;
+        const float rby = (first ? 0.f : W.f3[idx]) + q;
+        float* gout = X.out;
+        if (n == 0) gout[idx] = rbx + rby;
+        if (n == -1) {
+          float g = rbx + rby;
+          if (M.nt >= 2) g += gout[idx];
+          gout[idx] = g * (0.25f / M.c2[idx]);
+        } else {
+          const float ax = M.arx[x], ay = M.ary[y], r0 = M.rho0[idx];
+          o[it] = make_float2(-dt * r0 * ax * rbx, -dt * r0 * ay * rby);
+          W.f2[idx] = ax * ax * rbx;
+          W.f3[idx] = ay * ay * rby;
+        }
+      }
+    }
+    __syncthreads();
+    if (MODE == RM_A1 || n != -1) {
+      r = fft_lines(o, other(o, bufA, bufB), rt, nx, nx, M.radx, M.nstx, M.twx);
+      store_pair_spectra(r, W.s0, W.s1, y0, rt, nx, nxh);
+    }
+  } else if constexpr (MODE == RM_A2) {
+    // transpose of the mass update and of the Y terms of eq num-p
+    load_pair_lines(bufA, W.s0, W.s1, y0, rt, nx, nxh);
+    __syncthreads();
+    float2* r = fft_lines(bufA, bufB, rt, nx, nx, M.radx, M.nstx, M.twx);
+    float2* o = other(r, bufA, bufB);
+    const bool first = (n == M.nt - 2);
+    const float dt = M.dt;
+    float* gout = X.out;
+    for (int it = threadIdx.x; it < tot; it += blockDim.x) {
+      const int j = it / nx, x = it - j * nx, y = y0 + j;
+      const size_t idx = size_t(y) * nx + x;
+      const float2 z = r[it];
+      const float yd = z.x, ya = -z.y;
+      const float sb = W.q[idx] - yd;
+      const float rbx = (first ? 0.f : W.f2[idx]) + sb;
+      const float rby = (first ? 0.f : W.f3[idx]) + sb;
+      if (n == 0) gout[idx] = rbx + rby;
+      if (n == -1) {
+        float g = rbx + rby;
+        if (M.nt >= 2) g += gout[idx];
+        gout[idx] = g * (0.25f / M.c2[idx]);
+      } else {
+        const float ax = M.arx[x], ay = M.ary[y], r0 = M.rho0[idx];
+        o[it] = make_float2(r0 * ax * (ya - dt * rbx), r0 * ay * (ya - dt * rby));
+        W.f2[idx] = ax * ax * rbx;
+        W.f3[idx] = ay * ay * rby;
+      }
+    }
+    __syncthreads();
+    if (n != -1) {
+      r = fft_lines(o, other(o, bufA, bufB), rt, nx, nx, M.radx, M.nstx, M.twx);
+      store_pair_spectra(r, W.s0, W.s1, y0, rt, nx, nxh);
+    }
+  } else if constexpr (MODE == RM_A3) {
+    // transpose of eq num-vel
+    load_pair_lines(bufA, W.s0, W.s1, y0, rt, nx, nxh);
+    __syncthreads();
+    float2* r = fft_lines(bufA, bufB, rt, nx, nx, M.radx, M.nstx, M.twx);
+    float2* o = other(r, bufA, bufB);
+    const bool first = (n == M.nt - 2);
+    for (int it = threadIdx.x; it < tot; it += blockDim.x) {
+      const int j = it / nx, x = it - j * nx, y = y0 + j;
+      const size_t idx = size_t(y) * nx + x;
+      const float2 z = r[it];
+      const float vbx = (first ? 0.f : W.f0[idx]) - z.x;
+      const float vby = (first ? 0.f : W.f1[idx]) + z.y;
+      const float ax = M.avx[x], ay = M.avy[y];
+      o[it] = make_float2(-ax * M.bx[idx] * vbx, -ay * M.by[idx] * vby);
+      W.f0[idx] = ax * ax * vbx;
+      W.f1[idx] = ay * ay * vby;
+    }
+    __syncthreads();
+    r = fft_lines(o, other(o, bufA, bufB), rt, nx, nx, M.radx, M.nstx, M.twx);
+    store_pair_spectra(r, W.s0, W.s1, y0, rt, nx, nxh);
+  } else if constexpr (MODE == RM_FWD1) {
+    const float* src = X.in;
+    for (int it = threadIdx.x; it < tot; it += blockDim.x) {
+      const int j = it / nx, x = it - j * nx;
+      pcomp(bufA, j, x, nx) = src[size_t(y0 + j) * nx + x];
+    }
+    __syncthreads();
+    float2* r = fft_lines(bufA, bufB, rt / 2, nx, nx, M.radx, M.nstx, M.twx);
+    store_rowpair_spectra(r, W.s0, y0, rt / 2, nx, nxh);
+  } else if constexpr (MODE == RM_INV1) {
+    load_rowpair_lines(bufA, W.s0, y0, rt / 2, nx, nxh);
+    __syncthreads();
+    float2* r = fft_lines(bufA, bufB, rt / 2, nx, nx, M.radx, M.nstx, M.twx);
+    float* dst = X.out;
+    for (int it = threadIdx.x; it < tot; it += blockDim.x) {
+      const int j = it / nx, x = it - j * nx;
+      const float v = pcomp(r, j, x, nx);
+      dst[size_t(y0 + j) * nx + x] = (j & 1) ? -v : v;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- column pass
+__device__ __forceinline__ float2 mult_val(const Medium& M, int code, int kx, int ky) {
+  const int t = ky * (M.nxh + 1) + kx;
+  switch (code) {
+    case MC_DXP: return cscale(M.dxp[kx], M.kap[t]);
+    case MC_DXM: return cscale(M.dxm[kx], M.kap[t]);
+    case MC_DYP: return cscale(M.dyp[ky], M.kap[t]);
+    case MC_DYM: return cscale(M.dym[ky], M.kap[t]);
+    case MC_LDIS: return make_float2(M.ldis[t], 0.f);
+    case MC_LABS: return make_float2(M.labs[t], 0.f);
+    default: return make_float2(0.f, 0.f);
+  }
+}
+
+__global__ void __launch_bounds__(kBlock)
+col_kernel(const Item* __restrict__ items, const int2* __restrict__ map, int mcode, int nin, int nout,
+           int n) {
+  extern __shared__ float2 lds[];
+  const int2 bm = map[blockIdx.x];
+  if (bm.x < 0) return;
+  const Medium& M = items[bm.x].m;
+  const Work& W = items[bm.x].w;
+  if (n > M.nt - 2) return;
+  const int ny = M.ny, nxh = M.nxh, ct = M.ct, ls = col_line_stride(ny, ct);
+  const int c0 = bm.y * ct;
+  const int nsl = nin > nout ? nin : nout;
+  float2* bufA = lds;
+  float2* bufB = lds + nsl * ct * ls;
+  // load the tile, transposed into lines (field, column)
+  for (int it = threadIdx.x; it < nin * ct * ny; it += blockDim.x) {
+    const int c = it % ct, rest = it / ct;
+    const int ky = rest % ny, f = rest / ny;
+    const float2* s = f ? W.s1 : W.s0;
+    bufA[(f * ct + c) * ls + ky] = s[size_t(ky) * nxh + c0 + c];
+  }
+  __syncthreads();
+  float2* r = fft_lines(bufA, bufB, nin * ct, ny, ls, M.rady, M.nsty, M.twy);
+  float2* o = other(r, bufA, bufB);
+  for (int it = threadIdx.x; it < ct * ny; it += blockDim.x) {
+    const int c = it / ny, ky = it - c * ny;
+    const int kx = c0 + c;
+    if (kx == 0) {
+      // packed column: DC (real part) and Nyquist (imaginary part) columns
+      const int km = ky ? ny - ky : 0;
+      float2 f0[2], fn[2];
+      for (int f = 0; f < nin; ++f) {
+        const float2 z = r[(f * ct + c) * ls + ky], zm = cconj(r[(f * ct + c) * ls + km]);
+        f0[f] = cscale(cadd(z, zm), 0.5f);
+        fn[f] = mul_mi(cscale(csub(z, zm), 0.5f));
+      }
+      for (int q = 0; q < nout; ++q) {
+        float2 g0 = make_float2(0.f, 0.f), gn = make_float2(0.f, 0.f);
+        for (int f = 0; f < nin; ++f) {
+          const int code = (mcode >> (4 * (2 * q + f))) & 15;
+          if (!code) continue;
+          g0 = cadd(g0, cmul(mult_val(M, code, 0, ky), f0[f]));
+          gn = cadd(gn, cmul(mult_val(M, code, nxh, ky), fn[f]));
+        }
+        // W = G0 + i GN, stored conjugated for the inverse transform
+        o[(q * ct + c) * ls + ky] = cconj(make_float2(g0.x - gn.y, g0.y + gn.x));
+      }
+    } else {
+      float2 in[2];
+      for (int f = 0; f < nin; ++f) in[f] = r[(f * ct + c) * ls + ky];
+      for (int q = 0; q < nout; ++q) {
+        float2 acc = make_float2(0.f, 0.f);
+        for (int f = 0; f < nin; ++f) {
+          const int code = (mcode >> (4 * (2 * q + f))) & 15;
+          if (code) acc = cadd(acc, cmul(mult_val(M, code, kx, ky), in[f]));
+        }
+        o[(q * ct + c) * ls + ky] = cconj(acc);
+      }
+    }
+  }
+  __syncthreads();
+  r = fft_lines(o, other(o, bufA, bufB), nout * ct, ny, ls, M.rady, M.nsty, M.twy);
+  for (int it = threadIdx.x; it < nout * ct * ny; it += blockDim.x) {
+    const int c = it % ct, rest = it / ct;
+    const int ky = rest % ny, f = rest / ny;
+    float2* s = f ? W.s1 : W.s0;
+    s[size_t(ky) * nxh + c0 + c] = cconj(r[(f * ct + c) * ls + ky]);
+  }
+}
+
+// ---------------------------------------------------------------- sensor data
+__global__ void combine_kernel(const Item* __restrict__ items, const IO* __restrict__ io) {
+  const Medium& M = items[blockIdx.y].m;
+  const float* part = items[blockIdx.y].w.part;
+  float* out = io[blockIdx.y].out;
+  const int total = M.nt * M.ns;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x)
+    out[i] = part[2 * i] + part[2 * i + 1];
+}
+
+// ---------------------------------------------------------------- reductions
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+__global__ void __launch_bounds__(kBlock) dot_partial(const float* __restrict__ a, const float* __restrict__ b,
+                                                      int64_t n, double* __restrict__ partial) {
+  __shared__ double red[kBlock / 64];
+  double acc = 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    acc += double(a[i]) * double(b[i]);
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < kBlock / 64; ++w) s += red[w];
+    partial[blockIdx.x] = s;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) dot_final(const double* __restrict__ partial, int nblk,
+                                                    double* __restrict__ out) {
+  __shared__ double red[kBlock / 64];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += blockDim.x) acc += partial[i];
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < kBlock / 64; ++w) s += red[w];
+    *out = s;
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+template <int MODE>
+static hipError_t launch_row_t(const Item* items, const IO* io, const int2* map, int nblocks,
+                               size_t lds, int n, int flags, hipStream_t st) {
+  hipLaunchKernelGGL(row_kernel<MODE>, dim3(nblocks), dim3(kBlock), lds, st, items, io, map, n, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_row(int mode, const Item* items, const IO* io, const int2* map, int nblocks,
+                      size_t lds, int n, int flags, hipStream_t st) {
+  switch (mode) {
+    case RM_F1: return launch_row_t<RM_F1>(items, io, map, nblocks, lds, n, flags, st);
+    case RM_F2: return launch_row_t<RM_F2>(items, io, map, nblocks, lds, n, flags, st);
+    case RM_F2L: return launch_row_t<RM_F2L>(items, io, map, nblocks, lds, n, flags, st);
+    case RM_F3: return launch_row_t<RM_F3>(items, io, map, nblocks, lds, n, flags, st);
+    case RM_A1: return launch_row_t<RM_A1>(items, io, map, nblocks, lds, n, flags, st);
+    case RM_A1L: return launch_row_t<RM_A1L>(items, io, map, nblocks, lds, n, flags, st);
+    case RM_A2: return launch_row_t<RM_A2>(items, io, map, nblocks, lds, n, flags, st);
+    case RM_A3: return launch_row_t<RM_A3>(items, io, map, nblocks, lds, n, flags, st);
+    case RM_FWD1: return launch_row_t<RM_FWD1>(items, io, map, nblocks, lds, n, flags, st);
+    case RM_INV1: return launch_row_t<RM_INV1>(items, io, map, nblocks, lds, n, flags, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_col(int mcode, int nin, int nout, const Item* items, const int2* map, int nblocks,
+                      size_t lds, int n, int /*reverse*/, hipStream_t st) {
+  hipLaunchKernelGGL(col_kernel, dim3(nblocks), dim3(kBlock), lds, st, items, map, mcode, nin, nout, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_combine(const Item* items, const IO* io, int nitems, int max_count, hipStream_t st) {
+  int bx = (max_count + kBlock - 1) / kBlock;
+  if (bx > 1024) bx = 1024;
+  if (bx < 1) bx = 1;
+  hipLaunchKernelGGL(combine_kernel, dim3(bx, nitems), dim3(kBlock), 0, st, items, io);
+  return hipGetLastError();
+}
+
+hipError_t launch_dot(const float* a, const float* b, int64_t n, double* partial, int nblk, double* out,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(dot_partial, dim3(nblk), dim3(kBlock), 0, st, a, b, n, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(dot_final, dim3(1), dim3(kBlock), 0, st, partial, nblk, out);
+  return hipGetLastError();
+}
+
+}  // namespace qpat

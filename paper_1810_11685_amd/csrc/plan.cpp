@@ -1,0 +1,1132 @@
+// Host runtime of libqpat: parameter validation, FP64 plan construction,
+// work buffers, launch sequencing of the forward / adjoint time loops,
+// checkpoints, uneven-grid batches, launch-shape tuning, hipGraph replay and
+// the extern "C" entry points declared in include/qpat.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/qpat.h"
+#include "qpat_internal.hpp"
+
+using namespace qpat;
+
+// ============================================================== errors
+namespace {
+thread_local std::string g_err;
+
+qpat_status fail(qpat_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIPCHK(expr)                                                                    \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(e_ == hipErrorOutOfMemory ? QPAT_E_OOM : QPAT_E_HIP,                  \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));                  \
+  } while (0)
+
+#define STCHK(expr)                 \
+  do {                              \
+    qpat_status s_ = (expr);        \
+    if (s_ != QPAT_OK) return s_;   \
+  } while (0)
+
+constexpr int kMaxN = 2048;
+constexpr int kMinN = 8;
+constexpr size_t kMaxLds = 65536;
+
+// n = 2^a or 3 * 2^a: radix plan (4 bits per stage, first stage lowest)
+bool radix_plan(int n, uint32_t* rad, int* nst) {
+  if (n < kMinN || n > kMaxN || (n & 1)) return false;
+  std::vector<int> r;
+  int m = n;
+  if (m % 3 == 0) {
+    r.push_back(3);
+    m /= 3;
+  }
+  if (m & (m - 1)) return false;
+  int a = 0;
+  while ((1 << a) < m) ++a;
+  const int q = a / 3, rem = a % 3;
+  if (rem == 1) r.push_back(2);
+  if (rem == 2) r.push_back(4);
+  for (int i = 0; i < q; ++i) r.push_back(8);
+  *rad = 0;
+  for (size_t i = 0; i < r.size(); ++i) *rad |= uint32_t(r[i]) << (4 * i);
+  *nst = int(r.size());
+  return true;
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+double alpha0_np(double a_db, double y) {
+  return a_db * 100.0 / (20.0 * std::log10(std::exp(1.0))) * std::pow(1e-6 / (2.0 * M_PI), y);
+}
+
+double stability_limit(double cmax, double cref, double dx, double dy) {
+  if (cref >= cmax) return INFINITY;
+  const double kmax = std::hypot(M_PI / dx, M_PI / dy);
+  return 2.0 * std::asin(cref / cmax) / (cref * kmax);
+}
+
+int pow2_floor(int v) {
+  int p = 1;
+  while (p * 2 <= v) p *= 2;
+  return p;
+}
+int pow2_divisor(int v) { return v & (-v); }
+
+bool row_tile_ok(int nx, int ny, int rt) {
+  return rt >= 2 && (rt & (rt - 1)) == 0 && ny % rt == 0 && row_lds_bytes(nx, rt) <= kMaxLds;
+}
+bool col_tile_ok(int nxh, int ny, int ct) {
+  return ct >= 1 && (ct & (ct - 1)) == 0 && nxh % ct == 0 && col_lds_bytes(ny, ct) <= kMaxLds;
+}
+
+void default_tiles(int nx, int ny, int* rt, int* ct) {
+  int r = 16;
+  while (r > 2 && !(row_tile_ok(nx, ny, r) && row_lds_bytes(nx, r) <= 32768)) r /= 2;
+  int c = 16;
+  while (c > 1 && !(col_tile_ok(nx / 2, ny, c) && col_lds_bytes(ny, c) <= 32768)) c /= 2;
+  *rt = r;
+  *ct = c;
+}
+
+}  // namespace
+
+// ============================================================== executor
+// A set of items (vectors / problems) advanced together: device item array,
+// per-call I/O table, block maps of the row and column passes.
+struct Exec {
+  std::vector<Item> items;
+  Item* d_items = nullptr;
+  IO* d_io = nullptr;
+  int2* d_rowmap = nullptr;
+  int2* d_colmap = nullptr;
+  int nrow = 0, ncol = 0;
+  size_t row_lds = 0, col_lds = 0;
+  int max_nt = 0, max_data = 0;
+  bool lossy = false;
+  // pinned staging ring for the I/O table
+  static constexpr int kRing = 16;
+  IO* h_io = nullptr;
+  hipEvent_t ev[kRing] = {};
+  bool ev_used[kRing] = {};
+  int ring_pos = 0;
+  // captured graphs, keyed by operation
+  std::map<int, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
+
+  ~Exec() { release(); }
+  void release() {
+    for (auto& g : graphs) {
+      if (g.second.second) (void)hipGraphExecDestroy(g.second.second);
+      if (g.second.first) (void)hipGraphDestroy(g.second.first);
+    }
+    graphs.clear();
+    if (d_items) (void)hipFree(d_items);
+    if (d_io) (void)hipFree(d_io);
+    if (d_rowmap) (void)hipFree(d_rowmap);
+    if (d_colmap) (void)hipFree(d_colmap);
+    if (h_io) (void)hipHostFree(h_io);
+    for (int i = 0; i < kRing; ++i)
+      if (ev[i]) (void)hipEventDestroy(ev[i]);
+    d_items = nullptr;
+    d_io = nullptr;
+    d_rowmap = d_colmap = nullptr;
+    h_io = nullptr;
+    for (int i = 0; i < kRing; ++i) {
+      ev[i] = nullptr;
+      ev_used[i] = false;
+    }
+  }
+};
+
+namespace {
+
+// XCD-aware block map: natural entry i goes to XCD i / chunk, so that
+// consecutive tiles of one item share an XCD (and its L2).
+std::vector<int2> xcd_map(const std::vector<int2>& nat) {
+  const int L = int(nat.size());
+  const int chunk = (L + kXcds - 1) / kXcds;
+  std::vector<int2> out(size_t(chunk) * kXcds, make_int2(-1, -1));
+  for (int i = 0; i < L; ++i) {
+    const int x = i / chunk, s = i % chunk;
+    out[size_t(s) * kXcds + x] = nat[i];
+  }
+  return out;
+}
+
+qpat_status exec_build(Exec& E, const std::vector<Item>& items) {
+  E.release();
+  E.items = items;
+  const int ni = int(items.size());
+  std::vector<int2> rows, cols;
+  E.max_nt = 0;
+  E.max_data = 0;
+  E.row_lds = E.col_lds = 0;
+  E.lossy = items[0].m.lossy != 0;
+  for (int i = 0; i < ni; ++i) {
+    const Medium& m = items[i].m;
+    for (int t = 0; t < m.ny / m.rt; ++t) rows.push_back(make_int2(i, t));
+    for (int t = 0; t < m.nxh / m.ct; ++t) cols.push_back(make_int2(i, t));
+    E.max_nt = std::max(E.max_nt, m.nt);
+    E.max_data = std::max(E.max_data, m.nt * m.ns);
+    E.row_lds = std::max(E.row_lds, row_lds_bytes(m.nx, m.rt));
+    E.col_lds = std::max(E.col_lds, col_lds_bytes(m.ny, m.ct));
+  }
+  const std::vector<int2> rm = xcd_map(rows), cm = xcd_map(cols);
+  E.nrow = int(rm.size());
+  E.ncol = int(cm.size());
+  HIPCHK(hipMalloc(&E.d_items, sizeof(Item) * ni));
+  HIPCHK(hipMalloc(&E.d_io, sizeof(IO) * ni));
+  HIPCHK(hipMalloc(&E.d_rowmap, sizeof(int2) * rm.size()));
+  HIPCHK(hipMalloc(&E.d_colmap, sizeof(int2) * cm.size()));
+  HIPCHK(hipMemcpy(E.d_items, items.data(), sizeof(Item) * ni, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(E.d_rowmap, rm.data(), sizeof(int2) * rm.size(), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(E.d_colmap, cm.data(), sizeof(int2) * cm.size(), hipMemcpyHostToDevice));
+  HIPCHK(hipMemset(E.d_io, 0, sizeof(IO) * ni));
+  HIPCHK(hipHostMalloc(&E.h_io, sizeof(IO) * ni * Exec::kRing, hipHostMallocDefault));
+  for (int i = 0; i < Exec::kRing; ++i) HIPCHK(hipEventCreateWithFlags(&E.ev[i], hipEventDisableTiming));
+  return QPAT_OK;
+}
+
+// Upload the per-call I/O table (stream ordered; the staging slot is reused
+// only after its previous copy has executed).
+qpat_status exec_set_io(Exec& E, const std::vector<IO>& io, hipStream_t st) {
+  const int ni = int(E.items.size());
+  const int slot = E.ring_pos;
+  E.ring_pos = (E.ring_pos + 1) % Exec::kRing;
+  if (E.ev_used[slot]) HIPCHK(hipEventSynchronize(E.ev[slot]));
+  IO* h = E.h_io + size_t(slot) * ni;
+  std::memcpy(h, io.data(), sizeof(IO) * ni);
+  HIPCHK(hipMemcpyAsync(E.d_io, h, sizeof(IO) * ni, hipMemcpyHostToDevice, st));
+  HIPCHK(hipEventRecord(E.ev[slot], st));
+  E.ev_used[slot] = true;
+  return QPAT_OK;
+}
+
+hipError_t row(Exec& E, int mode, int n, int flags, hipStream_t st) {
+  return launch_row(mode, E.d_items, E.d_io, E.d_rowmap, E.nrow, E.row_lds, n, flags, st);
+}
+hipError_t col(Exec& E, int mcode, int nin, int nout, int n, hipStream_t st) {
+  return launch_col(mcode, nin, nout, E.d_items, E.d_colmap, E.ncol, E.col_lds, n, 0, st);
+}
+
+#define LCHK(expr)                           \
+  do {                                       \
+    hipError_t e_ = (expr);                  \
+    if (e_ != hipSuccess) return e_;         \
+  } while (0)
+
+// One forward iterate n (eqs num-vel, num-rho, num-p, num-m).
+hipError_t fwd_iterate(Exec& E, int n, int flags, hipStream_t st) {
+  if (n > -1) {
+    LCHK(col(E, mpack(MC_DXP, 0, MC_DYP, 0), 1, 2, n, st));
+    LCHK(row(E, RM_F1, n, 0, st));
+    LCHK(col(E, mpack(MC_DXM, 0, 0, MC_DYM), 2, 2, n, st));
+  }
+  if (E.lossy) {
+    LCHK(row(E, RM_F2, n, 0, st));
+    LCHK(col(E, mpack(MC_LDIS, 0, 0, MC_LABS), 2, 2, n, st));
+    LCHK(row(E, RM_F3, n, flags, st));
+  } else {
+    LCHK(row(E, RM_F2L, n, flags, st));
+  }
+  return hipSuccess;
+}
+
+// The forward time loop up to iterate n_last (inclusive), then the sensor data.
+hipError_t seq_forward(Exec& E, int n_last, hipStream_t st) {
+  for (int n = -1; n <= n_last; ++n) LCHK(fwd_iterate(E, n, 0, st));
+  return launch_combine(E.d_items, E.d_io, int(E.items.size()), E.max_data, st);
+}
+
+// The reverse time loop of the adjoint (transposes of the forward passes).
+hipError_t seq_adjoint(Exec& E, hipStream_t st) {
+  for (int n = E.max_nt - 2; n >= -1; --n) {
+    if (E.lossy) {
+      LCHK(row(E, RM_A1, n, 0, st));
+      LCHK(col(E, mpack(MC_LDIS, 0, 0, MC_LABS), 2, 2, n, st));
+      LCHK(row(E, RM_A2, n, 0, st));
+    } else {
+      LCHK(row(E, RM_A1L, n, 0, st));
+    }
+    if (n == -1) break;
+    LCHK(col(E, mpack(MC_DXP, 0, 0, MC_DYP), 2, 2, n, st));
+    LCHK(row(E, RM_A3, n, 0, st));
+    LCHK(col(E, mpack(MC_DXM, MC_DYM, 0, 0), 2, 1, n, st));
+  }
+  return hipSuccess;
+}
+
+enum Op { OP_FWD = 1, OP_ADJ = 2 };
+
+// Run `op` on the executor, via a captured graph when enabled.
+qpat_status exec_run(Exec& E, int op, bool use_graph, hipStream_t st) {
+  auto body = [&](hipStream_t s) -> hipError_t {
+    return op == OP_FWD ? seq_forward(E, E.max_nt - 2, s) : seq_adjoint(E, s);
+  };
+  if (!use_graph || st == nullptr) {
+    hipError_t e = body(st);
+    if (e != hipSuccess) return fail(QPAT_E_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+    return QPAT_OK;
+  }
+  auto it = E.graphs.find(op);
+  if (it == E.graphs.end()) {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    hipError_t e = body(st);
+    hipError_t e2 = hipStreamEndCapture(st, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return fail(QPAT_E_HIP, std::string("graph capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    HIPCHK(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+    it = E.graphs.emplace(op, std::make_pair(g, ge)).first;
+  }
+  HIPCHK(hipGraphLaunch(it->second.second, st));
+  return QPAT_OK;
+}
+
+}  // namespace
+
+// ============================================================== plan
+struct qpat_plan_s {
+  qpat_params prm{};
+  std::vector<double> sensors;
+  Medium med{};
+  void* d_med = nullptr;      // one allocation for all medium tables
+  size_t med_bytes = 0;
+  // per-vector work buffers
+  int cap = 0;
+  void* d_work = nullptr;
+  size_t work_item_bytes = 0;
+  std::vector<Work> works;
+  std::vector<float*> datas;  // per-vector data buffers for jtjv
+  // executors per batch size (rebuilt when tiles change)
+  std::map<int, std::unique_ptr<Exec>> execs;
+  bool graph = false;
+  int rt = 2, ct = 1;
+};
+
+struct qpat_batch_s {
+  std::vector<qpat_plan> plans;
+  std::vector<void*> blocks;       // per-problem work allocations (owned)
+  std::vector<Work> works;
+  std::vector<float*> datas;
+  Exec exec;
+  bool graph = false;
+  ~qpat_batch_s() {
+    exec.release();
+    for (void* b : blocks)
+      if (b) (void)hipFree(b);
+  }
+};
+
+namespace {
+
+qpat_status validate(const qpat_params* p) {
+  if (!p) return fail(QPAT_E_INVALID, "params is NULL");
+  uint32_t r;
+  int s;
+  if (!radix_plan(p->nx, &r, &s) || !radix_plan(p->ny, &r, &s))
+    return fail(QPAT_E_UNSUPPORTED, "nx, ny must be 2^a or 3*2^a in [8, 2048] (got " +
+                                        std::to_string(p->nx) + " x " + std::to_string(p->ny) + ")");
+  if (!finite_pos(p->dx) || !finite_pos(p->dy) || !finite_pos(p->dt))
+    return fail(QPAT_E_INVALID, "dx, dy, dt must be finite and > 0");
+  if (p->nt < 1) return fail(QPAT_E_INVALID, "nt must be >= 1");
+  if (!finite_pos(p->c_ref)) return fail(QPAT_E_INVALID, "c_ref must be finite and > 0");
+  if (p->pml_size < 0 || 2 * p->pml_size >= std::min(p->nx, p->ny))
+    return fail(QPAT_E_INVALID, "pml_size must be in [0, min(nx, ny)/2)");
+  if (!(std::isfinite(p->pml_alpha) && p->pml_alpha >= 0.0))
+    return fail(QPAT_E_INVALID, "pml_alpha must be finite and >= 0");
+  if (!(std::isfinite(p->alpha0_db) && p->alpha0_db >= 0.0))
+    return fail(QPAT_E_INVALID, "alpha0_db must be finite and >= 0");
+  if (p->alpha0_db > 0.0) {
+    if (!(std::isfinite(p->y) && p->y > 0.0 && p->y <= 3.0))
+      return fail(QPAT_E_INVALID, "y must be in (0, 3]");
+    if (std::fabs(std::cos(M_PI * p->y / 2.0)) < 1e-9)
+      return fail(QPAT_E_UNSUPPORTED, "tan(pi y / 2) is singular for odd integer y");
+  }
+  if (p->ns < 1) return fail(QPAT_E_INVALID, "ns must be >= 1");
+  if (!p->sensor_xy) return fail(QPAT_E_INVALID, "sensor_xy is NULL");
+  for (int s2 = 0; s2 < p->ns; ++s2) {
+    const double x = p->sensor_xy[2 * s2], y = p->sensor_xy[2 * s2 + 1];
+    const double u = x / p->dx + p->nx / 2, v = y / p->dy + p->ny / 2;
+    if (!(std::isfinite(u) && std::isfinite(v) && u >= 0.0 && u <= p->nx - 1 && v >= 0.0 &&
+          v <= p->ny - 1))
+      return fail(QPAT_E_INVALID, "sensor " + std::to_string(s2) + " lies outside the grid");
+  }
+  const long long data = (long long)p->nt * p->ns;
+  if (data > (1LL << 30)) return fail(QPAT_E_INVALID, "nt * ns too large");
+  return QPAT_OK;
+}
+
+// Bilinear taps (eq num-m), grouped by grid row in CSR form.
+void build_taps(const qpat_params& p, std::vector<Tap>& taps, std::vector<int>& off) {
+  std::vector<std::vector<Tap>> byrow(p.ny);
+  for (int s = 0; s < p.ns; ++s) {
+    const double u = p.sensor_xy[2 * s] / p.dx + p.nx / 2, v = p.sensor_xy[2 * s + 1] / p.dy + p.ny / 2;
+    const int ix = int(std::floor(u)), iy = int(std::floor(v));
+    const double fx = u - ix, fy = v - iy;
+    const int ix1 = std::min(ix + 1, p.nx - 1), iy1 = std::min(iy + 1, p.ny - 1);
+    Tap a{s, 0, iy, ix, ix1, float((1 - fx) * (1 - fy)), float(fx * (1 - fy)), 0};
+    Tap b{s, 1, iy1, ix, ix1, float((1 - fx) * fy), float(fx * fy), 0};
+    byrow[iy].push_back(a);
+    byrow[iy1].push_back(b);
+  }
+  taps.clear();
+  off.assign(p.ny + 1, 0);
+  for (int y = 0; y < p.ny; ++y) {
+    off[y] = int(taps.size());
+    for (const Tap& t : byrow[y]) taps.push_back(t);
+  }
+  off[p.ny] = int(taps.size());
+}
+
+// Carve aligned sub-buffers out of one allocation.
+struct Carver {
+  size_t off = 0;
+  template <typename T>
+  size_t take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    const size_t o = off;
+    off += count * sizeof(T);
+    return o;
+  }
+};
+
+qpat_status plan_build(qpat_plan P, const double* c0, const double* rho0) {
+  const qpat_params& p = P->prm;
+  const int nx = p.nx, ny = p.ny, nxh = nx / 2, N = nx * ny;
+  const double dx = p.dx, dy = p.dy, dt = p.dt;
+  // medium checks
+  double cmax = 0.0;
+  for (int i = 0; i < N; ++i) {
+    if (!finite_pos(c0[i])) return fail(QPAT_E_INVALID, "c0 must be finite and > 0 everywhere");
+    if (!finite_pos(rho0[i])) return fail(QPAT_E_INVALID, "rho0 must be finite and > 0 everywhere");
+    cmax = std::max(cmax, c0[i]);
+  }
+  const double lim = stability_limit(cmax, p.c_ref, dx, dy);
+  if (dt > lim)
+    return fail(QPAT_E_UNSTABLE, "dt = " + std::to_string(dt) + " exceeds the k-space stability bound " +
+                                     std::to_string(lim) + " for c_ref < max(c0)");
+  const bool lossy = p.alpha0_db > 0.0;
+
+  // ---- FP64 derived quantities
+  std::vector<float> c2(N), c2eta(N), c2tau(N), r0(N), bx(N), by(N);
+  const double a0 = lossy ? alpha0_np(p.alpha0_db, p.y) : 0.0;
+  const double tn = lossy ? std::tan(M_PI * p.y / 2.0) : 0.0;
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      const int k = j * nx + i;
+      const double c = c0[k];
+      c2[k] = float(c * c);
+      // eq Twelve: tau = -2 a0 c^(y-1), eta = 2 a0 c^y tan(pi y/2)
+      c2eta[k] = lossy ? float(c * c * 2.0 * a0 * std::pow(c, p.y) * tn) : 0.f;
+      c2tau[k] = lossy ? float(c * c * -2.0 * a0 * std::pow(c, p.y - 1.0)) : 0.f;
+      r0[k] = float(rho0[k]);
+      const double rx = 0.5 * (rho0[k] + rho0[j * nx + (i + 1) % nx]);
+      const double ry = 0.5 * (rho0[k] + rho0[((j + 1) % ny) * nx + i]);
+      bx[k] = float(dt / rx);
+      by[k] = float(dt / ry);
+    }
+  // PML (eq dis-pml), 4th-power profile inside the grid
+  auto sigma = [&](double pos, int n, double d) {
+    const int L = p.pml_size;
+    if (L <= 0) return 0.0;
+    const double xi = std::max(0.0, std::max(L - pos, pos - (n - 1 - L)));
+    return p.pml_alpha * (p.c_ref / d) * std::pow(xi / L, 4);
+  };
+  std::vector<float> avx(nx), arx(nx), avy(ny), ary(ny);
+  for (int i = 0; i < nx; ++i) {
+    arx[i] = float(std::exp(-sigma(i, nx, dx) * dt / 2.0));
+    avx[i] = float(std::exp(-sigma(i + 0.5, nx, dx) * dt / 2.0));
+  }
+  for (int j = 0; j < ny; ++j) {
+    ary[j] = float(std::exp(-sigma(j, ny, dy) * dt / 2.0));
+    avy[j] = float(std::exp(-sigma(j + 0.5, ny, dy) * dt / 2.0));
+  }
+  // wavenumbers; Nyquist at -pi/d where the staggered symbol is real
+  auto kval = [](int idx, int n, double d) {
+    const int f = idx < n / 2 ? idx : idx - n;
+    return 2.0 * M_PI * f / (n * d);
+  };
+  auto dsym = [](double k, double d, int sgn, bool nyq) {
+    // i k e^{sgn i k d/2}
+    const double th = sgn * k * d / 2.0;
+    if (nyq) return make_float2(float(-k * std::sin(th)), 0.f);
+    return make_float2(float(-k * std::sin(th)), float(k * std::cos(th)));
+  };
+  std::vector<float2> dxp(nxh + 1), dxm(nxh + 1), dyp(ny), dym(ny);
+  for (int i = 0; i <= nxh; ++i) {
+    const double k = kval(i, nx, dx);
+    dxp[i] = dsym(k, dx, +1, i == nxh);
+    dxm[i] = dsym(k, dx, -1, i == nxh);
+  }
+  for (int j = 0; j < ny; ++j) {
+    const double k = kval(j, ny, dy);
+    dyp[j] = dsym(k, dy, +1, j == ny / 2);
+    dym[j] = dsym(k, dy, -1, j == ny / 2);
+  }
+  const size_t nt2 = size_t(ny) * (nxh + 1);
+  std::vector<float> kap(nt2), ldis(nt2), labs(nt2);
+  const double inv = 1.0 / (double(nx) * ny);
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i <= nxh; ++i) {
+      const double kx = kval(i, nx, dx), ky = kval(j, ny, dy);
+      const double K = std::sqrt(kx * kx + ky * ky);
+      const double arg = p.c_ref * K * dt / 2.0;
+      const double kp = arg == 0.0 ? 1.0 : std::sin(arg) / arg;
+      const size_t t = size_t(j) * (nxh + 1) + i;
+      kap[t] = float(kp * inv);
+      ldis[t] = (K == 0.0 || !lossy) ? 0.f : float(std::pow(K, p.y - 1.0) * inv);
+      labs[t] = (K == 0.0 || !lossy) ? 0.f : float(std::pow(K, p.y - 2.0) * inv);
+    }
+  auto twid = [](int n) {
+    std::vector<float2> t(n);
+    for (int k = 0; k < n; ++k) {
+      const double a = -2.0 * M_PI * k / n;
+      t[k] = make_float2(float(std::cos(a)), float(std::sin(a)));
+    }
+    return t;
+  };
+  const std::vector<float2> twx = twid(nx), twy = twid(ny);
+  std::vector<Tap> taps;
+  std::vector<int> toff;
+  build_taps(p, taps, toff);
+  if (taps.empty()) taps.push_back(Tap{});
+
+  // ---- upload
+  Carver cv;
+  const size_t o_c2 = cv.take<float>(N), o_c2eta = cv.take<float>(N), o_c2tau = cv.take<float>(N);
+  const size_t o_r0 = cv.take<float>(N), o_bx = cv.take<float>(N), o_by = cv.take<float>(N);
+  const size_t o_avx = cv.take<float>(nx), o_arx = cv.take<float>(nx);
+  const size_t o_avy = cv.take<float>(ny), o_ary = cv.take<float>(ny);
+  const size_t o_dxp = cv.take<float2>(nxh + 1), o_dxm = cv.take<float2>(nxh + 1);
+  const size_t o_dyp = cv.take<float2>(ny), o_dym = cv.take<float2>(ny);
+  const size_t o_kap = cv.take<float>(nt2), o_ldis = cv.take<float>(nt2), o_labs = cv.take<float>(nt2);
+  const size_t o_twx = cv.take<float2>(nx), o_twy = cv.take<float2>(ny);
+  const size_t o_toff = cv.take<int>(toff.size()), o_taps = cv.take<Tap>(taps.size());
+  const size_t total = cv.off;
+  std::vector<char> host(total, 0);
+  auto put = [&](size_t o, const void* src, size_t bytes) { std::memcpy(host.data() + o, src, bytes); };
+  put(o_c2, c2.data(), N * 4);
+  put(o_c2eta, c2eta.data(), N * 4);
+  put(o_c2tau, c2tau.data(), N * 4);
+  put(o_r0, r0.data(), N * 4);
+  put(o_bx, bx.data(), N * 4);
+  put(o_by, by.data(), N * 4);
+  put(o_avx, avx.data(), nx * 4);
+  put(o_arx, arx.data(), nx * 4);
+  put(o_avy, avy.data(), ny * 4);
+  put(o_ary, ary.data(), ny * 4);
+  put(o_dxp, dxp.data(), (nxh + 1) * 8);
+  put(o_dxm, dxm.data(), (nxh + 1) * 8);
+  put(o_dyp, dyp.data(), ny * 8);
+  put(o_dym, dym.data(), ny * 8);
+  put(o_kap, kap.data(), nt2 * 4);
+  put(o_ldis, ldis.data(), nt2 * 4);
+  put(o_labs, labs.data(), nt2 * 4);
+  put(o_twx, twx.data(), nx * 8);
+  put(o_twy, twy.data(), ny * 8);
+  put(o_toff, toff.data(), toff.size() * 4);
+  put(o_taps, taps.data(), taps.size() * sizeof(Tap));
+  char* d = nullptr;
+  HIPCHK(hipMalloc(&d, total));
+  P->d_med = d;
+  P->med_bytes = total;
+  HIPCHK(hipMemcpy(d, host.data(), total, hipMemcpyHostToDevice));
+
+  Medium& M = P->med;
+  M.nx = nx;
+  M.ny = ny;
+  M.nxh = nxh;
+  M.nt = p.nt;
+  M.ns = p.ns;
+  M.lossy = lossy ? 1 : 0;
+  M.dt = float(dt);
+  radix_plan(nx, &M.radx, &M.nstx);
+  radix_plan(ny, &M.rady, &M.nsty);
+  M.c2 = (const float*)(d + o_c2);
+  M.c2eta = (const float*)(d + o_c2eta);
+  M.c2tau = (const float*)(d + o_c2tau);
+  M.rho0 = (const float*)(d + o_r0);
+  M.bx = (const float*)(d + o_bx);
+  M.by = (const float*)(d + o_by);
+  M.avx = (const float*)(d + o_avx);
+  M.arx = (const float*)(d + o_arx);
+  M.avy = (const float*)(d + o_avy);
+  M.ary = (const float*)(d + o_ary);
+  M.dxp = (const float2*)(d + o_dxp);
+  M.dxm = (const float2*)(d + o_dxm);
+  M.dyp = (const float2*)(d + o_dyp);
+  M.dym = (const float2*)(d + o_dym);
+  M.kap = (const float*)(d + o_kap);
+  M.ldis = (const float*)(d + o_ldis);
+  M.labs = (const float*)(d + o_labs);
+  M.twx = (const float2*)(d + o_twx);
+  M.twy = (const float2*)(d + o_twy);
+  M.tap_off = (const int*)(d + o_toff);
+  M.taps = (const Tap*)(d + o_taps);
+  default_tiles(nx, ny, &P->rt, &P->ct);
+  M.rt = P->rt;
+  M.ct = P->ct;
+  return QPAT_OK;
+}
+
+// Work buffers for `count` vectors of a problem of the size of `p` in one
+// allocation: per vector [f0 f1 f2 f3 q] fields, two half spectra, the sensor
+// partials and a data buffer (used by jtjv).
+qpat_status alloc_works(const qpat_params& p, int count, void** block, size_t* per_item,
+                        std::vector<Work>& works, std::vector<float*>& datas) {
+  const int nx = p.nx, ny = p.ny, N = nx * ny;
+  const size_t ndata = size_t(p.nt) * p.ns;
+  Carver cv;
+  const size_t o_f = cv.take<float>(size_t(5) * N);
+  const size_t o_s0 = cv.take<float2>(size_t(ny) * (nx / 2));
+  const size_t o_s1 = cv.take<float2>(size_t(ny) * (nx / 2));
+  const size_t o_part = cv.take<float>(2 * ndata);
+  const size_t o_data = cv.take<float>(ndata);
+  const size_t per = (cv.off + 255) & ~size_t(255);
+  char* d = nullptr;
+  HIPCHK(hipMalloc(&d, per * count));
+  *block = d;
+  *per_item = per;
+  works.clear();
+  datas.clear();
+  for (int i = 0; i < count; ++i) {
+    char* base = d + per * i;
+    Work w{};
+    float* f = (float*)(base + o_f);
+    w.f0 = f;
+    w.f1 = f + N;
+    w.f2 = f + 2 * N;
+    w.f3 = f + 3 * N;
+    w.q = f + 4 * N;
+    w.s0 = (float2*)(base + o_s0);
+    w.s1 = (float2*)(base + o_s1);
+    w.part = (float*)(base + o_part);
+    works.push_back(w);
+    datas.push_back((float*)(base + o_data));
+  }
+  return QPAT_OK;
+}
+
+// Make sure the plan has work buffers for `b` vectors.
+qpat_status plan_reserve(qpat_plan P, int b) {
+  if (b <= P->cap) return QPAT_OK;
+  if (P->d_work) {
+    HIPCHK(hipDeviceSynchronize());
+    HIPCHK(hipFree(P->d_work));
+    P->d_work = nullptr;
+  }
+  P->execs.clear();
+  P->cap = 0;
+  STCHK(alloc_works(P->prm, b, &P->d_work, &P->work_item_bytes, P->works, P->datas));
+  P->cap = b;
+  return QPAT_OK;
+}
+
+qpat_status plan_exec(qpat_plan P, int b, Exec** out) {
+  STCHK(plan_reserve(P, b));
+  auto it = P->execs.find(b);
+  if (it == P->execs.end()) {
+    std::vector<Item> items(b);
+    for (int i = 0; i < b; ++i) {
+      items[i].m = P->med;
+      items[i].m.rt = P->rt;
+      items[i].m.ct = P->ct;
+      items[i].w = P->works[i];
+    }
+    std::unique_ptr<Exec> E(new Exec());
+    STCHK(exec_build(*E, items));
+    it = P->execs.emplace(b, std::move(E)).first;
+  }
+  *out = it->second.get();
+  return QPAT_OK;
+}
+
+qpat_status check_plan_call(qpat_plan P, const void* a, const void* b, int batch) {
+  if (!P) return fail(QPAT_E_INVALID, "plan is NULL");
+  if (!a || !b) return fail(QPAT_E_INVALID, "input / output pointer is NULL");
+  if (batch < 1 || batch > 4096) return fail(QPAT_E_INVALID, "batch must be in [1, 4096]");
+  return QPAT_OK;
+}
+
+size_t field_elems(qpat_plan P) { return size_t(P->prm.nx) * P->prm.ny; }
+size_t data_elems(qpat_plan P) { return size_t(P->prm.nt) * P->prm.ns; }
+
+qpat_status do_forward(qpat_plan P, const float* p0, float* data, int batch, hipStream_t st,
+                       bool internal_data) {
+  Exec* E = nullptr;
+  STCHK(plan_exec(P, batch, &E));
+  std::vector<IO> io(batch);
+  for (int i = 0; i < batch; ++i) {
+    io[i].in = p0 + field_elems(P) * i;
+    io[i].out = internal_data ? P->datas[i] : data + data_elems(P) * i;
+  }
+  STCHK(exec_set_io(*E, io, st));
+  return exec_run(*E, OP_FWD, P->graph, st);
+}
+
+qpat_status do_adjoint(qpat_plan P, const float* res, float* grad, int batch, hipStream_t st,
+                       bool internal_data) {
+  Exec* E = nullptr;
+  STCHK(plan_exec(P, batch, &E));
+  std::vector<IO> io(batch);
+  for (int i = 0; i < batch; ++i) {
+    io[i].in = internal_data ? P->datas[i] : res + data_elems(P) * i;
+    io[i].out = grad + field_elems(P) * i;
+  }
+  STCHK(exec_set_io(*E, io, st));
+  return exec_run(*E, OP_ADJ, P->graph, st);
+}
+
+// ---- tuning cache
+std::string tune_key(qpat_plan P, int batch) {
+  char buf[128];
+  std::snprintf(buf, sizeof buf, "%d %d %d %d", P->prm.nx, P->prm.ny, batch, P->med.lossy);
+  return buf;
+}
+
+bool tune_lookup(const std::string& key, int* rt, int* ct) {
+  const char* path = std::getenv("QPAT_TUNE_CACHE");
+  if (!path) return false;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  char line[256];
+  bool found = false;
+  while (std::fgets(line, sizeof line, f)) {
+    int a, b, c, d, r, co;
+    if (std::sscanf(line, "%d %d %d %d %d %d", &a, &b, &c, &d, &r, &co) == 6) {
+      char k[128];
+      std::snprintf(k, sizeof k, "%d %d %d %d", a, b, c, d);
+      if (key == k) {
+        *rt = r;
+        *ct = co;
+        found = true;
+      }
+    }
+  }
+  std::fclose(f);
+  return found;
+}
+
+void tune_store(const std::string& key, int rt, int ct) {
+  const char* path = std::getenv("QPAT_TUNE_CACHE");
+  if (!path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "%s %d %d\n", key.c_str(), rt, ct);
+  std::fclose(f);
+}
+
+qpat_status set_tiles(qpat_plan P, int rt, int ct) {
+  if (!row_tile_ok(P->prm.nx, P->prm.ny, rt))
+    return fail(QPAT_E_INVALID, "rows per tile must be an even power of two dividing ny within the LDS limit");
+  if (!col_tile_ok(P->prm.nx / 2, P->prm.ny, ct))
+    return fail(QPAT_E_INVALID, "columns per tile must be a power of two dividing nx/2 within the LDS limit");
+  if (rt != P->rt || ct != P->ct) {
+    P->rt = rt;
+    P->ct = ct;
+    P->med.rt = rt;
+    P->med.ct = ct;
+    HIPCHK(hipDeviceSynchronize());
+    P->execs.clear();
+  }
+  return QPAT_OK;
+}
+
+// Time a short forward solve (first `steps` iterates) with the current tiles.
+qpat_status time_forward(qpat_plan P, int batch, int steps, hipStream_t st, float* ms) {
+  Exec* E = nullptr;
+  STCHK(plan_exec(P, batch, &E));
+  std::vector<IO> io(batch);
+  for (int i = 0; i < batch; ++i) {
+    io[i].in = P->works[i].q;  // any field-sized buffer works as p0 for timing
+    io[i].out = P->datas[i];
+  }
+  STCHK(exec_set_io(*E, io, st));
+  const int nl = std::min(P->prm.nt - 2, steps);
+  hipEvent_t a, b;
+  HIPCHK(hipEventCreate(&a));
+  HIPCHK(hipEventCreate(&b));
+  hipError_t e = seq_forward(*E, nl, st);  // warm-up
+  if (e == hipSuccess) e = hipEventRecord(a, st);
+  if (e == hipSuccess) e = seq_forward(*E, nl, st);
+  if (e == hipSuccess) e = hipEventRecord(b, st);
+  if (e == hipSuccess) e = hipEventSynchronize(b);
+  if (e == hipSuccess) e = hipEventElapsedTime(ms, a, b);
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (e != hipSuccess) return fail(QPAT_E_HIP, std::string("tune timing: ") + hipGetErrorString(e));
+  return QPAT_OK;
+}
+
+}  // namespace
+
+// ============================================================== C API
+extern "C" {
+
+const char* qpat_status_string(qpat_status s) {
+  switch (s) {
+    case QPAT_OK: return "ok";
+    case QPAT_E_INVALID: return "invalid argument";
+    case QPAT_E_UNSUPPORTED: return "unsupported configuration";
+    case QPAT_E_UNSTABLE: return "time step above the stability bound";
+    case QPAT_E_HIP: return "HIP runtime error";
+    case QPAT_E_OOM: return "out of memory";
+  }
+  return "unknown status";
+}
+
+const char* qpat_last_error(void) { return g_err.c_str(); }
+
+qpat_status qpat_validate(const qpat_params* prm) { return validate(prm); }
+
+qpat_status qpat_plan_create(const qpat_params* prm, const double* c0, const double* rho0, qpat_plan* out) {
+  if (!out) return fail(QPAT_E_INVALID, "out is NULL");
+  *out = nullptr;
+  STCHK(validate(prm));
+  if (!c0 || !rho0) return fail(QPAT_E_INVALID, "c0 / rho0 is NULL");
+  qpat_plan P = new qpat_plan_s();
+  P->prm = *prm;
+  P->sensors.assign(prm->sensor_xy, prm->sensor_xy + 2 * size_t(prm->ns));
+  P->prm.sensor_xy = P->sensors.data();
+  qpat_status s = plan_build(P, c0, rho0);
+  if (s != QPAT_OK) {
+    qpat_plan_destroy(P);
+    return s;
+  }
+  *out = P;
+  return QPAT_OK;
+}
+
+void qpat_plan_destroy(qpat_plan P) {
+  if (!P) return;
+  (void)hipDeviceSynchronize();
+  P->execs.clear();
+  if (P->d_work) (void)hipFree(P->d_work);
+  if (P->d_med) (void)hipFree(P->d_med);
+  delete P;
+}
+
+qpat_status qpat_forward(qpat_plan P, const float* p0, float* data, int32_t batch, qpat_stream stream) {
+  STCHK(check_plan_call(P, p0, data, batch));
+  return do_forward(P, p0, data, batch, (hipStream_t)stream, false);
+}
+
+qpat_status qpat_jv(qpat_plan P, const float* v, float* data, int32_t batch, qpat_stream stream) {
+  return qpat_forward(P, v, data, batch, stream);
+}
+
+qpat_status qpat_adjoint(qpat_plan P, const float* res, float* grad, int32_t batch, qpat_stream stream) {
+  STCHK(check_plan_call(P, res, grad, batch));
+  return do_adjoint(P, res, grad, batch, (hipStream_t)stream, false);
+}
+
+qpat_status qpat_jtjv(qpat_plan P, const float* v, float* out, int32_t batch, qpat_stream stream) {
+  STCHK(check_plan_call(P, v, out, batch));
+  STCHK(do_forward(P, v, nullptr, batch, (hipStream_t)stream, true));
+  return do_adjoint(P, nullptr, out, batch, (hipStream_t)stream, true);
+}
+
+qpat_status qpat_apply(qpat_plan P, int32_t op, const float* in, float* out, int32_t batch, qpat_stream stream) {
+  STCHK(check_plan_call(P, in, out, batch));
+  static const int codes[6] = {MC_DXP, MC_DXM, MC_DYP, MC_DYM, MC_LDIS, MC_LABS};
+  if (op < 0 || op > 5) return fail(QPAT_E_INVALID, "unknown operator");
+  if ((op == QPAT_OP_YDIS || op == QPAT_OP_YABS) && !P->med.lossy)
+    return fail(QPAT_E_INVALID, "Y_dis / Y_abs need a lossy plan (alpha0_db > 0)");
+  hipStream_t st = (hipStream_t)stream;
+  Exec* E = nullptr;
+  STCHK(plan_exec(P, batch, &E));
+  std::vector<IO> io(batch);
+  for (int i = 0; i < batch; ++i) {
+    io[i].in = in + field_elems(P) * i;
+    io[i].out = out + field_elems(P) * i;
+  }
+  STCHK(exec_set_io(*E, io, st));
+  hipError_t e = row(*E, RM_FWD1, -1, 0, st);
+  if (e == hipSuccess) e = col(*E, mpack(codes[op], 0, 0, 0), 1, 1, -1, st);
+  if (e == hipSuccess) e = row(*E, RM_INV1, -1, 0, st);
+  if (e != hipSuccess) return fail(QPAT_E_HIP, std::string("apply: ") + hipGetErrorString(e));
+  return QPAT_OK;
+}
+
+qpat_status qpat_ckpt_bytes(qpat_plan P, int32_t K, int32_t batch, size_t* bytes) {
+  if (!P || !bytes) return fail(QPAT_E_INVALID, "plan / bytes is NULL");
+  if (K < 1) return fail(QPAT_E_INVALID, "interval must be >= 1");
+  if (batch < 1) return fail(QPAT_E_INVALID, "batch must be >= 1");
+  const size_t nck = (size_t(P->prm.nt) + K - 1) / K;
+  *bytes = size_t(batch) * nck * 5 * field_elems(P) * sizeof(float);
+  return QPAT_OK;
+}
+
+qpat_status qpat_forward_ckpt(qpat_plan P, const float* p0, float* data, int32_t K, float* ckpt,
+                              int32_t batch, qpat_stream stream) {
+  STCHK(check_plan_call(P, p0, data, batch));
+  if (!ckpt) return fail(QPAT_E_INVALID, "ckpt is NULL");
+  if (K < 1) return fail(QPAT_E_INVALID, "interval must be >= 1");
+  hipStream_t st = (hipStream_t)stream;
+  Exec* E = nullptr;
+  STCHK(plan_exec(P, batch, &E));
+  std::vector<IO> io(batch);
+  for (int i = 0; i < batch; ++i) {
+    io[i].in = p0 + field_elems(P) * i;
+    io[i].out = data + data_elems(P) * i;
+  }
+  STCHK(exec_set_io(*E, io, st));
+  const size_t N = field_elems(P), nck = (size_t(P->prm.nt) + K - 1) / K;
+  for (int n = -1; n <= P->prm.nt - 2; ++n) {
+    const int m = n + 1;
+    const bool store = (m % K) == 0;
+    hipError_t e = fwd_iterate(*E, n, store ? FL_STORE_P : 0, st);
+    if (e != hipSuccess) return fail(QPAT_E_HIP, std::string("forward_ckpt: ") + hipGetErrorString(e));
+    if (store)
+      for (int i = 0; i < batch; ++i)
+        HIPCHK(hipMemcpyAsync(ckpt + (size_t(i) * nck + m / K) * 5 * N, P->works[i].f0, 5 * N * sizeof(float),
+                              hipMemcpyDeviceToDevice, st));
+  }
+  hipError_t e = launch_combine(E->d_items, E->d_io, batch, E->max_data, st);
+  if (e != hipSuccess) return fail(QPAT_E_HIP, std::string("forward_ckpt: ") + hipGetErrorString(e));
+  return QPAT_OK;
+}
+
+qpat_status qpat_replay(qpat_plan P, const float* p0, const float* ckpt, int32_t K, int32_t seg,
+                        float* states, int32_t batch, qpat_stream stream) {
+  STCHK(check_plan_call(P, ckpt, states, batch));
+  if (!p0) return fail(QPAT_E_INVALID, "p0 is NULL");
+  if (K < 1) return fail(QPAT_E_INVALID, "interval must be >= 1");
+  const int nt = P->prm.nt;
+  const int nck = (nt + K - 1) / K;
+  if (seg < 0 || seg >= nck) return fail(QPAT_E_INVALID, "segment out of range");
+  hipStream_t st = (hipStream_t)stream;
+  Exec* E = nullptr;
+  STCHK(plan_exec(P, batch, &E));
+  const size_t N = field_elems(P);
+  const int m0 = seg * K, cnt = std::min(K, nt - m0);
+  // restore z_{m0} and the spectrum of its pressure
+  for (int i = 0; i < batch; ++i)
+    HIPCHK(hipMemcpyAsync(P->works[i].f0, ckpt + (size_t(i) * nck + seg) * 5 * N, 5 * N * sizeof(float),
+                          hipMemcpyDeviceToDevice, st));
+  std::vector<IO> io(batch);
+  for (int i = 0; i < batch; ++i) {
+    io[i].in = P->works[i].q;
+    io[i].out = nullptr;
+  }
+  STCHK(exec_set_io(*E, io, st));
+  hipError_t e = row(*E, RM_FWD1, -1, 0, st);
+  if (e != hipSuccess) return fail(QPAT_E_HIP, std::string("replay: ") + hipGetErrorString(e));
+  for (int i = 0; i < batch; ++i) {
+    io[i].in = p0 + N * i;
+    io[i].out = nullptr;
+  }
+  STCHK(exec_set_io(*E, io, st));
+  for (int c = 0; c < cnt; ++c) {
+    if (c > 0) {
+      e = fwd_iterate(*E, m0 + c - 1, FL_STORE_P | FL_NO_SENSORS, st);
+      if (e != hipSuccess) return fail(QPAT_E_HIP, std::string("replay: ") + hipGetErrorString(e));
+    }
+    for (int i = 0; i < batch; ++i)
+      HIPCHK(hipMemcpyAsync(states + (size_t(i) * cnt + c) * 5 * N, P->works[i].f0, 5 * N * sizeof(float),
+                            hipMemcpyDeviceToDevice, st));
+  }
+  return QPAT_OK;
+}
+
+qpat_status qpat_set_tiles(qpat_plan P, int32_t rows, int32_t cols) {
+  if (!P) return fail(QPAT_E_INVALID, "plan is NULL");
+  return set_tiles(P, rows, cols);
+}
+
+qpat_status qpat_get_tiles(qpat_plan P, int32_t* rows, int32_t* cols) {
+  if (!P || !rows || !cols) return fail(QPAT_E_INVALID, "NULL argument");
+  *rows = P->rt;
+  *cols = P->ct;
+  return QPAT_OK;
+}
+
+qpat_status qpat_tune(qpat_plan P, int32_t batch, qpat_stream stream) {
+  if (!P) return fail(QPAT_E_INVALID, "plan is NULL");
+  if (batch < 1) return fail(QPAT_E_INVALID, "batch must be >= 1");
+  const std::string key = tune_key(P, batch);
+  int rt, ct;
+  if (tune_lookup(key, &rt, &ct) && row_tile_ok(P->prm.nx, P->prm.ny, rt) &&
+      col_tile_ok(P->prm.nx / 2, P->prm.ny, ct))
+    return set_tiles(P, rt, ct);
+  hipStream_t st = (hipStream_t)stream;
+  const int steps = 12;
+  int best_rt = P->rt, best_ct = P->ct;
+  float best = INFINITY;
+  // rows first (column tile fixed), then columns with the best row tile
+  for (int r = 2; r <= 32; r *= 2) {
+    if (!row_tile_ok(P->prm.nx, P->prm.ny, r)) continue;
+    STCHK(set_tiles(P, r, best_ct));
+    float ms;
+    STCHK(time_forward(P, batch, steps, st, &ms));
+    if (ms < best) {
+      best = ms;
+      best_rt = r;
+    }
+  }
+  best = INFINITY;
+  for (int c = 1; c <= 32; c *= 2) {
+    if (!col_tile_ok(P->prm.nx / 2, P->prm.ny, c)) continue;
+    STCHK(set_tiles(P, best_rt, c));
+    float ms;
+    STCHK(time_forward(P, batch, steps, st, &ms));
+    if (ms < best) {
+      best = ms;
+      best_ct = c;
+    }
+  }
+  STCHK(set_tiles(P, best_rt, best_ct));
+  tune_store(key, best_rt, best_ct);
+  return QPAT_OK;
+}
+
+qpat_status qpat_set_graph(qpat_plan P, int32_t enable) {
+  if (!P) return fail(QPAT_E_INVALID, "plan is NULL");
+  P->graph = enable != 0;
+  return QPAT_OK;
+}
+
+qpat_status qpat_plan_info(qpat_plan P, int32_t* nx, int32_t* ny, int32_t* nt, int32_t* ns, size_t* bytes) {
+  if (!P) return fail(QPAT_E_INVALID, "plan is NULL");
+  if (nx) *nx = P->prm.nx;
+  if (ny) *ny = P->prm.ny;
+  if (nt) *nt = P->prm.nt;
+  if (ns) *ns = P->prm.ns;
+  if (bytes) *bytes = P->med_bytes + P->work_item_bytes * P->cap;
+  return QPAT_OK;
+}
+
+// ---- uneven batches
+qpat_status qpat_batch_create(const qpat_plan* plans, int32_t count, qpat_batch* out) {
+  if (!out) return fail(QPAT_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!plans || count < 1) return fail(QPAT_E_INVALID, "need at least one plan");
+  for (int i = 0; i < count; ++i) {
+    if (!plans[i]) return fail(QPAT_E_INVALID, "plan " + std::to_string(i) + " is NULL");
+    if (plans[i]->med.lossy != plans[0]->med.lossy)
+      return fail(QPAT_E_UNSUPPORTED, "a batch must be all lossy or all lossless");
+    for (int j = 0; j < i; ++j)
+      if (plans[j] == plans[i]) return fail(QPAT_E_INVALID, "a plan may appear only once in a batch");
+  }
+  qpat_batch B = new qpat_batch_s();
+  B->plans.assign(plans, plans + count);
+  std::vector<Item> items(count);
+  for (int i = 0; i < count; ++i) {
+    void* blk = nullptr;
+    size_t per = 0;
+    std::vector<Work> w;
+    std::vector<float*> dd;
+    qpat_status s = alloc_works(plans[i]->prm, 1, &blk, &per, w, dd);
+    if (s != QPAT_OK) {
+      delete B;
+      return s;
+    }
+    B->blocks.push_back(blk);
+    B->works.push_back(w[0]);
+    B->datas.push_back(dd[0]);
+    items[i].m = plans[i]->med;
+    items[i].m.rt = plans[i]->rt;
+    items[i].m.ct = plans[i]->ct;
+    items[i].w = w[0];
+  }
+  qpat_status s = exec_build(B->exec, items);
+  if (s != QPAT_OK) {
+    delete B;
+    return s;
+  }
+  *out = B;
+  return QPAT_OK;
+}
+
+void qpat_batch_destroy(qpat_batch B) {
+  if (!B) return;
+  (void)hipDeviceSynchronize();
+  delete B;
+}
+
+static qpat_status batch_io(qpat_batch B, const float* const* in, float* const* out, bool internal_in,
+                            bool internal_out, hipStream_t st) {
+  std::vector<IO> io(B->plans.size());
+  for (size_t i = 0; i < B->plans.size(); ++i) {
+    io[i].in = internal_in ? B->datas[i] : in[i];
+    io[i].out = internal_out ? B->datas[i] : out[i];
+    if (!io[i].in || !io[i].out) return fail(QPAT_E_INVALID, "NULL pointer in batch arrays");
+  }
+  return exec_set_io(B->exec, io, st);
+}
+
+qpat_status qpat_batch_forward(qpat_batch B, const float* const* p0, float* const* data, qpat_stream stream) {
+  if (!B || !p0 || !data) return fail(QPAT_E_INVALID, "NULL argument");
+  STCHK(batch_io(B, p0, data, false, false, (hipStream_t)stream));
+  return exec_run(B->exec, OP_FWD, B->graph, (hipStream_t)stream);
+}
+
+qpat_status qpat_batch_adjoint(qpat_batch B, const float* const* res, float* const* grad, qpat_stream stream) {
+  if (!B || !res || !grad) return fail(QPAT_E_INVALID, "NULL argument");
+  STCHK(batch_io(B, res, grad, false, false, (hipStream_t)stream));
+  return exec_run(B->exec, OP_ADJ, B->graph, (hipStream_t)stream);
+}
+
+qpat_status qpat_batch_jtjv(qpat_batch B, const float* const* v, float* const* out, qpat_stream stream) {
+  if (!B || !v || !out) return fail(QPAT_E_INVALID, "NULL argument");
+  hipStream_t st = (hipStream_t)stream;
+  STCHK(batch_io(B, v, nullptr, false, true, st));
+  STCHK(exec_run(B->exec, OP_FWD, B->graph, st));
+  STCHK(batch_io(B, nullptr, out, true, false, st));
+  return exec_run(B->exec, OP_ADJ, B->graph, st);
+}
+
+qpat_status qpat_batch_set_graph(qpat_batch B, int32_t enable) {
+  if (!B) return fail(QPAT_E_INVALID, "batch is NULL");
+  B->graph = enable != 0;
+  return QPAT_OK;
+}
+
+// ---- reductions
+qpat_status qpat_dot(const float* a, const float* b, int64_t n, double* out, qpat_stream stream) {
+  if (!a || !b || !out) return fail(QPAT_E_INVALID, "NULL argument");
+  if (n < 0) return fail(QPAT_E_INVALID, "n must be >= 0");
+  static std::mutex mu;
+  static std::map<int, double*> partials;
+  constexpr int kNblk = 512;
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  double* part = nullptr;
+  {
+    std::lock_guard<std::mutex> g(mu);
+    auto it = partials.find(dev);
+    if (it == partials.end()) {
+      HIPCHK(hipMalloc(&part, kNblk * sizeof(double)));
+      partials[dev] = part;
+    } else {
+      part = it->second;
+    }
+  }
+  int nblk = int(std::min<int64_t>(kNblk, (n + kBlock - 1) / kBlock));
+  if (nblk < 1) nblk = 1;
+  hipError_t e = launch_dot(a, b, n, part, nblk, out, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(QPAT_E_HIP, std::string("dot: ") + hipGetErrorString(e));
+  return QPAT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,107 @@
+// Internal structures shared by the HIP kernels (kernels.hip) and the host
+// runtime (plan.cpp).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace qpat {
+
+constexpr int kBlock = 256;   // threads per block of every pass
+constexpr int kXcds = 8;      // MI355X: 8 XCDs, work-groups dispatched round-robin
+
+// One bilinear sensor tap pair on one grid row: the sensor's contribution from
+// row y is wl * f[y][ixl] + wr * f[y][ixr]; `slot` (0/1) says whether y is the
+// sensor's lower or upper row; entries are sorted by row y.
+struct Tap {
+  int s, slot, y, ixl, ixr;
+  float wl, wr;
+  int pad;
+};
+
+// Per-plan device data (medium diagonals, multipliers, twiddles, taps).
+struct Medium {
+  int nx, ny, nxh, nt, ns, lossy;
+  float dt;
+  int rt, ct;             // rows per row-pass tile, spectrum columns per column-pass tile
+  uint32_t radx, rady;    // radix plans, 4 bits per stage, first stage lowest
+  int nstx, nsty;
+  const float *c2, *c2eta, *c2tau, *rho0, *bx, *by;   // [ny][nx]; bx = dt/rho_x, by = dt/rho_y
+  const float *avx, *arx, *avy, *ary;                 // PML diagonals: [nx] / [ny]
+  const float2 *dxp, *dxm;                            // [nxh+1] i kx e^{+-i kx dx/2}
+  const float2 *dyp, *dym;                            // [ny]
+  const float *kap, *ldis, *labs;                     // [ny][nxh+1], divided by nx*ny
+  const float2 *twx, *twy;                            // twiddles e^{-2 pi i k / n}
+  const int* tap_off;                                 // [ny+1] CSR offsets into taps
+  const Tap* taps;
+};
+
+// Per-vector work buffers (owned by the plan).
+struct Work {
+  float *f0, *f1, *f2, *f3;   // forward: v_x v_y rho_x rho_y;  adjoint: their adjoints
+  float* q;                   // forward: p snapshot (checkpoints); adjoint: q = c^2 p*
+  float2 *s0, *s1;            // half spectra [ny][nx/2] (DC / Nyquist packed in column 0)
+  float* part;                // forward sensor partials [nt][ns][2]
+};
+
+// Per-call input / output pointers of one vector.
+struct IO {
+  const float* in;   // forward: p0 [ny][nx]; adjoint: residual [nt][ns]; apply: field
+  float* out;        // forward: data [nt][ns]; adjoint: gradient [ny][nx]; apply: field
+};
+
+struct Item {
+  Medium m;
+  Work w;
+};
+
+// Column-pass multiplier codes: out_o = sum_i M[o][i] * in_i, code per entry.
+enum MultCode : int {
+  MC_NONE = 0, MC_DXP = 1, MC_DXM = 2, MC_DYP = 3, MC_DYM = 4, MC_LDIS = 5, MC_LABS = 6
+};
+constexpr int mpack(int m00, int m01, int m10, int m11) {
+  return m00 | (m01 << 4) | (m10 << 8) | (m11 << 12);
+}
+
+// Row-pass kernels.
+enum RowMode : int {
+  RM_F1 = 0,   // forward: grad p -> v update -> spectra of (v_x, v_y)
+  RM_F2 = 1,   // forward: div v -> rho update (+ source) -> spectra of (S, u)   [lossy]
+  RM_F2L = 2,  // forward lossless: div v -> rho update -> p, sensors, spectrum of p
+  RM_F3 = 3,   // forward lossy: Y S, Y u -> p, sensors, spectrum of p
+  RM_A1 = 4,   // adjoint lossy: p* -> + M^T r -> q, spectra of (eta q, tau q)
+  RM_A1L = 5,  // adjoint lossless: p* -> + M^T r -> rho* update -> spectra of e*
+  RM_A2 = 6,   // adjoint lossy: Y ops -> rho* update -> spectra of e*
+  RM_A3 = 7,   // adjoint: grad e* -> v* update -> spectra of g*
+  RM_FWD1 = 8, // single real field (row pairs) -> spectrum s0
+  RM_INV1 = 9  // spectrum s0 -> single real field (row pairs)
+};
+
+// Per-launch flags.
+enum Flags : int {
+  FL_STORE_P = 1,     // forward: also store p into Work::q
+  FL_NO_SENSORS = 2,  // forward: skip the sensor partials (replay)
+};
+
+// Launch helpers implemented in kernels.hip.
+hipError_t launch_row(int mode, const Item* items, const IO* io, const int2* map, int nblocks,
+                      size_t lds, int n, int flags, hipStream_t st);
+hipError_t launch_col(int mcode, int nin, int nout, const Item* items, const int2* map,
+                      int nblocks, size_t lds, int n, int reverse, hipStream_t st);
+hipError_t launch_combine(const Item* items, const IO* io, int nitems, int max_count,
+                          hipStream_t st);
+hipError_t launch_dot(const float* a, const float* b, int64_t n, double* partial, int nblk,
+                      double* out, hipStream_t st);
+
+// LDS bytes of one block of each pass (ping-pong buffers).
+inline size_t row_lds_bytes(int nx, int rt) { return size_t(2) * rt * nx * sizeof(float2); }
+// Column lines are padded by one element when a tile holds several columns
+// (their transposed loads would otherwise hit one LDS bank).
+__host__ __device__ inline int col_line_stride(int ny, int ct) { return ct == 1 ? ny : ny + 1; }
+inline size_t col_lds_bytes(int ny, int ct) {
+  return size_t(2) * 2 * ct * col_line_stride(ny, ct) * sizeof(float2);
+}
+
+}  // namespace qpat
