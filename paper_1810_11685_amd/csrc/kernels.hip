@@ -211,6 +211,12 @@ __device__ __forceinline__ float& pcomp(float2* buf, int j, int x, int nx) {
   return (j & 1) ? e->y : e->x;
 }
 
+// Value of row y0+j after an inverse FFT of row-pair lines (conj trick undone).
+__device__ __forceinline__ float rowpair_val(const float2* buf, int j, int x, int nx) {
+  const float2 e = buf[(j >> 1) * nx + x];
+  return (j & 1) ? -e.y : e.x;
+}
+
 // Forward sensor partials for rows y0 .. y0+rt-1 (bilinear taps, eq num-m).
 __device__ __forceinline__ void sensor_partials(const Medium& M, float2* buf, int y0, int rt,
                                                 float* __restrict__ part, int m) {
@@ -314,8 +320,11 @@ row_kernel(const Item* __restrict__ items, const IO* __restrict__ io, const int2
       W.f2[idx] = rx;
       W.f3[idx] = ry;
       if constexpr (MODE == RM_F2) {
-        // S = sum_i rho_i and u = rho0 sum_i A_i d/dr_i^- v_i feed eq num-p
-        o[it] = make_float2(rx + ry, r0 * (ax * ex + ay * ey));
+        // S = sum_i rho_i and u = rho0 sum_i A_i d/dr_i^- v_i feed eq num-p.
+        // Each is transformed with its own rows paired (S and u differ by
+        // orders of magnitude, so they must not share one complex FFT).
+        pcomp(o, j, x, nx) = rx + ry;
+        pcomp(o + (rt / 2) * nx, j, x, nx) = r0 * (ax * ex + ay * ey);
       } else {
         const float p = M.c2[idx] * (rx + ry);
         pcomp(o, j, x, nx) = p;
@@ -325,7 +334,8 @@ row_kernel(const Item* __restrict__ items, const IO* __restrict__ io, const int2
     __syncthreads();
     if constexpr (MODE == RM_F2) {
       r = fft_lines(o, other(o, bufA, bufB), rt, nx, nx, M.radx, M.nstx, M.twx);
-      store_pair_spectra(r, W.s0, W.s1, y0, rt, nx, nxh);
+      store_rowpair_spectra(r, W.s0, y0, rt / 2, nx, nxh);
+      store_rowpair_spectra(r + (rt / 2) * nx, W.s1, y0, rt / 2, nx, nxh);
     } else {
       if (!(flags & FL_NO_SENSORS)) sensor_partials(M, o, y0, rt, W.part, n + 1);
       r = fft_lines(o, other(o, bufA, bufB), rt / 2, nx, nx, M.radx, M.nstx, M.twx);
@@ -333,16 +343,17 @@ row_kernel(const Item* __restrict__ items, const IO* __restrict__ io, const int2
     }
   } else if constexpr (MODE == RM_F3) {
     // eq num-p: p = c^2 (S - eta Y_dis S + tau Y_abs u)
-    load_pair_lines(bufA, W.s0, W.s1, y0, rt, nx, nxh);
+    load_rowpair_lines(bufA, W.s0, y0, rt / 2, nx, nxh);
+    load_rowpair_lines(bufA + (rt / 2) * nx, W.s1, y0, rt / 2, nx, nxh);
     __syncthreads();
     float2* r = fft_lines(bufA, bufB, rt, nx, nx, M.radx, M.nstx, M.twx);
     float2* o = other(r, bufA, bufB);
     for (int it = threadIdx.x; it < tot; it += blockDim.x) {
       const int j = it / nx, x = it - j * nx, y = y0 + j;
       const size_t idx = size_t(y) * nx + x;
-      const float2 z = r[it];
+      const float ys = rowpair_val(r, j, x, nx), yu = rowpair_val(r + (rt / 2) * nx, j, x, nx);
       const float S = W.f2[idx] + W.f3[idx];
-      const float p = M.c2[idx] * S - M.c2eta[idx] * z.x + M.c2tau[idx] * (-z.y);
+      const float p = M.c2[idx] * S - M.c2eta[idx] * ys + M.c2tau[idx] * yu;
       pcomp(o, j, x, nx) = p;
       if (flags & FL_STORE_P) W.q[idx] = p;
     }
@@ -377,8 +388,10 @@ row_kernel(const Item* __restrict__ items, const IO* __restrict__ io, const int2
       const size_t idx = size_t(y) * nx + x;
       const float pb = pcomp(r, j, x, nx);
       if constexpr (MODE == RM_A1) {
+        // eta q and tau q, each with its own rows paired (see RM_F2)
         W.q[idx] = M.c2[idx] * pb;
-        o[it] = make_float2(M.c2eta[idx] * pb, M.c2tau[idx] * pb);
+        pcomp(o, j, x, nx) = M.c2eta[idx] * pb;
+        pcomp(o + half * nx, j, x, nx) = M.c2tau[idx] * pb;
       } else {
         // lossless: S* = q, u* = 0, then the transposed mass update
         const float q = M.c2[idx] * pb;
@@ -399,13 +412,18 @@ row_kernel(const Item* __restrict__ items, const IO* __restrict__ io, const int2
       }
     }
     __syncthreads();
-    if (MODE == RM_A1 || n != -1) {
+    if constexpr (MODE == RM_A1) {
+      r = fft_lines(o, other(o, bufA, bufB), rt, nx, nx, M.radx, M.nstx, M.twx);
+      store_rowpair_spectra(r, W.s0, y0, half, nx, nxh);
+      store_rowpair_spectra(r + half * nx, W.s1, y0, half, nx, nxh);
+    } else if (n != -1) {
       r = fft_lines(o, other(o, bufA, bufB), rt, nx, nx, M.radx, M.nstx, M.twx);
       store_pair_spectra(r, W.s0, W.s1, y0, rt, nx, nxh);
     }
   } else if constexpr (MODE == RM_A2) {
     // transpose of the mass update and of the Y terms of eq num-p
-    load_pair_lines(bufA, W.s0, W.s1, y0, rt, nx, nxh);
+    load_rowpair_lines(bufA, W.s0, y0, rt / 2, nx, nxh);
+    load_rowpair_lines(bufA + (rt / 2) * nx, W.s1, y0, rt / 2, nx, nxh);
     __syncthreads();
     float2* r = fft_lines(bufA, bufB, rt, nx, nx, M.radx, M.nstx, M.twx);
     float2* o = other(r, bufA, bufB);
@@ -415,8 +433,7 @@ row_kernel(const Item* __restrict__ items, const IO* __restrict__ io, const int2
     for (int it = threadIdx.x; it < tot; it += blockDim.x) {
       const int j = it / nx, x = it - j * nx, y = y0 + j;
       const size_t idx = size_t(y) * nx + x;
-      const float2 z = r[it];
-      const float yd = z.x, ya = -z.y;
+      const float yd = rowpair_val(r, j, x, nx), ya = rowpair_val(r + (rt / 2) * nx, j, x, nx);
       const float sb = W.q[idx] - yd;
       const float rbx = (first ? 0.f : W.f2[idx]) + sb;
       const float rby = (first ? 0.f : W.f3[idx]) + sb;
