@@ -1,0 +1,288 @@
+#!/usr/bin/env python3
+"""Benchmark of the FP32 k-space acoustic forward + adjoint on one MI355X.
+
+Headline: grid-point-steps/s of one forward solve H_a p0 plus one adjoint
+solve H_a^* r on the 512 x 512, Nt = 2000, 256-ring-sensor workload (lossy,
+alpha0 = 0.75 dB MHz^-1.5 cm^-1, y = 1.5, 20-cell PML).  One benchmark step is
+that forward + adjoint pair; value = 2 * 512^2 * 2000 / step time, with inputs
+resident in HBM.
+
+Also reported on the same JSON line:
+  roofline      - the dominant pass kind: algorithmic bytes per launch / its
+                  mean launch time (HIP events, live), against 8 TB/s HBM;
+  cpu_baseline  - the FP64 oracle on the host cores, on a bounded sample;
+  batched       - Gauss-Newton J^T J v on 8 Krylov vectors at 1024^2, Nt = 4000
+                  (alpha0 = 0.5, y = 1.3): one batched call vs 8 plain calls;
+  uneven        - 32 J^T J v products over 256^2 / 384^2 / 512^2 grids in one
+                  batched call vs one call per problem.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "grid-point-steps/s fwd+adjoint (512², FP32) and batched J^TJv/s vs plain"
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic HBM bytes per grid point moved by one launch of each pass kind
+# (FP32 fields 4 B/pt; a half spectrum [ny][nx/2] of complex64 is 4 B/pt; the
+# [ny][nx/2+1] multiplier tables ~2 B/pt each).  Sum: 160 B/pt per forward
+# iterate and 160 B/pt per adjoint iterate.
+PASS_BYTES = {
+    0: 4 + 8 + 2,            # col grad p: spec p in, 2 spectra out, kappa
+    1: 8 + 8 + 8 + 8 + 8,    # row velocity: 2 spectra in, v in, dt/rho_i, v out, 2 spectra out
+    2: 8 + 8 + 2,            # col div v
+    3: 8 + 8 + 4 + 8 + 8,    # row density: 2 spectra, rho in, rho0, rho out, 2 spectra out
+    4: 8 + 8 + 4,            # col Y_dis, Y_abs: 2 in, 2 out, two tables
+    5: 8 + 8 + 12 + 4,       # row pressure: 2 spectra, rho in, c^2, c^2 eta, c^2 tau, spec p out
+    6: 4 + 12 + 4 + 8,       # adj row: spec p* in, c^2 c^2eta c^2tau, q out, 2 spectra out
+    7: 8 + 8 + 4,            # adj col Y
+    8: 8 + 4 + 8 + 4 + 8 + 8,  # adj row density: 2 spectra, q, rho* in, rho0, rho* out, 2 spectra out
+    9: 8 + 8 + 2,            # adj col grad
+    10: 8 + 8 + 8 + 8 + 8,   # adj row velocity
+    11: 8 + 4 + 2,           # adj col div: 2 in, 1 out, kappa
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "qpat_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_1810_11685_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def pmc_traffic(pass_name: str):
+    """HBM traffic per launch from the committed rocprofv3 counter summary, if it
+    was taken with the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_hash") != kernel_hash():
+        return None
+    k = rec.get("per_pass", {}).get(pass_name)
+    return None if k is None else k.get("bytes_per_launch")
+
+
+def sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def cpu_baseline(cfg, budget_s: float):
+    """FP64 oracle forward + adjoint on a bounded number of iterates of the same
+    512^2 workload; returns grid-point-steps/s and what was sampled."""
+    import numpy as np
+    import qpat_inputs as qi
+    from oracle import kspace as K
+    workers = min(os.cpu_count() or 1, 16)
+    K.set_workers(workers)
+    prm, c0, rho0, p0 = cfg["params"], cfg["c0"], cfg["rho0"], cfg["p0"]
+    ops = K.Operators(prm, c0, rho0)
+    n_pts = prm["nx"] * prm["ny"]
+    t = time.perf_counter()
+    K.forward(prm, c0, rho0, p0, ops=ops, nsteps=3)
+    per = (time.perf_counter() - t) / 3
+    steps = int(max(5, min(prm["nt"], budget_s / (2.2 * per))))
+    short = dict(prm, nt=steps)
+    t0 = time.perf_counter()
+    d = K.forward(short, c0, rho0, p0, ops=ops)
+    t1 = time.perf_counter()
+    K.adjoint(short, c0, rho0, qi.gaussian_field(d.shape, 5), ops=ops)
+    t2 = time.perf_counter()
+    return {"value": 2 * n_pts * steps / (t2 - t0), "unit": "grid-point-steps/s", "cores": workers,
+            "kind": "oracle",
+            "sample": f"FP64 numpy/scipy.fft oracle, 512x512 workload, first {steps} of 2000 iterates: "
+                      f"forward {t1 - t0:.1f} s + adjoint {t2 - t1:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched J^T J v comparisons")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default launch tiles")
+    ap.add_argument("--graph", choices=["on", "off"], default="on")
+    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only (the operator shards over independent "
+              "solves, not within one); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1810_11685_amd as q
+    import qpat_inputs as qi
+    from paper_1810_11685_amd.ops import PASSES
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    T = lambda x: torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float32, device=dev)
+
+    # ------------------------------------------------------------ headline
+    cfg = qi.config("fwdadj512")
+    prm = cfg["params"]
+    nx, ny, nt, ns = prm["nx"], prm["ny"], prm["nt"], len(prm["sensor_xy"])
+    plan = q.Plan(prm, cfg["c0"], cfg["rho0"])
+    tiles_default = plan.tiles()
+    if not args.no_tune:
+        t = time.perf_counter()
+        plan.tune(1)
+        log(f"tuned tiles {plan.tiles()} (default {tiles_default}) in {time.perf_counter() - t:.1f} s")
+    plan.set_graph(args.graph == "on")
+    stream = torch.cuda.Stream(device=dev)
+    p0 = T(cfg["p0"])
+    res = T(qi.gaussian_field((nt, ns), 1823))
+
+    def step():
+        plan.forward(p0)
+        plan.adjoint(res)
+
+    with torch.cuda.stream(stream):
+        for i in range(args.warmup):
+            step()
+            sync()
+            log(f"warmup step {i + 1}/{args.warmup} done")
+        sync()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        sync()
+        t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / args.steps
+    value = 2.0 * nx * ny * nt / (ms * 1e-3)
+    log(f"forward+adjoint {ms:.2f} ms/step -> {value:.3e} grid-point-steps/s")
+
+    # ------------------------------------------------------------ roofline (live, HIP events)
+    passes = {}
+    with torch.cuda.stream(stream):
+        for pid, (name, kind) in enumerate(PASSES):
+            t_ms = plan.time_pass(pid, batch=1, reps=50)
+            gbs = PASS_BYTES[pid] * nx * ny / (t_ms * 1e-3) / 1e9
+            passes[name] = {"kernel": kind, "ms": round(t_ms, 5), "bytes_per_pt": PASS_BYTES[pid],
+                            "GB_s": round(gbs, 1)}
+    dom = max(passes, key=lambda k: passes[k]["ms"])
+    dpid = [n for n, _ in PASSES].index(dom)
+    achieved = passes[dom]["GB_s"]
+    traffic = pmc_traffic(dom)
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": dom, "bytes_per_launch": PASS_BYTES[dpid] * nx * ny,
+                "launch_ms": passes[dom]["ms"]}
+    whole = value * 160.0 / 1e9
+    log(f"dominant pass {dom}: {passes[dom]['ms'] * 1e3:.1f} us, {achieved:.0f} GB/s; "
+        f"whole solve {whole:.0f} GB/s algorithmic")
+
+    out = {"metric": METRIC, "value": round(value, 1), "unit": "grid-point-steps/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "fwdadj512: one forward + one adjoint k-space solve, 512x512 grid, "
+                                  "Nt=2000, 256 ring sensors, lossy (alpha0=0.75 dB/MHz^1.5/cm, y=1.5), "
+                                  "20-cell PML, heterogeneous c0/rho0",
+                      "grid": [ny, nx], "nt": nt, "ns": ns, "batch": 1,
+                      "launch": "hipGraph" if args.graph == "on" else "stream",
+                      "tiles": list(plan.tiles()), "whole_solve_GB_s": round(whole, 1)},
+           "roofline": roofline, "passes": passes}
+
+    # ------------------------------------------------------------ batched vs plain J^T J v
+    if not args.no_batch:
+        g = qi.config("gn1024")
+        gp = g["params"]
+        B = 8
+        gplan = q.Plan(gp, g["c0"], g["rho0"])
+        if not args.no_tune:
+            gplan.tune(B)
+        vs = T(np.stack([qi.smooth_noise(1024, 1024, 8.0, 3000 + j) for j in range(B)]))
+        with torch.cuda.stream(stream):
+            gplan.set_graph(False)
+            gplan.jtjv(vs[0])                     # warm-up (plain)
+            sync()
+            t = time.perf_counter()
+            for j in range(B):
+                gplan.jtjv(vs[j])
+            sync()
+            t_plain = time.perf_counter() - t
+            log(f"plain J^T J v x{B} (1024^2, Nt=4000): {t_plain:.2f} s")
+            gplan.set_graph(args.graph == "on")
+            gplan.jtjv(vs)                        # warm-up (batched; captures the graph)
+            sync()
+            t = time.perf_counter()
+            gplan.jtjv(vs)
+            sync()
+            t_batch = time.perf_counter() - t
+            log(f"batched J^T J v x{B}: {t_batch:.2f} s")
+        pts = 2.0 * 1024 * 1024 * gp["nt"] * B
+        out["batched"] = {"workload": "gn1024: J^T J v, 1024x1024, Nt=4000, 512 ring sensors, "
+                                      "alpha0=0.5, y=1.3, 8 Krylov vectors",
+                          "jtjv_per_s_plain": round(B / t_plain, 4), "jtjv_per_s_batched": round(B / t_batch, 4),
+                          "speedup": round(t_plain / t_batch, 3),
+                          "grid_point_steps_per_s_batched": round(pts / t_batch, 1),
+                          "tiles": list(gplan.tiles())}
+        del gplan, vs
+        torch.cuda.empty_cache()
+
+        probs = qi.uneven_batch()
+        plans = [q.Plan(p["params"], p["c0"], p["rho0"]) for p in probs]
+        xs = [T(p["p0"]) for p in probs]
+        bat = q.Batch(plans)
+        pts = sum(2.0 * p["params"]["nx"] * p["params"]["ny"] * p["params"]["nt"] for p in probs)
+        with torch.cuda.stream(stream):
+            for pl, x in zip(plans, xs):          # warm-up
+                pl.jtjv(x)
+            sync()
+            t = time.perf_counter()
+            for pl, x in zip(plans, xs):
+                pl.jtjv(x)
+            sync()
+            t_plain = time.perf_counter() - t
+            bat.set_graph(args.graph == "on")
+            bat.jtjv(xs)
+            sync()
+            t = time.perf_counter()
+            bat.jtjv(xs)
+            sync()
+            t_batch = time.perf_counter() - t
+        log(f"uneven batch of {len(probs)}: plain {t_plain:.2f} s, batched {t_batch:.2f} s")
+        out["uneven"] = {"workload": "32 J^T J v over 12x256^2 (Nt=1380), 10x384^2 (Nt=2069), "
+                                     "10x512^2 (Nt=2759), N/2 ring sensors each, dt=1.875e-8 s",
+                         "jtjv_per_s_plain": round(len(probs) / t_plain, 3),
+                         "jtjv_per_s_batched": round(len(probs) / t_batch, 3),
+                         "speedup": round(t_plain / t_batch, 3),
+                         "grid_point_steps_per_s_batched": round(pts / t_batch, 1)}
+        del bat, plans, xs
+        torch.cuda.empty_cache()
+
+    # ------------------------------------------------------------ CPU baseline (oracle)
+    if not args.no_cpu:
+        t = time.perf_counter()
+        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_budget)
+        log(f"cpu baseline {out['cpu_baseline']['value']:.3e} grid-point-steps/s "
+            f"({time.perf_counter() - t:.1f} s)")
+    else:
+        out["cpu_baseline"] = None
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

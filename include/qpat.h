@@ -158,6 +158,21 @@ qpat_status qpat_set_tiles(qpat_plan plan, int32_t rows, int32_t cols);
 qpat_status qpat_get_tiles(qpat_plan plan, int32_t* rows, int32_t* cols);
 qpat_status qpat_tune(qpat_plan plan, int32_t batch, qpat_stream stream);
 
+/* Diagnostic timing of one pass kind on the plan's work buffers: the
+ * kernel of one phase of an iterate, launched `reps` times back-to-back on
+ * `stream` between two HIP events (after one warm-up launch), at iterate n = 1.
+ * Returns the mean duration per launch in milliseconds and synchronises the
+ * stream; the plan's work buffers are overwritten.  Pass ids:
+ *   forward  0 column d/dx^+, d/dy^+ of p      1 row: velocity update (eq num-vel)
+ *            2 column d/dx^-, d/dy^- of v      3 row: density update (eq num-rho)
+ *            4 column Y_dis, Y_abs             5 row: pressure (eq num-p), sensors
+ *   adjoint  6 row: M^T r, c^2 p*              7 column Y_dis, Y_abs
+ *            8 row: transposed density update  9 column d/dx^+, d/dy^+
+ *           10 row: transposed velocity update 11 column sum of d/dr_i^-
+ * Passes 4, 5, 7, 8 exist only for lossy plans (QPAT_E_INVALID otherwise). */
+qpat_status qpat_time_pass(qpat_plan plan, int32_t pass, int32_t batch, int32_t reps,
+                           qpat_stream stream, float* ms_per_launch);
+
 /* hipGraph mode: when enabled, the kernel sequence of a forward / adjoint /
  * jtjv call is captured into a hipGraph on first use and replayed on later
  * calls with the same operation, batch and buffer addresses. */

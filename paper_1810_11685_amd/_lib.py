@@ -52,6 +52,7 @@ _SIGS = {
     "qpat_get_tiles": (c_int32, [c_void_p, ctypes.POINTER(c_int32), ctypes.POINTER(c_int32)]),
     "qpat_tune": (c_int32, [c_void_p, c_int32, c_void_p]),
     "qpat_set_graph": (c_int32, [c_void_p, c_int32]),
+    "qpat_time_pass": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_void_p, ctypes.POINTER(ctypes.c_float)]),
     "qpat_batch_create": (c_int32, [ctypes.POINTER(c_void_p), c_int32, ctypes.POINTER(c_void_p)]),
     "qpat_batch_destroy": (None, [c_void_p]),
     "qpat_batch_forward": (c_int32, [c_void_p, ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p), c_void_p]),

@@ -1000,6 +1000,59 @@ qpat_status qpat_tune(qpat_plan P, int32_t batch, qpat_stream stream) {
   return QPAT_OK;
 }
 
+// One pass kind of the forward (0-5) or adjoint (6-11) iterate, see qpat.h.
+static hipError_t launch_pass(Exec& E, int pass, int n, hipStream_t st) {
+  switch (pass) {
+    case 0: return col(E, mpack(MC_DXP, 0, MC_DYP, 0), 1, 2, n, st);
+    case 1: return row(E, RM_F1, n, 0, st);
+    case 2: return col(E, mpack(MC_DXM, 0, 0, MC_DYM), 2, 2, n, st);
+    case 3: return row(E, E.lossy ? RM_F2 : RM_F2L, n, 0, st);
+    case 4: return col(E, mpack(MC_LDIS, 0, 0, MC_LABS), 2, 2, n, st);
+    case 5: return row(E, RM_F3, n, 0, st);
+    case 6: return row(E, E.lossy ? RM_A1 : RM_A1L, n, 0, st);
+    case 7: return col(E, mpack(MC_LDIS, 0, 0, MC_LABS), 2, 2, n, st);
+    case 8: return row(E, RM_A2, n, 0, st);
+    case 9: return col(E, mpack(MC_DXP, 0, 0, MC_DYP), 2, 2, n, st);
+    case 10: return row(E, RM_A3, n, 0, st);
+    case 11: return col(E, mpack(MC_DXM, MC_DYM, 0, 0), 2, 1, n, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+qpat_status qpat_time_pass(qpat_plan P, int32_t pass, int32_t batch, int32_t reps, qpat_stream stream,
+                           float* ms_per_launch) {
+  if (!P || !ms_per_launch) return fail(QPAT_E_INVALID, "NULL argument");
+  if (pass < 0 || pass > 11) return fail(QPAT_E_INVALID, "pass must be in [0, 11]");
+  if (!P->med.lossy && (pass == 4 || pass == 5 || pass == 7 || pass == 8))
+    return fail(QPAT_E_INVALID, "this pass exists only for lossy plans");
+  if (batch < 1 || reps < 1) return fail(QPAT_E_INVALID, "batch and reps must be >= 1");
+  hipStream_t st = (hipStream_t)stream;
+  Exec* E = nullptr;
+  STCHK(plan_exec(P, batch, &E));
+  std::vector<IO> io(batch);
+  for (int i = 0; i < batch; ++i) {
+    io[i].in = P->datas[i];
+    io[i].out = P->datas[i];
+  }
+  STCHK(exec_set_io(*E, io, st));
+  const int n = std::min(1, P->prm.nt - 2);
+  hipEvent_t a, b;
+  HIPCHK(hipEventCreate(&a));
+  HIPCHK(hipEventCreate(&b));
+  hipError_t e = launch_pass(*E, pass, n, st);  // warm-up
+  if (e == hipSuccess) e = hipEventRecord(a, st);
+  for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_pass(*E, pass, n, st);
+  if (e == hipSuccess) e = hipEventRecord(b, st);
+  if (e == hipSuccess) e = hipEventSynchronize(b);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (e != hipSuccess) return fail(QPAT_E_HIP, std::string("time_pass: ") + hipGetErrorString(e));
+  *ms_per_launch = ms / reps;
+  return QPAT_OK;
+}
+
 qpat_status qpat_set_graph(qpat_plan P, int32_t enable) {
   if (!P) return fail(QPAT_E_INVALID, "plan is NULL");
   P->graph = enable != 0;
@@ -1104,8 +1157,9 @@ qpat_status qpat_batch_set_graph(qpat_batch B, int32_t enable) {
 
 // ---- reductions
 qpat_status qpat_dot(const float* a, const float* b, int64_t n, double* out, qpat_stream stream) {
-  if (!a || !b || !out) return fail(QPAT_E_INVALID, "NULL argument");
+  if (!out) return fail(QPAT_E_INVALID, "out is NULL");
   if (n < 0) return fail(QPAT_E_INVALID, "n must be >= 0");
+  if (n > 0 && (!a || !b)) return fail(QPAT_E_INVALID, "NULL input with n > 0");
   static std::mutex mu;
   static std::map<int, double*> partials;
   constexpr int kNblk = 512;

@@ -15,6 +15,12 @@ from ._lib import QpatParams, check, lib
 
 OPS = {"dx+": 0, "dx-": 1, "dy+": 2, "dy-": 3, "ydis": 4, "yabs": 5}
 
+# pass ids of qpat_time_pass: (name, kernel kind)
+PASSES = [("fwd_col_grad_p", "col"), ("fwd_row_velocity", "row"), ("fwd_col_div_v", "col"),
+          ("fwd_row_density", "row"), ("fwd_col_fraclap", "col"), ("fwd_row_pressure", "row"),
+          ("adj_row_pressure", "row"), ("adj_col_fraclap", "col"), ("adj_row_density", "row"),
+          ("adj_col_grad", "col"), ("adj_row_velocity", "row"), ("adj_col_div", "col")]
+
 
 def _stream(stream=None) -> int:
     s = torch.cuda.current_stream() if stream is None else stream
@@ -163,6 +169,13 @@ class Plan:
 
     def set_graph(self, enable: bool = True) -> None:
         check(lib().qpat_set_graph(self._h, int(bool(enable))), "qpat_set_graph")
+
+    def time_pass(self, pass_id: int, batch: int = 1, reps: int = 20, stream=None) -> float:
+        """Mean duration in ms of one launch of a pass kind (qpat_time_pass)."""
+        ms = ctypes.c_float()
+        check(lib().qpat_time_pass(self._h, pass_id, batch, reps, _stream(stream), ctypes.byref(ms)),
+              "qpat_time_pass")
+        return float(ms.value)
 
     def device_bytes(self) -> int:
         n = ctypes.c_size_t()
