@@ -42,7 +42,7 @@ extern "C" {
 typedef enum {
   QPAT_OK = 0,
   QPAT_E_INVALID = 1,     /* bad argument (null pointer, bad size, non-positive medium, ...) */
-  QPAT_E_UNSUPPORTED = 2, /* grid size not 2^a or 3*2^a in [8, 2048], y odd with loss, mixed batch */
+  QPAT_E_UNSUPPORTED = 2, /* grid size not 2^a or 3*2^a in [8, 1024], y odd with loss, mixed batch */
   QPAT_E_UNSTABLE = 3,    /* dt above the k-space stability bound for c_ref < max(c0) */
   QPAT_E_HIP = 4,         /* a HIP runtime call failed (message has the HIP error) */
   QPAT_E_OOM = 5          /* device or pinned host allocation failed */
@@ -54,7 +54,7 @@ typedef void* qpat_stream; /* hipStream_t */
 
 /*
  * Problem parameters (host struct, copied by qpat_plan_create).
- *  nx, ny      grid nodes (each 2^a or 3*2^a, 8 <= n <= 2048); the PML lies
+ *  nx, ny      grid nodes (each 2^a or 3*2^a, 8 <= n <= 1024); the PML lies
  *              inside this grid.
  *  dx, dy, dt  grid spacing [m] and time step [s].
  *  nt          number of time samples (the loop runs n = -1 .. nt-2).
@@ -149,13 +149,18 @@ qpat_status qpat_forward_ckpt(qpat_plan plan, const float* p0, float* data, int3
 qpat_status qpat_replay(qpat_plan plan, const float* p0, const float* ckpt, int32_t interval,
                         int32_t seg, float* states, int32_t batch, qpat_stream stream);
 
-/* Launch shape of the FFT passes: rows per row-pass block and spectrum columns
- * per column-pass block (powers of two dividing ny and nx/2).  qpat_tune times
- * the candidates on `stream` for `batch` vectors (it runs short forward
- * solves, synchronising the stream) and keeps the fastest; results are cached
- * per (nx, ny, batch, lossy) in the file named by QPAT_TUNE_CACHE, if set. */
-qpat_status qpat_set_tiles(qpat_plan plan, int32_t rows, int32_t cols);
-qpat_status qpat_get_tiles(qpat_plan plan, int32_t* rows, int32_t* cols);
+/* Launch shape of the FFT passes: rows per row-pass block, spectrum columns
+ * per column-pass block (powers of two dividing ny and nx/2; rows even) and
+ * threads per block of each pass (64, 128 or 256; rows*nx and cols*ny at most
+ * 8 times the threads).  qpat_tune times the candidates on `stream` for
+ * `batch` vectors (short forward solves, synchronising the stream) and keeps
+ * the fastest; results are cached per (nx, ny, batch, lossy) in the file named
+ * by QPAT_TUNE_CACHE, if set.  row_threads / col_threads may be NULL in
+ * qpat_get_tiles. */
+qpat_status qpat_set_tiles(qpat_plan plan, int32_t rows, int32_t cols, int32_t row_threads,
+                           int32_t col_threads);
+qpat_status qpat_get_tiles(qpat_plan plan, int32_t* rows, int32_t* cols, int32_t* row_threads,
+                           int32_t* col_threads);
 qpat_status qpat_tune(qpat_plan plan, int32_t batch, qpat_stream stream);
 
 /* Diagnostic timing of one pass kind on the plan's work buffers: the

@@ -48,8 +48,9 @@ _SIGS = {
     "qpat_ckpt_bytes": (c_int32, [c_void_p, c_int32, c_int32, ctypes.POINTER(c_size_t)]),
     "qpat_forward_ckpt": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_int32, c_void_p]),
     "qpat_replay": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_void_p, c_int32, c_void_p]),
-    "qpat_set_tiles": (c_int32, [c_void_p, c_int32, c_int32]),
-    "qpat_get_tiles": (c_int32, [c_void_p, ctypes.POINTER(c_int32), ctypes.POINTER(c_int32)]),
+    "qpat_set_tiles": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_int32]),
+    "qpat_get_tiles": (c_int32, [c_void_p, ctypes.POINTER(c_int32), ctypes.POINTER(c_int32),
+                                 ctypes.POINTER(c_int32), ctypes.POINTER(c_int32)]),
     "qpat_tune": (c_int32, [c_void_p, c_int32, c_void_p]),
     "qpat_set_graph": (c_int32, [c_void_p, c_int32]),
     "qpat_time_pass": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_void_p, ctypes.POINTER(ctypes.c_float)]),

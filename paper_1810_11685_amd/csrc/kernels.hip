@@ -81,7 +81,7 @@ template <> __device__ __forceinline__ void bfly<8>(float2* v) {
 // W_{Ns R}^{k r} (k = j mod Ns), writes dst[(j - k) R + k + r Ns].
 template <int R>
 __device__ __forceinline__ void stockham(const float2* src, float2* dst, int j, int nb, int Ns,
-                                         int tws, const float2* __restrict__ tw) {
+                                         int tws, const float2* tw) {
   float2 v[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) v[r] = src[j + r * nb];
@@ -97,11 +97,11 @@ __device__ __forceinline__ void stockham(const float2* src, float2* dst, int j, 
 }
 
 // Forward FFT of `nlines` lines of length n (line stride ls) held in LDS
-// buffer a, using b as the ping-pong partner.  All threads of the block take
-// part; returns the buffer that holds the result.  The caller must have
+// buffer a, using b as the ping-pong partner and the twiddle table tw (LDS).
+// All threads of the block take part; returns the buffer that holds the result.  The caller must have
 // synchronised after writing the input; the routine ends synchronised.
 __device__ float2* fft_lines(float2* a, float2* b, int nlines, int n, int ls, uint32_t rad, int nst,
-                             const float2* __restrict__ tw) {
+                             const float2* tw) {
   int Ns = 1;
   for (int s = 0; s < nst; ++s) {
     const int R = (rad >> (4 * s)) & 15;
@@ -217,12 +217,40 @@ __device__ __forceinline__ float rowpair_val(const float2* buf, int j, int x, in
   return (j & 1) ? -e.y : e.x;
 }
 
+// Sensor taps of the tile's rows (and, in the adjoint, the residual samples
+// they need) are staged in LDS during the load phase; entries beyond the LDS
+// capacity are read from global memory.
+struct TapStage {
+  Tap* tl;     // [kTapCap]
+  float* rv;   // [kTapCap]
+  int e0, e1;  // CSR range of the tile
+};
+
+__device__ __forceinline__ TapStage stage_taps(const Medium& M, void* base, int y0, int rt,
+                                               const float* __restrict__ res, int m) {
+  TapStage T;
+  T.tl = reinterpret_cast<Tap*>(base);
+  T.rv = reinterpret_cast<float*>(T.tl + kTapCap);
+  T.e0 = M.tap_off[y0];
+  T.e1 = M.tap_off[y0 + rt];
+  const int cnt = min(T.e1 - T.e0, kTapCap);
+  for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+    const Tap t = M.taps[T.e0 + i];
+    T.tl[i] = t;
+    if (res) T.rv[i] = res[size_t(m) * M.ns + t.s];
+  }
+  return T;
+}
+
+__device__ __forceinline__ Tap tap_at(const Medium& M, const TapStage& T, int e) {
+  return (e - T.e0 < kTapCap) ? T.tl[e - T.e0] : M.taps[e];
+}
+
 // Forward sensor partials for rows y0 .. y0+rt-1 (bilinear taps, eq num-m).
-__device__ __forceinline__ void sensor_partials(const Medium& M, float2* buf, int y0, int rt,
+__device__ __forceinline__ void sensor_partials(const Medium& M, const TapStage& T, float2* buf, int y0,
                                                 float* __restrict__ part, int m) {
-  const int e0 = M.tap_off[y0], e1 = M.tap_off[y0 + rt];
-  for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-    const Tap t = M.taps[e];
+  for (int e = T.e0 + threadIdx.x; e < T.e1; e += blockDim.x) {
+    const Tap t = tap_at(M, T, e);
     const int j = t.y - y0;
     const float v = t.wl * pcomp(buf, j, t.ixl, M.nx) + t.wr * pcomp(buf, j, t.ixr, M.nx);
     part[(size_t(m) * M.ns + t.s) * 2 + t.slot] = v;
@@ -231,21 +259,30 @@ __device__ __forceinline__ void sensor_partials(const Medium& M, float2* buf, in
 
 // Adjoint sensor scatter M^T r for rows y0 .. y0+rt-1, one thread per row so
 // taps hitting the same node are added in a fixed order.
-__device__ __forceinline__ void sensor_scatter(const Medium& M, float2* buf, int y0, int rt,
-                                               const float* __restrict__ res, int m) {
+__device__ __forceinline__ void sensor_scatter(const Medium& M, const TapStage& T, float2* buf, int y0,
+                                               int rt, const float* __restrict__ res, int m) {
   const int r = threadIdx.x;
   if (r < rt) {
-    const int e0 = M.tap_off[y0 + r], e1 = M.tap_off[y0 + r + 1];
-    for (int e = e0; e < e1; ++e) {
-      const Tap t = M.taps[e];
-      const float rv = res[size_t(m) * M.ns + t.s];
+    const int a = M.tap_off[y0 + r], b = M.tap_off[y0 + r + 1];
+    for (int e = a; e < b; ++e) {
+      const Tap t = tap_at(M, T, e);
+      const float rv = (e - T.e0 < kTapCap) ? T.rv[e - T.e0] : res[size_t(m) * M.ns + t.s];
       pcomp(buf, r, t.ixl, M.nx) += t.wl * rv;
       pcomp(buf, r, t.ixr, M.nx) += t.wr * rv;
     }
   }
 }
 
+__device__ __forceinline__ void load_tw(float2* dst, const float2* __restrict__ tw, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = tw[i];
+}
+
 // ---------------------------------------------------------------- row pass
+// Every global load of a pass is issued in one phase at the start: spectra and
+// twiddles into LDS, pointwise operands into registers (at most kMaxPer
+// elements per thread); the FFT stages then run out of LDS only.
+#define FOR_K _Pragma("unroll") for (int k = 0; k < kMaxPer; ++k)
+
 template <int MODE>
 __global__ void __launch_bounds__(kBlock)
 row_kernel(const Item* __restrict__ items, const IO* __restrict__ io, const int2* __restrict__ map,
@@ -259,254 +296,367 @@ row_kernel(const Item* __restrict__ items, const IO* __restrict__ io, const int2
   if (n > M.nt - 2) return;  // this problem has finished (uneven batches)
   const int nx = M.nx, nxh = M.nxh, rt = M.rt;
   const int y0 = bm.y * rt;
+  const int B = blockDim.x;
   float2* bufA = lds;
   float2* bufB = lds + rt * nx;
+  float2* tw = lds + 2 * rt * nx;
+  void* tap_base = lds + 2 * rt * nx + nx;
   const int tot = rt * nx;
+  const float dt = M.dt;
 
   if constexpr (MODE == RM_F1) {
     // eq num-vel: v_i = A_i (A_i v_i - dt/rho_i d/dr_i^+ p)
+    const bool first = (n == 0);  // v^{-1/2} = 0
+    float vxo[kMaxPer], vyo[kMaxPer], bx[kMaxPer], by[kMaxPer], ax[kMaxPer], ay[kMaxPer];
     load_pair_lines(bufA, W.s0, W.s1, y0, rt, nx, nxh);
-    __syncthreads();
-    float2* r = fft_lines(bufA, bufB, rt, nx, nx, M.radx, M.nstx, M.twx);
-    float2* o = other(r, bufA, bufB);
-    const bool first = (n == 0);
-    for (int it = threadIdx.x; it < tot; it += blockDim.x) {
-      const int j = it / nx, x = it - j * nx, y = y0 + j;
-      const size_t idx = size_t(y) * nx + x;
-      const float2 z = r[it];
-      const float gx = z.x, gy = -z.y;
-      const float vxo = first ? 0.f : W.f0[idx], vyo = first ? 0.f : W.f1[idx];
-      const float ax = M.avx[x], ay = M.avy[y];
-      const float vx = ax * (ax * vxo - M.bx[idx] * gx);
-      const float vy = ay * (ay * vyo - M.by[idx] * gy);
-      W.f0[idx] = vx;
-      W.f1[idx] = vy;
-      o[it] = make_float2(vx, vy);
+    load_tw(tw, M.twx, nx);
+    FOR_K {
+      const int it = threadIdx.x + k * B;
+      if (it < tot) {
+        const int j = it / nx, x = it - j * nx, y = y0 + j;
+        const size_t idx = size_t(y) * nx + x;
+        vxo[k] = first ? 0.f : W.f0[idx];
+        vyo[k] = first ? 0.f : W.f1[idx];
+        bx[k] = M.bx[idx];
+        by[k] = M.by[idx];
+        ax[k] = M.avx[x];
+        ay[k] = M.avy[y];
+      }
     }
     __syncthreads();
-    r = fft_lines(o, other(o, bufA, bufB), rt, nx, nx, M.radx, M.nstx, M.twx);
+    float2* r = fft_lines(bufA, bufB, rt, nx, nx, M.radx, M.nstx, tw);
+    float2* o = other(r, bufA, bufB);
+    FOR_K {
+      const int it = threadIdx.x + k * B;
+      if (it < tot) {
+        const int j = it / nx, x = it - j * nx;
+        const size_t idx = size_t(y0 + j) * nx + x;
+        const float2 z = r[it];
+        const float vx = ax[k] * (ax[k] * vxo[k] - bx[k] * z.x);
+        const float vy = ay[k] * (ay[k] * vyo[k] + by[k] * z.y);
+        W.f0[idx] = vx;
+        W.f1[idx] = vy;
+        o[it] = make_float2(vx, vy);
+      }
+    }
+    __syncthreads();
+    r = fft_lines(o, other(o, bufA, bufB), rt, nx, nx, M.radx, M.nstx, tw);
     store_pair_spectra(r, W.s0, W.s1, y0, rt, nx, nxh);
   } else if constexpr (MODE == RM_F2 || MODE == RM_F2L) {
     // eq num-rho with the additive source of eq s1 (dt s = p0 / (2 d c^2), d = 2)
     const bool skip = (n == -1);  // v^{-1/2} = 0 and rho^{-1} = 0
+    const bool inject = (n <= 0);
+    float rxo[kMaxPer], ryo[kMaxPer], r0[kMaxPer], ax[kMaxPer], ay[kMaxPer], src[kMaxPer], c2[kMaxPer];
+    if (!skip) load_pair_lines(bufA, W.s0, W.s1, y0, rt, nx, nxh);
+    load_tw(tw, M.twx, nx);
+    TapStage T{};
+    if constexpr (MODE == RM_F2L) T = stage_taps(M, tap_base, y0, rt, nullptr, 0);
+    FOR_K {
+      const int it = threadIdx.x + k * B;
+      if (it < tot) {
+        const int j = it / nx, x = it - j * nx, y = y0 + j;
+        const size_t idx = size_t(y) * nx + x;
+        rxo[k] = skip ? 0.f : W.f2[idx];
+        ryo[k] = skip ? 0.f : W.f3[idx];
+        r0[k] = M.rho0[idx];
+        ax[k] = M.arx[x];
+        ay[k] = M.ary[y];
+        c2[k] = (MODE == RM_F2L || inject) ? M.c2[idx] : 0.f;
+        src[k] = inject ? X.in[idx] : 0.f;
+      }
+    }
+    __syncthreads();
     float2* r = nullptr;
     float2* o = bufA;
     if (!skip) {
-      load_pair_lines(bufA, W.s0, W.s1, y0, rt, nx, nxh);
-      __syncthreads();
-      r = fft_lines(bufA, bufB, rt, nx, nx, M.radx, M.nstx, M.twx);
+      r = fft_lines(bufA, bufB, rt, nx, nx, M.radx, M.nstx, tw);
       o = other(r, bufA, bufB);
     }
-    const bool inject = (n <= 0);
-    const float dt = M.dt;
-    for (int it = threadIdx.x; it < tot; it += blockDim.x) {
-      const int j = it / nx, x = it - j * nx, y = y0 + j;
-      const size_t idx = size_t(y) * nx + x;
-      float ex = 0.f, ey = 0.f, rxo = 0.f, ryo = 0.f;
-      if (!skip) {
-        const float2 z = r[it];
-        ex = z.x;
-        ey = -z.y;
-        rxo = W.f2[idx];
-        ryo = W.f3[idx];
-      } else {
-        W.f0[idx] = 0.f;  // the state z_0 holds v^{-1/2} = 0
-        W.f1[idx] = 0.f;
-      }
-      const float ax = M.arx[x], ay = M.ary[y], r0 = M.rho0[idx];
-      const float src = inject ? X.in[idx] * (0.25f / M.c2[idx]) : 0.f;
-      const float rx = ax * (ax * rxo - dt * r0 * ex) + src;
-      const float ry = ay * (ay * ryo - dt * r0 * ey) + src;
-      W.f2[idx] = rx;
-      W.f3[idx] = ry;
-      if constexpr (MODE == RM_F2) {
-        // S = sum_i rho_i and u = rho0 sum_i A_i d/dr_i^- v_i feed eq num-p.
-        // Each is transformed with its own rows paired (S and u differ by
-        // orders of magnitude, so they must not share one complex FFT).
-        pcomp(o, j, x, nx) = rx + ry;
-        pcomp(o + (rt / 2) * nx, j, x, nx) = r0 * (ax * ex + ay * ey);
-      } else {
-        const float p = M.c2[idx] * (rx + ry);
-        pcomp(o, j, x, nx) = p;
-        if (flags & FL_STORE_P) W.q[idx] = p;
+    FOR_K {
+      const int it = threadIdx.x + k * B;
+      if (it < tot) {
+        const int j = it / nx, x = it - j * nx;
+        const size_t idx = size_t(y0 + j) * nx + x;
+        float ex = 0.f, ey = 0.f;
+        if (!skip) {
+          const float2 z = r[it];
+          ex = z.x;
+          ey = -z.y;
+        } else {
+          W.f0[idx] = 0.f;  // the state z_0 holds v^{-1/2} = 0
+          W.f1[idx] = 0.f;
+        }
+        const float s = inject ? src[k] * (0.25f / c2[k]) : 0.f;
+        const float rx = ax[k] * (ax[k] * rxo[k] - dt * r0[k] * ex) + s;
+        const float ry = ay[k] * (ay[k] * ryo[k] - dt * r0[k] * ey) + s;
+        W.f2[idx] = rx;
+        W.f3[idx] = ry;
+        if constexpr (MODE == RM_F2) {
+          // S = sum_i rho_i and u = rho0 sum_i A_i d/dr_i^- v_i feed eq num-p.
+          // Each is transformed with its own rows paired (S and u differ by
+          // orders of magnitude, so they must not share one complex FFT).
+          pcomp(o, j, x, nx) = rx + ry;
+          pcomp(o + (rt / 2) * nx, j, x, nx) = r0[k] * (ax[k] * ex + ay[k] * ey);
+        } else {
+          const float p = c2[k] * (rx + ry);
+          pcomp(o, j, x, nx) = p;
+          if (flags & FL_STORE_P) W.q[idx] = p;
+        }
       }
     }
     __syncthreads();
     if constexpr (MODE == RM_F2) {
-      r = fft_lines(o, other(o, bufA, bufB), rt, nx, nx, M.radx, M.nstx, M.twx);
+      r = fft_lines(o, other(o, bufA, bufB), rt, nx, nx, M.radx, M.nstx, tw);
       store_rowpair_spectra(r, W.s0, y0, rt / 2, nx, nxh);
       store_rowpair_spectra(r + (rt / 2) * nx, W.s1, y0, rt / 2, nx, nxh);
     } else {
-      if (!(flags & FL_NO_SENSORS)) sensor_partials(M, o, y0, rt, W.part, n + 1);
-      r = fft_lines(o, other(o, bufA, bufB), rt / 2, nx, nx, M.radx, M.nstx, M.twx);
+      if (!(flags & FL_NO_SENSORS)) sensor_partials(M, T, o, y0, W.part, n + 1);
+      r = fft_lines(o, other(o, bufA, bufB), rt / 2, nx, nx, M.radx, M.nstx, tw);
       store_rowpair_spectra(r, W.s0, y0, rt / 2, nx, nxh);
     }
   } else if constexpr (MODE == RM_F3) {
     // eq num-p: p = c^2 (S - eta Y_dis S + tau Y_abs u)
+    float rs[kMaxPer], c2[kMaxPer], ce[kMaxPer], ctau[kMaxPer];
     load_rowpair_lines(bufA, W.s0, y0, rt / 2, nx, nxh);
     load_rowpair_lines(bufA + (rt / 2) * nx, W.s1, y0, rt / 2, nx, nxh);
-    __syncthreads();
-    float2* r = fft_lines(bufA, bufB, rt, nx, nx, M.radx, M.nstx, M.twx);
-    float2* o = other(r, bufA, bufB);
-    for (int it = threadIdx.x; it < tot; it += blockDim.x) {
-      const int j = it / nx, x = it - j * nx, y = y0 + j;
-      const size_t idx = size_t(y) * nx + x;
-      const float ys = rowpair_val(r, j, x, nx), yu = rowpair_val(r + (rt / 2) * nx, j, x, nx);
-      const float S = W.f2[idx] + W.f3[idx];
-      const float p = M.c2[idx] * S - M.c2eta[idx] * ys + M.c2tau[idx] * yu;
-      pcomp(o, j, x, nx) = p;
-      if (flags & FL_STORE_P) W.q[idx] = p;
+    load_tw(tw, M.twx, nx);
+    const TapStage T = stage_taps(M, tap_base, y0, rt, nullptr, 0);
+    FOR_K {
+      const int it = threadIdx.x + k * B;
+      if (it < tot) {
+        const int j = it / nx, x = it - j * nx;
+        const size_t idx = size_t(y0 + j) * nx + x;
+        rs[k] = W.f2[idx] + W.f3[idx];
+        c2[k] = M.c2[idx];
+        ce[k] = M.c2eta[idx];
+        ctau[k] = M.c2tau[idx];
+      }
     }
     __syncthreads();
-    if (!(flags & FL_NO_SENSORS)) sensor_partials(M, o, y0, rt, W.part, n + 1);
-    r = fft_lines(o, other(o, bufA, bufB), rt / 2, nx, nx, M.radx, M.nstx, M.twx);
+    float2* r = fft_lines(bufA, bufB, rt, nx, nx, M.radx, M.nstx, tw);
+    float2* o = other(r, bufA, bufB);
+    FOR_K {
+      const int it = threadIdx.x + k * B;
+      if (it < tot) {
+        const int j = it / nx, x = it - j * nx;
+        const float ys = rowpair_val(r, j, x, nx), yu = rowpair_val(r + (rt / 2) * nx, j, x, nx);
+        const float p = c2[k] * rs[k] - ce[k] * ys + ctau[k] * yu;
+        pcomp(o, j, x, nx) = p;
+        if (flags & FL_STORE_P) W.q[size_t(y0 + j) * nx + x] = p;
+      }
+    }
+    __syncthreads();
+    if (!(flags & FL_NO_SENSORS)) sensor_partials(M, T, o, y0, W.part, n + 1);
+    r = fft_lines(o, other(o, bufA, bufB), rt / 2, nx, nx, M.radx, M.nstx, tw);
     store_rowpair_spectra(r, W.s0, y0, rt / 2, nx, nxh);
   } else if constexpr (MODE == RM_A1 || MODE == RM_A1L) {
     // transpose of eqs num-m and num-p: p* += M^T r_{n+1}; q = c^2 p*
     const bool first = (n == M.nt - 2);
     const int half = rt / 2;
+    float c2[kMaxPer], ce[kMaxPer], ctau[kMaxPer], rbx0[kMaxPer], rby0[kMaxPer], r0[kMaxPer];
+    float ax[kMaxPer], ay[kMaxPer], gacc[kMaxPer];
+    if (!first) load_rowpair_lines(bufA, W.s0, y0, half, nx, nxh);
+    load_tw(tw, M.twx, nx);
+    const TapStage T = stage_taps(M, tap_base, y0, rt, X.in, n + 1);
+    FOR_K {
+      const int it = threadIdx.x + k * B;
+      if (it < tot) {
+        const int j = it / nx, x = it - j * nx, y = y0 + j;
+        const size_t idx = size_t(y) * nx + x;
+        c2[k] = M.c2[idx];
+        if constexpr (MODE == RM_A1) {
+          ce[k] = M.c2eta[idx];
+          ctau[k] = M.c2tau[idx];
+        } else {
+          rbx0[k] = first ? 0.f : W.f2[idx];
+          rby0[k] = first ? 0.f : W.f3[idx];
+          r0[k] = M.rho0[idx];
+          ax[k] = M.arx[x];
+          ay[k] = M.ary[y];
+          gacc[k] = (n == -1 && M.nt >= 2) ? X.out[idx] : 0.f;
+        }
+      }
+    }
+    __syncthreads();
     float2* r = bufA;
     if (!first) {
-      load_rowpair_lines(bufA, W.s0, y0, half, nx, nxh);
-      __syncthreads();
-      r = fft_lines(bufA, bufB, half, nx, nx, M.radx, M.nstx, M.twx);
+      r = fft_lines(bufA, bufB, half, nx, nx, M.radx, M.nstx, tw);
       // p* = -(grad_x^- g_x + grad_y^- g_y): negate the (conjugated) inverse
-      for (int it = threadIdx.x; it < half * nx; it += blockDim.x) {
+      for (int it = threadIdx.x; it < half * nx; it += B) {
         const float2 z = r[it];
         r[it] = make_float2(-z.x, z.y);
       }
     } else {
-      for (int it = threadIdx.x; it < half * nx; it += blockDim.x) r[it] = make_float2(0.f, 0.f);
+      for (int it = threadIdx.x; it < half * nx; it += B) r[it] = make_float2(0.f, 0.f);
     }
     __syncthreads();
-    sensor_scatter(M, r, y0, rt, X.in, n + 1);
+    sensor_scatter(M, T, r, y0, rt, X.in, n + 1);
     __syncthreads();
     float2* o = other(r, bufA, bufB);
-    const float dt = M.dt;
-    for (int it = threadIdx.x; it < tot; it += blockDim.x) {
-      const int j = it / nx, x = it - j * nx, y = y0 + j;
-      const size_t idx = size_t(y) * nx + x;
-      const float pb = pcomp(r, j, x, nx);
-      if constexpr (MODE == RM_A1) {
-        // eta q and tau q, each with its own rows paired (see RM_F2)
-        W.q[idx] = M.c2[idx] * pb;
-        pcomp(o, j, x, nx) = M.c2eta[idx] * pb;
-        pcomp(o + half * nx, j, x, nx) = M.c2tau[idx] * pb;
-      } else {
-        // lossless: S* = q, u* = 0, then the transposed mass update
-        const float q = M.c2[idx] * pb;
-        const float rbx = (first ? 0.f : W.f2[idx]) + q;
-        const float rby = (first ? 0.f : W.f3[idx]) + q;
-        float* gout = X.out;
-        if (n == 0) gout[idx] = rbx + rby;
-        if (n == -1) {
-          float g = rbx + rby;
-          if (M.nt >= 2) g += gout[idx];
-          gout[idx] = g * (0.25f / M.c2[idx]);
+    FOR_K {
+      const int it = threadIdx.x + k * B;
+      if (it < tot) {
+        const int j = it / nx, x = it - j * nx;
+        const size_t idx = size_t(y0 + j) * nx + x;
+        const float pb = pcomp(r, j, x, nx);
+        if constexpr (MODE == RM_A1) {
+          // eta q and tau q, each with its own rows paired (see RM_F2)
+          W.q[idx] = c2[k] * pb;
+          pcomp(o, j, x, nx) = ce[k] * pb;
+          pcomp(o + half * nx, j, x, nx) = ctau[k] * pb;
         } else {
-          const float ax = M.arx[x], ay = M.ary[y], r0 = M.rho0[idx];
-          o[it] = make_float2(-dt * r0 * ax * rbx, -dt * r0 * ay * rby);
-          W.f2[idx] = ax * ax * rbx;
-          W.f3[idx] = ay * ay * rby;
+          // lossless: S* = q, u* = 0, then the transposed mass update
+          const float q = c2[k] * pb;
+          const float rbx = rbx0[k] + q, rby = rby0[k] + q;
+          if (n == 0) X.out[idx] = rbx + rby;
+          if (n == -1) {
+            X.out[idx] = (rbx + rby + gacc[k]) * (0.25f / c2[k]);
+          } else {
+            o[it] = make_float2(-dt * r0[k] * ax[k] * rbx, -dt * r0[k] * ay[k] * rby);
+            W.f2[idx] = ax[k] * ax[k] * rbx;
+            W.f3[idx] = ay[k] * ay[k] * rby;
+          }
         }
       }
     }
     __syncthreads();
     if constexpr (MODE == RM_A1) {
-      r = fft_lines(o, other(o, bufA, bufB), rt, nx, nx, M.radx, M.nstx, M.twx);
+      r = fft_lines(o, other(o, bufA, bufB), rt, nx, nx, M.radx, M.nstx, tw);
       store_rowpair_spectra(r, W.s0, y0, half, nx, nxh);
       store_rowpair_spectra(r + half * nx, W.s1, y0, half, nx, nxh);
     } else if (n != -1) {
-      r = fft_lines(o, other(o, bufA, bufB), rt, nx, nx, M.radx, M.nstx, M.twx);
+      r = fft_lines(o, other(o, bufA, bufB), rt, nx, nx, M.radx, M.nstx, tw);
       store_pair_spectra(r, W.s0, W.s1, y0, rt, nx, nxh);
     }
   } else if constexpr (MODE == RM_A2) {
     // transpose of the mass update and of the Y terms of eq num-p
+    const bool first = (n == M.nt - 2);
+    float qv[kMaxPer], rbx0[kMaxPer], rby0[kMaxPer], r0[kMaxPer], ax[kMaxPer], ay[kMaxPer];
+    float c2[kMaxPer], gacc[kMaxPer];
     load_rowpair_lines(bufA, W.s0, y0, rt / 2, nx, nxh);
     load_rowpair_lines(bufA + (rt / 2) * nx, W.s1, y0, rt / 2, nx, nxh);
+    load_tw(tw, M.twx, nx);
+    FOR_K {
+      const int it = threadIdx.x + k * B;
+      if (it < tot) {
+        const int j = it / nx, x = it - j * nx, y = y0 + j;
+        const size_t idx = size_t(y) * nx + x;
+        qv[k] = W.q[idx];
+        rbx0[k] = first ? 0.f : W.f2[idx];
+        rby0[k] = first ? 0.f : W.f3[idx];
+        r0[k] = M.rho0[idx];
+        ax[k] = M.arx[x];
+        ay[k] = M.ary[y];
+        c2[k] = (n == -1) ? M.c2[idx] : 1.f;
+        gacc[k] = (n == -1 && M.nt >= 2) ? X.out[idx] : 0.f;
+      }
+    }
     __syncthreads();
-    float2* r = fft_lines(bufA, bufB, rt, nx, nx, M.radx, M.nstx, M.twx);
+    float2* r = fft_lines(bufA, bufB, rt, nx, nx, M.radx, M.nstx, tw);
     float2* o = other(r, bufA, bufB);
-    const bool first = (n == M.nt - 2);
-    const float dt = M.dt;
-    float* gout = X.out;
-    for (int it = threadIdx.x; it < tot; it += blockDim.x) {
-      const int j = it / nx, x = it - j * nx, y = y0 + j;
-      const size_t idx = size_t(y) * nx + x;
-      const float yd = rowpair_val(r, j, x, nx), ya = rowpair_val(r + (rt / 2) * nx, j, x, nx);
-      const float sb = W.q[idx] - yd;
-      const float rbx = (first ? 0.f : W.f2[idx]) + sb;
-      const float rby = (first ? 0.f : W.f3[idx]) + sb;
-      if (n == 0) gout[idx] = rbx + rby;
-      if (n == -1) {
-        float g = rbx + rby;
-        if (M.nt >= 2) g += gout[idx];
-        gout[idx] = g * (0.25f / M.c2[idx]);
-      } else {
-        const float ax = M.arx[x], ay = M.ary[y], r0 = M.rho0[idx];
-        o[it] = make_float2(r0 * ax * (ya - dt * rbx), r0 * ay * (ya - dt * rby));
-        W.f2[idx] = ax * ax * rbx;
-        W.f3[idx] = ay * ay * rby;
+    FOR_K {
+      const int it = threadIdx.x + k * B;
+      if (it < tot) {
+        const int j = it / nx, x = it - j * nx;
+        const size_t idx = size_t(y0 + j) * nx + x;
+        const float yd = rowpair_val(r, j, x, nx), ya = rowpair_val(r + (rt / 2) * nx, j, x, nx);
+        const float sb = qv[k] - yd;
+        const float rbx = rbx0[k] + sb, rby = rby0[k] + sb;
+        if (n == 0) X.out[idx] = rbx + rby;
+        if (n == -1) {
+          X.out[idx] = (rbx + rby + gacc[k]) * (0.25f / c2[k]);
+        } else {
+          o[it] = make_float2(r0[k] * ax[k] * (ya - dt * rbx), r0[k] * ay[k] * (ya - dt * rby));
+          W.f2[idx] = ax[k] * ax[k] * rbx;
+          W.f3[idx] = ay[k] * ay[k] * rby;
+        }
       }
     }
     __syncthreads();
     if (n != -1) {
-      r = fft_lines(o, other(o, bufA, bufB), rt, nx, nx, M.radx, M.nstx, M.twx);
+      r = fft_lines(o, other(o, bufA, bufB), rt, nx, nx, M.radx, M.nstx, tw);
       store_pair_spectra(r, W.s0, W.s1, y0, rt, nx, nxh);
     }
   } else if constexpr (MODE == RM_A3) {
     // transpose of eq num-vel
-    load_pair_lines(bufA, W.s0, W.s1, y0, rt, nx, nxh);
-    __syncthreads();
-    float2* r = fft_lines(bufA, bufB, rt, nx, nx, M.radx, M.nstx, M.twx);
-    float2* o = other(r, bufA, bufB);
     const bool first = (n == M.nt - 2);
-    for (int it = threadIdx.x; it < tot; it += blockDim.x) {
-      const int j = it / nx, x = it - j * nx, y = y0 + j;
-      const size_t idx = size_t(y) * nx + x;
-      const float2 z = r[it];
-      const float vbx = (first ? 0.f : W.f0[idx]) - z.x;
-      const float vby = (first ? 0.f : W.f1[idx]) + z.y;
-      const float ax = M.avx[x], ay = M.avy[y];
-      o[it] = make_float2(-ax * M.bx[idx] * vbx, -ay * M.by[idx] * vby);
-      W.f0[idx] = ax * ax * vbx;
-      W.f1[idx] = ay * ay * vby;
+    float vbx0[kMaxPer], vby0[kMaxPer], bx[kMaxPer], by[kMaxPer], ax[kMaxPer], ay[kMaxPer];
+    load_pair_lines(bufA, W.s0, W.s1, y0, rt, nx, nxh);
+    load_tw(tw, M.twx, nx);
+    FOR_K {
+      const int it = threadIdx.x + k * B;
+      if (it < tot) {
+        const int j = it / nx, x = it - j * nx, y = y0 + j;
+        const size_t idx = size_t(y) * nx + x;
+        vbx0[k] = first ? 0.f : W.f0[idx];
+        vby0[k] = first ? 0.f : W.f1[idx];
+        bx[k] = M.bx[idx];
+        by[k] = M.by[idx];
+        ax[k] = M.avx[x];
+        ay[k] = M.avy[y];
+      }
     }
     __syncthreads();
-    r = fft_lines(o, other(o, bufA, bufB), rt, nx, nx, M.radx, M.nstx, M.twx);
+    float2* r = fft_lines(bufA, bufB, rt, nx, nx, M.radx, M.nstx, tw);
+    float2* o = other(r, bufA, bufB);
+    FOR_K {
+      const int it = threadIdx.x + k * B;
+      if (it < tot) {
+        const int j = it / nx, x = it - j * nx;
+        const size_t idx = size_t(y0 + j) * nx + x;
+        const float2 z = r[it];
+        const float vbx = vbx0[k] - z.x;
+        const float vby = vby0[k] + z.y;
+        o[it] = make_float2(-ax[k] * bx[k] * vbx, -ay[k] * by[k] * vby);
+        W.f0[idx] = ax[k] * ax[k] * vbx;
+        W.f1[idx] = ay[k] * ay[k] * vby;
+      }
+    }
+    __syncthreads();
+    r = fft_lines(o, other(o, bufA, bufB), rt, nx, nx, M.radx, M.nstx, tw);
     store_pair_spectra(r, W.s0, W.s1, y0, rt, nx, nxh);
   } else if constexpr (MODE == RM_FWD1) {
     const float* src = X.in;
-    for (int it = threadIdx.x; it < tot; it += blockDim.x) {
+    load_tw(tw, M.twx, nx);
+    for (int it = threadIdx.x; it < tot; it += B) {
       const int j = it / nx, x = it - j * nx;
       pcomp(bufA, j, x, nx) = src[size_t(y0 + j) * nx + x];
     }
     __syncthreads();
-    float2* r = fft_lines(bufA, bufB, rt / 2, nx, nx, M.radx, M.nstx, M.twx);
+    float2* r = fft_lines(bufA, bufB, rt / 2, nx, nx, M.radx, M.nstx, tw);
     store_rowpair_spectra(r, W.s0, y0, rt / 2, nx, nxh);
   } else if constexpr (MODE == RM_INV1) {
     load_rowpair_lines(bufA, W.s0, y0, rt / 2, nx, nxh);
+    load_tw(tw, M.twx, nx);
     __syncthreads();
-    float2* r = fft_lines(bufA, bufB, rt / 2, nx, nx, M.radx, M.nstx, M.twx);
+    float2* r = fft_lines(bufA, bufB, rt / 2, nx, nx, M.radx, M.nstx, tw);
     float* dst = X.out;
-    for (int it = threadIdx.x; it < tot; it += blockDim.x) {
+    for (int it = threadIdx.x; it < tot; it += B) {
       const int j = it / nx, x = it - j * nx;
-      const float v = pcomp(r, j, x, nx);
-      dst[size_t(y0 + j) * nx + x] = (j & 1) ? -v : v;
+      dst[size_t(y0 + j) * nx + x] = rowpair_val(r, j, x, nx);
     }
   }
 }
 
 // ---------------------------------------------------------------- column pass
-__device__ __forceinline__ float2 mult_val(const Medium& M, int code, int kx, int ky) {
-  const int t = ky * (M.nxh + 1) + kx;
+// Multipliers of a launch are either the staggered gradients (kappa times a
+// 1-D symbol in x or y) or the fractional-Laplacian tables; the values a
+// thread needs are prefetched into registers in the load phase.
+struct MultPre {
+  float a, b;     // table A / B at (kx, ky): kappa (or Y_dis) and Y_abs
+  float an, bn;   // the same at the Nyquist column (packed column 0 only)
+  float2 sx, sxn; // x symbol at kx and at the Nyquist column
+  float2 sy;      // y symbol at ky
+};
+
+__device__ __forceinline__ float2 mult_of(int code, const MultPre& P, bool nyq) {
   switch (code) {
-    case MC_DXP: return cscale(M.dxp[kx], M.kap[t]);
-    case MC_DXM: return cscale(M.dxm[kx], M.kap[t]);
-    case MC_DYP: return cscale(M.dyp[ky], M.kap[t]);
-    case MC_DYM: return cscale(M.dym[ky], M.kap[t]);
-    case MC_LDIS: return make_float2(M.ldis[t], 0.f);
-    case MC_LABS: return make_float2(M.labs[t], 0.f);
+    case MC_DXP:
+    case MC_DXM: return cscale(nyq ? P.sxn : P.sx, nyq ? P.an : P.a);
+    case MC_DYP:
+    case MC_DYM: return cscale(P.sy, nyq ? P.an : P.a);
+    case MC_LDIS: return make_float2(nyq ? P.an : P.a, 0.f);
+    case MC_LABS: return make_float2(nyq ? P.bn : P.b, 0.f);
     default: return make_float2(0.f, 0.f);
   }
 }
@@ -522,58 +672,97 @@ col_kernel(const Item* __restrict__ items, const int2* __restrict__ map, int mco
   if (n > M.nt - 2) return;
   const int ny = M.ny, nxh = M.nxh, ct = M.ct, ls = col_line_stride(ny, ct);
   const int c0 = bm.y * ct;
-  const int nsl = nin > nout ? nin : nout;
+  const int B = blockDim.x;
+  const int nsl = 2;
   float2* bufA = lds;
   float2* bufB = lds + nsl * ct * ls;
-  // load the tile, transposed into lines (field, column)
-  for (int it = threadIdx.x; it < nin * ct * ny; it += blockDim.x) {
+  float2* tw = lds + 2 * nsl * ct * ls;
+  // which tables this launch uses
+  int xcode = 0, ycode = 0;
+  bool frac = false, labs = false;
+  for (int e = 0; e < 4; ++e) {
+    const int c = (mcode >> (4 * e)) & 15;
+    if (c == MC_DXP || c == MC_DXM) xcode = c;
+    if (c == MC_DYP || c == MC_DYM) ycode = c;
+    if (c == MC_LDIS) frac = true;
+    if (c == MC_LABS) { frac = true; labs = true; }
+  }
+  const float* tabA = frac ? M.ldis : M.kap;
+  const float2* symx = xcode == MC_DXP ? M.dxp : M.dxm;
+  const float2* symy = ycode == MC_DYP ? M.dyp : M.dym;
+  // load phase: the tile (transposed into lines), twiddles, multiplier values
+  for (int it = threadIdx.x; it < nin * ct * ny; it += B) {
     const int c = it % ct, rest = it / ct;
     const int ky = rest % ny, f = rest / ny;
     const float2* s = f ? W.s1 : W.s0;
     bufA[(f * ct + c) * ls + ky] = s[size_t(ky) * nxh + c0 + c];
   }
-  __syncthreads();
-  float2* r = fft_lines(bufA, bufB, nin * ct, ny, ls, M.rady, M.nsty, M.twy);
-  float2* o = other(r, bufA, bufB);
-  for (int it = threadIdx.x; it < ct * ny; it += blockDim.x) {
-    const int c = it / ny, ky = it - c * ny;
-    const int kx = c0 + c;
-    if (kx == 0) {
-      // packed column: DC (real part) and Nyquist (imaginary part) columns
-      const int km = ky ? ny - ky : 0;
-      float2 f0[2], fn[2];
-      for (int f = 0; f < nin; ++f) {
-        const float2 z = r[(f * ct + c) * ls + ky], zm = cconj(r[(f * ct + c) * ls + km]);
-        f0[f] = cscale(cadd(z, zm), 0.5f);
-        fn[f] = mul_mi(cscale(csub(z, zm), 0.5f));
-      }
-      for (int q = 0; q < nout; ++q) {
-        float2 g0 = make_float2(0.f, 0.f), gn = make_float2(0.f, 0.f);
-        for (int f = 0; f < nin; ++f) {
-          const int code = (mcode >> (4 * (2 * q + f))) & 15;
-          if (!code) continue;
-          g0 = cadd(g0, cmul(mult_val(M, code, 0, ky), f0[f]));
-          gn = cadd(gn, cmul(mult_val(M, code, nxh, ky), fn[f]));
-        }
-        // W = G0 + i GN, stored conjugated for the inverse transform
-        o[(q * ct + c) * ls + ky] = cconj(make_float2(g0.x - gn.y, g0.y + gn.x));
-      }
-    } else {
-      float2 in[2];
-      for (int f = 0; f < nin; ++f) in[f] = r[(f * ct + c) * ls + ky];
-      for (int q = 0; q < nout; ++q) {
-        float2 acc = make_float2(0.f, 0.f);
-        for (int f = 0; f < nin; ++f) {
-          const int code = (mcode >> (4 * (2 * q + f))) & 15;
-          if (code) acc = cadd(acc, cmul(mult_val(M, code, kx, ky), in[f]));
-        }
-        o[(q * ct + c) * ls + ky] = cconj(acc);
+  load_tw(tw, M.twy, ny);
+  const int tot = ct * ny;
+  MultPre P[kMaxPer];
+  FOR_K {
+    const int it = threadIdx.x + k * B;
+    if (it < tot) {
+      const int c = it / ny, ky = it - c * ny, kx = c0 + c;
+      const int t = ky * (nxh + 1) + kx;
+      MultPre& p = P[k];
+      p.a = tabA[t];
+      p.b = labs ? M.labs[t] : 0.f;
+      p.sx = xcode ? symx[kx] : make_float2(0.f, 0.f);
+      p.sy = ycode ? symy[ky] : make_float2(0.f, 0.f);
+      if (kx == 0) {
+        p.an = tabA[t + nxh];
+        p.bn = labs ? M.labs[t + nxh] : 0.f;
+        p.sxn = xcode ? symx[nxh] : make_float2(0.f, 0.f);
       }
     }
   }
   __syncthreads();
-  r = fft_lines(o, other(o, bufA, bufB), nout * ct, ny, ls, M.rady, M.nsty, M.twy);
-  for (int it = threadIdx.x; it < nout * ct * ny; it += blockDim.x) {
+  float2* r = fft_lines(bufA, bufB, nin * ct, ny, ls, M.rady, M.nsty, tw);
+  float2* o = other(r, bufA, bufB);
+  FOR_K {
+    const int it = threadIdx.x + k * B;
+    if (it < tot) {
+      const int c = it / ny, ky = it - c * ny;
+      const int kx = c0 + c;
+      const MultPre& p = P[k];
+      if (kx == 0) {
+        // packed column: DC (real part) and Nyquist (imaginary part) columns
+        const int km = ky ? ny - ky : 0;
+        float2 f0[2], fn[2];
+        for (int f = 0; f < nin; ++f) {
+          const float2 z = r[(f * ct + c) * ls + ky], zm = cconj(r[(f * ct + c) * ls + km]);
+          f0[f] = cscale(cadd(z, zm), 0.5f);
+          fn[f] = mul_mi(cscale(csub(z, zm), 0.5f));
+        }
+        for (int q = 0; q < nout; ++q) {
+          float2 g0 = make_float2(0.f, 0.f), gn = make_float2(0.f, 0.f);
+          for (int f = 0; f < nin; ++f) {
+            const int code = (mcode >> (4 * (2 * q + f))) & 15;
+            if (!code) continue;
+            g0 = cadd(g0, cmul(mult_of(code, p, false), f0[f]));
+            gn = cadd(gn, cmul(mult_of(code, p, true), fn[f]));
+          }
+          // W = G0 + i GN, stored conjugated for the inverse transform
+          o[(q * ct + c) * ls + ky] = cconj(make_float2(g0.x - gn.y, g0.y + gn.x));
+        }
+      } else {
+        float2 in[2];
+        for (int f = 0; f < nin; ++f) in[f] = r[(f * ct + c) * ls + ky];
+        for (int q = 0; q < nout; ++q) {
+          float2 acc = make_float2(0.f, 0.f);
+          for (int f = 0; f < nin; ++f) {
+            const int code = (mcode >> (4 * (2 * q + f))) & 15;
+            if (code) acc = cadd(acc, cmul(mult_of(code, p, false), in[f]));
+          }
+          o[(q * ct + c) * ls + ky] = cconj(acc);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  r = fft_lines(o, other(o, bufA, bufB), nout * ct, ny, ls, M.rady, M.nsty, tw);
+  for (int it = threadIdx.x; it < nout * ct * ny; it += B) {
     const int c = it % ct, rest = it / ct;
     const int ky = rest % ny, f = rest / ny;
     float2* s = f ? W.s1 : W.s0;
@@ -630,32 +819,32 @@ __global__ void __launch_bounds__(kBlock) dot_final(const double* __restrict__ p
 
 // ---------------------------------------------------------------- launchers
 template <int MODE>
-static hipError_t launch_row_t(const Item* items, const IO* io, const int2* map, int nblocks,
+static hipError_t launch_row_t(const Item* items, const IO* io, const int2* map, int nblocks, int threads,
                                size_t lds, int n, int flags, hipStream_t st) {
-  hipLaunchKernelGGL(row_kernel<MODE>, dim3(nblocks), dim3(kBlock), lds, st, items, io, map, n, flags);
+  hipLaunchKernelGGL(row_kernel<MODE>, dim3(nblocks), dim3(threads), lds, st, items, io, map, n, flags);
   return hipGetLastError();
 }
 
-hipError_t launch_row(int mode, const Item* items, const IO* io, const int2* map, int nblocks,
+hipError_t launch_row(int mode, const Item* items, const IO* io, const int2* map, int nblocks, int threads,
                       size_t lds, int n, int flags, hipStream_t st) {
   switch (mode) {
-    case RM_F1: return launch_row_t<RM_F1>(items, io, map, nblocks, lds, n, flags, st);
-    case RM_F2: return launch_row_t<RM_F2>(items, io, map, nblocks, lds, n, flags, st);
-    case RM_F2L: return launch_row_t<RM_F2L>(items, io, map, nblocks, lds, n, flags, st);
-    case RM_F3: return launch_row_t<RM_F3>(items, io, map, nblocks, lds, n, flags, st);
-    case RM_A1: return launch_row_t<RM_A1>(items, io, map, nblocks, lds, n, flags, st);
-    case RM_A1L: return launch_row_t<RM_A1L>(items, io, map, nblocks, lds, n, flags, st);
-    case RM_A2: return launch_row_t<RM_A2>(items, io, map, nblocks, lds, n, flags, st);
-    case RM_A3: return launch_row_t<RM_A3>(items, io, map, nblocks, lds, n, flags, st);
-    case RM_FWD1: return launch_row_t<RM_FWD1>(items, io, map, nblocks, lds, n, flags, st);
-    case RM_INV1: return launch_row_t<RM_INV1>(items, io, map, nblocks, lds, n, flags, st);
+    case RM_F1: return launch_row_t<RM_F1>(items, io, map, nblocks, threads, lds, n, flags, st);
+    case RM_F2: return launch_row_t<RM_F2>(items, io, map, nblocks, threads, lds, n, flags, st);
+    case RM_F2L: return launch_row_t<RM_F2L>(items, io, map, nblocks, threads, lds, n, flags, st);
+    case RM_F3: return launch_row_t<RM_F3>(items, io, map, nblocks, threads, lds, n, flags, st);
+    case RM_A1: return launch_row_t<RM_A1>(items, io, map, nblocks, threads, lds, n, flags, st);
+    case RM_A1L: return launch_row_t<RM_A1L>(items, io, map, nblocks, threads, lds, n, flags, st);
+    case RM_A2: return launch_row_t<RM_A2>(items, io, map, nblocks, threads, lds, n, flags, st);
+    case RM_A3: return launch_row_t<RM_A3>(items, io, map, nblocks, threads, lds, n, flags, st);
+    case RM_FWD1: return launch_row_t<RM_FWD1>(items, io, map, nblocks, threads, lds, n, flags, st);
+    case RM_INV1: return launch_row_t<RM_INV1>(items, io, map, nblocks, threads, lds, n, flags, st);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_col(int mcode, int nin, int nout, const Item* items, const int2* map, int nblocks,
-                      size_t lds, int n, int /*reverse*/, hipStream_t st) {
-  hipLaunchKernelGGL(col_kernel, dim3(nblocks), dim3(kBlock), lds, st, items, map, mcode, nin, nout, n);
+                      int threads, size_t lds, int n, hipStream_t st) {
+  hipLaunchKernelGGL(col_kernel, dim3(nblocks), dim3(threads), lds, st, items, map, mcode, nin, nout, n);
   return hipGetLastError();
 }
 

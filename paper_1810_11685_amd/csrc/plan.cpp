@@ -44,7 +44,7 @@ qpat_status fail(qpat_status s, const std::string& msg) {
     if (s_ != QPAT_OK) return s_;   \
   } while (0)
 
-constexpr int kMaxN = 2048;
+constexpr int kMaxN = 1024;
 constexpr int kMinN = 8;
 constexpr size_t kMaxLds = 65536;
 
@@ -89,20 +89,34 @@ int pow2_floor(int v) {
 }
 int pow2_divisor(int v) { return v & (-v); }
 
-bool row_tile_ok(int nx, int ny, int rt) {
-  return rt >= 2 && (rt & (rt - 1)) == 0 && ny % rt == 0 && row_lds_bytes(nx, rt) <= kMaxLds;
+bool threads_ok(int t) { return t == 64 || t == 128 || t == 256; }
+
+// A row tile of rt rows (rt even, dividing ny) fits the LDS limit and leaves
+// at most kMaxPer pointwise elements per thread.
+bool row_tile_ok(int nx, int ny, int rt, int thr) {
+  return rt >= 2 && (rt & (rt - 1)) == 0 && ny % rt == 0 && row_lds_bytes(nx, rt) <= kMaxLds &&
+         threads_ok(thr) && rt * nx <= kMaxPer * thr;
 }
-bool col_tile_ok(int nxh, int ny, int ct) {
-  return ct >= 1 && (ct & (ct - 1)) == 0 && nxh % ct == 0 && col_lds_bytes(ny, ct) <= kMaxLds;
+bool col_tile_ok(int nxh, int ny, int ct, int thr) {
+  return ct >= 1 && (ct & (ct - 1)) == 0 && nxh % ct == 0 && col_lds_bytes(ny, ct) <= kMaxLds &&
+         threads_ok(thr) && ct * ny <= kMaxPer * thr;
 }
 
-void default_tiles(int nx, int ny, int* rt, int* ct) {
-  int r = 16;
-  while (r > 2 && !(row_tile_ok(nx, ny, r) && row_lds_bytes(nx, r) <= 32768)) r /= 2;
-  int c = 16;
-  while (c > 1 && !(col_tile_ok(nx / 2, ny, c) && col_lds_bytes(ny, c) <= 32768)) c /= 2;
+// Defaults: small tiles (many blocks) with enough threads to keep every
+// thread busy in the radix-8 stages.
+void default_tiles(int nx, int ny, int* rt, int* ct, int* rthr, int* cthr) {
+  int r = 2;
+  while (r < 16 && r * nx < 2048 && row_tile_ok(nx, ny, 2 * r, 256)) r *= 2;
+  int rthr_ = 64;
+  while (rthr_ < 256 && (r * nx / 8 > rthr_ || !row_tile_ok(nx, ny, r, rthr_))) rthr_ *= 2;
+  int c = 1;
+  while (c < 16 && c * ny < 1024 && col_tile_ok(nx / 2, ny, 2 * c, 256)) c *= 2;
+  int cthr_ = 64;
+  while (cthr_ < 256 && (2 * c * ny / 8 > cthr_ || !col_tile_ok(nx / 2, ny, c, cthr_))) cthr_ *= 2;
   *rt = r;
   *ct = c;
+  *rthr = rthr_;
+  *cthr = cthr_;
 }
 
 }  // namespace
@@ -118,6 +132,7 @@ struct Exec {
   int2* d_colmap = nullptr;
   int nrow = 0, ncol = 0;
   size_t row_lds = 0, col_lds = 0;
+  int rthr = kBlock, cthr = kBlock;  // threads per block (max over items)
   int max_nt = 0, max_data = 0;
   bool lossy = false;
   // pinned staging ring for the I/O table
@@ -177,6 +192,7 @@ qpat_status exec_build(Exec& E, const std::vector<Item>& items) {
   E.max_nt = 0;
   E.max_data = 0;
   E.row_lds = E.col_lds = 0;
+  E.rthr = E.cthr = 0;
   E.lossy = items[0].m.lossy != 0;
   for (int i = 0; i < ni; ++i) {
     const Medium& m = items[i].m;
@@ -186,6 +202,8 @@ qpat_status exec_build(Exec& E, const std::vector<Item>& items) {
     E.max_data = std::max(E.max_data, m.nt * m.ns);
     E.row_lds = std::max(E.row_lds, row_lds_bytes(m.nx, m.rt));
     E.col_lds = std::max(E.col_lds, col_lds_bytes(m.ny, m.ct));
+    E.rthr = std::max(E.rthr, m.rthr);
+    E.cthr = std::max(E.cthr, m.cthr);
   }
   const std::vector<int2> rm = xcd_map(rows), cm = xcd_map(cols);
   E.nrow = int(rm.size());
@@ -219,10 +237,10 @@ qpat_status exec_set_io(Exec& E, const std::vector<IO>& io, hipStream_t st) {
 }
 
 hipError_t row(Exec& E, int mode, int n, int flags, hipStream_t st) {
-  return launch_row(mode, E.d_items, E.d_io, E.d_rowmap, E.nrow, E.row_lds, n, flags, st);
+  return launch_row(mode, E.d_items, E.d_io, E.d_rowmap, E.nrow, E.rthr, E.row_lds, n, flags, st);
 }
 hipError_t col(Exec& E, int mcode, int nin, int nout, int n, hipStream_t st) {
-  return launch_col(mcode, nin, nout, E.d_items, E.d_colmap, E.ncol, E.col_lds, n, 0, st);
+  return launch_col(mcode, nin, nout, E.d_items, E.d_colmap, E.ncol, E.cthr, E.col_lds, n, st);
 }
 
 #define LCHK(expr)                           \
@@ -320,7 +338,7 @@ struct qpat_plan_s {
   // executors per batch size (rebuilt when tiles change)
   std::map<int, std::unique_ptr<Exec>> execs;
   bool graph = false;
-  int rt = 2, ct = 1;
+  int rt = 2, ct = 1, rthr = kBlock, cthr = kBlock;
 };
 
 struct qpat_batch_s {
@@ -344,7 +362,7 @@ qpat_status validate(const qpat_params* p) {
   uint32_t r;
   int s;
   if (!radix_plan(p->nx, &r, &s) || !radix_plan(p->ny, &r, &s))
-    return fail(QPAT_E_UNSUPPORTED, "nx, ny must be 2^a or 3*2^a in [8, 2048] (got " +
+    return fail(QPAT_E_UNSUPPORTED, "nx, ny must be 2^a or 3*2^a in [8, 1024] (got " +
                                         std::to_string(p->nx) + " x " + std::to_string(p->ny) + ")");
   if (!finite_pos(p->dx) || !finite_pos(p->dy) || !finite_pos(p->dt))
     return fail(QPAT_E_INVALID, "dx, dy, dt must be finite and > 0");
@@ -583,9 +601,11 @@ qpat_status plan_build(qpat_plan P, const double* c0, const double* rho0) {
   M.twy = (const float2*)(d + o_twy);
   M.tap_off = (const int*)(d + o_toff);
   M.taps = (const Tap*)(d + o_taps);
-  default_tiles(nx, ny, &P->rt, &P->ct);
+  default_tiles(nx, ny, &P->rt, &P->ct, &P->rthr, &P->cthr);
   M.rt = P->rt;
   M.ct = P->ct;
+  M.rthr = P->rthr;
+  M.cthr = P->cthr;
   return QPAT_OK;
 }
 
@@ -649,8 +669,6 @@ qpat_status plan_exec(qpat_plan P, int b, Exec** out) {
     std::vector<Item> items(b);
     for (int i = 0; i < b; ++i) {
       items[i].m = P->med;
-      items[i].m.rt = P->rt;
-      items[i].m.ct = P->ct;
       items[i].w = P->works[i];
     }
     std::unique_ptr<Exec> E(new Exec());
@@ -704,7 +722,7 @@ std::string tune_key(qpat_plan P, int batch) {
   return buf;
 }
 
-bool tune_lookup(const std::string& key, int* rt, int* ct) {
+bool tune_lookup(const std::string& key, int* rt, int* ct, int* rthr, int* cthr) {
   const char* path = std::getenv("QPAT_TUNE_CACHE");
   if (!path) return false;
   FILE* f = std::fopen(path, "r");
@@ -712,13 +730,15 @@ bool tune_lookup(const std::string& key, int* rt, int* ct) {
   char line[256];
   bool found = false;
   while (std::fgets(line, sizeof line, f)) {
-    int a, b, c, d, r, co;
-    if (std::sscanf(line, "%d %d %d %d %d %d", &a, &b, &c, &d, &r, &co) == 6) {
+    int a, b, c, d, r, co, rh, ch;
+    if (std::sscanf(line, "%d %d %d %d %d %d %d %d", &a, &b, &c, &d, &r, &co, &rh, &ch) == 8) {
       char k[128];
       std::snprintf(k, sizeof k, "%d %d %d %d", a, b, c, d);
       if (key == k) {
         *rt = r;
         *ct = co;
+        *rthr = rh;
+        *cthr = ch;
         found = true;
       }
     }
@@ -727,25 +747,27 @@ bool tune_lookup(const std::string& key, int* rt, int* ct) {
   return found;
 }
 
-void tune_store(const std::string& key, int rt, int ct) {
+void tune_store(const std::string& key, int rt, int ct, int rthr, int cthr) {
   const char* path = std::getenv("QPAT_TUNE_CACHE");
   if (!path) return;
   FILE* f = std::fopen(path, "a");
   if (!f) return;
-  std::fprintf(f, "%s %d %d\n", key.c_str(), rt, ct);
+  std::fprintf(f, "%s %d %d %d %d\n", key.c_str(), rt, ct, rthr, cthr);
   std::fclose(f);
 }
 
-qpat_status set_tiles(qpat_plan P, int rt, int ct) {
-  if (!row_tile_ok(P->prm.nx, P->prm.ny, rt))
-    return fail(QPAT_E_INVALID, "rows per tile must be an even power of two dividing ny within the LDS limit");
-  if (!col_tile_ok(P->prm.nx / 2, P->prm.ny, ct))
-    return fail(QPAT_E_INVALID, "columns per tile must be a power of two dividing nx/2 within the LDS limit");
-  if (rt != P->rt || ct != P->ct) {
-    P->rt = rt;
-    P->ct = ct;
-    P->med.rt = rt;
-    P->med.ct = ct;
+qpat_status set_tiles(qpat_plan P, int rt, int ct, int rthr, int cthr) {
+  if (!row_tile_ok(P->prm.nx, P->prm.ny, rt, rthr))
+    return fail(QPAT_E_INVALID, "row tile: rows must be an even power of two dividing ny, threads 64/128/256, "
+                                "rows*nx <= 8*threads, within the LDS limit");
+  if (!col_tile_ok(P->prm.nx / 2, P->prm.ny, ct, cthr))
+    return fail(QPAT_E_INVALID, "column tile: columns must be a power of two dividing nx/2, threads "
+                                "64/128/256, columns*ny <= 8*threads, within the LDS limit");
+  if (rt != P->rt || ct != P->ct || rthr != P->rthr || cthr != P->cthr) {
+    P->rt = P->med.rt = rt;
+    P->ct = P->med.ct = ct;
+    P->rthr = P->med.rthr = rthr;
+    P->cthr = P->med.cthr = cthr;
     HIPCHK(hipDeviceSynchronize());
     P->execs.clear();
   }
@@ -949,15 +971,19 @@ qpat_status qpat_replay(qpat_plan P, const float* p0, const float* ckpt, int32_t
   return QPAT_OK;
 }
 
-qpat_status qpat_set_tiles(qpat_plan P, int32_t rows, int32_t cols) {
+qpat_status qpat_set_tiles(qpat_plan P, int32_t rows, int32_t cols, int32_t row_threads,
+                           int32_t col_threads) {
   if (!P) return fail(QPAT_E_INVALID, "plan is NULL");
-  return set_tiles(P, rows, cols);
+  return set_tiles(P, rows, cols, row_threads, col_threads);
 }
 
-qpat_status qpat_get_tiles(qpat_plan P, int32_t* rows, int32_t* cols) {
+qpat_status qpat_get_tiles(qpat_plan P, int32_t* rows, int32_t* cols, int32_t* row_threads,
+                           int32_t* col_threads) {
   if (!P || !rows || !cols) return fail(QPAT_E_INVALID, "NULL argument");
   *rows = P->rt;
   *cols = P->ct;
+  if (row_threads) *row_threads = P->rthr;
+  if (col_threads) *col_threads = P->cthr;
   return QPAT_OK;
 }
 
@@ -965,38 +991,42 @@ qpat_status qpat_tune(qpat_plan P, int32_t batch, qpat_stream stream) {
   if (!P) return fail(QPAT_E_INVALID, "plan is NULL");
   if (batch < 1) return fail(QPAT_E_INVALID, "batch must be >= 1");
   const std::string key = tune_key(P, batch);
-  int rt, ct;
-  if (tune_lookup(key, &rt, &ct) && row_tile_ok(P->prm.nx, P->prm.ny, rt) &&
-      col_tile_ok(P->prm.nx / 2, P->prm.ny, ct))
-    return set_tiles(P, rt, ct);
+  const int nx = P->prm.nx, ny = P->prm.ny;
+  int rt, ct, rh, ch;
+  if (tune_lookup(key, &rt, &ct, &rh, &ch) && row_tile_ok(nx, ny, rt, rh) && col_tile_ok(nx / 2, ny, ct, ch))
+    return set_tiles(P, rt, ct, rh, ch);
   hipStream_t st = (hipStream_t)stream;
   const int steps = 12;
-  int best_rt = P->rt, best_ct = P->ct;
+  int brt = P->rt, bct = P->ct, brh = P->rthr, bch = P->cthr;
   float best = INFINITY;
-  // rows first (column tile fixed), then columns with the best row tile
-  for (int r = 2; r <= 32; r *= 2) {
-    if (!row_tile_ok(P->prm.nx, P->prm.ny, r)) continue;
-    STCHK(set_tiles(P, r, best_ct));
-    float ms;
-    STCHK(time_forward(P, batch, steps, st, &ms));
-    if (ms < best) {
-      best = ms;
-      best_rt = r;
+  // row shapes first (column shape fixed), then column shapes with the best row shape
+  for (int r = 2; r <= 32; r *= 2)
+    for (int h = 64; h <= 256; h *= 2) {
+      if (!row_tile_ok(nx, ny, r, h)) continue;
+      STCHK(set_tiles(P, r, bct, h, bch));
+      float ms;
+      STCHK(time_forward(P, batch, steps, st, &ms));
+      if (ms < best) {
+        best = ms;
+        brt = r;
+        brh = h;
+      }
     }
-  }
   best = INFINITY;
-  for (int c = 1; c <= 32; c *= 2) {
-    if (!col_tile_ok(P->prm.nx / 2, P->prm.ny, c)) continue;
-    STCHK(set_tiles(P, best_rt, c));
-    float ms;
-    STCHK(time_forward(P, batch, steps, st, &ms));
-    if (ms < best) {
-      best = ms;
-      best_ct = c;
+  for (int c = 1; c <= 32; c *= 2)
+    for (int h = 64; h <= 256; h *= 2) {
+      if (!col_tile_ok(nx / 2, ny, c, h)) continue;
+      STCHK(set_tiles(P, brt, c, brh, h));
+      float ms;
+      STCHK(time_forward(P, batch, steps, st, &ms));
+      if (ms < best) {
+        best = ms;
+        bct = c;
+        bch = h;
+      }
     }
-  }
-  STCHK(set_tiles(P, best_rt, best_ct));
-  tune_store(key, best_rt, best_ct);
+  STCHK(set_tiles(P, brt, bct, brh, bch));
+  tune_store(key, brt, bct, brh, bch);
   return QPAT_OK;
 }
 
@@ -1098,8 +1128,6 @@ qpat_status qpat_batch_create(const qpat_plan* plans, int32_t count, qpat_batch*
     B->works.push_back(w[0]);
     B->datas.push_back(dd[0]);
     items[i].m = plans[i]->med;
-    items[i].m.rt = plans[i]->rt;
-    items[i].m.ct = plans[i]->ct;
     items[i].w = w[0];
   }
   qpat_status s = exec_build(B->exec, items);

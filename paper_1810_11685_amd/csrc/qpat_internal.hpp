@@ -9,7 +9,9 @@
 
 namespace qpat {
 
-constexpr int kBlock = 256;   // threads per block of every pass
+constexpr int kBlock = 256;   // maximum threads per block of a pass
+constexpr int kMaxPer = 8;    // pointwise elements per thread held in registers
+constexpr int kTapCap = 64;   // sensor taps of one row tile staged in LDS
 constexpr int kXcds = 8;      // MI355X: 8 XCDs, work-groups dispatched round-robin
 
 // One bilinear sensor tap pair on one grid row: the sensor's contribution from
@@ -26,6 +28,7 @@ struct Medium {
   int nx, ny, nxh, nt, ns, lossy;
   float dt;
   int rt, ct;             // rows per row-pass tile, spectrum columns per column-pass tile
+  int rthr, cthr;         // threads per block of the row / column passes
   uint32_t radx, rady;    // radix plans, 4 bits per stage, first stage lowest
   int nstx, nsty;
   const float *c2, *c2eta, *c2tau, *rho0, *bx, *by;   // [ny][nx]; bx = dt/rho_x, by = dt/rho_y
@@ -87,21 +90,24 @@ enum Flags : int {
 
 // Launch helpers implemented in kernels.hip.
 hipError_t launch_row(int mode, const Item* items, const IO* io, const int2* map, int nblocks,
-                      size_t lds, int n, int flags, hipStream_t st);
+                      int threads, size_t lds, int n, int flags, hipStream_t st);
 hipError_t launch_col(int mcode, int nin, int nout, const Item* items, const int2* map,
-                      int nblocks, size_t lds, int n, int reverse, hipStream_t st);
+                      int nblocks, int threads, size_t lds, int n, hipStream_t st);
 hipError_t launch_combine(const Item* items, const IO* io, int nitems, int max_count,
                           hipStream_t st);
 hipError_t launch_dot(const float* a, const float* b, int64_t n, double* partial, int nblk,
                       double* out, hipStream_t st);
 
-// LDS bytes of one block of each pass (ping-pong buffers).
-inline size_t row_lds_bytes(int nx, int rt) { return size_t(2) * rt * nx * sizeof(float2); }
+// LDS bytes of one block of each pass: ping-pong line buffers, the twiddle
+// table, and (rows) the staged sensor taps.
+inline size_t row_lds_bytes(int nx, int rt) {
+  return size_t(2 * rt * nx + nx) * sizeof(float2) + kTapCap * (sizeof(Tap) + sizeof(float));
+}
 // Column lines are padded by one element when a tile holds several columns
 // (their transposed loads would otherwise hit one LDS bank).
 __host__ __device__ inline int col_line_stride(int ny, int ct) { return ct == 1 ? ny : ny + 1; }
 inline size_t col_lds_bytes(int ny, int ct) {
-  return size_t(2) * 2 * ct * col_line_stride(ny, ct) * sizeof(float2);
+  return (size_t(2) * 2 * ct * col_line_stride(ny, ct) + ny) * sizeof(float2);
 }
 
 }  // namespace qpat

@@ -155,15 +155,17 @@ class Plan:
         return out
 
     # ---- launch shape
-    def set_tiles(self, rows: int, cols: int) -> None:
-        check(lib().qpat_set_tiles(self._h, rows, cols), "qpat_set_tiles")
+    def set_tiles(self, rows: int, cols: int, row_threads: int = 256, col_threads: int = 256) -> None:
+        check(lib().qpat_set_tiles(self._h, rows, cols, row_threads, col_threads), "qpat_set_tiles")
 
-    def tiles(self) -> tuple[int, int]:
-        r, c = ctypes.c_int32(), ctypes.c_int32()
-        check(lib().qpat_get_tiles(self._h, ctypes.byref(r), ctypes.byref(c)), "qpat_get_tiles")
-        return int(r.value), int(c.value)
+    def tiles(self) -> tuple[int, int, int, int]:
+        """(rows per row block, columns per column block, row threads, column threads)."""
+        r, c, rh, ch = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        check(lib().qpat_get_tiles(self._h, ctypes.byref(r), ctypes.byref(c), ctypes.byref(rh),
+                                   ctypes.byref(ch)), "qpat_get_tiles")
+        return int(r.value), int(c.value), int(rh.value), int(ch.value)
 
-    def tune(self, batch: int = 1, stream=None) -> tuple[int, int]:
+    def tune(self, batch: int = 1, stream=None) -> tuple[int, int, int, int]:
         check(lib().qpat_tune(self._h, batch, _stream(stream)), "qpat_tune")
         return self.tiles()
 

@@ -47,7 +47,7 @@ def good(**kw):
 
 @pytest.mark.parametrize("kw,status", [
     ({}, 0),
-    ({"nx": 100}, 2), ({"ny": 4}, 2), ({"nx": 4096}, 2), ({"nx": 63}, 2), ({"nx": 384, "ny": 1536}, 0),
+    ({"nx": 100}, 2), ({"ny": 4}, 2), ({"nx": 4096}, 2), ({"nx": 63}, 2), ({"nx": 384, "ny": 768}, 0), ({"nx": 2048}, 2),
     ({"dx": 0.0}, 1), ({"dt": -1.0}, 1), ({"dy": float("nan")}, 1),
     ({"nt": 0}, 1), ({"c_ref": 0.0}, 1),
     ({"pml_size": 24}, 1), ({"pml_size": -1}, 1), ({"pml_alpha": -2.0}, 1),

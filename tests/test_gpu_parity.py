@@ -181,9 +181,9 @@ def test_tiles_do_not_change_results_beyond_rounding(q):
     prm, c0, rho0, p0 = problem(64, 64, 50)
     plan = q.Plan(prm, c0, rho0)
     base = N(plan.forward(T(p0)))
-    for rt, ct in [(2, 1), (4, 4), (16, 8)]:
-        plan.set_tiles(rt, ct)
-        assert plan.tiles() == (rt, ct)
+    for shape in [(2, 1, 64, 64), (4, 4, 128, 256), (16, 8, 256, 128), (2, 2, 256, 64)]:
+        plan.set_tiles(*shape)
+        assert plan.tiles() == shape
         assert np.array_equal(N(plan.forward(T(p0))), base)
 
 
