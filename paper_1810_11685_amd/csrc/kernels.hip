@@ -77,15 +77,24 @@ template <> __device__ __forceinline__ void bfly<8>(float2* v) {
   v[7] = csub(e[3], o3);
 }
 
+// Quotient a / d for 0 <= a < 2^22 without an integer divide: a float
+// reciprocal estimate and one exact correction step.
+__device__ __forceinline__ int fdiv(int a, int d, float rcp) {
+  int q = static_cast<int>(static_cast<float>(a) * rcp);
+  const int r = a - q * d;
+  q += (r >= d) - (r < 0);
+  return q;
+}
+
 // One Stockham stage for butterfly j: reads src[j + r nb], twiddles by
-// W_{Ns R}^{k r} (k = j mod Ns), writes dst[(j - k) R + k + r Ns].
+// W_{Ns R}^{k r} (k = j mod Ns, Ns a power of two), writes dst[(j - k) R + k + r Ns].
 template <int R>
 __device__ __forceinline__ void stockham(const float2* src, float2* dst, int j, int nb, int Ns,
                                          int tws, const float2* tw) {
   float2 v[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) v[r] = src[j + r * nb];
-  const int k = j % Ns;
+  const int k = j & (Ns - 1);
   if (Ns > 1) {
 #pragma unroll
     for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw[k * r * tws]);
@@ -98,18 +107,26 @@ __device__ __forceinline__ void stockham(const float2* src, float2* dst, int j, 
 
 // Forward FFT of `nlines` lines of length n (line stride ls) held in LDS
 // buffer a, using b as the ping-pong partner and the twiddle table tw (LDS).
-// All threads of the block take part; returns the buffer that holds the result.  The caller must have
-// synchronised after writing the input; the routine ends synchronised.
-__device__ float2* fft_lines(float2* a, float2* b, int nlines, int n, int ls, uint32_t rad, int nst,
-                             const float2* tw) {
+// Radix plans put the radix-3 stage (if any) last so that Ns is a power of two
+// in every stage.  `rad8`/`rad4` are plans with maximal radix 8 / 4; the
+// radix-4 plan is used when radix-8 stages would leave threads idle.  All
+// threads of the block take part; returns the buffer that holds the result.
+// The caller must have synchronised after writing the input; the routine ends
+// synchronised.
+__device__ float2* fft_lines(float2* a, float2* b, int nlines, int n, int ls, uint32_t rad8, int nst8,
+                             uint32_t rad4, int nst4, const float2* tw) {
+  const bool use4 = nlines * (n / 8) < static_cast<int>(blockDim.x);
+  const uint32_t rad = use4 ? rad4 : rad8;
+  const int nst = use4 ? nst4 : nst8;
   int Ns = 1;
   for (int s = 0; s < nst; ++s) {
     const int R = (rad >> (4 * s)) & 15;
     const int nb = n / R;
+    const float rnb = 1.0f / static_cast<float>(nb);
     const int tws = n / (Ns * R);
     const int total = nlines * nb;
     for (int it = threadIdx.x; it < total; it += blockDim.x) {
-      const int line = it / nb;
+      const int line = fdiv(it, nb, rnb);
       const int j = it - line * nb;
       const float2* src = a + line * ls;
       float2* dst = b + line * ls;
@@ -163,8 +180,9 @@ __device__ __forceinline__ float2* other(float2* r, float2* a, float2* b) { retu
 __device__ __forceinline__ void load_pair_lines(float2* buf, const float2* __restrict__ s0,
                                                 const float2* __restrict__ s1, int y0, int nlines,
                                                 int nx, int nxh) {
+  const float rc = 1.0f / static_cast<float>(nxh);
   for (int it = threadIdx.x; it < nlines * nxh; it += blockDim.x) {
-    const int j = it / nxh, k = it - j * nxh;
+    const int j = fdiv(it, nxh, rc), k = it - j * nxh;
     const size_t off = size_t(y0 + j) * nxh + k;
     build_inv(buf + j * nx, s0[off], s1[off], k, nx, nxh);
   }
@@ -173,8 +191,9 @@ __device__ __forceinline__ void load_pair_lines(float2* buf, const float2* __res
 // line l <- rows (y0+2l, y0+2l+1) of s0
 __device__ __forceinline__ void load_rowpair_lines(float2* buf, const float2* __restrict__ s0, int y0,
                                                    int nlines, int nx, int nxh) {
+  const float rc = 1.0f / static_cast<float>(nxh);
   for (int it = threadIdx.x; it < nlines * nxh; it += blockDim.x) {
-    const int l = it / nxh, k = it - l * nxh;
+    const int l = fdiv(it, nxh, rc), k = it - l * nxh;
     const size_t off = size_t(y0 + 2 * l) * nxh + k;
     build_inv(buf + l * nx, s0[off], s0[off + nxh], k, nx, nxh);
   }
@@ -183,8 +202,9 @@ __device__ __forceinline__ void load_rowpair_lines(float2* buf, const float2* __
 __device__ __forceinline__ void store_pair_spectra(const float2* buf, float2* __restrict__ s0,
                                                    float2* __restrict__ s1, int y0, int nlines, int nx,
                                                    int nxh) {
+  const float rc = 1.0f / static_cast<float>(nxh);
   for (int it = threadIdx.x; it < nlines * nxh; it += blockDim.x) {
-    const int j = it / nxh, k = it - j * nxh;
+    const int j = fdiv(it, nxh, rc), k = it - j * nxh;
     float2 A, B;
     unpack(buf + j * nx, k, nx, nxh, A, B);
     const size_t off = size_t(y0 + j) * nxh + k;
@@ -195,8 +215,9 @@ __device__ __forceinline__ void store_pair_spectra(const float2* buf, float2* __
 
 __device__ __forceinline__ void store_rowpair_spectra(const float2* buf, float2* __restrict__ s0, int y0,
                                                       int nlines, int nx, int nxh) {
+  const float rc = 1.0f / static_cast<float>(nxh);
   for (int it = threadIdx.x; it < nlines * nxh; it += blockDim.x) {
-    const int l = it / nxh, k = it - l * nxh;
+    const int l = fdiv(it, nxh, rc), k = it - l * nxh;
     float2 A, B;
     unpack(buf + l * nx, k, nx, nxh, A, B);
     const size_t off = size_t(y0 + 2 * l) * nxh + k;
@@ -303,6 +324,7 @@ row_kernel(const Item* __restrict__ items, const IO* __restrict__ io, const int2
   void* tap_base = lds + 2 * rt * nx + nx;
   const int tot = rt * nx;
   const float dt = M.dt;
+  const float rnx = 1.0f / static_cast<float>(nx);
 
   if constexpr (MODE == RM_F1) {
     // eq num-vel: v_i = A_i (A_i v_i - dt/rho_i d/dr_i^+ p)
@@ -313,7 +335,7 @@ row_kernel(const Item* __restrict__ items, const IO* __restrict__ io, const int2
     FOR_K {
       const int it = threadIdx.x + k * B;
       if (it < tot) {
-        const int j = it / nx, x = it - j * nx, y = y0 + j;
+        const int j = fdiv(it, nx, rnx), x = it - j * nx, y = y0 + j;
         const size_t idx = size_t(y) * nx + x;
         vxo[k] = first ? 0.f : W.f0[idx];
         vyo[k] = first ? 0.f : W.f1[idx];
@@ -324,12 +346,12 @@ row_kernel(const Item* __restrict__ items, const IO* __restrict__ io, const int2
       }
     }
     __syncthreads();
-    float2* r = fft_lines(bufA, bufB, rt, nx, nx, M.radx, M.nstx, tw);
+    float2* r = fft_lines(bufA, bufB, rt, nx, nx, M.radx, M.nstx, M.radx4, M.nstx4, tw);
     float2* o = other(r, bufA, bufB);
     FOR_K {
       const int it = threadIdx.x + k * B;
       if (it < tot) {
-        const int j = it / nx, x = it - j * nx;
+        const int j = fdiv(it, nx, rnx), x = it - j * nx;
         const size_t idx = size_t(y0 + j) * nx + x;
         const float2 z = r[it];
         const float vx = ax[k] * (ax[k] * vxo[k] - bx[k] * z.x);
@@ -340,7 +362,7 @@ row_kernel(const Item* __restrict__ items, const IO* __restrict__ io, const int2
       }
     }
     __syncthreads();
-    r = fft_lines(o, other(o, bufA, bufB), rt, nx, nx, M.radx, M.nstx, tw);
+    r = fft_lines(o, other(o, bufA, bufB), rt, nx, nx, M.radx, M.nstx, M.radx4, M.nstx4, tw);
     store_pair_spectra(r, W.s0, W.s1, y0, rt, nx, nxh);
   } else if constexpr (MODE == RM_F2 || MODE == RM_F2L) {
     // eq num-rho with the additive source of eq s1 (dt s = p0 / (2 d c^2), d = 2)
@@ -354,7 +376,7 @@ row_kernel(const Item* __restrict__ items, const IO* __restrict__ io, const int2
     FOR_K {
       const int it = threadIdx.x + k * B;
       if (it < tot) {
-        const int j = it / nx, x = it - j * nx, y = y0 + j;
+        const int j = fdiv(it, nx, rnx), x = it - j * nx, y = y0 + j;
         const size_t idx = size_t(y) * nx + x;
         rxo[k] = skip ? 0.f : W.f2[idx];
         ryo[k] = skip ? 0.f : W.f3[idx];
@@ -369,13 +391,13 @@ row_kernel(const Item* __restrict__ items, const IO* __restrict__ io, const int2
     float2* r = nullptr;
     float2* o = bufA;
     if (!skip) {
-      r = fft_lines(bufA, bufB, rt, nx, nx, M.radx, M.nstx, tw);
+      r = fft_lines(bufA, bufB, rt, nx, nx, M.radx, M.nstx, M.radx4, M.nstx4, tw);
       o = other(r, bufA, bufB);
     }
     FOR_K {
       const int it = threadIdx.x + k * B;
       if (it < tot) {
-        const int j = it / nx, x = it - j * nx;
+        const int j = fdiv(it, nx, rnx), x = it - j * nx;
         const size_t idx = size_t(y0 + j) * nx + x;
         float ex = 0.f, ey = 0.f;
         if (!skip) {
@@ -406,12 +428,12 @@ row_kernel(const Item* __restrict__ items, const IO* __restrict__ io, const int2
     }
     __syncthreads();
     if constexpr (MODE == RM_F2) {
-      r = fft_lines(o, other(o, bufA, bufB), rt, nx, nx, M.radx, M.nstx, tw);
+      r = fft_lines(o, other(o, bufA, bufB), rt, nx, nx, M.radx, M.nstx, M.radx4, M.nstx4, tw);
       store_rowpair_spectra(r, W.s0, y0, rt / 2, nx, nxh);
       store_rowpair_spectra(r + (rt / 2) * nx, W.s1, y0, rt / 2, nx, nxh);
     } else {
       if (!(flags & FL_NO_SENSORS)) sensor_partials(M, T, o, y0, W.part, n + 1);
-      r = fft_lines(o, other(o, bufA, bufB), rt / 2, nx, nx, M.radx, M.nstx, tw);
+      r = fft_lines(o, other(o, bufA, bufB), rt / 2, nx, nx, M.radx, M.nstx, M.radx4, M.nstx4, tw);
       store_rowpair_spectra(r, W.s0, y0, rt / 2, nx, nxh);
     }
   } else if constexpr (MODE == RM_F3) {
@@ -424,7 +446,7 @@ row_kernel(const Item* __restrict__ items, const IO* __restrict__ io, const int2
     FOR_K {
       const int it = threadIdx.x + k * B;
       if (it < tot) {
-        const int j = it / nx, x = it - j * nx;
+        const int j = fdiv(it, nx, rnx), x = it - j * nx;
         const size_t idx = size_t(y0 + j) * nx + x;
         rs[k] = W.f2[idx] + W.f3[idx];
         c2[k] = M.c2[idx];
@@ -433,12 +455,12 @@ row_kernel(const Item* __restrict__ items, const IO* __restrict__ io, const int2
       }
     }
     __syncthreads();
-    float2* r = fft_lines(bufA, bufB, rt, nx, nx, M.radx, M.nstx, tw);
+    float2* r = fft_lines(bufA, bufB, rt, nx, nx, M.radx, M.nstx, M.radx4, M.nstx4, tw);
     float2* o = other(r, bufA, bufB);
     FOR_K {
       const int it = threadIdx.x + k * B;
       if (it < tot) {
-        const int j = it / nx, x = it - j * nx;
+        const int j = fdiv(it, nx, rnx), x = it - j * nx;
         const float ys = rowpair_val(r, j, x, nx), yu = rowpair_val(r + (rt / 2) * nx, j, x, nx);
         const float p = c2[k] * rs[k] - ce[k] * ys + ctau[k] * yu;
         pcomp(o, j, x, nx) = p;
@@ -447,7 +469,7 @@ row_kernel(const Item* __restrict__ items, const IO* __restrict__ io, const int2
     }
     __syncthreads();
     if (!(flags & FL_NO_SENSORS)) sensor_partials(M, T, o, y0, W.part, n + 1);
-    r = fft_lines(o, other(o, bufA, bufB), rt / 2, nx, nx, M.radx, M.nstx, tw);
+    r = fft_lines(o, other(o, bufA, bufB), rt / 2, nx, nx, M.radx, M.nstx, M.radx4, M.nstx4, tw);
     store_rowpair_spectra(r, W.s0, y0, rt / 2, nx, nxh);
   } else if constexpr (MODE == RM_A1 || MODE == RM_A1L) {
     // transpose of eqs num-m and num-p: p* += M^T r_{n+1}; q = c^2 p*
@@ -461,7 +483,7 @@ row_kernel(const Item* __restrict__ items, const IO* __restrict__ io, const int2
     FOR_K {
       const int it = threadIdx.x + k * B;
       if (it < tot) {
-        const int j = it / nx, x = it - j * nx, y = y0 + j;
+        const int j = fdiv(it, nx, rnx), x = it - j * nx, y = y0 + j;
         const size_t idx = size_t(y) * nx + x;
         c2[k] = M.c2[idx];
         if constexpr (MODE == RM_A1) {
@@ -480,7 +502,7 @@ row_kernel(const Item* __restrict__ items, const IO* __restrict__ io, const int2
     __syncthreads();
     float2* r = bufA;
     if (!first) {
-      r = fft_lines(bufA, bufB, half, nx, nx, M.radx, M.nstx, tw);
+      r = fft_lines(bufA, bufB, half, nx, nx, M.radx, M.nstx, M.radx4, M.nstx4, tw);
       // p* = -(grad_x^- g_x + grad_y^- g_y): negate the (conjugated) inverse
       for (int it = threadIdx.x; it < half * nx; it += B) {
         const float2 z = r[it];
@@ -496,7 +518,7 @@ row_kernel(const Item* __restrict__ items, const IO* __restrict__ io, const int2
     FOR_K {
       const int it = threadIdx.x + k * B;
       if (it < tot) {
-        const int j = it / nx, x = it - j * nx;
+        const int j = fdiv(it, nx, rnx), x = it - j * nx;
         const size_t idx = size_t(y0 + j) * nx + x;
         const float pb = pcomp(r, j, x, nx);
         if constexpr (MODE == RM_A1) {
@@ -521,11 +543,11 @@ row_kernel(const Item* __restrict__ items, const IO* __restrict__ io, const int2
     }
     __syncthreads();
     if constexpr (MODE == RM_A1) {
-      r = fft_lines(o, other(o, bufA, bufB), rt, nx, nx, M.radx, M.nstx, tw);
+      r = fft_lines(o, other(o, bufA, bufB), rt, nx, nx, M.radx, M.nstx, M.radx4, M.nstx4, tw);
       store_rowpair_spectra(r, W.s0, y0, half, nx, nxh);
       store_rowpair_spectra(r + half * nx, W.s1, y0, half, nx, nxh);
     } else if (n != -1) {
-      r = fft_lines(o, other(o, bufA, bufB), rt, nx, nx, M.radx, M.nstx, tw);
+      r = fft_lines(o, other(o, bufA, bufB), rt, nx, nx, M.radx, M.nstx, M.radx4, M.nstx4, tw);
       store_pair_spectra(r, W.s0, W.s1, y0, rt, nx, nxh);
     }
   } else if constexpr (MODE == RM_A2) {
@@ -539,7 +561,7 @@ row_kernel(const Item* __restrict__ items, const IO* __restrict__ io, const int2
     FOR_K {
       const int it = threadIdx.x + k * B;
       if (it < tot) {
-        const int j = it / nx, x = it - j * nx, y = y0 + j;
+        const int j = fdiv(it, nx, rnx), x = it - j * nx, y = y0 + j;
         const size_t idx = size_t(y) * nx + x;
         qv[k] = W.q[idx];
         rbx0[k] = first ? 0.f : W.f2[idx];
@@ -552,12 +574,12 @@ row_kernel(const Item* __restrict__ items, const IO* __restrict__ io, const int2
       }
     }
     __syncthreads();
-    float2* r = fft_lines(bufA, bufB, rt, nx, nx, M.radx, M.nstx, tw);
+    float2* r = fft_lines(bufA, bufB, rt, nx, nx, M.radx, M.nstx, M.radx4, M.nstx4, tw);
     float2* o = other(r, bufA, bufB);
     FOR_K {
       const int it = threadIdx.x + k * B;
       if (it < tot) {
-        const int j = it / nx, x = it - j * nx;
+        const int j = fdiv(it, nx, rnx), x = it - j * nx;
         const size_t idx = size_t(y0 + j) * nx + x;
         const float yd = rowpair_val(r, j, x, nx), ya = rowpair_val(r + (rt / 2) * nx, j, x, nx);
         const float sb = qv[k] - yd;
@@ -574,7 +596,7 @@ row_kernel(const Item* __restrict__ items, const IO* __restrict__ io, const int2
     }
     __syncthreads();
     if (n != -1) {
-      r = fft_lines(o, other(o, bufA, bufB), rt, nx, nx, M.radx, M.nstx, tw);
+      r = fft_lines(o, other(o, bufA, bufB), rt, nx, nx, M.radx, M.nstx, M.radx4, M.nstx4, tw);
       store_pair_spectra(r, W.s0, W.s1, y0, rt, nx, nxh);
     }
   } else if constexpr (MODE == RM_A3) {
@@ -586,7 +608,7 @@ row_kernel(const Item* __restrict__ items, const IO* __restrict__ io, const int2
     FOR_K {
       const int it = threadIdx.x + k * B;
       if (it < tot) {
-        const int j = it / nx, x = it - j * nx, y = y0 + j;
+        const int j = fdiv(it, nx, rnx), x = it - j * nx, y = y0 + j;
         const size_t idx = size_t(y) * nx + x;
         vbx0[k] = first ? 0.f : W.f0[idx];
         vby0[k] = first ? 0.f : W.f1[idx];
@@ -597,12 +619,12 @@ row_kernel(const Item* __restrict__ items, const IO* __restrict__ io, const int2
       }
     }
     __syncthreads();
-    float2* r = fft_lines(bufA, bufB, rt, nx, nx, M.radx, M.nstx, tw);
+    float2* r = fft_lines(bufA, bufB, rt, nx, nx, M.radx, M.nstx, M.radx4, M.nstx4, tw);
     float2* o = other(r, bufA, bufB);
     FOR_K {
       const int it = threadIdx.x + k * B;
       if (it < tot) {
-        const int j = it / nx, x = it - j * nx;
+        const int j = fdiv(it, nx, rnx), x = it - j * nx;
         const size_t idx = size_t(y0 + j) * nx + x;
         const float2 z = r[it];
         const float vbx = vbx0[k] - z.x;
@@ -613,26 +635,26 @@ row_kernel(const Item* __restrict__ items, const IO* __restrict__ io, const int2
       }
     }
     __syncthreads();
-    r = fft_lines(o, other(o, bufA, bufB), rt, nx, nx, M.radx, M.nstx, tw);
+    r = fft_lines(o, other(o, bufA, bufB), rt, nx, nx, M.radx, M.nstx, M.radx4, M.nstx4, tw);
     store_pair_spectra(r, W.s0, W.s1, y0, rt, nx, nxh);
   } else if constexpr (MODE == RM_FWD1) {
     const float* src = X.in;
     load_tw(tw, M.twx, nx);
     for (int it = threadIdx.x; it < tot; it += B) {
-      const int j = it / nx, x = it - j * nx;
+      const int j = fdiv(it, nx, rnx), x = it - j * nx;
       pcomp(bufA, j, x, nx) = src[size_t(y0 + j) * nx + x];
     }
     __syncthreads();
-    float2* r = fft_lines(bufA, bufB, rt / 2, nx, nx, M.radx, M.nstx, tw);
+    float2* r = fft_lines(bufA, bufB, rt / 2, nx, nx, M.radx, M.nstx, M.radx4, M.nstx4, tw);
     store_rowpair_spectra(r, W.s0, y0, rt / 2, nx, nxh);
   } else if constexpr (MODE == RM_INV1) {
     load_rowpair_lines(bufA, W.s0, y0, rt / 2, nx, nxh);
     load_tw(tw, M.twx, nx);
     __syncthreads();
-    float2* r = fft_lines(bufA, bufB, rt / 2, nx, nx, M.radx, M.nstx, tw);
+    float2* r = fft_lines(bufA, bufB, rt / 2, nx, nx, M.radx, M.nstx, M.radx4, M.nstx4, tw);
     float* dst = X.out;
     for (int it = threadIdx.x; it < tot; it += B) {
-      const int j = it / nx, x = it - j * nx;
+      const int j = fdiv(it, nx, rnx), x = it - j * nx;
       dst[size_t(y0 + j) * nx + x] = rowpair_val(r, j, x, nx);
     }
   }
@@ -691,9 +713,10 @@ col_kernel(const Item* __restrict__ items, const int2* __restrict__ map, int mco
   const float2* symx = xcode == MC_DXP ? M.dxp : M.dxm;
   const float2* symy = ycode == MC_DYP ? M.dyp : M.dym;
   // load phase: the tile (transposed into lines), twiddles, multiplier values
+  const float rct = 1.0f / static_cast<float>(ct), rny = 1.0f / static_cast<float>(ny);
   for (int it = threadIdx.x; it < nin * ct * ny; it += B) {
-    const int c = it % ct, rest = it / ct;
-    const int ky = rest % ny, f = rest / ny;
+    const int rest = fdiv(it, ct, rct), c = it - rest * ct;
+    const int f = fdiv(rest, ny, rny), ky = rest - f * ny;
     const float2* s = f ? W.s1 : W.s0;
     bufA[(f * ct + c) * ls + ky] = s[size_t(ky) * nxh + c0 + c];
   }
@@ -703,7 +726,7 @@ col_kernel(const Item* __restrict__ items, const int2* __restrict__ map, int mco
   FOR_K {
     const int it = threadIdx.x + k * B;
     if (it < tot) {
-      const int c = it / ny, ky = it - c * ny, kx = c0 + c;
+      const int c = fdiv(it, ny, rny), ky = it - c * ny, kx = c0 + c;
       const int t = ky * (nxh + 1) + kx;
       MultPre& p = P[k];
       p.a = tabA[t];
@@ -718,12 +741,12 @@ col_kernel(const Item* __restrict__ items, const int2* __restrict__ map, int mco
     }
   }
   __syncthreads();
-  float2* r = fft_lines(bufA, bufB, nin * ct, ny, ls, M.rady, M.nsty, tw);
+  float2* r = fft_lines(bufA, bufB, nin * ct, ny, ls, M.rady, M.nsty, M.rady4, M.nsty4, tw);
   float2* o = other(r, bufA, bufB);
   FOR_K {
     const int it = threadIdx.x + k * B;
     if (it < tot) {
-      const int c = it / ny, ky = it - c * ny;
+      const int c = fdiv(it, ny, rny), ky = it - c * ny;
       const int kx = c0 + c;
       const MultPre& p = P[k];
       if (kx == 0) {
@@ -761,10 +784,10 @@ col_kernel(const Item* __restrict__ items, const int2* __restrict__ map, int mco
     }
   }
   __syncthreads();
-  r = fft_lines(o, other(o, bufA, bufB), nout * ct, ny, ls, M.rady, M.nsty, tw);
+  r = fft_lines(o, other(o, bufA, bufB), nout * ct, ny, ls, M.rady, M.nsty, M.rady4, M.nsty4, tw);
   for (int it = threadIdx.x; it < nout * ct * ny; it += B) {
-    const int c = it % ct, rest = it / ct;
-    const int ky = rest % ny, f = rest / ny;
+    const int rest = fdiv(it, ct, rct), c = it - rest * ct;
+    const int f = fdiv(rest, ny, rny), ky = rest - f * ny;
     float2* s = f ? W.s1 : W.s0;
     s[size_t(ky) * nxh + c0 + c] = cconj(r[(f * ct + c) * ls + ky]);
   }

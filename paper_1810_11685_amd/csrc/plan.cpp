@@ -48,22 +48,29 @@ constexpr int kMaxN = 1024;
 constexpr int kMinN = 8;
 constexpr size_t kMaxLds = 65536;
 
-// n = 2^a or 3 * 2^a: radix plan (4 bits per stage, first stage lowest)
-bool radix_plan(int n, uint32_t* rad, int* nst) {
+// n = 2^a or 3 * 2^a: radix plan with radices up to `maxr` (8 or 4), 4 bits
+// per stage, first stage lowest; the radix-3 stage comes last so that the
+// sub-transform length before every stage is a power of two.
+bool radix_plan(int n, uint32_t* rad, int* nst, int maxr = 8) {
   if (n < kMinN || n > kMaxN || (n & 1)) return false;
   std::vector<int> r;
   int m = n;
-  if (m % 3 == 0) {
-    r.push_back(3);
-    m /= 3;
-  }
+  const bool three = (m % 3 == 0);
+  if (three) m /= 3;
   if (m & (m - 1)) return false;
   int a = 0;
   while ((1 << a) < m) ++a;
-  const int q = a / 3, rem = a % 3;
-  if (rem == 1) r.push_back(2);
-  if (rem == 2) r.push_back(4);
-  for (int i = 0; i < q; ++i) r.push_back(8);
+  if (maxr == 8) {
+    const int q = a / 3, rem = a % 3;
+    if (rem == 1) r.push_back(2);
+    if (rem == 2) r.push_back(4);
+    for (int i = 0; i < q; ++i) r.push_back(8);
+  } else {
+    const int q = a / 2, rem = a % 2;
+    if (rem == 1) r.push_back(2);
+    for (int i = 0; i < q; ++i) r.push_back(4);
+  }
+  if (three) r.push_back(3);
   *rad = 0;
   for (size_t i = 0; i < r.size(); ++i) *rad |= uint32_t(r[i]) << (4 * i);
   *nst = int(r.size());
@@ -578,8 +585,10 @@ qpat_status plan_build(qpat_plan P, const double* c0, const double* rho0) {
   M.ns = p.ns;
   M.lossy = lossy ? 1 : 0;
   M.dt = float(dt);
-  radix_plan(nx, &M.radx, &M.nstx);
-  radix_plan(ny, &M.rady, &M.nsty);
+  radix_plan(nx, &M.radx, &M.nstx, 8);
+  radix_plan(ny, &M.rady, &M.nsty, 8);
+  radix_plan(nx, &M.radx4, &M.nstx4, 4);
+  radix_plan(ny, &M.rady4, &M.nsty4, 4);
   M.c2 = (const float*)(d + o_c2);
   M.c2eta = (const float*)(d + o_c2eta);
   M.c2tau = (const float*)(d + o_c2tau);

@@ -29,8 +29,10 @@ struct Medium {
   float dt;
   int rt, ct;             // rows per row-pass tile, spectrum columns per column-pass tile
   int rthr, cthr;         // threads per block of the row / column passes
-  uint32_t radx, rady;    // radix plans, 4 bits per stage, first stage lowest
+  uint32_t radx, rady;    // radix plans (max radix 8), 4 bits per stage, first stage lowest
   int nstx, nsty;
+  uint32_t radx4, rady4;  // radix plans with max radix 4
+  int nstx4, nsty4;
   const float *c2, *c2eta, *c2tau, *rho0, *bx, *by;   // [ny][nx]; bx = dt/rho_x, by = dt/rho_y
   const float *avx, *arx, *avy, *ary;                 // PML diagonals: [nx] / [ny]
   const float2 *dxp, *dxm;                            // [nxh+1] i kx e^{+-i kx dx/2}
