@@ -86,14 +86,19 @@ __device__ __forceinline__ int fdiv(int a, int d, float rcp) {
   return q;
 }
 
+// LDS lines are padded by one element per 8 so that the strided Stockham
+// writes and the transposed column loads spread over the LDS banks.
+__device__ __forceinline__ int px(int x) { return x + (x >> 3); }
+
 // One Stockham stage for butterfly j: reads src[j + r nb], twiddles by
-// W_{Ns R}^{k r} (k = j mod Ns, Ns a power of two), writes dst[(j - k) R + k + r Ns].
+// W_{Ns R}^{k r} (k = j mod Ns, Ns a power of two), writes dst[(j - k) R + k + r Ns]
+// (positions within a line mapped through px()).
 template <int R>
 __device__ __forceinline__ void stockham(const float2* src, float2* dst, int j, int nb, int Ns,
                                          int tws, const float2* tw) {
   float2 v[R];
 #pragma unroll
-  for (int r = 0; r < R; ++r) v[r] = src[j + r * nb];
+  for (int r = 0; r < R; ++r) v[r] = src[px(j + r * nb)];
   const int k = j & (Ns - 1);
   if (Ns > 1) {
 #pragma unroll
@@ -102,22 +107,17 @@ __device__ __forceinline__ void stockham(const float2* src, float2* dst, int j, 
   bfly<R>(v);
   const int base = (j - k) * R + k;
 #pragma unroll
-  for (int r = 0; r < R; ++r) dst[base + r * Ns] = v[r];
+  for (int r = 0; r < R; ++r) dst[px(base + r * Ns)] = v[r];
 }
 
 // Forward FFT of `nlines` lines of length n (line stride ls) held in LDS
 // buffer a, using b as the ping-pong partner and the twiddle table tw (LDS).
-// Radix plans put the radix-3 stage (if any) last so that Ns is a power of two
-// in every stage.  `rad8`/`rad4` are plans with maximal radix 8 / 4; the
-// radix-4 plan is used when radix-8 stages would leave threads idle.  All
-// threads of the block take part; returns the buffer that holds the result.
-// The caller must have synchronised after writing the input; the routine ends
-// synchronised.
-__device__ float2* fft_lines(float2* a, float2* b, int nlines, int n, int ls, uint32_t rad8, int nst8,
-                             uint32_t rad4, int nst4, const float2* tw) {
-  const bool use4 = nlines * (n / 8) < static_cast<int>(blockDim.x);
-  const uint32_t rad = use4 ? rad4 : rad8;
-  const int nst = use4 ? nst4 : nst8;
+// The radix plan puts the radix-3 stage (if any) last so that Ns is a power of
+// two in every stage.  All threads of the block take part; returns the buffer
+// that holds the result.  The caller must have synchronised after writing the
+// input; the routine ends synchronised.
+__device__ float2* fft_lines(float2* a, float2* b, int nlines, int n, int ls, uint32_t rad, int nst,
+                             const float2* tw) {
   int Ns = 1;
   for (int s = 0; s < nst; ++s) {
     const int R = (rad >> (4 * s)) & 15;
@@ -154,21 +154,21 @@ __device__ float2* fft_lines(float2* a, float2* b, int nlines, int n, int ls, ui
 __device__ __forceinline__ void build_inv(float2* L, float2 A, float2 B, int k, int nx, int nxh) {
   if (k == 0) {
     L[0] = make_float2(A.x, -B.x);
-    L[nxh] = make_float2(A.y, -B.y);
+    L[px(nxh)] = make_float2(A.y, -B.y);
   } else {
-    L[k] = make_float2(A.x - B.y, -(A.y + B.x));
-    L[nx - k] = make_float2(A.x + B.y, -(B.x - A.y));
+    L[px(k)] = make_float2(A.x - B.y, -(A.y + B.x));
+    L[px(nx - k)] = make_float2(A.x + B.y, -(B.x - A.y));
   }
 }
 
 // Split the FFT Z of a + i b into the packed half spectra A (of a), B (of b).
 __device__ __forceinline__ void unpack(const float2* L, int k, int nx, int nxh, float2& A, float2& B) {
   if (k == 0) {
-    const float2 z0 = L[0], zn = L[nxh];
+    const float2 z0 = L[0], zn = L[px(nxh)];
     A = make_float2(z0.x, zn.x);
     B = make_float2(z0.y, zn.y);
   } else {
-    const float2 zk = L[k], zm = L[nx - k];
+    const float2 zk = L[px(k)], zm = L[px(nx - k)];
     A = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
     B = make_float2(0.5f * (zk.y + zm.y), 0.5f * (zm.x - zk.x));
   }
@@ -184,7 +184,7 @@ __device__ __forceinline__ void load_pair_lines(float2* buf, const float2* __res
   for (int it = threadIdx.x; it < nlines * nxh; it += blockDim.x) {
     const int j = fdiv(it, nxh, rc), k = it - j * nxh;
     const size_t off = size_t(y0 + j) * nxh + k;
-    build_inv(buf + j * nx, s0[off], s1[off], k, nx, nxh);
+    build_inv(buf + j * lstride(nx), s0[off], s1[off], k, nx, nxh);
   }
 }
 
@@ -195,7 +195,7 @@ __device__ __forceinline__ void load_rowpair_lines(float2* buf, const float2* __
   for (int it = threadIdx.x; it < nlines * nxh; it += blockDim.x) {
     const int l = fdiv(it, nxh, rc), k = it - l * nxh;
     const size_t off = size_t(y0 + 2 * l) * nxh + k;
-    build_inv(buf + l * nx, s0[off], s0[off + nxh], k, nx, nxh);
+    build_inv(buf + l * lstride(nx), s0[off], s0[off + nxh], k, nx, nxh);
   }
 }
 
@@ -206,7 +206,7 @@ __device__ __forceinline__ void store_pair_spectra(const float2* buf, float2* __
   for (int it = threadIdx.x; it < nlines * nxh; it += blockDim.x) {
     const int j = fdiv(it, nxh, rc), k = it - j * nxh;
     float2 A, B;
-    unpack(buf + j * nx, k, nx, nxh, A, B);
+    unpack(buf + j * lstride(nx), k, nx, nxh, A, B);
     const size_t off = size_t(y0 + j) * nxh + k;
     s0[off] = A;
     s1[off] = B;
@@ -219,7 +219,7 @@ __device__ __forceinline__ void store_rowpair_spectra(const float2* buf, float2*
   for (int it = threadIdx.x; it < nlines * nxh; it += blockDim.x) {
     const int l = fdiv(it, nxh, rc), k = it - l * nxh;
     float2 A, B;
-    unpack(buf + l * nx, k, nx, nxh, A, B);
+    unpack(buf + l * lstride(nx), k, nx, nxh, A, B);
     const size_t off = size_t(y0 + 2 * l) * nxh + k;
     s0[off] = A;
     s0[off + nxh] = B;
@@ -228,13 +228,13 @@ __device__ __forceinline__ void store_rowpair_spectra(const float2* buf, float2*
 
 // Row-pair LDS layout: row y0+j lives in component (j & 1) of line j >> 1.
 __device__ __forceinline__ float& pcomp(float2* buf, int j, int x, int nx) {
-  float2* e = buf + (j >> 1) * nx + x;
+  float2* e = buf + (j >> 1) * lstride(nx) + px(x);
   return (j & 1) ? e->y : e->x;
 }
 
 // Value of row y0+j after an inverse FFT of row-pair lines (conj trick undone).
 __device__ __forceinline__ float rowpair_val(const float2* buf, int j, int x, int nx) {
-  const float2 e = buf[(j >> 1) * nx + x];
+  const float2 e = buf[(j >> 1) * lstride(nx) + px(x)];
   return (j & 1) ? -e.y : e.x;
 }
 
@@ -318,10 +318,11 @@ row_kernel(const Item* __restrict__ items, const IO* __restrict__ io, const int2
   const int nx = M.nx, nxh = M.nxh, rt = M.rt;
   const int y0 = bm.y * rt;
   const int B = blockDim.x;
+  const int LS = lstride(nx);
   float2* bufA = lds;
-  float2* bufB = lds + rt * nx;
-  float2* tw = lds + 2 * rt * nx;
-  void* tap_base = lds + 2 * rt * nx + nx;
+  float2* bufB = lds + rt * LS;
+  float2* tw = lds + 2 * rt * LS;
+  void* tap_base = lds + 2 * rt * LS + nx;
   const int tot = rt * nx;
   const float dt = M.dt;
   const float rnx = 1.0f / static_cast<float>(nx);
@@ -346,23 +347,23 @@ row_kernel(const Item* __restrict__ items, const IO* __restrict__ io, const int2
       }
     }
     __syncthreads();
-    float2* r = fft_lines(bufA, bufB, rt, nx, nx, M.radx, M.nstx, M.radx4, M.nstx4, tw);
+    float2* r = fft_lines(bufA, bufB, rt, nx, LS, M.radx, M.nstx, tw);
     float2* o = other(r, bufA, bufB);
     FOR_K {
       const int it = threadIdx.x + k * B;
       if (it < tot) {
         const int j = fdiv(it, nx, rnx), x = it - j * nx;
         const size_t idx = size_t(y0 + j) * nx + x;
-        const float2 z = r[it];
+        const float2 z = r[j * LS + px(x)];
         const float vx = ax[k] * (ax[k] * vxo[k] - bx[k] * z.x);
         const float vy = ay[k] * (ay[k] * vyo[k] + by[k] * z.y);
         W.f0[idx] = vx;
         W.f1[idx] = vy;
-        o[it] = make_float2(vx, vy);
+        o[j * LS + px(x)] = make_float2(vx, vy);
       }
     }
     __syncthreads();
-    r = fft_lines(o, other(o, bufA, bufB), rt, nx, nx, M.radx, M.nstx, M.radx4, M.nstx4, tw);
+    r = fft_lines(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
     store_pair_spectra(r, W.s0, W.s1, y0, rt, nx, nxh);
   } else if constexpr (MODE == RM_F2 || MODE == RM_F2L) {
     // eq num-rho with the additive source of eq s1 (dt s = p0 / (2 d c^2), d = 2)
@@ -391,7 +392,7 @@ row_kernel(const Item* __restrict__ items, const IO* __restrict__ io, const int2
     float2* r = nullptr;
     float2* o = bufA;
     if (!skip) {
-      r = fft_lines(bufA, bufB, rt, nx, nx, M.radx, M.nstx, M.radx4, M.nstx4, tw);
+      r = fft_lines(bufA, bufB, rt, nx, LS, M.radx, M.nstx, tw);
       o = other(r, bufA, bufB);
     }
     FOR_K {
@@ -401,7 +402,7 @@ row_kernel(const Item* __restrict__ items, const IO* __restrict__ io, const int2
         const size_t idx = size_t(y0 + j) * nx + x;
         float ex = 0.f, ey = 0.f;
         if (!skip) {
-          const float2 z = r[it];
+          const float2 z = r[j * LS + px(x)];
           ex = z.x;
           ey = -z.y;
         } else {
@@ -418,7 +419,7 @@ row_kernel(const Item* __restrict__ items, const IO* __restrict__ io, const int2
           // Each is transformed with its own rows paired (S and u differ by
           // orders of magnitude, so they must not share one complex FFT).
           pcomp(o, j, x, nx) = rx + ry;
-          pcomp(o + (rt / 2) * nx, j, x, nx) = r0[k] * (ax[k] * ex + ay[k] * ey);
+          pcomp(o + (rt / 2) * LS, j, x, nx) = r0[k] * (ax[k] * ex + ay[k] * ey);
         } else {
           const float p = c2[k] * (rx + ry);
           pcomp(o, j, x, nx) = p;
@@ -428,19 +429,19 @@ row_kernel(const Item* __restrict__ items, const IO* __restrict__ io, const int2
     }
     __syncthreads();
     if constexpr (MODE == RM_F2) {
-      r = fft_lines(o, other(o, bufA, bufB), rt, nx, nx, M.radx, M.nstx, M.radx4, M.nstx4, tw);
+      r = fft_lines(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
       store_rowpair_spectra(r, W.s0, y0, rt / 2, nx, nxh);
-      store_rowpair_spectra(r + (rt / 2) * nx, W.s1, y0, rt / 2, nx, nxh);
+      store_rowpair_spectra(r + (rt / 2) * LS, W.s1, y0, rt / 2, nx, nxh);
     } else {
       if (!(flags & FL_NO_SENSORS)) sensor_partials(M, T, o, y0, W.part, n + 1);
-      r = fft_lines(o, other(o, bufA, bufB), rt / 2, nx, nx, M.radx, M.nstx, M.radx4, M.nstx4, tw);
+      r = fft_lines(o, other(o, bufA, bufB), rt / 2, nx, LS, M.radx, M.nstx, tw);
       store_rowpair_spectra(r, W.s0, y0, rt / 2, nx, nxh);
     }
   } else if constexpr (MODE == RM_F3) {
     // eq num-p: p = c^2 (S - eta Y_dis S + tau Y_abs u)
     float rs[kMaxPer], c2[kMaxPer], ce[kMaxPer], ctau[kMaxPer];
     load_rowpair_lines(bufA, W.s0, y0, rt / 2, nx, nxh);
-    load_rowpair_lines(bufA + (rt / 2) * nx, W.s1, y0, rt / 2, nx, nxh);
+    load_rowpair_lines(bufA + (rt / 2) * LS, W.s1, y0, rt / 2, nx, nxh);
     load_tw(tw, M.twx, nx);
     const TapStage T = stage_taps(M, tap_base, y0, rt, nullptr, 0);
     FOR_K {
@@ -455,13 +456,13 @@ row_kernel(const Item* __restrict__ items, const IO* __restrict__ io, const int2
       }
     }
     __syncthreads();
-    float2* r = fft_lines(bufA, bufB, rt, nx, nx, M.radx, M.nstx, M.radx4, M.nstx4, tw);
+    float2* r = fft_lines(bufA, bufB, rt, nx, LS, M.radx, M.nstx, tw);
     float2* o = other(r, bufA, bufB);
     FOR_K {
       const int it = threadIdx.x + k * B;
       if (it < tot) {
         const int j = fdiv(it, nx, rnx), x = it - j * nx;
-        const float ys = rowpair_val(r, j, x, nx), yu = rowpair_val(r + (rt / 2) * nx, j, x, nx);
+        const float ys = rowpair_val(r, j, x, nx), yu = rowpair_val(r + (rt / 2) * LS, j, x, nx);
         const float p = c2[k] * rs[k] - ce[k] * ys + ctau[k] * yu;
         pcomp(o, j, x, nx) = p;
         if (flags & FL_STORE_P) W.q[size_t(y0 + j) * nx + x] = p;
@@ -469,7 +470,7 @@ row_kernel(const Item* __restrict__ items, const IO* __restrict__ io, const int2
     }
     __syncthreads();
     if (!(flags & FL_NO_SENSORS)) sensor_partials(M, T, o, y0, W.part, n + 1);
-    r = fft_lines(o, other(o, bufA, bufB), rt / 2, nx, nx, M.radx, M.nstx, M.radx4, M.nstx4, tw);
+    r = fft_lines(o, other(o, bufA, bufB), rt / 2, nx, LS, M.radx, M.nstx, tw);
     store_rowpair_spectra(r, W.s0, y0, rt / 2, nx, nxh);
   } else if constexpr (MODE == RM_A1 || MODE == RM_A1L) {
     // transpose of eqs num-m and num-p: p* += M^T r_{n+1}; q = c^2 p*
@@ -502,14 +503,14 @@ row_kernel(const Item* __restrict__ items, const IO* __restrict__ io, const int2
     __syncthreads();
     float2* r = bufA;
     if (!first) {
-      r = fft_lines(bufA, bufB, half, nx, nx, M.radx, M.nstx, M.radx4, M.nstx4, tw);
+      r = fft_lines(bufA, bufB, half, nx, LS, M.radx, M.nstx, tw);
       // p* = -(grad_x^- g_x + grad_y^- g_y): negate the (conjugated) inverse
-      for (int it = threadIdx.x; it < half * nx; it += B) {
+      for (int it = threadIdx.x; it < half * LS; it += B) {
         const float2 z = r[it];
         r[it] = make_float2(-z.x, z.y);
       }
     } else {
-      for (int it = threadIdx.x; it < half * nx; it += B) r[it] = make_float2(0.f, 0.f);
+      for (int it = threadIdx.x; it < half * LS; it += B) r[it] = make_float2(0.f, 0.f);
     }
     __syncthreads();
     sensor_scatter(M, T, r, y0, rt, X.in, n + 1);
@@ -525,7 +526,7 @@ row_kernel(const Item* __restrict__ items, const IO* __restrict__ io, const int2
           // eta q and tau q, each with its own rows paired (see RM_F2)
           W.q[idx] = c2[k] * pb;
           pcomp(o, j, x, nx) = ce[k] * pb;
-          pcomp(o + half * nx, j, x, nx) = ctau[k] * pb;
+          pcomp(o + half * LS, j, x, nx) = ctau[k] * pb;
         } else {
           // lossless: S* = q, u* = 0, then the transposed mass update
           const float q = c2[k] * pb;
@@ -534,7 +535,7 @@ row_kernel(const Item* __restrict__ items, const IO* __restrict__ io, const int2
           if (n == -1) {
             X.out[idx] = (rbx + rby + gacc[k]) * (0.25f / c2[k]);
           } else {
-            o[it] = make_float2(-dt * r0[k] * ax[k] * rbx, -dt * r0[k] * ay[k] * rby);
+            o[j * LS + px(x)] = make_float2(-dt * r0[k] * ax[k] * rbx, -dt * r0[k] * ay[k] * rby);
             W.f2[idx] = ax[k] * ax[k] * rbx;
             W.f3[idx] = ay[k] * ay[k] * rby;
           }
@@ -543,11 +544,11 @@ row_kernel(const Item* __restrict__ items, const IO* __restrict__ io, const int2
     }
     __syncthreads();
     if constexpr (MODE == RM_A1) {
-      r = fft_lines(o, other(o, bufA, bufB), rt, nx, nx, M.radx, M.nstx, M.radx4, M.nstx4, tw);
+      r = fft_lines(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
       store_rowpair_spectra(r, W.s0, y0, half, nx, nxh);
-      store_rowpair_spectra(r + half * nx, W.s1, y0, half, nx, nxh);
+      store_rowpair_spectra(r + half * LS, W.s1, y0, half, nx, nxh);
     } else if (n != -1) {
-      r = fft_lines(o, other(o, bufA, bufB), rt, nx, nx, M.radx, M.nstx, M.radx4, M.nstx4, tw);
+      r = fft_lines(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
       store_pair_spectra(r, W.s0, W.s1, y0, rt, nx, nxh);
     }
   } else if constexpr (MODE == RM_A2) {
@@ -556,7 +557,7 @@ row_kernel(const Item* __restrict__ items, const IO* __restrict__ io, const int2
     float qv[kMaxPer], rbx0[kMaxPer], rby0[kMaxPer], r0[kMaxPer], ax[kMaxPer], ay[kMaxPer];
     float c2[kMaxPer], gacc[kMaxPer];
     load_rowpair_lines(bufA, W.s0, y0, rt / 2, nx, nxh);
-    load_rowpair_lines(bufA + (rt / 2) * nx, W.s1, y0, rt / 2, nx, nxh);
+    load_rowpair_lines(bufA + (rt / 2) * LS, W.s1, y0, rt / 2, nx, nxh);
     load_tw(tw, M.twx, nx);
     FOR_K {
       const int it = threadIdx.x + k * B;
@@ -574,21 +575,21 @@ row_kernel(const Item* __restrict__ items, const IO* __restrict__ io, const int2
       }
     }
     __syncthreads();
-    float2* r = fft_lines(bufA, bufB, rt, nx, nx, M.radx, M.nstx, M.radx4, M.nstx4, tw);
+    float2* r = fft_lines(bufA, bufB, rt, nx, LS, M.radx, M.nstx, tw);
     float2* o = other(r, bufA, bufB);
     FOR_K {
       const int it = threadIdx.x + k * B;
       if (it < tot) {
         const int j = fdiv(it, nx, rnx), x = it - j * nx;
         const size_t idx = size_t(y0 + j) * nx + x;
-        const float yd = rowpair_val(r, j, x, nx), ya = rowpair_val(r + (rt / 2) * nx, j, x, nx);
+        const float yd = rowpair_val(r, j, x, nx), ya = rowpair_val(r + (rt / 2) * LS, j, x, nx);
         const float sb = qv[k] - yd;
         const float rbx = rbx0[k] + sb, rby = rby0[k] + sb;
         if (n == 0) X.out[idx] = rbx + rby;
         if (n == -1) {
           X.out[idx] = (rbx + rby + gacc[k]) * (0.25f / c2[k]);
         } else {
-          o[it] = make_float2(r0[k] * ax[k] * (ya - dt * rbx), r0[k] * ay[k] * (ya - dt * rby));
+          o[j * LS + px(x)] = make_float2(r0[k] * ax[k] * (ya - dt * rbx), r0[k] * ay[k] * (ya - dt * rby));
           W.f2[idx] = ax[k] * ax[k] * rbx;
           W.f3[idx] = ay[k] * ay[k] * rby;
         }
@@ -596,7 +597,7 @@ row_kernel(const Item* __restrict__ items, const IO* __restrict__ io, const int2
     }
     __syncthreads();
     if (n != -1) {
-      r = fft_lines(o, other(o, bufA, bufB), rt, nx, nx, M.radx, M.nstx, M.radx4, M.nstx4, tw);
+      r = fft_lines(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
       store_pair_spectra(r, W.s0, W.s1, y0, rt, nx, nxh);
     }
   } else if constexpr (MODE == RM_A3) {
@@ -619,23 +620,23 @@ row_kernel(const Item* __restrict__ items, const IO* __restrict__ io, const int2
       }
     }
     __syncthreads();
-    float2* r = fft_lines(bufA, bufB, rt, nx, nx, M.radx, M.nstx, M.radx4, M.nstx4, tw);
+    float2* r = fft_lines(bufA, bufB, rt, nx, LS, M.radx, M.nstx, tw);
     float2* o = other(r, bufA, bufB);
     FOR_K {
       const int it = threadIdx.x + k * B;
       if (it < tot) {
         const int j = fdiv(it, nx, rnx), x = it - j * nx;
         const size_t idx = size_t(y0 + j) * nx + x;
-        const float2 z = r[it];
+        const float2 z = r[j * LS + px(x)];
         const float vbx = vbx0[k] - z.x;
         const float vby = vby0[k] + z.y;
-        o[it] = make_float2(-ax[k] * bx[k] * vbx, -ay[k] * by[k] * vby);
+        o[j * LS + px(x)] = make_float2(-ax[k] * bx[k] * vbx, -ay[k] * by[k] * vby);
         W.f0[idx] = ax[k] * ax[k] * vbx;
         W.f1[idx] = ay[k] * ay[k] * vby;
       }
     }
     __syncthreads();
-    r = fft_lines(o, other(o, bufA, bufB), rt, nx, nx, M.radx, M.nstx, M.radx4, M.nstx4, tw);
+    r = fft_lines(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
     store_pair_spectra(r, W.s0, W.s1, y0, rt, nx, nxh);
   } else if constexpr (MODE == RM_FWD1) {
     const float* src = X.in;
@@ -645,13 +646,13 @@ row_kernel(const Item* __restrict__ items, const IO* __restrict__ io, const int2
       pcomp(bufA, j, x, nx) = src[size_t(y0 + j) * nx + x];
     }
     __syncthreads();
-    float2* r = fft_lines(bufA, bufB, rt / 2, nx, nx, M.radx, M.nstx, M.radx4, M.nstx4, tw);
+    float2* r = fft_lines(bufA, bufB, rt / 2, nx, LS, M.radx, M.nstx, tw);
     store_rowpair_spectra(r, W.s0, y0, rt / 2, nx, nxh);
   } else if constexpr (MODE == RM_INV1) {
     load_rowpair_lines(bufA, W.s0, y0, rt / 2, nx, nxh);
     load_tw(tw, M.twx, nx);
     __syncthreads();
-    float2* r = fft_lines(bufA, bufB, rt / 2, nx, nx, M.radx, M.nstx, M.radx4, M.nstx4, tw);
+    float2* r = fft_lines(bufA, bufB, rt / 2, nx, LS, M.radx, M.nstx, tw);
     float* dst = X.out;
     for (int it = threadIdx.x; it < tot; it += B) {
       const int j = fdiv(it, nx, rnx), x = it - j * nx;
@@ -692,7 +693,7 @@ col_kernel(const Item* __restrict__ items, const int2* __restrict__ map, int mco
   const Medium& M = items[bm.x].m;
   const Work& W = items[bm.x].w;
   if (n > M.nt - 2) return;
-  const int ny = M.ny, nxh = M.nxh, ct = M.ct, ls = col_line_stride(ny, ct);
+  const int ny = M.ny, nxh = M.nxh, ct = M.ct, ls = lstride(ny);
   const int c0 = bm.y * ct;
   const int B = blockDim.x;
   const int nsl = 2;
@@ -718,7 +719,7 @@ col_kernel(const Item* __restrict__ items, const int2* __restrict__ map, int mco
     const int rest = fdiv(it, ct, rct), c = it - rest * ct;
     const int f = fdiv(rest, ny, rny), ky = rest - f * ny;
     const float2* s = f ? W.s1 : W.s0;
-    bufA[(f * ct + c) * ls + ky] = s[size_t(ky) * nxh + c0 + c];
+    bufA[(f * ct + c) * ls + px(ky)] = s[size_t(ky) * nxh + c0 + c];
   }
   load_tw(tw, M.twy, ny);
   const int tot = ct * ny;
@@ -741,7 +742,7 @@ col_kernel(const Item* __restrict__ items, const int2* __restrict__ map, int mco
     }
   }
   __syncthreads();
-  float2* r = fft_lines(bufA, bufB, nin * ct, ny, ls, M.rady, M.nsty, M.rady4, M.nsty4, tw);
+  float2* r = fft_lines(bufA, bufB, nin * ct, ny, ls, M.rady, M.nsty, tw);
   float2* o = other(r, bufA, bufB);
   FOR_K {
     const int it = threadIdx.x + k * B;
@@ -754,7 +755,7 @@ col_kernel(const Item* __restrict__ items, const int2* __restrict__ map, int mco
         const int km = ky ? ny - ky : 0;
         float2 f0[2], fn[2];
         for (int f = 0; f < nin; ++f) {
-          const float2 z = r[(f * ct + c) * ls + ky], zm = cconj(r[(f * ct + c) * ls + km]);
+          const float2 z = r[(f * ct + c) * ls + px(ky)], zm = cconj(r[(f * ct + c) * ls + px(km)]);
           f0[f] = cscale(cadd(z, zm), 0.5f);
           fn[f] = mul_mi(cscale(csub(z, zm), 0.5f));
         }
@@ -767,29 +768,29 @@ col_kernel(const Item* __restrict__ items, const int2* __restrict__ map, int mco
             gn = cadd(gn, cmul(mult_of(code, p, true), fn[f]));
           }
           // W = G0 + i GN, stored conjugated for the inverse transform
-          o[(q * ct + c) * ls + ky] = cconj(make_float2(g0.x - gn.y, g0.y + gn.x));
+          o[(q * ct + c) * ls + px(ky)] = cconj(make_float2(g0.x - gn.y, g0.y + gn.x));
         }
       } else {
         float2 in[2];
-        for (int f = 0; f < nin; ++f) in[f] = r[(f * ct + c) * ls + ky];
+        for (int f = 0; f < nin; ++f) in[f] = r[(f * ct + c) * ls + px(ky)];
         for (int q = 0; q < nout; ++q) {
           float2 acc = make_float2(0.f, 0.f);
           for (int f = 0; f < nin; ++f) {
             const int code = (mcode >> (4 * (2 * q + f))) & 15;
             if (code) acc = cadd(acc, cmul(mult_of(code, p, false), in[f]));
           }
-          o[(q * ct + c) * ls + ky] = cconj(acc);
+          o[(q * ct + c) * ls + px(ky)] = cconj(acc);
         }
       }
     }
   }
   __syncthreads();
-  r = fft_lines(o, other(o, bufA, bufB), nout * ct, ny, ls, M.rady, M.nsty, M.rady4, M.nsty4, tw);
+  r = fft_lines(o, other(o, bufA, bufB), nout * ct, ny, ls, M.rady, M.nsty, tw);
   for (int it = threadIdx.x; it < nout * ct * ny; it += B) {
     const int rest = fdiv(it, ct, rct), c = it - rest * ct;
     const int f = fdiv(rest, ny, rny), ky = rest - f * ny;
     float2* s = f ? W.s1 : W.s0;
-    s[size_t(ky) * nxh + c0 + c] = cconj(r[(f * ct + c) * ls + ky]);
+    s[size_t(ky) * nxh + c0 + c] = cconj(r[(f * ct + c) * ls + px(ky)]);
   }
 }
 

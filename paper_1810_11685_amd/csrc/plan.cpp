@@ -587,8 +587,6 @@ qpat_status plan_build(qpat_plan P, const double* c0, const double* rho0) {
   M.dt = float(dt);
   radix_plan(nx, &M.radx, &M.nstx, 8);
   radix_plan(ny, &M.rady, &M.nsty, 8);
-  radix_plan(nx, &M.radx4, &M.nstx4, 4);
-  radix_plan(ny, &M.rady4, &M.nsty4, 4);
   M.c2 = (const float*)(d + o_c2);
   M.c2eta = (const float*)(d + o_c2eta);
   M.c2tau = (const float*)(d + o_c2tau);

@@ -31,8 +31,6 @@ struct Medium {
   int rthr, cthr;         // threads per block of the row / column passes
   uint32_t radx, rady;    // radix plans (max radix 8), 4 bits per stage, first stage lowest
   int nstx, nsty;
-  uint32_t radx4, rady4;  // radix plans with max radix 4
-  int nstx4, nsty4;
   const float *c2, *c2eta, *c2tau, *rho0, *bx, *by;   // [ny][nx]; bx = dt/rho_x, by = dt/rho_y
   const float *avx, *arx, *avy, *ary;                 // PML diagonals: [nx] / [ny]
   const float2 *dxp, *dxm;                            // [nxh+1] i kx e^{+-i kx dx/2}
@@ -100,16 +98,16 @@ hipError_t launch_combine(const Item* items, const IO* io, int nitems, int max_c
 hipError_t launch_dot(const float* a, const float* b, int64_t n, double* partial, int nblk,
                       double* out, hipStream_t st);
 
+// LDS line stride: one pad element per 8 (see px() in the kernels).
+__host__ __device__ inline int lstride(int n) { return n + (n >> 3); }
+
 // LDS bytes of one block of each pass: ping-pong line buffers, the twiddle
 // table, and (rows) the staged sensor taps.
 inline size_t row_lds_bytes(int nx, int rt) {
-  return size_t(2 * rt * nx + nx) * sizeof(float2) + kTapCap * (sizeof(Tap) + sizeof(float));
+  return size_t(2 * rt * lstride(nx) + nx) * sizeof(float2) + kTapCap * (sizeof(Tap) + sizeof(float));
 }
-// Column lines are padded by one element when a tile holds several columns
-// (their transposed loads would otherwise hit one LDS bank).
-__host__ __device__ inline int col_line_stride(int ny, int ct) { return ct == 1 ? ny : ny + 1; }
 inline size_t col_lds_bytes(int ny, int ct) {
-  return (size_t(2) * 2 * ct * col_line_stride(ny, ct) + ny) * sizeof(float2);
+  return (size_t(2) * 2 * ct * lstride(ny) + ny) * sizeof(float2);
 }
 
 }  // namespace qpat

@@ -177,18 +177,15 @@ def test_batch_equals_single_bitwise(q):
         assert np.array_equal(gb[i], N(plan.adjoint(rb[i])))
 
 
-def test_tiles_do_not_change_results_beyond_rounding(q):
+def test_tiles_do_not_change_results(q):
     prm, c0, rho0, p0 = problem(64, 64, 50)
     plan = q.Plan(prm, c0, rho0)
     base = N(plan.forward(T(p0)))
-    # launch shapes change the FFT radix plan (radix 4 when radix 8 would leave
-    # threads idle), so results agree to FP32 rounding, not bit for bit
+    # the per-line arithmetic does not depend on the launch shape
     for shape in [(2, 1, 64, 64), (4, 4, 128, 256), (16, 8, 256, 128), (2, 2, 256, 64)]:
         plan.set_tiles(*shape)
         assert plan.tiles() == shape
-        d = N(plan.forward(T(p0)))
-        assert rel(d, base) <= 1e-6
-        assert np.array_equal(N(plan.forward(T(p0))), d)
+        assert np.array_equal(N(plan.forward(T(p0))), base)
 
 
 def test_graph_mode_replays_match(q):
