@@ -256,15 +256,31 @@ __device__ __forceinline__ TapStage stage_taps(const Medium& M, void* base, int 
   T.e1 = M.tap_off[y0 + rt];
   const int cnt = min(T.e1 - T.e0, kTapCap);
   for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
-    const Tap t = M.taps[T.e0 + i];
-    T.tl[i] = t;
-    if (res) T.rv[i] = res[size_t(m) * M.ns + t.s];
+    // copied word by word (a struct copy would go through scratch)
+    const int* src = reinterpret_cast<const int*>(M.taps + T.e0 + i);
+    int* dst = reinterpret_cast<int*>(T.tl + i);
+    int w[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) w[q] = src[q];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) dst[q] = w[q];
+    if (res) T.rv[i] = res[size_t(m) * M.ns + w[0]];
   }
   return T;
 }
 
 __device__ __forceinline__ Tap tap_at(const Medium& M, const TapStage& T, int e) {
-  return (e - T.e0 < kTapCap) ? T.tl[e - T.e0] : M.taps[e];
+  const Tap* src = (e - T.e0 < kTapCap) ? T.tl + (e - T.e0) : M.taps + e;
+  Tap t;
+  t.s = src->s;
+  t.slot = src->slot;
+  t.y = src->y;
+  t.ixl = src->ixl;
+  t.ixr = src->ixr;
+  t.wl = src->wl;
+  t.wr = src->wr;
+  t.pad = 0;
+  return t;
 }
 
 // Forward sensor partials for rows y0 .. y0+rt-1 (bilinear taps, eq num-m).
@@ -750,36 +766,52 @@ col_kernel(const Item* __restrict__ items, const int2* __restrict__ map, int mco
       const int c = fdiv(it, ny, rny), ky = it - c * ny;
       const int kx = c0 + c;
       const MultPre& p = P[k];
+      // (loops over fields have compile-time bounds so the arrays stay in registers)
       if (kx == 0) {
         // packed column: DC (real part) and Nyquist (imaginary part) columns
         const int km = ky ? ny - ky : 0;
         float2 f0[2], fn[2];
-        for (int f = 0; f < nin; ++f) {
-          const float2 z = r[(f * ct + c) * ls + px(ky)], zm = cconj(r[(f * ct + c) * ls + px(km)]);
-          f0[f] = cscale(cadd(z, zm), 0.5f);
-          fn[f] = mul_mi(cscale(csub(z, zm), 0.5f));
-        }
-        for (int q = 0; q < nout; ++q) {
-          float2 g0 = make_float2(0.f, 0.f), gn = make_float2(0.f, 0.f);
-          for (int f = 0; f < nin; ++f) {
-            const int code = (mcode >> (4 * (2 * q + f))) & 15;
-            if (!code) continue;
-            g0 = cadd(g0, cmul(mult_of(code, p, false), f0[f]));
-            gn = cadd(gn, cmul(mult_of(code, p, true), fn[f]));
+#pragma unroll
+        for (int f = 0; f < 2; ++f) {
+          if (f < nin) {
+            const float2 z = r[(f * ct + c) * ls + px(ky)], zm = cconj(r[(f * ct + c) * ls + px(km)]);
+            f0[f] = cscale(cadd(z, zm), 0.5f);
+            fn[f] = mul_mi(cscale(csub(z, zm), 0.5f));
+          } else {
+            f0[f] = fn[f] = make_float2(0.f, 0.f);
           }
-          // W = G0 + i GN, stored conjugated for the inverse transform
-          o[(q * ct + c) * ls + px(ky)] = cconj(make_float2(g0.x - gn.y, g0.y + gn.x));
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          if (q < nout) {
+            float2 g0 = make_float2(0.f, 0.f), gn = make_float2(0.f, 0.f);
+#pragma unroll
+            for (int f = 0; f < 2; ++f) {
+              const int code = (mcode >> (4 * (2 * q + f))) & 15;
+              if (code) {
+                g0 = cadd(g0, cmul(mult_of(code, p, false), f0[f]));
+                gn = cadd(gn, cmul(mult_of(code, p, true), fn[f]));
+              }
+            }
+            // W = G0 + i GN, stored conjugated for the inverse transform
+            o[(q * ct + c) * ls + px(ky)] = cconj(make_float2(g0.x - gn.y, g0.y + gn.x));
+          }
         }
       } else {
         float2 in[2];
-        for (int f = 0; f < nin; ++f) in[f] = r[(f * ct + c) * ls + px(ky)];
-        for (int q = 0; q < nout; ++q) {
-          float2 acc = make_float2(0.f, 0.f);
-          for (int f = 0; f < nin; ++f) {
-            const int code = (mcode >> (4 * (2 * q + f))) & 15;
-            if (code) acc = cadd(acc, cmul(mult_of(code, p, false), in[f]));
+#pragma unroll
+        for (int f = 0; f < 2; ++f) in[f] = f < nin ? r[(f * ct + c) * ls + px(ky)] : make_float2(0.f, 0.f);
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          if (q < nout) {
+            float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+            for (int f = 0; f < 2; ++f) {
+              const int code = (mcode >> (4 * (2 * q + f))) & 15;
+              if (code) acc = cadd(acc, cmul(mult_of(code, p, false), in[f]));
+            }
+            o[(q * ct + c) * ls + px(ky)] = cconj(acc);
           }
-          o[(q * ct + c) * ls + px(ky)] = cconj(acc);
         }
       }
     }

@@ -17,7 +17,7 @@ constexpr int kXcds = 8;      // MI355X: 8 XCDs, work-groups dispatched round-ro
 // One bilinear sensor tap pair on one grid row: the sensor's contribution from
 // row y is wl * f[y][ixl] + wr * f[y][ixr]; `slot` (0/1) says whether y is the
 // sensor's lower or upper row; entries are sorted by row y.
-struct Tap {
+struct alignas(16) Tap {
   int s, slot, y, ixl, ixr;
   float wl, wr;
   int pad;
