@@ -314,25 +314,68 @@ __device__ __forceinline__ void load_tw(float2* dst, const float2* __restrict__ 
   for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = tw[i];
 }
 
+// ---------------------------------------------------------------- block -> (item, tile)
+// Uniform launches (all items are vectors of one plan) carry the medium in
+// the kernel arguments and find their work buffers by a fixed stride, so the
+// first global loads of a block are its data; other launches read (item,
+// tile) from a block map and the item descriptors from device memory.
+// Either way consecutive tiles of one item are placed on one XCD.
+template <bool U>
+__device__ __forceinline__ bool locate(const Launch& L, int ntile, int chunk, int& item, int& tile) {
+  if constexpr (U) {
+    const int b = blockIdx.x;
+    const int i = (b & (kXcds - 1)) * chunk + (b / kXcds);
+    if (i >= L.nitems * ntile) return false;
+    item = i / ntile;
+    tile = i - item * ntile;
+    return true;
+  } else {
+    const int2 bm = L.map[blockIdx.x];
+    item = bm.x;
+    tile = bm.y;
+    return bm.x >= 0;
+  }
+}
+
+template <bool U>
+__device__ __forceinline__ const Medium& medium_of(const Launch& L, int item) {
+  if constexpr (U)
+    return L.m;
+  else
+    return L.items[item].m;
+}
+
+__device__ __forceinline__ Work shift_work(const Work& w, long long off) {
+  Work r;
+  r.f0 = reinterpret_cast<float*>(reinterpret_cast<char*>(w.f0) + off);
+  r.f1 = reinterpret_cast<float*>(reinterpret_cast<char*>(w.f1) + off);
+  r.f2 = reinterpret_cast<float*>(reinterpret_cast<char*>(w.f2) + off);
+  r.f3 = reinterpret_cast<float*>(reinterpret_cast<char*>(w.f3) + off);
+  r.q = reinterpret_cast<float*>(reinterpret_cast<char*>(w.q) + off);
+  r.s0 = reinterpret_cast<float2*>(reinterpret_cast<char*>(w.s0) + off);
+  r.s1 = reinterpret_cast<float2*>(reinterpret_cast<char*>(w.s1) + off);
+  r.part = reinterpret_cast<float*>(reinterpret_cast<char*>(w.part) + off);
+  return r;
+}
+
 // ---------------------------------------------------------------- row pass
 // Every global load of a pass is issued in one phase at the start: spectra and
 // twiddles into LDS, pointwise operands into registers (at most kMaxPer
 // elements per thread); the FFT stages then run out of LDS only.
 #define FOR_K _Pragma("unroll") for (int k = 0; k < kMaxPer; ++k)
 
-template <int MODE>
+template <int MODE, bool U>
 __global__ void __launch_bounds__(kBlock)
-row_kernel(const Item* __restrict__ items, const IO* __restrict__ io, const int2* __restrict__ map,
-           int n, int flags) {
+row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
   extern __shared__ float2 lds[];
-  const int2 bm = map[blockIdx.x];
-  if (bm.x < 0) return;
-  const Medium& M = items[bm.x].m;
-  const Work& W = items[bm.x].w;
-  const IO& X = io[bm.x];
+  int item, tile;
+  if (!locate<U>(L, ntile, chunk, item, tile)) return;
+  const Medium& M = medium_of<U>(L, item);
+  const Work W = U ? shift_work(L.w0, item * L.wstride) : L.items[item].w;
+  const IO& X = L.io[item];
   if (n > M.nt - 2) return;  // this problem has finished (uneven batches)
   const int nx = M.nx, nxh = M.nxh, rt = M.rt;
-  const int y0 = bm.y * rt;
+  const int y0 = tile * rt;
   const int B = blockDim.x;
   const int LS = lstride(nx);
   float2* bufA = lds;
@@ -700,17 +743,17 @@ __device__ __forceinline__ float2 mult_of(int code, const MultPre& P, bool nyq) 
   }
 }
 
+template <bool U>
 __global__ void __launch_bounds__(kBlock)
-col_kernel(const Item* __restrict__ items, const int2* __restrict__ map, int mcode, int nin, int nout,
-           int n) {
+col_kernel(const Launch L, int ntile, int chunk, int mcode, int nin, int nout, int n) {
   extern __shared__ float2 lds[];
-  const int2 bm = map[blockIdx.x];
-  if (bm.x < 0) return;
-  const Medium& M = items[bm.x].m;
-  const Work& W = items[bm.x].w;
+  int item, tile;
+  if (!locate<U>(L, ntile, chunk, item, tile)) return;
+  const Medium& M = medium_of<U>(L, item);
+  const Work W = U ? shift_work(L.w0, item * L.wstride) : L.items[item].w;
   if (n > M.nt - 2) return;
   const int ny = M.ny, nxh = M.nxh, ct = M.ct, ls = lstride(ny);
-  const int c0 = bm.y * ct;
+  const int c0 = tile * ct;
   const int B = blockDim.x;
   const int nsl = 2;
   float2* bufA = lds;
@@ -875,32 +918,45 @@ __global__ void __launch_bounds__(kBlock) dot_final(const double* __restrict__ p
 
 // ---------------------------------------------------------------- launchers
 template <int MODE>
-static hipError_t launch_row_t(const Item* items, const IO* io, const int2* map, int nblocks, int threads,
+static hipError_t launch_row_t(const Launch& L, bool uniform, int ntile, int chunk, int nblocks, int threads,
                                size_t lds, int n, int flags, hipStream_t st) {
-  hipLaunchKernelGGL(row_kernel<MODE>, dim3(nblocks), dim3(threads), lds, st, items, io, map, n, flags);
+  if (uniform)
+    hipLaunchKernelGGL((row_kernel<MODE, true>), dim3(nblocks), dim3(threads), lds, st, L, ntile, chunk, n,
+                       flags);
+  else
+    hipLaunchKernelGGL((row_kernel<MODE, false>), dim3(nblocks), dim3(threads), lds, st, L, ntile, chunk, n,
+                       flags);
   return hipGetLastError();
 }
 
-hipError_t launch_row(int mode, const Item* items, const IO* io, const int2* map, int nblocks, int threads,
+hipError_t launch_row(int mode, const Launch& L, bool uniform, int ntile, int chunk, int nblocks, int threads,
                       size_t lds, int n, int flags, hipStream_t st) {
+#define QPAT_ROW_CASE(m) \
+  case m: return launch_row_t<m>(L, uniform, ntile, chunk, nblocks, threads, lds, n, flags, st);
   switch (mode) {
-    case RM_F1: return launch_row_t<RM_F1>(items, io, map, nblocks, threads, lds, n, flags, st);
-    case RM_F2: return launch_row_t<RM_F2>(items, io, map, nblocks, threads, lds, n, flags, st);
-    case RM_F2L: return launch_row_t<RM_F2L>(items, io, map, nblocks, threads, lds, n, flags, st);
-    case RM_F3: return launch_row_t<RM_F3>(items, io, map, nblocks, threads, lds, n, flags, st);
-    case RM_A1: return launch_row_t<RM_A1>(items, io, map, nblocks, threads, lds, n, flags, st);
-    case RM_A1L: return launch_row_t<RM_A1L>(items, io, map, nblocks, threads, lds, n, flags, st);
-    case RM_A2: return launch_row_t<RM_A2>(items, io, map, nblocks, threads, lds, n, flags, st);
-    case RM_A3: return launch_row_t<RM_A3>(items, io, map, nblocks, threads, lds, n, flags, st);
-    case RM_FWD1: return launch_row_t<RM_FWD1>(items, io, map, nblocks, threads, lds, n, flags, st);
-    case RM_INV1: return launch_row_t<RM_INV1>(items, io, map, nblocks, threads, lds, n, flags, st);
+    QPAT_ROW_CASE(RM_F1)
+    QPAT_ROW_CASE(RM_F2)
+    QPAT_ROW_CASE(RM_F2L)
+    QPAT_ROW_CASE(RM_F3)
+    QPAT_ROW_CASE(RM_A1)
+    QPAT_ROW_CASE(RM_A1L)
+    QPAT_ROW_CASE(RM_A2)
+    QPAT_ROW_CASE(RM_A3)
+    QPAT_ROW_CASE(RM_FWD1)
+    QPAT_ROW_CASE(RM_INV1)
     default: return hipErrorInvalidValue;
   }
+#undef QPAT_ROW_CASE
 }
 
-hipError_t launch_col(int mcode, int nin, int nout, const Item* items, const int2* map, int nblocks,
-                      int threads, size_t lds, int n, hipStream_t st) {
-  hipLaunchKernelGGL(col_kernel, dim3(nblocks), dim3(threads), lds, st, items, map, mcode, nin, nout, n);
+hipError_t launch_col(int mcode, int nin, int nout, const Launch& L, bool uniform, int ntile, int chunk,
+                      int nblocks, int threads, size_t lds, int n, hipStream_t st) {
+  if (uniform)
+    hipLaunchKernelGGL((col_kernel<true>), dim3(nblocks), dim3(threads), lds, st, L, ntile, chunk, mcode, nin,
+                       nout, n);
+  else
+    hipLaunchKernelGGL((col_kernel<false>), dim3(nblocks), dim3(threads), lds, st, L, ntile, chunk, mcode, nin,
+                       nout, n);
   return hipGetLastError();
 }
 

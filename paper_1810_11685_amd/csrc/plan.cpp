@@ -141,6 +141,11 @@ struct Exec {
   size_t row_lds = 0, col_lds = 0;
   int rthr = kBlock, cthr = kBlock;  // threads per block (max over items)
   int max_nt = 0, max_data = 0;
+  // launch arguments; uniform = all items are vectors of one plan with equally
+  // spaced work buffers (no block map / descriptor loads in the kernels)
+  Launch L{};
+  bool uniform = false;
+  int row_ntile = 0, col_ntile = 0, row_chunk = 0, col_chunk = 0;
   bool lossy = false;
   // pinned staging ring for the I/O table
   static constexpr int kRing = 16;
@@ -215,6 +220,34 @@ qpat_status exec_build(Exec& E, const std::vector<Item>& items) {
   const std::vector<int2> rm = xcd_map(rows), cm = xcd_map(cols);
   E.nrow = int(rm.size());
   E.ncol = int(cm.size());
+  // uniform launch?
+  {
+    const Medium& m0 = items[0].m;
+    bool u = true;
+    long long stride = 0;
+    if (ni > 1) stride = (const char*)items[1].w.f0 - (const char*)items[0].w.f0;
+    for (int i = 0; i < ni && u; ++i) {
+      const Medium& m = items[i].m;
+      u = m.c2 == m0.c2 && m.nx == m0.nx && m.ny == m0.ny && m.nt == m0.nt && m.rt == m0.rt &&
+          m.ct == m0.ct && m.rthr == m0.rthr && m.cthr == m0.cthr;
+      const Work& w = items[i].w;
+      const Work& w0 = items[0].w;
+      auto d = [&](const void* a, const void* b) { return (long long)((const char*)a - (const char*)b); };
+      const long long off = stride * i;
+      u = u && d(w.f0, w0.f0) == off && d(w.f1, w0.f1) == off && d(w.f2, w0.f2) == off &&
+          d(w.f3, w0.f3) == off && d(w.q, w0.q) == off && d(w.s0, w0.s0) == off && d(w.s1, w0.s1) == off &&
+          d(w.part, w0.part) == off;
+    }
+    E.uniform = u;
+    E.L.m = m0;
+    E.L.w0 = items[0].w;
+    E.L.wstride = stride;
+    E.L.nitems = ni;
+    E.row_ntile = m0.ny / m0.rt;
+    E.col_ntile = m0.nxh / m0.ct;
+    E.row_chunk = (ni * E.row_ntile + kXcds - 1) / kXcds;
+    E.col_chunk = (ni * E.col_ntile + kXcds - 1) / kXcds;
+  }
   HIPCHK(hipMalloc(&E.d_items, sizeof(Item) * ni));
   HIPCHK(hipMalloc(&E.d_io, sizeof(IO) * ni));
   HIPCHK(hipMalloc(&E.d_rowmap, sizeof(int2) * rm.size()));
@@ -224,6 +257,9 @@ qpat_status exec_build(Exec& E, const std::vector<Item>& items) {
   HIPCHK(hipMemcpy(E.d_colmap, cm.data(), sizeof(int2) * cm.size(), hipMemcpyHostToDevice));
   HIPCHK(hipMemset(E.d_io, 0, sizeof(IO) * ni));
   HIPCHK(hipHostMalloc(&E.h_io, sizeof(IO) * ni * Exec::kRing, hipHostMallocDefault));
+  E.L.map = nullptr;
+  E.L.items = E.d_items;
+  E.L.io = E.d_io;
   for (int i = 0; i < Exec::kRing; ++i) HIPCHK(hipEventCreateWithFlags(&E.ev[i], hipEventDisableTiming));
   return QPAT_OK;
 }
@@ -244,10 +280,20 @@ qpat_status exec_set_io(Exec& E, const std::vector<IO>& io, hipStream_t st) {
 }
 
 hipError_t row(Exec& E, int mode, int n, int flags, hipStream_t st) {
-  return launch_row(mode, E.d_items, E.d_io, E.d_rowmap, E.nrow, E.rthr, E.row_lds, n, flags, st);
+  if (E.uniform)
+    return launch_row(mode, E.L, true, E.row_ntile, E.row_chunk, E.row_chunk * kXcds, E.rthr, E.row_lds, n,
+                      flags, st);
+  Launch L = E.L;
+  L.map = E.d_rowmap;
+  return launch_row(mode, L, false, 0, 0, E.nrow, E.rthr, E.row_lds, n, flags, st);
 }
 hipError_t col(Exec& E, int mcode, int nin, int nout, int n, hipStream_t st) {
-  return launch_col(mcode, nin, nout, E.d_items, E.d_colmap, E.ncol, E.cthr, E.col_lds, n, st);
+  if (E.uniform)
+    return launch_col(mcode, nin, nout, E.L, true, E.col_ntile, E.col_chunk, E.col_chunk * kXcds, E.cthr,
+                      E.col_lds, n, st);
+  Launch L = E.L;
+  L.map = E.d_colmap;
+  return launch_col(mcode, nin, nout, L, false, 0, 0, E.ncol, E.cthr, E.col_lds, n, st);
 }
 
 #define LCHK(expr)                           \

@@ -60,6 +60,19 @@ struct Item {
   Work w;
 };
 
+// Kernel argument block of the row / column passes.  Uniform launches use m,
+// w0 and wstride (item i's work buffers are w0 shifted by i * wstride bytes);
+// table launches use map and items.  io holds the per-call pointers.
+struct Launch {
+  Medium m;
+  Work w0;
+  long long wstride;
+  int nitems;
+  const int2* map;
+  const Item* items;
+  const IO* io;
+};
+
 // Column-pass multiplier codes: out_o = sum_i M[o][i] * in_i, code per entry.
 enum MultCode : int {
   MC_NONE = 0, MC_DXP = 1, MC_DXM = 2, MC_DYP = 3, MC_DYM = 4, MC_LDIS = 5, MC_LABS = 6
@@ -89,9 +102,9 @@ enum Flags : int {
 };
 
 // Launch helpers implemented in kernels.hip.
-hipError_t launch_row(int mode, const Item* items, const IO* io, const int2* map, int nblocks,
+hipError_t launch_row(int mode, const Launch& L, bool uniform, int ntile, int chunk, int nblocks,
                       int threads, size_t lds, int n, int flags, hipStream_t st);
-hipError_t launch_col(int mcode, int nin, int nout, const Item* items, const int2* map,
+hipError_t launch_col(int mcode, int nin, int nout, const Launch& L, bool uniform, int ntile, int chunk,
                       int nblocks, int threads, size_t lds, int n, hipStream_t st);
 hipError_t launch_combine(const Item* items, const IO* io, int nitems, int max_count,
                           hipStream_t st);
