@@ -90,6 +90,9 @@ __device__ __forceinline__ int fdiv(int a, int d, float rcp) {
 // writes and the transposed column loads spread over the LDS banks.
 __device__ __forceinline__ int px(int x) { return x + (x >> 3); }
 
+// column index of element ix of spectrum tile column tx
+__device__ __forceinline__ int k_of(int tx, int ix, int lct) { return (tx << lct) + ix; }
+
 // One Stockham stage for butterfly j: reads src[j + r nb], twiddles by
 // W_{Ns R}^{k r} (k = j mod Ns, Ns a power of two), writes dst[(j - k) R + k + r Ns]
 // (positions within a line mapped through px()).
@@ -176,53 +179,63 @@ __device__ __forceinline__ void unpack(const float2* L, int k, int nx, int nxh, 
 
 __device__ __forceinline__ float2* other(float2* r, float2* a, float2* b) { return r == a ? b : a; }
 
-// line j <- rows y0+j of (s0, s1)
-__device__ __forceinline__ void load_pair_lines(float2* buf, const float2* __restrict__ s0,
-                                                const float2* __restrict__ s1, int y0, int nlines,
-                                                int nx, int nxh) {
-  const float rc = 1.0f / static_cast<float>(nxh);
-  for (int it = threadIdx.x; it < nlines * nxh; it += blockDim.x) {
-    const int j = fdiv(it, nxh, rc), k = it - j * nxh;
-    const size_t off = size_t(y0 + j) * nxh + k;
-    build_inv(buf + j * lstride(nx), s0[off], s1[off], k, nx, nxh);
+// Half spectra are stored in tiles of rt rows x ct columns (the row- and
+// column-pass tile sizes): element (ky, kx) sits at
+//   ((ky / rt) (nxh / ct) + kx / ct) rt ct + (ky mod rt) ct + kx mod ct,
+// so the rt rows of one row tile form one contiguous run and a column tile is
+// a sequence of runs of rt*ct elements.  All loops below walk memory order.
+
+// line j <- rows j of the row tile (s0, s1)
+__device__ __forceinline__ void load_pair_lines(float2* buf, const Medium& M, const float2* __restrict__ s0,
+                                                const float2* __restrict__ s1, int tile) {
+  const int nx = M.nx, nxh = M.nxh, LS = lstride(nx), rc = M.rt * M.ct;
+  const size_t base = size_t(tile) * M.rt * nxh;
+  for (int p = threadIdx.x; p < M.rt * nxh; p += blockDim.x) {
+    const int w = p & (rc - 1);
+    const int j = w >> M.lct, k = ((p >> (M.lrt + M.lct)) << M.lct) + (w & (M.ct - 1));
+    build_inv(buf + j * LS, s0[base + p], s1[base + p], k, nx, nxh);
   }
 }
 
-// line l <- rows (y0+2l, y0+2l+1) of s0
-__device__ __forceinline__ void load_rowpair_lines(float2* buf, const float2* __restrict__ s0, int y0,
-                                                   int nlines, int nx, int nxh) {
-  const float rc = 1.0f / static_cast<float>(nxh);
-  for (int it = threadIdx.x; it < nlines * nxh; it += blockDim.x) {
-    const int l = fdiv(it, nxh, rc), k = it - l * nxh;
-    const size_t off = size_t(y0 + 2 * l) * nxh + k;
-    build_inv(buf + l * lstride(nx), s0[off], s0[off + nxh], k, nx, nxh);
+// line l <- rows (2l, 2l+1) of the row tile of s0
+__device__ __forceinline__ void load_rowpair_lines(float2* buf, const Medium& M, const float2* __restrict__ s0,
+                                                   int tile) {
+  const int nx = M.nx, nxh = M.nxh, LS = lstride(nx), hc = (M.rt >> 1) * M.ct;
+  const size_t base = size_t(tile) * M.rt * nxh;
+  for (int q = threadIdx.x; q < (M.rt >> 1) * nxh; q += blockDim.x) {
+    const int tx = q >> (M.lrt - 1 + M.lct), w2 = q & (hc - 1);
+    const int l = w2 >> M.lct, ix = w2 & (M.ct - 1);
+    const size_t off = base + size_t(tx) * M.rt * M.ct + (2 * l) * M.ct + ix;
+    build_inv(buf + l * LS, s0[off], s0[off + M.ct], k_of(tx, ix, M.lct), nx, nxh);
   }
 }
 
-__device__ __forceinline__ void store_pair_spectra(const float2* buf, float2* __restrict__ s0,
-                                                   float2* __restrict__ s1, int y0, int nlines, int nx,
-                                                   int nxh) {
-  const float rc = 1.0f / static_cast<float>(nxh);
-  for (int it = threadIdx.x; it < nlines * nxh; it += blockDim.x) {
-    const int j = fdiv(it, nxh, rc), k = it - j * nxh;
+__device__ __forceinline__ void store_pair_spectra(const float2* buf, const Medium& M, float2* __restrict__ s0,
+                                                   float2* __restrict__ s1, int tile) {
+  const int nx = M.nx, nxh = M.nxh, LS = lstride(nx), rc = M.rt * M.ct;
+  const size_t base = size_t(tile) * M.rt * nxh;
+  for (int p = threadIdx.x; p < M.rt * nxh; p += blockDim.x) {
+    const int w = p & (rc - 1);
+    const int j = w >> M.lct, k = ((p >> (M.lrt + M.lct)) << M.lct) + (w & (M.ct - 1));
     float2 A, B;
-    unpack(buf + j * lstride(nx), k, nx, nxh, A, B);
-    const size_t off = size_t(y0 + j) * nxh + k;
-    s0[off] = A;
-    s1[off] = B;
+    unpack(buf + j * LS, k, nx, nxh, A, B);
+    s0[base + p] = A;
+    s1[base + p] = B;
   }
 }
 
-__device__ __forceinline__ void store_rowpair_spectra(const float2* buf, float2* __restrict__ s0, int y0,
-                                                      int nlines, int nx, int nxh) {
-  const float rc = 1.0f / static_cast<float>(nxh);
-  for (int it = threadIdx.x; it < nlines * nxh; it += blockDim.x) {
-    const int l = fdiv(it, nxh, rc), k = it - l * nxh;
+__device__ __forceinline__ void store_rowpair_spectra(const float2* buf, const Medium& M, float2* __restrict__ s0,
+                                                      int tile) {
+  const int nx = M.nx, nxh = M.nxh, LS = lstride(nx), hc = (M.rt >> 1) * M.ct;
+  const size_t base = size_t(tile) * M.rt * nxh;
+  for (int q = threadIdx.x; q < (M.rt >> 1) * nxh; q += blockDim.x) {
+    const int tx = q >> (M.lrt - 1 + M.lct), w2 = q & (hc - 1);
+    const int l = w2 >> M.lct, ix = w2 & (M.ct - 1);
+    const size_t off = base + size_t(tx) * M.rt * M.ct + (2 * l) * M.ct + ix;
     float2 A, B;
-    unpack(buf + l * lstride(nx), k, nx, nxh, A, B);
-    const size_t off = size_t(y0 + 2 * l) * nxh + k;
+    unpack(buf + l * LS, k_of(tx, ix, M.lct), nx, nxh, A, B);
     s0[off] = A;
-    s0[off + nxh] = B;
+    s0[off + M.ct] = B;
   }
 }
 
@@ -390,7 +403,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     // eq num-vel: v_i = A_i (A_i v_i - dt/rho_i d/dr_i^+ p)
     const bool first = (n == 0);  // v^{-1/2} = 0
     float vxo[kMaxPer], vyo[kMaxPer], bx[kMaxPer], by[kMaxPer], ax[kMaxPer], ay[kMaxPer];
-    load_pair_lines(bufA, W.s0, W.s1, y0, rt, nx, nxh);
+    load_pair_lines(bufA, M, W.s0, W.s1, tile);
     load_tw(tw, M.twx, nx);
     FOR_K {
       const int it = threadIdx.x + k * B;
@@ -423,13 +436,13 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     }
     __syncthreads();
     r = fft_lines(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
-    store_pair_spectra(r, W.s0, W.s1, y0, rt, nx, nxh);
+    store_pair_spectra(r, M, W.s0, W.s1, tile);
   } else if constexpr (MODE == RM_F2 || MODE == RM_F2L) {
     // eq num-rho with the additive source of eq s1 (dt s = p0 / (2 d c^2), d = 2)
     const bool skip = (n == -1);  // v^{-1/2} = 0 and rho^{-1} = 0
     const bool inject = (n <= 0);
     float rxo[kMaxPer], ryo[kMaxPer], r0[kMaxPer], ax[kMaxPer], ay[kMaxPer], src[kMaxPer], c2[kMaxPer];
-    if (!skip) load_pair_lines(bufA, W.s0, W.s1, y0, rt, nx, nxh);
+    if (!skip) load_pair_lines(bufA, M, W.s0, W.s1, tile);
     load_tw(tw, M.twx, nx);
     TapStage T{};
     if constexpr (MODE == RM_F2L) T = stage_taps(M, tap_base, y0, rt, nullptr, 0);
@@ -489,18 +502,18 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     __syncthreads();
     if constexpr (MODE == RM_F2) {
       r = fft_lines(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
-      store_rowpair_spectra(r, W.s0, y0, rt / 2, nx, nxh);
-      store_rowpair_spectra(r + (rt / 2) * LS, W.s1, y0, rt / 2, nx, nxh);
+      store_rowpair_spectra(r, M, W.s0, tile);
+      store_rowpair_spectra(r + (rt / 2) * LS, M, W.s1, tile);
     } else {
       if (!(flags & FL_NO_SENSORS)) sensor_partials(M, T, o, y0, W.part, n + 1);
       r = fft_lines(o, other(o, bufA, bufB), rt / 2, nx, LS, M.radx, M.nstx, tw);
-      store_rowpair_spectra(r, W.s0, y0, rt / 2, nx, nxh);
+      store_rowpair_spectra(r, M, W.s0, tile);
     }
   } else if constexpr (MODE == RM_F3) {
     // eq num-p: p = c^2 (S - eta Y_dis S + tau Y_abs u)
     float rs[kMaxPer], c2[kMaxPer], ce[kMaxPer], ctau[kMaxPer];
-    load_rowpair_lines(bufA, W.s0, y0, rt / 2, nx, nxh);
-    load_rowpair_lines(bufA + (rt / 2) * LS, W.s1, y0, rt / 2, nx, nxh);
+    load_rowpair_lines(bufA, M, W.s0, tile);
+    load_rowpair_lines(bufA + (rt / 2) * LS, M, W.s1, tile);
     load_tw(tw, M.twx, nx);
     const TapStage T = stage_taps(M, tap_base, y0, rt, nullptr, 0);
     FOR_K {
@@ -530,14 +543,14 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     __syncthreads();
     if (!(flags & FL_NO_SENSORS)) sensor_partials(M, T, o, y0, W.part, n + 1);
     r = fft_lines(o, other(o, bufA, bufB), rt / 2, nx, LS, M.radx, M.nstx, tw);
-    store_rowpair_spectra(r, W.s0, y0, rt / 2, nx, nxh);
+    store_rowpair_spectra(r, M, W.s0, tile);
   } else if constexpr (MODE == RM_A1 || MODE == RM_A1L) {
     // transpose of eqs num-m and num-p: p* += M^T r_{n+1}; q = c^2 p*
     const bool first = (n == M.nt - 2);
     const int half = rt / 2;
     float c2[kMaxPer], ce[kMaxPer], ctau[kMaxPer], rbx0[kMaxPer], rby0[kMaxPer], r0[kMaxPer];
     float ax[kMaxPer], ay[kMaxPer], gacc[kMaxPer];
-    if (!first) load_rowpair_lines(bufA, W.s0, y0, half, nx, nxh);
+    if (!first) load_rowpair_lines(bufA, M, W.s0, tile);
     load_tw(tw, M.twx, nx);
     const TapStage T = stage_taps(M, tap_base, y0, rt, X.in, n + 1);
     FOR_K {
@@ -604,19 +617,19 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     __syncthreads();
     if constexpr (MODE == RM_A1) {
       r = fft_lines(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
-      store_rowpair_spectra(r, W.s0, y0, half, nx, nxh);
-      store_rowpair_spectra(r + half * LS, W.s1, y0, half, nx, nxh);
+      store_rowpair_spectra(r, M, W.s0, tile);
+      store_rowpair_spectra(r + half * LS, M, W.s1, tile);
     } else if (n != -1) {
       r = fft_lines(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
-      store_pair_spectra(r, W.s0, W.s1, y0, rt, nx, nxh);
+      store_pair_spectra(r, M, W.s0, W.s1, tile);
     }
   } else if constexpr (MODE == RM_A2) {
     // transpose of the mass update and of the Y terms of eq num-p
     const bool first = (n == M.nt - 2);
     float qv[kMaxPer], rbx0[kMaxPer], rby0[kMaxPer], r0[kMaxPer], ax[kMaxPer], ay[kMaxPer];
     float c2[kMaxPer], gacc[kMaxPer];
-    load_rowpair_lines(bufA, W.s0, y0, rt / 2, nx, nxh);
-    load_rowpair_lines(bufA + (rt / 2) * LS, W.s1, y0, rt / 2, nx, nxh);
+    load_rowpair_lines(bufA, M, W.s0, tile);
+    load_rowpair_lines(bufA + (rt / 2) * LS, M, W.s1, tile);
     load_tw(tw, M.twx, nx);
     FOR_K {
       const int it = threadIdx.x + k * B;
@@ -657,13 +670,13 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     __syncthreads();
     if (n != -1) {
       r = fft_lines(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
-      store_pair_spectra(r, W.s0, W.s1, y0, rt, nx, nxh);
+      store_pair_spectra(r, M, W.s0, W.s1, tile);
     }
   } else if constexpr (MODE == RM_A3) {
     // transpose of eq num-vel
     const bool first = (n == M.nt - 2);
     float vbx0[kMaxPer], vby0[kMaxPer], bx[kMaxPer], by[kMaxPer], ax[kMaxPer], ay[kMaxPer];
-    load_pair_lines(bufA, W.s0, W.s1, y0, rt, nx, nxh);
+    load_pair_lines(bufA, M, W.s0, W.s1, tile);
     load_tw(tw, M.twx, nx);
     FOR_K {
       const int it = threadIdx.x + k * B;
@@ -696,7 +709,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     }
     __syncthreads();
     r = fft_lines(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
-    store_pair_spectra(r, W.s0, W.s1, y0, rt, nx, nxh);
+    store_pair_spectra(r, M, W.s0, W.s1, tile);
   } else if constexpr (MODE == RM_FWD1) {
     const float* src = X.in;
     load_tw(tw, M.twx, nx);
@@ -706,9 +719,9 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     }
     __syncthreads();
     float2* r = fft_lines(bufA, bufB, rt / 2, nx, LS, M.radx, M.nstx, tw);
-    store_rowpair_spectra(r, W.s0, y0, rt / 2, nx, nxh);
+    store_rowpair_spectra(r, M, W.s0, tile);
   } else if constexpr (MODE == RM_INV1) {
-    load_rowpair_lines(bufA, W.s0, y0, rt / 2, nx, nxh);
+    load_rowpair_lines(bufA, M, W.s0, tile);
     load_tw(tw, M.twx, nx);
     __syncthreads();
     float2* r = fft_lines(bufA, bufB, rt / 2, nx, LS, M.radx, M.nstx, tw);
@@ -773,12 +786,15 @@ col_kernel(const Launch L, int ntile, int chunk, int mcode, int nin, int nout, i
   const float2* symx = xcode == MC_DXP ? M.dxp : M.dxm;
   const float2* symy = ycode == MC_DYP ? M.dyp : M.dym;
   // load phase: the tile (transposed into lines), twiddles, multiplier values
-  const float rct = 1.0f / static_cast<float>(ct), rny = 1.0f / static_cast<float>(ny);
+  // memory order: field, tile row ty, element (iy, c) of the rt x ct tile
+  const float rny = 1.0f / static_cast<float>(ny);
+  const int rc = M.rt * ct, ntx = nxh / ct;
   for (int it = threadIdx.x; it < nin * ct * ny; it += B) {
-    const int rest = fdiv(it, ct, rct), c = it - rest * ct;
-    const int f = fdiv(rest, ny, rny), ky = rest - f * ny;
+    const int f = fdiv(it, ny * ct, rny / ct), rem = it - f * ny * ct;
+    const int ty = rem >> (M.lrt + M.lct), w = rem & (rc - 1);
+    const int ky = (ty << M.lrt) + (w >> M.lct), c = w & (ct - 1);
     const float2* s = f ? W.s1 : W.s0;
-    bufA[(f * ct + c) * ls + px(ky)] = s[size_t(ky) * nxh + c0 + c];
+    bufA[(f * ct + c) * ls + px(ky)] = s[(size_t(ty) * ntx + tile) * rc + w];
   }
   load_tw(tw, M.twy, ny);
   const int tot = ct * ny;
@@ -862,10 +878,11 @@ col_kernel(const Launch L, int ntile, int chunk, int mcode, int nin, int nout, i
   __syncthreads();
   r = fft_lines(o, other(o, bufA, bufB), nout * ct, ny, ls, M.rady, M.nsty, tw);
   for (int it = threadIdx.x; it < nout * ct * ny; it += B) {
-    const int rest = fdiv(it, ct, rct), c = it - rest * ct;
-    const int f = fdiv(rest, ny, rny), ky = rest - f * ny;
+    const int f = fdiv(it, ny * ct, rny / ct), rem = it - f * ny * ct;
+    const int ty = rem >> (M.lrt + M.lct), w = rem & (rc - 1);
+    const int ky = (ty << M.lrt) + (w >> M.lct), c = w & (ct - 1);
     float2* s = f ? W.s1 : W.s0;
-    s[size_t(ky) * nxh + c0 + c] = cconj(r[(f * ct + c) * ls + px(ky)]);
+    s[(size_t(ty) * ntx + tile) * rc + w] = cconj(r[(f * ct + c) * ls + px(ky)]);
   }
 }
 

@@ -96,6 +96,12 @@ int pow2_floor(int v) {
 }
 int pow2_divisor(int v) { return v & (-v); }
 
+int ilog2(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+
 bool threads_ok(int t) { return t == 64 || t == 128 || t == 256; }
 
 // A row tile of rt rows (rt even, dividing ny) fits the LDS limit and leaves
@@ -659,6 +665,8 @@ qpat_status plan_build(qpat_plan P, const double* c0, const double* rho0) {
   M.ct = P->ct;
   M.rthr = P->rthr;
   M.cthr = P->cthr;
+  M.lrt = ilog2(P->rt);
+  M.lct = ilog2(P->ct);
   return QPAT_OK;
 }
 
@@ -819,6 +827,8 @@ qpat_status set_tiles(qpat_plan P, int rt, int ct, int rthr, int cthr) {
   if (rt != P->rt || ct != P->ct || rthr != P->rthr || cthr != P->cthr) {
     P->rt = P->med.rt = rt;
     P->ct = P->med.ct = ct;
+    P->med.lrt = ilog2(rt);
+    P->med.lct = ilog2(ct);
     P->rthr = P->med.rthr = rthr;
     P->cthr = P->med.cthr = cthr;
     HIPCHK(hipDeviceSynchronize());

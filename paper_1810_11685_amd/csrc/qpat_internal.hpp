@@ -28,6 +28,7 @@ struct Medium {
   int nx, ny, nxh, nt, ns, lossy;
   float dt;
   int rt, ct;             // rows per row-pass tile, spectrum columns per column-pass tile
+  int lrt, lct;           // log2(rt), log2(ct); spectra are stored in rt x ct tiles
   int rthr, cthr;         // threads per block of the row / column passes
   uint32_t radx, rady;    // radix plans (max radix 8), 4 bits per stage, first stage lowest
   int nstx, nsty;
@@ -45,7 +46,7 @@ struct Medium {
 struct Work {
   float *f0, *f1, *f2, *f3;   // forward: v_x v_y rho_x rho_y;  adjoint: their adjoints
   float* q;                   // forward: p snapshot (checkpoints); adjoint: q = c^2 p*
-  float2 *s0, *s1;            // half spectra [ny][nx/2] (DC / Nyquist packed in column 0)
+  float2 *s0, *s1;            // half spectra, ny x nx/2 in rt x ct tiles (DC / Nyquist packed in column 0)
   float* part;                // forward sensor partials [nt][ns][2]
 };
 
