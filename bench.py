@@ -75,6 +75,8 @@ def pmc_traffic(pass_name: str):
         return None
     if rec.get("kernel_hash") != kernel_hash():
         return None
+    if pass_name in ("fwd_col_fraclap", "adj_col_fraclap"):
+        pass_name = "col_fraclap"      # one kernel serves both
     k = rec.get("per_pass", {}).get(pass_name)
     return None if k is None else k.get("bytes_per_launch")
 

@@ -756,9 +756,22 @@ __device__ __forceinline__ float2 mult_of(int code, const MultPre& P, bool nyq) 
   }
 }
 
-template <bool U>
+// Column-pass kinds: multiplier codes (out_o = sum_i M[o][i] in_i), inputs, outputs.
+__device__ constexpr int kColCode[kColModes] = {
+    mpack(MC_DXP, 0, MC_DYP, 0),    // CM_GRADP1: d/dx^+ p, d/dy^+ p
+    mpack(MC_DXM, 0, 0, MC_DYM),    // CM_GRADM2: d/dx^- v_x, d/dy^- v_y
+    mpack(MC_LDIS, 0, 0, MC_LABS),  // CM_FRAC:   Y_dis S, Y_abs u
+    mpack(MC_DXP, 0, 0, MC_DYP),    // CM_GRADP2: d/dx^+ e_x, d/dy^+ e_y
+    mpack(MC_DXM, MC_DYM, 0, 0),    // CM_DIVM:   d/dx^- g_x + d/dy^- g_y
+    0};                             // CM_APPLY:  one operator given at launch
+__device__ constexpr int kColIn[kColModes] = {1, 2, 2, 2, 2, 1};
+__device__ constexpr int kColOut[kColModes] = {2, 2, 2, 2, 1, 1};
+
+template <bool U, int CM>
 __global__ void __launch_bounds__(kBlock)
-col_kernel(const Launch L, int ntile, int chunk, int mcode, int nin, int nout, int n) {
+col_kernel(const Launch L, int ntile, int chunk, int mcode_arg, int n) {
+  constexpr int nin = kColIn[CM], nout = kColOut[CM];
+  const int mcode = CM == CM_APPLY ? mcode_arg : kColCode[CM];
   extern __shared__ float2 lds[];
   int item, tile;
   if (!locate<U>(L, ntile, chunk, item, tile)) return;
@@ -966,15 +979,28 @@ hipError_t launch_row(int mode, const Launch& L, bool uniform, int ntile, int ch
 #undef QPAT_ROW_CASE
 }
 
-hipError_t launch_col(int mcode, int nin, int nout, const Launch& L, bool uniform, int ntile, int chunk,
-                      int nblocks, int threads, size_t lds, int n, hipStream_t st) {
+template <int CM>
+static hipError_t launch_col_t(int mcode, const Launch& L, bool uniform, int ntile, int chunk, int nblocks,
+                               int threads, size_t lds, int n, hipStream_t st) {
   if (uniform)
-    hipLaunchKernelGGL((col_kernel<true>), dim3(nblocks), dim3(threads), lds, st, L, ntile, chunk, mcode, nin,
-                       nout, n);
+    hipLaunchKernelGGL((col_kernel<true, CM>), dim3(nblocks), dim3(threads), lds, st, L, ntile, chunk, mcode, n);
   else
-    hipLaunchKernelGGL((col_kernel<false>), dim3(nblocks), dim3(threads), lds, st, L, ntile, chunk, mcode, nin,
-                       nout, n);
+    hipLaunchKernelGGL((col_kernel<false, CM>), dim3(nblocks), dim3(threads), lds, st, L, ntile, chunk, mcode,
+                       n);
   return hipGetLastError();
+}
+
+hipError_t launch_col(int cm, int mcode, const Launch& L, bool uniform, int ntile, int chunk, int nblocks,
+                      int threads, size_t lds, int n, hipStream_t st) {
+  switch (cm) {
+    case CM_GRADP1: return launch_col_t<CM_GRADP1>(mcode, L, uniform, ntile, chunk, nblocks, threads, lds, n, st);
+    case CM_GRADM2: return launch_col_t<CM_GRADM2>(mcode, L, uniform, ntile, chunk, nblocks, threads, lds, n, st);
+    case CM_FRAC: return launch_col_t<CM_FRAC>(mcode, L, uniform, ntile, chunk, nblocks, threads, lds, n, st);
+    case CM_GRADP2: return launch_col_t<CM_GRADP2>(mcode, L, uniform, ntile, chunk, nblocks, threads, lds, n, st);
+    case CM_DIVM: return launch_col_t<CM_DIVM>(mcode, L, uniform, ntile, chunk, nblocks, threads, lds, n, st);
+    case CM_APPLY: return launch_col_t<CM_APPLY>(mcode, L, uniform, ntile, chunk, nblocks, threads, lds, n, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_combine(const Item* items, const IO* io, int nitems, int max_count, hipStream_t st) {

@@ -293,13 +293,13 @@ hipError_t row(Exec& E, int mode, int n, int flags, hipStream_t st) {
   L.map = E.d_rowmap;
   return launch_row(mode, L, false, 0, 0, E.nrow, E.rthr, E.row_lds, n, flags, st);
 }
-hipError_t col(Exec& E, int mcode, int nin, int nout, int n, hipStream_t st) {
+hipError_t col(Exec& E, int cm, int n, hipStream_t st, int mcode = 0) {
   if (E.uniform)
-    return launch_col(mcode, nin, nout, E.L, true, E.col_ntile, E.col_chunk, E.col_chunk * kXcds, E.cthr,
-                      E.col_lds, n, st);
+    return launch_col(cm, mcode, E.L, true, E.col_ntile, E.col_chunk, E.col_chunk * kXcds, E.cthr, E.col_lds, n,
+                      st);
   Launch L = E.L;
   L.map = E.d_colmap;
-  return launch_col(mcode, nin, nout, L, false, 0, 0, E.ncol, E.cthr, E.col_lds, n, st);
+  return launch_col(cm, mcode, L, false, 0, 0, E.ncol, E.cthr, E.col_lds, n, st);
 }
 
 #define LCHK(expr)                           \
@@ -311,13 +311,13 @@ hipError_t col(Exec& E, int mcode, int nin, int nout, int n, hipStream_t st) {
 // One forward iterate n (eqs num-vel, num-rho, num-p, num-m).
 hipError_t fwd_iterate(Exec& E, int n, int flags, hipStream_t st) {
   if (n > -1) {
-    LCHK(col(E, mpack(MC_DXP, 0, MC_DYP, 0), 1, 2, n, st));
+    LCHK(col(E, CM_GRADP1, n, st));
     LCHK(row(E, RM_F1, n, 0, st));
-    LCHK(col(E, mpack(MC_DXM, 0, 0, MC_DYM), 2, 2, n, st));
+    LCHK(col(E, CM_GRADM2, n, st));
   }
   if (E.lossy) {
     LCHK(row(E, RM_F2, n, 0, st));
-    LCHK(col(E, mpack(MC_LDIS, 0, 0, MC_LABS), 2, 2, n, st));
+    LCHK(col(E, CM_FRAC, n, st));
     LCHK(row(E, RM_F3, n, flags, st));
   } else {
     LCHK(row(E, RM_F2L, n, flags, st));
@@ -336,15 +336,15 @@ hipError_t seq_adjoint(Exec& E, hipStream_t st) {
   for (int n = E.max_nt - 2; n >= -1; --n) {
     if (E.lossy) {
       LCHK(row(E, RM_A1, n, 0, st));
-      LCHK(col(E, mpack(MC_LDIS, 0, 0, MC_LABS), 2, 2, n, st));
+      LCHK(col(E, CM_FRAC, n, st));
       LCHK(row(E, RM_A2, n, 0, st));
     } else {
       LCHK(row(E, RM_A1L, n, 0, st));
     }
     if (n == -1) break;
-    LCHK(col(E, mpack(MC_DXP, 0, 0, MC_DYP), 2, 2, n, st));
+    LCHK(col(E, CM_GRADP2, n, st));
     LCHK(row(E, RM_A3, n, 0, st));
-    LCHK(col(E, mpack(MC_DXM, MC_DYM, 0, 0), 2, 1, n, st));
+    LCHK(col(E, CM_DIVM, n, st));
   }
   return hipSuccess;
 }
@@ -947,7 +947,7 @@ qpat_status qpat_apply(qpat_plan P, int32_t op, const float* in, float* out, int
   }
   STCHK(exec_set_io(*E, io, st));
   hipError_t e = row(*E, RM_FWD1, -1, 0, st);
-  if (e == hipSuccess) e = col(*E, mpack(codes[op], 0, 0, 0), 1, 1, -1, st);
+  if (e == hipSuccess) e = col(*E, CM_APPLY, -1, st, mpack(codes[op], 0, 0, 0));
   if (e == hipSuccess) e = row(*E, RM_INV1, -1, 0, st);
   if (e != hipSuccess) return fail(QPAT_E_HIP, std::string("apply: ") + hipGetErrorString(e));
   return QPAT_OK;
@@ -1096,18 +1096,18 @@ qpat_status qpat_tune(qpat_plan P, int32_t batch, qpat_stream stream) {
 // One pass kind of the forward (0-5) or adjoint (6-11) iterate, see qpat.h.
 static hipError_t launch_pass(Exec& E, int pass, int n, hipStream_t st) {
   switch (pass) {
-    case 0: return col(E, mpack(MC_DXP, 0, MC_DYP, 0), 1, 2, n, st);
+    case 0: return col(E, CM_GRADP1, n, st);
     case 1: return row(E, RM_F1, n, 0, st);
-    case 2: return col(E, mpack(MC_DXM, 0, 0, MC_DYM), 2, 2, n, st);
+    case 2: return col(E, CM_GRADM2, n, st);
     case 3: return row(E, E.lossy ? RM_F2 : RM_F2L, n, 0, st);
-    case 4: return col(E, mpack(MC_LDIS, 0, 0, MC_LABS), 2, 2, n, st);
+    case 4: return col(E, CM_FRAC, n, st);
     case 5: return row(E, RM_F3, n, 0, st);
     case 6: return row(E, E.lossy ? RM_A1 : RM_A1L, n, 0, st);
-    case 7: return col(E, mpack(MC_LDIS, 0, 0, MC_LABS), 2, 2, n, st);
+    case 7: return col(E, CM_FRAC, n, st);
     case 8: return row(E, RM_A2, n, 0, st);
-    case 9: return col(E, mpack(MC_DXP, 0, 0, MC_DYP), 2, 2, n, st);
+    case 9: return col(E, CM_GRADP2, n, st);
     case 10: return row(E, RM_A3, n, 0, st);
-    case 11: return col(E, mpack(MC_DXM, MC_DYM, 0, 0), 2, 1, n, st);
+    case 11: return col(E, CM_DIVM, n, st);
     default: return hipErrorInvalidValue;
   }
 }

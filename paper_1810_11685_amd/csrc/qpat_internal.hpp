@@ -82,6 +82,10 @@ constexpr int mpack(int m00, int m01, int m10, int m11) {
   return m00 | (m01 << 4) | (m10 << 8) | (m11 << 12);
 }
 
+// Column-pass kinds (see kColCode in the kernels).
+enum ColMode : int { CM_GRADP1 = 0, CM_GRADM2 = 1, CM_FRAC = 2, CM_GRADP2 = 3, CM_DIVM = 4, CM_APPLY = 5 };
+constexpr int kColModes = 6;
+
 // Row-pass kernels.
 enum RowMode : int {
   RM_F1 = 0,   // forward: grad p -> v update -> spectra of (v_x, v_y)
@@ -105,8 +109,8 @@ enum Flags : int {
 // Launch helpers implemented in kernels.hip.
 hipError_t launch_row(int mode, const Launch& L, bool uniform, int ntile, int chunk, int nblocks,
                       int threads, size_t lds, int n, int flags, hipStream_t st);
-hipError_t launch_col(int mcode, int nin, int nout, const Launch& L, bool uniform, int ntile, int chunk,
-                      int nblocks, int threads, size_t lds, int n, hipStream_t st);
+hipError_t launch_col(int cm, int mcode, const Launch& L, bool uniform, int ntile, int chunk, int nblocks,
+                      int threads, size_t lds, int n, hipStream_t st);
 hipError_t launch_combine(const Item* items, const IO* io, int nitems, int max_count,
                           hipStream_t st);
 hipError_t launch_dot(const float* a, const float* b, int64_t n, double* partial, int nblk,

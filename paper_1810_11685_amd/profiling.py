@@ -1,0 +1,151 @@
+"""Profiling helpers: a calibration copy kernel for rocprofv3 byte counters and
+summaries of rocprofv3 CSV output.
+
+    python -m paper_1810_11685_amd.profiling copy --mib 256
+        runs a plain device-to-device copy of the given size (the reference
+        for scaling FETCH_SIZE / WRITE_SIZE to bytes).
+    python -m paper_1810_11685_amd.profiling stats <kernel_stats.csv>
+        prints a short per-kernel table from a --stats CSV.
+    python -m paper_1810_11685_amd.profiling pmc <dir_fetch> <dir_write> <dir_cfetch> <dir_cwrite> \
+            --copy-mib 256 --out profiles/pmc_traffic.json
+        combines two counter runs of the benchmark with two of the copy kernel
+        into per-pass HBM traffic per launch.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+# kernel-name fragments of the pass kinds (row kernels by mode, template arg U)
+ROW_MODES = {0: "fwd_row_velocity", 1: "fwd_row_density", 2: "fwd_row_density", 3: "fwd_row_pressure",
+             4: "adj_row_pressure", 5: "adj_row_pressure", 6: "adj_row_density", 7: "adj_row_velocity"}
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "qpat_internal.hpp"):
+        with open(os.path.join(HERE, "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def copy_kernel(mib: int, reps: int = 5) -> None:
+    import torch
+    n = mib * 1024 * 1024 // 4
+    a = torch.ones(n, device="cuda", dtype=torch.float32)
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(f"copied {mib} MiB x {reps}", flush=True)
+
+
+COL_MODES = {0: "fwd_col_grad_p", 1: "fwd_col_div_v", 2: "col_fraclap", 3: "adj_col_grad", 4: "adj_col_div",
+             5: "col_apply"}
+
+
+def pass_of(name: str):
+    """Pass-kind name of a row / column kernel dispatch (the Y_dis/Y_abs column
+    kernel serves the forward and the adjoint pass alike: 'col_fraclap')."""
+    if "col_kernel<" in name:
+        mode = int(name.split("col_kernel<")[1].split(",")[1].split(">")[0])
+        return COL_MODES.get(mode, f"col_mode_{mode}")
+    if "row_kernel<" in name:
+        mode = int(name.split("row_kernel<")[1].split(",")[0].split(">")[0])
+        return ROW_MODES.get(mode, f"row_mode_{mode}")
+    return None
+
+
+def read_counters(d: str, counter: str):
+    """{kernel name: [values per dispatch]} from a rocprofv3 --pmc CSV directory."""
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    out = {}
+    for f in files:
+        for r in csv.DictReader(open(f)):
+            if r.get("Counter_Name") != counter:
+                continue
+            out.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+    return out
+
+
+def stats_table(path: str) -> str:
+    rows = list(csv.DictReader(open(path)))
+    lines = [f"{'calls':>7} {'avg_us':>9} {'min_us':>9} {'max_us':>9} {'total_ms':>9} {'pct':>6}  kernel"]
+    for r in rows:
+        lines.append(f"{int(r['Calls']):7d} {float(r['AverageNs']) / 1e3:9.2f} {float(r['MinNs']) / 1e3:9.2f} "
+                     f"{float(r['MaxNs']) / 1e3:9.2f} {float(r['TotalDurationNs']) / 1e6:9.2f} "
+                     f"{float(r['Percentage']):6.1f}  {r['Name'][:110]}")
+    return "\n".join(lines)
+
+
+def pmc_summary(dfetch, dwrite, dcf, dcw, copy_mib, out):
+    fetch, write = read_counters(dfetch, "FETCH_SIZE"), read_counters(dwrite, "WRITE_SIZE")
+    cf, cw = read_counters(dcf, "FETCH_SIZE"), read_counters(dcw, "WRITE_SIZE")
+
+    def copy_val(d):
+        best = None
+        for k, v in d.items():
+            if "copy" in k.lower() or "elementwise" in k.lower() or "Copy" in k:
+                m = max(v)
+                best = m if best is None else max(best, m)
+        return best
+
+    expected_kib = copy_mib * 1024.0
+    sf = expected_kib / copy_val(cf) if copy_val(cf) else None
+    sw = expected_kib / copy_val(cw) if copy_val(cw) else None
+    per = {}
+    for name in set(fetch) | set(write):
+        p = pass_of(name)
+        if p is None:
+            continue
+        f = fetch.get(name, [])
+        w = write.get(name, [])
+        fk = sum(f) / len(f) if f else None
+        wk = sum(w) / len(w) if w else None
+        e = per.setdefault(p, {"kernels": []})
+        e["kernels"].append(name[:80])
+        e["fetch_KiB_per_launch"] = fk
+        e["write_KiB_per_launch"] = wk
+        if fk is not None and wk is not None and sf and sw:
+            e["bytes_per_launch"] = (fk * sf + wk * sw) * 1024.0
+    rec = {"kernel_hash": kernel_hash(), "copy_MiB": copy_mib, "scale_fetch": sf, "scale_write": sw,
+           "note": "HBM-side bytes per launch = FETCH_SIZE*scale_fetch + WRITE_SIZE*scale_write (KiB -> B); "
+                   "scales make a plain copy of known size read and write exactly its size",
+           "per_pass": per}
+    with open(out, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec, indent=1))
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    c = sub.add_parser("copy")
+    c.add_argument("--mib", type=int, default=256)
+    s = sub.add_parser("stats")
+    s.add_argument("csv")
+    p = sub.add_parser("pmc")
+    p.add_argument("fetch")
+    p.add_argument("write")
+    p.add_argument("copy_fetch")
+    p.add_argument("copy_write")
+    p.add_argument("--copy-mib", type=int, default=256)
+    p.add_argument("--out", required=True)
+    a = ap.parse_args(argv)
+    if a.cmd == "copy":
+        copy_kernel(a.mib)
+    elif a.cmd == "stats":
+        print(stats_table(a.csv))
+    else:
+        pmc_summary(a.fetch, a.write, a.copy_fetch, a.copy_write, a.copy_mib, a.out)
+
+
+if __name__ == "__main__":
+    sys.exit(main())
