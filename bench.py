@@ -67,7 +67,7 @@ def kernel_hash() -> str:
 def pmc_traffic(pass_name: str):
     """HBM traffic per launch from the committed rocprofv3 counter summary, if it
     was taken with the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    path = os.path.join(ROOT, "profiles", "fwdadj512_pmc_traffic.json")
     try:
         with open(path) as f:
             rec = json.load(f)
