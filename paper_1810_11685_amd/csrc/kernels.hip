@@ -86,22 +86,18 @@ __device__ __forceinline__ int fdiv(int a, int d, float rcp) {
   return q;
 }
 
-// LDS lines are padded by one element per 8 so that the strided Stockham
-// writes and the transposed column loads spread over the LDS banks.
-__device__ __forceinline__ int px(int x) { return x + (x >> 3); }
-
 // column index of element ix of spectrum tile column tx
 __device__ __forceinline__ int k_of(int tx, int ix, int lct) { return (tx << lct) + ix; }
 
 // One Stockham stage for butterfly j: reads src[j + r nb], twiddles by
 // W_{Ns R}^{k r} (k = j mod Ns, Ns a power of two), writes dst[(j - k) R + k + r Ns]
-// (positions within a line mapped through px()).
+// (positions within a line mapped through ).
 template <int R>
 __device__ __forceinline__ void stockham(const float2* src, float2* dst, int j, int nb, int Ns,
                                          int tws, const float2* tw) {
   float2 v[R];
 #pragma unroll
-  for (int r = 0; r < R; ++r) v[r] = src[px(j + r * nb)];
+  for (int r = 0; r < R; ++r) v[r] = src[j + r * nb];
   const int k = j & (Ns - 1);
   if (Ns > 1) {
 #pragma unroll
@@ -110,7 +106,7 @@ __device__ __forceinline__ void stockham(const float2* src, float2* dst, int j, 
   bfly<R>(v);
   const int base = (j - k) * R + k;
 #pragma unroll
-  for (int r = 0; r < R; ++r) dst[px(base + r * Ns)] = v[r];
+  for (int r = 0; r < R; ++r) dst[base + r * Ns] = v[r];
 }
 
 // Forward FFT of `nlines` lines of length n (line stride ls) held in LDS
@@ -151,27 +147,100 @@ __device__ float2* fft_lines(float2* a, float2* b, int nlines, int n, int ls, ui
   return a;
 }
 
+// Compile-time versions of the same radix plans ([2|4] 8 ... 8 [3]) for the
+// common line lengths: every stage's radix, stride and twiddle step is a
+// constant, so index arithmetic folds into shifts and LDS immediate offsets.
+__host__ __device__ constexpr int ilog2c(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+__host__ __device__ constexpr int plan_nst(int n) {
+  const bool three = n % 3 == 0;
+  const int a = ilog2c(three ? n / 3 : n);
+  return (a % 3 ? 1 : 0) + a / 3 + (three ? 1 : 0);
+}
+__host__ __device__ constexpr int plan_radix(int n, int s) {
+  const bool three = n % 3 == 0;
+  const int a = ilog2c(three ? n / 3 : n);
+  const int rem = a % 3, q = a / 3;
+  int idx = 0;
+  if (rem) {
+    if (s == 0) return rem == 1 ? 2 : 4;
+    idx = 1;
+  }
+  return s < idx + q ? 8 : 3;
+}
+
+template <int R, int NS, int NB, int TWS>
+__device__ __forceinline__ void stockham_c(const float2* src, float2* dst, int j, const float2* tw) {
+  float2 v[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) v[r] = src[j + r * NB];
+  const int k = j & (NS - 1);
+  if constexpr (NS > 1) {
+    const float2* t = tw + k * TWS;
+#pragma unroll
+    for (int r = 1; r < R; ++r) v[r] = cmul(v[r], t[(r - 1) * k * TWS]);
+  }
+  bfly<R>(v);
+  float2* d = dst + (j - k) * R + k;
+#pragma unroll
+  for (int r = 0; r < R; ++r) d[r * NS] = v[r];
+}
+
+template <int N, int S, int NS>
+__device__ __forceinline__ float2* fft_c(float2* a, float2* b, int nlines, int ls, const float2* tw) {
+  if constexpr (S == plan_nst(N)) {
+    return a;
+  } else {
+    constexpr int R = plan_radix(N, S), NB = N / R, TWS = N / (NS * R);
+    const int total = nlines * NB;
+    for (int it = threadIdx.x; it < total; it += blockDim.x) {
+      const int line = it / NB;
+      const int j = it - line * NB;
+      stockham_c<R, NS, NB, TWS>(a + line * ls, b + line * ls, j, tw);
+    }
+    __syncthreads();
+    return fft_c<N, S + 1, NS * R>(b, a, nlines, ls, tw);
+  }
+}
+
+// FFT of `nlines` lines: compile-time plan for the common lengths, the
+// runtime plan otherwise.  Same contract as fft_lines.
+__device__ __forceinline__ float2* fft_any(float2* a, float2* b, int nlines, int n, int ls, uint32_t rad,
+                                           int nst, const float2* tw) {
+  switch (n) {
+    case 128: return fft_c<128, 0, 1>(a, b, nlines, ls, tw);
+    case 256: return fft_c<256, 0, 1>(a, b, nlines, ls, tw);
+    case 384: return fft_c<384, 0, 1>(a, b, nlines, ls, tw);
+    case 512: return fft_c<512, 0, 1>(a, b, nlines, ls, tw);
+    case 1024: return fft_c<1024, 0, 1>(a, b, nlines, ls, tw);
+    default: return fft_lines(a, b, nlines, n, ls, rad, nst, tw);
+  }
+}
+
 // ---------------------------------------------------------------- packing
 // Conjugated inverse-FFT input of the pair (A, B) of packed half-spectrum
 // rows: Z = A + iB with Hermitian completion; writes Z[k] and Z[n-k].
 __device__ __forceinline__ void build_inv(float2* L, float2 A, float2 B, int k, int nx, int nxh) {
   if (k == 0) {
     L[0] = make_float2(A.x, -B.x);
-    L[px(nxh)] = make_float2(A.y, -B.y);
+    L[nxh] = make_float2(A.y, -B.y);
   } else {
-    L[px(k)] = make_float2(A.x - B.y, -(A.y + B.x));
-    L[px(nx - k)] = make_float2(A.x + B.y, -(B.x - A.y));
+    L[k] = make_float2(A.x - B.y, -(A.y + B.x));
+    L[nx - k] = make_float2(A.x + B.y, -(B.x - A.y));
   }
 }
 
 // Split the FFT Z of a + i b into the packed half spectra A (of a), B (of b).
 __device__ __forceinline__ void unpack(const float2* L, int k, int nx, int nxh, float2& A, float2& B) {
   if (k == 0) {
-    const float2 z0 = L[0], zn = L[px(nxh)];
+    const float2 z0 = L[0], zn = L[nxh];
     A = make_float2(z0.x, zn.x);
     B = make_float2(z0.y, zn.y);
   } else {
-    const float2 zk = L[px(k)], zm = L[px(nx - k)];
+    const float2 zk = L[k], zm = L[nx - k];
     A = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
     B = make_float2(0.5f * (zk.y + zm.y), 0.5f * (zm.x - zk.x));
   }
@@ -241,13 +310,13 @@ __device__ __forceinline__ void store_rowpair_spectra(const float2* buf, const M
 
 // Row-pair LDS layout: row y0+j lives in component (j & 1) of line j >> 1.
 __device__ __forceinline__ float& pcomp(float2* buf, int j, int x, int nx) {
-  float2* e = buf + (j >> 1) * lstride(nx) + px(x);
+  float2* e = buf + (j >> 1) * lstride(nx) + x;
   return (j & 1) ? e->y : e->x;
 }
 
 // Value of row y0+j after an inverse FFT of row-pair lines (conj trick undone).
 __device__ __forceinline__ float rowpair_val(const float2* buf, int j, int x, int nx) {
-  const float2 e = buf[(j >> 1) * lstride(nx) + px(x)];
+  const float2 e = buf[(j >> 1) * lstride(nx) + x];
   return (j & 1) ? -e.y : e.x;
 }
 
@@ -419,23 +488,23 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
       }
     }
     __syncthreads();
-    float2* r = fft_lines(bufA, bufB, rt, nx, LS, M.radx, M.nstx, tw);
+    float2* r = fft_any(bufA, bufB, rt, nx, LS, M.radx, M.nstx, tw);
     float2* o = other(r, bufA, bufB);
     FOR_K {
       const int it = threadIdx.x + k * B;
       if (it < tot) {
         const int j = fdiv(it, nx, rnx), x = it - j * nx;
         const size_t idx = size_t(y0 + j) * nx + x;
-        const float2 z = r[j * LS + px(x)];
+        const float2 z = r[j * LS + x];
         const float vx = ax[k] * (ax[k] * vxo[k] - bx[k] * z.x);
         const float vy = ay[k] * (ay[k] * vyo[k] + by[k] * z.y);
         W.f0[idx] = vx;
         W.f1[idx] = vy;
-        o[j * LS + px(x)] = make_float2(vx, vy);
+        o[j * LS + x] = make_float2(vx, vy);
       }
     }
     __syncthreads();
-    r = fft_lines(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
+    r = fft_any(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
     store_pair_spectra(r, M, W.s0, W.s1, tile);
   } else if constexpr (MODE == RM_F2 || MODE == RM_F2L) {
     // eq num-rho with the additive source of eq s1 (dt s = p0 / (2 d c^2), d = 2)
@@ -464,7 +533,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     float2* r = nullptr;
     float2* o = bufA;
     if (!skip) {
-      r = fft_lines(bufA, bufB, rt, nx, LS, M.radx, M.nstx, tw);
+      r = fft_any(bufA, bufB, rt, nx, LS, M.radx, M.nstx, tw);
       o = other(r, bufA, bufB);
     }
     FOR_K {
@@ -474,7 +543,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
         const size_t idx = size_t(y0 + j) * nx + x;
         float ex = 0.f, ey = 0.f;
         if (!skip) {
-          const float2 z = r[j * LS + px(x)];
+          const float2 z = r[j * LS + x];
           ex = z.x;
           ey = -z.y;
         } else {
@@ -501,12 +570,12 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     }
     __syncthreads();
     if constexpr (MODE == RM_F2) {
-      r = fft_lines(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
+      r = fft_any(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
       store_rowpair_spectra(r, M, W.s0, tile);
       store_rowpair_spectra(r + (rt / 2) * LS, M, W.s1, tile);
     } else {
       if (!(flags & FL_NO_SENSORS)) sensor_partials(M, T, o, y0, W.part, n + 1);
-      r = fft_lines(o, other(o, bufA, bufB), rt / 2, nx, LS, M.radx, M.nstx, tw);
+      r = fft_any(o, other(o, bufA, bufB), rt / 2, nx, LS, M.radx, M.nstx, tw);
       store_rowpair_spectra(r, M, W.s0, tile);
     }
   } else if constexpr (MODE == RM_F3) {
@@ -528,7 +597,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
       }
     }
     __syncthreads();
-    float2* r = fft_lines(bufA, bufB, rt, nx, LS, M.radx, M.nstx, tw);
+    float2* r = fft_any(bufA, bufB, rt, nx, LS, M.radx, M.nstx, tw);
     float2* o = other(r, bufA, bufB);
     FOR_K {
       const int it = threadIdx.x + k * B;
@@ -542,7 +611,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     }
     __syncthreads();
     if (!(flags & FL_NO_SENSORS)) sensor_partials(M, T, o, y0, W.part, n + 1);
-    r = fft_lines(o, other(o, bufA, bufB), rt / 2, nx, LS, M.radx, M.nstx, tw);
+    r = fft_any(o, other(o, bufA, bufB), rt / 2, nx, LS, M.radx, M.nstx, tw);
     store_rowpair_spectra(r, M, W.s0, tile);
   } else if constexpr (MODE == RM_A1 || MODE == RM_A1L) {
     // transpose of eqs num-m and num-p: p* += M^T r_{n+1}; q = c^2 p*
@@ -575,7 +644,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     __syncthreads();
     float2* r = bufA;
     if (!first) {
-      r = fft_lines(bufA, bufB, half, nx, LS, M.radx, M.nstx, tw);
+      r = fft_any(bufA, bufB, half, nx, LS, M.radx, M.nstx, tw);
       // p* = -(grad_x^- g_x + grad_y^- g_y): negate the (conjugated) inverse
       for (int it = threadIdx.x; it < half * LS; it += B) {
         const float2 z = r[it];
@@ -607,7 +676,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
           if (n == -1) {
             X.out[idx] = (rbx + rby + gacc[k]) * (0.25f / c2[k]);
           } else {
-            o[j * LS + px(x)] = make_float2(-dt * r0[k] * ax[k] * rbx, -dt * r0[k] * ay[k] * rby);
+            o[j * LS + x] = make_float2(-dt * r0[k] * ax[k] * rbx, -dt * r0[k] * ay[k] * rby);
             W.f2[idx] = ax[k] * ax[k] * rbx;
             W.f3[idx] = ay[k] * ay[k] * rby;
           }
@@ -616,11 +685,11 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     }
     __syncthreads();
     if constexpr (MODE == RM_A1) {
-      r = fft_lines(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
+      r = fft_any(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
       store_rowpair_spectra(r, M, W.s0, tile);
       store_rowpair_spectra(r + half * LS, M, W.s1, tile);
     } else if (n != -1) {
-      r = fft_lines(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
+      r = fft_any(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
       store_pair_spectra(r, M, W.s0, W.s1, tile);
     }
   } else if constexpr (MODE == RM_A2) {
@@ -647,7 +716,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
       }
     }
     __syncthreads();
-    float2* r = fft_lines(bufA, bufB, rt, nx, LS, M.radx, M.nstx, tw);
+    float2* r = fft_any(bufA, bufB, rt, nx, LS, M.radx, M.nstx, tw);
     float2* o = other(r, bufA, bufB);
     FOR_K {
       const int it = threadIdx.x + k * B;
@@ -661,7 +730,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
         if (n == -1) {
           X.out[idx] = (rbx + rby + gacc[k]) * (0.25f / c2[k]);
         } else {
-          o[j * LS + px(x)] = make_float2(r0[k] * ax[k] * (ya - dt * rbx), r0[k] * ay[k] * (ya - dt * rby));
+          o[j * LS + x] = make_float2(r0[k] * ax[k] * (ya - dt * rbx), r0[k] * ay[k] * (ya - dt * rby));
           W.f2[idx] = ax[k] * ax[k] * rbx;
           W.f3[idx] = ay[k] * ay[k] * rby;
         }
@@ -669,7 +738,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     }
     __syncthreads();
     if (n != -1) {
-      r = fft_lines(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
+      r = fft_any(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
       store_pair_spectra(r, M, W.s0, W.s1, tile);
     }
   } else if constexpr (MODE == RM_A3) {
@@ -692,23 +761,23 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
       }
     }
     __syncthreads();
-    float2* r = fft_lines(bufA, bufB, rt, nx, LS, M.radx, M.nstx, tw);
+    float2* r = fft_any(bufA, bufB, rt, nx, LS, M.radx, M.nstx, tw);
     float2* o = other(r, bufA, bufB);
     FOR_K {
       const int it = threadIdx.x + k * B;
       if (it < tot) {
         const int j = fdiv(it, nx, rnx), x = it - j * nx;
         const size_t idx = size_t(y0 + j) * nx + x;
-        const float2 z = r[j * LS + px(x)];
+        const float2 z = r[j * LS + x];
         const float vbx = vbx0[k] - z.x;
         const float vby = vby0[k] + z.y;
-        o[j * LS + px(x)] = make_float2(-ax[k] * bx[k] * vbx, -ay[k] * by[k] * vby);
+        o[j * LS + x] = make_float2(-ax[k] * bx[k] * vbx, -ay[k] * by[k] * vby);
         W.f0[idx] = ax[k] * ax[k] * vbx;
         W.f1[idx] = ay[k] * ay[k] * vby;
       }
     }
     __syncthreads();
-    r = fft_lines(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
+    r = fft_any(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
     store_pair_spectra(r, M, W.s0, W.s1, tile);
   } else if constexpr (MODE == RM_FWD1) {
     const float* src = X.in;
@@ -718,13 +787,13 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
       pcomp(bufA, j, x, nx) = src[size_t(y0 + j) * nx + x];
     }
     __syncthreads();
-    float2* r = fft_lines(bufA, bufB, rt / 2, nx, LS, M.radx, M.nstx, tw);
+    float2* r = fft_any(bufA, bufB, rt / 2, nx, LS, M.radx, M.nstx, tw);
     store_rowpair_spectra(r, M, W.s0, tile);
   } else if constexpr (MODE == RM_INV1) {
     load_rowpair_lines(bufA, M, W.s0, tile);
     load_tw(tw, M.twx, nx);
     __syncthreads();
-    float2* r = fft_lines(bufA, bufB, rt / 2, nx, LS, M.radx, M.nstx, tw);
+    float2* r = fft_any(bufA, bufB, rt / 2, nx, LS, M.radx, M.nstx, tw);
     float* dst = X.out;
     for (int it = threadIdx.x; it < tot; it += B) {
       const int j = fdiv(it, nx, rnx), x = it - j * nx;
@@ -778,7 +847,7 @@ col_kernel(const Launch L, int ntile, int chunk, int mcode_arg, int n) {
   const Medium& M = medium_of<U>(L, item);
   const Work W = U ? shift_work(L.w0, item * L.wstride) : L.items[item].w;
   if (n > M.nt - 2) return;
-  const int ny = M.ny, nxh = M.nxh, ct = M.ct, ls = lstride(ny);
+  const int ny = M.ny, nxh = M.nxh, ct = M.ct, ls = col_lstride(ny, ct);
   const int c0 = tile * ct;
   const int B = blockDim.x;
   const int nsl = 2;
@@ -807,7 +876,7 @@ col_kernel(const Launch L, int ntile, int chunk, int mcode_arg, int n) {
     const int ty = rem >> (M.lrt + M.lct), w = rem & (rc - 1);
     const int ky = (ty << M.lrt) + (w >> M.lct), c = w & (ct - 1);
     const float2* s = f ? W.s1 : W.s0;
-    bufA[(f * ct + c) * ls + px(ky)] = s[(size_t(ty) * ntx + tile) * rc + w];
+    bufA[(f * ct + c) * ls + ky] = s[(size_t(ty) * ntx + tile) * rc + w];
   }
   load_tw(tw, M.twy, ny);
   const int tot = ct * ny;
@@ -830,7 +899,7 @@ col_kernel(const Launch L, int ntile, int chunk, int mcode_arg, int n) {
     }
   }
   __syncthreads();
-  float2* r = fft_lines(bufA, bufB, nin * ct, ny, ls, M.rady, M.nsty, tw);
+  float2* r = fft_any(bufA, bufB, nin * ct, ny, ls, M.rady, M.nsty, tw);
   float2* o = other(r, bufA, bufB);
   FOR_K {
     const int it = threadIdx.x + k * B;
@@ -846,7 +915,7 @@ col_kernel(const Launch L, int ntile, int chunk, int mcode_arg, int n) {
 #pragma unroll
         for (int f = 0; f < 2; ++f) {
           if (f < nin) {
-            const float2 z = r[(f * ct + c) * ls + px(ky)], zm = cconj(r[(f * ct + c) * ls + px(km)]);
+            const float2 z = r[(f * ct + c) * ls + ky], zm = cconj(r[(f * ct + c) * ls + km]);
             f0[f] = cscale(cadd(z, zm), 0.5f);
             fn[f] = mul_mi(cscale(csub(z, zm), 0.5f));
           } else {
@@ -866,13 +935,13 @@ col_kernel(const Launch L, int ntile, int chunk, int mcode_arg, int n) {
               }
             }
             // W = G0 + i GN, stored conjugated for the inverse transform
-            o[(q * ct + c) * ls + px(ky)] = cconj(make_float2(g0.x - gn.y, g0.y + gn.x));
+            o[(q * ct + c) * ls + ky] = cconj(make_float2(g0.x - gn.y, g0.y + gn.x));
           }
         }
       } else {
         float2 in[2];
 #pragma unroll
-        for (int f = 0; f < 2; ++f) in[f] = f < nin ? r[(f * ct + c) * ls + px(ky)] : make_float2(0.f, 0.f);
+        for (int f = 0; f < 2; ++f) in[f] = f < nin ? r[(f * ct + c) * ls + ky] : make_float2(0.f, 0.f);
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
           if (q < nout) {
@@ -882,20 +951,20 @@ col_kernel(const Launch L, int ntile, int chunk, int mcode_arg, int n) {
               const int code = (mcode >> (4 * (2 * q + f))) & 15;
               if (code) acc = cadd(acc, cmul(mult_of(code, p, false), in[f]));
             }
-            o[(q * ct + c) * ls + px(ky)] = cconj(acc);
+            o[(q * ct + c) * ls + ky] = cconj(acc);
           }
         }
       }
     }
   }
   __syncthreads();
-  r = fft_lines(o, other(o, bufA, bufB), nout * ct, ny, ls, M.rady, M.nsty, tw);
+  r = fft_any(o, other(o, bufA, bufB), nout * ct, ny, ls, M.rady, M.nsty, tw);
   for (int it = threadIdx.x; it < nout * ct * ny; it += B) {
     const int f = fdiv(it, ny * ct, rny / ct), rem = it - f * ny * ct;
     const int ty = rem >> (M.lrt + M.lct), w = rem & (rc - 1);
     const int ky = (ty << M.lrt) + (w >> M.lct), c = w & (ct - 1);
     float2* s = f ? W.s1 : W.s0;
-    s[(size_t(ty) * ntx + tile) * rc + w] = cconj(r[(f * ct + c) * ls + px(ky)]);
+    s[(size_t(ty) * ntx + tile) * rc + w] = cconj(r[(f * ct + c) * ls + ky]);
   }
 }
 

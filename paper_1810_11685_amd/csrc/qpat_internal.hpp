@@ -116,8 +116,11 @@ hipError_t launch_combine(const Item* items, const IO* io, int nitems, int max_c
 hipError_t launch_dot(const float* a, const float* b, int64_t n, double* partial, int nblk,
                       double* out, hipStream_t st);
 
-// LDS line stride: one pad element per 8 (see px() in the kernels).
-__host__ __device__ inline int lstride(int n) { return n + (n >> 3); }
+// LDS line strides: row lines are unpadded; column lines get one pad element
+// when a tile holds several columns (their transposed loads would otherwise
+// hit one LDS bank).
+__host__ __device__ inline int lstride(int n) { return n; }
+__host__ __device__ inline int col_lstride(int ny, int ct) { return ny + (ct > 1 ? 1 : 0); }
 
 // LDS bytes of one block of each pass: ping-pong line buffers, the twiddle
 // table, and (rows) the staged sensor taps.
@@ -125,7 +128,7 @@ inline size_t row_lds_bytes(int nx, int rt) {
   return size_t(2 * rt * lstride(nx) + nx) * sizeof(float2) + kTapCap * (sizeof(Tap) + sizeof(float));
 }
 inline size_t col_lds_bytes(int ny, int ct) {
-  return (size_t(2) * 2 * ct * lstride(ny) + ny) * sizeof(float2);
+  return (size_t(2) * 2 * ct * col_lstride(ny, ct) + ny) * sizeof(float2);
 }
 
 }  // namespace qpat
