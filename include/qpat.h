@@ -151,8 +151,9 @@ qpat_status qpat_replay(qpat_plan plan, const float* p0, const float* ckpt, int3
 
 /* Launch shape of the FFT passes: rows per row-pass block, spectrum columns
  * per column-pass block (powers of two dividing ny and nx/2; rows even) and
- * threads per block of each pass (64, 128 or 256; rows*nx and cols*ny at most
- * 8 times the threads).  qpat_tune times the candidates on `stream` for
+ * threads per block of each pass (64, 128, 256 or 512; rows*nx and cols*ny at
+ * most 8 times the threads; a block's LDS within the 160 KB of a gfx950
+ * work-group).  qpat_tune times the candidates on `stream` for
  * `batch` vectors (short forward solves, synchronising the stream) and keeps
  * the fastest; results are cached per (nx, ny, batch, lossy) in the file named
  * by QPAT_TUNE_CACHE, if set.  row_threads / col_threads may be NULL in

@@ -77,6 +77,10 @@ template <> __device__ __forceinline__ void bfly<8>(float2* v) {
   v[7] = csub(e[3], o3);
 }
 
+// 24-bit unsigned product (full-rate multiply); every grid and spectrum
+// index of a pass is below 2^24.
+__device__ __forceinline__ unsigned mul24(unsigned a, unsigned b) { return __umul24(a, b); }
+
 // Quotient a / d for 0 <= a < 2^22 without an integer divide: a float
 // reciprocal estimate and one exact correction step.
 __device__ __forceinline__ int fdiv(int a, int d, float rcp) {
@@ -90,23 +94,25 @@ __device__ __forceinline__ int fdiv(int a, int d, float rcp) {
 __device__ __forceinline__ int k_of(int tx, int ix, int lct) { return (tx << lct) + ix; }
 
 // One Stockham stage for butterfly j: reads src[j + r nb], twiddles by
-// W_{Ns R}^{k r} (k = j mod Ns, Ns a power of two), writes dst[(j - k) R + k + r Ns]
-// (positions within a line mapped through ).
+// W_{Ns R}^{k r} (k = j mod Ns, Ns a power of two), writes dst[(j - k) R + k + r Ns].
+// Twiddles are stored per stage as [r - 1][k] (the stage's block starts at
+// Ns - R0, R0 the first radix), so the lanes of a wave read consecutive
+// entries.
 template <int R>
 __device__ __forceinline__ void stockham(const float2* src, float2* dst, int j, int nb, int Ns,
-                                         int tws, const float2* tw) {
+                                         int off, const float2* tw) {
   float2 v[R];
 #pragma unroll
-  for (int r = 0; r < R; ++r) v[r] = src[j + r * nb];
+  for (int r = 0; r < R; ++r) v[r] = src[px(j + r * nb)];
   const int k = j & (Ns - 1);
   if (Ns > 1) {
 #pragma unroll
-    for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw[k * r * tws]);
+    for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw[off + (r - 1) * Ns + k]);
   }
   bfly<R>(v);
   const int base = (j - k) * R + k;
 #pragma unroll
-  for (int r = 0; r < R; ++r) dst[base + r * Ns] = v[r];
+  for (int r = 0; r < R; ++r) dst[px(base + r * Ns)] = v[r];
 }
 
 // Forward FFT of `nlines` lines of length n (line stride ls) held in LDS
@@ -118,11 +124,12 @@ __device__ __forceinline__ void stockham(const float2* src, float2* dst, int j, 
 __device__ float2* fft_lines(float2* a, float2* b, int nlines, int n, int ls, uint32_t rad, int nst,
                              const float2* tw) {
   int Ns = 1;
+  const int R0 = rad & 15;
   for (int s = 0; s < nst; ++s) {
     const int R = (rad >> (4 * s)) & 15;
     const int nb = n / R;
     const float rnb = 1.0f / static_cast<float>(nb);
-    const int tws = n / (Ns * R);
+    const int off = Ns - R0;
     const int total = nlines * nb;
     for (int it = threadIdx.x; it < total; it += blockDim.x) {
       const int line = fdiv(it, nb, rnb);
@@ -130,13 +137,13 @@ __device__ float2* fft_lines(float2* a, float2* b, int nlines, int n, int ls, ui
       const float2* src = a + line * ls;
       float2* dst = b + line * ls;
       if (R == 8)
-        stockham<8>(src, dst, j, nb, Ns, tws, tw);
+        stockham<8>(src, dst, j, nb, Ns, off, tw);
       else if (R == 4)
-        stockham<4>(src, dst, j, nb, Ns, tws, tw);
+        stockham<4>(src, dst, j, nb, Ns, off, tw);
       else if (R == 2)
-        stockham<2>(src, dst, j, nb, Ns, tws, tw);
+        stockham<2>(src, dst, j, nb, Ns, off, tw);
       else
-        stockham<3>(src, dst, j, nb, Ns, tws, tw);
+        stockham<3>(src, dst, j, nb, Ns, off, tw);
     }
     __syncthreads();
     float2* t = a;
@@ -172,52 +179,72 @@ __host__ __device__ constexpr int plan_radix(int n, int s) {
   return s < idx + q ? 8 : 3;
 }
 
-template <int R, int NS, int NB, int TWS>
-__device__ __forceinline__ void stockham_c(const float2* src, float2* dst, int j, const float2* tw) {
-  float2 v[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) v[r] = src[j + r * NB];
-  const int k = j & (NS - 1);
-  if constexpr (NS > 1) {
-    const float2* t = tw + k * TWS;
-#pragma unroll
-    for (int r = 1; r < R; ++r) v[r] = cmul(v[r], t[(r - 1) * k * TWS]);
-  }
-  bfly<R>(v);
-  float2* d = dst + (j - k) * R + k;
-#pragma unroll
-  for (int r = 0; r < R; ++r) d[r * NS] = v[r];
+// Padded offset of a displacement d from a base position b when b + d stays
+// in b's run of 8 or d is a multiple of 8: px(b + d) = px(b) + pxd(d).
+__host__ __device__ constexpr int pxd(int d) { return d + (d >> 3); }
+
+// The stage shapes of the compile-time plans keep every butterfly access in
+// that form: reads j + r NB with NB a multiple of 8; writes base + r NS with
+// NS a multiple of 8, or base = (j - k) R + k whose residue mod 8 (k, or a
+// multiple of R when NS = 1) leaves room for r NS mod 8.
+__host__ __device__ constexpr bool stage_folds(int R, int NS, int NB) {
+  return NB % 8 == 0 &&
+         (NS % 8 == 0 || (R != 3 && 8 % NS == 0 && (NS == 1 ? 8 % R == 0 : (NS * R) % 8 == 0)));
 }
 
-template <int N, int S, int NS>
-__device__ __forceinline__ float2* fft_c(float2* a, float2* b, int nlines, int ls, const float2* tw) {
+template <int R, int NS, int NB, int OFF>
+__device__ __forceinline__ void stockham_c(const float2* src, float2* dst, unsigned j, const float2* tw) {
+  static_assert(stage_folds(R, NS, NB), "stage offsets do not fold");
+  float2 v[R];
+  const float2* s = src + px(int(j));
+#pragma unroll
+  for (int r = 0; r < R; ++r) v[r] = s[pxd(r * NB)];
+  const unsigned k = j & (NS - 1);
+  if constexpr (NS > 1) {
+    const float2* t = tw + OFF + k;
+#pragma unroll
+    for (int r = 1; r < R; ++r) v[r] = cmul(v[r], t[(r - 1) * NS]);
+  }
+  bfly<R>(v);
+  float2* d = dst + px(int((j - k) * R + k));
+#pragma unroll
+  for (int r = 0; r < R; ++r) d[pxd(r * NS)] = v[r];
+}
+
+// LS: line stride (a compile-time constant, so line offsets fold too).
+template <int N, int LS, int S, int NS>
+__device__ __forceinline__ float2* fft_c(float2* a, float2* b, int nlines, const float2* tw) {
   if constexpr (S == plan_nst(N)) {
     return a;
   } else {
-    constexpr int R = plan_radix(N, S), NB = N / R, TWS = N / (NS * R);
-    const int total = nlines * NB;
-    for (int it = threadIdx.x; it < total; it += blockDim.x) {
-      const int line = it / NB;
-      const int j = it - line * NB;
-      stockham_c<R, NS, NB, TWS>(a + line * ls, b + line * ls, j, tw);
+    constexpr int R = plan_radix(N, S), NB = N / R, OFF = NS - plan_radix(N, 0);
+    const unsigned total = unsigned(nlines) * NB;
+    for (unsigned it = threadIdx.x; it < total; it += blockDim.x) {
+      const unsigned line = it / NB, j = it % NB;
+      stockham_c<R, NS, NB, OFF>(a + line * LS, b + line * LS, j, tw);
     }
     __syncthreads();
-    return fft_c<N, S + 1, NS * R>(b, a, nlines, ls, tw);
+    return fft_c<N, LS, S + 1, NS * R>(b, a, nlines, tw);
   }
 }
 
 // FFT of `nlines` lines: compile-time plan for the common lengths, the
-// runtime plan otherwise.  Same contract as fft_lines.
+// runtime plan otherwise.  Same contract as fft_lines; row lines have stride
+// lstride(n), column lines (COL) col_lstride(n).
+template <bool COL>
 __device__ __forceinline__ float2* fft_any(float2* a, float2* b, int nlines, int n, int ls, uint32_t rad,
                                            int nst, const float2* tw) {
+#define QPAT_FFT_CASE(N) \
+  case N: return fft_c<N, COL ? col_lstride(N) : lstride(N), 0, 1>(a, b, nlines, tw);
   switch (n) {
-    case 128: return fft_c<128, 0, 1>(a, b, nlines, ls, tw);
-    case 256: return fft_c<256, 0, 1>(a, b, nlines, ls, tw);
-    case 384: return fft_c<384, 0, 1>(a, b, nlines, ls, tw);
-    case 512: return fft_c<512, 0, 1>(a, b, nlines, ls, tw);
-    case 1024: return fft_c<1024, 0, 1>(a, b, nlines, ls, tw);
+    QPAT_FFT_CASE(128)
+    QPAT_FFT_CASE(256)
+    QPAT_FFT_CASE(384)
+    QPAT_FFT_CASE(512)
+    QPAT_FFT_CASE(1024)
     default: return fft_lines(a, b, nlines, n, ls, rad, nst, tw);
   }
+#undef QPAT_FFT_CASE
 }
 
 // ---------------------------------------------------------------- packing
@@ -226,21 +253,21 @@ __device__ __forceinline__ float2* fft_any(float2* a, float2* b, int nlines, int
 __device__ __forceinline__ void build_inv(float2* L, float2 A, float2 B, int k, int nx, int nxh) {
   if (k == 0) {
     L[0] = make_float2(A.x, -B.x);
-    L[nxh] = make_float2(A.y, -B.y);
+    L[px(nxh)] = make_float2(A.y, -B.y);
   } else {
-    L[k] = make_float2(A.x - B.y, -(A.y + B.x));
-    L[nx - k] = make_float2(A.x + B.y, -(B.x - A.y));
+    L[px(k)] = make_float2(A.x - B.y, -(A.y + B.x));
+    L[px(nx - k)] = make_float2(A.x + B.y, -(B.x - A.y));
   }
 }
 
 // Split the FFT Z of a + i b into the packed half spectra A (of a), B (of b).
 __device__ __forceinline__ void unpack(const float2* L, int k, int nx, int nxh, float2& A, float2& B) {
   if (k == 0) {
-    const float2 z0 = L[0], zn = L[nxh];
+    const float2 z0 = L[0], zn = L[px(nxh)];
     A = make_float2(z0.x, zn.x);
     B = make_float2(z0.y, zn.y);
   } else {
-    const float2 zk = L[k], zm = L[nx - k];
+    const float2 zk = L[px(k)], zm = L[px(nx - k)];
     A = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
     B = make_float2(0.5f * (zk.y + zm.y), 0.5f * (zm.x - zk.x));
   }
@@ -254,35 +281,100 @@ __device__ __forceinline__ float2* other(float2* r, float2* a, float2* b) { retu
 // so the rt rows of one row tile form one contiguous run and a column tile is
 // a sequence of runs of rt*ct elements.  All loops below walk memory order.
 
+// The load phase of a block issues every global load before its first LDS
+// write: fetch_* gathers into registers, put_* scatters into LDS, so the phase
+// costs one memory round trip rather than one per loop iteration.  Bounds
+// (enforced on the host): a row tile holds rt*nx <= kMaxPer*B reals, hence at
+// most kPairIt complex pairs per thread; a line length is at most kMaxPer*B.
+constexpr int kPairIt = kMaxPer / 2;
+constexpr int kRowPairIt = kMaxPer / 4;
+
+struct PairRegs {
+  float2 a[kPairIt], b[kPairIt];
+};
+struct RowPairRegs {
+  float2 a[kRowPairIt], b[kRowPairIt];
+};
+struct TwRegs {
+  float2 t[kMaxPer];
+};
+
 // line j <- rows j of the row tile (s0, s1)
-__device__ __forceinline__ void load_pair_lines(float2* buf, const Medium& M, const float2* __restrict__ s0,
-                                                const float2* __restrict__ s1, int tile) {
-  const int nx = M.nx, nxh = M.nxh, LS = lstride(nx), rc = M.rt * M.ct;
-  const size_t base = size_t(tile) * M.rt * nxh;
-  for (int p = threadIdx.x; p < M.rt * nxh; p += blockDim.x) {
-    const int w = p & (rc - 1);
-    const int j = w >> M.lct, k = ((p >> (M.lrt + M.lct)) << M.lct) + (w & (M.ct - 1));
-    build_inv(buf + j * LS, s0[base + p], s1[base + p], k, nx, nxh);
+__device__ __forceinline__ void fetch_pair(PairRegs& R, const Medium& M, const float2* __restrict__ s0,
+                                           const float2* __restrict__ s1, int tile) {
+  const int tot = M.rt * M.nxh;
+  const unsigned base = mul24(tile, tot);
+#pragma unroll
+  for (int k = 0; k < kPairIt; ++k) {
+    const int p = threadIdx.x + k * blockDim.x;
+    if (p < tot) {
+      R.a[k] = s0[base + p];
+      R.b[k] = s1[base + p];
+    }
+  }
+}
+__device__ __forceinline__ void put_pair(const PairRegs& R, float2* buf, const Medium& M) {
+  const int nx = M.nx, nxh = M.nxh, LS = lstride(nx), rc = M.rt * M.ct, tot = M.rt * nxh;
+#pragma unroll
+  for (int k = 0; k < kPairIt; ++k) {
+    const int p = threadIdx.x + k * blockDim.x;
+    if (p < tot) {
+      const int w = p & (rc - 1);
+      const int j = w >> M.lct, kx = ((p >> (M.lrt + M.lct)) << M.lct) + (w & (M.ct - 1));
+      build_inv(buf + j * LS, R.a[k], R.b[k], kx, nx, nxh);
+    }
   }
 }
 
 // line l <- rows (2l, 2l+1) of the row tile of s0
-__device__ __forceinline__ void load_rowpair_lines(float2* buf, const Medium& M, const float2* __restrict__ s0,
-                                                   int tile) {
-  const int nx = M.nx, nxh = M.nxh, LS = lstride(nx), hc = (M.rt >> 1) * M.ct;
-  const size_t base = size_t(tile) * M.rt * nxh;
-  for (int q = threadIdx.x; q < (M.rt >> 1) * nxh; q += blockDim.x) {
-    const int tx = q >> (M.lrt - 1 + M.lct), w2 = q & (hc - 1);
-    const int l = w2 >> M.lct, ix = w2 & (M.ct - 1);
-    const size_t off = base + size_t(tx) * M.rt * M.ct + (2 * l) * M.ct + ix;
-    build_inv(buf + l * LS, s0[off], s0[off + M.ct], k_of(tx, ix, M.lct), nx, nxh);
+__device__ __forceinline__ void fetch_rowpair(RowPairRegs& R, const Medium& M, const float2* __restrict__ s0,
+                                              int tile) {
+  const int nxh = M.nxh, hc = (M.rt >> 1) * M.ct, tot = (M.rt >> 1) * nxh;
+  const unsigned base = mul24(tile, M.rt * nxh);
+#pragma unroll
+  for (int k = 0; k < kRowPairIt; ++k) {
+    const int q = threadIdx.x + k * blockDim.x;
+    if (q < tot) {
+      const int tx = q >> (M.lrt - 1 + M.lct), w2 = q & (hc - 1);
+      const int l = w2 >> M.lct, ix = w2 & (M.ct - 1);
+      const unsigned off = base + (unsigned(tx) << (M.lrt + M.lct)) + (2 * l) * M.ct + ix;
+      R.a[k] = s0[off];
+      R.b[k] = s0[off + M.ct];
+    }
+  }
+}
+__device__ __forceinline__ void put_rowpair(const RowPairRegs& R, float2* buf, const Medium& M) {
+  const int nx = M.nx, nxh = M.nxh, LS = lstride(nx), hc = (M.rt >> 1) * M.ct, tot = (M.rt >> 1) * nxh;
+#pragma unroll
+  for (int k = 0; k < kRowPairIt; ++k) {
+    const int q = threadIdx.x + k * blockDim.x;
+    if (q < tot) {
+      const int tx = q >> (M.lrt - 1 + M.lct), w2 = q & (hc - 1);
+      const int l = w2 >> M.lct, ix = w2 & (M.ct - 1);
+      build_inv(buf + l * LS, R.a[k], R.b[k], k_of(tx, ix, M.lct), nx, nxh);
+    }
+  }
+}
+
+__device__ __forceinline__ void fetch_tw(TwRegs& R, const float2* __restrict__ tw, int n) {
+#pragma unroll
+  for (int k = 0; k < kMaxPer; ++k) {
+    const int i = threadIdx.x + k * blockDim.x;
+    if (i < n) R.t[k] = tw[i];
+  }
+}
+__device__ __forceinline__ void put_tw(const TwRegs& R, float2* dst, int n) {
+#pragma unroll
+  for (int k = 0; k < kMaxPer; ++k) {
+    const int i = threadIdx.x + k * blockDim.x;
+    if (i < n) dst[i] = R.t[k];
   }
 }
 
 __device__ __forceinline__ void store_pair_spectra(const float2* buf, const Medium& M, float2* __restrict__ s0,
                                                    float2* __restrict__ s1, int tile) {
   const int nx = M.nx, nxh = M.nxh, LS = lstride(nx), rc = M.rt * M.ct;
-  const size_t base = size_t(tile) * M.rt * nxh;
+  const unsigned base = mul24(tile, M.rt * nxh);
   for (int p = threadIdx.x; p < M.rt * nxh; p += blockDim.x) {
     const int w = p & (rc - 1);
     const int j = w >> M.lct, k = ((p >> (M.lrt + M.lct)) << M.lct) + (w & (M.ct - 1));
@@ -296,11 +388,11 @@ __device__ __forceinline__ void store_pair_spectra(const float2* buf, const Medi
 __device__ __forceinline__ void store_rowpair_spectra(const float2* buf, const Medium& M, float2* __restrict__ s0,
                                                       int tile) {
   const int nx = M.nx, nxh = M.nxh, LS = lstride(nx), hc = (M.rt >> 1) * M.ct;
-  const size_t base = size_t(tile) * M.rt * nxh;
+  const unsigned base = mul24(tile, M.rt * nxh);
   for (int q = threadIdx.x; q < (M.rt >> 1) * nxh; q += blockDim.x) {
     const int tx = q >> (M.lrt - 1 + M.lct), w2 = q & (hc - 1);
     const int l = w2 >> M.lct, ix = w2 & (M.ct - 1);
-    const size_t off = base + size_t(tx) * M.rt * M.ct + (2 * l) * M.ct + ix;
+    const unsigned off = base + (unsigned(tx) << (M.lrt + M.lct)) + (2 * l) * M.ct + ix;
     float2 A, B;
     unpack(buf + l * LS, k_of(tx, ix, M.lct), nx, nxh, A, B);
     s0[off] = A;
@@ -310,45 +402,57 @@ __device__ __forceinline__ void store_rowpair_spectra(const float2* buf, const M
 
 // Row-pair LDS layout: row y0+j lives in component (j & 1) of line j >> 1.
 __device__ __forceinline__ float& pcomp(float2* buf, int j, int x, int nx) {
-  float2* e = buf + (j >> 1) * lstride(nx) + x;
+  float2* e = buf + (j >> 1) * lstride(nx) + px(x);
   return (j & 1) ? e->y : e->x;
 }
 
 // Value of row y0+j after an inverse FFT of row-pair lines (conj trick undone).
 __device__ __forceinline__ float rowpair_val(const float2* buf, int j, int x, int nx) {
-  const float2 e = buf[(j >> 1) * lstride(nx) + x];
+  const float2 e = buf[(j >> 1) * lstride(nx) + px(x)];
   return (j & 1) ? -e.y : e.x;
 }
 
 // Sensor taps of the tile's rows (and, in the adjoint, the residual samples
-// they need) are staged in LDS during the load phase; entries beyond the LDS
-// capacity are read from global memory.
+// they need, in tap order) are staged in LDS; entries beyond the LDS capacity
+// are read from global memory.  The tap range is read with the first loads of
+// a block; the taps themselves are fetched after the first barrier (thread i
+// holds tap e0 + i, blockDim.x >= kTapCap) and written to LDS only where the
+// sensors are used, so their latency hides behind the first FFT.
 struct TapStage {
   Tap* tl;     // [kTapCap]
   float* rv;   // [kTapCap]
   int e0, e1;  // CSR range of the tile
+  int w[8];    // this thread's tap, word by word
+  float r;     // and its residual sample
 };
 
-__device__ __forceinline__ TapStage stage_taps(const Medium& M, void* base, int y0, int rt,
-                                               const float* __restrict__ res, int m) {
-  TapStage T;
+__device__ __forceinline__ void taps_range(TapStage& T, const Medium& M, void* base, int y0, int rt) {
   T.tl = reinterpret_cast<Tap*>(base);
   T.rv = reinterpret_cast<float*>(T.tl + kTapCap);
   T.e0 = M.tap_off[y0];
   T.e1 = M.tap_off[y0 + rt];
-  const int cnt = min(T.e1 - T.e0, kTapCap);
-  for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
-    // copied word by word (a struct copy would go through scratch)
-    const int* src = reinterpret_cast<const int*>(M.taps + T.e0 + i);
-    int* dst = reinterpret_cast<int*>(T.tl + i);
-    int w[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) w[q] = src[q];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) dst[q] = w[q];
-    if (res) T.rv[i] = res[size_t(m) * M.ns + w[0]];
+}
+
+// rtap: residual samples in tap order for sample m ([nt][ntap]), or null
+__device__ __forceinline__ void taps_fetch(TapStage& T, const Medium& M, const float* __restrict__ rtap, int m) {
+  const int i = threadIdx.x;
+  if (i < min(T.e1 - T.e0, kTapCap)) {
+    const int4* src = reinterpret_cast<const int4*>(M.taps + T.e0 + i);
+    const int4 lo = src[0], hi = src[1];
+    T.w[0] = lo.x, T.w[1] = lo.y, T.w[2] = lo.z, T.w[3] = lo.w;
+    T.w[4] = hi.x, T.w[5] = hi.y, T.w[6] = hi.z, T.w[7] = hi.w;
+    if (rtap) T.r = rtap[unsigned(m) * unsigned(2 * M.ns) + T.e0 + i];
   }
-  return T;
+}
+
+__device__ __forceinline__ void taps_put(const TapStage& T, bool with_res) {
+  const int i = threadIdx.x;
+  if (i < min(T.e1 - T.e0, kTapCap)) {
+    int4* dst = reinterpret_cast<int4*>(T.tl + i);
+    dst[0] = make_int4(T.w[0], T.w[1], T.w[2], T.w[3]);
+    dst[1] = make_int4(T.w[4], T.w[5], T.w[6], T.w[7]);
+    if (with_res) T.rv[i] = T.r;
+  }
 }
 
 __device__ __forceinline__ Tap tap_at(const Medium& M, const TapStage& T, int e) {
@@ -372,28 +476,24 @@ __device__ __forceinline__ void sensor_partials(const Medium& M, const TapStage&
     const Tap t = tap_at(M, T, e);
     const int j = t.y - y0;
     const float v = t.wl * pcomp(buf, j, t.ixl, M.nx) + t.wr * pcomp(buf, j, t.ixr, M.nx);
-    part[(size_t(m) * M.ns + t.s) * 2 + t.slot] = v;
+    part[(unsigned(m) * unsigned(M.ns) + t.s) * 2 + t.slot] = v;
   }
 }
 
 // Adjoint sensor scatter M^T r for rows y0 .. y0+rt-1, one thread per row so
 // taps hitting the same node are added in a fixed order.
 __device__ __forceinline__ void sensor_scatter(const Medium& M, const TapStage& T, float2* buf, int y0,
-                                               int rt, const float* __restrict__ res, int m) {
+                                               int rt, const float* __restrict__ rtap, int m) {
   const int r = threadIdx.x;
   if (r < rt) {
     const int a = M.tap_off[y0 + r], b = M.tap_off[y0 + r + 1];
     for (int e = a; e < b; ++e) {
       const Tap t = tap_at(M, T, e);
-      const float rv = (e - T.e0 < kTapCap) ? T.rv[e - T.e0] : res[size_t(m) * M.ns + t.s];
+      const float rv = (e - T.e0 < kTapCap) ? T.rv[e - T.e0] : rtap[unsigned(m) * unsigned(2 * M.ns) + e];
       pcomp(buf, r, t.ixl, M.nx) += t.wl * rv;
       pcomp(buf, r, t.ixr, M.nx) += t.wr * rv;
     }
   }
-}
-
-__device__ __forceinline__ void load_tw(float2* dst, const float2* __restrict__ tw, int n) {
-  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = tw[i];
 }
 
 // ---------------------------------------------------------------- block -> (item, tile)
@@ -445,9 +545,13 @@ __device__ __forceinline__ Work shift_work(const Work& w, long long off) {
 // twiddles into LDS, pointwise operands into registers (at most kMaxPer
 // elements per thread); the FFT stages then run out of LDS only.
 #define FOR_K _Pragma("unroll") for (int k = 0; k < kMaxPer; ++k)
+// Load loops skip whole iterations on a block-uniform test and clamp the
+// ragged last one (its extra lanes re-read the last element): no per-lane
+// branch, so the loads of all iterations issue back to back.
+#define FOR_K_LD _Pragma("unroll") for (int k = 0; k < kMaxPer; ++k) if (k * B < tot)
 
 template <int MODE, bool U>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kMaxThreads)
 row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
   extern __shared__ float2 lds[];
   int item, tile;
@@ -472,78 +576,97 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     // eq num-vel: v_i = A_i (A_i v_i - dt/rho_i d/dr_i^+ p)
     const bool first = (n == 0);  // v^{-1/2} = 0
     float vxo[kMaxPer], vyo[kMaxPer], bx[kMaxPer], by[kMaxPer], ax[kMaxPer], ay[kMaxPer];
-    load_pair_lines(bufA, M, W.s0, W.s1, tile);
-    load_tw(tw, M.twx, nx);
-    FOR_K {
-      const int it = threadIdx.x + k * B;
-      if (it < tot) {
+    PairRegs S;
+    TwRegs TW;
+    fetch_pair(S, M, W.s0, W.s1, tile);
+    fetch_tw(TW, M.twx, nx);
+    FOR_K_LD {
+      const int it = min(int(threadIdx.x) + k * B, tot - 1);
+      {
         const int j = fdiv(it, nx, rnx), x = it - j * nx, y = y0 + j;
-        const size_t idx = size_t(y) * nx + x;
-        vxo[k] = first ? 0.f : W.f0[idx];
-        vyo[k] = first ? 0.f : W.f1[idx];
+        const unsigned idx = mul24(y, nx) + x;
+        vxo[k] = W.f0[idx];
+        vyo[k] = W.f1[idx];
         bx[k] = M.bx[idx];
         by[k] = M.by[idx];
         ax[k] = M.avx[x];
         ay[k] = M.avy[y];
       }
     }
+    put_pair(S, bufA, M);
+    put_tw(TW, tw, nx);
     __syncthreads();
-    float2* r = fft_any(bufA, bufB, rt, nx, LS, M.radx, M.nstx, tw);
+    float2* r = fft_any<false>(bufA, bufB, rt, nx, LS, M.radx, M.nstx, tw);
     float2* o = other(r, bufA, bufB);
     FOR_K {
       const int it = threadIdx.x + k * B;
       if (it < tot) {
         const int j = fdiv(it, nx, rnx), x = it - j * nx;
-        const size_t idx = size_t(y0 + j) * nx + x;
-        const float2 z = r[j * LS + x];
-        const float vx = ax[k] * (ax[k] * vxo[k] - bx[k] * z.x);
-        const float vy = ay[k] * (ay[k] * vyo[k] + by[k] * z.y);
+        const unsigned idx = mul24(y0 + j, nx) + x;
+        const float2 z = r[j * LS + px(x)];
+        const float vx = ax[k] * (ax[k] * (first ? 0.f : vxo[k]) - bx[k] * z.x);
+        const float vy = ay[k] * (ay[k] * (first ? 0.f : vyo[k]) + by[k] * z.y);
         W.f0[idx] = vx;
         W.f1[idx] = vy;
-        o[j * LS + x] = make_float2(vx, vy);
+        o[j * LS + px(x)] = make_float2(vx, vy);
       }
     }
     __syncthreads();
-    r = fft_any(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
+    r = fft_any<false>(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
     store_pair_spectra(r, M, W.s0, W.s1, tile);
   } else if constexpr (MODE == RM_F2 || MODE == RM_F2L) {
     // eq num-rho with the additive source of eq s1 (dt s = p0 / (2 d c^2), d = 2)
     const bool skip = (n == -1);  // v^{-1/2} = 0 and rho^{-1} = 0
     const bool inject = (n <= 0);
     float rxo[kMaxPer], ryo[kMaxPer], r0[kMaxPer], ax[kMaxPer], ay[kMaxPer], src[kMaxPer], c2[kMaxPer];
-    if (!skip) load_pair_lines(bufA, M, W.s0, W.s1, tile);
-    load_tw(tw, M.twx, nx);
+    PairRegs S;
+    TwRegs TW;
     TapStage T{};
-    if constexpr (MODE == RM_F2L) T = stage_taps(M, tap_base, y0, rt, nullptr, 0);
-    FOR_K {
-      const int it = threadIdx.x + k * B;
-      if (it < tot) {
+    if constexpr (MODE == RM_F2L) taps_range(T, M, tap_base, y0, rt);
+    if (!skip) fetch_pair(S, M, W.s0, W.s1, tile);
+    fetch_tw(TW, M.twx, nx);
+    FOR_K_LD {
+      const int it = min(int(threadIdx.x) + k * B, tot - 1);
+      {
         const int j = fdiv(it, nx, rnx), x = it - j * nx, y = y0 + j;
-        const size_t idx = size_t(y) * nx + x;
-        rxo[k] = skip ? 0.f : W.f2[idx];
-        ryo[k] = skip ? 0.f : W.f3[idx];
+        const unsigned idx = mul24(y, nx) + x;
+        rxo[k] = W.f2[idx];
+        ryo[k] = W.f3[idx];
         r0[k] = M.rho0[idx];
         ax[k] = M.arx[x];
         ay[k] = M.ary[y];
-        c2[k] = (MODE == RM_F2L || inject) ? M.c2[idx] : 0.f;
-        src[k] = inject ? X.in[idx] : 0.f;
+        if constexpr (MODE == RM_F2L) c2[k] = M.c2[idx];
       }
     }
+    if (inject) {  // first two iterates only (kept apart so the loads above issue back to back)
+      FOR_K_LD {
+        const int it = min(int(threadIdx.x) + k * B, tot - 1);
+        {
+          const int j = fdiv(it, nx, rnx), x = it - j * nx;
+          const unsigned idx = mul24(y0 + j, nx) + x;
+          if constexpr (MODE != RM_F2L) c2[k] = M.c2[idx];
+          src[k] = X.in[idx];
+        }
+      }
+    }
+    if (!skip) put_pair(S, bufA, M);
+    put_tw(TW, tw, nx);
     __syncthreads();
+    if constexpr (MODE == RM_F2L) taps_fetch(T, M, nullptr, 0);
     float2* r = nullptr;
     float2* o = bufA;
     if (!skip) {
-      r = fft_any(bufA, bufB, rt, nx, LS, M.radx, M.nstx, tw);
+      r = fft_any<false>(bufA, bufB, rt, nx, LS, M.radx, M.nstx, tw);
       o = other(r, bufA, bufB);
     }
     FOR_K {
       const int it = threadIdx.x + k * B;
       if (it < tot) {
         const int j = fdiv(it, nx, rnx), x = it - j * nx;
-        const size_t idx = size_t(y0 + j) * nx + x;
+        const unsigned idx = mul24(y0 + j, nx) + x;
         float ex = 0.f, ey = 0.f;
         if (!skip) {
-          const float2 z = r[j * LS + x];
+          const float2 z = r[j * LS + px(x)];
           ex = z.x;
           ey = -z.y;
         } else {
@@ -551,8 +674,8 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
           W.f1[idx] = 0.f;
         }
         const float s = inject ? src[k] * (0.25f / c2[k]) : 0.f;
-        const float rx = ax[k] * (ax[k] * rxo[k] - dt * r0[k] * ex) + s;
-        const float ry = ay[k] * (ay[k] * ryo[k] - dt * r0[k] * ey) + s;
+        const float rx = ax[k] * (ax[k] * (skip ? 0.f : rxo[k]) - dt * r0[k] * ex) + s;
+        const float ry = ay[k] * (ay[k] * (skip ? 0.f : ryo[k]) - dt * r0[k] * ey) + s;
         W.f2[idx] = rx;
         W.f3[idx] = ry;
         if constexpr (MODE == RM_F2) {
@@ -568,50 +691,60 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
         }
       }
     }
+    if constexpr (MODE == RM_F2L) taps_put(T, false);
     __syncthreads();
     if constexpr (MODE == RM_F2) {
-      r = fft_any(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
+      r = fft_any<false>(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
       store_rowpair_spectra(r, M, W.s0, tile);
       store_rowpair_spectra(r + (rt / 2) * LS, M, W.s1, tile);
     } else {
       if (!(flags & FL_NO_SENSORS)) sensor_partials(M, T, o, y0, W.part, n + 1);
-      r = fft_any(o, other(o, bufA, bufB), rt / 2, nx, LS, M.radx, M.nstx, tw);
+      r = fft_any<false>(o, other(o, bufA, bufB), rt / 2, nx, LS, M.radx, M.nstx, tw);
       store_rowpair_spectra(r, M, W.s0, tile);
     }
   } else if constexpr (MODE == RM_F3) {
     // eq num-p: p = c^2 (S - eta Y_dis S + tau Y_abs u)
-    float rs[kMaxPer], c2[kMaxPer], ce[kMaxPer], ctau[kMaxPer];
-    load_rowpair_lines(bufA, M, W.s0, tile);
-    load_rowpair_lines(bufA + (rt / 2) * LS, M, W.s1, tile);
-    load_tw(tw, M.twx, nx);
-    const TapStage T = stage_taps(M, tap_base, y0, rt, nullptr, 0);
-    FOR_K {
-      const int it = threadIdx.x + k * B;
-      if (it < tot) {
+    float rxo[kMaxPer], ryo[kMaxPer], c2[kMaxPer], ce[kMaxPer], ctau[kMaxPer];
+    TapStage T;
+    taps_range(T, M, tap_base, y0, rt);
+    RowPairRegs S0, S1;
+    TwRegs TW;
+    fetch_rowpair(S0, M, W.s0, tile);
+    fetch_rowpair(S1, M, W.s1, tile);
+    fetch_tw(TW, M.twx, nx);
+    FOR_K_LD {
+      const int it = min(int(threadIdx.x) + k * B, tot - 1);
+      {
         const int j = fdiv(it, nx, rnx), x = it - j * nx;
-        const size_t idx = size_t(y0 + j) * nx + x;
-        rs[k] = W.f2[idx] + W.f3[idx];
+        const unsigned idx = mul24(y0 + j, nx) + x;
+        rxo[k] = W.f2[idx];
+        ryo[k] = W.f3[idx];
         c2[k] = M.c2[idx];
         ce[k] = M.c2eta[idx];
         ctau[k] = M.c2tau[idx];
       }
     }
+    put_rowpair(S0, bufA, M);
+    put_rowpair(S1, bufA + (rt / 2) * LS, M);
+    put_tw(TW, tw, nx);
     __syncthreads();
-    float2* r = fft_any(bufA, bufB, rt, nx, LS, M.radx, M.nstx, tw);
+    taps_fetch(T, M, nullptr, 0);
+    float2* r = fft_any<false>(bufA, bufB, rt, nx, LS, M.radx, M.nstx, tw);
     float2* o = other(r, bufA, bufB);
     FOR_K {
       const int it = threadIdx.x + k * B;
       if (it < tot) {
         const int j = fdiv(it, nx, rnx), x = it - j * nx;
         const float ys = rowpair_val(r, j, x, nx), yu = rowpair_val(r + (rt / 2) * LS, j, x, nx);
-        const float p = c2[k] * rs[k] - ce[k] * ys + ctau[k] * yu;
+        const float p = c2[k] * (rxo[k] + ryo[k]) - ce[k] * ys + ctau[k] * yu;
         pcomp(o, j, x, nx) = p;
-        if (flags & FL_STORE_P) W.q[size_t(y0 + j) * nx + x] = p;
+        if (flags & FL_STORE_P) W.q[mul24(y0 + j, nx) + x] = p;
       }
     }
+    taps_put(T, false);
     __syncthreads();
     if (!(flags & FL_NO_SENSORS)) sensor_partials(M, T, o, y0, W.part, n + 1);
-    r = fft_any(o, other(o, bufA, bufB), rt / 2, nx, LS, M.radx, M.nstx, tw);
+    r = fft_any<false>(o, other(o, bufA, bufB), rt / 2, nx, LS, M.radx, M.nstx, tw);
     store_rowpair_spectra(r, M, W.s0, tile);
   } else if constexpr (MODE == RM_A1 || MODE == RM_A1L) {
     // transpose of eqs num-m and num-p: p* += M^T r_{n+1}; q = c^2 p*
@@ -619,32 +752,48 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     const int half = rt / 2;
     float c2[kMaxPer], ce[kMaxPer], ctau[kMaxPer], rbx0[kMaxPer], rby0[kMaxPer], r0[kMaxPer];
     float ax[kMaxPer], ay[kMaxPer], gacc[kMaxPer];
-    if (!first) load_rowpair_lines(bufA, M, W.s0, tile);
-    load_tw(tw, M.twx, nx);
-    const TapStage T = stage_taps(M, tap_base, y0, rt, X.in, n + 1);
-    FOR_K {
-      const int it = threadIdx.x + k * B;
-      if (it < tot) {
+    TapStage T;
+    taps_range(T, M, tap_base, y0, rt);
+    RowPairRegs S0;
+    TwRegs TW;
+    if (!first) fetch_rowpair(S0, M, W.s0, tile);
+    fetch_tw(TW, M.twx, nx);
+    FOR_K_LD {
+      const int it = min(int(threadIdx.x) + k * B, tot - 1);
+      {
         const int j = fdiv(it, nx, rnx), x = it - j * nx, y = y0 + j;
-        const size_t idx = size_t(y) * nx + x;
+        const unsigned idx = mul24(y, nx) + x;
         c2[k] = M.c2[idx];
         if constexpr (MODE == RM_A1) {
           ce[k] = M.c2eta[idx];
           ctau[k] = M.c2tau[idx];
         } else {
-          rbx0[k] = first ? 0.f : W.f2[idx];
-          rby0[k] = first ? 0.f : W.f3[idx];
+          rbx0[k] = W.f2[idx];
+          rby0[k] = W.f3[idx];
           r0[k] = M.rho0[idx];
           ax[k] = M.arx[x];
           ay[k] = M.ary[y];
-          gacc[k] = (n == -1 && M.nt >= 2) ? X.out[idx] : 0.f;
         }
       }
     }
+    if constexpr (MODE == RM_A1L) {
+      if (n == -1 && M.nt >= 2) {  // the gradient accumulated at n = 0
+        FOR_K_LD {
+          const int it = min(int(threadIdx.x) + k * B, tot - 1);
+          {
+            const int j = fdiv(it, nx, rnx), x = it - j * nx;
+            gacc[k] = X.out[mul24(y0 + j, nx) + x];
+          }
+        }
+      }
+    }
+    if (!first) put_rowpair(S0, bufA, M);
+    put_tw(TW, tw, nx);
     __syncthreads();
+    taps_fetch(T, M, W.part, n + 1);
     float2* r = bufA;
     if (!first) {
-      r = fft_any(bufA, bufB, half, nx, LS, M.radx, M.nstx, tw);
+      r = fft_any<false>(bufA, bufB, half, nx, LS, M.radx, M.nstx, tw);
       // p* = -(grad_x^- g_x + grad_y^- g_y): negate the (conjugated) inverse
       for (int it = threadIdx.x; it < half * LS; it += B) {
         const float2 z = r[it];
@@ -653,15 +802,16 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     } else {
       for (int it = threadIdx.x; it < half * LS; it += B) r[it] = make_float2(0.f, 0.f);
     }
+    taps_put(T, true);
     __syncthreads();
-    sensor_scatter(M, T, r, y0, rt, X.in, n + 1);
+    sensor_scatter(M, T, r, y0, rt, W.part, n + 1);
     __syncthreads();
     float2* o = other(r, bufA, bufB);
     FOR_K {
       const int it = threadIdx.x + k * B;
       if (it < tot) {
         const int j = fdiv(it, nx, rnx), x = it - j * nx;
-        const size_t idx = size_t(y0 + j) * nx + x;
+        const unsigned idx = mul24(y0 + j, nx) + x;
         const float pb = pcomp(r, j, x, nx);
         if constexpr (MODE == RM_A1) {
           // eta q and tau q, each with its own rows paired (see RM_F2)
@@ -671,12 +821,12 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
         } else {
           // lossless: S* = q, u* = 0, then the transposed mass update
           const float q = c2[k] * pb;
-          const float rbx = rbx0[k] + q, rby = rby0[k] + q;
+          const float rbx = (first ? 0.f : rbx0[k]) + q, rby = (first ? 0.f : rby0[k]) + q;
           if (n == 0) X.out[idx] = rbx + rby;
           if (n == -1) {
-            X.out[idx] = (rbx + rby + gacc[k]) * (0.25f / c2[k]);
+            X.out[idx] = (rbx + rby + (M.nt >= 2 ? gacc[k] : 0.f)) * (0.25f / c2[k]);
           } else {
-            o[j * LS + x] = make_float2(-dt * r0[k] * ax[k] * rbx, -dt * r0[k] * ay[k] * rby);
+            o[j * LS + px(x)] = make_float2(-dt * r0[k] * ax[k] * rbx, -dt * r0[k] * ay[k] * rby);
             W.f2[idx] = ax[k] * ax[k] * rbx;
             W.f3[idx] = ay[k] * ay[k] * rby;
           }
@@ -685,11 +835,11 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     }
     __syncthreads();
     if constexpr (MODE == RM_A1) {
-      r = fft_any(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
+      r = fft_any<false>(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
       store_rowpair_spectra(r, M, W.s0, tile);
       store_rowpair_spectra(r + half * LS, M, W.s1, tile);
     } else if (n != -1) {
-      r = fft_any(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
+      r = fft_any<false>(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
       store_pair_spectra(r, M, W.s0, W.s1, tile);
     }
   } else if constexpr (MODE == RM_A2) {
@@ -697,40 +847,54 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     const bool first = (n == M.nt - 2);
     float qv[kMaxPer], rbx0[kMaxPer], rby0[kMaxPer], r0[kMaxPer], ax[kMaxPer], ay[kMaxPer];
     float c2[kMaxPer], gacc[kMaxPer];
-    load_rowpair_lines(bufA, M, W.s0, tile);
-    load_rowpair_lines(bufA + (rt / 2) * LS, M, W.s1, tile);
-    load_tw(tw, M.twx, nx);
-    FOR_K {
-      const int it = threadIdx.x + k * B;
-      if (it < tot) {
+    RowPairRegs S0, S1;
+    TwRegs TW;
+    fetch_rowpair(S0, M, W.s0, tile);
+    fetch_rowpair(S1, M, W.s1, tile);
+    fetch_tw(TW, M.twx, nx);
+    FOR_K_LD {
+      const int it = min(int(threadIdx.x) + k * B, tot - 1);
+      {
         const int j = fdiv(it, nx, rnx), x = it - j * nx, y = y0 + j;
-        const size_t idx = size_t(y) * nx + x;
+        const unsigned idx = mul24(y, nx) + x;
         qv[k] = W.q[idx];
-        rbx0[k] = first ? 0.f : W.f2[idx];
-        rby0[k] = first ? 0.f : W.f3[idx];
+        rbx0[k] = W.f2[idx];
+        rby0[k] = W.f3[idx];
         r0[k] = M.rho0[idx];
         ax[k] = M.arx[x];
         ay[k] = M.ary[y];
-        c2[k] = (n == -1) ? M.c2[idx] : 1.f;
-        gacc[k] = (n == -1 && M.nt >= 2) ? X.out[idx] : 0.f;
       }
     }
+    if (n == -1) {  // the last iterate: gradient scaling and the sum accumulated at n = 0
+      FOR_K_LD {
+        const int it = min(int(threadIdx.x) + k * B, tot - 1);
+        {
+          const int j = fdiv(it, nx, rnx), x = it - j * nx;
+          const unsigned idx = mul24(y0 + j, nx) + x;
+          c2[k] = M.c2[idx];
+          gacc[k] = M.nt >= 2 ? X.out[idx] : 0.f;
+        }
+      }
+    }
+    put_rowpair(S0, bufA, M);
+    put_rowpair(S1, bufA + (rt / 2) * LS, M);
+    put_tw(TW, tw, nx);
     __syncthreads();
-    float2* r = fft_any(bufA, bufB, rt, nx, LS, M.radx, M.nstx, tw);
+    float2* r = fft_any<false>(bufA, bufB, rt, nx, LS, M.radx, M.nstx, tw);
     float2* o = other(r, bufA, bufB);
     FOR_K {
       const int it = threadIdx.x + k * B;
       if (it < tot) {
         const int j = fdiv(it, nx, rnx), x = it - j * nx;
-        const size_t idx = size_t(y0 + j) * nx + x;
+        const unsigned idx = mul24(y0 + j, nx) + x;
         const float yd = rowpair_val(r, j, x, nx), ya = rowpair_val(r + (rt / 2) * LS, j, x, nx);
         const float sb = qv[k] - yd;
-        const float rbx = rbx0[k] + sb, rby = rby0[k] + sb;
+        const float rbx = (first ? 0.f : rbx0[k]) + sb, rby = (first ? 0.f : rby0[k]) + sb;
         if (n == 0) X.out[idx] = rbx + rby;
         if (n == -1) {
           X.out[idx] = (rbx + rby + gacc[k]) * (0.25f / c2[k]);
         } else {
-          o[j * LS + x] = make_float2(r0[k] * ax[k] * (ya - dt * rbx), r0[k] * ay[k] * (ya - dt * rby));
+          o[j * LS + px(x)] = make_float2(r0[k] * ax[k] * (ya - dt * rbx), r0[k] * ay[k] * (ya - dt * rby));
           W.f2[idx] = ax[k] * ax[k] * rbx;
           W.f3[idx] = ay[k] * ay[k] * rby;
         }
@@ -738,66 +902,87 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     }
     __syncthreads();
     if (n != -1) {
-      r = fft_any(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
+      r = fft_any<false>(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
       store_pair_spectra(r, M, W.s0, W.s1, tile);
     }
   } else if constexpr (MODE == RM_A3) {
     // transpose of eq num-vel
     const bool first = (n == M.nt - 2);
     float vbx0[kMaxPer], vby0[kMaxPer], bx[kMaxPer], by[kMaxPer], ax[kMaxPer], ay[kMaxPer];
-    load_pair_lines(bufA, M, W.s0, W.s1, tile);
-    load_tw(tw, M.twx, nx);
-    FOR_K {
-      const int it = threadIdx.x + k * B;
-      if (it < tot) {
+    PairRegs S;
+    TwRegs TW;
+    fetch_pair(S, M, W.s0, W.s1, tile);
+    fetch_tw(TW, M.twx, nx);
+    FOR_K_LD {
+      const int it = min(int(threadIdx.x) + k * B, tot - 1);
+      {
         const int j = fdiv(it, nx, rnx), x = it - j * nx, y = y0 + j;
-        const size_t idx = size_t(y) * nx + x;
-        vbx0[k] = first ? 0.f : W.f0[idx];
-        vby0[k] = first ? 0.f : W.f1[idx];
+        const unsigned idx = mul24(y, nx) + x;
+        vbx0[k] = W.f0[idx];
+        vby0[k] = W.f1[idx];
         bx[k] = M.bx[idx];
         by[k] = M.by[idx];
         ax[k] = M.avx[x];
         ay[k] = M.avy[y];
       }
     }
+    put_pair(S, bufA, M);
+    put_tw(TW, tw, nx);
     __syncthreads();
-    float2* r = fft_any(bufA, bufB, rt, nx, LS, M.radx, M.nstx, tw);
+    float2* r = fft_any<false>(bufA, bufB, rt, nx, LS, M.radx, M.nstx, tw);
     float2* o = other(r, bufA, bufB);
     FOR_K {
       const int it = threadIdx.x + k * B;
       if (it < tot) {
         const int j = fdiv(it, nx, rnx), x = it - j * nx;
-        const size_t idx = size_t(y0 + j) * nx + x;
-        const float2 z = r[j * LS + x];
-        const float vbx = vbx0[k] - z.x;
-        const float vby = vby0[k] + z.y;
-        o[j * LS + x] = make_float2(-ax[k] * bx[k] * vbx, -ay[k] * by[k] * vby);
+        const unsigned idx = mul24(y0 + j, nx) + x;
+        const float2 z = r[j * LS + px(x)];
+        const float vbx = (first ? 0.f : vbx0[k]) - z.x;
+        const float vby = (first ? 0.f : vby0[k]) + z.y;
+        o[j * LS + px(x)] = make_float2(-ax[k] * bx[k] * vbx, -ay[k] * by[k] * vby);
         W.f0[idx] = ax[k] * ax[k] * vbx;
         W.f1[idx] = ay[k] * ay[k] * vby;
       }
     }
     __syncthreads();
-    r = fft_any(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
+    r = fft_any<false>(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
     store_pair_spectra(r, M, W.s0, W.s1, tile);
   } else if constexpr (MODE == RM_FWD1) {
     const float* src = X.in;
-    load_tw(tw, M.twx, nx);
-    for (int it = threadIdx.x; it < tot; it += B) {
-      const int j = fdiv(it, nx, rnx), x = it - j * nx;
-      pcomp(bufA, j, x, nx) = src[size_t(y0 + j) * nx + x];
+    TwRegs TW;
+    float v[kMaxPer];
+    fetch_tw(TW, M.twx, nx);
+    FOR_K_LD {
+      const int it = min(int(threadIdx.x) + k * B, tot - 1);
+      {
+        const int j = fdiv(it, nx, rnx), x = it - j * nx;
+        v[k] = src[mul24(y0 + j, nx) + x];
+      }
     }
+    FOR_K {
+      const int it = threadIdx.x + k * B;
+      if (it < tot) {
+        const int j = fdiv(it, nx, rnx), x = it - j * nx;
+        pcomp(bufA, j, x, nx) = v[k];
+      }
+    }
+    put_tw(TW, tw, nx);
     __syncthreads();
-    float2* r = fft_any(bufA, bufB, rt / 2, nx, LS, M.radx, M.nstx, tw);
+    float2* r = fft_any<false>(bufA, bufB, rt / 2, nx, LS, M.radx, M.nstx, tw);
     store_rowpair_spectra(r, M, W.s0, tile);
   } else if constexpr (MODE == RM_INV1) {
-    load_rowpair_lines(bufA, M, W.s0, tile);
-    load_tw(tw, M.twx, nx);
+    RowPairRegs S0;
+    TwRegs TW;
+    fetch_rowpair(S0, M, W.s0, tile);
+    fetch_tw(TW, M.twx, nx);
+    put_rowpair(S0, bufA, M);
+    put_tw(TW, tw, nx);
     __syncthreads();
-    float2* r = fft_any(bufA, bufB, rt / 2, nx, LS, M.radx, M.nstx, tw);
+    float2* r = fft_any<false>(bufA, bufB, rt / 2, nx, LS, M.radx, M.nstx, tw);
     float* dst = X.out;
     for (int it = threadIdx.x; it < tot; it += B) {
       const int j = fdiv(it, nx, rnx), x = it - j * nx;
-      dst[size_t(y0 + j) * nx + x] = rowpair_val(r, j, x, nx);
+      dst[mul24(y0 + j, nx) + x] = rowpair_val(r, j, x, nx);
     }
   }
 }
@@ -837,7 +1022,7 @@ __device__ constexpr int kColIn[kColModes] = {1, 2, 2, 2, 2, 1};
 __device__ constexpr int kColOut[kColModes] = {2, 2, 2, 2, 1, 1};
 
 template <bool U, int CM>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kMaxThreads)
 col_kernel(const Launch L, int ntile, int chunk, int mcode_arg, int n) {
   constexpr int nin = kColIn[CM], nout = kColOut[CM];
   const int mcode = CM == CM_APPLY ? mcode_arg : kColCode[CM];
@@ -847,7 +1032,7 @@ col_kernel(const Launch L, int ntile, int chunk, int mcode_arg, int n) {
   const Medium& M = medium_of<U>(L, item);
   const Work W = U ? shift_work(L.w0, item * L.wstride) : L.items[item].w;
   if (n > M.nt - 2) return;
-  const int ny = M.ny, nxh = M.nxh, ct = M.ct, ls = col_lstride(ny, ct);
+  const int ny = M.ny, nxh = M.nxh, ct = M.ct, ls = col_lstride(ny);
   const int c0 = tile * ct;
   const int B = blockDim.x;
   const int nsl = 2;
@@ -870,22 +1055,32 @@ col_kernel(const Launch L, int ntile, int chunk, int mcode_arg, int n) {
   // load phase: the tile (transposed into lines), twiddles, multiplier values
   // memory order: field, tile row ty, element (iy, c) of the rt x ct tile
   const float rny = 1.0f / static_cast<float>(ny);
-  const int rc = M.rt * ct, ntx = nxh / ct;
-  for (int it = threadIdx.x; it < nin * ct * ny; it += B) {
-    const int f = fdiv(it, ny * ct, rny / ct), rem = it - f * ny * ct;
-    const int ty = rem >> (M.lrt + M.lct), w = rem & (rc - 1);
-    const int ky = (ty << M.lrt) + (w >> M.lct), c = w & (ct - 1);
-    const float2* s = f ? W.s1 : W.s0;
-    bufA[(f * ct + c) * ls + ky] = s[(size_t(ty) * ntx + tile) * rc + w];
+  const int rc = M.rt * ct;
+  // (a tile holds nin*ct*ny <= nin*kMaxPer*B elements: all loads are issued
+  // into registers before the first LDS write)
+  constexpr int kIt = nin * kMaxPer;
+  const unsigned ncol = unsigned(ct) * ny, ntot = nin * ncol;     // elements per field / tile
+  const unsigned rowstep = unsigned(nxh) * M.rt, tbase = unsigned(tile) * rc;  // tile row ty at ty * rowstep
+  const int lsh = M.lrt + M.lct;
+  float2 tv[kIt];
+#pragma unroll
+  for (int k = 0; k < kIt; ++k) {
+    const unsigned it = threadIdx.x + k * B;
+    if (it < ntot) {
+      const bool f = it >= ncol;
+      const unsigned rem = f ? it - ncol : it;
+      tv[k] = (f ? W.s1 : W.s0)[mul24(rem >> lsh, rowstep) + tbase + (rem & (rc - 1))];
+    }
   }
-  load_tw(tw, M.twy, ny);
+  TwRegs TW;
+  fetch_tw(TW, M.twy, ny);
   const int tot = ct * ny;
   MultPre P[kMaxPer];
   FOR_K {
     const int it = threadIdx.x + k * B;
     if (it < tot) {
-      const int c = fdiv(it, ny, rny), ky = it - c * ny, kx = c0 + c;
-      const int t = ky * (nxh + 1) + kx;
+      const int c = ct == 1 ? 0 : fdiv(it, ny, rny), ky = it - c * ny, kx = c0 + c;
+      const unsigned t = mul24(ky, nxh + 1) + kx;
       MultPre& p = P[k];
       p.a = tabA[t];
       p.b = labs ? M.labs[t] : 0.f;
@@ -898,13 +1093,24 @@ col_kernel(const Launch L, int ntile, int chunk, int mcode_arg, int n) {
       }
     }
   }
+#pragma unroll
+  for (int k = 0; k < kIt; ++k) {
+    const unsigned it = threadIdx.x + k * B;
+    if (it < ntot) {
+      const bool f = it >= ncol;
+      const unsigned rem = f ? it - ncol : it, w = rem & (rc - 1);
+      const unsigned ky = ((rem >> lsh) << M.lrt) + (w >> M.lct), c = w & (ct - 1);
+      bufA[mul24((f ? ct : 0) + c, ls) + px(ky)] = tv[k];
+    }
+  }
+  put_tw(TW, tw, ny);
   __syncthreads();
-  float2* r = fft_any(bufA, bufB, nin * ct, ny, ls, M.rady, M.nsty, tw);
+  float2* r = fft_any<true>(bufA, bufB, nin * ct, ny, ls, M.rady, M.nsty, tw);
   float2* o = other(r, bufA, bufB);
   FOR_K {
     const int it = threadIdx.x + k * B;
     if (it < tot) {
-      const int c = fdiv(it, ny, rny), ky = it - c * ny;
+      const int c = ct == 1 ? 0 : fdiv(it, ny, rny), ky = it - c * ny;
       const int kx = c0 + c;
       const MultPre& p = P[k];
       // (loops over fields have compile-time bounds so the arrays stay in registers)
@@ -915,7 +1121,7 @@ col_kernel(const Launch L, int ntile, int chunk, int mcode_arg, int n) {
 #pragma unroll
         for (int f = 0; f < 2; ++f) {
           if (f < nin) {
-            const float2 z = r[(f * ct + c) * ls + ky], zm = cconj(r[(f * ct + c) * ls + km]);
+            const float2 z = r[mul24(f * ct + c, ls) + px(ky)], zm = cconj(r[mul24(f * ct + c, ls) + px(km)]);
             f0[f] = cscale(cadd(z, zm), 0.5f);
             fn[f] = mul_mi(cscale(csub(z, zm), 0.5f));
           } else {
@@ -935,13 +1141,13 @@ col_kernel(const Launch L, int ntile, int chunk, int mcode_arg, int n) {
               }
             }
             // W = G0 + i GN, stored conjugated for the inverse transform
-            o[(q * ct + c) * ls + ky] = cconj(make_float2(g0.x - gn.y, g0.y + gn.x));
+            o[mul24(q * ct + c, ls) + px(ky)] = cconj(make_float2(g0.x - gn.y, g0.y + gn.x));
           }
         }
       } else {
         float2 in[2];
 #pragma unroll
-        for (int f = 0; f < 2; ++f) in[f] = f < nin ? r[(f * ct + c) * ls + ky] : make_float2(0.f, 0.f);
+        for (int f = 0; f < 2; ++f) in[f] = f < nin ? r[mul24(f * ct + c, ls) + px(ky)] : make_float2(0.f, 0.f);
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
           if (q < nout) {
@@ -951,20 +1157,19 @@ col_kernel(const Launch L, int ntile, int chunk, int mcode_arg, int n) {
               const int code = (mcode >> (4 * (2 * q + f))) & 15;
               if (code) acc = cadd(acc, cmul(mult_of(code, p, false), in[f]));
             }
-            o[(q * ct + c) * ls + ky] = cconj(acc);
+            o[mul24(q * ct + c, ls) + px(ky)] = cconj(acc);
           }
         }
       }
     }
   }
   __syncthreads();
-  r = fft_any(o, other(o, bufA, bufB), nout * ct, ny, ls, M.rady, M.nsty, tw);
-  for (int it = threadIdx.x; it < nout * ct * ny; it += B) {
-    const int f = fdiv(it, ny * ct, rny / ct), rem = it - f * ny * ct;
-    const int ty = rem >> (M.lrt + M.lct), w = rem & (rc - 1);
-    const int ky = (ty << M.lrt) + (w >> M.lct), c = w & (ct - 1);
-    float2* s = f ? W.s1 : W.s0;
-    s[(size_t(ty) * ntx + tile) * rc + w] = cconj(r[(f * ct + c) * ls + ky]);
+  r = fft_any<true>(o, other(o, bufA, bufB), nout * ct, ny, ls, M.rady, M.nsty, tw);
+  for (unsigned it = threadIdx.x; it < nout * ncol; it += B) {
+    const bool f = it >= ncol;
+    const unsigned rem = f ? it - ncol : it, w = rem & (rc - 1), ty = rem >> lsh;
+    const unsigned ky = (ty << M.lrt) + (w >> M.lct), c = w & (ct - 1);
+    (f ? W.s1 : W.s0)[mul24(ty, rowstep) + tbase + w] = cconj(r[mul24((f ? ct : 0) + c, ls) + px(ky)]);
   }
 }
 
@@ -976,6 +1181,20 @@ __global__ void combine_kernel(const Item* __restrict__ items, const IO* __restr
   const int total = M.nt * M.ns;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x)
     out[i] = part[2 * i] + part[2 * i + 1];
+}
+
+// Residual samples in sensor-tap order, rtap[m][e] = r[m][s(e)] for the 2 ns
+// taps e (the adjoint row passes read one contiguous run per tile).  Written
+// into the vector's sensor-partial buffer, which the adjoint does not use.
+__global__ void tap_order_kernel(const Item* __restrict__ items, const IO* __restrict__ io) {
+  const Medium& M = items[blockIdx.y].m;
+  float* dst = items[blockIdx.y].w.part;
+  const float* r = io[blockIdx.y].in;
+  const int ntap = 2 * M.ns, total = M.nt * ntap;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+    const int m = i / ntap, e = i - m * ntap;
+    dst[i] = r[unsigned(m) * unsigned(M.ns) + M.taps[e].s];
+  }
 }
 
 // ---------------------------------------------------------------- reductions
@@ -1072,11 +1291,49 @@ hipError_t launch_col(int cm, int mcode, const Launch& L, bool uniform, int ntil
   }
 }
 
+// Let every row / column pass kernel use up to `bytes` of dynamic LDS.
+template <int MODE>
+static hipError_t allow_row(size_t bytes) {
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&row_kernel<MODE, true>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&row_kernel<MODE, false>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
+}
+template <int CM>
+static hipError_t allow_col(size_t bytes) {
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&col_kernel<true, CM>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&col_kernel<false, CM>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
+}
+
+hipError_t kernels_allow_lds(size_t bytes) {
+  const hipError_t es[] = {allow_row<RM_F1>(bytes),      allow_row<RM_F2>(bytes),     allow_row<RM_F2L>(bytes),
+                           allow_row<RM_F3>(bytes),      allow_row<RM_A1>(bytes),     allow_row<RM_A1L>(bytes),
+                           allow_row<RM_A2>(bytes),      allow_row<RM_A3>(bytes),     allow_row<RM_FWD1>(bytes),
+                           allow_row<RM_INV1>(bytes),    allow_col<CM_GRADP1>(bytes), allow_col<CM_GRADM2>(bytes),
+                           allow_col<CM_FRAC>(bytes),    allow_col<CM_GRADP2>(bytes), allow_col<CM_DIVM>(bytes),
+                           allow_col<CM_APPLY>(bytes)};
+  for (hipError_t e : es)
+    if (e != hipSuccess) return e;
+  return hipSuccess;
+}
+
 hipError_t launch_combine(const Item* items, const IO* io, int nitems, int max_count, hipStream_t st) {
   int bx = (max_count + kBlock - 1) / kBlock;
   if (bx > 1024) bx = 1024;
   if (bx < 1) bx = 1;
   hipLaunchKernelGGL(combine_kernel, dim3(bx, nitems), dim3(kBlock), 0, st, items, io);
+  return hipGetLastError();
+}
+
+hipError_t launch_tap_order(const Item* items, const IO* io, int nitems, int max_count, hipStream_t st) {
+  int bx = (max_count + kBlock - 1) / kBlock;
+  if (bx > 1024) bx = 1024;
+  if (bx < 1) bx = 1;
+  hipLaunchKernelGGL(tap_order_kernel, dim3(bx, nitems), dim3(kBlock), 0, st, items, io);
   return hipGetLastError();
 }
 

@@ -46,7 +46,6 @@ qpat_status fail(qpat_status s, const std::string& msg) {
 
 constexpr int kMaxN = 1024;
 constexpr int kMinN = 8;
-constexpr size_t kMaxLds = 65536;
 
 // n = 2^a or 3 * 2^a: radix plan with radices up to `maxr` (8 or 4), 4 bits
 // per stage, first stage lowest; the radix-3 stage comes last so that the
@@ -102,7 +101,7 @@ int ilog2(int v) {
   return l;
 }
 
-bool threads_ok(int t) { return t == 64 || t == 128 || t == 256; }
+bool threads_ok(int t) { return t == 64 || t == 128 || t == 256 || t == 512; }
 
 // A row tile of rt rows (rt even, dividing ny) fits the LDS limit and leaves
 // at most kMaxPer pointwise elements per thread.
@@ -333,6 +332,7 @@ hipError_t seq_forward(Exec& E, int n_last, hipStream_t st) {
 
 // The reverse time loop of the adjoint (transposes of the forward passes).
 hipError_t seq_adjoint(Exec& E, hipStream_t st) {
+  LCHK(launch_tap_order(E.d_items, E.d_io, int(E.items.size()), 2 * E.max_data, st));
   for (int n = E.max_nt - 2; n >= -1; --n) {
     if (E.lossy) {
       LCHK(row(E, RM_A1, n, 0, st));
@@ -426,6 +426,8 @@ qpat_status validate(const qpat_params* p) {
   if (!finite_pos(p->dx) || !finite_pos(p->dy) || !finite_pos(p->dt))
     return fail(QPAT_E_INVALID, "dx, dy, dt must be finite and > 0");
   if (p->nt < 1) return fail(QPAT_E_INVALID, "nt must be >= 1");
+  if (int64_t(p->nt) * std::max(p->ns, 0) >= (int64_t(1) << 30))
+    return fail(QPAT_E_UNSUPPORTED, "nt * ns must be below 2^30 (32-bit sample indices)");
   if (!finite_pos(p->c_ref)) return fail(QPAT_E_INVALID, "c_ref must be finite and > 0");
   if (p->pml_size < 0 || 2 * p->pml_size >= std::min(p->nx, p->ny))
     return fail(QPAT_E_INVALID, "pml_size must be in [0, min(nx, ny)/2)");
@@ -574,11 +576,25 @@ qpat_status plan_build(qpat_plan P, const double* c0, const double* rho0) {
       ldis[t] = (K == 0.0 || !lossy) ? 0.f : float(std::pow(K, p.y - 1.0) * inv);
       labs[t] = (K == 0.0 || !lossy) ? 0.f : float(std::pow(K, p.y - 2.0) * inv);
     }
+  // FFT twiddles W_{Ns R}^{k r} per Stockham stage (radix R, Ns = product of
+  // the earlier radices), stored as [stage][r - 1][k]; the stage blocks
+  // telescope to n - R0 entries.
   auto twid = [](int n) {
-    std::vector<float2> t(n);
-    for (int k = 0; k < n; ++k) {
-      const double a = -2.0 * M_PI * k / n;
-      t[k] = make_float2(float(std::cos(a)), float(std::sin(a)));
+    uint32_t rad = 0;
+    int nst = 0;
+    radix_plan(n, &rad, &nst, 8);
+    std::vector<float2> t(n, make_float2(0.f, 0.f));
+    const int r0 = int(rad & 15);
+    int ns = 1;
+    for (int st = 0; st < nst; ++st) {
+      const int R = int((rad >> (4 * st)) & 15);
+      if (st > 0)
+        for (int r = 1; r < R; ++r)
+          for (int k = 0; k < ns; ++k) {
+            const double a = -2.0 * M_PI * double(k) * double(r) / double(ns * R);
+            t[size_t(ns - r0 + (r - 1) * ns + k)] = make_float2(float(std::cos(a)), float(std::sin(a)));
+          }
+      ns *= R;
     }
     return t;
   };
@@ -588,7 +604,11 @@ qpat_status plan_build(qpat_plan P, const double* c0, const double* rho0) {
   build_taps(p, taps, toff);
   if (taps.empty()) taps.push_back(Tap{});
 
-  // ---- upload
+  // ---- upload (host checks are done; from here on a device is needed)
+  {
+    const hipError_t e = kernels_allow_lds(kMaxLds);
+    if (e != hipSuccess) return fail(QPAT_E_HIP, std::string("LDS attribute: ") + hipGetErrorString(e));
+  }
   Carver cv;
   const size_t o_c2 = cv.take<float>(N), o_c2eta = cv.take<float>(N), o_c2tau = cv.take<float>(N);
   const size_t o_r0 = cv.take<float>(N), o_bx = cv.take<float>(N), o_by = cv.take<float>(N);
@@ -819,11 +839,11 @@ void tune_store(const std::string& key, int rt, int ct, int rthr, int cthr) {
 
 qpat_status set_tiles(qpat_plan P, int rt, int ct, int rthr, int cthr) {
   if (!row_tile_ok(P->prm.nx, P->prm.ny, rt, rthr))
-    return fail(QPAT_E_INVALID, "row tile: rows must be an even power of two dividing ny, threads 64/128/256, "
+    return fail(QPAT_E_INVALID, "row tile: rows must be an even power of two dividing ny, threads 64/128/256/512, "
                                 "rows*nx <= 8*threads, within the LDS limit");
   if (!col_tile_ok(P->prm.nx / 2, P->prm.ny, ct, cthr))
     return fail(QPAT_E_INVALID, "column tile: columns must be a power of two dividing nx/2, threads "
-                                "64/128/256, columns*ny <= 8*threads, within the LDS limit");
+                                "64/128/256/512, columns*ny <= 8*threads, within the LDS limit");
   if (rt != P->rt || ct != P->ct || rthr != P->rthr || cthr != P->cthr) {
     P->rt = P->med.rt = rt;
     P->ct = P->med.ct = ct;
@@ -1064,7 +1084,7 @@ qpat_status qpat_tune(qpat_plan P, int32_t batch, qpat_stream stream) {
   float best = INFINITY;
   // row shapes first (column shape fixed), then column shapes with the best row shape
   for (int r = 2; r <= 32; r *= 2)
-    for (int h = 64; h <= 256; h *= 2) {
+    for (int h = 64; h <= kMaxThreads; h *= 2) {
       if (!row_tile_ok(nx, ny, r, h)) continue;
       STCHK(set_tiles(P, r, bct, h, bch));
       float ms;
@@ -1077,7 +1097,7 @@ qpat_status qpat_tune(qpat_plan P, int32_t batch, qpat_stream stream) {
     }
   best = INFINITY;
   for (int c = 1; c <= 32; c *= 2)
-    for (int h = 64; h <= 256; h *= 2) {
+    for (int h = 64; h <= kMaxThreads; h *= 2) {
       if (!col_tile_ok(nx / 2, ny, c, h)) continue;
       STCHK(set_tiles(P, brt, c, brh, h));
       float ms;

@@ -9,7 +9,9 @@
 
 namespace qpat {
 
-constexpr int kBlock = 256;   // maximum threads per block of a pass
+constexpr int kBlock = 256;   // threads per block of the helper kernels (default for the passes)
+constexpr int kMaxThreads = 512;  // maximum threads per block of a row / column pass
+constexpr size_t kMaxLds = 163840;  // gfx950: LDS bytes available to one work-group
 constexpr int kMaxPer = 8;    // pointwise elements per thread held in registers
 constexpr int kTapCap = 64;   // sensor taps of one row tile staged in LDS
 constexpr int kXcds = 8;      // MI355X: 8 XCDs, work-groups dispatched round-robin
@@ -47,7 +49,7 @@ struct Work {
   float *f0, *f1, *f2, *f3;   // forward: v_x v_y rho_x rho_y;  adjoint: their adjoints
   float* q;                   // forward: p snapshot (checkpoints); adjoint: q = c^2 p*
   float2 *s0, *s1;            // half spectra, ny x nx/2 in rt x ct tiles (DC / Nyquist packed in column 0)
-  float* part;                // forward sensor partials [nt][ns][2]
+  float* part;                // forward: sensor partials [nt][ns][2]; adjoint: residual in tap order [nt][2 ns]
 };
 
 // Per-call input / output pointers of one vector.
@@ -113,14 +115,18 @@ hipError_t launch_col(int cm, int mcode, const Launch& L, bool uniform, int ntil
                       int threads, size_t lds, int n, hipStream_t st);
 hipError_t launch_combine(const Item* items, const IO* io, int nitems, int max_count,
                           hipStream_t st);
+hipError_t kernels_allow_lds(size_t bytes);
+hipError_t launch_tap_order(const Item* items, const IO* io, int nitems, int max_count, hipStream_t st);
 hipError_t launch_dot(const float* a, const float* b, int64_t n, double* partial, int nblk,
                       double* out, hipStream_t st);
 
-// LDS line strides: row lines are unpadded; column lines get one pad element
-// when a tile holds several columns (their transposed loads would otherwise
-// hit one LDS bank).
-__host__ __device__ inline int lstride(int n) { return n; }
-__host__ __device__ inline int col_lstride(int ny, int ct) { return ny + (ct > 1 ? 1 : 0); }
+// LDS line layout: element e of a line sits at px(e) = e + e/8.  The pad slot
+// after every 8 elements spreads the strided writes of the early Stockham
+// stages over the banks.  Column lines get one more slot (the transposed
+// loads of a multi-column tile would otherwise hit one bank).
+__host__ __device__ constexpr int px(int e) { return e + (e >> 3); }
+__host__ __device__ constexpr int lstride(int n) { return n + (n >> 3); }
+__host__ __device__ constexpr int col_lstride(int ny) { return lstride(ny) + 1; }
 
 // LDS bytes of one block of each pass: ping-pong line buffers, the twiddle
 // table, and (rows) the staged sensor taps.
@@ -128,7 +134,7 @@ inline size_t row_lds_bytes(int nx, int rt) {
   return size_t(2 * rt * lstride(nx) + nx) * sizeof(float2) + kTapCap * (sizeof(Tap) + sizeof(float));
 }
 inline size_t col_lds_bytes(int ny, int ct) {
-  return (size_t(2) * 2 * ct * col_lstride(ny, ct) + ny) * sizeof(float2);
+  return (size_t(2) * 2 * ct * col_lstride(ny) + ny) * sizeof(float2);
 }
 
 }  // namespace qpat

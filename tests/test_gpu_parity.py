@@ -182,10 +182,28 @@ def test_tiles_do_not_change_results(q):
     plan = q.Plan(prm, c0, rho0)
     base = N(plan.forward(T(p0)))
     # the per-line arithmetic does not depend on the launch shape
-    for shape in [(2, 1, 64, 64), (4, 4, 128, 256), (16, 8, 256, 128), (2, 2, 256, 64)]:
+    for shape in [(2, 1, 64, 64), (4, 4, 128, 256), (16, 8, 256, 128), (2, 2, 256, 64), (2, 1, 512, 512),
+                  (4, 4, 512, 256)]:
         plan.set_tiles(*shape)
         assert plan.tiles() == shape
         assert np.array_equal(N(plan.forward(T(p0))), base)
+
+
+def test_large_lds_tiles_do_not_change_results(q):
+    """1024-point lines: tiles whose LDS exceeds 64 KB (up to the 160 KB of a
+    gfx950 work-group) and 512-thread blocks give the same bits."""
+    prm, c0, rho0, p0 = problem(1024, 1024, 12, ns=64)
+    plan = q.Plan(prm, c0, rho0)
+    plan.set_tiles(2, 1, 256, 256)
+    x = T(p0)
+    d0 = N(plan.forward(x))
+    r = T(qi.gaussian_field((12, 64), 7))
+    g0 = N(plan.adjoint(r))
+    for shape in [(4, 2, 512, 256), (2, 2, 256, 256), (4, 1, 512, 128)]:
+        plan.set_tiles(*shape)
+        assert plan.tiles() == shape
+        assert np.array_equal(N(plan.forward(x)), d0)
+        assert np.array_equal(N(plan.adjoint(r)), g0)
 
 
 def test_graph_mode_replays_match(q):
