@@ -192,23 +192,38 @@ __host__ __device__ constexpr bool stage_folds(int R, int NS, int NB) {
          (NS % 8 == 0 || (R != 3 && 8 % NS == 0 && (NS == 1 ? 8 % R == 0 : (NS * R) % 8 == 0)));
 }
 
-template <int R, int NS, int NB, int OFF>
-__device__ __forceinline__ void stockham_c(const float2* src, float2* dst, unsigned j, const float2* tw) {
-  static_assert(stage_folds(R, NS, NB), "stage offsets do not fold");
-  float2 v[R];
+// The three parts of a compile-time stage for butterfly j: gather its inputs
+// from an LDS line, twiddle and transform in registers, scatter its outputs.
+template <int R, int NB>
+__device__ __forceinline__ void stage_load(float2* v, const float2* src, unsigned j) {
   const float2* s = src + px(int(j));
 #pragma unroll
   for (int r = 0; r < R; ++r) v[r] = s[pxd(r * NB)];
-  const unsigned k = j & (NS - 1);
+}
+template <int R, int NS, int OFF>
+__device__ __forceinline__ void stage_regs(float2* v, unsigned j, const float2* tw) {
   if constexpr (NS > 1) {
-    const float2* t = tw + OFF + k;
+    const float2* t = tw + OFF + (j & (NS - 1));
 #pragma unroll
     for (int r = 1; r < R; ++r) v[r] = cmul(v[r], t[(r - 1) * NS]);
   }
   bfly<R>(v);
+}
+template <int R, int NS>
+__device__ __forceinline__ void stage_store(const float2* v, float2* dst, unsigned j) {
+  const unsigned k = j & (NS - 1);
   float2* d = dst + px(int((j - k) * R + k));
 #pragma unroll
   for (int r = 0; r < R; ++r) d[pxd(r * NS)] = v[r];
+}
+
+template <int R, int NS, int NB, int OFF>
+__device__ __forceinline__ void stockham_c(const float2* src, float2* dst, unsigned j, const float2* tw) {
+  static_assert(stage_folds(R, NS, NB), "stage offsets do not fold");
+  float2 v[R];
+  stage_load<R, NB>(v, src, j);
+  stage_regs<R, NS, OFF>(v, j, tw);
+  stage_store<R, NS>(v, dst, j);
 }
 
 // LS: line stride (a compile-time constant, so line offsets fold too).
@@ -225,6 +240,33 @@ __device__ __forceinline__ float2* fft_c(float2* a, float2* b, int nlines, const
     }
     __syncthreads();
     return fft_c<N, LS, S + 1, NS * R>(b, a, nlines, tw);
+  }
+}
+
+// Radix of stage s of the compile-time plan of length N, or of that plan in
+// reverse order (REV).  A power-of-two plan reversed still has power-of-two
+// Ns in every stage; its per-stage twiddles form their own table.
+template <int N, bool REV>
+__host__ __device__ constexpr int radix_of(int s) {
+  return REV ? plan_radix(N, plan_nst(N) - 1 - s) : plan_radix(N, s);
+}
+
+// Stages S .. S1-1 of the plan (direction REV) on `nlines` LDS lines of
+// stride LS, ping-ponging from a; NS = product of the radices before S.
+// Returns the buffer holding the result; ends synchronised.
+template <int N, bool REV, int LS, int S, int S1, int NS>
+__device__ __forceinline__ float2* fft_stages(float2* a, float2* b, int nlines, const float2* tw) {
+  if constexpr (S == S1) {
+    return a;
+  } else {
+    constexpr int R = radix_of<N, REV>(S), NB = N / R, OFF = NS - radix_of<N, REV>(0);
+    const unsigned total = unsigned(nlines) * NB;
+    for (unsigned it = threadIdx.x; it < total; it += blockDim.x) {
+      const unsigned line = it / NB, j = it % NB;
+      stockham_c<R, NS, NB, OFF>(a + line * LS, b + line * LS, j, tw);
+    }
+    __syncthreads();
+    return fft_stages<N, REV, LS, S + 1, S1, NS * R>(b, a, nlines, tw);
   }
 }
 
@@ -1021,17 +1063,11 @@ __device__ constexpr int kColCode[kColModes] = {
 __device__ constexpr int kColIn[kColModes] = {1, 2, 2, 2, 2, 1};
 __device__ constexpr int kColOut[kColModes] = {2, 2, 2, 2, 1, 1};
 
-template <bool U, int CM>
-__global__ void __launch_bounds__(kMaxThreads)
-col_kernel(const Launch L, int ntile, int chunk, int mcode_arg, int n) {
+// Column pass for any supported line length (runtime or compile-time FFT
+// plan): the tile goes through LDS between every phase.
+template <int CM>
+__device__ __forceinline__ void col_generic(const Medium& M, const Work& W, int tile, int mcode, float2* lds) {
   constexpr int nin = kColIn[CM], nout = kColOut[CM];
-  const int mcode = CM == CM_APPLY ? mcode_arg : kColCode[CM];
-  extern __shared__ float2 lds[];
-  int item, tile;
-  if (!locate<U>(L, ntile, chunk, item, tile)) return;
-  const Medium& M = medium_of<U>(L, item);
-  const Work W = U ? shift_work(L.w0, item * L.wstride) : L.items[item].w;
-  if (n > M.nt - 2) return;
   const int ny = M.ny, nxh = M.nxh, ct = M.ct, ls = col_lstride(ny);
   const int c0 = tile * ct;
   const int B = blockDim.x;
@@ -1171,6 +1207,285 @@ col_kernel(const Launch L, int ntile, int chunk, int mcode_arg, int n) {
     const unsigned ky = (ty << M.lrt) + (w >> M.lct), c = w & (ct - 1);
     (f ? W.s1 : W.s0)[mul24(ty, rowstep) + tbase + w] = cconj(r[mul24((f ? ct : 0) + c, ls) + px(ky)]);
   }
+}
+
+// Value of one multiplier code applied to z at (ky, kx): a = kappa (or Y_dis),
+// b = Y_abs, sx / sy the 1-D staggered symbols at kx / ky.
+__device__ __forceinline__ float2 mult_apply(int code, float a, float b, float2 sx, float2 sy, float2 z) {
+  switch (code) {
+    case MC_DXP:
+    case MC_DXM: return cmul(cscale(sx, a), z);
+    case MC_DYP:
+    case MC_DYM: return cmul(cscale(sy, a), z);
+    case MC_LDIS: return cscale(z, a);
+    case MC_LABS: return cscale(z, b);
+    default: return make_float2(0.f, 0.f);
+  }
+}
+
+// Multiply phase through LDS for the first `ncols` columns of the tile
+// (including the packed DC / Nyquist column, whose two real columns are
+// separated with the mirror element ny - ky): r holds the forward spectra, o
+// receives the conjugated products.  Loads its multiplier values itself.
+template <int CM>
+__device__ __forceinline__ void col_mult_lds(const Medium& M, int tile, int mcode, int ls, int ncols,
+                                             const float2* r, float2* o) {
+  constexpr int nin = kColIn[CM], nout = kColOut[CM];
+  const int ny = M.ny, nxh = M.nxh, ct = M.ct, c0 = tile * ct, B = blockDim.x;
+  int xcode = 0, ycode = 0;
+  bool frac = false, labs = false;
+  for (int e = 0; e < 4; ++e) {
+    const int c = (mcode >> (4 * e)) & 15;
+    if (c == MC_DXP || c == MC_DXM) xcode = c;
+    if (c == MC_DYP || c == MC_DYM) ycode = c;
+    if (c == MC_LDIS) frac = true;
+    if (c == MC_LABS) { frac = true; labs = true; }
+  }
+  const float* tabA = frac ? M.ldis : M.kap;
+  const float2* symx = xcode == MC_DXP ? M.dxp : M.dxm;
+  const float2* symy = ycode == MC_DYP ? M.dyp : M.dym;
+  const float rny = 1.0f / static_cast<float>(ny);
+  for (int it = threadIdx.x; it < ncols * ny; it += B) {
+    const int c = ncols == 1 ? 0 : fdiv(it, ny, rny), ky = it - c * ny, kx = c0 + c;
+    const unsigned t = mul24(ky, nxh + 1) + kx;
+    const float a = tabA[t], b = labs ? M.labs[t] : 0.f;
+    const float2 sx = xcode ? symx[kx] : make_float2(0.f, 0.f), sy = ycode ? symy[ky] : make_float2(0.f, 0.f);
+    if (kx == 0) {
+      const float an = tabA[t + nxh], bn = labs ? M.labs[t + nxh] : 0.f;
+      const float2 sxn = xcode ? symx[nxh] : make_float2(0.f, 0.f);
+      const int km = ky ? ny - ky : 0;
+      float2 f0[2], fn[2];
+#pragma unroll
+      for (int f = 0; f < 2; ++f) {
+        if (f < nin) {
+          const float2 z = r[mul24(f * ct + c, ls) + px(ky)], zm = cconj(r[mul24(f * ct + c, ls) + px(km)]);
+          f0[f] = cscale(cadd(z, zm), 0.5f);
+          fn[f] = mul_mi(cscale(csub(z, zm), 0.5f));
+        } else {
+          f0[f] = fn[f] = make_float2(0.f, 0.f);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        if (q < nout) {
+          float2 g0 = make_float2(0.f, 0.f), gn = make_float2(0.f, 0.f);
+#pragma unroll
+          for (int f = 0; f < 2; ++f) {
+            const int code = (mcode >> (4 * (2 * q + f))) & 15;
+            if (code) {
+              g0 = cadd(g0, mult_apply(code, a, b, sx, sy, f0[f]));
+              gn = cadd(gn, mult_apply(code, an, bn, sxn, sy, fn[f]));
+            }
+          }
+          o[mul24(q * ct + c, ls) + px(ky)] = cconj(make_float2(g0.x - gn.y, g0.y + gn.x));
+        }
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        if (q < nout) {
+          float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+          for (int f = 0; f < 2; ++f) {
+            const int code = (mcode >> (4 * (2 * q + f))) & 15;
+            if (code && f < nin) acc = cadd(acc, mult_apply(code, a, b, sx, sy, r[mul24(f * ct + c, ls) + px(ky)]));
+          }
+          o[mul24(q * ct + c, ls) + px(ky)] = cconj(acc);
+        }
+      }
+    }
+  }
+}
+
+// Column pass for power-of-two line lengths N with a compile-time plan.  The
+// forward transform's first stage is computed straight from the global loads
+// and the inverse transform (the same plan in reverse order, so that its
+// first stage takes the butterfly outputs one thread already holds) writes
+// its last stage straight to global memory; in between, the forward
+// transform's last stage, the multipliers and the inverse transform's first
+// stage stay in registers.  The tile with the packed DC / Nyquist column
+// (tile 0) takes its multiply phase through LDS.
+template <int CM, int N>
+__device__ __forceinline__ void col_fused(const Medium& M, const Work& W, int tile, int mcode, float2* lds) {
+  constexpr int nin = kColIn[CM], nout = kColOut[CM];
+  constexpr int NST = plan_nst(N), LS = col_lstride(N);
+  constexpr int R1 = radix_of<N, false>(0), NB1 = N / R1;        // first forward = last inverse stage
+  constexpr int RS = radix_of<N, false>(NST - 1), NBS = N / RS;  // last forward = first inverse stage
+  static_assert(RS == radix_of<N, true>(0) && R1 == radix_of<N, true>(NST - 1), "plan reversal");
+  constexpr int OFFS = NBS - R1;  // twiddles of the last forward stage (Ns = NBS)
+  constexpr int OFFL = NB1 - RS;  // twiddles of the last inverse stage (Ns = NB1)
+  constexpr int kQ = nin * kMaxPer / R1;          // first-stage butterflies per thread (bound)
+  constexpr int kP = kMaxPer / RS > 0 ? kMaxPer / RS : 1;  // middle butterflies per thread (bound)
+  const int nxh = M.nxh, ct = M.ct, c0 = tile * ct, B = blockDim.x, lct = M.lct, lrt = M.lrt;
+  const int tid = threadIdx.x;
+  float2* bufA = lds;
+  float2* bufB = lds + 2 * ct * LS;
+  float2* tw = lds + 4 * ct * LS;  // forward-plan twiddles
+  float2* twr = tw + N;            // reversed-plan twiddles
+  int xcode = 0, ycode = 0;
+  bool frac = false, labs = false;
+  for (int e = 0; e < 4; ++e) {
+    const int c = (mcode >> (4 * e)) & 15;
+    if (c == MC_DXP || c == MC_DXM) xcode = c;
+    if (c == MC_DYP || c == MC_DYM) ycode = c;
+    if (c == MC_LDIS) frac = true;
+    if (c == MC_LABS) { frac = true; labs = true; }
+  }
+  const float* tabA = frac ? M.ldis : M.kap;
+  const float2* symx = xcode == MC_DXP ? M.dxp : M.dxm;
+  const float2* symy = ycode == MC_DYP ? M.dyp : M.dym;
+  // element ky of column c of the tile: (ky / rt) rowstep + tbase + (ky mod rt) ct + c;
+  // inputs r and r + 1 of a first-stage butterfly are step1 apart (rt divides NB1)
+  const unsigned rowstep = unsigned(nxh) * M.rt, tbase = unsigned(tile) * (M.rt * ct);
+  const unsigned step1 = mul24(NB1 >> lrt, rowstep);
+  auto elem = [&](unsigned j, unsigned c) { return mul24(j >> lrt, rowstep) + tbase + ((j & (M.rt - 1)) << lct) + c; };
+
+  // ---- load phase: first-stage inputs, both twiddle tables, middle multipliers
+  const unsigned nq = unsigned(nin * ct) * NB1;
+  float2 v1[kQ][R1];
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) {
+    if (i * B < int(nq)) {
+      const unsigned q = min(unsigned(tid + i * B), nq - 1);
+      const unsigned l = q / NB1, j = q % NB1, f = l >> lct, c = l & (ct - 1);
+      const float2* src = (f ? W.s1 : W.s0) + elem(j, c);
+#pragma unroll
+      for (int r = 0; r < R1; ++r) v1[i][r] = src[r * step1];
+    }
+  }
+  TwRegs TW, TWR;
+  fetch_tw(TW, M.twy, N);
+  fetch_tw(TWR, M.twyr, N);
+  const unsigned np = unsigned(ct) * NBS;
+  const unsigned tstep = unsigned(NBS) * (nxh + 1);
+  float ma[kP][RS], mb[kP][RS];
+  float2 msy[kP][RS], msx[kP];
+#pragma unroll
+  for (int i = 0; i < kP; ++i) {
+    if (i * B < int(np)) {
+      const unsigned pp = min(unsigned(tid + i * B), np - 1);
+      const unsigned c = pp / NBS, j = pp % NBS, kx = c0 + c;
+      const unsigned t0 = mul24(j, nxh + 1) + kx;
+      msx[i] = xcode ? symx[kx] : make_float2(0.f, 0.f);
+#pragma unroll
+      for (int r = 0; r < RS; ++r) {
+        ma[i][r] = tabA[t0 + r * tstep];
+        mb[i][r] = labs ? M.labs[t0 + r * tstep] : 0.f;
+        msy[i][r] = ycode ? symy[j + r * NBS] : make_float2(0.f, 0.f);
+      }
+    }
+  }
+  // ---- forward first stage from registers
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) {
+    const unsigned q = tid + i * B;
+    if (q < nq) {
+      const unsigned l = q / NB1, j = q % NB1;
+      stage_regs<R1, 1, 0>(v1[i], j, tw);
+      stage_store<R1, 1>(v1[i], bufA + l * LS, j);
+    }
+  }
+  put_tw(TW, tw, N);
+  put_tw(TWR, twr, N);
+  __syncthreads();
+  // ---- forward stages 2 .. NST-1
+  float2* r = fft_stages<N, false, LS, 1, NST - 1, R1>(bufA, bufB, nin * ct, tw);
+  float2* o = other(r, bufA, bufB);
+  // column 0 of tile 0 holds the packed DC / Nyquist column: its last forward
+  // stage goes to LDS (into its own lines of o) for the mirror-element
+  // multiply; every other column stays in registers.  A column takes the
+  // same path whatever the tile shape, so results do not depend on it.
+  const bool packed = c0 == 0;
+  if (packed) {
+    for (unsigned it = tid; it < unsigned(nin) * NBS; it += B) {
+      const unsigned f = it / NBS, j = it % NBS;
+      stockham_c<RS, NBS, NBS, OFFS>(r + f * ct * LS, o + f * ct * LS, j, tw);
+    }
+  }
+  {
+    // last forward stage, multipliers, first inverse stage: registers only
+#pragma unroll
+    for (int i = 0; i < kP; ++i) {
+      const unsigned pp = tid + i * B;
+      if (pp < np && !(packed && pp < NBS)) {
+        const unsigned c = pp / NBS, j = pp % NBS;
+        float2 z[nin][RS];
+#pragma unroll
+        for (int f = 0; f < nin; ++f) {
+          stage_load<RS, NBS>(z[f], r + (f * ct + c) * LS, j);
+          stage_regs<RS, NBS, OFFS>(z[f], j, tw);
+        }
+#pragma unroll
+        for (int q = 0; q < nout; ++q) {
+          float2 w[RS];
+#pragma unroll
+          for (int rr = 0; rr < RS; ++rr) {
+            float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+            for (int f = 0; f < nin; ++f) {
+              const int code = (mcode >> (4 * (2 * q + f))) & 15;
+              if (code) acc = cadd(acc, mult_apply(code, ma[i][rr], mb[i][rr], msx[i], msy[i][rr], z[f][rr]));
+            }
+            w[rr] = cconj(acc);
+          }
+          stage_regs<RS, 1, 0>(w, j, twr);
+          stage_store<RS, 1>(w, o + (q * ct + c) * LS, j);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (packed) {
+    // column 0 lines: o (f ct) -> products r (q ct) -> first inverse stage o (q ct)
+    col_mult_lds<CM>(M, tile, mcode, LS, 1, o, r);
+    __syncthreads();
+    for (unsigned it = tid; it < unsigned(nout) * NBS; it += B) {
+      const unsigned q = it / NBS, j = it % NBS;
+      stockham_c<RS, 1, NBS, 1 - RS>(r + q * ct * LS, o + q * ct * LS, j, twr);
+    }
+    __syncthreads();
+  }
+  // ---- inverse stages 2 .. NST-1, then the last one straight to global memory
+  float2* r2 = fft_stages<N, true, LS, 1, NST - 1, RS>(o, other(o, bufA, bufB), nout * ct, twr);
+  const unsigned nq2 = unsigned(nout * ct) * NB1;
+  for (unsigned q = tid; q < nq2; q += B) {
+    const unsigned l = q / NB1, j = q % NB1, f = l >> lct, c = l & (ct - 1);
+    float2 v[R1];
+    stage_load<R1, NB1>(v, r2 + l * LS, j);
+    stage_regs<R1, NB1, OFFL>(v, j, twr);
+    float2* dst = (f ? W.s1 : W.s0) + elem(j, c);
+#pragma unroll
+    for (int rr = 0; rr < R1; ++rr) dst[rr * step1] = cconj(v[rr]);
+  }
+}
+
+template <bool U, int CM>
+__global__ void __launch_bounds__(kMaxThreads)
+col_kernel(const Launch L, int ntile, int chunk, int mcode_arg, int n) {
+  const int mcode = CM == CM_APPLY ? mcode_arg : kColCode[CM];
+  extern __shared__ float2 lds[];
+  int item, tile;
+  if (!locate<U>(L, ntile, chunk, item, tile)) return;
+  const Medium& M = medium_of<U>(L, item);
+  const Work W = U ? shift_work(L.w0, item * L.wstride) : L.items[item].w;
+  if (n > M.nt - 2) return;  // this problem has finished (uneven batches)
+  // fused path: power-of-two lengths whose first-stage stride is a whole number of tile rows
+#define QPAT_COL_CASE(N)                                                 \
+  case N:                                                                \
+    if ((N / radix_of<N, false>(0)) % M.rt == 0) {                       \
+      col_fused<CM, N>(M, W, tile, mcode, lds);                          \
+      return;                                                            \
+    }                                                                    \
+    break;
+  switch (M.ny) {
+    QPAT_COL_CASE(128)
+    QPAT_COL_CASE(256)
+    QPAT_COL_CASE(512)
+    QPAT_COL_CASE(1024)
+    default: break;
+  }
+#undef QPAT_COL_CASE
+  col_generic<CM>(M, W, tile, mcode, lds);
 }
 
 // ---------------------------------------------------------------- sensor data

@@ -106,8 +106,11 @@ bool threads_ok(int t) { return t == 64 || t == 128 || t == 256 || t == 512; }
 // A row tile of rt rows (rt even, dividing ny) fits the LDS limit and leaves
 // at most kMaxPer pointwise elements per thread.
 bool row_tile_ok(int nx, int ny, int rt, int thr) {
+  // power-of-two columns of 128+ take the fused column pass, which needs the
+  // tile height to divide the first-stage stride (at least ny / 8)
+  const bool fused_cols = ny >= 128 && (ny & (ny - 1)) == 0;
   return rt >= 2 && (rt & (rt - 1)) == 0 && ny % rt == 0 && row_lds_bytes(nx, rt) <= kMaxLds &&
-         threads_ok(thr) && rt * nx <= kMaxPer * thr;
+         threads_ok(thr) && rt * nx <= kMaxPer * thr && (!fused_cols || rt <= ny / 8);
 }
 bool col_tile_ok(int nxh, int ny, int ct, int thr) {
   return ct >= 1 && (ct & (ct - 1)) == 0 && nxh % ct == 0 && col_lds_bytes(ny, ct) <= kMaxLds &&
@@ -579,15 +582,19 @@ qpat_status plan_build(qpat_plan P, const double* c0, const double* rho0) {
   // FFT twiddles W_{Ns R}^{k r} per Stockham stage (radix R, Ns = product of
   // the earlier radices), stored as [stage][r - 1][k]; the stage blocks
   // telescope to n - R0 entries.
-  auto twid = [](int n) {
+  // rev: the plan in reverse order (the inverse transforms of the fused
+  // column passes; power-of-two lengths only, Ns stays a power of two).
+  auto twid = [](int n, bool rev) {
     uint32_t rad = 0;
     int nst = 0;
     radix_plan(n, &rad, &nst, 8);
     std::vector<float2> t(n, make_float2(0.f, 0.f));
-    const int r0 = int(rad & 15);
+    if (rev && (n & (n - 1))) return t;
+    auto radix = [&](int st) { return int((rad >> (4 * (rev ? nst - 1 - st : st))) & 15); };
+    const int r0 = radix(0);
     int ns = 1;
     for (int st = 0; st < nst; ++st) {
-      const int R = int((rad >> (4 * st)) & 15);
+      const int R = radix(st);
       if (st > 0)
         for (int r = 1; r < R; ++r)
           for (int k = 0; k < ns; ++k) {
@@ -598,7 +605,7 @@ qpat_status plan_build(qpat_plan P, const double* c0, const double* rho0) {
     }
     return t;
   };
-  const std::vector<float2> twx = twid(nx), twy = twid(ny);
+  const std::vector<float2> twx = twid(nx, false), twy = twid(ny, false), twyr = twid(ny, true);
   std::vector<Tap> taps;
   std::vector<int> toff;
   build_taps(p, taps, toff);
@@ -617,7 +624,7 @@ qpat_status plan_build(qpat_plan P, const double* c0, const double* rho0) {
   const size_t o_dxp = cv.take<float2>(nxh + 1), o_dxm = cv.take<float2>(nxh + 1);
   const size_t o_dyp = cv.take<float2>(ny), o_dym = cv.take<float2>(ny);
   const size_t o_kap = cv.take<float>(nt2), o_ldis = cv.take<float>(nt2), o_labs = cv.take<float>(nt2);
-  const size_t o_twx = cv.take<float2>(nx), o_twy = cv.take<float2>(ny);
+  const size_t o_twx = cv.take<float2>(nx), o_twy = cv.take<float2>(ny), o_twyr = cv.take<float2>(ny);
   const size_t o_toff = cv.take<int>(toff.size()), o_taps = cv.take<Tap>(taps.size());
   const size_t total = cv.off;
   std::vector<char> host(total, 0);
@@ -641,6 +648,7 @@ qpat_status plan_build(qpat_plan P, const double* c0, const double* rho0) {
   put(o_labs, labs.data(), nt2 * 4);
   put(o_twx, twx.data(), nx * 8);
   put(o_twy, twy.data(), ny * 8);
+  put(o_twyr, twyr.data(), ny * 8);
   put(o_toff, toff.data(), toff.size() * 4);
   put(o_taps, taps.data(), taps.size() * sizeof(Tap));
   char* d = nullptr;
@@ -678,6 +686,7 @@ qpat_status plan_build(qpat_plan P, const double* c0, const double* rho0) {
   M.labs = (const float*)(d + o_labs);
   M.twx = (const float2*)(d + o_twx);
   M.twy = (const float2*)(d + o_twy);
+  M.twyr = (const float2*)(d + o_twyr);
   M.tap_off = (const int*)(d + o_toff);
   M.taps = (const Tap*)(d + o_taps);
   default_tiles(nx, ny, &P->rt, &P->ct, &P->rthr, &P->cthr);
@@ -839,8 +848,9 @@ void tune_store(const std::string& key, int rt, int ct, int rthr, int cthr) {
 
 qpat_status set_tiles(qpat_plan P, int rt, int ct, int rthr, int cthr) {
   if (!row_tile_ok(P->prm.nx, P->prm.ny, rt, rthr))
-    return fail(QPAT_E_INVALID, "row tile: rows must be an even power of two dividing ny, threads 64/128/256/512, "
-                                "rows*nx <= 8*threads, within the LDS limit");
+    return fail(QPAT_E_INVALID, "row tile: rows must be an even power of two dividing ny (at most ny/8 for "
+                                "power-of-two ny >= 128), threads 64/128/256/512, rows*nx <= 8*threads, within "
+                                "the LDS limit");
   if (!col_tile_ok(P->prm.nx / 2, P->prm.ny, ct, cthr))
     return fail(QPAT_E_INVALID, "column tile: columns must be a power of two dividing nx/2, threads "
                                 "64/128/256/512, columns*ny <= 8*threads, within the LDS limit");

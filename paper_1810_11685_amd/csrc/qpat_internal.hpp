@@ -39,7 +39,8 @@ struct Medium {
   const float2 *dxp, *dxm;                            // [nxh+1] i kx e^{+-i kx dx/2}
   const float2 *dyp, *dym;                            // [ny]
   const float *kap, *ldis, *labs;                     // [ny][nxh+1], divided by nx*ny
-  const float2 *twx, *twy;                            // twiddles e^{-2 pi i k / n}
+  const float2 *twx, *twy;                            // per-stage FFT twiddles [nx] / [ny]
+  const float2* twyr;                                 // the same for the reversed ny plan
   const int* tap_off;                                 // [ny+1] CSR offsets into taps
   const Tap* taps;
 };
@@ -129,12 +130,12 @@ __host__ __device__ constexpr int lstride(int n) { return n + (n >> 3); }
 __host__ __device__ constexpr int col_lstride(int ny) { return lstride(ny) + 1; }
 
 // LDS bytes of one block of each pass: ping-pong line buffers, the twiddle
-// table, and (rows) the staged sensor taps.
+// tables (columns: the plan and its reverse), and (rows) the staged sensor taps.
 inline size_t row_lds_bytes(int nx, int rt) {
   return size_t(2 * rt * lstride(nx) + nx) * sizeof(float2) + kTapCap * (sizeof(Tap) + sizeof(float));
 }
 inline size_t col_lds_bytes(int ny, int ct) {
-  return (size_t(2) * 2 * ct * col_lstride(ny) + ny) * sizeof(float2);
+  return (size_t(2) * 2 * ct * col_lstride(ny) + 2 * size_t(ny)) * sizeof(float2);
 }
 
 }  // namespace qpat
