@@ -122,6 +122,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched J^T J v comparisons")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch tiles")
     ap.add_argument("--graph", choices=["on", "off"], default="on")
+    ap.add_argument("--tiles", default=None,
+                    help="launch shape rows,cols,row_threads,col_threads of the headline plan (skips tuning)")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -146,7 +148,10 @@ def main():
     nx, ny, nt, ns = prm["nx"], prm["ny"], prm["nt"], len(prm["sensor_xy"])
     plan = q.Plan(prm, cfg["c0"], cfg["rho0"])
     tiles_default = plan.tiles()
-    if not args.no_tune:
+    if args.tiles:
+        plan.set_tiles(*[int(v) for v in args.tiles.split(",")])
+        log(f"tiles {plan.tiles()} (given)")
+    elif not args.no_tune:
         t = time.perf_counter()
         plan.tune(1)
         log(f"tuned tiles {plan.tiles()} (default {tiles_default}) in {time.perf_counter() - t:.1f} s")
@@ -212,10 +217,15 @@ def main():
         gp = g["params"]
         B = 8
         gplan = q.Plan(gp, g["c0"], g["rho0"])
-        if not args.no_tune:
+        tiles_1 = tiles_b = gplan.tiles()
+        if not args.no_tune:                      # each path gets the launch shape tuned for its batch
+            gplan.tune(1)
+            tiles_1 = gplan.tiles()
             gplan.tune(B)
+            tiles_b = gplan.tiles()
         vs = T(np.stack([qi.smooth_noise(1024, 1024, 8.0, 3000 + j) for j in range(B)]))
         with torch.cuda.stream(stream):
+            gplan.set_tiles(*tiles_1)
             gplan.set_graph(False)
             gplan.jtjv(vs[0])                     # warm-up (plain)
             sync()
@@ -225,6 +235,7 @@ def main():
             sync()
             t_plain = time.perf_counter() - t
             log(f"plain J^T J v x{B} (1024^2, Nt=4000): {t_plain:.2f} s")
+            gplan.set_tiles(*tiles_b)
             gplan.set_graph(args.graph == "on")
             gplan.jtjv(vs)                        # warm-up (batched; captures the graph)
             sync()
@@ -233,21 +244,59 @@ def main():
             sync()
             t_batch = time.perf_counter() - t
             log(f"batched J^T J v x{B}: {t_batch:.2f} s")
+            # per-pass bandwidth of the batched launches (in-sequence HIP-event timing)
+            bpass = {}
+            for pid, (name, kind) in enumerate(PASSES):
+                t_ms = gplan.time_pass(pid, batch=B, reps=5)
+                bpass[name] = {"kernel": kind, "ms": round(t_ms, 4),
+                               "GB_s": round(PASS_BYTES[pid] * 1024 * 1024 * B / (t_ms * 1e-3) / 1e9, 1)}
+            bdom = max(bpass, key=lambda k: bpass[k]["ms"])
+            bsum = sum(v["ms"] for v in bpass.values())
+            bavg = sum(PASS_BYTES.values()) * 1024 * 1024 * B / (bsum * 1e-3) / 1e9
+            log(f"batched passes: dominant {bdom} {bpass[bdom]['GB_s']:.0f} GB/s; "
+                f"iterate pair {bsum * 1e3:.0f} us = {bavg:.0f} GB/s algorithmic")
         pts = 2.0 * 1024 * 1024 * gp["nt"] * B
         out["batched"] = {"workload": "gn1024: J^T J v, 1024x1024, Nt=4000, 512 ring sensors, "
                                       "alpha0=0.5, y=1.3, 8 Krylov vectors",
                           "jtjv_per_s_plain": round(B / t_plain, 4), "jtjv_per_s_batched": round(B / t_batch, 4),
                           "speedup": round(t_plain / t_batch, 3),
                           "grid_point_steps_per_s_batched": round(pts / t_batch, 1),
-                          "tiles": list(gplan.tiles())}
+                          "tiles_plain": list(tiles_1), "tiles_batched": list(tiles_b),
+                          "passes": bpass,
+                          "roofline": {"bound": "hbm", "kernel": bdom, "achieved": bpass[bdom]["GB_s"],
+                                       "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                       "frac": round(bpass[bdom]["GB_s"] / HBM_PEAK_GBS, 4),
+                                       "iterate_pair_GB_s": round(bavg, 1),
+                                       "iterate_pair_frac": round(bavg / HBM_PEAK_GBS, 4)}}
         del gplan, vs
         torch.cuda.empty_cache()
 
         probs = qi.uneven_batch()
         plans = [q.Plan(p["params"], p["c0"], p["rho0"]) for p in probs]
         xs = [T(p["p0"]) for p in probs]
-        bat = q.Batch(plans)
         pts = sum(2.0 * p["params"]["nx"] * p["params"]["ny"] * p["params"]["nt"] for p in probs)
+        # launch shapes per grid size: tuned for one vector (plain) and for the
+        # number of problems of that size (batched)
+        # one shared launch shape for the mixed batch (a launch runs with the
+        # largest LDS and thread count of its items): tuned on the largest grid
+        # for the number of problems of that size, and applied to every plan
+        sizes = sorted({p["params"]["nx"] for p in probs})
+        shape_1, shape_b = {}, {}
+        for n in sizes:
+            group = [pl for pl, p in zip(plans, probs) if p["params"]["nx"] == n]
+            shape_1[n] = group[0].tiles()
+            if not args.no_tune:
+                group[0].tune(1)
+                shape_1[n] = group[0].tiles()
+        big = [pl for pl, p in zip(plans, probs) if p["params"]["nx"] == sizes[-1]]
+        shared = big[0].tiles()
+        if not args.no_tune:
+            big[0].tune(len(big))
+            shared = big[0].tiles()
+        for n in sizes:
+            shape_b[n] = shared
+        for pl, p in zip(plans, probs):
+            pl.set_tiles(*shape_1[p["params"]["nx"]])
         with torch.cuda.stream(stream):
             for pl, x in zip(plans, xs):          # warm-up
                 pl.jtjv(x)
@@ -257,6 +306,12 @@ def main():
                 pl.jtjv(x)
             sync()
             t_plain = time.perf_counter() - t
+            for pl, p in zip(plans, probs):
+                try:
+                    pl.set_tiles(*shape_b[p["params"]["nx"]])
+                except q.QpatError:               # not valid for this grid: keep its own
+                    shape_b[p["params"]["nx"]] = pl.tiles()
+            bat = q.Batch(plans)
             bat.set_graph(args.graph == "on")
             bat.jtjv(xs)
             sync()
@@ -270,7 +325,9 @@ def main():
                          "jtjv_per_s_plain": round(len(probs) / t_plain, 3),
                          "jtjv_per_s_batched": round(len(probs) / t_batch, 3),
                          "speedup": round(t_plain / t_batch, 3),
-                         "grid_point_steps_per_s_batched": round(pts / t_batch, 1)}
+                         "grid_point_steps_per_s_batched": round(pts / t_batch, 1),
+                         "tiles_plain": {str(n): list(shape_1[n]) for n in sizes},
+                         "tiles_batched": {str(n): list(shape_b[n]) for n in sizes}}
         del bat, plans, xs
         torch.cuda.empty_cache()
 

@@ -882,11 +882,16 @@ qpat_status time_forward(qpat_plan P, int batch, int steps, hipStream_t st, floa
   HIPCHK(hipEventCreate(&a));
   HIPCHK(hipEventCreate(&b));
   hipError_t e = seq_forward(*E, nl, st);  // warm-up
-  if (e == hipSuccess) e = hipEventRecord(a, st);
-  if (e == hipSuccess) e = seq_forward(*E, nl, st);
-  if (e == hipSuccess) e = hipEventRecord(b, st);
-  if (e == hipSuccess) e = hipEventSynchronize(b);
-  if (e == hipSuccess) e = hipEventElapsedTime(ms, a, b);
+  *ms = INFINITY;
+  for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {  // best of three: the candidates differ by a few %
+    float t = 0.f;
+    e = hipEventRecord(a, st);
+    if (e == hipSuccess) e = seq_forward(*E, nl, st);
+    if (e == hipSuccess) e = hipEventRecord(b, st);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
+    if (e == hipSuccess) *ms = std::min(*ms, t);
+  }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
   if (e != hipSuccess) return fail(QPAT_E_HIP, std::string("tune timing: ") + hipGetErrorString(e));
@@ -1089,7 +1094,7 @@ qpat_status qpat_tune(qpat_plan P, int32_t batch, qpat_stream stream) {
   if (tune_lookup(key, &rt, &ct, &rh, &ch) && row_tile_ok(nx, ny, rt, rh) && col_tile_ok(nx / 2, ny, ct, ch))
     return set_tiles(P, rt, ct, rh, ch);
   hipStream_t st = (hipStream_t)stream;
-  const int steps = 12;
+  const int steps = 16;
   int brt = P->rt, bct = P->ct, brh = P->rthr, bch = P->cthr;
   float best = INFINITY;
   // row shapes first (column shape fixed), then column shapes with the best row shape
