@@ -205,6 +205,40 @@ qpat_status qpat_batch_set_graph(qpat_batch batch, int32_t enable);
  * block partition reduced in a fixed order (wavefront shuffles, then LDS). */
 qpat_status qpat_dot(const float* a, const float* b, int64_t n, double* out, qpat_stream stream);
 
+/* ---- Lagged-diffusivity TV priorconditioner of the inexact-Newton driver
+ * (Section 5.2: the TV functional of eq tvm with D of eq dd, its gradient
+ * M[x] x of eqs jm, m, m1, and M_gamma = M + gamma I of eq pre), for fields on
+ * an nx x ny grid (row-major [ny][nx], device floats, caller-owned).  D takes
+ * the differences across the internal edges between horizontally and
+ * vertically adjacent nodes, every edge of length 1 (the grid's edges all have
+ * one length, which only rescales beta and gamma); C[x] = diag((|D x|^2 +
+ * beta)^(-1/2)).  A qpat_tv holds the edge weights C and the FP64 work space
+ * of its solver for up to `batch` fields; calls are asynchronous on `stream`
+ * unless they say otherwise, and one qpat_tv must not be used from two streams
+ * at once. */
+typedef struct qpat_tv_s* qpat_tv;
+/* nx, ny >= 2 with nx*ny <= 2^24; batch in [1, 64]. */
+qpat_status qpat_tv_create(int32_t nx, int32_t ny, int32_t batch, qpat_tv* out);
+void qpat_tv_destroy(qpat_tv tv);
+/* C from fields x [batch][ny][nx] (beta > 0): the lagged weights of eq m1. */
+qpat_status qpat_tv_set_weights(qpat_tv tv, const float* x, double beta, int32_t batch, qpat_stream stream);
+/* y = M_gamma x for [batch][ny][nx] fields with the current weights (gamma >= 0). */
+qpat_status qpat_tv_apply(qpat_tv tv, double gamma, const float* x, float* y, int32_t batch,
+                          qpat_stream stream);
+/* z = M_gamma^-1 r (gamma > 0), the preconditioner solve of Algorithm 4, per
+ * field: conjugate gradients in FP64 preconditioned by the diagonal of
+ * M_gamma, until ||r - M_gamma z|| <= tol ||r|| (0 < tol < 1) or max_iter
+ * iterations; *iters (may be NULL) receives the iterations run.  Synchronises
+ * the stream (the convergence test reads residual norms every 32 iterations). */
+qpat_status qpat_tv_solve(qpat_tv tv, double gamma, const float* r, float* z, int32_t batch, double tol,
+                          int32_t max_iter, int32_t* iters, qpat_stream stream);
+/* Smoothed TV value sum_l sqrt((D x)_l^2 + beta) per field into out[batch]
+ * (host doubles).  Synchronises the stream. */
+qpat_status qpat_tv_value(qpat_tv tv, const float* x, double beta, int32_t batch, double* out,
+                          qpat_stream stream);
+/* y = a x + b y over n device floats (the vector updates of Algorithm 4). */
+qpat_status qpat_axpby(int64_t n, float a, const float* x, float b, float* y, qpat_stream stream);
+
 /* Plan introspection: sizes and the device bytes the plan holds. */
 qpat_status qpat_plan_info(qpat_plan plan, int32_t* nx, int32_t* ny, int32_t* nt, int32_t* ns,
                            size_t* device_bytes);

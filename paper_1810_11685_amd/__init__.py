@@ -4,6 +4,8 @@ C ABI (include/qpat.h), with a thin torch binding."""
 from ._lib import EXPORTED, LIB_PATH, QpatError, lib
 from .ops import Batch, Plan, dot, make_params, validate
 from .autograd import AcousticForward, acoustic, replay_states
+from .recon import TV, axpby, ld_reconstruct
 
-__all__ = ["Plan", "Batch", "dot", "validate", "make_params", "acoustic", "AcousticForward",
+__all__ = ["Plan", "Batch", "dot", "validate", "make_params", "acoustic", "AcousticForward", "TV", "axpby",
+           "ld_reconstruct",
            "replay_states", "QpatError", "lib", "LIB_PATH", "EXPORTED"]

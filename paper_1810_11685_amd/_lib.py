@@ -61,6 +61,15 @@ _SIGS = {
     "qpat_batch_jtjv": (c_int32, [c_void_p, ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p), c_void_p]),
     "qpat_batch_set_graph": (c_int32, [c_void_p, c_int32]),
     "qpat_dot": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_void_p]),
+    "qpat_tv_create": (c_int32, [c_int32, c_int32, c_int32, ctypes.POINTER(c_void_p)]),
+    "qpat_tv_destroy": (None, [c_void_p]),
+    "qpat_tv_set_weights": (c_int32, [c_void_p, c_void_p, ctypes.c_double, c_int32, c_void_p]),
+    "qpat_tv_apply": (c_int32, [c_void_p, ctypes.c_double, c_void_p, c_void_p, c_int32, c_void_p]),
+    "qpat_tv_solve": (c_int32, [c_void_p, ctypes.c_double, c_void_p, c_void_p, c_int32, ctypes.c_double, c_int32,
+                                ctypes.POINTER(c_int32), c_void_p]),
+    "qpat_tv_value": (c_int32, [c_void_p, c_void_p, ctypes.c_double, c_int32, ctypes.POINTER(ctypes.c_double),
+                                c_void_p]),
+    "qpat_axpby": (c_int32, [c_int64, ctypes.c_float, c_void_p, ctypes.c_float, c_void_p, c_void_p]),
     "qpat_plan_info": (c_int32, [c_void_p, ctypes.POINTER(c_int32), ctypes.POINTER(c_int32),
                                  ctypes.POINTER(c_int32), ctypes.POINTER(c_int32), ctypes.POINTER(c_size_t)]),
     "qpat_status_string": (ctypes.c_char_p, [c_int32]),

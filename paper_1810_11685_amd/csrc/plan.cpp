@@ -29,6 +29,14 @@ qpat_status fail(qpat_status s, const std::string& msg) {
   g_err = msg;
   return s;
 }
+}  // namespace
+
+namespace qpat {
+// the error channel of qpat_last_error, for the other translation units
+qpat_status set_error(qpat_status s, const std::string& msg) { return fail(s, msg); }
+}  // namespace qpat
+
+namespace {
 
 #define HIPCHK(expr)                                                                    \
   do {                                                                                  \

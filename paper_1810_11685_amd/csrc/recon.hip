@@ -1,0 +1,307 @@
+// Lagged-diffusivity TV priorconditioner of the inexact-Newton driver
+// (Section 5.2: eqs tvm, dd, jm, m, m1, pre) and the vector update of its PCG
+// loop (Algorithm 4), for fields on the acoustic grid.
+//
+// D takes differences across the internal edges between horizontally and
+// vertically adjacent grid nodes (unit edge length); C[x] = diag((|D x|^2 +
+// beta)^(-1/2)); M_gamma = D^T C D + gamma I.  Edge weights are stored per
+// node: wh[j][i] for the edge (j, i)-(j, i+1), wv[j][i] for (j, i)-(j+1, i)
+// (zero past the last column / row).  M_gamma z = r is solved by conjugate
+// gradients in FP64 with the diagonal of M_gamma as preconditioner; the
+// scalars of every field stay in device memory, and each iteration is three
+// launches whose reductions are deterministic (fixed block partition, fixed
+// order; every block re-reduces the block partials itself).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "recon_internal.hpp"
+
+namespace qpat {
+
+namespace {
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+// Block sum of one value per thread (blockDim.x = kRedThreads); result in thread 0.
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  v = wave_sum_d(v);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < kRedThreads / 64; ++w) s += red[w];
+  __syncthreads();
+  return s;
+}
+
+// Sum of the kRedBlocks partials of field b, in a fixed order (every block
+// computes the same value).
+__device__ __forceinline__ double partial_total(const double* __restrict__ part, int b, double* red) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < kRedBlocks; i += blockDim.x) v += part[size_t(b) * kRedBlocks + i];
+  __shared__ double tot;
+  const double s = block_sum(v, red);
+  if (threadIdx.x == 0) tot = s;
+  __syncthreads();
+  return tot;
+}
+
+__global__ void __launch_bounds__(kRedThreads)
+tv_weights_kernel(const float* __restrict__ x, int nx, int ny, double beta, double* __restrict__ wh,
+                  double* __restrict__ wv) {
+  const int b = blockIdx.y;
+  const size_t n = size_t(nx) * ny, base = size_t(b) * n;
+  for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < n; k += size_t(gridDim.x) * blockDim.x) {
+    const int j = int(k / nx), i = int(k - size_t(j) * nx);
+    const double xc = x[base + k];
+    double h = 0.0, v = 0.0;
+    if (i + 1 < nx) {
+      const double g = xc - double(x[base + k + 1]);
+      h = 1.0 / sqrt(g * g + beta);
+    }
+    if (j + 1 < ny) {
+      const double g = xc - double(x[base + k + nx]);
+      v = 1.0 / sqrt(g * g + beta);
+    }
+    wh[base + k] = h;
+    wv[base + k] = v;
+  }
+}
+
+// (M_gamma u)_k for node k = (j, i) of field b.
+template <typename T>
+__device__ __forceinline__ double mgamma_at(const T* __restrict__ u, const double* __restrict__ wh,
+                                            const double* __restrict__ wv, size_t base, size_t k, int i, int j,
+                                            int nx, int ny, double gamma) {
+  const double uc = double(u[base + k]);
+  double y = gamma * uc;
+  if (i + 1 < nx) y += wh[base + k] * (uc - double(u[base + k + 1]));
+  if (i > 0) y += wh[base + k - 1] * (uc - double(u[base + k - 1]));
+  if (j + 1 < ny) y += wv[base + k] * (uc - double(u[base + k + nx]));
+  if (j > 0) y += wv[base + k - nx] * (uc - double(u[base + k - nx]));
+  return y;
+}
+
+__global__ void __launch_bounds__(kRedThreads)
+tv_apply_kernel(const float* __restrict__ x, float* __restrict__ y, const double* __restrict__ wh,
+                const double* __restrict__ wv, int nx, int ny, double gamma) {
+  const int b = blockIdx.y;
+  const size_t n = size_t(nx) * ny, base = size_t(b) * n;
+  for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < n; k += size_t(gridDim.x) * blockDim.x) {
+    const int j = int(k / nx), i = int(k - size_t(j) * nx);
+    y[base + k] = float(mgamma_at(x, wh, wv, base, k, i, j, nx, ny, gamma));
+  }
+}
+
+// smoothed TV value: block partials of sum_l sqrt((D x)_l^2 + beta)
+__global__ void __launch_bounds__(kRedThreads)
+tv_value_kernel(const float* __restrict__ x, int nx, int ny, double beta, double* __restrict__ part) {
+  __shared__ double red[kRedThreads / 64];
+  const int b = blockIdx.y;
+  const size_t n = size_t(nx) * ny, base = size_t(b) * n;
+  double acc = 0.0;
+  for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < n; k += size_t(gridDim.x) * blockDim.x) {
+    const int j = int(k / nx), i = int(k - size_t(j) * nx);
+    const double xc = x[base + k];
+    if (i + 1 < nx) {
+      const double g = xc - double(x[base + k + 1]);
+      acc += sqrt(g * g + beta);
+    }
+    if (j + 1 < ny) {
+      const double g = xc - double(x[base + k + nx]);
+      acc += sqrt(g * g + beta);
+    }
+  }
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) part[size_t(b) * kRedBlocks + blockIdx.x] = s;
+}
+
+// ---- conjugate gradients for M_gamma z = r, per field (FP64)
+// start: x = 0, r = rhs, dinv = 1 / diag(M_gamma), z = dinv r, p = z; partials of r.z and r.r
+__global__ void __launch_bounds__(kRedThreads)
+cg_start_kernel(const float* __restrict__ rhs, TvCg c, int nx, int ny, double gamma) {
+  __shared__ double red[kRedThreads / 64];
+  const int b = blockIdx.y;
+  const size_t n = size_t(nx) * ny, base = size_t(b) * n;
+  double rz = 0.0, rr = 0.0;
+  for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < n; k += size_t(gridDim.x) * blockDim.x) {
+    const int j = int(k / nx), i = int(k - size_t(j) * nx);
+    double d = gamma;
+    if (i + 1 < nx) d += c.wh[base + k];
+    if (i > 0) d += c.wh[base + k - 1];
+    if (j + 1 < ny) d += c.wv[base + k];
+    if (j > 0) d += c.wv[base + k - nx];
+    const double di = 1.0 / d, r = rhs[base + k], z = di * r;
+    c.dinv[base + k] = di;
+    c.x[base + k] = 0.0;
+    c.r[base + k] = r;
+    c.p[base + k] = z;
+    rz += r * z;
+    rr += r * r;
+  }
+  const double s1 = block_sum(rz, red), s2 = block_sum(rr, red);
+  if (threadIdx.x == 0) {
+    c.part_rz[size_t(b) * kRedBlocks + blockIdx.x] = s1;
+    c.part_rr[size_t(b) * kRedBlocks + blockIdx.x] = s2;
+  }
+}
+
+// totals of the start partials: rz[0][b], rr[b], bb[b] = r.r of the right-hand side
+__global__ void __launch_bounds__(kRedThreads) cg_start_total_kernel(TvCg c) {
+  __shared__ double red[kRedThreads / 64];
+  const int b = blockIdx.x;
+  const double rz = partial_total(c.part_rz, b, red);
+  const double rr = partial_total(c.part_rr, b, red);
+  if (threadIdx.x == 0) {
+    c.rz[b] = rz;
+    c.rr[b] = rr;
+    c.rr_next[b] = rr;
+    c.bb[b] = rr;
+  }
+}
+
+// q = M_gamma p; partials of p.q.  Block (0, 0) also publishes the r.r of the
+// previous iteration (nothing reads rr while this kernel runs).
+__global__ void __launch_bounds__(kRedThreads) cg_q_kernel(TvCg c, int nx, int ny, double gamma) {
+  __shared__ double red[kRedThreads / 64];
+  const int b = blockIdx.y;
+  if (blockIdx.x == 0 && blockIdx.y == 0)
+    for (int t = threadIdx.x; t < int(gridDim.y); t += blockDim.x) c.rr[t] = c.rr_next[t];
+  const size_t n = size_t(nx) * ny, base = size_t(b) * n;
+  double pq = 0.0;
+  for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < n; k += size_t(gridDim.x) * blockDim.x) {
+    const int j = int(k / nx), i = int(k - size_t(j) * nx);
+    const double q = mgamma_at(c.p, c.wh, c.wv, base, k, i, j, nx, ny, gamma);
+    c.q[base + k] = q;
+    pq += c.p[base + k] * q;
+  }
+  const double s = block_sum(pq, red);
+  if (threadIdx.x == 0) c.part_pq[size_t(b) * kRedBlocks + blockIdx.x] = s;
+}
+
+// alpha = r.z / p.q (0 once the field has converged: r.r <= tol^2 b.b);
+// x += alpha p; r -= alpha q; z = dinv r; partials of the new r.z and r.r.
+// rz[par] holds the current r.z, the new one goes to rz[1 - par] (cg_dir).
+__global__ void __launch_bounds__(kRedThreads)
+cg_update_kernel(TvCg c, int nx, int ny, int par, double tol2) {
+  __shared__ double red[kRedThreads / 64];
+  const int b = blockIdx.y, nb = gridDim.y;
+  const size_t n = size_t(nx) * ny, base = size_t(b) * n;
+  const double pq = partial_total(c.part_pq, b, red);
+  const double rz = c.rz[size_t(par) * nb + b];
+  const bool live = c.rr[b] > tol2 * c.bb[b] && pq > 0.0;
+  const double alpha = live ? rz / pq : 0.0;
+  double rzn = 0.0, rr = 0.0;
+  for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < n; k += size_t(gridDim.x) * blockDim.x) {
+    c.x[base + k] += alpha * c.p[base + k];
+    const double r = c.r[base + k] - alpha * c.q[base + k];
+    c.r[base + k] = r;
+    const double z = c.dinv[base + k] * r;
+    c.z[base + k] = z;
+    rzn += r * z;
+    rr += r * r;
+  }
+  const double s1 = block_sum(rzn, red), s2 = block_sum(rr, red);
+  if (threadIdx.x == 0) {
+    c.part_rz[size_t(b) * kRedBlocks + blockIdx.x] = s1;
+    c.part_rr[size_t(b) * kRedBlocks + blockIdx.x] = s2;
+  }
+}
+
+// beta = r.z(new) / r.z(old); p = z + beta p; block 0 stores the new r.z and r.r.
+__global__ void __launch_bounds__(kRedThreads)
+cg_dir_kernel(TvCg c, int nx, int ny, int par, double tol2) {
+  __shared__ double red[kRedThreads / 64];
+  const int b = blockIdx.y, nb = gridDim.y;
+  const size_t n = size_t(nx) * ny, base = size_t(b) * n;
+  const double rzn = partial_total(c.part_rz, b, red);
+  const double rr = partial_total(c.part_rr, b, red);
+  const double rz = c.rz[size_t(par) * nb + b];
+  const bool live = c.rr[b] > tol2 * c.bb[b];
+  const double beta = (live && rz > 0.0) ? rzn / rz : 0.0;
+  for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < n; k += size_t(gridDim.x) * blockDim.x)
+    c.p[base + k] = c.z[base + k] + beta * c.p[base + k];
+  // every block has read rz[par] and rr[b] above; the new values go to rz[1 - par]
+  // and to rr_next, which the next cg_q publishes as rr
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    c.rz[size_t(1 - par) * nb + b] = live ? rzn : rz;
+    c.rr_next[b] = live ? rr : c.rr[b];
+  }
+}
+
+__global__ void __launch_bounds__(kRedThreads)
+cg_finish_kernel(TvCg c, float* __restrict__ out, int nx, int ny) {
+  const int b = blockIdx.y;
+  if (blockIdx.x == 0 && blockIdx.y == 0)
+    for (int t = threadIdx.x; t < int(gridDim.y); t += blockDim.x) c.rr[t] = c.rr_next[t];
+  const size_t n = size_t(nx) * ny, base = size_t(b) * n;
+  for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < n; k += size_t(gridDim.x) * blockDim.x)
+    out[base + k] = float(c.x[base + k]);
+}
+
+__global__ void __launch_bounds__(kRedThreads)
+axpby_kernel(int64_t n, float a, const float* __restrict__ x, float b, float* __restrict__ y) {
+  for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < n; k += int64_t(gridDim.x) * blockDim.x)
+    y[k] = a * x[k] + b * y[k];
+}
+
+}  // namespace
+
+hipError_t launch_tv_weights(const float* x, int nx, int ny, int batch, double beta, double* wh, double* wv,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(tv_weights_kernel, dim3(kRedBlocks, batch), dim3(kRedThreads), 0, st, x, nx, ny, beta, wh, wv);
+  return hipGetLastError();
+}
+
+hipError_t launch_tv_apply(const float* x, float* y, const double* wh, const double* wv, int nx, int ny, int batch,
+                           double gamma, hipStream_t st) {
+  hipLaunchKernelGGL(tv_apply_kernel, dim3(kRedBlocks, batch), dim3(kRedThreads), 0, st, x, y, wh, wv, nx, ny, gamma);
+  return hipGetLastError();
+}
+
+hipError_t launch_tv_value(const float* x, int nx, int ny, int batch, double beta, double* part, hipStream_t st) {
+  hipLaunchKernelGGL(tv_value_kernel, dim3(kRedBlocks, batch), dim3(kRedThreads), 0, st, x, nx, ny, beta, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_start(const float* rhs, const TvCg& c, int nx, int ny, int batch, double gamma,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(cg_start_kernel, dim3(kRedBlocks, batch), dim3(kRedThreads), 0, st, rhs, c, nx, ny, gamma);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(cg_start_total_kernel, dim3(batch), dim3(kRedThreads), 0, st, c);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_iteration(const TvCg& c, int nx, int ny, int batch, double gamma, int par, double tol2,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(cg_q_kernel, dim3(kRedBlocks, batch), dim3(kRedThreads), 0, st, c, nx, ny, gamma);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(cg_update_kernel, dim3(kRedBlocks, batch), dim3(kRedThreads), 0, st, c, nx, ny, par, tol2);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(cg_dir_kernel, dim3(kRedBlocks, batch), dim3(kRedThreads), 0, st, c, nx, ny, par, tol2);
+  return hipGetLastError();
+}
+
+// publishes the last r.r (the convergence test reads rr) and writes the solution
+hipError_t launch_cg_finish(const TvCg& c, float* out, int nx, int ny, int batch, hipStream_t st) {
+  hipLaunchKernelGGL(cg_finish_kernel, dim3(kRedBlocks, batch), dim3(kRedThreads), 0, st, c, out, nx, ny);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpby(int64_t n, float a, const float* x, float b, float* y, hipStream_t st) {
+  int64_t blocks = (n + kRedThreads - 1) / kRedThreads;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(axpby_kernel, dim3(unsigned(blocks)), dim3(kRedThreads), 0, st, n, a, x, b, y);
+  return hipGetLastError();
+}
+
+}  // namespace qpat

@@ -1,0 +1,37 @@
+// Internal interface of the TV priorconditioner kernels (recon.hip) and their
+// host side (recon.cpp).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace qpat {
+
+constexpr int kRedThreads = 256;  // threads per block of the TV / CG kernels
+constexpr int kRedBlocks = 256;   // blocks per field (fixed: the reductions run in a fixed order)
+
+// Device buffers of the FP64 conjugate-gradient solve of M_gamma z = r for
+// `batch` fields of n = nx*ny nodes each ([batch][n] unless noted).
+struct TvCg {
+  double *x, *r, *z, *p, *q, *dinv;  // iterate, residual, preconditioned residual, direction, M p, 1/diag
+  double *wh, *wv;                   // edge weights C (horizontal / vertical edge of each node)
+  double *part_rz, *part_rr, *part_pq;  // block partials [batch][kRedBlocks]
+  double* rz;                        // r.z [2][batch] (current and next, alternating)
+  double *rr, *rr_next, *bb;         // r.r (published / pending), r.r of the right-hand side [batch]
+};
+
+hipError_t launch_tv_weights(const float* x, int nx, int ny, int batch, double beta, double* wh, double* wv,
+                             hipStream_t st);
+hipError_t launch_tv_apply(const float* x, float* y, const double* wh, const double* wv, int nx, int ny, int batch,
+                           double gamma, hipStream_t st);
+hipError_t launch_tv_value(const float* x, int nx, int ny, int batch, double beta, double* part, hipStream_t st);
+hipError_t launch_cg_start(const float* rhs, const TvCg& c, int nx, int ny, int batch, double gamma,
+                           hipStream_t st);
+hipError_t launch_cg_iteration(const TvCg& c, int nx, int ny, int batch, double gamma, int par, double tol2,
+                               hipStream_t st);
+hipError_t launch_cg_finish(const TvCg& c, float* out, int nx, int ny, int batch, hipStream_t st);
+hipError_t launch_axpby(int64_t n, float a, const float* x, float b, float* y, hipStream_t st);
+
+}  // namespace qpat
