@@ -122,6 +122,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched J^T J v comparisons")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch tiles")
     ap.add_argument("--graph", choices=["on", "off"], default="on")
+    ap.add_argument("--no-recon", action="store_true", help="skip the reconstruction-driver measurement")
     ap.add_argument("--tiles", default=None,
                     help="launch shape rows,cols,row_threads,col_threads of the headline plan (skips tuning)")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work")
@@ -329,6 +330,42 @@ def main():
                          "tiles_plain": {str(n): list(shape_1[n]) for n in sizes},
                          "tiles_batched": {str(n): list(shape_b[n]) for n in sizes}}
         del bat, plans, xs
+        torch.cuda.empty_cache()
+
+    # ------------------------------------------------------------ reconstruction driver
+    # One outer step of the inexact-Newton method (PCG of Algorithm 4 with the
+    # TV priorconditioner, fixed 10 iterations) for 4 data sets of the
+    # headline workload, solved side by side on batched J^T J v.
+    if not args.no_recon:
+        nq, its = 4, 10
+        p0s = T(np.stack([qi.blobs(ny, nx, 1900 + j, count=5, radius_cells=0.2 * 220) for j in range(nq)]))
+        with torch.cuda.stream(stream):
+            datas = plan.forward(p0s)
+            v = torch.zeros_like(p0s)
+            plan.jtjv(v)                          # warm-up of the batched graph
+            sync()
+            t = time.perf_counter()
+            plan.jtjv(v)
+            sync()
+            t_h = time.perf_counter() - t
+            t = time.perf_counter()
+            x, hist, iters, solves = q.ld_reconstruct(plan, datas, torch.zeros_like(p0s), beta=1e-3, gamma=1e-4,
+                                                      i_max=its, i_m=its, tol_in=-np.inf, tol_out=-np.inf,
+                                                      outer_max=1, solve_tol=1e-6, stream=stream)
+            sync()
+            t_r = time.perf_counter() - t
+        rel_err = [float(torch.linalg.norm(x[j] - p0s[j]) / torch.linalg.norm(p0s[j])) for j in range(nq)]
+        log(f"reconstruction step: {its} PCG iterations x {nq} data sets in {t_r:.2f} s "
+            f"(batched J^T J v {t_h:.3f} s each; {solves} M_gamma solver iterations)")
+        out["recon"] = {"workload": f"one inexact-Newton step (Algorithm 5) with {its} PCG iterations "
+                                    f"(Algorithm 4, TV priorconditioner beta=1e-3, gamma=1e-4) for {nq} "
+                                    "data sets of the 512x512 Nt=2000 workload, side by side",
+                        "seconds": round(t_r, 3), "seconds_per_pcg_iteration": round(t_r / its, 4),
+                        "jtjv_batched_seconds": round(t_h, 4),
+                        "jtjv_fraction": round(its * t_h / t_r, 3), "mgamma_solver_iterations": solves,
+                        "misfit_reduction": [round(h[-1] / h[0], 6) for h in hist],
+                        "rel_error_vs_p0": [round(e, 4) for e in rel_err]}
+        del p0s, datas, v, x
         torch.cuda.empty_cache()
 
     # ------------------------------------------------------------ CPU baseline (oracle)
