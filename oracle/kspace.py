@@ -231,14 +231,15 @@ def forward(prm: dict, c0, rho0, p0, *, ops: Operators | None = None, record=Non
     return data
 
 
-def adjoint(prm: dict, c0, rho0, r, *, ops: Operators | None = None) -> np.ndarray:
+def adjoint(prm: dict, c0, rho0, r, *, ops: Operators | None = None, record=None) -> np.ndarray:
     """H_a^T r by reverse-mode transposition of `forward`, one linear
     operation at a time, under the unweighted Euclidean inner products of
     R^N and R^{Ns Nt} (discretise-then-adjoint, Section 3.3.4).
 
     Transposes used: the medium, PML and source maps are diagonal;
     (F^-1 diag(m) F)^T = F^-1 diag(conj m) F for a real operator, hence
-    (grad_i^+)^T = -grad_i^- and Y_abs, Y_dis are symmetric."""
+    (grad_i^+)^T = -grad_i^- and Y_abs, Y_dis are symmetric.  `record(n, pb)`
+    receives the complete adjoint of p^{n+1} at every iterate n."""
     op = Operators(prm, c0, rho0) if ops is None else ops
     nt, dt = prm["nt"], prm["dt"]
     r = np.asarray(r, dtype=np.float64).reshape(nt, -1)
@@ -250,6 +251,8 @@ def adjoint(prm: dict, c0, rho0, r, *, ops: Operators | None = None) -> np.ndarr
     for n in range(nt - 2, -2, -1):
         # 4^T: measurement
         pb = pb + op.measure_T(r[n + 1])
+        if record is not None:
+            record(n, pb)
         # 3^T: equation of state (p^{n+1} does not depend on p^n directly)
         q = op.c2 * pb
         if op.lossy:
