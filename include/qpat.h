@@ -149,6 +149,30 @@ qpat_status qpat_forward_ckpt(qpat_plan plan, const float* p0, float* data, int3
 qpat_status qpat_replay(qpat_plan plan, const float* p0, const float* ckpt, int32_t interval,
                         int32_t seg, float* states, int32_t batch, qpat_stream stream);
 
+/* Sound-speed gradient (towards the joint sound-speed reconstruction that the
+ * paper's Discussion names as future work): for residuals r [B][nt][ns] and initial pressures p0 [B][ny][nx],
+ *   grad_c = d <r, H_a[c0] p0> / d c0   [B][ny][nx],
+ *   grad_p0 = H_a^* r                   [B][ny][nx] (as qpat_adjoint),
+ * with c_ref (hence kappa and the PML, eqs kappa and pml) held fixed.  c0
+ * enters the discrete operator through the equation of state (eq num-p: c^2,
+ * and c^2 eta ~ c^(y+2), c^2 tau ~ c^(y+1) by eq Twelve) and through the
+ * source scaling p0 / (4 c^2) of eq s1, so
+ *   grad_c = sum_m p*^m dp^m/dc - (2/c) p0 grad_p0,
+ * p*^m being the adjoint of p^m.  The forward wavefield is checkpointed every
+ * `interval` = K iterates; the reverse sweep recomputes one segment of K
+ * pressures at a time from its checkpoint, storing only dp^m/dc, and
+ * correlates it with the adjoint of that segment (FP64 sum).  K >= nt - 1
+ * keeps every sensitivity (one forward and one adjoint sweep); a smaller K
+ * costs one more forward sweep.  Per vector the workspace holds one FP64
+ * field, min(K, nt - 1) + 1 sensitivity fields and floor((nt - 2) / K)
+ * checkpoints of 5 fields (memory O(nt/K + K)).
+ *  qpat_medium_grad_bytes  size of the device workspace `work` (caller-owned,
+ *                          256-byte aligned, contents need not be initialised).
+ * Uses plan work space for 2B vectors.  Calls on one plan must not overlap. */
+qpat_status qpat_medium_grad_bytes(qpat_plan plan, int32_t interval, int32_t batch, size_t* bytes);
+qpat_status qpat_medium_grad(qpat_plan plan, const float* p0, const float* res, int32_t interval, void* work,
+                             float* grad_p0, float* grad_c, int32_t batch, qpat_stream stream);
+
 /* Launch shape of the FFT passes: rows per row-pass block, spectrum columns
  * per column-pass block (powers of two dividing ny and nx/2; rows even, and at
  * most ny/8 when ny is a power of two of 128 or more) and

@@ -48,6 +48,9 @@ _SIGS = {
     "qpat_ckpt_bytes": (c_int32, [c_void_p, c_int32, c_int32, ctypes.POINTER(c_size_t)]),
     "qpat_forward_ckpt": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_int32, c_void_p]),
     "qpat_replay": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_void_p, c_int32, c_void_p]),
+    "qpat_medium_grad_bytes": (c_int32, [c_void_p, c_int32, c_int32, ctypes.POINTER(c_size_t)]),
+    "qpat_medium_grad": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_int32,
+                                   c_void_p]),
     "qpat_set_tiles": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_int32]),
     "qpat_get_tiles": (c_int32, [c_void_p, ctypes.POINTER(c_int32), ctypes.POINTER(c_int32),
                                  ctypes.POINTER(c_int32), ctypes.POINTER(c_int32)]),

@@ -595,6 +595,8 @@ __device__ __forceinline__ Work shift_work(const Work& w, long long off) {
 template <int MODE, bool U>
 __global__ void __launch_bounds__(kMaxThreads)
 row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
+  constexpr int BM = MODE & ~RM_X;
+  constexpr bool XS = (MODE & RM_X) != 0;
   extern __shared__ float2 lds[];
   int item, tile;
   if (!locate<U>(L, ntile, chunk, item, tile)) return;
@@ -613,8 +615,10 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
   const int tot = rt * nx;
   const float dt = M.dt;
   const float rnx = 1.0f / static_cast<float>(nx);
+  // RM_X variants: this iterate's slot of the sound-speed sensitivities
+  float* const sens = XS ? X.sens + size_t(unsigned(flags) >> kSlotShift) * unsigned(nx * M.ny) : nullptr;
 
-  if constexpr (MODE == RM_F1) {
+  if constexpr (BM == RM_F1) {
     // eq num-vel: v_i = A_i (A_i v_i - dt/rho_i d/dr_i^+ p)
     const bool first = (n == 0);  // v^{-1/2} = 0
     float vxo[kMaxPer], vyo[kMaxPer], bx[kMaxPer], by[kMaxPer], ax[kMaxPer], ay[kMaxPer];
@@ -656,7 +660,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     __syncthreads();
     r = fft_any<false>(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
     store_pair_spectra(r, M, W.s0, W.s1, tile);
-  } else if constexpr (MODE == RM_F2 || MODE == RM_F2L) {
+  } else if constexpr (BM == RM_F2 || BM == RM_F2L) {
     // eq num-rho with the additive source of eq s1 (dt s = p0 / (2 d c^2), d = 2)
     const bool skip = (n == -1);  // v^{-1/2} = 0 and rho^{-1} = 0
     const bool inject = (n <= 0);
@@ -664,7 +668,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     PairRegs S;
     TwRegs TW;
     TapStage T{};
-    if constexpr (MODE == RM_F2L) taps_range(T, M, tap_base, y0, rt);
+    if constexpr (BM == RM_F2L) taps_range(T, M, tap_base, y0, rt);
     if (!skip) fetch_pair(S, M, W.s0, W.s1, tile);
     fetch_tw(TW, M.twx, nx);
     FOR_K_LD {
@@ -677,7 +681,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
         r0[k] = M.rho0[idx];
         ax[k] = M.arx[x];
         ay[k] = M.ary[y];
-        if constexpr (MODE == RM_F2L) c2[k] = M.c2[idx];
+        if constexpr (BM == RM_F2L) c2[k] = M.c2[idx];
       }
     }
     if (inject) {  // first two iterates only (kept apart so the loads above issue back to back)
@@ -686,7 +690,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
         {
           const int j = fdiv(it, nx, rnx), x = it - j * nx;
           const unsigned idx = mul24(y0 + j, nx) + x;
-          if constexpr (MODE != RM_F2L) c2[k] = M.c2[idx];
+          if constexpr (BM != RM_F2L) c2[k] = M.c2[idx];
           src[k] = X.in[idx];
         }
       }
@@ -694,7 +698,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     if (!skip) put_pair(S, bufA, M);
     put_tw(TW, tw, nx);
     __syncthreads();
-    if constexpr (MODE == RM_F2L) taps_fetch(T, M, nullptr, 0);
+    if constexpr (BM == RM_F2L) taps_fetch(T, M, nullptr, 0);
     float2* r = nullptr;
     float2* o = bufA;
     if (!skip) {
@@ -720,7 +724,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
         const float ry = ay[k] * (ay[k] * (skip ? 0.f : ryo[k]) - dt * r0[k] * ey) + s;
         W.f2[idx] = rx;
         W.f3[idx] = ry;
-        if constexpr (MODE == RM_F2) {
+        if constexpr (BM == RM_F2) {
           // S = sum_i rho_i and u = rho0 sum_i A_i d/dr_i^- v_i feed eq num-p.
           // Each is transformed with its own rows paired (S and u differ by
           // orders of magnitude, so they must not share one complex FFT).
@@ -730,12 +734,13 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
           const float p = c2[k] * (rx + ry);
           pcomp(o, j, x, nx) = p;
           if (flags & FL_STORE_P) W.q[idx] = p;
+          if constexpr (XS) sens[idx] = 2.f * p * rsqrtf(c2[k]);  // d(c^2 S)/dc
         }
       }
     }
-    if constexpr (MODE == RM_F2L) taps_put(T, false);
+    if constexpr (BM == RM_F2L) taps_put(T, false);
     __syncthreads();
-    if constexpr (MODE == RM_F2) {
+    if constexpr (BM == RM_F2) {
       r = fft_any<false>(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
       store_rowpair_spectra(r, M, W.s0, tile);
       store_rowpair_spectra(r + (rt / 2) * LS, M, W.s1, tile);
@@ -744,7 +749,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
       r = fft_any<false>(o, other(o, bufA, bufB), rt / 2, nx, LS, M.radx, M.nstx, tw);
       store_rowpair_spectra(r, M, W.s0, tile);
     }
-  } else if constexpr (MODE == RM_F3) {
+  } else if constexpr (BM == RM_F3) {
     // eq num-p: p = c^2 (S - eta Y_dis S + tau Y_abs u)
     float rxo[kMaxPer], ryo[kMaxPer], c2[kMaxPer], ce[kMaxPer], ctau[kMaxPer];
     TapStage T;
@@ -780,7 +785,14 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
         const float ys = rowpair_val(r, j, x, nx), yu = rowpair_val(r + (rt / 2) * LS, j, x, nx);
         const float p = c2[k] * (rxo[k] + ryo[k]) - ce[k] * ys + ctau[k] * yu;
         pcomp(o, j, x, nx) = p;
-        if (flags & FL_STORE_P) W.q[mul24(y0 + j, nx) + x] = p;
+        const unsigned idx = mul24(y0 + j, nx) + x;
+        if (flags & FL_STORE_P) W.q[idx] = p;
+        if constexpr (XS) {
+          // eq Twelve: c^2 eta ~ c^(y+2) and c^2 tau ~ c^(y+1), so each term of
+          // eq num-p differentiates to its power over c
+          const float S = rxo[k] + ryo[k];
+          sens[idx] = (2.f * c2[k] * S - (M.ypow + 2.f) * ce[k] * ys + (M.ypow + 1.f) * ctau[k] * yu) * rsqrtf(c2[k]);
+        }
       }
     }
     taps_put(T, false);
@@ -788,7 +800,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     if (!(flags & FL_NO_SENSORS)) sensor_partials(M, T, o, y0, W.part, n + 1);
     r = fft_any<false>(o, other(o, bufA, bufB), rt / 2, nx, LS, M.radx, M.nstx, tw);
     store_rowpair_spectra(r, M, W.s0, tile);
-  } else if constexpr (MODE == RM_A1 || MODE == RM_A1L) {
+  } else if constexpr (BM == RM_A1 || BM == RM_A1L) {
     // transpose of eqs num-m and num-p: p* += M^T r_{n+1}; q = c^2 p*
     const bool first = (n == M.nt - 2);
     const int half = rt / 2;
@@ -806,7 +818,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
         const int j = fdiv(it, nx, rnx), x = it - j * nx, y = y0 + j;
         const unsigned idx = mul24(y, nx) + x;
         c2[k] = M.c2[idx];
-        if constexpr (MODE == RM_A1) {
+        if constexpr (BM == RM_A1) {
           ce[k] = M.c2eta[idx];
           ctau[k] = M.c2tau[idx];
         } else {
@@ -818,7 +830,20 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
         }
       }
     }
-    if constexpr (MODE == RM_A1L) {
+    float sv[kMaxPer];
+    double gprev[kMaxPer];
+    if constexpr (XS) {
+      FOR_K_LD {
+        const int it = min(int(threadIdx.x) + k * B, tot - 1);
+        {
+          const int j = fdiv(it, nx, rnx), x = it - j * nx;
+          const unsigned idx = mul24(y0 + j, nx) + x;
+          sv[k] = sens[idx];
+          gprev[k] = first ? 0.0 : X.gc[idx];
+        }
+      }
+    }
+    if constexpr (BM == RM_A1L) {
       if (n == -1 && M.nt >= 2) {  // the gradient accumulated at n = 0
         FOR_K_LD {
           const int it = min(int(threadIdx.x) + k * B, tot - 1);
@@ -855,7 +880,8 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
         const int j = fdiv(it, nx, rnx), x = it - j * nx;
         const unsigned idx = mul24(y0 + j, nx) + x;
         const float pb = pcomp(r, j, x, nx);
-        if constexpr (MODE == RM_A1) {
+        if constexpr (XS) X.gc[idx] = gprev[k] + double(pb) * double(sv[k]);
+        if constexpr (BM == RM_A1) {
           // eta q and tau q, each with its own rows paired (see RM_F2)
           W.q[idx] = c2[k] * pb;
           pcomp(o, j, x, nx) = ce[k] * pb;
@@ -876,7 +902,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
       }
     }
     __syncthreads();
-    if constexpr (MODE == RM_A1) {
+    if constexpr (BM == RM_A1) {
       r = fft_any<false>(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
       store_rowpair_spectra(r, M, W.s0, tile);
       store_rowpair_spectra(r + half * LS, M, W.s1, tile);
@@ -884,7 +910,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
       r = fft_any<false>(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
       store_pair_spectra(r, M, W.s0, W.s1, tile);
     }
-  } else if constexpr (MODE == RM_A2) {
+  } else if constexpr (BM == RM_A2) {
     // transpose of the mass update and of the Y terms of eq num-p
     const bool first = (n == M.nt - 2);
     float qv[kMaxPer], rbx0[kMaxPer], rby0[kMaxPer], r0[kMaxPer], ax[kMaxPer], ay[kMaxPer];
@@ -947,7 +973,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
       r = fft_any<false>(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
       store_pair_spectra(r, M, W.s0, W.s1, tile);
     }
-  } else if constexpr (MODE == RM_A3) {
+  } else if constexpr (BM == RM_A3) {
     // transpose of eq num-vel
     const bool first = (n == M.nt - 2);
     float vbx0[kMaxPer], vby0[kMaxPer], bx[kMaxPer], by[kMaxPer], ax[kMaxPer], ay[kMaxPer];
@@ -989,7 +1015,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     __syncthreads();
     r = fft_any<false>(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
     store_pair_spectra(r, M, W.s0, W.s1, tile);
-  } else if constexpr (MODE == RM_FWD1) {
+  } else if constexpr (BM == RM_FWD1) {
     const float* src = X.in;
     TwRegs TW;
     float v[kMaxPer];
@@ -1012,7 +1038,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     __syncthreads();
     float2* r = fft_any<false>(bufA, bufB, rt / 2, nx, LS, M.radx, M.nstx, tw);
     store_rowpair_spectra(r, M, W.s0, tile);
-  } else if constexpr (MODE == RM_INV1) {
+  } else if constexpr (BM == RM_INV1) {
     RowPairRegs S0;
     TwRegs TW;
     fetch_rowpair(S0, M, W.s0, tile);
@@ -1512,6 +1538,19 @@ __global__ void tap_order_kernel(const Item* __restrict__ items, const IO* __res
   }
 }
 
+// ---------------------------------------------------------------- sound-speed gradient
+// d<r, H_a p0>/dc = sum_m p*^m dp^m/dc (the equation-of-state part, gc) minus
+// (2/c) p0 H_a^* r (the source of eq s1 scales as 1/c^2).
+__global__ void __launch_bounds__(kBlock) grad_c_kernel(const float* __restrict__ c2, const float* __restrict__ p0,
+                                                        const float* __restrict__ g0, const double* __restrict__ gc,
+                                                        long long n, long long gc_stride, float* __restrict__ out) {
+  const long long b = blockIdx.y;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const double c = sqrt(double(c2[i]));
+    out[b * n + i] = float(gc[b * gc_stride + i] - 2.0 * double(p0[b * n + i]) * double(g0[b * n + i]) / c);
+  }
+}
+
 // ---------------------------------------------------------------- reductions
 __device__ __forceinline__ double wave_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
@@ -1577,6 +1616,10 @@ hipError_t launch_row(int mode, const Launch& L, bool uniform, int ntile, int ch
     QPAT_ROW_CASE(RM_A3)
     QPAT_ROW_CASE(RM_FWD1)
     QPAT_ROW_CASE(RM_INV1)
+    QPAT_ROW_CASE(RM_F2L | RM_X)
+    QPAT_ROW_CASE(RM_F3 | RM_X)
+    QPAT_ROW_CASE(RM_A1 | RM_X)
+    QPAT_ROW_CASE(RM_A1L | RM_X)
     default: return hipErrorInvalidValue;
   }
 #undef QPAT_ROW_CASE
@@ -1628,7 +1671,9 @@ hipError_t kernels_allow_lds(size_t bytes) {
   const hipError_t es[] = {allow_row<RM_F1>(bytes),      allow_row<RM_F2>(bytes),     allow_row<RM_F2L>(bytes),
                            allow_row<RM_F3>(bytes),      allow_row<RM_A1>(bytes),     allow_row<RM_A1L>(bytes),
                            allow_row<RM_A2>(bytes),      allow_row<RM_A3>(bytes),     allow_row<RM_FWD1>(bytes),
-                           allow_row<RM_INV1>(bytes),    allow_col<CM_GRADP1>(bytes), allow_col<CM_GRADM2>(bytes),
+                           allow_row<RM_INV1>(bytes),    allow_row<RM_F2L | RM_X>(bytes), allow_row<RM_F3 | RM_X>(bytes),
+                           allow_row<RM_A1 | RM_X>(bytes), allow_row<RM_A1L | RM_X>(bytes),
+                           allow_col<CM_GRADP1>(bytes), allow_col<CM_GRADM2>(bytes),
                            allow_col<CM_FRAC>(bytes),    allow_col<CM_GRADP2>(bytes), allow_col<CM_DIVM>(bytes),
                            allow_col<CM_APPLY>(bytes)};
   for (hipError_t e : es)
@@ -1649,6 +1694,15 @@ hipError_t launch_tap_order(const Item* items, const IO* io, int nitems, int max
   if (bx > 1024) bx = 1024;
   if (bx < 1) bx = 1;
   hipLaunchKernelGGL(tap_order_kernel, dim3(bx, nitems), dim3(kBlock), 0, st, items, io);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_c(const float* c2, const float* p0, const float* g0, const double* gc, long long n,
+                         int batch, long long gc_stride, float* out, hipStream_t st) {
+  long long bx = (n + kBlock - 1) / kBlock;
+  if (bx > 1024) bx = 1024;
+  hipLaunchKernelGGL(grad_c_kernel, dim3(unsigned(bx), unsigned(batch)), dim3(kBlock), 0, st, c2, p0, g0, gc, n,
+                     gc_stride, out);
   return hipGetLastError();
 }
 

@@ -318,8 +318,9 @@ hipError_t col(Exec& E, int cm, int n, hipStream_t st, int mcode = 0) {
     if (e_ != hipSuccess) return e_;         \
   } while (0)
 
-// One forward iterate n (eqs num-vel, num-rho, num-p, num-m).
-hipError_t fwd_iterate(Exec& E, int n, int flags, hipStream_t st) {
+// One forward iterate n (eqs num-vel, num-rho, num-p, num-m).  With `sens`
+// the pressure pass also stores dp^{n+1}/dc at the slot carried in `flags`.
+hipError_t fwd_iterate(Exec& E, int n, int flags, hipStream_t st, bool sens = false) {
   if (n > -1) {
     LCHK(col(E, CM_GRADP1, n, st));
     LCHK(row(E, RM_F1, n, 0, st));
@@ -328,9 +329,9 @@ hipError_t fwd_iterate(Exec& E, int n, int flags, hipStream_t st) {
   if (E.lossy) {
     LCHK(row(E, RM_F2, n, 0, st));
     LCHK(col(E, CM_FRAC, n, st));
-    LCHK(row(E, RM_F3, n, flags, st));
+    LCHK(row(E, sens ? (RM_F3 | RM_X) : RM_F3, n, flags, st));
   } else {
-    LCHK(row(E, RM_F2L, n, flags, st));
+    LCHK(row(E, sens ? (RM_F2L | RM_X) : RM_F2L, n, flags, st));
   }
   return hipSuccess;
 }
@@ -341,22 +342,28 @@ hipError_t seq_forward(Exec& E, int n_last, hipStream_t st) {
   return launch_combine(E.d_items, E.d_io, int(E.items.size()), E.max_data, st);
 }
 
-// The reverse time loop of the adjoint (transposes of the forward passes).
+// One adjoint iterate n (transposes of the forward passes of iterate n, in
+// reverse order).  With `gc` the first pass also adds p*^{n+1} dp^{n+1}/dc,
+// the sensitivity read from the slot carried in `flags`.
+hipError_t adj_iterate(Exec& E, int n, int flags, hipStream_t st, bool gc = false) {
+  if (E.lossy) {
+    LCHK(row(E, gc ? (RM_A1 | RM_X) : RM_A1, n, flags, st));
+    LCHK(col(E, CM_FRAC, n, st));
+    LCHK(row(E, RM_A2, n, 0, st));
+  } else {
+    LCHK(row(E, gc ? (RM_A1L | RM_X) : RM_A1L, n, flags, st));
+  }
+  if (n == -1) return hipSuccess;
+  LCHK(col(E, CM_GRADP2, n, st));
+  LCHK(row(E, RM_A3, n, 0, st));
+  LCHK(col(E, CM_DIVM, n, st));
+  return hipSuccess;
+}
+
+// The reverse time loop of the adjoint.
 hipError_t seq_adjoint(Exec& E, hipStream_t st) {
   LCHK(launch_tap_order(E.d_items, E.d_io, int(E.items.size()), 2 * E.max_data, st));
-  for (int n = E.max_nt - 2; n >= -1; --n) {
-    if (E.lossy) {
-      LCHK(row(E, RM_A1, n, 0, st));
-      LCHK(col(E, CM_FRAC, n, st));
-      LCHK(row(E, RM_A2, n, 0, st));
-    } else {
-      LCHK(row(E, RM_A1L, n, 0, st));
-    }
-    if (n == -1) break;
-    LCHK(col(E, CM_GRADP2, n, st));
-    LCHK(row(E, RM_A3, n, 0, st));
-    LCHK(col(E, CM_DIVM, n, st));
-  }
+  for (int n = E.max_nt - 2; n >= -1; --n) LCHK(adj_iterate(E, n, 0, st));
   return hipSuccess;
 }
 
@@ -407,6 +414,14 @@ struct qpat_plan_s {
   std::vector<float*> datas;  // per-vector data buffers for jtjv
   // executors per batch size (rebuilt when tiles change)
   std::map<int, std::unique_ptr<Exec>> execs;
+  // sound-speed gradient: per batch size, a forward executor on work vectors
+  // [0, B) and an adjoint executor on [B, 2B), so that replaying the forward
+  // leaves the adjoint state alone
+  std::map<int, std::pair<std::unique_ptr<Exec>, std::unique_ptr<Exec>>> grad_execs;
+  void clear_execs() {
+    execs.clear();
+    grad_execs.clear();
+  }
   bool graph = false;
   int rt = 2, ct = 1, rthr = kBlock, cthr = kBlock;
 };
@@ -673,6 +688,7 @@ qpat_status plan_build(qpat_plan P, const double* c0, const double* rho0) {
   M.ns = p.ns;
   M.lossy = lossy ? 1 : 0;
   M.dt = float(dt);
+  M.ypow = float(p.y);
   radix_plan(nx, &M.radx, &M.nstx, 8);
   radix_plan(ny, &M.rady, &M.nsty, 8);
   M.c2 = (const float*)(d + o_c2);
@@ -753,7 +769,7 @@ qpat_status plan_reserve(qpat_plan P, int b) {
     HIPCHK(hipFree(P->d_work));
     P->d_work = nullptr;
   }
-  P->execs.clear();
+  P->clear_execs();
   P->cap = 0;
   STCHK(alloc_works(P->prm, b, &P->d_work, &P->work_item_bytes, P->works, P->datas));
   P->cap = b;
@@ -870,7 +886,7 @@ qpat_status set_tiles(qpat_plan P, int rt, int ct, int rthr, int cthr) {
     P->rthr = P->med.rthr = rthr;
     P->cthr = P->med.cthr = cthr;
     HIPCHK(hipDeviceSynchronize());
-    P->execs.clear();
+    P->clear_execs();
   }
   return QPAT_OK;
 }
@@ -948,7 +964,7 @@ qpat_status qpat_plan_create(const qpat_params* prm, const double* c0, const dou
 void qpat_plan_destroy(qpat_plan P) {
   if (!P) return;
   (void)hipDeviceSynchronize();
-  P->execs.clear();
+  P->clear_execs();
   if (P->d_work) (void)hipFree(P->d_work);
   if (P->d_med) (void)hipFree(P->d_med);
   delete P;
@@ -1074,6 +1090,123 @@ qpat_status qpat_replay(qpat_plan P, const float* p0, const float* ckpt, int32_t
       HIPCHK(hipMemcpyAsync(states + (size_t(i) * cnt + c) * 5 * N, P->works[i].f0, 5 * N * sizeof(float),
                             hipMemcpyDeviceToDevice, st));
   }
+  return QPAT_OK;
+}
+
+// ---- sound-speed gradient (checkpointed forward correlated with the adjoint)
+namespace {
+
+// Segment j of the time axis holds the pressures p^m, m in [lo_j, hi_j]:
+// segment 0 starts at m = 0 (recomputed from p0 alone), segment j >= 1 at
+// m = jK + 1 (recomputed from the checkpointed state at m = jK).  The
+// sensitivity of p^m sits at slot m - jK.
+struct GradLayout {
+  int nseg = 0, slots = 0;
+  size_t gc_off = 0, sens_off = 0, ck_off = 0, total = 0;
+};
+
+size_t round256(size_t b) { return (b + 255) & ~size_t(255); }
+
+GradLayout grad_layout(qpat_plan P, int K, int batch) {
+  const int nt = P->prm.nt;
+  const size_t N = field_elems(P), B = size_t(batch);
+  GradLayout g;
+  g.nseg = nt >= 2 ? 1 + (nt - 2) / K : 1;
+  g.slots = std::min(K, nt - 1) + 1;
+  g.gc_off = 0;
+  g.sens_off = round256(B * N * sizeof(double));
+  g.ck_off = round256(g.sens_off + B * size_t(g.slots) * N * sizeof(float));
+  g.total = g.ck_off + B * size_t(g.nseg - 1) * 5 * N * sizeof(float);
+  return g;
+}
+
+qpat_status grad_execs(qpat_plan P, int b, Exec** ef, Exec** ea) {
+  STCHK(plan_reserve(P, 2 * b));
+  auto it = P->grad_execs.find(b);
+  if (it == P->grad_execs.end()) {
+    std::vector<Item> fi(b), ai(b);
+    for (int i = 0; i < b; ++i) {
+      fi[i].m = ai[i].m = P->med;
+      fi[i].w = P->works[i];
+      ai[i].w = P->works[b + i];
+    }
+    std::unique_ptr<Exec> f(new Exec()), a(new Exec());
+    STCHK(exec_build(*f, fi));
+    STCHK(exec_build(*a, ai));
+    it = P->grad_execs.emplace(b, std::make_pair(std::move(f), std::move(a))).first;
+  }
+  *ef = it->second.first.get();
+  *ea = it->second.second.get();
+  return QPAT_OK;
+}
+
+// The forward state that iterate m + 1 starts from: v_x, v_y, rho_x, rho_y
+// (4 fields) and the half spectrum of p^m (ny * nx/2 complex = one field).
+hipError_t state_copy(const Work& w, float* ck, size_t N, bool save, hipStream_t st) {
+  const size_t fb = 4 * N * sizeof(float), sb = N * sizeof(float);
+  hipError_t e = save ? hipMemcpyAsync(ck, w.f0, fb, hipMemcpyDeviceToDevice, st)
+                      : hipMemcpyAsync(w.f0, ck, fb, hipMemcpyDeviceToDevice, st);
+  if (e != hipSuccess) return e;
+  return save ? hipMemcpyAsync(ck + 4 * N, w.s0, sb, hipMemcpyDeviceToDevice, st)
+              : hipMemcpyAsync(w.s0, ck + 4 * N, sb, hipMemcpyDeviceToDevice, st);
+}
+
+}  // namespace
+
+qpat_status qpat_medium_grad_bytes(qpat_plan P, int32_t K, int32_t batch, size_t* bytes) {
+  if (!P || !bytes) return fail(QPAT_E_INVALID, "plan / bytes is NULL");
+  if (K < 1) return fail(QPAT_E_INVALID, "interval must be >= 1");
+  if (batch < 1 || batch > 4096) return fail(QPAT_E_INVALID, "batch must be in [1, 4096]");
+  *bytes = grad_layout(P, K, batch).total;
+  return QPAT_OK;
+}
+
+qpat_status qpat_medium_grad(qpat_plan P, const float* p0, const float* res, int32_t K, void* work,
+                             float* grad_p0, float* grad_c, int32_t batch, qpat_stream stream) {
+  STCHK(check_plan_call(P, p0, res, batch));
+  if (!work || !grad_p0 || !grad_c) return fail(QPAT_E_INVALID, "work / grad_p0 / grad_c is NULL");
+  if (K < 1) return fail(QPAT_E_INVALID, "interval must be >= 1");
+  const GradLayout g = grad_layout(P, K, batch);
+  if (g.slots >= (1 << (30 - kSlotShift))) return fail(QPAT_E_INVALID, "interval too long");
+  hipStream_t st = (hipStream_t)stream;
+  Exec *Ef = nullptr, *Ea = nullptr;
+  STCHK(grad_execs(P, batch, &Ef, &Ea));
+  const int nt = P->prm.nt;
+  const size_t N = field_elems(P), D = data_elems(P);
+  char* w = static_cast<char*>(work);
+  double* gc = reinterpret_cast<double*>(w + g.gc_off);
+  float* sens = reinterpret_cast<float*>(w + g.sens_off);
+  float* ck = reinterpret_cast<float*>(w + g.ck_off);
+  auto ckpt = [&](int i, int j) { return ck + (size_t(i) * (g.nseg - 1) + (j - 1)) * 5 * N; };
+  std::vector<IO> iof(batch), ioa(batch);
+  for (int i = 0; i < batch; ++i) {
+    iof[i] = IO{p0 + N * i, nullptr, sens + size_t(i) * g.slots * N, nullptr};
+    ioa[i] = IO{res + D * i, grad_p0 + N * i, sens + size_t(i) * g.slots * N, gc + N * i};
+  }
+  STCHK(exec_set_io(*Ef, iof, st));
+  STCHK(exec_set_io(*Ea, ioa, st));
+  auto run = [&]() -> hipError_t {
+    // forward sweep: the states at m = jK, j = 1 .. nseg - 1
+    for (int m = 0; m <= (g.nseg - 1) * K && g.nseg > 1; ++m) {
+      LCHK(fwd_iterate(*Ef, m - 1, FL_NO_SENSORS, st));
+      if (m > 0 && m % K == 0)
+        for (int i = 0; i < batch; ++i) LCHK(state_copy(P->works[i], ckpt(i, m / K), N, true, st));
+    }
+    // reverse sweep, one segment at a time: recompute its sensitivities, then
+    // run its adjoint iterates
+    LCHK(launch_tap_order(Ea->d_items, Ea->d_io, batch, 2 * Ea->max_data, st));
+    for (int j = g.nseg - 1; j >= 0; --j) {
+      const int base = j * K, lo = j == 0 ? 0 : base + 1, hi = std::min(base + K, nt - 1);
+      if (j > 0)
+        for (int i = 0; i < batch; ++i) LCHK(state_copy(P->works[i], ckpt(i, j), N, false, st));
+      for (int m = lo; m <= hi; ++m)
+        LCHK(fwd_iterate(*Ef, m - 1, FL_NO_SENSORS | ((m - base) << kSlotShift), st, true));
+      for (int m = hi; m >= lo; --m) LCHK(adj_iterate(*Ea, m - 1, (m - base) << kSlotShift, st, true));
+    }
+    return launch_grad_c(P->med.c2, p0, grad_p0, gc, (long long)N, batch, (long long)N, grad_c, st);
+  };
+  const hipError_t e = run();
+  if (e != hipSuccess) return fail(QPAT_E_HIP, std::string("medium_grad: ") + hipGetErrorString(e));
   return QPAT_OK;
 }
 

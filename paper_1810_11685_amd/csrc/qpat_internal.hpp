@@ -29,6 +29,7 @@ struct alignas(16) Tap {
 struct Medium {
   int nx, ny, nxh, nt, ns, lossy;
   float dt;
+  float ypow;             // power-law exponent y of the absorption
   int rt, ct;             // rows per row-pass tile, spectrum columns per column-pass tile
   int lrt, lct;           // log2(rt), log2(ct); spectra are stored in rt x ct tiles
   int rthr, cthr;         // threads per block of the row / column passes
@@ -57,6 +58,8 @@ struct Work {
 struct IO {
   const float* in;   // forward: p0 [ny][nx]; adjoint: residual [nt][ns]; apply: field
   float* out;        // forward: data [nt][ns]; adjoint: gradient [ny][nx]; apply: field
+  float* sens;       // sound-speed sensitivities dp^m/dc, [slots][ny][nx] (RM_X passes only)
+  double* gc;        // adjoint: correlation sum_m p*^m dp^m/dc [ny][nx] (RM_X passes only)
 };
 
 struct Item {
@@ -100,7 +103,11 @@ enum RowMode : int {
   RM_A2 = 6,   // adjoint lossy: Y ops -> rho* update -> spectra of e*
   RM_A3 = 7,   // adjoint: grad e* -> v* update -> spectra of g*
   RM_FWD1 = 8, // single real field (row pairs) -> spectrum s0
-  RM_INV1 = 9  // spectrum s0 -> single real field (row pairs)
+  RM_INV1 = 9, // spectrum s0 -> single real field (row pairs)
+  // Modifier of RM_F2L / RM_F3 / RM_A1 / RM_A1L: the forward passes also store
+  // the sensitivity dp/dc of the new pressure into IO::sens at the slot held in
+  // the flags; the adjoint passes add p* times that sensitivity into IO::gc.
+  RM_X = 16
 };
 
 // Per-launch flags.
@@ -108,6 +115,7 @@ enum Flags : int {
   FL_STORE_P = 1,     // forward: also store p into Work::q
   FL_NO_SENSORS = 2,  // forward: skip the sensor partials (replay)
 };
+constexpr int kSlotShift = 8;  // RM_X passes: flags >> kSlotShift is the sensitivity slot
 
 // Launch helpers implemented in kernels.hip.
 hipError_t launch_row(int mode, const Launch& L, bool uniform, int ntile, int chunk, int nblocks,
@@ -118,6 +126,8 @@ hipError_t launch_combine(const Item* items, const IO* io, int nitems, int max_c
                           hipStream_t st);
 hipError_t kernels_allow_lds(size_t bytes);
 hipError_t launch_tap_order(const Item* items, const IO* io, int nitems, int max_count, hipStream_t st);
+hipError_t launch_grad_c(const float* c2, const float* p0, const float* g0, const double* gc, long long n,
+                         int batch, long long gc_stride, float* out, hipStream_t st);
 hipError_t launch_dot(const float* a, const float* b, int64_t n, double* partial, int nblk,
                       double* out, hipStream_t st);
 

@@ -154,6 +154,34 @@ class Plan:
               "qpat_replay")
         return out
 
+    # ---- sound-speed gradient
+    def medium_grad_bytes(self, interval: int, batch: int = 1) -> int:
+        n = ctypes.c_size_t()
+        check(lib().qpat_medium_grad_bytes(self._h, interval, batch, ctypes.byref(n)), "qpat_medium_grad_bytes")
+        return int(n.value)
+
+    def medium_grad(self, p0: torch.Tensor, res: torch.Tensor, interval: int | None = None, work=None,
+                    stream=None) -> tuple[torch.Tensor, torch.Tensor]:
+        """(d<res, H_a[c0] p0>/dc0, H_a^* res) for p0 [..., ny, nx] and res
+        [..., nt, ns] (c_ref fixed), recomputing the forward wavefield from
+        checkpoints every `interval` iterates (None: keep every sensitivity).
+        `work` may pass a reusable uint8 device buffer of medium_grad_bytes."""
+        p0, b, lead = self._fields(p0, "p0")
+        res, b2, _ = self._data(res, "res")
+        if b2 != b:
+            raise ValueError("medium_grad: p0 and res must hold the same number of vectors")
+        k = max(self.nt - 1, 1) if interval is None else int(interval)
+        need = self.medium_grad_bytes(k, b)
+        if work is None:
+            work = torch.empty(need, device=p0.device, dtype=torch.uint8)
+        elif work.numel() * work.element_size() < need or not work.is_contiguous():
+            raise ValueError(f"medium_grad: work buffer needs {need} contiguous bytes")
+        gp = torch.empty(*lead, self.ny, self.nx, device=p0.device, dtype=torch.float32)
+        gc = torch.empty_like(gp)
+        check(lib().qpat_medium_grad(self._h, _ptr(p0), _ptr(res), k, _ptr(work), _ptr(gp), _ptr(gc), b,
+                                     _stream(stream)), "qpat_medium_grad")
+        return gc, gp
+
     # ---- launch shape
     def set_tiles(self, rows: int, cols: int, row_threads: int = 256, col_threads: int = 256) -> None:
         check(lib().qpat_set_tiles(self._h, rows, cols, row_threads, col_threads), "qpat_set_tiles")
