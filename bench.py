@@ -123,6 +123,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch tiles")
     ap.add_argument("--graph", choices=["on", "off"], default="on")
     ap.add_argument("--no-recon", action="store_true", help="skip the reconstruction-driver measurement")
+    ap.add_argument("--no-medium", action="store_true", help="skip the sound-speed gradient measurement")
     ap.add_argument("--tiles", default=None,
                     help="launch shape rows,cols,row_threads,col_threads of the headline plan (skips tuning)")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work")
@@ -367,6 +368,36 @@ def main():
                         "rel_error_vs_p0": [round(e, 4) for e in rel_err]}
         del p0s, datas, v, x
         torch.cuda.empty_cache()
+
+    # ------------------------------------------------------------ sound-speed gradient
+    # d<r, H_a[c0] p0>/dc0 for the headline workload: checkpoints every 100
+    # iterates with the reverse sweep recomputing one segment at a time, and
+    # every sensitivity kept (no recomputation); compared with one forward +
+    # adjoint pair.
+    if not args.no_medium:
+        mg = {}
+        with torch.cuda.stream(stream):
+            for label, k in (("K100", 100), ("all", nt - 1)):
+                for b in (1, 4):
+                    pb = p0.expand(b, ny, nx).contiguous()
+                    rb = res.expand(b, nt, ns).contiguous()
+                    work = torch.empty(plan.medium_grad_bytes(k, b), dtype=torch.uint8, device=dev)
+                    plan.medium_grad(pb, rb, interval=k, work=work)       # warm-up
+                    sync()
+                    t = time.perf_counter()
+                    plan.medium_grad(pb, rb, interval=k, work=work)
+                    sync()
+                    dt_g = time.perf_counter() - t
+                    mg[f"{label}_B{b}"] = {"interval": k, "batch": b, "seconds": round(dt_g, 4),
+                                           "workspace_MB": round(work.numel() / 2 ** 20, 1),
+                                           "vs_fwd_adj": round(dt_g / (b * ms * 1e-3), 3)}
+                    log(f"medium gradient K={k} B={b}: {dt_g * 1e3:.1f} ms "
+                        f"({dt_g / (b * ms * 1e-3):.2f} x forward+adjoint per vector), "
+                        f"workspace {work.numel() / 2 ** 20:.0f} MB")
+                    del work, pb, rb
+                    torch.cuda.empty_cache()
+        out["medium_grad"] = {"workload": "sound-speed gradient d<r, H_a[c0] p0>/dc0 of the 512x512 Nt=2000 "
+                                          "workload (grad_p0 as a by-product)", "runs": mg}
 
     # ------------------------------------------------------------ CPU baseline (oracle)
     if not args.no_cpu:
