@@ -23,6 +23,7 @@ import numpy as np
 __all__ = [
     "smooth_noise", "medium", "blobs", "ring_sensors", "gaussian_field",
     "make_params", "config", "block_mean", "CONFIGS",
+    "smooth_noise3d", "medium3d", "blobs3d", "face_sensors", "make_params3d", "config3d",
 ]
 
 
@@ -153,3 +154,95 @@ def uneven_batch(seed0: int = 2000, dx: float = 1e-4, dt: float = 1.875e-8,
             probs.append(dict(params=prm, c0=c0, rho0=rho0, p0=p0))
             i += 1
     return probs
+
+
+# ---------------------------------------------------------------- 3-D inputs
+def smooth_noise3d(n_z: int, n_y: int, n_x: int, sigma_cells: float, seed: int) -> np.ndarray:
+    """3-D white N(0,1) noise, periodically Gaussian-filtered, mean removed and
+    scaled to a maximum absolute value of 1."""
+    w = _rng(seed).standard_normal((n_z, n_y, n_x))
+    fz = np.fft.fftfreq(n_z)[:, None, None]
+    fy = np.fft.fftfreq(n_y)[None, :, None]
+    fx = np.fft.fftfreq(n_x)[None, None, :]
+    g = np.exp(-2.0 * (math.pi * sigma_cells) ** 2 * (fx ** 2 + fy ** 2 + fz ** 2))
+    s = np.real(np.fft.ifftn(np.fft.fftn(w) * g))
+    s -= s.mean()
+    m = np.abs(s).max()
+    return s / m if m > 0 else s
+
+
+def medium3d(n_z: int, n_y: int, n_x: int, seed_c: int, seed_rho: int, *, c_range=(1390.0, 1897.0),
+             rho_range=(956.0, 1252.0), sigma_cells=3.0):
+    """Smooth heterogeneous 3-D medium spanning the given ranges (defaults: the
+    reconstruction-grid ranges of the paper's 3-D phantom, Table 3)."""
+    cm, ca = 0.5 * (c_range[0] + c_range[1]), 0.5 * (c_range[1] - c_range[0])
+    rm, ra = 0.5 * (rho_range[0] + rho_range[1]), 0.5 * (rho_range[1] - rho_range[0])
+    c0 = cm + ca * smooth_noise3d(n_z, n_y, n_x, sigma_cells, seed_c)
+    rho0 = rm + ra * smooth_noise3d(n_z, n_y, n_x, sigma_cells, seed_rho)
+    return c0, rho0
+
+
+def blobs3d(n_z: int, n_y: int, n_x: int, seed: int, *, count=5, radius_cells=None,
+            sigma_range=(1.5, 3.0), amp_range=(0.0, 1.0)) -> np.ndarray:
+    """Initial pressure: `count` Gaussian blobs with centres drawn uniformly in a
+    ball about the centre node."""
+    rng = _rng(seed)
+    if radius_cells is None:
+        radius_cells = 0.2 * min(n_x, n_y, n_z)
+    zz, yy, xx = np.mgrid[0:n_z, 0:n_y, 0:n_x].astype(np.float64)
+    out = np.zeros((n_z, n_y, n_x))
+    for _ in range(count):
+        d = rng.standard_normal(3)
+        d /= np.linalg.norm(d)
+        r = radius_cells * rng.uniform() ** (1.0 / 3.0)
+        cx, cy, cz = n_x / 2 + r * d[0], n_y / 2 + r * d[1], n_z / 2 + r * d[2]
+        sg = rng.uniform(*sigma_range)
+        a = rng.uniform(*amp_range)
+        out += a * np.exp(-((xx - cx) ** 2 + (yy - cy) ** 2 + (zz - cz) ** 2) / (2.0 * sg * sg))
+    return out
+
+
+def face_sensors(n: int, lo: int, d: float, n_grid: int) -> np.ndarray:
+    """Detectors at the nodes of two adjacent faces (x = lo and y = lo) of the
+    n x n x n block of nodes lo .. lo+n-1 of an n_grid^3 grid, the shared edge
+    once: 2 n^2 - n detectors (2145 for n = 33, as in the paper's 3-D
+    reconstruction).  Returns [ns, 3] positions (x, y, z) in metres, node i at
+    (i - n_grid/2) d."""
+    idx = np.arange(lo, lo + n)
+    pos = lambda i: (i - n_grid / 2) * d
+    pts = [(pos(lo), pos(j), pos(k)) for k in idx for j in idx]
+    pts += [(pos(i), pos(lo), pos(k)) for k in idx for i in idx if i != lo]
+    return np.asarray(pts, dtype=np.float64)
+
+
+def make_params3d(nx, ny, nz, dx, dt, nt, c_ref, sensor_xyz, *, dy=None, dz=None, pml_size=8,
+                  pml_alpha=2.0, alpha0_db=0.75, y=1.5) -> dict:
+    return dict(nx=int(nx), ny=int(ny), nz=int(nz), dx=float(dx), dy=float(dx if dy is None else dy),
+                dz=float(dx if dz is None else dz), dt=float(dt), nt=int(nt), c_ref=float(c_ref),
+                pml_size=int(pml_size), pml_alpha=float(pml_alpha), alpha0_db=float(alpha0_db), y=float(y),
+                sensor_xyz=np.ascontiguousarray(sensor_xyz, dtype=np.float64))
+
+
+def config3d(name: str = "vol33", *, seeds=(3300, 3301, 3302), cfl=0.3) -> dict:
+    """The 3-D reconstruction workload of the paper (Section 6.2): a 33^3 node
+    domain of spacing 0.3125 mm with an 8-cell PML added on every side (a 49^3
+    grid), Nt = 292, detectors at the 2145 nodes of two adjacent domain faces,
+    tissue absorption alpha0 = 0.75 dB MHz^-1.5 cm^-1, y = 1.5, a smooth
+    medium spanning Table 3's reconstruction ranges and Gaussian blobs for p0.
+    "vol37" is the data-generation grid: 37^3 nodes of 0.278 mm (53^3 with the
+    PML) with the same physical detector positions, off its nodes."""
+    if name == "vol33":
+        n, d = 33, 3.125e-4
+    elif name == "vol37":
+        n, d = 37, 2.78e-4
+    else:
+        raise KeyError(name)
+    pml = 8
+    ng = n + 2 * pml
+    sc, sr, sp = seeds
+    c0, rho0 = medium3d(ng, ng, ng, sc, sr, sigma_cells=3.0 * ng / 49)
+    p0 = blobs3d(ng, ng, ng, sp, radius_cells=0.25 * n, sigma_range=(1.5 * ng / 49, 3.0 * ng / 49))
+    cmax = float(c0.max())
+    sens = face_sensors(33, 8, 3.125e-4, 49)
+    prm = make_params3d(ng, ng, ng, d, cfl * d / cmax, 292, cmax, sens, pml_size=pml)
+    return dict(params=prm, c0=c0, rho0=rho0, p0=p0)
