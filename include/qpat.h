@@ -263,6 +263,60 @@ qpat_status qpat_tv_value(qpat_tv tv, const float* x, double beta, int32_t batch
 /* y = a x + b y over n device floats (the vector updates of Algorithm 4). */
 qpat_status qpat_axpby(int64_t n, float a, const float* x, float b, float* y, qpat_stream stream);
 
+/* ---- 3-D solver (Section 3.3.3 with d = 3: velocity and density with three
+ * components each, so the stacked state z_n of Section 3.3.4 holds 7N values,
+ * and the source of eq s1 puts p0 / (6 c0^2) into each density component at
+ * n = -1 and 0).  Conventions follow the 2-D solver axis by axis: fields are
+ * [nz][ny][nx] (x fastest), node (k, j, i) at ((i - nx/2) dx, (j - ny/2) dy,
+ * (k - nz/2) dz); the PML lies inside the grid on all six faces; the
+ * measurement M interpolates trilinearly from the 8 surrounding nodes.
+ *  nx, ny, nz  axis lengths in [4, 128]; every prime factor of 11 or more is
+ *              transformed by a direct DFT stage (e.g. 33, 37, 49, 53 are
+ *              supported); ny * nz <= 4096.
+ *  dz          spacing along z [m]; sensor_xyz host [ns][3] positions [m].
+ *  Other fields as in qpat_params.
+ * Work is in FP32 with the medium tables built in FP64 and rounded once.
+ * The 3-D plan has its own entry points; `batch` vectors run in one set of
+ * launches, in [1, 4096]. */
+typedef struct {
+  int32_t nx, ny, nz;
+  double dx, dy, dz, dt;
+  int32_t nt;
+  double c_ref;
+  int32_t pml_size;
+  double pml_alpha;
+  double alpha0_db;
+  double y;
+  int32_t ns;
+  const double* sensor_xyz;
+} qpat_params3d;
+typedef struct qpat_plan3d_s* qpat_plan3d;
+
+/* Host-only parameter check (sizes, values, sensors inside the grid). */
+qpat_status qpat3d_validate(const qpat_params3d* prm);
+/* c0, rho0: host [nz][ny][nx], finite and > 0.  QPAT_E_UNSTABLE when dt
+ * exceeds 2 asin(c_ref / max c0) / (c_ref |k|_max) with c_ref < max c0. */
+qpat_status qpat3d_plan_create(const qpat_params3d* prm, const double* c0, const double* rho0,
+                               qpat_plan3d* out);
+void qpat3d_plan_destroy(qpat_plan3d plan);
+/* H_a: p0 [B][nz][ny][nx] -> data [B][nt][ns]. */
+qpat_status qpat3d_forward(qpat_plan3d plan, const float* p0, float* data, int32_t batch, qpat_stream stream);
+/* H_a^*: residual [B][nt][ns] -> gradient [B][nz][ny][nx] (reverse mode of the forward). */
+qpat_status qpat3d_adjoint(qpat_plan3d plan, const float* res, float* grad, int32_t batch,
+                           qpat_stream stream);
+/* J^T J v = H_a^* H_a v: v [B][nz][ny][nx] -> out [B][nz][ny][nx]. */
+qpat_status qpat3d_jtjv(qpat_plan3d plan, const float* v, float* out, int32_t batch, qpat_stream stream);
+/* One spectral operator on B fields: op 0..7 = d/dx^+, d/dx^-, d/dy^+, d/dy^-,
+ * d/dz^+, d/dz^-, Y_dis, Y_abs (symbols as in qpat_op, with the 3-D |k|). */
+qpat_status qpat3d_apply(qpat_plan3d plan, int32_t op, const float* in, float* out, int32_t batch,
+                         qpat_stream stream);
+/* Launch shape: x-lines per row block (even, >= 2, at most 64) and spectrum
+ * columns per plane block (>= 1); both blocks must fit the 160 KB of LDS. */
+qpat_status qpat3d_set_tiles(qpat_plan3d plan, int32_t rows, int32_t cols);
+qpat_status qpat3d_get_tiles(qpat_plan3d plan, int32_t* rows, int32_t* cols);
+/* hipGraph capture and replay of whole 3-D solves (as qpat_set_graph). */
+qpat_status qpat3d_set_graph(qpat_plan3d plan, int32_t enable);
+
 /* Plan introspection: sizes and the device bytes the plan holds. */
 qpat_status qpat_plan_info(qpat_plan plan, int32_t* nx, int32_t* ny, int32_t* nt, int32_t* ns,
                            size_t* device_bytes);

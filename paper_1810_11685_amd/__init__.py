@@ -5,7 +5,8 @@ from ._lib import EXPORTED, LIB_PATH, QpatError, lib
 from .ops import Batch, Plan, dot, make_params, validate
 from .autograd import AcousticForward, acoustic, replay_states
 from .recon import TV, axpby, ld_reconstruct
+from .ops3d import Plan3D, validate3d
 
 __all__ = ["Plan", "Batch", "dot", "validate", "make_params", "acoustic", "AcousticForward", "TV", "axpby",
-           "ld_reconstruct",
+           "ld_reconstruct", "Plan3D", "validate3d",
            "replay_states", "QpatError", "lib", "LIB_PATH", "EXPORTED"]

@@ -32,6 +32,21 @@ class QpatParams(ctypes.Structure):
     ]
 
 
+class QpatParams3d(ctypes.Structure):
+    _fields_ = [
+        ("nx", c_int32), ("ny", c_int32), ("nz", c_int32),
+        ("dx", c_double), ("dy", c_double), ("dz", c_double), ("dt", c_double),
+        ("nt", c_int32),
+        ("c_ref", c_double),
+        ("pml_size", c_int32),
+        ("pml_alpha", c_double),
+        ("alpha0_db", c_double),
+        ("y", c_double),
+        ("ns", c_int32),
+        ("sensor_xyz", ctypes.POINTER(c_double)),
+    ]
+
+
 STATUS = {0: "QPAT_OK", 1: "QPAT_E_INVALID", 2: "QPAT_E_UNSUPPORTED", 3: "QPAT_E_UNSTABLE",
           4: "QPAT_E_HIP", 5: "QPAT_E_OOM"}
 
@@ -73,6 +88,16 @@ _SIGS = {
     "qpat_tv_value": (c_int32, [c_void_p, c_void_p, ctypes.c_double, c_int32, ctypes.POINTER(ctypes.c_double),
                                 c_void_p]),
     "qpat_axpby": (c_int32, [c_int64, ctypes.c_float, c_void_p, ctypes.c_float, c_void_p, c_void_p]),
+    "qpat3d_validate": (c_int32, [ctypes.POINTER(QpatParams3d)]),
+    "qpat3d_plan_create": (c_int32, [ctypes.POINTER(QpatParams3d), c_void_p, c_void_p, ctypes.POINTER(c_void_p)]),
+    "qpat3d_plan_destroy": (None, [c_void_p]),
+    "qpat3d_forward": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_void_p]),
+    "qpat3d_adjoint": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_void_p]),
+    "qpat3d_jtjv": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_void_p]),
+    "qpat3d_apply": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_int32, c_void_p]),
+    "qpat3d_set_tiles": (c_int32, [c_void_p, c_int32, c_int32]),
+    "qpat3d_get_tiles": (c_int32, [c_void_p, ctypes.POINTER(c_int32), ctypes.POINTER(c_int32)]),
+    "qpat3d_set_graph": (c_int32, [c_void_p, c_int32]),
     "qpat_plan_info": (c_int32, [c_void_p, ctypes.POINTER(c_int32), ctypes.POINTER(c_int32),
                                  ctypes.POINTER(c_int32), ctypes.POINTER(c_int32), ctypes.POINTER(c_size_t)]),
     "qpat_status_string": (ctypes.c_char_p, [c_int32]),

@@ -1,0 +1,617 @@
+// 3-D k-space PSTD passes for gfx950 (Section 3.3.3 with d = 3).
+//
+// One iterate is three (row pass, plane pass) pairs, as in 2-D:
+//   row pass   - rt consecutive x-lines: inverse x-FFT of the incoming half
+//                spectra (two real lines per complex FFT), the pointwise
+//                update of the scheme, forward x-FFT of the outgoing fields;
+//   plane pass - ct spectrum columns of every y-z plane: forward y- and
+//                z-FFTs, the k-space multiplier, inverse z- and y-FFTs.
+// The FFTs are mixed-radix Stockham transforms in LDS with a runtime plan per
+// axis: radices 2, 3, 4, 5, 7, 8 as butterflies, any other prime factor as a
+// direct DFT stage, so axis lengths such as 33, 37, 49 and 53 of the paper's
+// 3-D grids (with their PML) run without padding.
+#include "k3d_internal.hpp"
+
+namespace qpat3 {
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+
+// ---------------------------------------------------------------- small DFTs
+// cos and sin of 2 pi m / R for the odd radices (folded at compile time).
+__host__ __device__ constexpr float ucos(int R, int m) {
+  return R == 3 ? (m == 0 ? 1.0f : -0.5f)
+       : R == 5 ? (m == 0 ? 1.0f : (m == 1 || m == 4) ? 0.309016994f : -0.809016994f)
+       : (m == 0 ? 1.0f : (m == 1 || m == 6) ? 0.623489802f : (m == 2 || m == 5) ? -0.222520934f : -0.900968868f);
+}
+__host__ __device__ constexpr float usin(int R, int m) {
+  return R == 3 ? (m == 0 ? 0.0f : m == 1 ? 0.866025404f : -0.866025404f)
+       : R == 5 ? (m == 0 ? 0.0f : m == 1 ? 0.951056516f : m == 2 ? 0.587785252f : m == 3 ? -0.587785252f
+                                                                                    : -0.951056516f)
+       : (m == 0 ? 0.0f : m == 1 ? 0.781831482f : m == 2 ? 0.974927912f : m == 3 ? 0.433883739f
+          : m == 4 ? -0.433883739f : m == 5 ? -0.974927912f : -0.781831482f);
+}
+
+// x * (-i) (forward) or x * (+i) (inverse)
+template <bool INV>
+__device__ __forceinline__ float2 rot90(float2 x) {
+  return INV ? make_float2(-x.y, x.x) : make_float2(x.y, -x.x);
+}
+
+template <int R, bool INV>
+__device__ __forceinline__ void dft(float2* v) {
+  if constexpr (R == 2) {
+    const float2 a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  } else if constexpr (R == 4) {
+    const float2 s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
+    const float2 s13 = cadd(v[1], v[3]), d13 = rot90<INV>(csub(v[1], v[3]));
+    v[0] = cadd(s02, s13);
+    v[2] = csub(s02, s13);
+    v[1] = cadd(d02, d13);
+    v[3] = csub(d02, d13);
+  } else if constexpr (R == 8) {
+    float2 e[4] = {v[0], v[2], v[4], v[6]}, o[4] = {v[1], v[3], v[5], v[7]};
+    dft<4, INV>(e);
+    dft<4, INV>(o);
+    constexpr float h = 0.707106781f;
+    const float2 w1 = INV ? make_float2(h, h) : make_float2(h, -h);
+    const float2 w3 = INV ? make_float2(-h, h) : make_float2(-h, -h);
+    o[1] = cmul(o[1], w1);
+    o[2] = rot90<INV>(o[2]);
+    o[3] = cmul(o[3], w3);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      v[q] = cadd(e[q], o[q]);
+      v[q + 4] = csub(e[q], o[q]);
+    }
+  } else {
+    float2 out[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      float2 acc = v[0];
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        const int m = (r * q) % R;
+        const float c = ucos(R, m), s = INV ? usin(R, m) : -usin(R, m);
+        acc.x += v[r].x * c - v[r].y * s;
+        acc.y += v[r].x * s + v[r].y * c;
+      }
+      out[q] = acc;
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q) v[q] = out[q];
+  }
+}
+
+// ---------------------------------------------------------------- LDS line FFTs
+// Element e of line L sits at line_off(L) + e * es, line_off(L) = (L / lpg) *
+// gs + (L % lpg) * ls: x-lines of a row block, y- and z-lines of a plane block.
+struct LineMap {
+  int nlines, lpg, gs, ls, es;
+};
+__device__ __forceinline__ int line_off(const LineMap& m, int L) {
+  const int g = L / m.lpg;
+  return g * m.gs + (L - g * m.lpg) * m.ls;
+}
+
+// One Stockham stage of radix R over every line: butterfly j (of n/R) reads
+// src[j + r n/R], twiddles input r by w^(r k n/(Ns R)) with k = j mod Ns, and
+// writes dst[(j - k) R + k + r Ns].
+template <int R, bool INV>
+__device__ void stage_small(const float2* __restrict__ src, float2* __restrict__ dst, const LineMap& m, int n,
+                            int Ns, const float2* __restrict__ tw) {
+  const int nb = n / R, tstep = n / (Ns * R), total = m.nlines * nb;
+  for (int t = threadIdx.x; t < total; t += blockDim.x) {
+    const int L = t / nb, j = t - L * nb;
+    const int off = line_off(m, L);
+    const int k = j % Ns;
+    float2 v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = src[off + (j + r * nb) * m.es];
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+      float2 w = tw[r * k * tstep];
+      if (INV) w.y = -w.y;
+      v[r] = cmul(v[r], w);
+    }
+    dft<R, INV>(v);
+    const int base = (j - k) * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) dst[off + (base + r * Ns) * m.es] = v[r];
+  }
+}
+
+// A stage of a prime radix R without a butterfly of its own: every thread
+// computes one output as a direct sum of R twiddled inputs.
+template <bool INV>
+__device__ void stage_generic(const float2* __restrict__ src, float2* __restrict__ dst, const LineMap& m, int n,
+                              int Ns, int R, const float2* __restrict__ tw) {
+  const int nb = n / R, tstep = n / (Ns * R), total = m.nlines * n;
+  for (int t = threadIdx.x; t < total; t += blockDim.x) {
+    const int L = t / n, o = t - L * n;
+    const int off = line_off(m, L);
+    const int g = o / (Ns * R), rem = o - g * Ns * R, q = rem / Ns, k = rem - q * Ns;
+    const int j = g * Ns + k;
+    const int e = k * tstep + q * nb;   // < n
+    float2 acc = make_float2(0.f, 0.f);
+    int idx = 0;
+    for (int r = 0; r < R; ++r) {
+      float2 w = tw[idx];
+      if (INV) w.y = -w.y;
+      const float2 x = src[off + (j + r * nb) * m.es];
+      acc.x += x.x * w.x - x.y * w.y;
+      acc.y += x.x * w.y + x.y * w.x;
+      idx += e;
+      if (idx >= n) idx -= n;
+    }
+    dst[off + o * m.es] = acc;
+  }
+}
+
+// All stages of one axis (barrier after each); returns the buffer holding the
+// result (a or b).
+template <bool INV>
+__device__ float2* fft_axis(float2* a, float2* b, const LineMap& m, const AxisPlan& P, const float2* tw) {
+  float2* s = a;
+  float2* d = b;
+  int Ns = 1;
+  for (int st = 0; st < P.nst; ++st) {
+    const int R = P.r[st];
+    switch (R) {
+      case 2: stage_small<2, INV>(s, d, m, P.n, Ns, tw); break;
+      case 3: stage_small<3, INV>(s, d, m, P.n, Ns, tw); break;
+      case 4: stage_small<4, INV>(s, d, m, P.n, Ns, tw); break;
+      case 5: stage_small<5, INV>(s, d, m, P.n, Ns, tw); break;
+      case 7: stage_small<7, INV>(s, d, m, P.n, Ns, tw); break;
+      case 8: stage_small<8, INV>(s, d, m, P.n, Ns, tw); break;
+      default: stage_generic<INV>(s, d, m, P.n, Ns, R, tw); break;
+    }
+    __syncthreads();
+    float2* t = s;
+    s = d;
+    d = t;
+    Ns *= R;
+  }
+  return s;
+}
+
+// ---------------------------------------------------------------- block -> (item, tile)
+// Consecutive tiles of one item go to one XCD (work-groups are dispatched to
+// the XCDs round-robin).
+__device__ __forceinline__ bool locate(int nitems, int ntile, int chunk, int& item, int& tile) {
+  const int b = blockIdx.x;
+  const int i = (b & (kXcds - 1)) * chunk + (b / kXcds);
+  if (i >= nitems * ntile) return false;
+  item = i / ntile;
+  tile = i - item * ntile;
+  return true;
+}
+
+__device__ __forceinline__ Work3 shift(const Work3& w, long long off) {
+  Work3 r;
+  r.f = reinterpret_cast<float*>(reinterpret_cast<char*>(w.f) + off);
+  r.s = reinterpret_cast<float2*>(reinterpret_cast<char*>(w.s) + off);
+  r.part = reinterpret_cast<float*>(reinterpret_cast<char*>(w.part) + off);
+  return r;
+}
+
+__device__ __forceinline__ size_t spec_index(const Medium3& M, int f, int c, int l) {
+  return size_t(f) * M.ctiles * M.ct * M.nlines + size_t(c / M.ct) * (M.nlines * M.ct) + size_t(l) * M.ct +
+         (c % M.ct);
+}
+
+// ---------------------------------------------------------------- row pass
+template <int MODE>
+__device__ __forceinline__ void row_counts(const Medium3& M, int n, int& nin, int& nout) {
+  const bool first = (n == M.nt - 2);
+  switch (MODE) {
+    case R3_F1: nin = 3; nout = 3; break;
+    case R3_F2: nin = n == -1 ? 0 : 3; nout = 2; break;
+    case R3_F2L: nin = n == -1 ? 0 : 3; nout = 1; break;
+    case R3_F3: nin = 2; nout = 1; break;
+    case R3_A1: nin = first ? 0 : 1; nout = 2; break;
+    case R3_A1L: nin = first ? 0 : 1; nout = n == -1 ? 0 : 3; break;
+    case R3_A2: nin = 2; nout = n == -1 ? 0 : 3; break;
+    case R3_A3: nin = 3; nout = 3; break;
+    case R3_FWD1: nin = 0; nout = 1; break;
+    default: nin = 1; nout = 0; break;  // R3_INV1
+  }
+}
+
+// value of line j2 (of the tile) of field f in a buffer of paired lines
+__device__ __forceinline__ float& pc(float2* buf, int hp, int nx, int f, int j2, int x) {
+  float2& z = buf[(f * hp + (j2 >> 1)) * nx + x];
+  return (j2 & 1) ? z.y : z.x;
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(kBlock) row3_kernel(const Launch3 L, int ntile, int chunk, int n) {
+  int item, tile;
+  if (!locate(L.nitems, ntile, chunk, item, tile)) return;
+  const Medium3& M = L.m;
+  const Work3 W = shift(L.w0, item * L.wstride);
+  const IO3 X = L.io[item];
+  const int nx = M.nx, ny = M.ny, rt = M.rt, hp = rt / 2, nl = M.nlines;
+  const int l0 = tile * rt;
+  const unsigned N = unsigned(nl) * unsigned(nx);
+  const int B = blockDim.x, tid = threadIdx.x;
+  extern __shared__ float2 lds[];
+  float2* bufA = lds;
+  float2* bufB = lds + 3 * hp * nx;
+  float2* tw = lds + 6 * hp * nx;
+  int nin, nout;
+  row_counts<MODE>(M, n, nin, nout);
+  const bool first = (n == M.nt - 2);
+  const float dt = M.dt;
+
+  for (int i = tid; i < nx; i += B) tw[i] = M.twx[i];
+  // incoming half spectra -> full spectra of the paired lines (a + i b)
+  const int ncol = M.nxh1;
+  for (int t = tid; t < nin * ncol * hp; t += B) {
+    const int j = t % hp, fc = t / hp, c = fc % ncol, f = fc / ncol;
+    const int la = l0 + 2 * j, lb = la + 1;
+    const float2 a = la < nl ? W.s[spec_index(M, f, c, la)] : make_float2(0.f, 0.f);
+    const float2 b = lb < nl ? W.s[spec_index(M, f, c, lb)] : make_float2(0.f, 0.f);
+    float2* Z = bufA + (f * hp + j) * nx;
+    Z[c] = make_float2(a.x - b.y, a.y + b.x);
+    if (c != 0 && 2 * c != nx) Z[nx - c] = make_float2(a.x + b.y, b.x - a.y);
+  }
+  if (nin == 0) {
+    for (int t = tid; t < 3 * hp * nx; t += B) bufA[t] = make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  float2* R = bufA;
+  if (nin > 0) {
+    const LineMap lm{nin * hp, nin * hp, 0, nx, 1};
+    R = fft_axis<true>(bufA, bufB, lm, M.px, tw);
+  }
+  float2* O = (R == bufA) ? bufB : bufA;
+
+  if constexpr (MODE == R3_A1 || MODE == R3_A1L) {
+    // p* = -(sum_i d_i^- g_i) + M^T r_{n+1}
+    for (int t = tid; t < hp * nx; t += B) {
+      const float2 z = R[t];
+      R[t] = make_float2(-z.x, -z.y);
+    }
+    __syncthreads();
+    if (tid < rt && l0 + tid < nl) {
+      const int l = l0 + tid;
+      const float* r = X.in + size_t(n + 1) * M.ns;
+      for (int e = M.tap_off[l]; e < M.tap_off[l + 1]; ++e) {
+        const Tap3 tp = M.taps[e];
+        const float rv = r[tp.s];
+        pc(R, hp, nx, 0, tid, tp.ixl) += tp.wl * rv;
+        pc(R, hp, nx, 0, tid, tp.ixr) += tp.wr * rv;
+      }
+    }
+    __syncthreads();
+  }
+
+  for (int t = tid; t < rt * nx; t += B) {
+    const int j2 = t / nx, x = t - j2 * nx, l = l0 + j2;
+    if (l >= nl) {
+      for (int o = 0; o < nout; ++o) pc(O, hp, nx, o, j2, x) = 0.f;
+      continue;
+    }
+    const int z = l / ny, y = l - z * ny;
+    const unsigned idx = unsigned(l) * unsigned(nx) + unsigned(x);
+    float* const fv = W.f;   // v_x v_y v_z rho_x rho_y rho_z q
+    if constexpr (MODE == R3_F1) {
+      const float av[3] = {M.avx[x], M.avy[y], M.avz[z]};
+      const float bb[3] = {M.bx[idx], M.by[idx], M.bz[idx]};
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const float g = pc(R, hp, nx, i, j2, x);
+        const float vo = (n == 0) ? 0.f : fv[i * N + idx];
+        const float v = av[i] * (av[i] * vo - bb[i] * g);
+        fv[i * N + idx] = v;
+        pc(O, hp, nx, i, j2, x) = v;
+      }
+    } else if constexpr (MODE == R3_F2 || MODE == R3_F2L) {
+      const bool skip = (n == -1);
+      const float ar[3] = {M.arx[x], M.ary[y], M.arz[z]};
+      const float r0 = M.rho0[idx], c2 = M.c2[idx];
+      const float src = (n <= 0) ? X.in[idx] * (1.0f / 6.0f) / c2 : 0.f;   // p0 / (2 d c^2), d = 3
+      float S = 0.f, u = 0.f;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const float e = skip ? 0.f : pc(R, hp, nx, i, j2, x);
+        const float ro = skip ? 0.f : fv[(3 + i) * N + idx];
+        const float rho = ar[i] * (ar[i] * ro - dt * r0 * e) + src;
+        fv[(3 + i) * N + idx] = rho;
+        S += rho;
+        u += ar[i] * e;
+      }
+      if constexpr (MODE == R3_F2) {
+        pc(O, hp, nx, 0, j2, x) = S;
+        pc(O, hp, nx, 1, j2, x) = r0 * u;
+      } else {
+        const float p = c2 * S;
+        fv[6 * N + idx] = p;
+        pc(O, hp, nx, 0, j2, x) = p;
+      }
+    } else if constexpr (MODE == R3_F3) {
+      const float S = fv[3 * N + idx] + fv[4 * N + idx] + fv[5 * N + idx];
+      const float ys = pc(R, hp, nx, 0, j2, x), yu = pc(R, hp, nx, 1, j2, x);
+      const float p = M.c2[idx] * S - M.c2eta[idx] * ys + M.c2tau[idx] * yu;
+      fv[6 * N + idx] = p;
+      pc(O, hp, nx, 0, j2, x) = p;
+    } else if constexpr (MODE == R3_A1) {
+      const float pb = pc(R, hp, nx, 0, j2, x);
+      fv[6 * N + idx] = M.c2[idx] * pb;
+      pc(O, hp, nx, 0, j2, x) = M.c2eta[idx] * pb;
+      pc(O, hp, nx, 1, j2, x) = M.c2tau[idx] * pb;
+    } else if constexpr (MODE == R3_A1L || MODE == R3_A2) {
+      const float ar[3] = {M.arx[x], M.ary[y], M.arz[z]};
+      const float r0 = M.rho0[idx], c2 = M.c2[idx];
+      float sb, ub;
+      if constexpr (MODE == R3_A1L) {
+        sb = c2 * pc(R, hp, nx, 0, j2, x);
+        ub = 0.f;
+      } else {
+        sb = fv[6 * N + idx] - pc(R, hp, nx, 0, j2, x);
+        ub = pc(R, hp, nx, 1, j2, x);
+      }
+      float rb[3], sum = 0.f;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        rb[i] = (first ? 0.f : fv[(3 + i) * N + idx]) + sb;
+        sum += rb[i];
+      }
+      if (n == 0) X.out[idx] = sum;
+      if (n == -1) {
+        const float acc = M.nt >= 2 ? X.out[idx] : 0.f;
+        X.out[idx] = (sum + acc) * (1.0f / 6.0f) / c2;
+      } else {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          pc(O, hp, nx, i, j2, x) = r0 * ar[i] * (ub - dt * rb[i]);
+          fv[(3 + i) * N + idx] = ar[i] * ar[i] * rb[i];
+        }
+      }
+    } else if constexpr (MODE == R3_A3) {
+      const float av[3] = {M.avx[x], M.avy[y], M.avz[z]};
+      const float bb[3] = {M.bx[idx], M.by[idx], M.bz[idx]};
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const float vb = (first ? 0.f : fv[i * N + idx]) - pc(R, hp, nx, i, j2, x);
+        pc(O, hp, nx, i, j2, x) = -av[i] * bb[i] * vb;
+        fv[i * N + idx] = av[i] * av[i] * vb;
+      }
+    } else if constexpr (MODE == R3_FWD1) {
+      pc(O, hp, nx, 0, j2, x) = X.in[idx];
+    } else {  // R3_INV1
+      X.out[idx] = pc(R, hp, nx, 0, j2, x);
+    }
+  }
+  __syncthreads();
+
+  if constexpr (MODE == R3_F2L || MODE == R3_F3) {
+    // sensor partials of this tile's lines: part[n+1][s][slot]
+    const int e0 = M.tap_off[l0], e1 = M.tap_off[min(l0 + rt, nl)];
+    for (int e = e0 + tid; e < e1; e += B) {
+      const Tap3 tp = M.taps[e];
+      const int j2 = tp.line - l0;
+      W.part[(size_t(n + 1) * M.ns + tp.s) * 4 + tp.slot] =
+          tp.wl * pc(O, hp, nx, 0, j2, tp.ixl) + tp.wr * pc(O, hp, nx, 0, j2, tp.ixr);
+    }
+  }
+  if (nout == 0) return;
+
+  // outgoing fields -> half spectra of each line
+  const LineMap lm{nout * hp, nout * hp, 0, nx, 1};
+  float2* Z = fft_axis<false>(O, R, lm, M.px, tw);
+  for (int t = tid; t < nout * ncol * hp; t += B) {
+    const int j = t % hp, oc = t / hp, c = oc % ncol, o = oc / ncol;
+    const float2* Zl = Z + (o * hp + j) * nx;
+    const float2 zk = Zl[c], zm = Zl[c == 0 ? 0 : nx - c];
+    const int la = l0 + 2 * j, lb = la + 1;
+    if (la < nl) W.s[spec_index(M, o, c, la)] = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
+    if (lb < nl) W.s[spec_index(M, o, c, lb)] = make_float2(0.5f * (zk.y + zm.y), 0.5f * (zm.x - zk.x));
+  }
+}
+
+// ---------------------------------------------------------------- plane pass
+__device__ __forceinline__ float2 symbol(const Medium3& M, int code, int col, int y, int z) {
+  const size_t k = (size_t(z) * M.ny + y) * M.nxh1 + col;
+  switch (code) {
+    case OP_DXP: return cscale(M.dxp[col], M.kap[k]);
+    case OP_DXM: return cscale(M.dxm[col], M.kap[k]);
+    case OP_DYP: return cscale(M.dyp[y], M.kap[k]);
+    case OP_DYM: return cscale(M.dym[y], M.kap[k]);
+    case OP_DZP: return cscale(M.dzp[z], M.kap[k]);
+    case OP_DZM: return cscale(M.dzm[z], M.kap[k]);
+    case OP_LDIS: return make_float2(M.ldis[k], 0.f);
+    default: return make_float2(M.labs[k], 0.f);
+  }
+}
+
+template <int MODE>
+__device__ __forceinline__ int plane_code(int f, int code) {
+  switch (MODE) {
+    case P3_GRADP1:
+    case P3_GRADP2: return f == 0 ? OP_DXP : f == 1 ? OP_DYP : OP_DZP;
+    case P3_GRADM2:
+    case P3_DIVM: return f == 0 ? OP_DXM : f == 1 ? OP_DYM : OP_DZM;
+    case P3_FRAC: return f == 0 ? OP_LDIS : OP_LABS;
+    default: return code;
+  }
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(kBlock) plane3_kernel(const Launch3 L, int ntile, int chunk, int code, int n) {
+  int item, tile;
+  if (!locate(L.nitems, ntile, chunk, item, tile)) return;
+  const Medium3& M = L.m;
+  const Work3 W = shift(L.w0, item * L.wstride);
+  const int ct = M.ct, ny = M.ny, nz = M.nz, nl = M.nlines;
+  const int c0 = tile * ct, ncols = min(ct, M.nxh1 - c0);
+  const int cnt = nl * ct;
+  const int B = blockDim.x, tid = threadIdx.x;
+  extern __shared__ float2 lds[];
+  float2* b0 = lds;
+  float2* b1 = lds + cnt;
+  float2* b2 = lds + 2 * cnt;
+  float2* twy = lds + 3 * cnt;
+  float2* twz = twy + ny;
+  for (int i = tid; i < ny; i += B) twy[i] = M.twy[i];
+  for (int i = tid; i < nz; i += B) twz[i] = M.twz[i];
+  const size_t specN = size_t(M.ctiles) * ct * nl;
+  auto chunk_of = [&](int f) { return W.s + size_t(f) * specN + size_t(tile) * cnt; };
+  // y-lines: (z, c) -> z * ny * ct + c, stride ct; z-lines: (y, c) -> y * ct + c, stride ny * ct
+  const LineMap my{nz * ct, ct, ny * ct, 1, ct};
+  const LineMap mz{ny * ct, ny * ct, 0, 1, ny * ct};
+  auto fwd = [&](float2* a, float2* b) {
+    float2* r = fft_axis<false>(a, b, my, M.py, twy);
+    return fft_axis<false>(r, r == a ? b : a, mz, M.pz, twz);
+  };
+  auto inv = [&](float2* a, float2* b) {
+    float2* r = fft_axis<true>(a, b, mz, M.pz, twz);
+    return fft_axis<true>(r, r == a ? b : a, my, M.py, twy);
+  };
+  auto load = [&](int f, float2* dst) {
+    const float2* src = chunk_of(f);
+    for (int i = tid; i < cnt; i += B) dst[i] = src[i];
+  };
+  auto store = [&](int f, const float2* src) {
+    float2* dst = chunk_of(f);
+    for (int i = tid; i < cnt; i += B) dst[i] = src[i];
+  };
+  // multiplier at chunk element i for operator `cd` (0 in the padding columns)
+  auto mult = [&](int cd, int i) {
+    const int c = i % ct, l = i / ct, z = l / ny, y = l - z * ny;
+    return c < ncols ? symbol(M, cd, c0 + c, y, z) : make_float2(0.f, 0.f);
+  };
+
+  if constexpr (MODE == P3_GRADP1) {
+    load(0, b0);
+    __syncthreads();
+    float2* F = fwd(b0, b1);
+    float2* x1 = (F == b0) ? b1 : b0;
+    float2* x2 = b2;
+    for (int o = 0; o < 3; ++o) {
+      const int cd = plane_code<MODE>(o, code);
+      for (int i = tid; i < cnt; i += B) x1[i] = cmul(F[i], mult(cd, i));
+      __syncthreads();
+      store(o, inv(x1, x2));
+      __syncthreads();
+    }
+  } else if constexpr (MODE == P3_DIVM) {
+    float2* acc = b2;
+    for (int f = 0; f < 3; ++f) {
+      load(f, b0);
+      __syncthreads();
+      float2* F = fwd(b0, b1);
+      const int cd = plane_code<MODE>(f, code);
+      for (int i = tid; i < cnt; i += B) {
+        const float2 v = cmul(F[i], mult(cd, i));
+        acc[i] = f == 0 ? v : cadd(acc[i], v);
+      }
+      __syncthreads();
+    }
+    store(0, inv(acc, b0));
+  } else {
+    const int nf = (MODE == P3_APPLY) ? 1 : (MODE == P3_FRAC) ? 2 : 3;
+    for (int f = 0; f < nf; ++f) {
+      load(f, b0);
+      __syncthreads();
+      float2* F = fwd(b0, b1);
+      const int cd = plane_code<MODE>(f, code);
+      for (int i = tid; i < cnt; i += B) F[i] = cmul(F[i], mult(cd, i));
+      __syncthreads();
+      store(f, inv(F, F == b0 ? b1 : b0));
+      __syncthreads();
+    }
+  }
+}
+
+// ---------------------------------------------------------------- sensor data
+__global__ void combine3_kernel(const Launch3 L) {
+  const Medium3& M = L.m;
+  const Work3 W = shift(L.w0, blockIdx.y * L.wstride);
+  float* out = L.io[blockIdx.y].out;
+  const int total = M.nt * M.ns;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+    const float* p = W.part + size_t(i) * 4;
+    out[i] = (p[0] + p[1]) + (p[2] + p[3]);
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+template <int MODE>
+static hipError_t row_t(const Launch3& L, int ntile, int chunk, int n, size_t lds, hipStream_t st) {
+  hipLaunchKernelGGL(row3_kernel<MODE>, dim3(chunk * kXcds), dim3(kBlock), lds, st, L, ntile, chunk, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_row3(int mode, const Launch3& L, int ntile, int chunk, int n, hipStream_t st) {
+  const size_t lds = row3_lds(L.m.nx, L.m.rt);
+  switch (mode) {
+    case R3_F1: return row_t<R3_F1>(L, ntile, chunk, n, lds, st);
+    case R3_F2: return row_t<R3_F2>(L, ntile, chunk, n, lds, st);
+    case R3_F2L: return row_t<R3_F2L>(L, ntile, chunk, n, lds, st);
+    case R3_F3: return row_t<R3_F3>(L, ntile, chunk, n, lds, st);
+    case R3_A1: return row_t<R3_A1>(L, ntile, chunk, n, lds, st);
+    case R3_A1L: return row_t<R3_A1L>(L, ntile, chunk, n, lds, st);
+    case R3_A2: return row_t<R3_A2>(L, ntile, chunk, n, lds, st);
+    case R3_A3: return row_t<R3_A3>(L, ntile, chunk, n, lds, st);
+    case R3_FWD1: return row_t<R3_FWD1>(L, ntile, chunk, n, lds, st);
+    case R3_INV1: return row_t<R3_INV1>(L, ntile, chunk, n, lds, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int MODE>
+static hipError_t plane_t(const Launch3& L, int ntile, int chunk, int code, int n, size_t lds, hipStream_t st) {
+  hipLaunchKernelGGL(plane3_kernel<MODE>, dim3(chunk * kXcds), dim3(kBlock), lds, st, L, ntile, chunk, code, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_plane3(int mode, int code, const Launch3& L, int ntile, int chunk, int n, hipStream_t st) {
+  const size_t lds = plane3_lds(L.m.ny, L.m.nz, L.m.ct);
+  switch (mode) {
+    case P3_GRADP1: return plane_t<P3_GRADP1>(L, ntile, chunk, code, n, lds, st);
+    case P3_GRADM2: return plane_t<P3_GRADM2>(L, ntile, chunk, code, n, lds, st);
+    case P3_FRAC: return plane_t<P3_FRAC>(L, ntile, chunk, code, n, lds, st);
+    case P3_GRADP2: return plane_t<P3_GRADP2>(L, ntile, chunk, code, n, lds, st);
+    case P3_DIVM: return plane_t<P3_DIVM>(L, ntile, chunk, code, n, lds, st);
+    case P3_APPLY: return plane_t<P3_APPLY>(L, ntile, chunk, code, n, lds, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_combine3(const Launch3& L, hipStream_t st) {
+  int bx = (L.m.nt * L.m.ns + kBlock - 1) / kBlock;
+  if (bx > 1024) bx = 1024;
+  if (bx < 1) bx = 1;
+  hipLaunchKernelGGL(combine3_kernel, dim3(bx, L.nitems), dim3(kBlock), 0, st, L);
+  return hipGetLastError();
+}
+
+template <typename K>
+static hipError_t allow(K* k, size_t bytes) {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             int(bytes));
+}
+
+hipError_t k3d_allow_lds(size_t bytes) {
+  const hipError_t es[] = {allow(&row3_kernel<R3_F1>, bytes),      allow(&row3_kernel<R3_F2>, bytes),
+                           allow(&row3_kernel<R3_F2L>, bytes),     allow(&row3_kernel<R3_F3>, bytes),
+                           allow(&row3_kernel<R3_A1>, bytes),      allow(&row3_kernel<R3_A1L>, bytes),
+                           allow(&row3_kernel<R3_A2>, bytes),      allow(&row3_kernel<R3_A3>, bytes),
+                           allow(&row3_kernel<R3_FWD1>, bytes),    allow(&row3_kernel<R3_INV1>, bytes),
+                           allow(&plane3_kernel<P3_GRADP1>, bytes), allow(&plane3_kernel<P3_GRADM2>, bytes),
+                           allow(&plane3_kernel<P3_FRAC>, bytes),   allow(&plane3_kernel<P3_GRADP2>, bytes),
+                           allow(&plane3_kernel<P3_DIVM>, bytes),   allow(&plane3_kernel<P3_APPLY>, bytes)};
+  for (hipError_t e : es)
+    if (e != hipSuccess) return e;
+  return hipSuccess;
+}
+
+}  // namespace qpat3

@@ -11,6 +11,7 @@ import pytest
 
 import qpat_inputs as qi
 from oracle import kspace as K
+from oracle import kspace3d as K3
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "qpat.h")
@@ -27,7 +28,7 @@ def q():
 def declared():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(qpat_[a-z_0-9]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(qpat(?:3d)?_[a-z_0-9]+)\s*\(", src)))
 
 
 def test_exports_every_declared_symbol(q):
@@ -101,3 +102,40 @@ def test_stability_bound_agrees_with_oracle(q):
         q.Plan(good(dt=0.999 * lim, c_ref=cref), c0, rho0)
     except q.QpatError as e2:
         assert e2.status in (4, 5)
+
+
+# ---------------------------------------------------------------- 3-D
+def good3(**kw):
+    sens = np.array([[0.0, 0.0, 0.0], [1e-4, -2e-4, 3e-4]])
+    prm = qi.make_params3d(49, 33, 20, 1e-4, 2e-8, 30, 1600.0, sens, pml_size=6)
+    prm.update(kw)
+    return prm
+
+
+@pytest.mark.parametrize("kw,status", [
+    ({}, 0), ({"nx": 37, "ny": 53, "nz": 13}, 0), ({"nz": 12}, 1), ({"nx": 128, "ny": 64, "nz": 64}, 0),
+    ({"nx": 3}, 2), ({"nx": 129}, 2), ({"ny": 128, "nz": 64}, 2), ({"nz": 256}, 2),
+    ({"dz": 0.0}, 1), ({"nt": 0}, 1), ({"pml_size": 10}, 1), ({"alpha0_db": -1.0}, 1), ({"y": 1.0}, 1),
+    ({"sensor_xyz": np.array([[0.0, 0.0, 1.1e-3]])}, 1), ({"sensor_xyz": np.array([[0.0, 0.0, 0.9e-3]])}, 0),
+    ({"sensor_xyz": np.zeros((0, 3))}, 0),
+])
+def test_validate3d(q, kw, status):
+    assert q.validate3d(good3(**kw)) == status
+
+
+def test_plan3d_host_checks(q):
+    c0, rho0 = qi.medium3d(20, 33, 49, 1, 2)
+    bad = c0.copy()
+    bad[1, 2, 3] = 0.0
+    with pytest.raises(q.QpatError) as e:
+        q.Plan3D(good3(), bad, rho0)
+    assert e.value.status == 1
+    cref = 0.6 * c0.max()
+    lim = K3.stability_limit(c0.max(), cref, 1e-4, 1e-4, 1e-4)
+    with pytest.raises(q.QpatError) as e:
+        q.Plan3D(good3(dt=1.001 * lim, c_ref=cref), c0, rho0)
+    assert e.value.status == 3
+    L = q.lib()
+    assert L.qpat3d_validate(None) == 1
+    assert L.qpat3d_forward(None, None, None, 1, None) == 1
+    assert L.qpat3d_set_tiles(None, 2, 1) == 1
