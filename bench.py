@@ -52,6 +52,18 @@ PASS_BYTES = {
 }
 
 
+def bytes_3d_pair(nx: int) -> float:
+    """Algorithmic HBM bytes per grid point of one lossy 3-D forward + adjoint
+    iterate pair.  A half spectrum holds h = (nx/2 + 1)/nx complex values per
+    point (8h bytes).  Forward: plane d_i^+ p 36h, row velocity 36 + 48h,
+    plane d_i^- v 52h, row density 28 + 40h, plane Y terms 40h, row pressure
+    24 + 24h; adjoint: row p* 16 + 24h, plane Y terms 40h, row density
+    32 + 40h, plane d_i^+ 52h, row velocity 36 + 48h, plane divergence 36h
+    (fields 4 B, spectra 8h B, k-space tables 4h B per point)."""
+    h = (nx // 2 + 1) / nx
+    return 172.0 + 480.0 * h
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -124,6 +136,7 @@ def main():
     ap.add_argument("--graph", choices=["on", "off"], default="on")
     ap.add_argument("--no-recon", action="store_true", help="skip the reconstruction-driver measurement")
     ap.add_argument("--no-medium", action="store_true", help="skip the sound-speed gradient measurement")
+    ap.add_argument("--no-3d", action="store_true", help="skip the 3-D solver measurement")
     ap.add_argument("--tiles", default=None,
                     help="launch shape rows,cols,row_threads,col_threads of the headline plan (skips tuning)")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work")
@@ -398,6 +411,44 @@ def main():
                     torch.cuda.empty_cache()
         out["medium_grad"] = {"workload": "sound-speed gradient d<r, H_a[c0] p0>/dc0 of the 512x512 Nt=2000 "
                                           "workload (grad_p0 as a by-product)", "runs": mg}
+
+    # ------------------------------------------------------------ 3-D solver
+    # The paper's 3-D reconstruction grid: 33^3 nodes plus an 8-cell PML
+    # (49^3), Nt = 292, 2145 detectors on two faces; forward + adjoint for one
+    # vector, for the three illuminations of the paper side by side, and for
+    # 16 Krylov vectors.
+    if not args.no_3d:
+        c3 = qi.config3d("vol33")
+        p3 = c3["params"]
+        n3, nt3, ns3 = p3["nx"] * p3["ny"] * p3["nz"], p3["nt"], p3["sensor_xyz"].shape[0]
+        BYTES_3D_PAIR = bytes_3d_pair(p3["nx"])
+        plan3 = q.Plan3D(p3, c3["c0"], c3["rho0"])
+        plan3.set_graph(args.graph == "on")
+        runs = {}
+        with torch.cuda.stream(stream):
+            for b in (1, 3, 16):
+                x3 = T(np.stack([c3["p0"]] * b))
+                r3 = T(qi.gaussian_field((b, nt3, ns3), 3303))
+                plan3.forward(x3, stream=stream)
+                plan3.adjoint(r3, stream=stream)
+                sync()
+                t = time.perf_counter()
+                for _ in range(2):
+                    plan3.forward(x3, stream=stream)
+                    plan3.adjoint(r3, stream=stream)
+                sync()
+                dt3 = (time.perf_counter() - t) / 2
+                gps3 = 2.0 * n3 * nt3 * b / dt3
+                runs[f"B{b}"] = {"batch": b, "ms": round(dt3 * 1e3, 2), "grid_point_steps_per_s": round(gps3, 1),
+                                 "algorithmic_GB_s": round(gps3 / 2 * BYTES_3D_PAIR / 1e9, 1)}
+                log(f"3-D 49^3 Nt=292 forward+adjoint B={b}: {dt3 * 1e3:.1f} ms -> {gps3:.3e} grid-point-steps/s")
+                del x3, r3
+        out["vol33"] = {"workload": "3-D: 33^3 nodes of 0.3125 mm plus an 8-cell PML (49^3 grid), Nt=292, "
+                                    "2145 detectors on two faces, lossy (alpha0=0.75, y=1.5), forward + adjoint",
+                        "tiles": list(plan3.tiles()), "bytes_per_point_per_iterate_pair": BYTES_3D_PAIR,
+                        "runs": runs}
+        del plan3
+        torch.cuda.empty_cache()
 
     # ------------------------------------------------------------ CPU baseline (oracle)
     if not args.no_cpu:

@@ -310,10 +310,15 @@ qpat_status qpat3d_jtjv(qpat_plan3d plan, const float* v, float* out, int32_t ba
  * d/dz^+, d/dz^-, Y_dis, Y_abs (symbols as in qpat_op, with the 3-D |k|). */
 qpat_status qpat3d_apply(qpat_plan3d plan, int32_t op, const float* in, float* out, int32_t batch,
                          qpat_stream stream);
-/* Launch shape: x-lines per row block (even, >= 2, at most 64) and spectrum
- * columns per plane block (>= 1); both blocks must fit the 160 KB of LDS. */
-qpat_status qpat3d_set_tiles(qpat_plan3d plan, int32_t rows, int32_t cols);
-qpat_status qpat3d_get_tiles(qpat_plan3d plan, int32_t* rows, int32_t* cols);
+/* Launch shape: x-lines per row block (even, >= 2, at most 64), spectrum
+ * columns per plane block (>= 1), threads per row block (64..512) and per
+ * plane block (64..1024, powers of two); both blocks must fit the 160 KB of
+ * LDS.  Results do not depend on the shape.  row_threads / plane_threads may
+ * be NULL in qpat3d_get_tiles. */
+qpat_status qpat3d_set_tiles(qpat_plan3d plan, int32_t rows, int32_t cols, int32_t row_threads,
+                             int32_t plane_threads);
+qpat_status qpat3d_get_tiles(qpat_plan3d plan, int32_t* rows, int32_t* cols, int32_t* row_threads,
+                             int32_t* plane_threads);
 /* hipGraph capture and replay of whole 3-D solves (as qpat_set_graph). */
 qpat_status qpat3d_set_graph(qpat_plan3d plan, int32_t enable);
 

@@ -95,8 +95,9 @@ _SIGS = {
     "qpat3d_adjoint": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_void_p]),
     "qpat3d_jtjv": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_void_p]),
     "qpat3d_apply": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_int32, c_void_p]),
-    "qpat3d_set_tiles": (c_int32, [c_void_p, c_int32, c_int32]),
-    "qpat3d_get_tiles": (c_int32, [c_void_p, ctypes.POINTER(c_int32), ctypes.POINTER(c_int32)]),
+    "qpat3d_set_tiles": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_int32]),
+    "qpat3d_get_tiles": (c_int32, [c_void_p, ctypes.POINTER(c_int32), ctypes.POINTER(c_int32),
+                                   ctypes.POINTER(c_int32), ctypes.POINTER(c_int32)]),
     "qpat3d_set_graph": (c_int32, [c_void_p, c_int32]),
     "qpat_plan_info": (c_int32, [c_void_p, ctypes.POINTER(c_int32), ctypes.POINTER(c_int32),
                                  ctypes.POINTER(c_int32), ctypes.POINTER(c_int32), ctypes.POINTER(c_size_t)]),

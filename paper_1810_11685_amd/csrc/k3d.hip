@@ -21,6 +21,11 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
 }
 __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
 
+// floor(a / d) for 0 <= a < 2^21, d >= 1, from rd = 1/d: (a + 1/2) / d lies at
+// least 1/(2d) from an integer and the float product errs by less than that.
+__device__ __forceinline__ int udiv(int a, float rd) { return int((float(a) + 0.5f) * rd); }
+__device__ __forceinline__ float rcp(int d) { return 1.0f / float(d); }
+
 // ---------------------------------------------------------------- small DFTs
 // cos and sin of 2 pi m / R for the odd radices (folded at compile time).
 __host__ __device__ constexpr float ucos(int R, int m) {
@@ -95,8 +100,8 @@ __device__ __forceinline__ void dft(float2* v) {
 struct LineMap {
   int nlines, lpg, gs, ls, es;
 };
-__device__ __forceinline__ int line_off(const LineMap& m, int L) {
-  const int g = L / m.lpg;
+__device__ __forceinline__ int line_off(const LineMap& m, int L, float rlpg) {
+  const int g = udiv(L, rlpg);
   return g * m.gs + (L - g * m.lpg) * m.ls;
 }
 
@@ -107,10 +112,11 @@ template <int R, bool INV>
 __device__ void stage_small(const float2* __restrict__ src, float2* __restrict__ dst, const LineMap& m, int n,
                             int Ns, const float2* __restrict__ tw) {
   const int nb = n / R, tstep = n / (Ns * R), total = m.nlines * nb;
+  const float rnb = rcp(nb), rns = rcp(Ns), rlpg = rcp(m.lpg);
   for (int t = threadIdx.x; t < total; t += blockDim.x) {
-    const int L = t / nb, j = t - L * nb;
-    const int off = line_off(m, L);
-    const int k = j % Ns;
+    const int L = udiv(t, rnb), j = t - L * nb;
+    const int off = line_off(m, L, rlpg);
+    const int k = j - udiv(j, rns) * Ns;
     float2 v[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) v[r] = src[off + (j + r * nb) * m.es];
@@ -133,10 +139,11 @@ template <bool INV>
 __device__ void stage_generic(const float2* __restrict__ src, float2* __restrict__ dst, const LineMap& m, int n,
                               int Ns, int R, const float2* __restrict__ tw) {
   const int nb = n / R, tstep = n / (Ns * R), total = m.nlines * n;
+  const float rn = rcp(n), rnsr = rcp(Ns * R), rns = rcp(Ns), rlpg = rcp(m.lpg);
   for (int t = threadIdx.x; t < total; t += blockDim.x) {
-    const int L = t / n, o = t - L * n;
-    const int off = line_off(m, L);
-    const int g = o / (Ns * R), rem = o - g * Ns * R, q = rem / Ns, k = rem - q * Ns;
+    const int L = udiv(t, rn), o = t - L * n;
+    const int off = line_off(m, L, rlpg);
+    const int g = udiv(o, rnsr), rem = o - g * Ns * R, q = udiv(rem, rns), k = rem - q * Ns;
     const int j = g * Ns + k;
     const int e = k * tstep + q * nb;   // < n
     float2 acc = make_float2(0.f, 0.f);
@@ -231,7 +238,7 @@ __device__ __forceinline__ float& pc(float2* buf, int hp, int nx, int f, int j2,
 }
 
 template <int MODE>
-__global__ void __launch_bounds__(kBlock) row3_kernel(const Launch3 L, int ntile, int chunk, int n) {
+__global__ void __launch_bounds__(kRowMax) row3_kernel(const Launch3 L, int ntile, int chunk, int n) {
   int item, tile;
   if (!locate(L.nitems, ntile, chunk, item, tile)) return;
   const Medium3& M = L.m;
@@ -253,8 +260,9 @@ __global__ void __launch_bounds__(kBlock) row3_kernel(const Launch3 L, int ntile
   for (int i = tid; i < nx; i += B) tw[i] = M.twx[i];
   // incoming half spectra -> full spectra of the paired lines (a + i b)
   const int ncol = M.nxh1;
+  const float rhp = rcp(hp), rncol = rcp(ncol), rnx = rcp(nx), rny = rcp(ny);
   for (int t = tid; t < nin * ncol * hp; t += B) {
-    const int j = t % hp, fc = t / hp, c = fc % ncol, f = fc / ncol;
+    const int fc = udiv(t, rhp), j = t - fc * hp, f = udiv(fc, rncol), c = fc - f * ncol;
     const int la = l0 + 2 * j, lb = la + 1;
     const float2 a = la < nl ? W.s[spec_index(M, f, c, la)] : make_float2(0.f, 0.f);
     const float2 b = lb < nl ? W.s[spec_index(M, f, c, lb)] : make_float2(0.f, 0.f);
@@ -294,12 +302,12 @@ __global__ void __launch_bounds__(kBlock) row3_kernel(const Launch3 L, int ntile
   }
 
   for (int t = tid; t < rt * nx; t += B) {
-    const int j2 = t / nx, x = t - j2 * nx, l = l0 + j2;
+    const int j2 = udiv(t, rnx), x = t - j2 * nx, l = l0 + j2;
     if (l >= nl) {
       for (int o = 0; o < nout; ++o) pc(O, hp, nx, o, j2, x) = 0.f;
       continue;
     }
-    const int z = l / ny, y = l - z * ny;
+    const int z = udiv(l, rny), y = l - z * ny;
     const unsigned idx = unsigned(l) * unsigned(nx) + unsigned(x);
     float* const fv = W.f;   // v_x v_y v_z rho_x rho_y rho_z q
     if constexpr (MODE == R3_F1) {
@@ -332,16 +340,12 @@ __global__ void __launch_bounds__(kBlock) row3_kernel(const Launch3 L, int ntile
         pc(O, hp, nx, 0, j2, x) = S;
         pc(O, hp, nx, 1, j2, x) = r0 * u;
       } else {
-        const float p = c2 * S;
-        fv[6 * N + idx] = p;
-        pc(O, hp, nx, 0, j2, x) = p;
+        pc(O, hp, nx, 0, j2, x) = c2 * S;
       }
     } else if constexpr (MODE == R3_F3) {
       const float S = fv[3 * N + idx] + fv[4 * N + idx] + fv[5 * N + idx];
       const float ys = pc(R, hp, nx, 0, j2, x), yu = pc(R, hp, nx, 1, j2, x);
-      const float p = M.c2[idx] * S - M.c2eta[idx] * ys + M.c2tau[idx] * yu;
-      fv[6 * N + idx] = p;
-      pc(O, hp, nx, 0, j2, x) = p;
+      pc(O, hp, nx, 0, j2, x) = M.c2[idx] * S - M.c2eta[idx] * ys + M.c2tau[idx] * yu;
     } else if constexpr (MODE == R3_A1) {
       const float pb = pc(R, hp, nx, 0, j2, x);
       fv[6 * N + idx] = M.c2[idx] * pb;
@@ -408,7 +412,7 @@ __global__ void __launch_bounds__(kBlock) row3_kernel(const Launch3 L, int ntile
   const LineMap lm{nout * hp, nout * hp, 0, nx, 1};
   float2* Z = fft_axis<false>(O, R, lm, M.px, tw);
   for (int t = tid; t < nout * ncol * hp; t += B) {
-    const int j = t % hp, oc = t / hp, c = oc % ncol, o = oc / ncol;
+    const int oc = udiv(t, rhp), j = t - oc * hp, o = udiv(oc, rncol), c = oc - o * ncol;
     const float2* Zl = Z + (o * hp + j) * nx;
     const float2 zk = Zl[c], zm = Zl[c == 0 ? 0 : nx - c];
     const int la = l0 + 2 * j, lb = la + 1;
@@ -445,7 +449,7 @@ __device__ __forceinline__ int plane_code(int f, int code) {
 }
 
 template <int MODE>
-__global__ void __launch_bounds__(kBlock) plane3_kernel(const Launch3 L, int ntile, int chunk, int code, int n) {
+__global__ void __launch_bounds__(kPlaneMax) plane3_kernel(const Launch3 L, int ntile, int chunk, int code, int n) {
   int item, tile;
   if (!locate(L.nitems, ntile, chunk, item, tile)) return;
   const Medium3& M = L.m;
@@ -455,11 +459,12 @@ __global__ void __launch_bounds__(kBlock) plane3_kernel(const Launch3 L, int nti
   const int cnt = nl * ct;
   const int B = blockDim.x, tid = threadIdx.x;
   extern __shared__ float2 lds[];
-  float2* b0 = lds;
-  float2* b1 = lds + cnt;
-  float2* b2 = lds + 2 * cnt;
-  float2* twy = lds + 3 * cnt;
+  float2* twy = lds;
   float2* twz = twy + ny;
+  float2* buf = twz + nz;
+  float2* b0 = buf;
+  float2* b1 = buf + cnt;
+  float2* b2 = buf + 2 * cnt;
   for (int i = tid; i < ny; i += B) twy[i] = M.twy[i];
   for (int i = tid; i < nz; i += B) twz[i] = M.twz[i];
   const size_t specN = size_t(M.ctiles) * ct * nl;
@@ -484,12 +489,72 @@ __global__ void __launch_bounds__(kBlock) plane3_kernel(const Launch3 L, int nti
     for (int i = tid; i < cnt; i += B) dst[i] = src[i];
   };
   // multiplier at chunk element i for operator `cd` (0 in the padding columns)
+  const float rct = rcp(ct), rny = rcp(ny);
   auto mult = [&](int cd, int i) {
-    const int c = i % ct, l = i / ct, z = l / ny, y = l - z * ny;
+    const int l = udiv(i, rct), c = i - l * ct, z = udiv(l, rny), y = l - z * ny;
     return c < ncols ? symbol(M, cd, c0 + c, y, z) : make_float2(0.f, 0.f);
   };
 
-  if constexpr (MODE == P3_GRADP1) {
+  if (M.wide) {
+    // every field of the pass transformed at once: more butterflies per
+    // stage and a third of the barriers (six buffers of one chunk in LDS)
+    float2* R0 = buf;
+    float2* R1 = buf + 3 * cnt;
+    const float rcnt = rcp(cnt);
+    auto fwdk = [&](float2* a, float2* b, int k) {
+      const LineMap yk{k * nz * ct, ct, ny * ct, 1, ct};
+      const LineMap zk{k * ny * ct, ny * ct, cnt, 1, ny * ct};
+      float2* r = fft_axis<false>(a, b, yk, M.py, twy);
+      return fft_axis<false>(r, r == a ? b : a, zk, M.pz, twz);
+    };
+    auto invk = [&](float2* a, float2* b, int k) {
+      const LineMap yk{k * nz * ct, ct, ny * ct, 1, ct};
+      const LineMap zk{k * ny * ct, ny * ct, cnt, 1, ny * ct};
+      float2* r = fft_axis<true>(a, b, zk, M.pz, twz);
+      return fft_axis<true>(r, r == a ? b : a, yk, M.py, twy);
+    };
+    auto loadk = [&](int k, float2* dst) {
+      for (int f = 0; f < k; ++f) load(f, dst + f * cnt);
+    };
+    auto storek = [&](int k, const float2* src) {
+      for (int f = 0; f < k; ++f) store(f, src + f * cnt);
+    };
+    if constexpr (MODE == P3_GRADP1) {
+      loadk(1, R0);
+      __syncthreads();
+      float2* F = fwdk(R0, R1, 1);
+      float2* X = (F == R0) ? R1 : R0;
+      for (int i = tid; i < 3 * cnt; i += B) {
+        const int o = udiv(i, rcnt), ii = i - o * cnt;
+        X[i] = cmul(F[ii], mult(plane_code<MODE>(o, code), ii));
+      }
+      __syncthreads();
+      storek(3, invk(X, X == R0 ? R1 : R0, 3));
+    } else if constexpr (MODE == P3_DIVM) {
+      loadk(3, R0);
+      __syncthreads();
+      float2* F = fwdk(R0, R1, 3);
+      float2* A = (F == R0) ? R1 : R0;
+      for (int i = tid; i < cnt; i += B) {
+        float2 acc = cmul(F[i], mult(plane_code<MODE>(0, code), i));
+        acc = cadd(acc, cmul(F[cnt + i], mult(plane_code<MODE>(1, code), i)));
+        A[i] = cadd(acc, cmul(F[2 * cnt + i], mult(plane_code<MODE>(2, code), i)));
+      }
+      __syncthreads();
+      storek(1, invk(A, A + cnt, 1));
+    } else {
+      const int nf = (MODE == P3_APPLY) ? 1 : (MODE == P3_FRAC) ? 2 : 3;
+      loadk(nf, R0);
+      __syncthreads();
+      float2* F = fwdk(R0, R1, nf);
+      for (int i = tid; i < nf * cnt; i += B) {
+        const int f = udiv(i, rcnt);
+        F[i] = cmul(F[i], mult(plane_code<MODE>(f, code), i - f * cnt));
+      }
+      __syncthreads();
+      storek(nf, invk(F, F == R0 ? R1 : R0, nf));
+    }
+  } else if constexpr (MODE == P3_GRADP1) {
     load(0, b0);
     __syncthreads();
     float2* F = fwd(b0, b1);
@@ -546,7 +611,7 @@ __global__ void combine3_kernel(const Launch3 L) {
 // ---------------------------------------------------------------- launchers
 template <int MODE>
 static hipError_t row_t(const Launch3& L, int ntile, int chunk, int n, size_t lds, hipStream_t st) {
-  hipLaunchKernelGGL(row3_kernel<MODE>, dim3(chunk * kXcds), dim3(kBlock), lds, st, L, ntile, chunk, n);
+  hipLaunchKernelGGL(row3_kernel<MODE>, dim3(chunk * kXcds), dim3(L.m.rthr), lds, st, L, ntile, chunk, n);
   return hipGetLastError();
 }
 
@@ -569,12 +634,12 @@ hipError_t launch_row3(int mode, const Launch3& L, int ntile, int chunk, int n, 
 
 template <int MODE>
 static hipError_t plane_t(const Launch3& L, int ntile, int chunk, int code, int n, size_t lds, hipStream_t st) {
-  hipLaunchKernelGGL(plane3_kernel<MODE>, dim3(chunk * kXcds), dim3(kBlock), lds, st, L, ntile, chunk, code, n);
+  hipLaunchKernelGGL(plane3_kernel<MODE>, dim3(chunk * kXcds), dim3(L.m.pthr), lds, st, L, ntile, chunk, code, n);
   return hipGetLastError();
 }
 
 hipError_t launch_plane3(int mode, int code, const Launch3& L, int ntile, int chunk, int n, hipStream_t st) {
-  const size_t lds = plane3_lds(L.m.ny, L.m.nz, L.m.ct);
+  const size_t lds = plane3_lds(L.m.ny, L.m.nz, L.m.ct, L.m.wide != 0);
   switch (mode) {
     case P3_GRADP1: return plane_t<P3_GRADP1>(L, ntile, chunk, code, n, lds, st);
     case P3_GRADM2: return plane_t<P3_GRADM2>(L, ntile, chunk, code, n, lds, st);

@@ -15,7 +15,9 @@
 
 namespace qpat3 {
 
-constexpr int kBlock = 256;          // threads per block of every 3-D kernel
+constexpr int kBlock = 256;          // threads per block of the helper kernels
+constexpr int kRowMax = 512;         // most threads of a row block
+constexpr int kPlaneMax = 1024;      // most threads of a plane block
 constexpr int kMaxN = 128;           // longest axis
 constexpr int kMaxStages = 8;        // FFT stages per axis
 constexpr size_t kMaxLds = 163840;   // gfx950 LDS per work-group
@@ -41,6 +43,8 @@ struct Medium3 {
   int nx, ny, nz, nxh1, nlines, nt, ns, lossy;
   float dt;
   int rt, ct, ctiles;                 // lines per row tile, columns per plane tile, column tiles
+  int rthr, pthr;                     // threads per row / plane block
+  int wide;                           // plane blocks hold all fields of a pass at once
   AxisPlan px, py, pz;
   const float *c2, *c2eta, *c2tau, *rho0;      // [N]
   const float *bx, *by, *bz;                   // dt / rho0 at the staggered positions [N]
@@ -97,10 +101,11 @@ enum Plane3 : int {
 enum OpCode3 : int { OP_DXP = 0, OP_DXM, OP_DYP, OP_DYM, OP_DZP, OP_DZM, OP_LDIS, OP_LABS };
 
 // LDS bytes of a row block (two buffers of 3 x rt/2 lines + twiddles) and of
-// a plane block (three buffers of ct columns x nlines + twiddles).
+// a plane block (twiddles + three buffers of ct columns x nlines, six when
+// all fields are transformed together).
 inline size_t row3_lds(int nx, int rt) { return (size_t(2) * 3 * (rt / 2) * nx + nx) * sizeof(float2); }
-inline size_t plane3_lds(int ny, int nz, int ct) {
-  return (size_t(3) * ct * ny * nz + ny + nz) * sizeof(float2);
+inline size_t plane3_lds(int ny, int nz, int ct, bool wide) {
+  return (size_t(wide ? 6 : 3) * ct * ny * nz + ny + nz) * sizeof(float2);
 }
 
 hipError_t launch_row3(int mode, const Launch3& L, int ntile, int chunk, int n, hipStream_t st);

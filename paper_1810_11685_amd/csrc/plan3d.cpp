@@ -92,9 +92,12 @@ double stability_limit3(double cmax, double c_ref, double dx, double dy, double 
   return 2.0 * std::asin(c_ref / cmax) / (c_ref * kmax);
 }
 
-bool tiles_ok(const qpat_params3d& p, int rt, int ct) {
+bool pow2_in(int v, int lo, int hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; }
+
+bool tiles_ok(const qpat_params3d& p, int rt, int ct, int rthr = 256, int pthr = 256) {
   if (rt < 2 || rt > 64 || (rt & 1) || ct < 1 || ct > p.nx / 2 + 1) return false;
-  return row3_lds(p.nx, rt) <= kMaxLds && plane3_lds(p.ny, p.nz, ct) <= kMaxLds;
+  if (!pow2_in(rthr, 64, kRowMax) || !pow2_in(pthr, 64, kPlaneMax)) return false;
+  return row3_lds(p.nx, rt) <= kMaxLds && plane3_lds(p.ny, p.nz, ct, false) <= kMaxLds;
 }
 
 qpat_status validate3(const qpat_params3d* p) {
@@ -420,6 +423,9 @@ qpat_status plan3_build(qpat_plan3d P, const double* c0, const double* rho0) {
   M.rt = rt;
   M.ct = 1;
   M.ctiles = nxh1;
+  M.rthr = 256;
+  M.pthr = 512;
+  M.wide = plane3_lds(ny, nz, 1, true) <= kMaxLds;
   return QPAT_OK;
 }
 
@@ -655,24 +661,33 @@ qpat_status qpat3d_apply(qpat_plan3d P, int32_t op, const float* in, float* out,
   return QPAT_OK;
 }
 
-qpat_status qpat3d_set_tiles(qpat_plan3d P, int32_t rows, int32_t cols) {
+qpat_status qpat3d_set_tiles(qpat_plan3d P, int32_t rows, int32_t cols, int32_t row_threads,
+                             int32_t plane_threads) {
   if (!P) return set_error(QPAT_E_INVALID, "plan is NULL");
-  if (!tiles_ok(P->prm, rows, cols))
-    return set_error(QPAT_E_INVALID, "tiles: rows even in [2, 64], cols in [1, nx/2 + 1], both within the LDS");
-  if (rows != P->med.rt || cols != P->med.ct) {
+  if (!tiles_ok(P->prm, rows, cols, row_threads, plane_threads))
+    return set_error(QPAT_E_INVALID, "tiles: rows even in [2, 64], cols in [1, nx/2 + 1], both within the LDS; "
+                                     "row threads 64..512 and plane threads 64..1024, powers of two");
+  Medium3& M = P->med;
+  if (rows != M.rt || cols != M.ct || row_threads != M.rthr || plane_threads != M.pthr) {
     H3CHK(hipDeviceSynchronize());
-    P->med.rt = rows;
-    P->med.ct = cols;
-    P->med.ctiles = (P->med.nxh1 + cols - 1) / cols;
+    M.rt = rows;
+    M.ct = cols;
+    M.ctiles = (M.nxh1 + cols - 1) / cols;
+    M.rthr = row_threads;
+    M.pthr = plane_threads;
+    M.wide = plane3_lds(M.ny, M.nz, cols, true) <= kMaxLds;
     P->execs.clear();
   }
   return QPAT_OK;
 }
 
-qpat_status qpat3d_get_tiles(qpat_plan3d P, int32_t* rows, int32_t* cols) {
+qpat_status qpat3d_get_tiles(qpat_plan3d P, int32_t* rows, int32_t* cols, int32_t* row_threads,
+                             int32_t* plane_threads) {
   if (!P || !rows || !cols) return set_error(QPAT_E_INVALID, "NULL argument");
   *rows = P->med.rt;
   *cols = P->med.ct;
+  if (row_threads) *row_threads = P->med.rthr;
+  if (plane_threads) *plane_threads = P->med.pthr;
   return QPAT_OK;
 }
 

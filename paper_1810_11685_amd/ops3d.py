@@ -93,13 +93,18 @@ class Plan3D:
         check(lib().qpat3d_apply(self._h, OPS3[op], _ptr(x), _ptr(out), b, _stream(stream)), "qpat3d_apply")
         return out
 
-    def set_tiles(self, rows: int, cols: int) -> None:
-        check(lib().qpat3d_set_tiles(self._h, rows, cols), "qpat3d_set_tiles")
+    def set_tiles(self, rows: int, cols: int, row_threads: int | None = None,
+                  plane_threads: int | None = None) -> None:
+        _, _, rth, pth = self.tiles()
+        rth = rth if row_threads is None else row_threads
+        pth = pth if plane_threads is None else plane_threads
+        check(lib().qpat3d_set_tiles(self._h, rows, cols, rth, pth), "qpat3d_set_tiles")
 
-    def tiles(self) -> tuple[int, int]:
-        r, c = ctypes.c_int32(), ctypes.c_int32()
-        check(lib().qpat3d_get_tiles(self._h, ctypes.byref(r), ctypes.byref(c)), "qpat3d_get_tiles")
-        return int(r.value), int(c.value)
+    def tiles(self) -> tuple[int, int, int, int]:
+        """(lines per row block, columns per plane block, row threads, plane threads)."""
+        v = [ctypes.c_int32() for _ in range(4)]
+        check(lib().qpat3d_get_tiles(self._h, *[ctypes.byref(x) for x in v]), "qpat3d_get_tiles")
+        return tuple(int(x.value) for x in v)
 
     def set_graph(self, enable: bool = True) -> None:
         check(lib().qpat3d_set_graph(self._h, int(bool(enable))), "qpat3d_set_graph")

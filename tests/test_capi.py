@@ -138,4 +138,4 @@ def test_plan3d_host_checks(q):
     L = q.lib()
     assert L.qpat3d_validate(None) == 1
     assert L.qpat3d_forward(None, None, None, 1, None) == 1
-    assert L.qpat3d_set_tiles(None, 2, 1) == 1
+    assert L.qpat3d_set_tiles(None, 2, 1, 256, 256) == 1

@@ -71,7 +71,7 @@ def test_apply_spectral_operator_3d(q, shape, op):
 CASES = [
     # nx, ny, nz, nt, alpha0_db, y, pml, tiles
     (16, 12, 10, 40, 0.75, 1.5, 3, None),
-    (11, 14, 9, 30, 0.5, 1.3, 2, (4, 2)),     # prime 11 (direct DFT stage), odd axes, ragged tiles
+    (11, 14, 9, 30, 0.5, 1.3, 2, (4, 2, 64, 128)),     # prime 11 (direct DFT stage), odd axes, ragged tiles
     (13, 7, 10, 30, 0.0, 1.5, 2, (6, 3)),     # lossless, prime 13 and 7
     (24, 20, 18, 40, 0.75, 1.5, 4, (16, 5)),
     (10, 15, 6, 25, 2.0, 1.5, 2, (2, 4)),      # radix 5
@@ -139,7 +139,7 @@ def test_batch_tiles_graph_bitwise_3d(q):
         assert np.array_equal(N(plan.forward(T(xs[b]))), base[b])
     r = qi.gaussian_field((3, 20, 9), 23)
     gbase = N(plan.adjoint(T(r)))
-    for tiles in [(2, 1), (8, 3), (14, 10), (64, 2)]:
+    for tiles in [(2, 1, 64, 64), (8, 3, 512, 1024), (14, 10, 256, 512), (64, 2, 128, 256)]:
         plan.set_tiles(*tiles)
         assert np.array_equal(N(plan.forward(T(xs))), base), tiles
         assert np.array_equal(N(plan.adjoint(T(r))), gbase), tiles
@@ -175,3 +175,20 @@ def test_nt_one_and_two_3d(q, nt):
     assert rel(N(plan.forward(T(p0))), K3.forward(prm, c0, rho0, p0)) <= TOL
     r = qi.gaussian_field((nt, 4), 41)
     assert rel(N(plan.adjoint(T(r))), K3.adjoint(prm, c0, rho0, r)) <= TOL
+
+
+def test_wide_and_narrow_plane_blocks_agree_bitwise(q):
+    """A plane block transforms all fields of a pass together when six chunk
+    buffers fit in LDS, else one field at a time: same arithmetic per line, so
+    the same bits (24 x 24 planes: one column per block fits six buffers, six
+    columns do not)."""
+    prm, c0, rho0, p0 = problem(16, 24, 24, 12, ns=6)
+    plan = q.Plan3D(prm, c0, rho0)
+    x = T(np.stack([p0, qi.gaussian_field(p0.shape, 51)]))
+    r = T(qi.gaussian_field((2, 12, 6), 52))
+    plan.set_tiles(8, 1, 256, 1024)
+    d1, g1 = N(plan.forward(x)), N(plan.adjoint(r))
+    plan.set_tiles(8, 6, 256, 512)
+    assert np.array_equal(N(plan.forward(x)), d1)
+    assert np.array_equal(N(plan.adjoint(r)), g1)
+    assert rel(d1[0], K3.forward(prm, c0, rho0, p0)) <= TOL
