@@ -137,6 +137,7 @@ def main():
     ap.add_argument("--no-recon", action="store_true", help="skip the reconstruction-driver measurement")
     ap.add_argument("--no-medium", action="store_true", help="skip the sound-speed gradient measurement")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3-D solver measurement")
+    ap.add_argument("--batches3d", default="1,3,16", help="batch sizes of the 3-D measurement")
     ap.add_argument("--tiles", default=None,
                     help="launch shape rows,cols,row_threads,col_threads of the headline plan (skips tuning)")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work")
@@ -426,7 +427,7 @@ def main():
         plan3.set_graph(args.graph == "on")
         runs = {}
         with torch.cuda.stream(stream):
-            for b in (1, 3, 16):
+            for b in [int(v) for v in args.batches3d.split(",")]:
                 x3 = T(np.stack([c3["p0"]] * b))
                 r3 = T(qi.gaussian_field((b, nt3, ns3), 3303))
                 plan3.forward(x3, stream=stream)

@@ -288,14 +288,18 @@ __global__ void __launch_bounds__(kRowMax) row3_kernel(const Launch3 L, int ntil
       R[t] = make_float2(-z.x, -z.y);
     }
     __syncthreads();
-    if (tid < rt && l0 + tid < nl) {
-      const int l = l0 + tid;
+    {
+      // one thread per receiving node, its entries summed in a fixed order
       const float* r = X.in + size_t(n + 1) * M.ns;
-      for (int e = M.tap_off[l]; e < M.tap_off[l + 1]; ++e) {
-        const Tap3 tp = M.taps[e];
-        const float rv = r[tp.s];
-        pc(R, hp, nx, 0, tid, tp.ixl) += tp.wl * rv;
-        pc(R, hp, nx, 0, tid, tp.ixr) += tp.wr * rv;
+      const int a = M.node_off[l0], b = M.node_off[min(l0 + rt, nl)];
+      for (int k = a + tid; k < b; k += B) {
+        const ScatterNode nd = M.nodes[k];
+        float acc = 0.f;
+        for (int e = nd.e0; e < nd.e1; ++e) {
+          const ScatterEntry en = M.entries[e];
+          acc += en.w * r[en.s];
+        }
+        pc(R, hp, nx, 0, nd.line - l0, nd.ix) += acc;
       }
     }
     __syncthreads();

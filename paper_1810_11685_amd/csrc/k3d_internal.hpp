@@ -39,6 +39,16 @@ struct Tap3 {
   int pad;
 };
 
+// One grid node that receives the transposed measurement M^T r: the sum of
+// w * r[s] over its entries [e0, e1) of the scatter list; sorted by (line, ix).
+struct ScatterNode {
+  int line, ix, e0, e1;
+};
+struct ScatterEntry {
+  int s;
+  float w;
+};
+
 struct Medium3 {
   int nx, ny, nz, nxh1, nlines, nt, ns, lossy;
   float dt;
@@ -54,6 +64,9 @@ struct Medium3 {
   const float2 *twx, *twy, *twz;               // e^{-2 pi i m / n}, m < n
   const int* tap_off;                          // [nlines + 1]
   const Tap3* taps;
+  const int* node_off;                         // [nlines + 1] into nodes
+  const ScatterNode* nodes;
+  const ScatterEntry* entries;
 };
 
 // Per-vector work buffers.

@@ -166,6 +166,32 @@ void build_taps3(const qpat_params3d& p, std::vector<Tap3>& taps, std::vector<in
   off[nl] = int(taps.size());
 }
 
+// The scatter list of M^T: every (node, sensor, weight) of the taps grouped by
+// node, nodes sorted by (line, ix), with per-line offsets into the nodes.
+void build_scatter3(const qpat_params3d& p, const std::vector<Tap3>& taps, std::vector<int>& noff,
+                    std::vector<ScatterNode>& nodes, std::vector<ScatterEntry>& entries) {
+  const int nl = p.ny * p.nz;
+  std::map<std::pair<int, int>, std::vector<ScatterEntry>> by;
+  for (const Tap3& t : taps) {
+    by[{t.line, t.ixl}].push_back(ScatterEntry{t.s, t.wl});
+    by[{t.line, t.ixr}].push_back(ScatterEntry{t.s, t.wr});
+  }
+  nodes.clear();
+  entries.clear();
+  noff.assign(nl + 1, 0);
+  for (const auto& kv : by) {
+    const int e0 = int(entries.size());
+    for (const ScatterEntry& e : kv.second) entries.push_back(e);
+    nodes.push_back(ScatterNode{kv.first.first, kv.first.second, e0, int(entries.size())});
+  }
+  // nodes are in (line, ix) order; offsets per line
+  size_t k = 0;
+  for (int l = 0; l <= nl; ++l) {
+    while (k < nodes.size() && nodes[k].line < l) ++k;
+    noff[l] = int(k);
+  }
+}
+
 struct Carver {
   size_t off = 0;
   template <typename T>
@@ -324,7 +350,13 @@ qpat_status plan3_build(qpat_plan3d P, const double* c0, const double* rho0) {
   std::vector<Tap3> taps;
   std::vector<int> toff;
   build_taps3(p, taps, toff);
+  std::vector<int> noff;
+  std::vector<ScatterNode> nodes;
+  std::vector<ScatterEntry> entries;
+  build_scatter3(p, taps, noff, nodes, entries);
   if (taps.empty()) taps.push_back(Tap3{});
+  if (nodes.empty()) nodes.push_back(ScatterNode{});
+  if (entries.empty()) entries.push_back(ScatterEntry{});
 
   {
     const hipError_t e = k3d_allow_lds(kMaxLds);
@@ -341,6 +373,8 @@ qpat_status plan3_build(qpat_plan3d P, const double* c0, const double* rho0) {
   const size_t o_kap = cv.take<float>(nk), o_ldis = cv.take<float>(nk), o_labs = cv.take<float>(nk);
   const size_t o_twx = cv.take<float2>(nx), o_twy = cv.take<float2>(ny), o_twz = cv.take<float2>(nz);
   const size_t o_toff = cv.take<int>(toff.size()), o_taps = cv.take<Tap3>(taps.size());
+  const size_t o_noff = cv.take<int>(noff.size()), o_nodes = cv.take<ScatterNode>(nodes.size()),
+               o_ent = cv.take<ScatterEntry>(entries.size());
   std::vector<char> host(cv.off, 0);
   auto put = [&](size_t o, const void* src, size_t bytes) { std::memcpy(host.data() + o, src, bytes); };
   put(o_c2, c2.data(), N * 4);
@@ -370,6 +404,9 @@ qpat_status plan3_build(qpat_plan3d P, const double* c0, const double* rho0) {
   put(o_twz, twz.data(), nz * 8);
   put(o_toff, toff.data(), toff.size() * 4);
   put(o_taps, taps.data(), taps.size() * sizeof(Tap3));
+  put(o_noff, noff.data(), noff.size() * 4);
+  put(o_nodes, nodes.data(), nodes.size() * sizeof(ScatterNode));
+  put(o_ent, entries.data(), entries.size() * sizeof(ScatterEntry));
   char* d = nullptr;
   H3CHK(hipMalloc(&d, cv.off));
   P->d_med = d;
@@ -415,6 +452,9 @@ qpat_status plan3_build(qpat_plan3d P, const double* c0, const double* rho0) {
   M.twz = (const float2*)(d + o_twz);
   M.tap_off = (const int*)(d + o_toff);
   M.taps = (const Tap3*)(d + o_taps);
+  M.node_off = (const int*)(d + o_noff);
+  M.nodes = (const ScatterNode*)(d + o_nodes);
+  M.entries = (const ScatterEntry*)(d + o_ent);
   // default shape: 16 lines per row block (fewer when nx is long), one
   // spectrum column per plane block
   int rt = 16;
