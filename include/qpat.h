@@ -322,6 +322,44 @@ qpat_status qpat3d_get_tiles(qpat_plan3d plan, int32_t* rows, int32_t* cols, int
 /* hipGraph capture and replay of whole 3-D solves (as qpat_set_graph). */
 qpat_status qpat3d_set_graph(qpat_plan3d plan, int32_t enable);
 
+/* ---- Optical operators (Section 3.1, 2-D): the diffusion approximation with
+ * its Robin condition (eq DA) discretised by P1 Galerkin FEM (eqs var_fo,
+ * system_forward2), the heating map H = mu o I Phi (eq forward_out), its
+ * Frechet derivative J_o (eq dh_des) and adjoint J_o^* (eqs system_adjoint,
+ * system_adjoint1, prodtproj).  The mesh is matched to an nx x ny acoustic
+ * grid of spacing dx: every grid node is the centre of a square pixel, the
+ * FEM nodes are the (nx + 1) x (ny + 1) pixel corners, and pixel (j, i) holds
+ * element 2 (j nx + i) (corners (j,i), (j,i+1), (j+1,i+1)) and element
+ * 2 (j nx + i) + 1 (corners (j,i), (j+1,i+1), (j+1,i)).  Coefficients and
+ * heating are elemental, [batch][2 nx ny] device floats; the work is FP64.
+ * Systems are solved by conjugate gradients with the diagonal of A_o as
+ * preconditioner to ||rhs - A x|| <= tol ||rhs||, checked every 32
+ * iterations (the calls synchronise the stream); *iters (may be NULL)
+ * receives the iterations run.  An optical handle holds the coefficients and
+ * Phi of its last forward call for J_o and J_o^*; one handle must not be used
+ * from two streams at once.
+ *  create      nx, ny >= 1, (nx + 1)(ny + 1) <= 2^26, dx > 0, batch in [1, 64].
+ *  forward     kappa, mu > 0 elemental; currents host [batch][4] doubles, the
+ *              inward current I_s on the bottom (j = 0), top, left (i = 0) and
+ *              right sides; gamma_2 = 1/pi.  H = mu o I Phi.
+ *  jv          dH = J_o [dkappa, dmu] at the last forward state.
+ *  jtv         (gkappa, gmu) = J_o^* H.
+ *  pixels      transpose = 0: p [batch][ny][nx] = mean of each pixel's two
+ *              elements of H (initial pressure on the acoustic grid,
+ *              Gruneisen 1); transpose = 1: H = half of p to each element. */
+typedef struct qpat_optical_s* qpat_optical;
+qpat_status qpat_optical_create(int32_t nx, int32_t ny, double dx, int32_t batch, qpat_optical* out);
+void qpat_optical_destroy(qpat_optical optical);
+qpat_status qpat_optical_forward(qpat_optical optical, const float* kappa, const float* mu, const double* currents,
+                                 float* H, int32_t batch, double tol, int32_t max_iter, int32_t* iters,
+                                 qpat_stream stream);
+qpat_status qpat_optical_jv(qpat_optical optical, const float* dkappa, const float* dmu, float* dH, int32_t batch,
+                            double tol, int32_t max_iter, int32_t* iters, qpat_stream stream);
+qpat_status qpat_optical_jtv(qpat_optical optical, const float* H, float* gkappa, float* gmu, int32_t batch,
+                             double tol, int32_t max_iter, int32_t* iters, qpat_stream stream);
+qpat_status qpat_optical_pixels(qpat_optical optical, const float* in, float* out, int32_t transpose,
+                                int32_t batch, qpat_stream stream);
+
 /* Plan introspection: sizes and the device bytes the plan holds. */
 qpat_status qpat_plan_info(qpat_plan plan, int32_t* nx, int32_t* ny, int32_t* nt, int32_t* ns,
                            size_t* device_bytes);

@@ -6,7 +6,8 @@ from .ops import Batch, Plan, dot, make_params, validate
 from .autograd import AcousticForward, acoustic, replay_states
 from .recon import TV, axpby, ld_reconstruct
 from .ops3d import Plan3D, validate3d
+from .optical import Optical, QPATJacobian
 
 __all__ = ["Plan", "Batch", "dot", "validate", "make_params", "acoustic", "AcousticForward", "TV", "axpby",
-           "ld_reconstruct", "Plan3D", "validate3d",
+           "ld_reconstruct", "Plan3D", "validate3d", "Optical", "QPATJacobian",
            "replay_states", "QpatError", "lib", "LIB_PATH", "EXPORTED"]

@@ -99,6 +99,15 @@ _SIGS = {
     "qpat3d_get_tiles": (c_int32, [c_void_p, ctypes.POINTER(c_int32), ctypes.POINTER(c_int32),
                                    ctypes.POINTER(c_int32), ctypes.POINTER(c_int32)]),
     "qpat3d_set_graph": (c_int32, [c_void_p, c_int32]),
+    "qpat_optical_create": (c_int32, [c_int32, c_int32, c_double, c_int32, ctypes.POINTER(c_void_p)]),
+    "qpat_optical_destroy": (None, [c_void_p]),
+    "qpat_optical_forward": (c_int32, [c_void_p, c_void_p, c_void_p, ctypes.POINTER(c_double), c_void_p, c_int32,
+                                       c_double, c_int32, ctypes.POINTER(c_int32), c_void_p]),
+    "qpat_optical_jv": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_double, c_int32,
+                                  ctypes.POINTER(c_int32), c_void_p]),
+    "qpat_optical_jtv": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_double, c_int32,
+                                   ctypes.POINTER(c_int32), c_void_p]),
+    "qpat_optical_pixels": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_void_p]),
     "qpat_plan_info": (c_int32, [c_void_p, ctypes.POINTER(c_int32), ctypes.POINTER(c_int32),
                                  ctypes.POINTER(c_int32), ctypes.POINTER(c_int32), ctypes.POINTER(c_size_t)]),
     "qpat_status_string": (ctypes.c_char_p, [c_int32]),

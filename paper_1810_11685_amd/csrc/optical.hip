@@ -1,0 +1,414 @@
+// Optical operators of Section 3.1 on the GPU: the P1 Galerkin system
+// A_o = K[kappa] + C[mu] + R of the diffusion approximation with its Robin
+// condition (eqs var_fo, system_forward2) on the grid-matched triangulation,
+// its solution by FP64 conjugate gradients (Jacobi preconditioner), the
+// heating map H = mu o I Phi (eq forward_out), J_o (eq dh_des) and J_o^*
+// (eqs system_adjoint, system_adjoint1, prodtproj).
+//
+// Mesh: nx x ny square pixels of side h; FEM nodes are the pixel corners,
+// node (r, c) = r (nx + 1) + c; pixel (j, i) holds element 2 (j nx + i) with
+// corners (j,i), (j,i+1), (j+1,i+1) and element 2 (j nx + i) + 1 with corners
+// (j,i), (j+1,i+1), (j+1,i).  A is applied matrix-free by gathering, at every
+// node, the rows of the (at most six) incident element matrices and of the
+// boundary edges: no atomics, a fixed summation order.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "optical_internal.hpp"
+
+namespace qpat {
+
+namespace {
+
+constexpr double kGamma2 = 0.31830988618379067154;  // gamma_2 = 1/pi
+
+// P1 stiffness of the two element shapes without kappa (S grad phi_a . grad phi_b,
+// independent of h in 2-D) and the P1 mass pattern (times S/12).
+__device__ __forceinline__ double kloc(int shape, int a, int b) {
+  // shape 0: [[1,-1,0],[-1,2,-1],[0,-1,1]] / 2; shape 1: [[1,0,-1],[0,1,-1],[-1,-1,2]] / 2
+  if (shape == 0) {
+    const int d = a > b ? a - b : b - a;
+    if (a == b) return a == 1 ? 1.0 : 0.5;
+    return d == 1 ? -0.5 : 0.0;
+  }
+  if (a == b) return a == 2 ? 1.0 : 0.5;
+  return (a == 2 || b == 2) ? -0.5 : 0.0;
+}
+__device__ __forceinline__ double mloc(int a, int b) { return a == b ? 2.0 / 12.0 : 1.0 / 12.0; }
+
+// local index of pixel corner (lr, lc) in element shape 0 / 1 (-1: not a vertex)
+__device__ __forceinline__ int local0(int lr, int lc) { return lr == 0 ? (lc == 0 ? 0 : 1) : (lc == 1 ? 2 : -1); }
+__device__ __forceinline__ int local1(int lr, int lc) { return lr == 0 ? (lc == 0 ? 0 : -1) : (lc == 1 ? 1 : 2); }
+
+struct Pix {
+  int n[4];  // corners (j,i), (j,i+1), (j+1,i+1), (j+1,i)
+};
+__device__ __forceinline__ Pix pixel(int j, int i, int nx) {
+  const int w = nx + 1;
+  return Pix{{j * w + i, j * w + i + 1, (j + 1) * w + i + 1, (j + 1) * w + i}};
+}
+// vertex b of element shape s as a pixel corner index
+__device__ __forceinline__ int vert(int s, int b) { return s == 0 ? b : (b == 0 ? 0 : b == 1 ? 2 : 3); }
+
+// (K[ka] + C[mu] (+ R)) x at node (r, c); ka, mu elemental; with `robin` the
+// boundary term 2 gamma int phi_k phi_p ds is added (edge mass h/6 [[2,1],[1,2]]).
+template <typename T>
+__device__ double apply_at(const T* __restrict__ x, const double* __restrict__ ka, const double* __restrict__ mu,
+                           int r, int c, int nx, int ny, double h, bool robin) {
+  double y = 0.0;
+  const double ms = 0.5 * h * h;  // element area
+  for (int dj = -1; dj <= 0; ++dj) {
+    const int j = r + dj;
+    if (j < 0 || j >= ny) continue;
+    for (int di = -1; di <= 0; ++di) {
+      const int i = c + di;
+      if (i < 0 || i >= nx) continue;
+      const Pix P = pixel(j, i, nx);
+      const int lr = r - j, lc = c - i;
+      const int e = 2 * (j * nx + i);
+      const int a0 = local0(lr, lc), a1 = local1(lr, lc);
+      if (a0 >= 0) {
+        double k = 0.0, m = 0.0;
+        for (int b = 0; b < 3; ++b) {
+          const double xb = double(x[P.n[vert(0, b)]]);
+          k += kloc(0, a0, b) * xb;
+          m += mloc(a0, b) * xb;
+        }
+        y += ka[e] * k + mu[e] * ms * m;
+      }
+      if (a1 >= 0) {
+        double k = 0.0, m = 0.0;
+        for (int b = 0; b < 3; ++b) {
+          const double xb = double(x[P.n[vert(1, b)]]);
+          k += kloc(1, a1, b) * xb;
+          m += mloc(a1, b) * xb;
+        }
+        y += ka[e + 1] * k + mu[e + 1] * ms * m;
+      }
+    }
+  }
+  if (robin) {
+    const double w = 2.0 * kGamma2 * h / 6.0;
+    const int W = nx + 1;
+    const double xc = double(x[r * W + c]);
+    if (r == 0 || r == ny) {  // bottom / top edges along x
+      if (c > 0) y += w * (2.0 * xc + double(x[r * W + c - 1]));
+      if (c < nx) y += w * (2.0 * xc + double(x[r * W + c + 1]));
+    }
+    if (c == 0 || c == nx) {  // left / right edges along y
+      if (r > 0) y += w * (2.0 * xc + double(x[(r - 1) * W + c]));
+      if (r < ny) y += w * (2.0 * xc + double(x[(r + 1) * W + c]));
+    }
+  }
+  return y;
+}
+
+__device__ double diag_at(const double* __restrict__ ka, const double* __restrict__ mu, int r, int c, int nx,
+                          int ny, double h) {
+  double d = 0.0;
+  const double ms = 0.5 * h * h;
+  for (int dj = -1; dj <= 0; ++dj) {
+    const int j = r + dj;
+    if (j < 0 || j >= ny) continue;
+    for (int di = -1; di <= 0; ++di) {
+      const int i = c + di;
+      if (i < 0 || i >= nx) continue;
+      const int lr = r - j, lc = c - i, e = 2 * (j * nx + i);
+      const int a0 = local0(lr, lc), a1 = local1(lr, lc);
+      if (a0 >= 0) d += ka[e] * kloc(0, a0, a0) + mu[e] * ms * mloc(a0, a0);
+      if (a1 >= 0) d += ka[e + 1] * kloc(1, a1, a1) + mu[e + 1] * ms * mloc(a1, a1);
+    }
+  }
+  const double w = 2.0 * kGamma2 * h / 6.0;
+  if (r == 0 || r == ny) d += w * (2.0 * (c > 0) + 2.0 * (c < nx));
+  if (c == 0 || c == nx) d += w * (2.0 * (r > 0) + 2.0 * (r < ny));
+  return d;
+}
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  v = wave_sum_d(v);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < kOptThreads / 64; ++w) s += red[w];
+  __syncthreads();
+  return s;
+}
+__device__ __forceinline__ double partial_total(const double* __restrict__ part, int b, int nblk, double* red) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += blockDim.x) v += part[size_t(b) * kOptBlocks + i];
+  __shared__ double tot;
+  const double s = block_sum(v, red);
+  if (threadIdx.x == 0) tot = s;
+  __syncthreads();
+  return tot;
+}
+
+#define FOR_NODES(k)                                                                         \
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < c.nn; k += gridDim.x * blockDim.x)
+#define FOR_ELEMS(e)                                                                         \
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < c.ne; e += gridDim.x * blockDim.x)
+
+// coefficients of field b in FP64
+__global__ void __launch_bounds__(kOptThreads) opt_set_kernel(OptCg c, const float* __restrict__ kappa,
+                                                              const float* __restrict__ mu) {
+  const int b = blockIdx.y;
+  const size_t be = size_t(b) * c.ne;
+  FOR_ELEMS(e) {
+    c.ka[be + e] = kappa[be + e];
+    c.mu[be + e] = mu[be + e];
+  }
+}
+
+// right-hand sides.  mode 0: G of constant side currents cur[b][4] (bottom,
+// top, left, right): int 2 I phi_p ds = I h per edge end;  mode 1:
+// -(K[dka] + C[dmu]) Phi0;  mode 2: -I^+(mu o H) = -(S/3) sum_{e at p} mu_e H_e.
+__global__ void __launch_bounds__(kOptThreads)
+opt_rhs_kernel(OptCg c, int mode, const double* __restrict__ cur, const float* __restrict__ Hin) {
+  const int b = blockIdx.y;
+  const size_t bn = size_t(b) * c.nn, be = size_t(b) * c.ne;
+  const int W = c.nx + 1;
+  FOR_NODES(k) {
+    const int r = k / W, col = k - r * W;
+    double v = 0.0;
+    if (mode == 0) {
+      const double* I = cur + 4 * b;
+      if (r == 0) v += I[0] * c.h * ((col > 0) + (col < c.nx));
+      if (r == c.ny) v += I[1] * c.h * ((col > 0) + (col < c.nx));
+      if (col == 0) v += I[2] * c.h * ((r > 0) + (r < c.ny));
+      if (col == c.nx) v += I[3] * c.h * ((r > 0) + (r < c.ny));
+    } else if (mode == 1) {
+      // the perturbations, staged in FP64 by opt_stage_kernel
+      v = -apply_at(c.phi + bn, c.ek + be, c.em + be, r, col, c.nx, c.ny, c.h, false);
+    } else {
+      const double s3 = 0.5 * c.h * c.h / 3.0;
+      for (int dj = -1; dj <= 0; ++dj) {
+        const int j = r + dj;
+        if (j < 0 || j >= c.ny) continue;
+        for (int di = -1; di <= 0; ++di) {
+          const int i = col + di;
+          if (i < 0 || i >= c.nx) continue;
+          const int lr = r - j, lc = col - i, e = 2 * (j * c.nx + i);
+          if (local0(lr, lc) >= 0) v -= s3 * c.mu[be + e] * double(Hin[be + e]);
+          if (local1(lr, lc) >= 0) v -= s3 * c.mu[be + e + 1] * double(Hin[be + e + 1]);
+        }
+      }
+    }
+    c.rhs[bn + k] = v;
+  }
+}
+
+// element perturbations to FP64 scratch (mode 1 of opt_rhs_kernel)
+__global__ void __launch_bounds__(kOptThreads) opt_stage_kernel(OptCg c, const float* __restrict__ da,
+                                                                const float* __restrict__ dm) {
+  const int b = blockIdx.y;
+  const size_t be = size_t(b) * c.ne;
+  FOR_ELEMS(e) {
+    c.ek[be + e] = da[be + e];
+    c.em[be + e] = dm[be + e];
+  }
+}
+
+// CG start: x = 0, r = rhs, dinv, p = dinv r; partials of r.z, r.r
+__global__ void __launch_bounds__(kOptThreads) opt_cg_start_kernel(OptCg c) {
+  __shared__ double red[kOptThreads / 64];
+  const int b = blockIdx.y;
+  const size_t bn = size_t(b) * c.nn, be = size_t(b) * c.ne;
+  const int W = c.nx + 1;
+  double rz = 0.0, rr = 0.0;
+  FOR_NODES(k) {
+    const int r = k / W, col = k - r * W;
+    const double di = 1.0 / diag_at(c.ka + be, c.mu + be, r, col, c.nx, c.ny, c.h);
+    const double rv = c.rhs[bn + k], z = di * rv;
+    c.dinv[bn + k] = di;
+    c.x[bn + k] = 0.0;
+    c.r[bn + k] = rv;
+    c.p[bn + k] = z;
+    rz += rv * z;
+    rr += rv * rv;
+  }
+  const double s1 = block_sum(rz, red), s2 = block_sum(rr, red);
+  if (threadIdx.x == 0) {
+    c.part_rz[size_t(b) * kOptBlocks + blockIdx.x] = s1;
+    c.part_rr[size_t(b) * kOptBlocks + blockIdx.x] = s2;
+  }
+}
+
+__global__ void __launch_bounds__(kOptThreads) opt_cg_start_total_kernel(OptCg c) {
+  __shared__ double red[kOptThreads / 64];
+  const int b = blockIdx.x;
+  const double rz = partial_total(c.part_rz, b, c.nblk, red);
+  const double rr = partial_total(c.part_rr, b, c.nblk, red);
+  if (threadIdx.x == 0) {
+    c.rz[b] = rz;
+    c.rr[b] = rr;
+    c.rr_next[b] = rr;
+    c.bb[b] = rr;
+  }
+}
+
+// q = A p, partials of p.q; block (0, 0) publishes the previous r.r
+__global__ void __launch_bounds__(kOptThreads) opt_cg_q_kernel(OptCg c) {
+  __shared__ double red[kOptThreads / 64];
+  const int b = blockIdx.y;
+  if (blockIdx.x == 0 && blockIdx.y == 0)
+    for (int t = threadIdx.x; t < int(gridDim.y); t += blockDim.x) c.rr[t] = c.rr_next[t];
+  const size_t bn = size_t(b) * c.nn, be = size_t(b) * c.ne;
+  const int W = c.nx + 1;
+  double pq = 0.0;
+  FOR_NODES(k) {
+    const int r = k / W, col = k - r * W;
+    const double q = apply_at(c.p + bn, c.ka + be, c.mu + be, r, col, c.nx, c.ny, c.h, true);
+    c.q[bn + k] = q;
+    pq += c.p[bn + k] * q;
+  }
+  const double s = block_sum(pq, red);
+  if (threadIdx.x == 0) c.part_pq[size_t(b) * kOptBlocks + blockIdx.x] = s;
+}
+
+// alpha = r.z / p.q (0 once converged); x += alpha p; r -= alpha q; partials of new r.z, r.r
+__global__ void __launch_bounds__(kOptThreads) opt_cg_update_kernel(OptCg c, int par, double tol2) {
+  __shared__ double red[kOptThreads / 64];
+  const int b = blockIdx.y, nb = gridDim.y;
+  const size_t bn = size_t(b) * c.nn;
+  const double pq = partial_total(c.part_pq, b, c.nblk, red);
+  const double rz = c.rz[size_t(par) * nb + b];
+  const bool live = c.rr[b] > tol2 * c.bb[b] && pq > 0.0;
+  const double alpha = live ? rz / pq : 0.0;
+  double rzn = 0.0, rr = 0.0;
+  FOR_NODES(k) {
+    c.x[bn + k] += alpha * c.p[bn + k];
+    const double rv = c.r[bn + k] - alpha * c.q[bn + k];
+    c.r[bn + k] = rv;
+    rzn += rv * c.dinv[bn + k] * rv;
+    rr += rv * rv;
+  }
+  const double s1 = block_sum(rzn, red), s2 = block_sum(rr, red);
+  if (threadIdx.x == 0) {
+    c.part_rz[size_t(b) * kOptBlocks + blockIdx.x] = s1;
+    c.part_rr[size_t(b) * kOptBlocks + blockIdx.x] = s2;
+  }
+}
+
+// beta = rz_new / rz; p = dinv r + beta p; block (0, b) stores rz_new, rr_next
+__global__ void __launch_bounds__(kOptThreads) opt_cg_dir_kernel(OptCg c, int par) {
+  __shared__ double red[kOptThreads / 64];
+  const int b = blockIdx.y, nb = gridDim.y;
+  const size_t bn = size_t(b) * c.nn;
+  const double rzn = partial_total(c.part_rz, b, c.nblk, red);
+  const double rrn = partial_total(c.part_rr, b, c.nblk, red);
+  const double rz = c.rz[size_t(par) * nb + b];
+  const double beta = rz > 0.0 ? rzn / rz : 0.0;
+  FOR_NODES(k) c.p[bn + k] = c.dinv[bn + k] * c.r[bn + k] + beta * c.p[bn + k];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    c.rz[size_t(1 - par) * nb + b] = rzn;
+    c.rr_next[b] = rrn;
+  }
+}
+
+__global__ void __launch_bounds__(kOptThreads) opt_cg_finish_kernel(OptCg c) {
+  for (int t = threadIdx.x; t < c.batch; t += blockDim.x) c.rr[t] = c.rr_next[t];
+}
+
+// outputs. mode 0 (forward): phi = x; H = mu o I phi.  mode 1 (J_o): dH =
+// dmu o I phi + mu o I x.  mode 2 (J_o^*): gk = grad x . grad phi,
+// gm = (1/12) x_e^T [[2,1,1],[1,2,1],[1,1,2]] phi_e + H o I phi.
+__global__ void __launch_bounds__(kOptThreads)
+opt_out_kernel(OptCg c, int mode, const float* __restrict__ Hin, float* __restrict__ o1, float* __restrict__ o2) {
+  const int b = blockIdx.y;
+  const size_t bn = size_t(b) * c.nn, be = size_t(b) * c.ne;
+  if (mode == 0) FOR_NODES(k) c.phi[bn + k] = c.x[bn + k];
+  FOR_ELEMS(e) {
+    const int pix = e >> 1, s = e & 1, j = pix / c.nx, i = pix - j * c.nx;
+    const Pix P = pixel(j, i, c.nx);
+    const int v0 = P.n[vert(s, 0)], v1 = P.n[vert(s, 1)], v2 = P.n[vert(s, 2)];
+    const double f0 = mode == 0 ? c.x[bn + v0] : c.phi[bn + v0];
+    const double f1 = mode == 0 ? c.x[bn + v1] : c.phi[bn + v1];
+    const double f2 = mode == 0 ? c.x[bn + v2] : c.phi[bn + v2];
+    const double If = (f0 + f1 + f2) / 3.0;
+    if (mode == 0) {
+      o1[be + e] = float(c.mu[be + e] * If);
+    } else if (mode == 1) {
+      const double Ix = (c.x[bn + v0] + c.x[bn + v1] + c.x[bn + v2]) / 3.0;
+      o1[be + e] = float(c.em[be + e] * If + c.mu[be + e] * Ix);
+    } else {
+      const double x0 = c.x[bn + v0], x1 = c.x[bn + v1], x2 = c.x[bn + v2];
+      // element gradients (h = side): shape 0 (x-step, y-step) = (u1 - u0, u2 - u1)/h,
+      // shape 1 = (u1 - u2, u2 - u0)/h
+      double gx0, gy0, gx1, gy1;
+      if (s == 0) {
+        gx0 = x1 - x0; gy0 = x2 - x1; gx1 = f1 - f0; gy1 = f2 - f1;
+      } else {
+        gx0 = x1 - x2; gy0 = x2 - x0; gx1 = f1 - f2; gy1 = f2 - f0;
+      }
+      o1[be + e] = float((gx0 * gx1 + gy0 * gy1) / (c.h * c.h));
+      const double m = (2.0 * x0 * f0 + 2.0 * x1 * f1 + 2.0 * x2 * f2 + x0 * (f1 + f2) + x1 * (f0 + f2) +
+                        x2 * (f0 + f1)) / 12.0;
+      o2[be + e] = float(m + double(Hin[be + e]) * If);
+    }
+  }
+}
+
+// pixel maps: p = mean of the pixel's two elements; transpose: half to each
+__global__ void __launch_bounds__(kOptThreads) opt_pixels_kernel(const float* __restrict__ H, float* __restrict__ p,
+                                                                 int npix, int transpose) {
+  const size_t b = blockIdx.y;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < npix; k += gridDim.x * blockDim.x) {
+    if (!transpose) {
+      p[b * npix + k] = 0.5f * (H[b * 2 * npix + 2 * k] + H[b * 2 * npix + 2 * k + 1]);
+    } else {
+      const float v = 0.5f * H[b * npix + k];
+      p[b * 2 * npix + 2 * k] = v;
+      p[b * 2 * npix + 2 * k + 1] = v;
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t opt_launch_set(const OptCg& c, const float* kappa, const float* mu, hipStream_t st) {
+  hipLaunchKernelGGL(opt_set_kernel, dim3(c.nblk, c.batch), dim3(kOptThreads), 0, st, c, kappa, mu);
+  return hipGetLastError();
+}
+hipError_t opt_launch_stage(const OptCg& c, const float* da, const float* dm, hipStream_t st) {
+  hipLaunchKernelGGL(opt_stage_kernel, dim3(c.nblk, c.batch), dim3(kOptThreads), 0, st, c, da, dm);
+  return hipGetLastError();
+}
+hipError_t opt_launch_rhs(const OptCg& c, int mode, const double* cur, const float* Hin, hipStream_t st) {
+  hipLaunchKernelGGL(opt_rhs_kernel, dim3(c.nblk, c.batch), dim3(kOptThreads), 0, st, c, mode, cur, Hin);
+  return hipGetLastError();
+}
+hipError_t opt_launch_cg_start(const OptCg& c, hipStream_t st) {
+  hipLaunchKernelGGL(opt_cg_start_kernel, dim3(c.nblk, c.batch), dim3(kOptThreads), 0, st, c);
+  hipLaunchKernelGGL(opt_cg_start_total_kernel, dim3(c.batch), dim3(kOptThreads), 0, st, c);
+  return hipGetLastError();
+}
+hipError_t opt_launch_cg_iteration(const OptCg& c, int par, double tol2, hipStream_t st) {
+  hipLaunchKernelGGL(opt_cg_q_kernel, dim3(c.nblk, c.batch), dim3(kOptThreads), 0, st, c);
+  hipLaunchKernelGGL(opt_cg_update_kernel, dim3(c.nblk, c.batch), dim3(kOptThreads), 0, st, c, par, tol2);
+  hipLaunchKernelGGL(opt_cg_dir_kernel, dim3(c.nblk, c.batch), dim3(kOptThreads), 0, st, c, par);
+  return hipGetLastError();
+}
+hipError_t opt_launch_cg_finish(const OptCg& c, hipStream_t st) {
+  hipLaunchKernelGGL(opt_cg_finish_kernel, dim3(1), dim3(kOptThreads), 0, st, c);
+  return hipGetLastError();
+}
+hipError_t opt_launch_out(const OptCg& c, int mode, const float* Hin, float* o1, float* o2, hipStream_t st) {
+  hipLaunchKernelGGL(opt_out_kernel, dim3(c.nblk, c.batch), dim3(kOptThreads), 0, st, c, mode, Hin, o1, o2);
+  return hipGetLastError();
+}
+hipError_t opt_launch_pixels(const float* in, float* out, int npix, int batch, bool transpose, hipStream_t st) {
+  const int nb = (npix + kOptThreads - 1) / kOptThreads;
+  hipLaunchKernelGGL(opt_pixels_kernel, dim3(nb < kOptBlocks ? nb : kOptBlocks, batch), dim3(kOptThreads), 0, st, in, out, npix,
+                     transpose ? 1 : 0);
+  return hipGetLastError();
+}
+
+}  // namespace qpat

@@ -139,3 +139,13 @@ def test_plan3d_host_checks(q):
     assert L.qpat3d_validate(None) == 1
     assert L.qpat3d_forward(None, None, None, 1, None) == 1
     assert L.qpat3d_set_tiles(None, 2, 1, 256, 256) == 1
+
+
+def test_optical_create_checks(q):
+    L = q.lib()
+    h = ctypes.c_void_p()
+    assert L.qpat_optical_create(0, 4, 1e-4, 1, ctypes.byref(h)) == 1
+    assert L.qpat_optical_create(4, 4, 0.0, 1, ctypes.byref(h)) == 1
+    assert L.qpat_optical_create(4, 4, 1e-4, 65, ctypes.byref(h)) == 1
+    assert L.qpat_optical_create(4, 4, 1e-4, 1, None) == 1
+    assert L.qpat_optical_forward(None, None, None, None, None, 1, 1e-8, 10, None, None) == 1

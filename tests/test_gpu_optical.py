@@ -1,0 +1,146 @@
+"""GPU parity of the optical operators (qpat_optical_*) with the optical
+oracle (oracle/optical.py) and of the composite QPAT Jacobian J = H_a P J_o
+with the composition of the two oracles: relative L2 <= 1e-5 on H, J_o dX and
+J_o^* H (FP64 solves, FP32 interfaces), 1e-4 on the composite (FP32 acoustic
+path); the FP32 adjoint identity of the composite."""
+import numpy as np
+import pytest
+
+import qpat_inputs as qi
+from oracle import kspace as K
+from oracle import optical as O
+
+pytestmark = pytest.mark.gpu
+
+SIDES = ["bottom", "top", "left", "right"]
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def q():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1810_11685_amd as q
+    return q
+
+
+def T(x):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float32, device="cuda")
+
+
+def N(t):
+    return t.detach().double().cpu().numpy()
+
+
+def tissue(mesh, B, seed):
+    """Smooth tissue-like elemental coefficients (SI units): mu_a about
+    0.01 /mm, mu_s' about 1 /mm, kappa = 1 / (3 (mu_a + mu_s'))."""
+    out_k, out_m = [], []
+    for b in range(B):
+        g = qi.smooth_noise(mesh.ny, mesh.nx, 3.0, seed + 2 * b)
+        g2 = qi.smooth_noise(mesh.ny, mesh.nx, 3.0, seed + 2 * b + 1)
+        mu = np.repeat((10.0 * (1.0 + 0.5 * g)).ravel(), 2)
+        mus = np.repeat((1000.0 * (1.0 + 0.3 * g2)).ravel(), 2)
+        out_k.append(1.0 / (3.0 * (mu + mus)))
+        out_m.append(mu)
+    return np.array(out_k, np.float32).astype(float), np.array(out_m, np.float32).astype(float)
+
+
+def oracle_G(mesh, cur):
+    return sum(cur[k] * O.load(mesh, [SIDES[k]]) for k in range(4))
+
+
+@pytest.mark.parametrize("nx,ny", [(24, 20), (7, 13)])
+def test_optical_forward_jv_jtv(q, nx, ny):
+    B = 2
+    dx = 1e-4
+    m = O.Mesh(nx, ny, dx)
+    kap, mu = tissue(m, B, 11)
+    cur = np.array([[1.0, 0.0, 0.5, 0.0], [0.0, 2.0, 0.0, 1.0]])
+    opt = q.Optical(nx, ny, dx, B)
+    H = N(opt.forward(T(kap), T(mu), cur))
+    rng = np.random.default_rng(12)
+    dk = (kap * rng.standard_normal(kap.shape)).astype(np.float32).astype(float)
+    dm = (mu * rng.standard_normal(mu.shape)).astype(np.float32).astype(float)
+    dH = N(opt.jv(T(dk), T(dm)))
+    Hq = rng.standard_normal(H.shape).astype(np.float32).astype(float)
+    gk, gm = (N(t) for t in opt.jtv(T(Hq)))
+    for b in range(B):
+        Hr, Phi = O.forward(m, kap[b], mu[b], oracle_G(m, cur[b]))
+        assert rel(H[b], Hr) <= 1e-5
+        assert rel(dH[b], O.jacobian(m, kap[b], mu[b], Phi, dk[b], dm[b])) <= 1e-5
+        ak, am = O.jacobian_adjoint(m, kap[b], mu[b], Phi, Hq[b])
+        assert rel(gk[b], ak) <= 1e-5
+        assert rel(gm[b], am) <= 1e-5
+    p = N(opt.pixels(T(H)))
+    assert np.allclose(p, np.stack([O.pixel_mean(m, H[b]) for b in range(B)]), rtol=1e-6, atol=0)
+    assert np.allclose(N(opt.pixels_T(T(p))), np.stack([O.pixel_mean_T(m, p[b]) for b in range(B)]), rtol=1e-6)
+
+
+def test_optical_paper_grid_four_illuminations(q):
+    """The paper's 2-D data-generation grid (128^2 pixels of 78.1 um), one
+    illumination per side (N_q = 4)."""
+    n, dx = 128, 7.81e-5
+    m = O.Mesh(n, n, dx)
+    kap, mu = tissue(m, 4, 21)
+    cur = np.eye(4)
+    opt = q.Optical(n, n, dx, 4)
+    H = N(opt.forward(T(kap), T(mu), cur))
+    assert opt.iters > 0
+    for b in range(4):
+        assert rel(H[b], O.forward(m, kap[b], mu[b], oracle_G(m, cur[b]))[0]) <= 1e-5
+
+
+def test_composite_jacobian(q):
+    """H_a P H_o, J and J^* of the composite against the composed oracles, and
+    the FP32 adjoint identity <J dX, r> = <dX, J^* r>."""
+    n, nt, B = 48, 60, 2
+    dx = 1e-4
+    c0, rho0 = qi.medium(n, n, 31, 32, sigma_cells=4.0)
+    prm = qi.make_params(n, n, dx, 0.3 * dx / c0.max(), nt, c0.max(), qi.ring_sensors(20, 18.5, dx, phase=0.1),
+                         pml_size=6, alpha0_db=0.75)
+    m = O.Mesh(n, n, dx)
+    kap, mu = tissue(m, B, 33)
+    cur = np.array([[1.0, 0, 0, 0], [0, 0, 1.0, 0]])
+    plan = q.Plan(prm, c0, rho0)
+    opt = q.Optical(n, n, dx, B)
+    Jc = q.QPATJacobian(plan, opt)
+    d = N(Jc.forward(T(kap), T(mu), cur))
+    ops = K.Operators(prm, c0, rho0)
+    Phis = []
+    for b in range(B):
+        Hr, Phi = O.forward(m, kap[b], mu[b], oracle_G(m, cur[b]))
+        Phis.append(Phi)
+        assert rel(d[b], K.forward(prm, c0, rho0, O.pixel_mean(m, Hr), ops=ops)) <= 1e-4
+    rng = np.random.default_rng(34)
+    dk = (kap * rng.standard_normal(kap.shape)).astype(np.float32).astype(float)
+    dm = (mu * rng.standard_normal(mu.shape)).astype(np.float32).astype(float)
+    jd = N(Jc.jv(T(dk), T(dm)))
+    r = rng.standard_normal(jd.shape).astype(np.float32).astype(float)
+    gk, gm = (N(t) for t in Jc.jtv(T(r)))
+    for b in range(B):
+        dH = O.jacobian(m, kap[b], mu[b], Phis[b], dk[b], dm[b])
+        assert rel(jd[b], K.forward(prm, c0, rho0, O.pixel_mean(m, dH), ops=ops)) <= 1e-4
+        g = O.pixel_mean_T(m, K.adjoint(prm, c0, rho0, r[b], ops=ops))
+        ak, am = O.jacobian_adjoint(m, kap[b], mu[b], Phis[b], g)
+        assert rel(gk[b], ak) <= 1e-4
+        assert rel(gm[b], am) <= 1e-4
+        lhs = float(np.sum(jd[b] * r[b]))
+        rhs = float(np.sum(dk[b] * gk[b]) + np.sum(dm[b] * gm[b]))
+        assert abs(lhs - rhs) <= 1e-4 * (np.linalg.norm(jd[b]) * np.linalg.norm(r[b]))
+
+
+def test_optical_argument_checks(q):
+    opt = q.Optical(8, 8, 1e-4, 2)
+    import torch
+    with pytest.raises(RuntimeError):
+        opt.jv(torch.zeros(2, 128, device="cuda"), torch.zeros(2, 128, device="cuda"))   # before forward
+    with pytest.raises(ValueError):
+        opt.forward(torch.zeros(2, 100, device="cuda"), torch.zeros(2, 100, device="cuda"), np.ones((2, 4)))
