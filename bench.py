@@ -52,6 +52,14 @@ PASS_BYTES = {
 }
 
 
+# Algorithmic HBM bytes per FEM node of one conjugate-gradient iteration of
+# the optical solve (FP64): A p reads p and the two elemental coefficients of
+# the pixel it owns (8 + 32) and writes q (8); the update reads x, p, r, q and
+# the inverse diagonal (40) and writes x, r (16); the new direction reads the
+# inverse diagonal, r, p (24) and writes p (8).
+OPT_BYTES_PER_NODE_ITER = 136.0
+
+
 def bytes_3d_pair(nx: int) -> float:
     """Algorithmic HBM bytes per grid point of one lossy 3-D forward + adjoint
     iterate pair.  A half spectrum holds h = (nx/2 + 1)/nx complex values per
@@ -137,6 +145,7 @@ def main():
     ap.add_argument("--no-recon", action="store_true", help="skip the reconstruction-driver measurement")
     ap.add_argument("--no-medium", action="store_true", help="skip the sound-speed gradient measurement")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3-D solver measurement")
+    ap.add_argument("--no-optical", action="store_true", help="skip the optical operator measurement")
     ap.add_argument("--batches3d", default="1,3,16", help="batch sizes of the 3-D measurement")
     ap.add_argument("--tiles", default=None,
                     help="launch shape rows,cols,row_threads,col_threads of the headline plan (skips tuning)")
@@ -450,6 +459,44 @@ def main():
                         "runs": runs}
         del plan3
         torch.cuda.empty_cache()
+
+    # ------------------------------------------------------------ optical operators
+    # The diffusion-approximation solve (FP64 Jacobi-CG on the grid-matched P1
+    # mesh) for N_q = 4 illuminations (one per side), on the paper's 2-D
+    # data-generation grid (128^2 pixels of 78.1 um) and on the headline
+    # 512^2 grid; then one composite J dX and J^* r on the headline workload.
+    if not args.no_optical:
+        runs = {}
+        for n_o, dx_o in ((128, 7.81e-5), (512, 1e-4)):
+            opt = q.Optical(n_o, n_o, dx_o, 4, tol=1e-8)
+            g1 = qi.smooth_noise(n_o, n_o, 8.0, 4100)
+            g2 = qi.smooth_noise(n_o, n_o, 8.0, 4101)
+            mu_e = np.repeat((10.0 * (1.0 + 0.5 * g1)).ravel(), 2)
+            kap_e = np.repeat((1.0 / (3.0 * (10.0 * (1.0 + 0.5 * g1) + 1000.0 * (1.0 + 0.3 * g2)))).ravel(), 2)
+            kt, mt = T(np.stack([kap_e] * 4)), T(np.stack([mu_e] * 4))
+            with torch.cuda.stream(stream):
+                opt.forward(kt, mt, np.eye(4), stream=stream)
+                sync()
+                t = time.perf_counter()
+                opt.forward(kt, mt, np.eye(4), stream=stream)
+                sync()
+                t_f = time.perf_counter() - t
+                its = opt.iters
+                t = time.perf_counter()
+                opt.jv(kt, mt, stream=stream)
+                sync()
+                t_j = time.perf_counter() - t
+            nn_o = (n_o + 1) ** 2
+            gbs = OPT_BYTES_PER_NODE_ITER * nn_o * 4 * its / t_f / 1e9
+            runs[f"{n_o}"] = {"grid": [n_o, n_o], "illuminations": 4, "forward_s": round(t_f, 4), "cg_iterations": its,
+                              "us_per_iteration": round(t_f / its * 1e6, 2), "jv_s": round(t_j, 4),
+                              "algorithmic_GB_s": round(gbs, 1)}
+            log(f"optical {n_o}^2 x4: forward {t_f * 1e3:.1f} ms ({its} CG iterations, "
+                f"{t_f / its * 1e6:.1f} us each, {gbs:.0f} GB/s), J_o v {t_j * 1e3:.1f} ms")
+            del opt
+        out["optical"] = {"workload": "P1-FEM diffusion approximation (Robin boundary) on the grid-matched mesh, "
+                                      "4 illuminations, FP64 Jacobi-CG to 1e-8",
+                          "bytes_per_node_per_iteration": OPT_BYTES_PER_NODE_ITER, "runs": runs}
 
     # ------------------------------------------------------------ CPU baseline (oracle)
     if not args.no_cpu:
