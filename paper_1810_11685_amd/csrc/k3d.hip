@@ -457,6 +457,12 @@ __global__ void __launch_bounds__(kPlaneMax) plane3_kernel(const Launch3 L, int 
   int item, tile;
   if (!locate(L.nitems, ntile, chunk, item, tile)) return;
   const Medium3& M = L.m;
+  const int nsplit = plane3_split(MODE, M);
+  int sub = 0;   // the one field of this block when split
+  if (nsplit > 1) {
+    sub = tile % nsplit;
+    tile /= nsplit;
+  }
   const Work3 W = shift(L.w0, item * L.wstride);
   const int ct = M.ct, ny = M.ny, nz = M.nz, nl = M.nlines;
   const int c0 = tile * ct, ncols = min(ct, M.nxh1 - c0);
@@ -499,7 +505,16 @@ __global__ void __launch_bounds__(kPlaneMax) plane3_kernel(const Launch3 L, int 
     return c < ncols ? symbol(M, cd, c0 + c, y, z) : make_float2(0.f, 0.f);
   };
 
-  if (M.wide) {
+  if (nsplit > 1) {
+    // one field of a diagonal pass: reads and writes only its own spectrum
+    load(sub, b0);
+    __syncthreads();
+    float2* F = fwd(b0, b1);
+    const int cd = plane_code<MODE>(sub, code);
+    for (int i = tid; i < cnt; i += B) F[i] = cmul(F[i], mult(cd, i));
+    __syncthreads();
+    store(sub, inv(F, F == b0 ? b1 : b0));
+  } else if (M.wide) {
     // every field of the pass transformed at once: more butterflies per
     // stage and a third of the barriers (six buffers of one chunk in LDS)
     float2* R0 = buf;

@@ -22,6 +22,7 @@ constexpr int kMaxN = 128;           // longest axis
 constexpr int kMaxStages = 8;        // FFT stages per axis
 constexpr size_t kMaxLds = 163840;   // gfx950 LDS per work-group
 constexpr int kXcds = 8;
+constexpr int kCus = 256;            // MI355X compute units
 
 // FFT plan of one axis: the radices in stage order (2, 3, 4, 5, 7, 8 have
 // their own butterflies; any other prime runs as a direct DFT stage).
@@ -55,6 +56,7 @@ struct Medium3 {
   int rt, ct, ctiles;                 // lines per row tile, columns per plane tile, column tiles
   int rthr, pthr;                     // threads per row / plane block
   int wide;                           // plane blocks hold all fields of a pass at once
+  int split;                          // diagonal plane passes: one block per (column tile, field)
   AxisPlan px, py, pz;
   const float *c2, *c2eta, *c2tau, *rho0;      // [N]
   const float *bx, *by, *bz;                   // dt / rho0 at the staggered positions [N]
@@ -122,6 +124,12 @@ inline size_t plane3_lds(int ny, int nz, int ct, bool wide) {
 }
 
 hipError_t launch_row3(int mode, const Launch3& L, int ntile, int chunk, int n, hipStream_t st);
+// blocks per column tile of a plane pass: one per field for the diagonal
+// passes when split, else one
+__host__ __device__ inline int plane3_split(int mode, const Medium3& m) {
+  if (!m.split) return 1;
+  return (mode == P3_GRADM2 || mode == P3_GRADP2) ? 3 : mode == P3_FRAC ? 2 : 1;
+}
 hipError_t launch_plane3(int mode, int code, const Launch3& L, int ntile, int chunk, int n, hipStream_t st);
 hipError_t launch_combine3(const Launch3& L, hipStream_t st);
 hipError_t k3d_allow_lds(size_t bytes);

@@ -192,3 +192,18 @@ def test_wide_and_narrow_plane_blocks_agree_bitwise(q):
     assert np.array_equal(N(plan.forward(x)), d1)
     assert np.array_equal(N(plan.adjoint(r)), g1)
     assert rel(d1[0], K3.forward(prm, c0, rho0, p0)) <= TOL
+
+
+def test_split_and_joint_plane_passes_agree_bitwise(q):
+    """Small batches run the diagonal plane passes one block per field, large
+    ones all fields per block (65 column tiles: 4 vectors reach the 256 CUs):
+    the same bits per vector either way."""
+    prm, c0, rho0, p0 = problem(128, 8, 8, 10, ns=5, pml=1)
+    plan = q.Plan3D(prm, c0, rho0)
+    xs = np.stack([p0] + [qi.gaussian_field(p0.shape, 60 + b) for b in range(3)])
+    r = qi.gaussian_field((4, 10, 5), 64)
+    d4, g4 = N(plan.forward(T(xs))), N(plan.adjoint(T(r)))
+    for b in range(4):
+        assert np.array_equal(N(plan.forward(T(xs[b]))), d4[b])
+        assert np.array_equal(N(plan.adjoint(T(r[b]))), g4[b])
+    assert rel(d4[0], K3.forward(prm, c0, rho0, p0)) <= TOL
