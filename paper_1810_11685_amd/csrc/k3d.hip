@@ -420,8 +420,11 @@ __global__ void __launch_bounds__(kRowMax) row3_kernel(const Launch3 L, int ntil
     const float2* Zl = Z + (o * hp + j) * nx;
     const float2 zk = Zl[c], zm = Zl[c == 0 ? 0 : nx - c];
     const int la = l0 + 2 * j, lb = la + 1;
-    if (la < nl) W.s[spec_index(M, o, c, la)] = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
-    if (lb < nl) W.s[spec_index(M, o, c, lb)] = make_float2(0.5f * (zk.y + zm.y), 0.5f * (zm.x - zk.x));
+    // the pressure goes to spectrum 3, which the gradient pass reads while it
+    // writes spectra 0..2
+    const int of = (MODE == R3_F2L || MODE == R3_F3) ? 3 : o;
+    if (la < nl) W.s[spec_index(M, of, c, la)] = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
+    if (lb < nl) W.s[spec_index(M, of, c, lb)] = make_float2(0.5f * (zk.y + zm.y), 0.5f * (zm.x - zk.x));
   }
 }
 
@@ -506,8 +509,9 @@ __global__ void __launch_bounds__(kPlaneMax) plane3_kernel(const Launch3 L, int 
   };
 
   if (nsplit > 1) {
-    // one field of a diagonal pass: reads and writes only its own spectrum
-    load(sub, b0);
+    // one field of a diagonal pass (reads and writes only its own spectrum),
+    // or one output of the gradient (reads spectrum 3)
+    load(MODE == P3_GRADP1 ? 3 : sub, b0);
     __syncthreads();
     float2* F = fwd(b0, b1);
     const int cd = plane_code<MODE>(sub, code);
@@ -539,7 +543,7 @@ __global__ void __launch_bounds__(kPlaneMax) plane3_kernel(const Launch3 L, int 
       for (int f = 0; f < k; ++f) store(f, src + f * cnt);
     };
     if constexpr (MODE == P3_GRADP1) {
-      loadk(1, R0);
+      load(3, R0);
       __syncthreads();
       float2* F = fwdk(R0, R1, 1);
       float2* X = (F == R0) ? R1 : R0;
@@ -574,7 +578,7 @@ __global__ void __launch_bounds__(kPlaneMax) plane3_kernel(const Launch3 L, int 
       storek(nf, invk(F, F == R0 ? R1 : R0, nf));
     }
   } else if constexpr (MODE == P3_GRADP1) {
-    load(0, b0);
+    load(3, b0);
     __syncthreads();
     float2* F = fwd(b0, b1);
     float2* x1 = (F == b0) ? b1 : b0;

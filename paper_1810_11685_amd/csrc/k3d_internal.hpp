@@ -56,7 +56,7 @@ struct Medium3 {
   int rt, ct, ctiles;                 // lines per row tile, columns per plane tile, column tiles
   int rthr, pthr;                     // threads per row / plane block
   int wide;                           // plane blocks hold all fields of a pass at once
-  int split;                          // diagonal plane passes: one block per (column tile, field)
+  int split;                          // plane passes: one block per (column tile, field or output)
   AxisPlan px, py, pz;
   const float *c2, *c2eta, *c2tau, *rho0;      // [N]
   const float *bx, *by, *bz;                   // dt / rho0 at the staggered positions [N]
@@ -74,7 +74,7 @@ struct Medium3 {
 // Per-vector work buffers.
 struct Work3 {
   float* f;       // 7 fields of N: forward v_x v_y v_z rho_x rho_y rho_z p; adjoint their adjoints, q
-  float2* s;      // 3 half spectra, each ctiles * ct * nlines
+  float2* s;      // 4 half spectra, each ctiles * ct * nlines (3: the pressure of the forward)
   float* part;    // forward: sensor partials [nt][ns][4]
 };
 
@@ -105,7 +105,7 @@ enum Row3 : int {
 };
 
 enum Plane3 : int {
-  P3_GRADP1 = 0,  // 1 -> 3: d_x^+, d_y^+, d_z^+ of one field
+  P3_GRADP1 = 0,  // 1 -> 3: d_x^+, d_y^+, d_z^+ of spectrum 3 into spectra 0..2
   P3_GRADM2 = 1,  // 3 -> 3: d_i^- of field i
   P3_FRAC = 2,    // 2 -> 2: Y_dis of field 0, Y_abs of field 1
   P3_GRADP2 = 3,  // 3 -> 3: d_i^+ of field i
@@ -124,11 +124,11 @@ inline size_t plane3_lds(int ny, int nz, int ct, bool wide) {
 }
 
 hipError_t launch_row3(int mode, const Launch3& L, int ntile, int chunk, int n, hipStream_t st);
-// blocks per column tile of a plane pass: one per field for the diagonal
-// passes when split, else one
+// blocks per column tile of a plane pass: when split, one per field of the
+// diagonal passes and one per output of the gradient, else one
 __host__ __device__ inline int plane3_split(int mode, const Medium3& m) {
   if (!m.split) return 1;
-  return (mode == P3_GRADM2 || mode == P3_GRADP2) ? 3 : mode == P3_FRAC ? 2 : 1;
+  return (mode == P3_GRADM2 || mode == P3_GRADP2 || mode == P3_GRADP1) ? 3 : mode == P3_FRAC ? 2 : 1;
 }
 hipError_t launch_plane3(int mode, int code, const Launch3& L, int ntile, int chunk, int n, hipStream_t st);
 hipError_t launch_combine3(const Launch3& L, hipStream_t st);

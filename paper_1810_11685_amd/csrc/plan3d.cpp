@@ -470,7 +470,7 @@ qpat_status plan3_build(qpat_plan3d P, const double* c0, const double* rho0) {
   return QPAT_OK;
 }
 
-// Work buffers of `count` vectors: 7 fields, 3 half spectra, sensor partials
+// Work buffers of `count` vectors: 7 fields, 4 half spectra, sensor partials
 // and a data buffer for jtjv.
 qpat_status reserve3(qpat_plan3d P, int count) {
   if (count <= P->cap) return QPAT_OK;
@@ -487,7 +487,7 @@ qpat_status reserve3(qpat_plan3d P, int count) {
   const size_t specN = size_t(2 * M.nxh1) * M.nlines;
   const size_t nd = size_t(M.nt) * M.ns;
   Carver cv;
-  const size_t o_f = cv.take<float>(7 * N), o_s = cv.take<float2>(3 * specN), o_p = cv.take<float>(4 * nd + 1),
+  const size_t o_f = cv.take<float>(7 * N), o_s = cv.take<float2>(4 * specN), o_p = cv.take<float>(4 * nd + 1),
                o_d = cv.take<float>(nd + 1);
   const size_t per = (cv.off + 255) & ~size_t(255);
   char* d = nullptr;
@@ -516,9 +516,11 @@ qpat_status exec3(qpat_plan3d P, int b, Exec3** out) {
     H3CHK(hipHostMalloc(&E->h_io, sizeof(IO3) * b, hipHostMallocDefault));
     H3CHK(hipEventCreateWithFlags(&E->ev, hipEventDisableTiming));
     E->L.io = E->d_io;
-    // diagonal plane passes go one block per field while a launch would
-    // otherwise have fewer blocks than the GPU has CUs (small batches)
-    E->L.m.split = b * P->med.ctiles < kCus ? 1 : 0;
+    // plane passes go one block per field (diagonal passes) or per output
+    // (gradient) while even the split launch fits within the GPU's CUs
+    // (small batches: a 2401-point field fills only a third of a block's
+    // butterfly slots, which costs more than it gains once the CUs are busy)
+    E->L.m.split = 3 * b * P->med.ctiles <= kCus ? 1 : 0;
     const Medium3& M = P->med;
     E->row_ntile = (M.nlines + M.rt - 1) / M.rt;
     E->pl_ntile = M.ctiles;

@@ -195,9 +195,9 @@ def test_wide_and_narrow_plane_blocks_agree_bitwise(q):
 
 
 def test_split_and_joint_plane_passes_agree_bitwise(q):
-    """Small batches run the diagonal plane passes one block per field, large
-    ones all fields per block (65 column tiles: 4 vectors reach the 256 CUs):
-    the same bits per vector either way."""
+    """Small batches run the plane passes one block per field or output, large
+    ones all fields per block (65 column tiles: one vector splits, four do
+    not): the same bits per vector either way."""
     prm, c0, rho0, p0 = problem(128, 8, 8, 10, ns=5, pml=1)
     plan = q.Plan3D(prm, c0, rho0)
     xs = np.stack([p0] + [qi.gaussian_field(p0.shape, 60 + b) for b in range(3)])
