@@ -146,7 +146,7 @@ def main():
     ap.add_argument("--no-medium", action="store_true", help="skip the sound-speed gradient measurement")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3-D solver measurement")
     ap.add_argument("--no-optical", action="store_true", help="skip the optical operator measurement")
-    ap.add_argument("--batches3d", default="1,3,16", help="batch sizes of the 3-D measurement")
+    ap.add_argument("--batches3d", default="1,3,8,16", help="batch sizes of the 3-D measurement")
     ap.add_argument("--tiles", default=None,
                     help="launch shape rows,cols,row_threads,col_threads of the headline plan (skips tuning)")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work")
