@@ -152,7 +152,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only (the operator shards over independent "
+        print("bench.py: the library runs on one GPU (the operator shards over independent "
               "solves, not within one); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
