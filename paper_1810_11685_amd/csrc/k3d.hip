@@ -76,21 +76,37 @@ __device__ __forceinline__ void dft(float2* v) {
       v[q + 4] = csub(e[q], o[q]);
     }
   } else {
-    float2 out[R];
+    // odd R: pair inputs r and R - r.  With a_r = x_r + x_{R-r} and
+    // b_r = x_r - x_{R-r}, output q is x_0 + sum_r cos(2 pi r q / R) a_r
+    // -+ i sum_r sin(2 pi r q / R) b_r, and output R - q takes the other sign.
+    constexpr int H = (R - 1) / 2;
+    float2 a[H], b[H];
 #pragma unroll
-    for (int q = 0; q < R; ++q) {
-      float2 acc = v[0];
-#pragma unroll
-      for (int r = 1; r < R; ++r) {
-        const int m = (r * q) % R;
-        const float c = ucos(R, m), s = INV ? usin(R, m) : -usin(R, m);
-        acc.x += v[r].x * c - v[r].y * s;
-        acc.y += v[r].x * s + v[r].y * c;
-      }
-      out[q] = acc;
+    for (int r = 1; r <= H; ++r) {
+      a[r - 1] = cadd(v[r], v[R - r]);
+      b[r - 1] = csub(v[r], v[R - r]);
     }
+    float2 y0 = v[0];
 #pragma unroll
-    for (int q = 0; q < R; ++q) v[q] = out[q];
+    for (int r = 0; r < H; ++r) y0 = cadd(y0, a[r]);
+#pragma unroll
+    for (int q = 1; q <= H; ++q) {
+      float2 A = v[0], S = make_float2(0.f, 0.f);
+#pragma unroll
+      for (int r = 1; r <= H; ++r) {
+        const int m = (r * q) % R;
+        const float c = ucos(R, m), sn = usin(R, m);
+        A.x += c * a[r - 1].x;
+        A.y += c * a[r - 1].y;
+        S.x += sn * b[r - 1].x;
+        S.y += sn * b[r - 1].y;
+      }
+      // forward: y_q = A - i S, y_{R-q} = A + i S (inverse: the signs swap)
+      const float2 iS = make_float2(-S.y, S.x);
+      v[q] = INV ? cadd(A, iS) : csub(A, iS);
+      v[R - q] = INV ? csub(A, iS) : cadd(A, iS);
+    }
+    v[0] = y0;
   }
 }
 
@@ -120,11 +136,13 @@ __device__ void stage_small(const float2* __restrict__ src, float2* __restrict__
     float2 v[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) v[r] = src[off + (j + r * nb) * m.es];
+    if (Ns > 1) {  // the first stage's twiddles are all 1 (block-uniform test)
 #pragma unroll
-    for (int r = 1; r < R; ++r) {
-      float2 w = tw[r * k * tstep];
-      if (INV) w.y = -w.y;
-      v[r] = cmul(v[r], w);
+      for (int r = 1; r < R; ++r) {
+        float2 w = tw[r * k * tstep];
+        if (INV) w.y = -w.y;
+        v[r] = cmul(v[r], w);
+      }
     }
     dft<R, INV>(v);
     const int base = (j - k) * R + k;
