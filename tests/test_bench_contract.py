@@ -1,0 +1,32 @@
+"""CPU checks of the benchmark's contract that need no GPU: more than one GPU
+is refused with a message, and the algorithmic byte counts it reports follow
+their stated per-pass sums."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+
+@pytest.mark.parametrize("n", [2, 8])
+def test_more_than_one_gpu_is_refused(n):
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", str(n)], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+def test_byte_counts():
+    import bench
+    # 2-D: each forward and adjoint iterate moves 160 B per point in the 12 passes
+    fwd = [bench.PASS_BYTES[i] for i in range(6)]
+    adj = [bench.PASS_BYTES[i] for i in range(6, 12)]
+    assert sum(fwd) == 160 and sum(adj) == 160
+    # 3-D: 172 + 480 h with h = (nx/2 + 1)/nx; 49^3 gives 416.9 B per point and iterate pair
+    assert bench.bytes_3d_pair(49) == pytest.approx(172 + 480 * 25 / 49)
+    assert bench.bytes_3d_pair(64) == pytest.approx(172 + 480 * 33 / 64)
+    assert bench.OPT_BYTES_PER_NODE_ITER == 48 + 56 + 32
