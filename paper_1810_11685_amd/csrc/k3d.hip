@@ -116,7 +116,7 @@ __device__ __forceinline__ void dft(float2* v) {
 struct LineMap {
   int nlines, lpg, gs, ls, es;
 };
-__device__ __forceinline__ int line_off(const LineMap& m, int L, float rlpg) {
+__device__ __forceinline__ int line_off(const LineMap m, int L, float rlpg) {
   const int g = udiv(L, rlpg);
   return g * m.gs + (L - g * m.lpg) * m.ls;
 }
@@ -125,7 +125,7 @@ __device__ __forceinline__ int line_off(const LineMap& m, int L, float rlpg) {
 // src[j + r n/R], twiddles input r by w^(r k n/(Ns R)) with k = j mod Ns, and
 // writes dst[(j - k) R + k + r Ns].
 template <int R, bool INV>
-__device__ void stage_small(const float2* __restrict__ src, float2* __restrict__ dst, const LineMap& m, int n,
+__device__ void stage_small(const float2* __restrict__ src, float2* __restrict__ dst, const LineMap m, int n,
                             int Ns, const float2* __restrict__ tw) {
   const int nb = n / R, tstep = n / (Ns * R), total = m.nlines * nb;
   const float rnb = rcp(nb), rns = rcp(Ns), rlpg = rcp(m.lpg);
@@ -154,7 +154,7 @@ __device__ void stage_small(const float2* __restrict__ src, float2* __restrict__
 // A stage of a prime radix R without a butterfly of its own: every thread
 // computes one output as a direct sum of R twiddled inputs.
 template <bool INV>
-__device__ void stage_generic(const float2* __restrict__ src, float2* __restrict__ dst, const LineMap& m, int n,
+__device__ void stage_generic(const float2* __restrict__ src, float2* __restrict__ dst, const LineMap m, int n,
                               int Ns, int R, const float2* __restrict__ tw) {
   const int nb = n / R, tstep = n / (Ns * R), total = m.nlines * n;
   const float rn = rcp(n), rnsr = rcp(Ns * R), rns = rcp(Ns), rlpg = rcp(m.lpg);
@@ -182,12 +182,16 @@ __device__ void stage_generic(const float2* __restrict__ src, float2* __restrict
 // All stages of one axis (barrier after each); returns the buffer holding the
 // result (a or b).
 template <bool INV>
-__device__ float2* fft_axis(float2* a, float2* b, const LineMap& m, const AxisPlan& P, const float2* tw) {
+__device__ float2* fft_axis(float2* a, float2* b, const LineMap m, const AxisPlan P, const float2* tw) {
+  // radices packed 8 bits a stage: a dynamic index into P would put P in scratch
+  unsigned long long rad = 0;
+#pragma unroll
+  for (int st = 0; st < kMaxStages; ++st) rad |= (unsigned long long)(P.r[st] & 255) << (8 * st);
   float2* s = a;
   float2* d = b;
   int Ns = 1;
   for (int st = 0; st < P.nst; ++st) {
-    const int R = P.r[st];
+    const int R = int((rad >> (8 * st)) & 255);
     switch (R) {
       case 2: stage_small<2, INV>(s, d, m, P.n, Ns, tw); break;
       case 3: stage_small<3, INV>(s, d, m, P.n, Ns, tw); break;
