@@ -452,7 +452,7 @@ __global__ void __launch_bounds__(kRowMax) row3_kernel(const Launch3 L, int ntil
 
 // ---------------------------------------------------------------- plane pass
 __device__ __forceinline__ float2 symbol(const Medium3& M, int code, int col, int y, int z) {
-  const size_t k = (size_t(z) * M.ny + y) * M.nxh1 + col;
+  const size_t k = size_t(col) * M.nlines + size_t(z) * M.ny + y;
   switch (code) {
     case OP_DXP: return cscale(M.dxp[col], M.kap[k]);
     case OP_DXM: return cscale(M.dxm[col], M.kap[k]);

@@ -62,7 +62,7 @@ struct Medium3 {
   const float *bx, *by, *bz;                   // dt / rho0 at the staggered positions [N]
   const float *avx, *arx, *avy, *ary, *avz, *arz;  // PML diagonals [nx] / [ny] / [nz]
   const float2 *dxp, *dxm, *dyp, *dym, *dzp, *dzm;  // 1-D symbols i k e^{+-i k d/2}: [nxh1] / [ny] / [nz]
-  const float *kap, *ldis, *labs;              // [nz][ny][nxh1], each divided by N
+  const float *kap, *ldis, *labs;              // [nxh1][nz][ny] (a column's lines contiguous), each / N
   const float2 *twx, *twy, *twz;               // e^{-2 pi i m / n}, m < n
   const int* tap_off;                          // [nlines + 1]
   const Tap3* taps;

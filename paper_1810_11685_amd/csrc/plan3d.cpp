@@ -333,7 +333,7 @@ qpat_status plan3_build(qpat_plan3d P, const double* c0, const double* rho0) {
         const double K = std::sqrt(kx * kx + ky * ky + kz * kz);
         const double arg = p.c_ref * K * dt / 2.0;
         const double kp = arg == 0.0 ? 1.0 : std::sin(arg) / arg;
-        const size_t t = (size_t(k) * ny + j) * nxh1 + i;
+        const size_t t = size_t(i) * nl + size_t(k) * ny + j;   // [column][line]
         kap[t] = float(kp * inv);
         ldis[t] = (K == 0.0 || !lossy) ? 0.f : float(std::pow(K, p.y - 1.0) * inv);
         labs[t] = (K == 0.0 || !lossy) ? 0.f : float(std::pow(K, p.y - 2.0) * inv);
