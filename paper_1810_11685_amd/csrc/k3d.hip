@@ -482,11 +482,11 @@ __global__ void __launch_bounds__(kPlaneMax) plane3_kernel(const Launch3 L, int 
   int item, tile;
   if (!locate(L.nitems, ntile, chunk, item, tile)) return;
   const Medium3& M = L.m;
-  const int nsplit = plane3_split(MODE, M);
-  int sub = 0;   // the one field of this block when split
-  if (nsplit > 1) {
-    sub = tile % nsplit;
-    tile /= nsplit;
+  constexpr int NSPLIT = plane3_split(MODE);
+  int sub = 0;   // the field (diagonal passes) or output (gradient) of this block
+  if constexpr (NSPLIT > 1) {
+    sub = tile % NSPLIT;
+    tile /= NSPLIT;
   }
   const Work3 W = shift(L.w0, item * L.wstride);
   const int ct = M.ct, ny = M.ny, nz = M.nz, nl = M.nlines;
@@ -530,9 +530,9 @@ __global__ void __launch_bounds__(kPlaneMax) plane3_kernel(const Launch3 L, int 
     return c < ncols ? symbol(M, cd, c0 + c, y, z) : make_float2(0.f, 0.f);
   };
 
-  if (nsplit > 1) {
+  if constexpr (MODE != P3_DIVM) {
     // one field of a diagonal pass (reads and writes only its own spectrum),
-    // or one output of the gradient (reads spectrum 3)
+    // one output of the gradient (reads spectrum 3), or a single operator
     load(MODE == P3_GRADP1 ? 3 : sub, b0);
     __syncthreads();
     float2* F = fwd(b0, b1);
@@ -541,78 +541,29 @@ __global__ void __launch_bounds__(kPlaneMax) plane3_kernel(const Launch3 L, int 
     __syncthreads();
     store(sub, inv(F, F == b0 ? b1 : b0));
   } else if (M.wide) {
-    // every field of the pass transformed at once: more butterflies per
-    // stage and a third of the barriers (six buffers of one chunk in LDS)
+    // the three fields transformed at once: more butterflies per stage and a
+    // third of the barriers (six buffers of one chunk in LDS)
     float2* R0 = buf;
     float2* R1 = buf + 3 * cnt;
-    const float rcnt = rcp(cnt);
     auto fwdk = [&](float2* a, float2* b, int k) {
       const LineMap yk{k * nz * ct, ct, ny * ct, 1, ct};
       const LineMap zk{k * ny * ct, ny * ct, cnt, 1, ny * ct};
       float2* r = fft_axis<false>(a, b, yk, M.py, twy);
       return fft_axis<false>(r, r == a ? b : a, zk, M.pz, twz);
     };
-    auto invk = [&](float2* a, float2* b, int k) {
-      const LineMap yk{k * nz * ct, ct, ny * ct, 1, ct};
-      const LineMap zk{k * ny * ct, ny * ct, cnt, 1, ny * ct};
-      float2* r = fft_axis<true>(a, b, zk, M.pz, twz);
-      return fft_axis<true>(r, r == a ? b : a, yk, M.py, twy);
-    };
-    auto loadk = [&](int k, float2* dst) {
-      for (int f = 0; f < k; ++f) load(f, dst + f * cnt);
-    };
-    auto storek = [&](int k, const float2* src) {
-      for (int f = 0; f < k; ++f) store(f, src + f * cnt);
-    };
-    if constexpr (MODE == P3_GRADP1) {
-      load(3, R0);
-      __syncthreads();
-      float2* F = fwdk(R0, R1, 1);
-      float2* X = (F == R0) ? R1 : R0;
-      for (int i = tid; i < 3 * cnt; i += B) {
-        const int o = udiv(i, rcnt), ii = i - o * cnt;
-        X[i] = cmul(F[ii], mult(plane_code<MODE>(o, code), ii));
-      }
-      __syncthreads();
-      storek(3, invk(X, X == R0 ? R1 : R0, 3));
-    } else if constexpr (MODE == P3_DIVM) {
-      loadk(3, R0);
-      __syncthreads();
-      float2* F = fwdk(R0, R1, 3);
-      float2* A = (F == R0) ? R1 : R0;
-      for (int i = tid; i < cnt; i += B) {
-        float2 acc = cmul(F[i], mult(plane_code<MODE>(0, code), i));
-        acc = cadd(acc, cmul(F[cnt + i], mult(plane_code<MODE>(1, code), i)));
-        A[i] = cadd(acc, cmul(F[2 * cnt + i], mult(plane_code<MODE>(2, code), i)));
-      }
-      __syncthreads();
-      storek(1, invk(A, A + cnt, 1));
-    } else {
-      const int nf = (MODE == P3_APPLY) ? 1 : (MODE == P3_FRAC) ? 2 : 3;
-      loadk(nf, R0);
-      __syncthreads();
-      float2* F = fwdk(R0, R1, nf);
-      for (int i = tid; i < nf * cnt; i += B) {
-        const int f = udiv(i, rcnt);
-        F[i] = cmul(F[i], mult(plane_code<MODE>(f, code), i - f * cnt));
-      }
-      __syncthreads();
-      storek(nf, invk(F, F == R0 ? R1 : R0, nf));
-    }
-  } else if constexpr (MODE == P3_GRADP1) {
-    load(3, b0);
+    for (int f = 0; f < 3; ++f) load(f, R0 + f * cnt);
     __syncthreads();
-    float2* F = fwd(b0, b1);
-    float2* x1 = (F == b0) ? b1 : b0;
-    float2* x2 = b2;
-    for (int o = 0; o < 3; ++o) {
-      const int cd = plane_code<MODE>(o, code);
-      for (int i = tid; i < cnt; i += B) x1[i] = cmul(F[i], mult(cd, i));
-      __syncthreads();
-      store(o, inv(x1, x2));
-      __syncthreads();
+    float2* F = fwdk(R0, R1, 3);
+    float2* A = (F == R0) ? R1 : R0;
+    for (int i = tid; i < cnt; i += B) {
+      float2 acc = cmul(F[i], mult(plane_code<MODE>(0, code), i));
+      acc = cadd(acc, cmul(F[cnt + i], mult(plane_code<MODE>(1, code), i)));
+      A[i] = cadd(acc, cmul(F[2 * cnt + i], mult(plane_code<MODE>(2, code), i)));
     }
-  } else if constexpr (MODE == P3_DIVM) {
+    __syncthreads();
+    store(0, inv(A, A + cnt));
+  } else {
+    // one field at a time, the sum kept in a third buffer
     float2* acc = b2;
     for (int f = 0; f < 3; ++f) {
       load(f, b0);
@@ -626,18 +577,6 @@ __global__ void __launch_bounds__(kPlaneMax) plane3_kernel(const Launch3 L, int 
       __syncthreads();
     }
     store(0, inv(acc, b0));
-  } else {
-    const int nf = (MODE == P3_APPLY) ? 1 : (MODE == P3_FRAC) ? 2 : 3;
-    for (int f = 0; f < nf; ++f) {
-      load(f, b0);
-      __syncthreads();
-      float2* F = fwd(b0, b1);
-      const int cd = plane_code<MODE>(f, code);
-      for (int i = tid; i < cnt; i += B) F[i] = cmul(F[i], mult(cd, i));
-      __syncthreads();
-      store(f, inv(F, F == b0 ? b1 : b0));
-      __syncthreads();
-    }
   }
 }
 
@@ -684,7 +623,10 @@ static hipError_t plane_t(const Launch3& L, int ntile, int chunk, int code, int 
 }
 
 hipError_t launch_plane3(int mode, int code, const Launch3& L, int ntile, int chunk, int n, hipStream_t st) {
-  const size_t lds = plane3_lds(L.m.ny, L.m.nz, L.m.ct, L.m.wide != 0);
+  // a one-field block ping-pongs between two buffers; the divergence keeps a
+  // third (a sum) or six (all fields at once)
+  const size_t lds = mode == P3_DIVM ? plane3_lds(L.m.ny, L.m.nz, L.m.ct, L.m.wide != 0)
+                                     : plane3_lds_bufs(L.m.ny, L.m.nz, L.m.ct, 2);
   switch (mode) {
     case P3_GRADP1: return plane_t<P3_GRADP1>(L, ntile, chunk, code, n, lds, st);
     case P3_GRADM2: return plane_t<P3_GRADM2>(L, ntile, chunk, code, n, lds, st);

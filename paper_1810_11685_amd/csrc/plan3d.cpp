@@ -466,7 +466,6 @@ qpat_status plan3_build(qpat_plan3d P, const double* c0, const double* rho0) {
   M.rthr = 256;
   M.pthr = 512;
   M.wide = plane3_lds(ny, nz, 1, true) <= kMaxLds;
-  M.split = 0;   // chosen per batch size (exec3)
   return QPAT_OK;
 }
 
@@ -516,11 +515,6 @@ qpat_status exec3(qpat_plan3d P, int b, Exec3** out) {
     H3CHK(hipHostMalloc(&E->h_io, sizeof(IO3) * b, hipHostMallocDefault));
     H3CHK(hipEventCreateWithFlags(&E->ev, hipEventDisableTiming));
     E->L.io = E->d_io;
-    // plane passes go one block per field (diagonal passes) or per output
-    // (gradient) while even the split launch fits within the GPU's CUs
-    // (small batches: a 2401-point field fills only a third of a block's
-    // butterfly slots, which costs more than it gains once the CUs are busy)
-    E->L.m.split = 3 * b * P->med.ctiles <= kCus ? 1 : 0;
     const Medium3& M = P->med;
     E->row_ntile = (M.nlines + M.rt - 1) / M.rt;
     E->pl_ntile = M.ctiles;
@@ -545,7 +539,7 @@ hipError_t row3(Exec3& E, int mode, int n, hipStream_t st) {
   return launch_row3(mode, E.L, E.row_ntile, E.row_chunk, n, st);
 }
 hipError_t plane3(Exec3& E, int mode, int n, hipStream_t st, int code = 0) {
-  const int ntile = E.pl_ntile * plane3_split(mode, E.L.m);
+  const int ntile = E.pl_ntile * plane3_split(mode);
   const int chunk = (E.L.nitems * ntile + kXcds - 1) / kXcds;
   return launch_plane3(mode, code, E.L, ntile, chunk, n, st);
 }

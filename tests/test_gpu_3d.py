@@ -194,10 +194,10 @@ def test_wide_and_narrow_plane_blocks_agree_bitwise(q):
     assert rel(d1[0], K3.forward(prm, c0, rho0, p0)) <= TOL
 
 
-def test_split_and_joint_plane_passes_agree_bitwise(q):
-    """Small batches run the plane passes one block per field or output, large
-    ones all fields per block (65 column tiles: one vector splits, four do
-    not): the same bits per vector either way."""
+def test_batched_and_single_launches_agree_bitwise(q):
+    """Four vectors in one launch and four one-vector launches give the same
+    bits per vector (65 column tiles, so the launches differ in block count
+    and in which XCD a tile lands on)."""
     prm, c0, rho0, p0 = problem(128, 8, 8, 10, ns=5, pml=1)
     plan = q.Plan3D(prm, c0, rho0)
     xs = np.stack([p0] + [qi.gaussian_field(p0.shape, 60 + b) for b in range(3)])
