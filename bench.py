@@ -65,11 +65,12 @@ def bytes_3d_pair(nx: int) -> float:
     iterate pair.  A half spectrum holds h = (nx/2 + 1)/nx complex values per
     point (8h bytes).  Forward: plane d_i^+ p 36h, row velocity 36 + 48h,
     plane d_i^- v 52h, row density 28 + 40h, plane Y terms 40h, row pressure
-    24 + 24h; adjoint: row p* 16 + 24h, plane Y terms 40h, row density
-    32 + 40h, plane d_i^+ 52h, row velocity 36 + 48h, plane divergence 36h
-    (fields 4 B, spectra 8h B, k-space tables 4h B per point)."""
+    24 + 24h; adjoint: row p* (reads the three divergence terms) 16 + 40h,
+    plane Y terms 40h, row density 32 + 40h, plane d_i^+ 52h, row velocity
+    36 + 48h, plane divergence terms d_i^- (3 -> 3) 52h (fields 4 B, spectra
+    8h B, k-space tables 4h B per point)."""
     h = (nx // 2 + 1) / nx
-    return 172.0 + 480.0 * h
+    return 172.0 + 512.0 * h
 
 
 def log(*a):

@@ -283,11 +283,18 @@ __global__ void __launch_bounds__(kRowMax) row3_kernel(const Launch3 L, int ntil
   // incoming half spectra -> full spectra of the paired lines (a + i b)
   const int ncol = M.nxh1;
   const float rhp = rcp(hp), rncol = rcp(ncol), rnx = rcp(nx), rny = rcp(ny);
+  // the adjoint divergence arrives as its three terms d_i^- g_i, one per
+  // spectrum, summed here in a fixed order
+  constexpr int NSUM = (MODE == R3_A1 || MODE == R3_A1L) ? 3 : 1;
   for (int t = tid; t < nin * ncol * hp; t += B) {
     const int fc = udiv(t, rhp), j = t - fc * hp, f = udiv(fc, rncol), c = fc - f * ncol;
     const int la = l0 + 2 * j, lb = la + 1;
-    const float2 a = la < nl ? W.s[spec_index(M, f, c, la)] : make_float2(0.f, 0.f);
-    const float2 b = lb < nl ? W.s[spec_index(M, f, c, lb)] : make_float2(0.f, 0.f);
+    float2 a = make_float2(0.f, 0.f), b = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int k = 0; k < NSUM; ++k) {
+      if (la < nl) a = cadd(a, W.s[spec_index(M, f + k, c, la)]);
+      if (lb < nl) b = cadd(b, W.s[spec_index(M, f + k, c, lb)]);
+    }
     float2* Z = bufA + (f * hp + j) * nx;
     Z[c] = make_float2(a.x - b.y, a.y + b.x);
     if (c != 0 && 2 * c != nx) Z[nx - c] = make_float2(a.x + b.y, b.x - a.y);
@@ -470,8 +477,7 @@ __device__ __forceinline__ int plane_code(int f, int code) {
   switch (MODE) {
     case P3_GRADP1:
     case P3_GRADP2: return f == 0 ? OP_DXP : f == 1 ? OP_DYP : OP_DZP;
-    case P3_GRADM2:
-    case P3_DIVM: return f == 0 ? OP_DXM : f == 1 ? OP_DYM : OP_DZM;
+    case P3_GRADM2: return f == 0 ? OP_DXM : f == 1 ? OP_DYM : OP_DZM;
     case P3_FRAC: return f == 0 ? OP_LDIS : OP_LABS;
     default: return code;
   }
@@ -499,7 +505,6 @@ __global__ void __launch_bounds__(kPlaneMax) plane3_kernel(const Launch3 L, int 
   float2* buf = twz + nz;
   float2* b0 = buf;
   float2* b1 = buf + cnt;
-  float2* b2 = buf + 2 * cnt;
   for (int i = tid; i < ny; i += B) twy[i] = M.twy[i];
   for (int i = tid; i < nz; i += B) twz[i] = M.twz[i];
   const size_t specN = size_t(M.ctiles) * ct * nl;
@@ -530,54 +535,15 @@ __global__ void __launch_bounds__(kPlaneMax) plane3_kernel(const Launch3 L, int 
     return c < ncols ? symbol(M, cd, c0 + c, y, z) : make_float2(0.f, 0.f);
   };
 
-  if constexpr (MODE != P3_DIVM) {
-    // one field of a diagonal pass (reads and writes only its own spectrum),
-    // one output of the gradient (reads spectrum 3), or a single operator
-    load(MODE == P3_GRADP1 ? 3 : sub, b0);
-    __syncthreads();
-    float2* F = fwd(b0, b1);
-    const int cd = plane_code<MODE>(sub, code);
-    for (int i = tid; i < cnt; i += B) F[i] = cmul(F[i], mult(cd, i));
-    __syncthreads();
-    store(sub, inv(F, F == b0 ? b1 : b0));
-  } else if (M.wide) {
-    // the three fields transformed at once: more butterflies per stage and a
-    // third of the barriers (six buffers of one chunk in LDS)
-    float2* R0 = buf;
-    float2* R1 = buf + 3 * cnt;
-    auto fwdk = [&](float2* a, float2* b, int k) {
-      const LineMap yk{k * nz * ct, ct, ny * ct, 1, ct};
-      const LineMap zk{k * ny * ct, ny * ct, cnt, 1, ny * ct};
-      float2* r = fft_axis<false>(a, b, yk, M.py, twy);
-      return fft_axis<false>(r, r == a ? b : a, zk, M.pz, twz);
-    };
-    for (int f = 0; f < 3; ++f) load(f, R0 + f * cnt);
-    __syncthreads();
-    float2* F = fwdk(R0, R1, 3);
-    float2* A = (F == R0) ? R1 : R0;
-    for (int i = tid; i < cnt; i += B) {
-      float2 acc = cmul(F[i], mult(plane_code<MODE>(0, code), i));
-      acc = cadd(acc, cmul(F[cnt + i], mult(plane_code<MODE>(1, code), i)));
-      A[i] = cadd(acc, cmul(F[2 * cnt + i], mult(plane_code<MODE>(2, code), i)));
-    }
-    __syncthreads();
-    store(0, inv(A, A + cnt));
-  } else {
-    // one field at a time, the sum kept in a third buffer
-    float2* acc = b2;
-    for (int f = 0; f < 3; ++f) {
-      load(f, b0);
-      __syncthreads();
-      float2* F = fwd(b0, b1);
-      const int cd = plane_code<MODE>(f, code);
-      for (int i = tid; i < cnt; i += B) {
-        const float2 v = cmul(F[i], mult(cd, i));
-        acc[i] = f == 0 ? v : cadd(acc[i], v);
-      }
-      __syncthreads();
-    }
-    store(0, inv(acc, b0));
-  }
+  // one field of a diagonal pass (reads and writes only its own spectrum),
+  // one output of the gradient (reads spectrum 3), or a single operator
+  load(MODE == P3_GRADP1 ? 3 : sub, b0);
+  __syncthreads();
+  float2* F = fwd(b0, b1);
+  const int cd = plane_code<MODE>(sub, code);
+  for (int i = tid; i < cnt; i += B) F[i] = cmul(F[i], mult(cd, i));
+  __syncthreads();
+  store(sub, inv(F, F == b0 ? b1 : b0));
 }
 
 // ---------------------------------------------------------------- sensor data
@@ -623,16 +589,12 @@ static hipError_t plane_t(const Launch3& L, int ntile, int chunk, int code, int 
 }
 
 hipError_t launch_plane3(int mode, int code, const Launch3& L, int ntile, int chunk, int n, hipStream_t st) {
-  // a one-field block ping-pongs between two buffers; the divergence keeps a
-  // third (a sum) or six (all fields at once)
-  const size_t lds = mode == P3_DIVM ? plane3_lds(L.m.ny, L.m.nz, L.m.ct, L.m.wide != 0)
-                                     : plane3_lds_bufs(L.m.ny, L.m.nz, L.m.ct, 2);
+  const size_t lds = plane3_lds(L.m.ny, L.m.nz, L.m.ct);
   switch (mode) {
     case P3_GRADP1: return plane_t<P3_GRADP1>(L, ntile, chunk, code, n, lds, st);
     case P3_GRADM2: return plane_t<P3_GRADM2>(L, ntile, chunk, code, n, lds, st);
     case P3_FRAC: return plane_t<P3_FRAC>(L, ntile, chunk, code, n, lds, st);
     case P3_GRADP2: return plane_t<P3_GRADP2>(L, ntile, chunk, code, n, lds, st);
-    case P3_DIVM: return plane_t<P3_DIVM>(L, ntile, chunk, code, n, lds, st);
     case P3_APPLY: return plane_t<P3_APPLY>(L, ntile, chunk, code, n, lds, st);
     default: return hipErrorInvalidValue;
   }
@@ -660,7 +622,7 @@ hipError_t k3d_allow_lds(size_t bytes) {
                            allow(&row3_kernel<R3_FWD1>, bytes),    allow(&row3_kernel<R3_INV1>, bytes),
                            allow(&plane3_kernel<P3_GRADP1>, bytes), allow(&plane3_kernel<P3_GRADM2>, bytes),
                            allow(&plane3_kernel<P3_FRAC>, bytes),   allow(&plane3_kernel<P3_GRADP2>, bytes),
-                           allow(&plane3_kernel<P3_DIVM>, bytes),   allow(&plane3_kernel<P3_APPLY>, bytes)};
+                           allow(&plane3_kernel<P3_APPLY>, bytes)};
   for (hipError_t e : es)
     if (e != hipSuccess) return e;
   return hipSuccess;

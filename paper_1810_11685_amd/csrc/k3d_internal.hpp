@@ -55,7 +55,6 @@ struct Medium3 {
   float dt;
   int rt, ct, ctiles;                 // lines per row tile, columns per plane tile, column tiles
   int rthr, pthr;                     // threads per row / plane block
-  int wide;                           // plane blocks hold all fields of a pass at once
   AxisPlan px, py, pz;
   const float *c2, *c2eta, *c2tau, *rho0;      // [N]
   const float *bx, *by, *bz;                   // dt / rho0 at the staggered positions [N]
@@ -108,26 +107,21 @@ enum Plane3 : int {
   P3_GRADM2 = 1,  // 3 -> 3: d_i^- of field i
   P3_FRAC = 2,    // 2 -> 2: Y_dis of field 0, Y_abs of field 1
   P3_GRADP2 = 3,  // 3 -> 3: d_i^+ of field i
-  P3_DIVM = 4,    // 3 -> 1: sum_i d_i^- of field i
   P3_APPLY = 5    // 1 -> 1: one operator (code in the launch)
 };
 
 enum OpCode3 : int { OP_DXP = 0, OP_DXM, OP_DYP, OP_DYM, OP_DZP, OP_DZM, OP_LDIS, OP_LABS };
 
 // LDS bytes of a row block (two buffers of 3 x rt/2 lines + twiddles) and of
-// a plane block (twiddles + nbuf buffers of ct columns x nlines: three, six
-// when all fields are transformed together, two for a one-field block).
+// a plane block (twiddles + two buffers of ct columns x nlines: a block
+// transforms one field).
 inline size_t row3_lds(int nx, int rt) { return (size_t(2) * 3 * (rt / 2) * nx + nx) * sizeof(float2); }
-inline size_t plane3_lds_bufs(int ny, int nz, int ct, int nbuf) {
-  return (size_t(nbuf) * ct * ny * nz + ny + nz) * sizeof(float2);
-}
-inline size_t plane3_lds(int ny, int nz, int ct, bool wide) { return plane3_lds_bufs(ny, nz, ct, wide ? 6 : 3); }
+inline size_t plane3_lds(int ny, int nz, int ct) { return (size_t(2) * ct * ny * nz + ny + nz) * sizeof(float2); }
 
 hipError_t launch_row3(int mode, const Launch3& L, int ntile, int chunk, int n, hipStream_t st);
 // blocks per column tile of a plane pass: one per field of the diagonal
-// passes and one per output of the gradient (one-field blocks need a third of
-// the LDS, so several share a CU and hide each other's barrier waits); one for
-// the divergence, which sums its three fields, and for a single operator
+// passes and one per output of the gradient (one-field blocks are small
+// enough in LDS that several share a CU and hide each other's barrier waits)
 __host__ __device__ constexpr int plane3_split(int mode) {
   return (mode == P3_GRADM2 || mode == P3_GRADP2 || mode == P3_GRADP1) ? 3 : mode == P3_FRAC ? 2 : 1;
 }

@@ -97,7 +97,7 @@ bool pow2_in(int v, int lo, int hi) { return v >= lo && v <= hi && (v & (v - 1))
 bool tiles_ok(const qpat_params3d& p, int rt, int ct, int rthr = 256, int pthr = 256) {
   if (rt < 2 || rt > 64 || (rt & 1) || ct < 1 || ct > p.nx / 2 + 1) return false;
   if (!pow2_in(rthr, 64, kRowMax) || !pow2_in(pthr, 64, kPlaneMax)) return false;
-  return row3_lds(p.nx, rt) <= kMaxLds && plane3_lds(p.ny, p.nz, ct, false) <= kMaxLds;
+  return row3_lds(p.nx, rt) <= kMaxLds && plane3_lds(p.ny, p.nz, ct) <= kMaxLds;
 }
 
 qpat_status validate3(const qpat_params3d* p) {
@@ -465,7 +465,6 @@ qpat_status plan3_build(qpat_plan3d P, const double* c0, const double* rho0) {
   M.ctiles = nxh1;
   M.rthr = 256;
   M.pthr = 512;
-  M.wide = plane3_lds(ny, nz, 1, true) <= kMaxLds;
   return QPAT_OK;
 }
 
@@ -576,7 +575,7 @@ hipError_t seq_adjoint3(Exec3& E, hipStream_t st) {
     if (n == -1) break;
     L3CHK(plane3(E, P3_GRADP2, n, st));
     L3CHK(row3(E, R3_A3, n, st));
-    L3CHK(plane3(E, P3_DIVM, n, st));
+    L3CHK(plane3(E, P3_GRADM2, n, st));   // the terms of the divergence, summed by the next row pass
   }
   return hipSuccess;
 }
@@ -717,7 +716,6 @@ qpat_status qpat3d_set_tiles(qpat_plan3d P, int32_t rows, int32_t cols, int32_t 
     M.ctiles = (M.nxh1 + cols - 1) / cols;
     M.rthr = row_threads;
     M.pthr = plane_threads;
-    M.wide = plane3_lds(M.ny, M.nz, cols, true) <= kMaxLds;
     P->execs.clear();
   }
   return QPAT_OK;

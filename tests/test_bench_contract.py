@@ -26,7 +26,11 @@ def test_byte_counts():
     fwd = [bench.PASS_BYTES[i] for i in range(6)]
     adj = [bench.PASS_BYTES[i] for i in range(6, 12)]
     assert sum(fwd) == 160 and sum(adj) == 160
-    # 3-D: 172 + 480 h with h = (nx/2 + 1)/nx; 49^3 gives 416.9 B per point and iterate pair
-    assert bench.bytes_3d_pair(49) == pytest.approx(172 + 480 * 25 / 49)
-    assert bench.bytes_3d_pair(64) == pytest.approx(172 + 480 * 33 / 64)
+    # 3-D: per pass (field bytes, half-spectrum bytes in units of h = (nx/2 + 1)/nx)
+    fwd3 = [(0, 36), (36, 48), (0, 52), (28, 40), (0, 40), (24, 24)]
+    adj3 = [(16, 40), (0, 40), (32, 40), (0, 52), (36, 48), (0, 52)]
+    for nx in (49, 64):
+        h = (nx // 2 + 1) / nx
+        assert bench.bytes_3d_pair(nx) == pytest.approx(sum(a + b * h for a, b in fwd3 + adj3))
+    assert bench.bytes_3d_pair(49) == pytest.approx(433.22, abs=0.01)
     assert bench.OPT_BYTES_PER_NODE_ITER == 48 + 56 + 32

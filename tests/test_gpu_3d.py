@@ -177,11 +177,10 @@ def test_nt_one_and_two_3d(q, nt):
     assert rel(N(plan.adjoint(T(r))), K3.adjoint(prm, c0, rho0, r)) <= TOL
 
 
-def test_wide_and_narrow_plane_blocks_agree_bitwise(q):
-    """A plane block transforms all fields of a pass together when six chunk
-    buffers fit in LDS, else one field at a time: same arithmetic per line, so
-    the same bits (24 x 24 planes: one column per block fits six buffers, six
-    columns do not)."""
+def test_plane_column_tile_width_does_not_change_bits(q):
+    """Plane blocks of one spectrum column and of six: same arithmetic per
+    line, so the same bits (24 x 24 planes; also a different row tile and
+    thread counts)."""
     prm, c0, rho0, p0 = problem(16, 24, 24, 12, ns=6)
     plan = q.Plan3D(prm, c0, rho0)
     x = T(np.stack([p0, qi.gaussian_field(p0.shape, 51)]))
