@@ -456,7 +456,8 @@ def main():
                 del x3, r3
         out["vol33"] = {"workload": "3-D: 33^3 nodes of 0.3125 mm plus an 8-cell PML (49^3 grid), Nt=292, "
                                     "2145 detectors on two faces, lossy (alpha0=0.75, y=1.5), forward + adjoint",
-                        "tiles": list(plan3.tiles()), "bytes_per_point_per_iterate_pair": BYTES_3D_PAIR,
+                        "shape": "automatic per batch size", "tiles_one_vector": list(plan3.tiles()),
+                        "bytes_per_point_per_iterate_pair": BYTES_3D_PAIR,
                         "runs": runs}
         del plan3
         torch.cuda.empty_cache()

@@ -313,8 +313,11 @@ qpat_status qpat3d_apply(qpat_plan3d plan, int32_t op, const float* in, float* o
 /* Launch shape: x-lines per row block (even, >= 2, at most 64), spectrum
  * columns per plane block (>= 1), threads per row block (64..512) and per
  * plane block (64..1024, powers of two); both blocks must fit the 160 KB of
- * LDS.  Results do not depend on the shape.  row_threads / plane_threads may
- * be NULL in qpat3d_get_tiles. */
+ * LDS.  Results do not depend on the shape.  A new plan picks the rows and
+ * both thread counts per batch size (fewer lines and more plane threads for
+ * batches that leave CUs idle); qpat3d_set_tiles fixes all four, and
+ * qpat3d_get_tiles reports the fixed shape, or the automatic one for a single
+ * vector.  row_threads / plane_threads may be NULL in qpat3d_get_tiles. */
 qpat_status qpat3d_set_tiles(qpat_plan3d plan, int32_t rows, int32_t cols, int32_t row_threads,
                              int32_t plane_threads);
 qpat_status qpat3d_get_tiles(qpat_plan3d plan, int32_t* rows, int32_t* cols, int32_t* row_threads,

@@ -238,6 +238,7 @@ struct qpat_plan3d_s {
   std::vector<float*> datas;
   std::map<int, std::unique_ptr<Exec3>> execs;
   bool graph = false;
+  bool auto_shape = true;   // rows and thread counts chosen per batch size until set_tiles
 };
 
 namespace {
@@ -501,12 +502,24 @@ qpat_status reserve3(qpat_plan3d P, int count) {
   return QPAT_OK;
 }
 
+// Launch shape for b vectors on automatic shape: 8-line row blocks while
+// 16-line ones would give fewer than two blocks per CU, and 1024-thread plane
+// blocks while the plane launches give at most one block per CU (more lines
+// and threads per block only lengthen each block's chain of dependent FFT
+// stages then); 16 lines (the plan's rows) and 512 threads otherwise.
+void auto_shape3(const Medium3& base, int b, Medium3& m) {
+  m.rt = size_t(b) * ((base.nlines + base.rt - 1) / base.rt) < size_t(2) * kCus ? std::min(8, base.rt) : base.rt;
+  m.rthr = 256;
+  m.pthr = size_t(3) * b * base.ctiles <= size_t(kCus) ? 1024 : 512;
+}
+
 qpat_status exec3(qpat_plan3d P, int b, Exec3** out) {
   S3CHK(reserve3(P, b));
   auto it = P->execs.find(b);
   if (it == P->execs.end()) {
     std::unique_ptr<Exec3> E(new Exec3());
     E->L.m = P->med;
+    if (P->auto_shape) auto_shape3(P->med, b, E->L.m);
     E->L.w0 = P->w0;
     E->L.wstride = (long long)P->item_bytes;
     E->L.nitems = b;
@@ -514,7 +527,7 @@ qpat_status exec3(qpat_plan3d P, int b, Exec3** out) {
     H3CHK(hipHostMalloc(&E->h_io, sizeof(IO3) * b, hipHostMallocDefault));
     H3CHK(hipEventCreateWithFlags(&E->ev, hipEventDisableTiming));
     E->L.io = E->d_io;
-    const Medium3& M = P->med;
+    const Medium3& M = E->L.m;
     E->row_ntile = (M.nlines + M.rt - 1) / M.rt;
     E->pl_ntile = M.ctiles;
     E->row_chunk = (b * E->row_ntile + kXcds - 1) / kXcds;
@@ -709,13 +722,14 @@ qpat_status qpat3d_set_tiles(qpat_plan3d P, int32_t rows, int32_t cols, int32_t 
     return set_error(QPAT_E_INVALID, "tiles: rows even in [2, 64], cols in [1, nx/2 + 1], both within the LDS; "
                                      "row threads 64..512 and plane threads 64..1024, powers of two");
   Medium3& M = P->med;
-  if (rows != M.rt || cols != M.ct || row_threads != M.rthr || plane_threads != M.pthr) {
+  if (P->auto_shape || rows != M.rt || cols != M.ct || row_threads != M.rthr || plane_threads != M.pthr) {
     H3CHK(hipDeviceSynchronize());
     M.rt = rows;
     M.ct = cols;
     M.ctiles = (M.nxh1 + cols - 1) / cols;
     M.rthr = row_threads;
     M.pthr = plane_threads;
+    P->auto_shape = false;
     P->execs.clear();
   }
   return QPAT_OK;
@@ -724,10 +738,12 @@ qpat_status qpat3d_set_tiles(qpat_plan3d P, int32_t rows, int32_t cols, int32_t 
 qpat_status qpat3d_get_tiles(qpat_plan3d P, int32_t* rows, int32_t* cols, int32_t* row_threads,
                              int32_t* plane_threads) {
   if (!P || !rows || !cols) return set_error(QPAT_E_INVALID, "NULL argument");
-  *rows = P->med.rt;
-  *cols = P->med.ct;
-  if (row_threads) *row_threads = P->med.rthr;
-  if (plane_threads) *plane_threads = P->med.pthr;
+  Medium3 m = P->med;
+  if (P->auto_shape) auto_shape3(P->med, 1, m);
+  *rows = m.rt;
+  *cols = m.ct;
+  if (row_threads) *row_threads = m.rthr;
+  if (plane_threads) *plane_threads = m.pthr;
   return QPAT_OK;
 }
 

@@ -131,8 +131,13 @@ def test_vol37_generation_grid_prime_axes(q):
 
 
 def test_batch_tiles_graph_bitwise_3d(q):
+    """Batched and single calls, the automatic shape (chosen per batch size)
+    and fixed shapes, and graph replays all give the same bits."""
     prm, c0, rho0, p0 = problem(18, 14, 12, 20)
     plan = q.Plan3D(prm, c0, rho0)
+    # automatic shape for one vector: 168 lines in 11 blocks of 16 leave CUs
+    # idle (8 lines), 3 x 10 plane blocks fit one per CU (1024 threads)
+    assert plan.tiles() == (8, 1, 256, 1024)
     xs = np.stack([p0, qi.gaussian_field(p0.shape, 21), qi.gaussian_field(p0.shape, 22)])
     base = N(plan.forward(T(xs)))
     for b in range(3):
@@ -141,6 +146,7 @@ def test_batch_tiles_graph_bitwise_3d(q):
     gbase = N(plan.adjoint(T(r)))
     for tiles in [(2, 1, 64, 64), (8, 3, 512, 1024), (14, 10, 256, 512), (64, 2, 128, 256)]:
         plan.set_tiles(*tiles)
+        assert plan.tiles() == tiles
         assert np.array_equal(N(plan.forward(T(xs))), base), tiles
         assert np.array_equal(N(plan.adjoint(T(r))), gbase), tiles
     import torch
