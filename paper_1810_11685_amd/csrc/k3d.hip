@@ -116,38 +116,46 @@ __device__ __forceinline__ void dft(float2* v) {
 struct LineMap {
   int nlines, lpg, gs, ls, es;
 };
-__device__ __forceinline__ int line_off(const LineMap m, int L, float rlpg) {
-  const int g = udiv(L, rlpg);
-  return g * m.gs + (L - g * m.lpg) * m.ls;
+__device__ __forceinline__ unsigned line_off(const LineMap m, unsigned L, float rlpg) {
+  const unsigned g = unsigned(udiv(int(L), rlpg));
+  return __umul24(g, unsigned(m.gs)) + __umul24(L - __umul24(g, unsigned(m.lpg)), unsigned(m.ls));
 }
 
 // One Stockham stage of radix R over every line: butterfly j (of n/R) reads
 // src[j + r n/R], twiddles input r by w^(r k n/(Ns R)) with k = j mod Ns, and
-// writes dst[(j - k) R + k + r Ns].
+// writes dst[(j - k) R + k + r Ns].  Every index is below 2^24, so products
+// take the 24-bit multiplier, and the strides between a butterfly's inputs
+// and outputs are block-uniform.
 template <int R, bool INV>
 __device__ void stage_small(const float2* __restrict__ src, float2* __restrict__ dst, const LineMap m, int n,
                             int Ns, const float2* __restrict__ tw) {
-  const int nb = n / R, tstep = n / (Ns * R), total = m.nlines * nb;
+  const unsigned nb = unsigned(n / R), ns = unsigned(Ns), tstep = unsigned(n / (Ns * R));
+  const unsigned total = unsigned(m.nlines) * nb, es = unsigned(m.es);
+  const unsigned istep = nb * es, ostep = ns * es;
   const float rnb = rcp(nb), rns = rcp(Ns), rlpg = rcp(m.lpg);
-  for (int t = threadIdx.x; t < total; t += blockDim.x) {
-    const int L = udiv(t, rnb), j = t - L * nb;
-    const int off = line_off(m, L, rlpg);
-    const int k = j - udiv(j, rns) * Ns;
+  for (unsigned t = threadIdx.x; t < total; t += blockDim.x) {
+    const unsigned L = unsigned(udiv(int(t), rnb)), j = t - __umul24(L, nb);
+    const unsigned off = line_off(m, L, rlpg);
+    const unsigned k = j - __umul24(unsigned(udiv(int(j), rns)), ns);
+    const float2* s = src + (off + __umul24(j, es));
     float2 v[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[r] = src[off + (j + r * nb) * m.es];
+    for (int r = 0; r < R; ++r) v[r] = s[r * istep];
     if (Ns > 1) {  // the first stage's twiddles are all 1 (block-uniform test)
+      const unsigned kt = __umul24(k, tstep);
+      unsigned e = 0;
 #pragma unroll
       for (int r = 1; r < R; ++r) {
-        float2 w = tw[r * k * tstep];
+        e += kt;   // r k tstep
+        float2 w = tw[e];
         if (INV) w.y = -w.y;
         v[r] = cmul(v[r], w);
       }
     }
     dft<R, INV>(v);
-    const int base = (j - k) * R + k;
+    float2* d = dst + (off + __umul24(__umul24(j - k, unsigned(R)) + k, es));
 #pragma unroll
-    for (int r = 0; r < R; ++r) dst[off + (base + r * Ns) * m.es] = v[r];
+    for (int r = 0; r < R; ++r) d[r * ostep] = v[r];
   }
 }
 
@@ -157,25 +165,27 @@ template <bool INV>
 __device__ void stage_generic(const float2* __restrict__ src, float2* __restrict__ dst, const LineMap m, int n,
                               int Ns, int R, const float2* __restrict__ tw) {
   const int nb = n / R, tstep = n / (Ns * R), total = m.nlines * n;
+  const unsigned es = unsigned(m.es), istep = unsigned(nb) * es;
   const float rn = rcp(n), rnsr = rcp(Ns * R), rns = rcp(Ns), rlpg = rcp(m.lpg);
   for (int t = threadIdx.x; t < total; t += blockDim.x) {
     const int L = udiv(t, rn), o = t - L * n;
-    const int off = line_off(m, L, rlpg);
+    const unsigned off = line_off(m, unsigned(L), rlpg);
     const int g = udiv(o, rnsr), rem = o - g * Ns * R, q = udiv(rem, rns), k = rem - q * Ns;
     const int j = g * Ns + k;
     const int e = k * tstep + q * nb;   // < n
+    const float2* s = src + (off + __umul24(unsigned(j), es));
     float2 acc = make_float2(0.f, 0.f);
     int idx = 0;
     for (int r = 0; r < R; ++r) {
       float2 w = tw[idx];
       if (INV) w.y = -w.y;
-      const float2 x = src[off + (j + r * nb) * m.es];
+      const float2 x = s[unsigned(r) * istep];
       acc.x += x.x * w.x - x.y * w.y;
       acc.y += x.x * w.y + x.y * w.x;
       idx += e;
       if (idx >= n) idx -= n;
     }
-    dst[off + o * m.es] = acc;
+    dst[off + __umul24(unsigned(o), es)] = acc;
   }
 }
 
