@@ -250,10 +250,12 @@ qpat_status qpat_tv_set_weights(qpat_tv tv, const float* x, double beta, int32_t
 qpat_status qpat_tv_apply(qpat_tv tv, double gamma, const float* x, float* y, int32_t batch,
                           qpat_stream stream);
 /* z = M_gamma^-1 r (gamma > 0), the preconditioner solve of Algorithm 4, per
- * field: conjugate gradients in FP64 preconditioned by the diagonal of
- * M_gamma, until ||r - M_gamma z|| <= tol ||r|| (0 < tol < 1) or max_iter
+ * field: conjugate gradients in FP64, each iteration preconditioned by one
+ * multigrid V-cycle (2 x 2 aggregation down to a single node, Galerkin coarse
+ * operators, one damped Jacobi sweep before and after each coarse
+ * correction), until ||r - M_gamma z|| <= tol ||r|| (0 < tol < 1) or max_iter
  * iterations; *iters (may be NULL) receives the iterations run.  Synchronises
- * the stream (the convergence test reads residual norms every 32 iterations). */
+ * the stream (the convergence test reads residual norms every 8 iterations). */
 qpat_status qpat_tv_solve(qpat_tv tv, double gamma, const float* r, float* z, int32_t batch, double tol,
                           int32_t max_iter, int32_t* iters, qpat_stream stream);
 /* Smoothed TV value sum_l sqrt((D x)_l^2 + beta) per field into out[batch]

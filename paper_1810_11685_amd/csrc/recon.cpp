@@ -26,7 +26,7 @@ namespace {
                        std::string(#expr) + ": " + hipGetErrorString(e_));                      \
   } while (0)
 
-constexpr int kCheckEvery = 32;  // CG iterations between host convergence checks
+constexpr int kCheckEvery = 8;  // CG iterations between host convergence checks
 
 }  // namespace
 
@@ -34,6 +34,7 @@ struct qpat_tv_s {
   int nx = 0, ny = 0, cap = 0;
   void* mem = nullptr;
   TvCg c{};
+  std::vector<MgLevel> lv;   // multigrid levels, finest first
   bool weights = false;
   std::vector<double> h_rr, h_bb, h_part;
   ~qpat_tv_s() {
@@ -55,7 +56,17 @@ qpat_status qpat_tv_create(int32_t nx, int32_t ny, int32_t batch, qpat_tv* out) 
   t->cap = batch;
   const size_t n = size_t(nx) * ny * batch;
   const size_t parts = size_t(batch) * kRedBlocks;
-  const size_t words = 8 * n + 3 * parts + 2 * size_t(batch) + 3 * size_t(batch);
+  // multigrid levels: 2 x 2 aggregates down to a single node
+  std::vector<std::pair<int, int>> dims{{nx, ny}};
+  while (int64_t(dims.back().first) * dims.back().second > 1)
+    dims.push_back({(dims.back().first + 1) / 2, (dims.back().second + 1) / 2});
+  if (int(dims.size()) > kMgMaxLevels) {
+    delete t;
+    return set_error(QPAT_E_UNSUPPORTED, "grid needs too many multigrid levels");
+  }
+  size_t coarse = 0;
+  for (size_t l = 1; l < dims.size(); ++l) coarse += size_t(dims[l].first) * dims[l].second * batch;
+  const size_t words = 8 * n + 3 * parts + 2 * size_t(batch) + 3 * size_t(batch) + 2 * n + 7 * coarse;
   hipError_t e = hipMalloc(&t->mem, words * sizeof(double));
   if (e != hipSuccess) {
     delete t;
@@ -83,6 +94,20 @@ qpat_status qpat_tv_create(int32_t nx, int32_t ny, int32_t batch, qpat_tv* out) 
   t->c.rr = take(batch);
   t->c.rr_next = take(batch);
   t->c.bb = take(batch);
+  // level 0 works on the CG vectors: b = r, result t = z
+  t->lv.push_back(MgLevel{nx, ny, t->c.wh, t->c.wv, take(n), t->c.dinv, t->c.r, take(n), t->c.z});
+  for (size_t l = 1; l < dims.size(); ++l) {
+    const size_t m = size_t(dims[l].first) * dims[l].second * batch;
+    MgLevel L{dims[l].first, dims[l].second, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    L.wh = take(m);
+    L.wv = take(m);
+    L.g = take(m);
+    L.dinv = take(m);
+    L.b = take(m);
+    L.x = take(m);
+    L.t = take(m);
+    t->lv.push_back(L);
+  }
   t->h_rr.resize(batch);
   t->h_bb.resize(batch);
   t->h_part.resize(parts);
@@ -133,12 +158,14 @@ qpat_status qpat_tv_solve(qpat_tv tv, double gamma, const float* r, float* z, in
   if (max_iter < 1) return set_error(QPAT_E_INVALID, "max_iter must be >= 1");
   hipStream_t st = (hipStream_t)stream;
   const double tol2 = tol * tol;
-  TVCHK(launch_cg_start(r, tv->c, tv->nx, tv->ny, batch, gamma, st));
+  const int nlev = int(tv->lv.size());
+  TVCHK(launch_mg_setup(tv->lv.data(), nlev, batch, gamma, st));
+  TVCHK(launch_cg_start(r, tv->c, tv->lv.data(), nlev, tv->nx, tv->ny, batch, st));
   int it = 0;
   while (it < max_iter) {
     const int chunk = std::min(kCheckEvery, max_iter - it);
     for (int k = 0; k < chunk; ++k, ++it)
-      TVCHK(launch_cg_iteration(tv->c, tv->nx, tv->ny, batch, gamma, it & 1, tol2, st));
+      TVCHK(launch_cg_iteration(tv->c, tv->lv.data(), nlev, tv->nx, tv->ny, batch, gamma, it & 1, tol2, st));
     // the pending r.r of the last iteration is published by the next cg_q or by the finish
     TVCHK(hipMemcpyAsync(tv->h_rr.data(), tv->c.rr_next, sizeof(double) * batch, hipMemcpyDeviceToHost, st));
     TVCHK(hipMemcpyAsync(tv->h_bb.data(), tv->c.bb, sizeof(double) * batch, hipMemcpyDeviceToHost, st));

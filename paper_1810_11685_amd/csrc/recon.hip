@@ -7,12 +7,18 @@
 // beta)^(-1/2)); M_gamma = D^T C D + gamma I.  Edge weights are stored per
 // node: wh[j][i] for the edge (j, i)-(j, i+1), wv[j][i] for (j, i)-(j+1, i)
 // (zero past the last column / row).  M_gamma z = r is solved by conjugate
-// gradients in FP64 with the diagonal of M_gamma as preconditioner; the
-// scalars of every field stay in device memory, and each iteration is three
-// launches whose reductions are deterministic (fixed block partition, fixed
-// order; every block re-reduces the block partials itself).
+// gradients in FP64, preconditioned by one multigrid V-cycle: 2 x 2
+// aggregation with piecewise-constant prolongation P, whose Galerkin coarse
+// operators P^T A P keep the same five-point form (a coarse edge weighs the
+// sum of the fine edges between its two aggregates, the diagonal term sums
+// over the aggregate), and one damped Jacobi sweep before and after each
+// coarse correction, which keeps the preconditioner symmetric.  The scalars of
+// every field stay in device memory; the reductions are deterministic (fixed
+// block partition, fixed order; every block re-reduces the block partials
+// itself).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "recon_internal.hpp"
@@ -121,34 +127,126 @@ tv_value_kernel(const float* __restrict__ x, int nx, int ny, double beta, double
   if (threadIdx.x == 0) part[size_t(b) * kRedBlocks + blockIdx.x] = s;
 }
 
+// ---- multigrid V-cycle (levels as in MgLevel)
+// y = (A u)_k at node (j, i) of a level: diagonal term plus edge differences
+template <typename U>
+__device__ __forceinline__ double level_op(const MgLevel& L, size_t base, int k, int i, int j, U u) {
+  const double uc = u(k, i, j);
+  double y = L.g[base + k] * uc;
+  if (i + 1 < L.nx) y += L.wh[base + k] * (uc - u(k + 1, i + 1, j));
+  if (i > 0) y += L.wh[base + k - 1] * (uc - u(k - 1, i - 1, j));
+  if (j + 1 < L.ny) y += L.wv[base + k] * (uc - u(k + L.nx, i, j + 1));
+  if (j > 0) y += L.wv[base + k - L.nx] * (uc - u(k - L.nx, i, j - 1));
+  return y;
+}
+
+__global__ void __launch_bounds__(kRedThreads) mg_fill_kernel(double* __restrict__ a, size_t n, double v) {
+  for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < n; k += size_t(gridDim.x) * blockDim.x) a[k] = v;
+}
+
+// coarse level operator from the finer one (one thread per coarse node)
+__global__ void __launch_bounds__(kRedThreads) mg_coarsen_kernel(MgLevel f, MgLevel c) {
+  const int b = blockIdx.y, nc = c.nx * c.ny;
+  const size_t bf = size_t(b) * f.nx * f.ny, bc = size_t(b) * nc;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nc; k += gridDim.x * blockDim.x) {
+    const int J = k / c.nx, I = k - J * c.nx, j0 = 2 * J, i0 = 2 * I;
+    double g = 0.0, h = 0.0, v = 0.0;
+    for (int j = j0; j < j0 + 2 && j < f.ny; ++j) {
+      for (int i = i0; i < i0 + 2 && i < f.nx; ++i) g += f.g[bf + size_t(j) * f.nx + i];
+      if (I + 1 < c.nx) h += f.wh[bf + size_t(j) * f.nx + i0 + 1];   // edge (j, i0+1)-(j, i0+2)
+    }
+    if (J + 1 < c.ny)
+      for (int i = i0; i < i0 + 2 && i < f.nx; ++i) v += f.wv[bf + size_t(j0 + 1) * f.nx + i];
+    c.g[bc + k] = g;
+    c.wh[bc + k] = h;
+    c.wv[bc + k] = v;
+  }
+}
+
+__global__ void __launch_bounds__(kRedThreads) mg_diag_kernel(MgLevel L) {
+  const int b = blockIdx.y, n = L.nx * L.ny;
+  const size_t base = size_t(b) * n;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+    const int j = k / L.nx, i = k - j * L.nx;
+    double d = L.g[base + k];
+    if (i + 1 < L.nx) d += L.wh[base + k];
+    if (i > 0) d += L.wh[base + k - 1];
+    if (j + 1 < L.ny) d += L.wv[base + k];
+    if (j > 0) d += L.wv[base + k - L.nx];
+    L.dinv[base + k] = 1.0 / d;
+  }
+}
+
+// first sweep from x = 0: x = om dinv b
+__global__ void __launch_bounds__(kRedThreads) mg_scale_kernel(MgLevel L, double om) {
+  const int b = blockIdx.y, n = L.nx * L.ny;
+  const size_t base = size_t(b) * n;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x)
+    L.x[base + k] = om * L.dinv[base + k] * L.b[base + k];
+}
+
+// coarse right-hand side: the aggregate sums of the residual b - A x
+__global__ void __launch_bounds__(kRedThreads) mg_restrict_kernel(MgLevel f, MgLevel c) {
+  const int b = blockIdx.y, nc = c.nx * c.ny;
+  const size_t bf = size_t(b) * f.nx * f.ny, bc = size_t(b) * nc;
+  auto xf = [&](int kk, int, int) { return f.x[bf + kk]; };
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nc; k += gridDim.x * blockDim.x) {
+    const int J = k / c.nx, I = k - J * c.nx;
+    double acc = 0.0;
+    for (int j = 2 * J; j < 2 * J + 2 && j < f.ny; ++j)
+      for (int i = 2 * I; i < 2 * I + 2 && i < f.nx; ++i) {
+        const int kf = j * f.nx + i;
+        acc += f.b[bf + kf] - level_op(f, bf, kf, i, j, xf);
+      }
+    c.b[bc + k] = acc;
+  }
+}
+
+// coarse correction and post-smoothing: with x' = x + P xc,
+// t = x' + om dinv (b - A x')
+__global__ void __launch_bounds__(kRedThreads) mg_post_kernel(MgLevel f, const double* __restrict__ xc, int nxc,
+                                                               int nyc, double om) {
+  const int b = blockIdx.y, n = f.nx * f.ny;
+  const size_t bf = size_t(b) * n, bc = size_t(b) * nxc * nyc;
+  auto xp = [&](int kk, int ii, int jj) { return f.x[bf + kk] + xc[bc + size_t(jj >> 1) * nxc + (ii >> 1)]; };
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+    const int j = k / f.nx, i = k - j * f.nx;
+    const double y = level_op(f, bf, k, i, j, xp);
+    f.t[bf + k] = xp(k, i, j) + om * f.dinv[bf + k] * (f.b[bf + k] - y);
+  }
+}
+
 // ---- conjugate gradients for M_gamma z = r, per field (FP64)
-// start: x = 0, r = rhs, dinv = 1 / diag(M_gamma), z = dinv r, p = z; partials of r.z and r.r
+// start: x = 0, r = rhs; partials of r.r (z and r.z follow the V-cycle)
 __global__ void __launch_bounds__(kRedThreads)
-cg_start_kernel(const float* __restrict__ rhs, TvCg c, int nx, int ny, double gamma) {
+cg_start_kernel(const float* __restrict__ rhs, TvCg c, int nx, int ny) {
   __shared__ double red[kRedThreads / 64];
   const int b = blockIdx.y;
   const size_t n = size_t(nx) * ny, base = size_t(b) * n;
-  double rz = 0.0, rr = 0.0;
+  double rr = 0.0;
   for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < n; k += size_t(gridDim.x) * blockDim.x) {
-    const int j = int(k / nx), i = int(k - size_t(j) * nx);
-    double d = gamma;
-    if (i + 1 < nx) d += c.wh[base + k];
-    if (i > 0) d += c.wh[base + k - 1];
-    if (j + 1 < ny) d += c.wv[base + k];
-    if (j > 0) d += c.wv[base + k - nx];
-    const double di = 1.0 / d, r = rhs[base + k], z = di * r;
-    c.dinv[base + k] = di;
+    const double r = rhs[base + k];
     c.x[base + k] = 0.0;
     c.r[base + k] = r;
-    c.p[base + k] = z;
-    rz += r * z;
     rr += r * r;
   }
-  const double s1 = block_sum(rz, red), s2 = block_sum(rr, red);
-  if (threadIdx.x == 0) {
-    c.part_rz[size_t(b) * kRedBlocks + blockIdx.x] = s1;
-    c.part_rr[size_t(b) * kRedBlocks + blockIdx.x] = s2;
+  const double s = block_sum(rr, red);
+  if (threadIdx.x == 0) c.part_rr[size_t(b) * kRedBlocks + blockIdx.x] = s;
+}
+
+// partials of r.z for the z the V-cycle left; at the start also p = z
+__global__ void __launch_bounds__(kRedThreads) cg_rz_kernel(TvCg c, int nx, int ny, int set_p) {
+  __shared__ double red[kRedThreads / 64];
+  const int b = blockIdx.y;
+  const size_t n = size_t(nx) * ny, base = size_t(b) * n;
+  double rz = 0.0;
+  for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < n; k += size_t(gridDim.x) * blockDim.x) {
+    const double z = c.z[base + k];
+    rz += c.r[base + k] * z;
+    if (set_p) c.p[base + k] = z;
   }
+  const double s = block_sum(rz, red);
+  if (threadIdx.x == 0) c.part_rz[size_t(b) * kRedBlocks + blockIdx.x] = s;
 }
 
 // totals of the start partials: rz[0][b], rr[b], bb[b] = r.r of the right-hand side
@@ -185,8 +283,8 @@ __global__ void __launch_bounds__(kRedThreads) cg_q_kernel(TvCg c, int nx, int n
 }
 
 // alpha = r.z / p.q (0 once the field has converged: r.r <= tol^2 b.b);
-// x += alpha p; r -= alpha q; z = dinv r; partials of the new r.z and r.r.
-// rz[par] holds the current r.z, the new one goes to rz[1 - par] (cg_dir).
+// x += alpha p; r -= alpha q; partials of the new r.r.  rz[par] holds the
+// current r.z, the new one goes to rz[1 - par] (cg_dir).
 __global__ void __launch_bounds__(kRedThreads)
 cg_update_kernel(TvCg c, int nx, int ny, int par, double tol2) {
   __shared__ double red[kRedThreads / 64];
@@ -196,21 +294,15 @@ cg_update_kernel(TvCg c, int nx, int ny, int par, double tol2) {
   const double rz = c.rz[size_t(par) * nb + b];
   const bool live = c.rr[b] > tol2 * c.bb[b] && pq > 0.0;
   const double alpha = live ? rz / pq : 0.0;
-  double rzn = 0.0, rr = 0.0;
+  double rr = 0.0;
   for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < n; k += size_t(gridDim.x) * blockDim.x) {
     c.x[base + k] += alpha * c.p[base + k];
     const double r = c.r[base + k] - alpha * c.q[base + k];
     c.r[base + k] = r;
-    const double z = c.dinv[base + k] * r;
-    c.z[base + k] = z;
-    rzn += r * z;
     rr += r * r;
   }
-  const double s1 = block_sum(rzn, red), s2 = block_sum(rr, red);
-  if (threadIdx.x == 0) {
-    c.part_rz[size_t(b) * kRedBlocks + blockIdx.x] = s1;
-    c.part_rr[size_t(b) * kRedBlocks + blockIdx.x] = s2;
-  }
+  const double s2 = block_sum(rr, red);
+  if (threadIdx.x == 0) c.part_rr[size_t(b) * kRedBlocks + blockIdx.x] = s2;
 }
 
 // beta = r.z(new) / r.z(old); p = z + beta p; block 0 stores the new r.z and r.r.
@@ -269,23 +361,60 @@ hipError_t launch_tv_value(const float* x, int nx, int ny, int batch, double bet
   return hipGetLastError();
 }
 
-hipError_t launch_cg_start(const float* rhs, const TvCg& c, int nx, int ny, int batch, double gamma,
+namespace {
+
+// blocks per field for a level of n nodes (grid-stride loops cover the rest)
+dim3 level_grid(const MgLevel& L, int batch) {
+  const int n = L.nx * L.ny;
+  return dim3(unsigned(std::min(kRedBlocks, (n + kRedThreads - 1) / kRedThreads)), unsigned(batch));
+}
+
+// z = V-cycle applied to level 0's b; the result lands in level 0's t
+hipError_t launch_vcycle(const MgLevel* lv, int nlev, int batch, hipStream_t st) {
+  for (int l = 0; l + 1 < nlev; ++l) {
+    hipLaunchKernelGGL(mg_scale_kernel, level_grid(lv[l], batch), dim3(kRedThreads), 0, st, lv[l], kMgOmega);
+    hipLaunchKernelGGL(mg_restrict_kernel, level_grid(lv[l + 1], batch), dim3(kRedThreads), 0, st, lv[l], lv[l + 1]);
+  }
+  // coarsest level: one node per field, solved exactly (x = b / diag)
+  hipLaunchKernelGGL(mg_scale_kernel, level_grid(lv[nlev - 1], batch), dim3(kRedThreads), 0, st, lv[nlev - 1], 1.0);
+  for (int l = nlev - 2; l >= 0; --l) {
+    const double* xc = (l + 1 == nlev - 1) ? lv[l + 1].x : lv[l + 1].t;
+    hipLaunchKernelGGL(mg_post_kernel, level_grid(lv[l], batch), dim3(kRedThreads), 0, st, lv[l], xc, lv[l + 1].nx,
+                       lv[l + 1].ny, kMgOmega);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_mg_setup(const MgLevel* lv, int nlev, int batch, double gamma, hipStream_t st) {
+  const size_t n0 = size_t(lv[0].nx) * lv[0].ny * batch;
+  hipLaunchKernelGGL(mg_fill_kernel, dim3(unsigned(std::min<size_t>(4096, (n0 + kRedThreads - 1) / kRedThreads))),
+                     dim3(kRedThreads), 0, st, lv[0].g, n0, gamma);
+  for (int l = 0; l + 1 < nlev; ++l)
+    hipLaunchKernelGGL(mg_coarsen_kernel, level_grid(lv[l + 1], batch), dim3(kRedThreads), 0, st, lv[l], lv[l + 1]);
+  for (int l = 0; l < nlev; ++l)
+    hipLaunchKernelGGL(mg_diag_kernel, level_grid(lv[l], batch), dim3(kRedThreads), 0, st, lv[l]);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_start(const float* rhs, const TvCg& c, const MgLevel* lv, int nlev, int nx, int ny, int batch,
                            hipStream_t st) {
-  hipLaunchKernelGGL(cg_start_kernel, dim3(kRedBlocks, batch), dim3(kRedThreads), 0, st, rhs, c, nx, ny, gamma);
-  hipError_t e = hipGetLastError();
+  hipLaunchKernelGGL(cg_start_kernel, dim3(kRedBlocks, batch), dim3(kRedThreads), 0, st, rhs, c, nx, ny);
+  hipError_t e = launch_vcycle(lv, nlev, batch, st);
   if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(cg_rz_kernel, dim3(kRedBlocks, batch), dim3(kRedThreads), 0, st, c, nx, ny, 1);
   hipLaunchKernelGGL(cg_start_total_kernel, dim3(batch), dim3(kRedThreads), 0, st, c);
   return hipGetLastError();
 }
 
-hipError_t launch_cg_iteration(const TvCg& c, int nx, int ny, int batch, double gamma, int par, double tol2,
-                               hipStream_t st) {
+hipError_t launch_cg_iteration(const TvCg& c, const MgLevel* lv, int nlev, int nx, int ny, int batch, double gamma,
+                               int par, double tol2, hipStream_t st) {
   hipLaunchKernelGGL(cg_q_kernel, dim3(kRedBlocks, batch), dim3(kRedThreads), 0, st, c, nx, ny, gamma);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(cg_update_kernel, dim3(kRedBlocks, batch), dim3(kRedThreads), 0, st, c, nx, ny, par, tol2);
-  e = hipGetLastError();
+  hipError_t e = launch_vcycle(lv, nlev, batch, st);
   if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(cg_rz_kernel, dim3(kRedBlocks, batch), dim3(kRedThreads), 0, st, c, nx, ny, 0);
   hipLaunchKernelGGL(cg_dir_kernel, dim3(kRedBlocks, batch), dim3(kRedThreads), 0, st, c, nx, ny, par, tol2);
   return hipGetLastError();
 }

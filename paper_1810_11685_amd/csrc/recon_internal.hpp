@@ -22,15 +22,29 @@ struct TvCg {
   double *rr, *rr_next, *bb;         // r.r (published / pending), r.r of the right-hand side [batch]
 };
 
+// One level of the multigrid preconditioner of the CG solve, [batch][ny][nx]
+// fields.  Level 0 is the grid itself (b is the CG residual, t receives the
+// preconditioned residual); level l + 1 aggregates 2 x 2 blocks of level l.
+struct MgLevel {
+  int nx, ny;
+  double *wh, *wv, *g, *dinv;  // operator: edge weights, diagonal (gamma) term, inverse diagonal
+  double *b, *x, *t;           // right-hand side, pre-smoothed iterate, post-smoothed iterate
+};
+constexpr int kMgMaxLevels = 32;
+constexpr double kMgOmega = 0.8;  // damping of the Jacobi sweeps
+
 hipError_t launch_tv_weights(const float* x, int nx, int ny, int batch, double beta, double* wh, double* wv,
                              hipStream_t st);
 hipError_t launch_tv_apply(const float* x, float* y, const double* wh, const double* wv, int nx, int ny, int batch,
                            double gamma, hipStream_t st);
 hipError_t launch_tv_value(const float* x, int nx, int ny, int batch, double beta, double* part, hipStream_t st);
-hipError_t launch_cg_start(const float* rhs, const TvCg& c, int nx, int ny, int batch, double gamma,
+// Operators of every level for this gamma (level 0's edge weights are the TV
+// weights; its inverse diagonal goes to c.dinv).
+hipError_t launch_mg_setup(const MgLevel* lv, int nlev, int batch, double gamma, hipStream_t st);
+hipError_t launch_cg_start(const float* rhs, const TvCg& c, const MgLevel* lv, int nlev, int nx, int ny, int batch,
                            hipStream_t st);
-hipError_t launch_cg_iteration(const TvCg& c, int nx, int ny, int batch, double gamma, int par, double tol2,
-                               hipStream_t st);
+hipError_t launch_cg_iteration(const TvCg& c, const MgLevel* lv, int nlev, int nx, int ny, int batch, double gamma,
+                               int par, double tol2, hipStream_t st);
 hipError_t launch_cg_finish(const TvCg& c, float* out, int nx, int ny, int batch, hipStream_t st);
 hipError_t launch_axpby(int64_t n, float a, const float* x, float b, float* y, hipStream_t st);
 

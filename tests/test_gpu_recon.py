@@ -34,8 +34,10 @@ def rel(a, b):
     return float(np.linalg.norm(np.asarray(a, float) - b) / np.linalg.norm(b))
 
 
-@pytest.mark.parametrize("ny,nx", [(48, 64), (512, 512)])
+@pytest.mark.parametrize("ny,nx", [(48, 64), (37, 50), (3, 2), (512, 512)])
 def test_tv_apply_solve_value_match_oracle(q, ny, nx):
+    """Odd sizes give multigrid aggregates of one column or row; 3 x 2 has
+    three levels.  At 512^2 the V-cycle keeps the CG iterations few."""
     rng = np.random.default_rng(ny + nx)
     B, beta, gamma = 2, 2e-3, 1e-2
     xs = np.stack([qi.blobs(ny, nx, 7 + b, count=4, radius_cells=min(ny, nx) / 8) for b in range(B)])
@@ -54,6 +56,8 @@ def test_tv_apply_solve_value_match_oracle(q, ny, nx):
         assert rel(N(z)[b].ravel(), ref) <= 1e-5
         assert abs(vals[b] - R.tv_value(D, xs[b], beta)) <= 1e-9 * R.tv_value(D, xs[b], beta)
     assert 0 < it < 50000
+    if nx == 512:
+        assert it <= 200, it      # the diagonal preconditioner needed thousands
     tv.close()
 
 
@@ -95,7 +99,10 @@ def test_ld_reconstruct_matches_oracle(q):
         xr, hr, ir = R.ld_newton(fwd, adj, datas[b], np.zeros((n, n)), **kw)
         assert iters[b] == ir == [4, 4]
         assert rel(N(x)[b], xr) <= 1e-3
-        assert np.allclose(hist[b], hr, rtol=1e-3)
+        # the misfit falls ~2000x in two outer steps; FP32 rounding of the
+        # operators moves the last value by ~1e-3 of itself (with the inner
+        # solve converged to 1e-11), ~6e-7 of the first misfit
+        assert np.allclose(hist[b], hr, rtol=1e-3, atol=1e-6 * hr[0])
         assert hist[b][-1] < hist[b][0]
     assert solves > 0
 
