@@ -28,7 +28,8 @@ namespace {
                        std::string(#expr) + ": " + hipGetErrorString(e_));                      \
   } while (0)
 
-constexpr int kCheckEvery = 32;
+constexpr int kCheckEvery = 32;   // CG iterations between host convergence checks
+static_assert(kCheckEvery % 2 == 0, "full chunks must start at an even iteration");
 
 }  // namespace
 
@@ -38,7 +39,21 @@ struct qpat_optical_s {
   OptCg c{};
   bool solved = false;
   std::vector<double> h_rr, h_bb;
+  // hipGraph of one chunk of kCheckEvery CG iterations (chunks start at an
+  // even iteration, so every full chunk launches the same kernels) for the
+  // batch and tolerance it was captured with; the buffers never move
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  int g_batch = 0;
+  double g_tol2 = 0.0;
+  void drop_graph() {
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    graph_exec = nullptr;
+    graph = nullptr;
+  }
   ~qpat_optical_s() {
+    drop_graph();
     if (mem) (void)hipFree(mem);
   }
 };
@@ -53,6 +68,41 @@ qpat_status check(qpat_optical o, int batch) {
 
 bool opt_ok(double tol, int max_iter) { return std::isfinite(tol) && tol > 0.0 && tol < 1.0 && max_iter >= 1; }
 
+// One full chunk of CG iterations: replayed from a captured graph on a
+// non-default stream (a chunk of small launches is bound by their issue
+// rate), launched one by one on the default stream, which cannot be captured.
+hipError_t cg_chunk(qpat_optical o, const OptCg& c, double tol2, hipStream_t st) {
+  if (st == nullptr) {
+    for (int k = 0; k < kCheckEvery; ++k) {
+      const hipError_t e = opt_launch_cg_iteration(c, k & 1, tol2, st);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+  if (!o->graph_exec || o->g_batch != c.batch || o->g_tol2 != tol2) {
+    o->drop_graph();
+    hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t el = hipSuccess;
+    for (int k = 0; k < kCheckEvery && el == hipSuccess; ++k) el = opt_launch_cg_iteration(c, k & 1, tol2, st);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(st, &g);
+    if (el != hipSuccess || e != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return el != hipSuccess ? el : e;
+    }
+    o->graph = g;
+    e = hipGraphInstantiate(&o->graph_exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      o->drop_graph();
+      return e;
+    }
+    o->g_batch = c.batch;
+    o->g_tol2 = tol2;
+  }
+  return hipGraphLaunch(o->graph_exec, st);
+}
+
 // Solve A x = rhs (already in c.rhs) for `batch` problems.
 qpat_status solve(qpat_optical o, int batch, double tol, int max_iter, int* iters, hipStream_t st) {
   OptCg c = o->c;
@@ -62,7 +112,12 @@ qpat_status solve(qpat_optical o, int batch, double tol, int max_iter, int* iter
   int it = 0;
   while (it < max_iter) {
     const int chunk = std::min(kCheckEvery, max_iter - it);
-    for (int k = 0; k < chunk; ++k, ++it) OPCHK(opt_launch_cg_iteration(c, it & 1, tol2, st));
+    if (chunk == kCheckEvery) {
+      OPCHK(cg_chunk(o, c, tol2, st));
+      it += chunk;
+    } else {
+      for (int k = 0; k < chunk; ++k, ++it) OPCHK(opt_launch_cg_iteration(c, it & 1, tol2, st));
+    }
     OPCHK(hipMemcpyAsync(o->h_rr.data(), c.rr_next, sizeof(double) * batch, hipMemcpyDeviceToHost, st));
     OPCHK(hipMemcpyAsync(o->h_bb.data(), c.bb, sizeof(double) * batch, hipMemcpyDeviceToHost, st));
     OPCHK(hipStreamSynchronize(st));

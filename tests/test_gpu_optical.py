@@ -84,6 +84,29 @@ def test_optical_forward_jv_jtv(q, nx, ny):
     assert np.allclose(N(opt.pixels_T(T(p))), np.stack([O.pixel_mean_T(m, p[b]) for b in range(B)]), rtol=1e-6)
 
 
+def test_optical_graph_replays_match_eager_launches(q):
+    """On a non-default stream the CG replays a captured graph of 32
+    iterations; on the default stream it launches them one by one.  Same bits
+    and iteration counts, over several solves with eager work in between."""
+    import torch
+    n, dx = 40, 1e-4
+    m = O.Mesh(n, n, dx)
+    opt = q.Optical(n, n, dx, 2)
+    s = torch.cuda.Stream()
+    for k in range(3):
+        kap, mu = tissue(m, 2, 40 + k)
+        cur = np.array([[1.0, 0.0, 0.5, 0.0], [0.0, 2.0, 0.0, 1.0]])
+        H0 = N(opt.forward(T(kap), T(mu), cur))
+        it0 = opt.iters
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            H1 = opt.forward(T(kap), T(mu), cur, stream=s)
+            s.synchronize()
+        assert opt.iters == it0 and it0 >= 64
+        assert np.array_equal(N(H1), H0), k
+        _ = N(opt.pixels(T(H0)))        # eager work between replays
+
+
 def test_optical_paper_grid_four_illuminations(q):
     """The paper's 2-D data-generation grid (128^2 pixels of 78.1 um), one
     illumination per side (N_q = 4)."""
