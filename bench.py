@@ -53,11 +53,18 @@ PASS_BYTES = {
 
 
 # Algorithmic HBM bytes per FEM node of one conjugate-gradient iteration of
-# the optical solve (FP64): A p reads p and the two elemental coefficients of
-# the pixel it owns (8 + 32) and writes q (8); the update reads x, p, r, q and
-# the inverse diagonal (40) and writes x, r (16); the new direction reads the
-# inverse diagonal, r, p (24) and writes p (8).
-OPT_BYTES_PER_NODE_ITER = 136.0
+# the optical solve (FP64).  CG: A p reads p and the two elemental
+# coefficients of the pixel it owns (8 + 32) and writes q (8); the update
+# reads x, p, r, q (32) and writes x, r (16); r.z reads r, z (16); the new
+# direction reads z, p (16) and writes p (8).  V-cycle, per node of a level:
+# the first sweep reads the inverse diagonal and b (16) and writes x (8); the
+# restriction reads b, x and the 4-array stencil (48) and writes a quarter of
+# a coarse value (2); correction and post-sweep read x, b, the inverse
+# diagonal, the stencil and a quarter of a coarse value (58) and write t (8).
+# The levels add up to 4/3 of the fine grid's nodes.
+OPT_CG_BYTES = 48.0 + 48.0 + 16.0 + 24.0
+OPT_VCYCLE_BYTES = (24.0 + 50.0 + 66.0) * 4.0 / 3.0
+OPT_BYTES_PER_NODE_ITER = OPT_CG_BYTES + OPT_VCYCLE_BYTES
 
 
 def bytes_3d_pair(nx: int) -> float:
@@ -497,7 +504,7 @@ def main():
                 f"{t_f / its * 1e6:.1f} us each, {gbs:.0f} GB/s), J_o v {t_j * 1e3:.1f} ms")
             del opt
         out["optical"] = {"workload": "P1-FEM diffusion approximation (Robin boundary) on the grid-matched mesh, "
-                                      "4 illuminations, FP64 Jacobi-CG to 1e-8",
+                                      "4 illuminations, FP64 CG preconditioned by a multigrid V-cycle, to 1e-8",
                           "bytes_per_node_per_iteration": OPT_BYTES_PER_NODE_ITER, "runs": runs}
 
     # ------------------------------------------------------------ CPU baseline (oracle)

@@ -337,8 +337,10 @@ qpat_status qpat3d_set_graph(qpat_plan3d plan, int32_t enable);
  * element 2 (j nx + i) (corners (j,i), (j,i+1), (j+1,i+1)) and element
  * 2 (j nx + i) + 1 (corners (j,i), (j+1,i+1), (j+1,i)).  Coefficients and
  * heating are elemental, [batch][2 nx ny] device floats; the work is FP64.
- * Systems are solved by conjugate gradients with the diagonal of A_o as
- * preconditioner to ||rhs - A x|| <= tol ||rhs||, checked every 32
+ * Systems are solved by conjugate gradients, each iteration preconditioned
+ * by one multigrid V-cycle on the node grid (2 x 2 aggregation down to one
+ * node, Galerkin coarse stencils, one damped Jacobi sweep before and after
+ * each coarse correction), to ||rhs - A x|| <= tol ||rhs||, checked every 8
  * iterations (the calls synchronise the stream); *iters (may be NULL)
  * receives the iterations run.  An optical handle holds the coefficients and
  * Phi of its last forward call for J_o and J_o^*; one handle must not be used

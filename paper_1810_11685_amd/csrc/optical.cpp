@@ -28,7 +28,7 @@ namespace {
                        std::string(#expr) + ": " + hipGetErrorString(e_));                      \
   } while (0)
 
-constexpr int kCheckEvery = 32;   // CG iterations between host convergence checks
+constexpr int kCheckEvery = 8;   // CG iterations between host convergence checks
 static_assert(kCheckEvery % 2 == 0, "full chunks must start at an even iteration");
 
 }  // namespace
@@ -37,6 +37,7 @@ struct qpat_optical_s {
   int cap = 0;
   void* mem = nullptr;
   OptCg c{};
+  std::vector<OptLevel> lv;   // multigrid levels, finest first
   bool solved = false;
   std::vector<double> h_rr, h_bb;
   // hipGraph of one chunk of kCheckEvery CG iterations (chunks start at an
@@ -74,7 +75,7 @@ bool opt_ok(double tol, int max_iter) { return std::isfinite(tol) && tol > 0.0 &
 hipError_t cg_chunk(qpat_optical o, const OptCg& c, double tol2, hipStream_t st) {
   if (st == nullptr) {
     for (int k = 0; k < kCheckEvery; ++k) {
-      const hipError_t e = opt_launch_cg_iteration(c, k & 1, tol2, st);
+      const hipError_t e = opt_launch_cg_iteration(c, o->lv.data(), int(o->lv.size()), k & 1, tol2, st);
       if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -84,7 +85,8 @@ hipError_t cg_chunk(qpat_optical o, const OptCg& c, double tol2, hipStream_t st)
     hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
     hipError_t el = hipSuccess;
-    for (int k = 0; k < kCheckEvery && el == hipSuccess; ++k) el = opt_launch_cg_iteration(c, k & 1, tol2, st);
+    for (int k = 0; k < kCheckEvery && el == hipSuccess; ++k)
+      el = opt_launch_cg_iteration(c, o->lv.data(), int(o->lv.size()), k & 1, tol2, st);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(st, &g);
     if (el != hipSuccess || e != hipSuccess) {
@@ -108,7 +110,8 @@ qpat_status solve(qpat_optical o, int batch, double tol, int max_iter, int* iter
   OptCg c = o->c;
   c.batch = batch;
   const double tol2 = tol * tol;
-  OPCHK(opt_launch_cg_start(c, st));
+  OPCHK(opt_launch_mg_setup(c, o->lv.data(), int(o->lv.size()), st));
+  OPCHK(opt_launch_cg_start(c, o->lv.data(), int(o->lv.size()), st));
   int it = 0;
   while (it < max_iter) {
     const int chunk = std::min(kCheckEvery, max_iter - it);
@@ -116,7 +119,8 @@ qpat_status solve(qpat_optical o, int batch, double tol, int max_iter, int* iter
       OPCHK(cg_chunk(o, c, tol2, st));
       it += chunk;
     } else {
-      for (int k = 0; k < chunk; ++k, ++it) OPCHK(opt_launch_cg_iteration(c, it & 1, tol2, st));
+      for (int k = 0; k < chunk; ++k, ++it)
+        OPCHK(opt_launch_cg_iteration(c, o->lv.data(), int(o->lv.size()), it & 1, tol2, st));
     }
     OPCHK(hipMemcpyAsync(o->h_rr.data(), c.rr_next, sizeof(double) * batch, hipMemcpyDeviceToHost, st));
     OPCHK(hipMemcpyAsync(o->h_bb.data(), c.bb, sizeof(double) * batch, hipMemcpyDeviceToHost, st));
@@ -157,7 +161,17 @@ qpat_status qpat_optical_create(int32_t nx, int32_t ny, double dx, int32_t batch
   c.h = dx;
   c.nblk = std::min(kOptBlocks, (c.nn + kOptThreads - 1) / kOptThreads);
   const size_t nn = size_t(c.nn) * batch, ne = size_t(c.ne) * batch, np = size_t(kOptBlocks) * batch;
-  const size_t total = 4 * ne + 7 * nn + 3 * np + 5 * size_t(batch) + 4 * size_t(batch);
+  // multigrid levels on the node grid: 2 x 2 aggregates down to a single node
+  std::vector<std::pair<int, int>> dims{{nx + 1, ny + 1}};
+  while (int64_t(dims.back().first) * dims.back().second > 1)
+    dims.push_back({(dims.back().first + 1) / 2, (dims.back().second + 1) / 2});
+  if (int(dims.size()) > kOptMgMaxLevels) {
+    delete o;
+    return set_error(QPAT_E_UNSUPPORTED, "mesh needs too many multigrid levels");
+  }
+  size_t coarse = 0;
+  for (size_t l = 1; l < dims.size(); ++l) coarse += size_t(dims[l].first) * dims[l].second * batch;
+  const size_t total = 4 * ne + 7 * nn + 3 * np + 5 * size_t(batch) + 4 * size_t(batch) + 6 * nn + 8 * coarse;
   void* mem = nullptr;
   hipError_t e = hipMalloc(&mem, total * sizeof(double));
   if (e != hipSuccess) {
@@ -190,6 +204,25 @@ qpat_status qpat_optical_create(int32_t nx, int32_t ny, double dx, int32_t batch
   c.rr_next = take(batch);
   c.bb = take(batch);
   c.cur = take(4 * size_t(batch));
+  c.z = take(nn);
+  {
+    // level 0 works on the CG vectors: b = r, result t = z
+    OptLevel L{nx + 1, ny + 1, take(nn), take(nn), take(nn), take(nn), c.dinv, c.r, take(nn), c.z};
+    o->lv.push_back(L);
+  }
+  for (size_t l = 1; l < dims.size(); ++l) {
+    const size_t m = size_t(dims[l].first) * dims[l].second * batch;
+    OptLevel L{dims[l].first, dims[l].second, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    L.sc = take(m);
+    L.se = take(m);
+    L.sn = take(m);
+    L.sd = take(m);
+    L.dinv = take(m);
+    L.b = take(m);
+    L.x = take(m);
+    L.t = take(m);
+    o->lv.push_back(L);
+  }
   o->cap = batch;
   o->h_rr.resize(batch);
   o->h_bb.resize(batch);

@@ -1,7 +1,8 @@
 // Optical operators of Section 3.1 on the GPU: the P1 Galerkin system
 // A_o = K[kappa] + C[mu] + R of the diffusion approximation with its Robin
 // condition (eqs var_fo, system_forward2) on the grid-matched triangulation,
-// its solution by FP64 conjugate gradients (Jacobi preconditioner), the
+// its solution by FP64 conjugate gradients (preconditioned by one multigrid
+// V-cycle of 2 x 2 node aggregation with Galerkin coarse stencils), the
 // heating map H = mu o I Phi (eq forward_out), J_o (eq dh_des) and J_o^*
 // (eqs system_adjoint, system_adjoint1, prodtproj).
 //
@@ -216,29 +217,148 @@ __global__ void __launch_bounds__(kOptThreads) opt_stage_kernel(OptCg c, const f
   }
 }
 
-// CG start: x = 0, r = rhs, dinv, p = dinv r; partials of r.z, r.r
+// ---- multigrid V-cycle (levels as in OptLevel)
+// fine-mesh element indices of pixel (j, i)
+__device__ __forceinline__ int elem0(int j, int i, int nx) { return 2 * (j * nx + i); }
+
+// Level 0 stencil of A_o at node (r, col): the diagonal (diag_at), and the
+// entries for the east edge (bottom edge of pixel (r, col), element shape 0;
+// top edge of pixel (r - 1, col), shape 1), the north edge (left edge of
+// pixel (r, col), shape 1; right edge of pixel (r, col - 1), shape 0) and the
+// north-east diagonal of pixel (r, col) (mass of both elements; the P1
+// stiffness across a right angle's hypotenuse is 0); boundary edges add the
+// Robin edge mass.
+__global__ void __launch_bounds__(kOptThreads) opt_mg_stencil_kernel(OptCg c, OptLevel L) {
+  const int b = blockIdx.y;
+  const size_t bn = size_t(b) * c.nn, be = size_t(b) * c.ne;
+  const double* ka = c.ka + be;
+  const double* mu = c.mu + be;
+  const int W = c.nx + 1, nx = c.nx, ny = c.ny;
+  const double ms = 0.5 * c.h * c.h, w = 2.0 * kGamma2 * c.h / 6.0;
+  FOR_NODES(k) {
+    const int r = k / W, col = k - r * W;
+    const double d = diag_at(ka, mu, r, col, nx, ny, c.h);
+    double e = 0.0, n = 0.0, g = 0.0;
+    if (col < nx) {
+      if (r < ny) e += -0.5 * ka[elem0(r, col, nx)] + ms / 12.0 * mu[elem0(r, col, nx)];
+      if (r > 0) e += -0.5 * ka[elem0(r - 1, col, nx) + 1] + ms / 12.0 * mu[elem0(r - 1, col, nx) + 1];
+      if (r == 0 || r == ny) e += w;
+    }
+    if (r < ny) {
+      if (col < nx) n += -0.5 * ka[elem0(r, col, nx) + 1] + ms / 12.0 * mu[elem0(r, col, nx) + 1];
+      if (col > 0) n += -0.5 * ka[elem0(r, col - 1, nx)] + ms / 12.0 * mu[elem0(r, col - 1, nx)];
+      if (col == 0 || col == nx) n += w;
+    }
+    if (r < ny && col < nx) g = ms / 12.0 * (mu[elem0(r, col, nx)] + mu[elem0(r, col, nx) + 1]);
+    L.sc[bn + k] = d;
+    L.se[bn + k] = e;
+    L.sn[bn + k] = n;
+    L.sd[bn + k] = g;
+    L.dinv[bn + k] = 1.0 / d;
+  }
+}
+
+// (A u)_k at node (j, i) of a level, u(k, i, j) the iterate
+template <typename U>
+__device__ __forceinline__ double stencil_op(const OptLevel& L, size_t base, int k, int i, int j, U u) {
+  const int nx = L.nx;
+  double y = L.sc[base + k] * u(k, i, j);
+  if (i + 1 < nx) y += L.se[base + k] * u(k + 1, i + 1, j);
+  if (i > 0) y += L.se[base + k - 1] * u(k - 1, i - 1, j);
+  if (j + 1 < L.ny) y += L.sn[base + k] * u(k + nx, i, j + 1);
+  if (j > 0) y += L.sn[base + k - nx] * u(k - nx, i, j - 1);
+  if (j + 1 < L.ny && i + 1 < nx) y += L.sd[base + k] * u(k + nx + 1, i + 1, j + 1);
+  if (j > 0 && i > 0) y += L.sd[base + k - nx - 1] * u(k - nx - 1, i - 1, j - 1);
+  return y;
+}
+
+// Galerkin coarse stencil P^T A P of 2 x 2 aggregates (one thread per coarse
+// node): the diagonal sums the aggregate's diagonal and twice its inner
+// couplings; a coarse coupling sums the fine couplings between two aggregates
+__global__ void __launch_bounds__(kOptThreads) opt_mg_coarsen_kernel(OptLevel f, OptLevel c) {
+  const int b = blockIdx.y, nc = c.nx * c.ny;
+  const size_t bf = size_t(b) * f.nx * f.ny, bc = size_t(b) * nc;
+  auto F = [&](const double* a, int j, int i) { return (j < f.ny && i < f.nx) ? a[bf + size_t(j) * f.nx + i] : 0.0; };
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nc; k += gridDim.x * blockDim.x) {
+    const int J = k / c.nx, I = k - J * c.nx, j = 2 * J, i = 2 * I;
+    const double d = F(f.sc, j, i) + F(f.sc, j, i + 1) + F(f.sc, j + 1, i) + F(f.sc, j + 1, i + 1) +
+                     2.0 * (F(f.se, j, i) + F(f.se, j + 1, i) + F(f.sn, j, i) + F(f.sn, j, i + 1) + F(f.sd, j, i));
+    const bool east = I + 1 < c.nx, north = J + 1 < c.ny;
+    c.sc[bc + k] = d;
+    c.se[bc + k] = east ? F(f.se, j, i + 1) + F(f.se, j + 1, i + 1) + F(f.sd, j, i + 1) : 0.0;
+    c.sn[bc + k] = north ? F(f.sn, j + 1, i) + F(f.sn, j + 1, i + 1) + F(f.sd, j + 1, i) : 0.0;
+    c.sd[bc + k] = (east && north) ? F(f.sd, j + 1, i + 1) : 0.0;
+    c.dinv[bc + k] = 1.0 / d;
+  }
+}
+
+// first sweep from x = 0: x = om dinv b
+__global__ void __launch_bounds__(kOptThreads) opt_mg_scale_kernel(OptLevel L, double om) {
+  const int b = blockIdx.y, n = L.nx * L.ny;
+  const size_t base = size_t(b) * n;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x)
+    L.x[base + k] = om * L.dinv[base + k] * L.b[base + k];
+}
+
+// coarse right-hand side: aggregate sums of the residual b - A x
+__global__ void __launch_bounds__(kOptThreads) opt_mg_restrict_kernel(OptLevel f, OptLevel c) {
+  const int b = blockIdx.y, nc = c.nx * c.ny;
+  const size_t bf = size_t(b) * f.nx * f.ny, bc = size_t(b) * nc;
+  auto xf = [&](int kk, int, int) { return f.x[bf + kk]; };
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nc; k += gridDim.x * blockDim.x) {
+    const int J = k / c.nx, I = k - J * c.nx;
+    double acc = 0.0;
+    for (int j = 2 * J; j < 2 * J + 2 && j < f.ny; ++j)
+      for (int i = 2 * I; i < 2 * I + 2 && i < f.nx; ++i) {
+        const int kf = j * f.nx + i;
+        acc += f.b[bf + kf] - stencil_op(f, bf, kf, i, j, xf);
+      }
+    c.b[bc + k] = acc;
+  }
+}
+
+// coarse correction and post-smoothing: x' = x + P xc; t = x' + om dinv (b - A x')
+__global__ void __launch_bounds__(kOptThreads) opt_mg_post_kernel(OptLevel f, const double* __restrict__ xc,
+                                                                   int nxc, int nyc, double om) {
+  const int b = blockIdx.y, n = f.nx * f.ny;
+  const size_t bf = size_t(b) * n, bc = size_t(b) * nxc * nyc;
+  auto xp = [&](int kk, int ii, int jj) { return f.x[bf + kk] + xc[bc + size_t(jj >> 1) * nxc + (ii >> 1)]; };
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+    const int j = k / f.nx, i = k - j * f.nx;
+    const double y = stencil_op(f, bf, k, i, j, xp);
+    f.t[bf + k] = xp(k, i, j) + om * f.dinv[bf + k] * (f.b[bf + k] - y);
+  }
+}
+
+// CG start: x = 0, r = rhs; partials of r.r (z and r.z follow the V-cycle)
 __global__ void __launch_bounds__(kOptThreads) opt_cg_start_kernel(OptCg c) {
   __shared__ double red[kOptThreads / 64];
   const int b = blockIdx.y;
-  const size_t bn = size_t(b) * c.nn, be = size_t(b) * c.ne;
-  const int W = c.nx + 1;
-  double rz = 0.0, rr = 0.0;
+  const size_t bn = size_t(b) * c.nn;
+  double rr = 0.0;
   FOR_NODES(k) {
-    const int r = k / W, col = k - r * W;
-    const double di = 1.0 / diag_at(c.ka + be, c.mu + be, r, col, c.nx, c.ny, c.h);
-    const double rv = c.rhs[bn + k], z = di * rv;
-    c.dinv[bn + k] = di;
+    const double rv = c.rhs[bn + k];
     c.x[bn + k] = 0.0;
     c.r[bn + k] = rv;
-    c.p[bn + k] = z;
-    rz += rv * z;
     rr += rv * rv;
   }
-  const double s1 = block_sum(rz, red), s2 = block_sum(rr, red);
-  if (threadIdx.x == 0) {
-    c.part_rz[size_t(b) * kOptBlocks + blockIdx.x] = s1;
-    c.part_rr[size_t(b) * kOptBlocks + blockIdx.x] = s2;
+  const double s = block_sum(rr, red);
+  if (threadIdx.x == 0) c.part_rr[size_t(b) * kOptBlocks + blockIdx.x] = s;
+}
+
+// partials of r.z for the z the V-cycle left; at the start also p = z
+__global__ void __launch_bounds__(kOptThreads) opt_cg_rz_kernel(OptCg c, int set_p) {
+  __shared__ double red[kOptThreads / 64];
+  const int b = blockIdx.y;
+  const size_t bn = size_t(b) * c.nn;
+  double rz = 0.0;
+  FOR_NODES(k) {
+    const double z = c.z[bn + k];
+    rz += c.r[bn + k] * z;
+    if (set_p) c.p[bn + k] = z;
   }
+  const double s = block_sum(rz, red);
+  if (threadIdx.x == 0) c.part_rz[size_t(b) * kOptBlocks + blockIdx.x] = s;
 }
 
 __global__ void __launch_bounds__(kOptThreads) opt_cg_start_total_kernel(OptCg c) {
@@ -273,7 +393,7 @@ __global__ void __launch_bounds__(kOptThreads) opt_cg_q_kernel(OptCg c) {
   if (threadIdx.x == 0) c.part_pq[size_t(b) * kOptBlocks + blockIdx.x] = s;
 }
 
-// alpha = r.z / p.q (0 once converged); x += alpha p; r -= alpha q; partials of new r.z, r.r
+// alpha = r.z / p.q (0 once converged); x += alpha p; r -= alpha q; partials of the new r.r
 __global__ void __launch_bounds__(kOptThreads) opt_cg_update_kernel(OptCg c, int par, double tol2) {
   __shared__ double red[kOptThreads / 64];
   const int b = blockIdx.y, nb = gridDim.y;
@@ -282,22 +402,18 @@ __global__ void __launch_bounds__(kOptThreads) opt_cg_update_kernel(OptCg c, int
   const double rz = c.rz[size_t(par) * nb + b];
   const bool live = c.rr[b] > tol2 * c.bb[b] && pq > 0.0;
   const double alpha = live ? rz / pq : 0.0;
-  double rzn = 0.0, rr = 0.0;
+  double rr = 0.0;
   FOR_NODES(k) {
     c.x[bn + k] += alpha * c.p[bn + k];
     const double rv = c.r[bn + k] - alpha * c.q[bn + k];
     c.r[bn + k] = rv;
-    rzn += rv * c.dinv[bn + k] * rv;
     rr += rv * rv;
   }
-  const double s1 = block_sum(rzn, red), s2 = block_sum(rr, red);
-  if (threadIdx.x == 0) {
-    c.part_rz[size_t(b) * kOptBlocks + blockIdx.x] = s1;
-    c.part_rr[size_t(b) * kOptBlocks + blockIdx.x] = s2;
-  }
+  const double s2 = block_sum(rr, red);
+  if (threadIdx.x == 0) c.part_rr[size_t(b) * kOptBlocks + blockIdx.x] = s2;
 }
 
-// beta = rz_new / rz; p = dinv r + beta p; block (0, b) stores rz_new, rr_next
+// beta = rz_new / rz; p = z + beta p; block (0, b) stores rz_new, rr_next
 __global__ void __launch_bounds__(kOptThreads) opt_cg_dir_kernel(OptCg c, int par) {
   __shared__ double red[kOptThreads / 64];
   const int b = blockIdx.y, nb = gridDim.y;
@@ -306,7 +422,7 @@ __global__ void __launch_bounds__(kOptThreads) opt_cg_dir_kernel(OptCg c, int pa
   const double rrn = partial_total(c.part_rr, b, c.nblk, red);
   const double rz = c.rz[size_t(par) * nb + b];
   const double beta = rz > 0.0 ? rzn / rz : 0.0;
-  FOR_NODES(k) c.p[bn + k] = c.dinv[bn + k] * c.r[bn + k] + beta * c.p[bn + k];
+  FOR_NODES(k) c.p[bn + k] = c.z[bn + k] + beta * c.p[bn + k];
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     c.rz[size_t(1 - par) * nb + b] = rzn;
     c.rr_next[b] = rrn;
@@ -385,14 +501,54 @@ hipError_t opt_launch_rhs(const OptCg& c, int mode, const double* cur, const flo
   hipLaunchKernelGGL(opt_rhs_kernel, dim3(c.nblk, c.batch), dim3(kOptThreads), 0, st, c, mode, cur, Hin);
   return hipGetLastError();
 }
-hipError_t opt_launch_cg_start(const OptCg& c, hipStream_t st) {
+namespace {
+
+// blocks per field for a level of n nodes (grid-stride loops cover the rest)
+dim3 level_grid(const OptLevel& L, int batch) {
+  const int n = L.nx * L.ny;
+  return dim3(unsigned(n < kOptBlocks * kOptThreads ? (n + kOptThreads - 1) / kOptThreads : kOptBlocks),
+              unsigned(batch));
+}
+
+// z = V-cycle applied to level 0's b; the result lands in level 0's t
+void launch_vcycle(const OptLevel* lv, int nlev, int batch, hipStream_t st) {
+  for (int l = 0; l + 1 < nlev; ++l) {
+    hipLaunchKernelGGL(opt_mg_scale_kernel, level_grid(lv[l], batch), dim3(kOptThreads), 0, st, lv[l], kOptMgOmega);
+    hipLaunchKernelGGL(opt_mg_restrict_kernel, level_grid(lv[l + 1], batch), dim3(kOptThreads), 0, st, lv[l],
+                       lv[l + 1]);
+  }
+  // coarsest level: one node per field, solved exactly (x = b / diag)
+  hipLaunchKernelGGL(opt_mg_scale_kernel, level_grid(lv[nlev - 1], batch), dim3(kOptThreads), 0, st, lv[nlev - 1],
+                     1.0);
+  for (int l = nlev - 2; l >= 0; --l) {
+    const double* xc = (l + 1 == nlev - 1) ? lv[l + 1].x : lv[l + 1].t;
+    hipLaunchKernelGGL(opt_mg_post_kernel, level_grid(lv[l], batch), dim3(kOptThreads), 0, st, lv[l], xc,
+                       lv[l + 1].nx, lv[l + 1].ny, kOptMgOmega);
+  }
+}
+
+}  // namespace
+
+hipError_t opt_launch_mg_setup(const OptCg& c, const OptLevel* lv, int nlev, hipStream_t st) {
+  hipLaunchKernelGGL(opt_mg_stencil_kernel, dim3(c.nblk, c.batch), dim3(kOptThreads), 0, st, c, lv[0]);
+  for (int l = 0; l + 1 < nlev; ++l)
+    hipLaunchKernelGGL(opt_mg_coarsen_kernel, level_grid(lv[l + 1], c.batch), dim3(kOptThreads), 0, st, lv[l],
+                       lv[l + 1]);
+  return hipGetLastError();
+}
+hipError_t opt_launch_cg_start(const OptCg& c, const OptLevel* lv, int nlev, hipStream_t st) {
   hipLaunchKernelGGL(opt_cg_start_kernel, dim3(c.nblk, c.batch), dim3(kOptThreads), 0, st, c);
+  launch_vcycle(lv, nlev, c.batch, st);
+  hipLaunchKernelGGL(opt_cg_rz_kernel, dim3(c.nblk, c.batch), dim3(kOptThreads), 0, st, c, 1);
   hipLaunchKernelGGL(opt_cg_start_total_kernel, dim3(c.batch), dim3(kOptThreads), 0, st, c);
   return hipGetLastError();
 }
-hipError_t opt_launch_cg_iteration(const OptCg& c, int par, double tol2, hipStream_t st) {
+hipError_t opt_launch_cg_iteration(const OptCg& c, const OptLevel* lv, int nlev, int par, double tol2,
+                                   hipStream_t st) {
   hipLaunchKernelGGL(opt_cg_q_kernel, dim3(c.nblk, c.batch), dim3(kOptThreads), 0, st, c);
   hipLaunchKernelGGL(opt_cg_update_kernel, dim3(c.nblk, c.batch), dim3(kOptThreads), 0, st, c, par, tol2);
+  launch_vcycle(lv, nlev, c.batch, st);
+  hipLaunchKernelGGL(opt_cg_rz_kernel, dim3(c.nblk, c.batch), dim3(kOptThreads), 0, st, c, 0);
   hipLaunchKernelGGL(opt_cg_dir_kernel, dim3(c.nblk, c.batch), dim3(kOptThreads), 0, st, c, par);
   return hipGetLastError();
 }

@@ -85,7 +85,7 @@ def test_optical_forward_jv_jtv(q, nx, ny):
 
 
 def test_optical_graph_replays_match_eager_launches(q):
-    """On a non-default stream the CG replays a captured graph of 32
+    """On a non-default stream the CG replays a captured graph of 8
     iterations; on the default stream it launches them one by one.  Same bits
     and iteration counts, over several solves with eager work in between."""
     import torch
@@ -102,7 +102,7 @@ def test_optical_graph_replays_match_eager_launches(q):
         with torch.cuda.stream(s):
             H1 = opt.forward(T(kap), T(mu), cur, stream=s)
             s.synchronize()
-        assert opt.iters == it0 and it0 >= 64
+        assert opt.iters == it0 and it0 >= 8      # at least one full chunk (graph)
         assert np.array_equal(N(H1), H0), k
         _ = N(opt.pixels(T(H0)))        # eager work between replays
 
