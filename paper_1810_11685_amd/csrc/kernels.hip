@@ -1142,15 +1142,15 @@ __device__ __forceinline__ void col_generic(const Medium& M, const Work& W, int 
     const int it = threadIdx.x + k * B;
     if (it < tot) {
       const int c = ct == 1 ? 0 : fdiv(it, ny, rny), ky = it - c * ny, kx = c0 + c;
-      const unsigned t = mul24(ky, nxh + 1) + kx;
+      const unsigned t = mul24(kx, ny) + ky, tn = mul24(nxh, ny) + ky;   // tables are [kx][ky]
       MultPre& p = P[k];
       p.a = tabA[t];
       p.b = labs ? M.labs[t] : 0.f;
       p.sx = xcode ? symx[kx] : make_float2(0.f, 0.f);
       p.sy = ycode ? symy[ky] : make_float2(0.f, 0.f);
       if (kx == 0) {
-        p.an = tabA[t + nxh];
-        p.bn = labs ? M.labs[t + nxh] : 0.f;
+        p.an = tabA[tn];
+        p.bn = labs ? M.labs[tn] : 0.f;
         p.sxn = xcode ? symx[nxh] : make_float2(0.f, 0.f);
       }
     }
@@ -1273,11 +1273,11 @@ __device__ __forceinline__ void col_mult_lds(const Medium& M, int tile, int mcod
   const float rny = 1.0f / static_cast<float>(ny);
   for (int it = threadIdx.x; it < ncols * ny; it += B) {
     const int c = ncols == 1 ? 0 : fdiv(it, ny, rny), ky = it - c * ny, kx = c0 + c;
-    const unsigned t = mul24(ky, nxh + 1) + kx;
+    const unsigned t = mul24(kx, ny) + ky, tn = mul24(nxh, ny) + ky;   // tables are [kx][ky]
     const float a = tabA[t], b = labs ? M.labs[t] : 0.f;
     const float2 sx = xcode ? symx[kx] : make_float2(0.f, 0.f), sy = ycode ? symy[ky] : make_float2(0.f, 0.f);
     if (kx == 0) {
-      const float an = tabA[t + nxh], bn = labs ? M.labs[t + nxh] : 0.f;
+      const float an = tabA[tn], bn = labs ? M.labs[tn] : 0.f;
       const float2 sxn = xcode ? symx[nxh] : make_float2(0.f, 0.f);
       const int km = ky ? ny - ky : 0;
       float2 f0[2], fn[2];
@@ -1383,7 +1383,7 @@ __device__ __forceinline__ void col_fused(const Medium& M, const Work& W, int ti
   fetch_tw(TW, M.twy, N);
   fetch_tw(TWR, M.twyr, N);
   const unsigned np = unsigned(ct) * NBS;
-  const unsigned tstep = unsigned(NBS) * (nxh + 1);
+  const unsigned tstep = unsigned(NBS);   // tables are [kx][ky]: a column's entries are contiguous
   float ma[kP][RS], mb[kP][RS];
   float2 msy[kP][RS], msx[kP];
 #pragma unroll
@@ -1391,7 +1391,7 @@ __device__ __forceinline__ void col_fused(const Medium& M, const Work& W, int ti
     if (i * B < int(np)) {
       const unsigned pp = min(unsigned(tid + i * B), np - 1);
       const unsigned c = pp / NBS, j = pp % NBS, kx = c0 + c;
-      const unsigned t0 = mul24(j, nxh + 1) + kx;
+      const unsigned t0 = mul24(kx, N) + j;
       msx[i] = xcode ? symx[kx] : make_float2(0.f, 0.f);
 #pragma unroll
       for (int r = 0; r < RS; ++r) {

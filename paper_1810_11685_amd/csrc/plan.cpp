@@ -597,7 +597,7 @@ qpat_status plan_build(qpat_plan P, const double* c0, const double* rho0) {
       const double K = std::sqrt(kx * kx + ky * ky);
       const double arg = p.c_ref * K * dt / 2.0;
       const double kp = arg == 0.0 ? 1.0 : std::sin(arg) / arg;
-      const size_t t = size_t(j) * (nxh + 1) + i;
+      const size_t t = size_t(i) * ny + j;   // [kx][ky]: a spectrum column's entries contiguous
       kap[t] = float(kp * inv);
       ldis[t] = (K == 0.0 || !lossy) ? 0.f : float(std::pow(K, p.y - 1.0) * inv);
       labs[t] = (K == 0.0 || !lossy) ? 0.f : float(std::pow(K, p.y - 2.0) * inv);

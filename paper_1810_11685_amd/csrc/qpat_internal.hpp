@@ -39,7 +39,7 @@ struct Medium {
   const float *avx, *arx, *avy, *ary;                 // PML diagonals: [nx] / [ny]
   const float2 *dxp, *dxm;                            // [nxh+1] i kx e^{+-i kx dx/2}
   const float2 *dyp, *dym;                            // [ny]
-  const float *kap, *ldis, *labs;                     // [ny][nxh+1], divided by nx*ny
+  const float *kap, *ldis, *labs;                     // [nxh+1][ny] (column-major), divided by nx*ny
   const float2 *twx, *twy;                            // per-stage FFT twiddles [nx] / [ny]
   const float2* twyr;                                 // the same for the reversed ny plan
   const int* tap_off;                                 // [ny+1] CSR offsets into taps
