@@ -189,10 +189,57 @@ __device__ void stage_generic(const float2* __restrict__ src, float2* __restrict
   }
 }
 
+// The stage of stage_small for a compile-time length N and stage (radix R,
+// NS = product of the earlier radices): the butterfly count, twiddle step and
+// k = j mod NS fold to constants, leaving the line offset as the only index
+// arithmetic done at run time.  Same operations in the same order.
+template <int R, bool INV, int N, int NS>
+__device__ __forceinline__ void stage_ct(const float2* __restrict__ src, float2* __restrict__ dst, const LineMap m,
+                                         const float2* __restrict__ tw) {
+  constexpr unsigned NB = N / R, TSTEP = N / (NS * R);
+  constexpr float RNB = 1.0f / float(NB);
+  const unsigned total = unsigned(m.nlines) * NB, es = unsigned(m.es);
+  const unsigned istep = NB * es, ostep = NS * es;
+  const float rlpg = rcp(m.lpg);
+  for (unsigned t = threadIdx.x; t < total; t += blockDim.x) {
+    const unsigned L = unsigned(udiv(int(t), RNB)), j = t - L * NB;
+    const unsigned off = line_off(m, L, rlpg);
+    // j < NB, so k = j mod NS is 0 in a first stage and j once NS >= NB
+    const unsigned k = NS == 1 ? 0u : (NS >= int(NB) ? j : j % NS);
+    const float2* s = src + (off + __umul24(j, es));
+    float2 v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = s[r * istep];
+    if constexpr (NS > 1) {
+      const unsigned kt = k * TSTEP;
+      unsigned e = 0;
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        e += kt;   // r k tstep
+        float2 w = tw[e];
+        if (INV) w.y = -w.y;
+        v[r] = cmul(v[r], w);
+      }
+    }
+    dft<R, INV>(v);
+    float2* d = dst + (off + __umul24((j - k) * R + k, es));
+#pragma unroll
+    for (int r = 0; r < R; ++r) d[r * ostep] = v[r];
+  }
+}
+
 // All stages of one axis (barrier after each); returns the buffer holding the
 // result (a or b).
 template <bool INV>
 __device__ float2* fft_axis(float2* a, float2* b, const LineMap m, const AxisPlan P, const float2* tw) {
+  if (P.n == 49) {
+    // 7 x 7: the axes of the paper's 33^3-node grid with its 8-cell PML
+    stage_ct<7, INV, 49, 1>(a, b, m, tw);
+    __syncthreads();
+    stage_ct<7, INV, 49, 7>(b, a, m, tw);
+    __syncthreads();
+    return a;
+  }
   // radices packed 8 bits a stage: a dynamic index into P would put P in scratch
   unsigned long long rad = 0;
 #pragma unroll
