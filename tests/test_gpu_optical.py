@@ -57,8 +57,10 @@ def oracle_G(mesh, cur):
     return sum(cur[k] * O.load(mesh, [SIDES[k]]) for k in range(4))
 
 
-@pytest.mark.parametrize("nx,ny", [(24, 20), (7, 13)])
+@pytest.mark.parametrize("nx,ny", [(24, 20), (7, 13), (2, 3), (1, 1)])
 def test_optical_forward_jv_jtv(q, nx, ny):
+    """Odd and tiny meshes give multigrid aggregates of one node row or column
+    (a 1 x 1 mesh has 2 x 2 nodes: two levels)."""
     B = 2
     dx = 1e-4
     m = O.Mesh(nx, ny, dx)
@@ -116,7 +118,7 @@ def test_optical_paper_grid_four_illuminations(q):
     cur = np.eye(4)
     opt = q.Optical(n, n, dx, 4)
     H = N(opt.forward(T(kap), T(mu), cur))
-    assert opt.iters > 0
+    assert 0 < opt.iters <= 80   # the V-cycle keeps the CG short (the diagonal alone needed ~480)
     for b in range(4):
         assert rel(H[b], O.forward(m, kap[b], mu[b], oracle_G(m, cur[b]))[0]) <= 1e-5
 
