@@ -300,11 +300,12 @@ __global__ void __launch_bounds__(kOptThreads) opt_mg_scale_kernel(OptLevel L, d
     L.x[base + k] = om * L.dinv[base + k] * L.b[base + k];
 }
 
-// coarse right-hand side: aggregate sums of the residual b - A x
-__global__ void __launch_bounds__(kOptThreads) opt_mg_restrict_kernel(OptLevel f, OptLevel c) {
+// coarse right-hand side: aggregate sums of the residual b - A x of the first
+// sweep from x = 0, x = om dinv b (recomputed where it is needed rather than stored)
+__global__ void __launch_bounds__(kOptThreads) opt_mg_restrict_kernel(OptLevel f, OptLevel c, double om) {
   const int b = blockIdx.y, nc = c.nx * c.ny;
   const size_t bf = size_t(b) * f.nx * f.ny, bc = size_t(b) * nc;
-  auto xf = [&](int kk, int, int) { return f.x[bf + kk]; };
+  auto xf = [&](int kk, int, int) { return om * f.dinv[bf + kk] * f.b[bf + kk]; };
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nc; k += gridDim.x * blockDim.x) {
     const int J = k / c.nx, I = k - J * c.nx;
     double acc = 0.0;
@@ -317,12 +318,15 @@ __global__ void __launch_bounds__(kOptThreads) opt_mg_restrict_kernel(OptLevel f
   }
 }
 
-// coarse correction and post-smoothing: x' = x + P xc; t = x' + om dinv (b - A x')
+// coarse correction and post-smoothing: x' = om dinv b + P xc (the first
+// sweep's x, recomputed); t = x' + om dinv (b - A x')
 __global__ void __launch_bounds__(kOptThreads) opt_mg_post_kernel(OptLevel f, const double* __restrict__ xc,
                                                                    int nxc, int nyc, double om) {
   const int b = blockIdx.y, n = f.nx * f.ny;
   const size_t bf = size_t(b) * n, bc = size_t(b) * nxc * nyc;
-  auto xp = [&](int kk, int ii, int jj) { return f.x[bf + kk] + xc[bc + size_t(jj >> 1) * nxc + (ii >> 1)]; };
+  auto xp = [&](int kk, int ii, int jj) {
+    return om * f.dinv[bf + kk] * f.b[bf + kk] + xc[bc + size_t(jj >> 1) * nxc + (ii >> 1)];
+  };
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
     const int j = k / f.nx, i = k - j * f.nx;
     const double y = stencil_op(f, bf, k, i, j, xp);
@@ -512,11 +516,9 @@ dim3 level_grid(const OptLevel& L, int batch) {
 
 // z = V-cycle applied to level 0's b; the result lands in level 0's t
 void launch_vcycle(const OptLevel* lv, int nlev, int batch, hipStream_t st) {
-  for (int l = 0; l + 1 < nlev; ++l) {
-    hipLaunchKernelGGL(opt_mg_scale_kernel, level_grid(lv[l], batch), dim3(kOptThreads), 0, st, lv[l], kOptMgOmega);
+  for (int l = 0; l + 1 < nlev; ++l)
     hipLaunchKernelGGL(opt_mg_restrict_kernel, level_grid(lv[l + 1], batch), dim3(kOptThreads), 0, st, lv[l],
-                       lv[l + 1]);
-  }
+                       lv[l + 1], kOptMgOmega);
   // coarsest level: one node per field, solved exactly (x = b / diag)
   hipLaunchKernelGGL(opt_mg_scale_kernel, level_grid(lv[nlev - 1], batch), dim3(kOptThreads), 0, st, lv[nlev - 1],
                      1.0);

@@ -38,7 +38,7 @@ hipError_t opt_launch_rhs(const OptCg& c, int mode, const double* cur, const flo
 struct OptLevel {
   int nx, ny;
   double *sc, *se, *sn, *sd, *dinv;  // stencil and inverse diagonal
-  double *b, *x, *t;                 // right-hand side, pre-smoothed, post-smoothed iterate
+  double *b, *x, *t;                 // right-hand side, iterate (coarsest level), post-smoothed iterate
 };
 constexpr int kOptMgMaxLevels = 32;
 constexpr double kOptMgOmega = 0.8;  // damping of the Jacobi sweeps

@@ -185,11 +185,12 @@ __global__ void __launch_bounds__(kRedThreads) mg_scale_kernel(MgLevel L, double
     L.x[base + k] = om * L.dinv[base + k] * L.b[base + k];
 }
 
-// coarse right-hand side: the aggregate sums of the residual b - A x
-__global__ void __launch_bounds__(kRedThreads) mg_restrict_kernel(MgLevel f, MgLevel c) {
+// coarse right-hand side: the aggregate sums of the residual b - A x of the
+// first sweep from x = 0, x = om dinv b (recomputed where it is needed)
+__global__ void __launch_bounds__(kRedThreads) mg_restrict_kernel(MgLevel f, MgLevel c, double om) {
   const int b = blockIdx.y, nc = c.nx * c.ny;
   const size_t bf = size_t(b) * f.nx * f.ny, bc = size_t(b) * nc;
-  auto xf = [&](int kk, int, int) { return f.x[bf + kk]; };
+  auto xf = [&](int kk, int, int) { return om * f.dinv[bf + kk] * f.b[bf + kk]; };
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nc; k += gridDim.x * blockDim.x) {
     const int J = k / c.nx, I = k - J * c.nx;
     double acc = 0.0;
@@ -202,13 +203,15 @@ __global__ void __launch_bounds__(kRedThreads) mg_restrict_kernel(MgLevel f, MgL
   }
 }
 
-// coarse correction and post-smoothing: with x' = x + P xc,
-// t = x' + om dinv (b - A x')
+// coarse correction and post-smoothing: with x' = om dinv b + P xc (the
+// first sweep's x, recomputed), t = x' + om dinv (b - A x')
 __global__ void __launch_bounds__(kRedThreads) mg_post_kernel(MgLevel f, const double* __restrict__ xc, int nxc,
                                                                int nyc, double om) {
   const int b = blockIdx.y, n = f.nx * f.ny;
   const size_t bf = size_t(b) * n, bc = size_t(b) * nxc * nyc;
-  auto xp = [&](int kk, int ii, int jj) { return f.x[bf + kk] + xc[bc + size_t(jj >> 1) * nxc + (ii >> 1)]; };
+  auto xp = [&](int kk, int ii, int jj) {
+    return om * f.dinv[bf + kk] * f.b[bf + kk] + xc[bc + size_t(jj >> 1) * nxc + (ii >> 1)];
+  };
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
     const int j = k / f.nx, i = k - j * f.nx;
     const double y = level_op(f, bf, k, i, j, xp);
@@ -371,10 +374,9 @@ dim3 level_grid(const MgLevel& L, int batch) {
 
 // z = V-cycle applied to level 0's b; the result lands in level 0's t
 hipError_t launch_vcycle(const MgLevel* lv, int nlev, int batch, hipStream_t st) {
-  for (int l = 0; l + 1 < nlev; ++l) {
-    hipLaunchKernelGGL(mg_scale_kernel, level_grid(lv[l], batch), dim3(kRedThreads), 0, st, lv[l], kMgOmega);
-    hipLaunchKernelGGL(mg_restrict_kernel, level_grid(lv[l + 1], batch), dim3(kRedThreads), 0, st, lv[l], lv[l + 1]);
-  }
+  for (int l = 0; l + 1 < nlev; ++l)
+    hipLaunchKernelGGL(mg_restrict_kernel, level_grid(lv[l + 1], batch), dim3(kRedThreads), 0, st, lv[l], lv[l + 1],
+                       kMgOmega);
   // coarsest level: one node per field, solved exactly (x = b / diag)
   hipLaunchKernelGGL(mg_scale_kernel, level_grid(lv[nlev - 1], batch), dim3(kRedThreads), 0, st, lv[nlev - 1], 1.0);
   for (int l = nlev - 2; l >= 0; --l) {

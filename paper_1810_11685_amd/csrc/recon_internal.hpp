@@ -28,7 +28,7 @@ struct TvCg {
 struct MgLevel {
   int nx, ny;
   double *wh, *wv, *g, *dinv;  // operator: edge weights, diagonal (gamma) term, inverse diagonal
-  double *b, *x, *t;           // right-hand side, pre-smoothed iterate, post-smoothed iterate
+  double *b, *x, *t;           // right-hand side, iterate (coarsest level), post-smoothed iterate
 };
 constexpr int kMgMaxLevels = 32;
 constexpr double kMgOmega = 0.8;  // damping of the Jacobi sweeps
