@@ -56,14 +56,14 @@ PASS_BYTES = {
 # the optical solve (FP64).  CG: A p reads p and the two elemental
 # coefficients of the pixel it owns (8 + 32) and writes q (8); the update
 # reads x, p, r, q (32) and writes x, r (16); r.z reads r, z (16); the new
-# direction reads z, p (16) and writes p (8).  V-cycle, per node of a level:
-# the first sweep reads the inverse diagonal and b (16) and writes x (8); the
-# restriction reads b, x and the 4-array stencil (48) and writes a quarter of
-# a coarse value (2); correction and post-sweep read x, b, the inverse
-# diagonal, the stencil and a quarter of a coarse value (58) and write t (8).
-# The levels add up to 4/3 of the fine grid's nodes.
+# direction reads z, p (16) and writes p (8).  V-cycle, per node of a level
+# (the first sweep's x = om dinv b is recomputed, not stored): the
+# restriction reads b, the inverse diagonal and the 4-array stencil (48) and
+# writes a quarter of a coarse value (2); correction and post-sweep read the
+# same (48) and a quarter of a coarse value (2) and write t (8).  The levels
+# add up to 4/3 of the fine grid's nodes.
 OPT_CG_BYTES = 48.0 + 48.0 + 16.0 + 24.0
-OPT_VCYCLE_BYTES = (24.0 + 50.0 + 66.0) * 4.0 / 3.0
+OPT_VCYCLE_BYTES = (50.0 + 58.0) * 4.0 / 3.0
 OPT_BYTES_PER_NODE_ITER = OPT_CG_BYTES + OPT_VCYCLE_BYTES
 
 

@@ -33,6 +33,6 @@ def test_byte_counts():
         h = (nx // 2 + 1) / nx
         assert bench.bytes_3d_pair(nx) == pytest.approx(sum(a + b * h for a, b in fwd3 + adj3))
     assert bench.bytes_3d_pair(49) == pytest.approx(433.22, abs=0.01)
-    # optical CG iteration: A p 48, update 48, r.z 16, direction 24; V-cycle 140 per
-    # level node over 4/3 of the fine nodes
-    assert bench.OPT_BYTES_PER_NODE_ITER == pytest.approx(48 + 48 + 16 + 24 + (24 + 50 + 66) * 4 / 3)
+    # optical CG iteration: A p 48, update 48, r.z 16, direction 24; V-cycle 108 per
+    # level node (restriction 50, correction + post-sweep 58) over 4/3 of the fine nodes
+    assert bench.OPT_BYTES_PER_NODE_ITER == pytest.approx(48 + 48 + 16 + 24 + (50 + 58) * 4 / 3)
