@@ -159,33 +159,62 @@ __device__ void stage_small(const float2* __restrict__ src, float2* __restrict__
   }
 }
 
-// A stage of a prime radix R without a butterfly of its own: every thread
-// computes one output as a direct sum of R twiddled inputs.
+// A stage of an odd prime radix R without a butterfly of its own, in the
+// symmetric form of the odd butterflies: with the twiddled inputs x_r of
+// butterfly j, a_r = x_r + x_{R-r} and b_r = x_r - x_{R-r} (r = 1 .. H,
+// H = (R - 1) / 2), output q is x_0 + sum_r cos(2 pi r q / R) a_r
+// -+ i sum_r sin(2 pi r q / R) b_r and output R - q takes the other sign.  A
+// work item is one butterfly and one q in [0, H] (q = 0: the sum of all
+// inputs), so each pair of outputs shares its loads and its H products.
 template <bool INV>
 __device__ void stage_generic(const float2* __restrict__ src, float2* __restrict__ dst, const LineMap m, int n,
                               int Ns, int R, const float2* __restrict__ tw) {
-  const int nb = n / R, tstep = n / (Ns * R), total = m.nlines * n;
+  const int nb = n / R, tstep = n / (Ns * R), H = (R - 1) / 2, per = nb * (H + 1);
+  const int total = m.nlines * per;
   const unsigned es = unsigned(m.es), istep = unsigned(nb) * es;
-  const float rn = rcp(n), rnsr = rcp(Ns * R), rns = rcp(Ns), rlpg = rcp(m.lpg);
+  const float rper = rcp(per), rnb = rcp(nb), rns = rcp(Ns), rlpg = rcp(m.lpg);
   for (int t = threadIdx.x; t < total; t += blockDim.x) {
-    const int L = udiv(t, rn), o = t - L * n;
+    const int L = udiv(t, rper), it = t - L * per;
+    const int q = udiv(it, rnb), j = it - q * nb;   // butterflies fastest
     const unsigned off = line_off(m, unsigned(L), rlpg);
-    const int g = udiv(o, rnsr), rem = o - g * Ns * R, q = udiv(rem, rns), k = rem - q * Ns;
-    const int j = g * Ns + k;
-    const int e = k * tstep + q * nb;   // < n
+    const int k = j - udiv(j, rns) * Ns, kt = k * tstep;  // input twiddle step (r kt < n)
     const float2* s = src + (off + __umul24(unsigned(j), es));
-    float2 acc = make_float2(0.f, 0.f);
-    int idx = 0;
-    for (int r = 0; r < R; ++r) {
-      float2 w = tw[idx];
-      if (INV) w.y = -w.y;
+    // twiddled input r (conjugated twiddle for the inverse)
+    auto input = [&](int r) {
       const float2 x = s[unsigned(r) * istep];
-      acc.x += x.x * w.x - x.y * w.y;
-      acc.y += x.x * w.y + x.y * w.x;
-      idx += e;
-      if (idx >= n) idx -= n;
+      if (kt == 0) return x;
+      float2 w = tw[r * kt];
+      if (INV) w.y = -w.y;
+      return cmul(x, w);
+    };
+    const float2 x0 = input(0);
+    float2 A = x0, S = make_float2(0.f, 0.f);
+    int p = 0;   // (r q) mod R
+    for (int r = 1; r <= H; ++r) {
+      const float2 xr = input(r), xm = input(R - r);
+      const float2 a = cadd(xr, xm), b = csub(xr, xm);
+      if (q == 0) {
+        A = cadd(A, a);
+      } else {
+        p += q;
+        if (p >= R) p -= R;
+        const float2 w = tw[p * nb];   // cos(2 pi p / R) - i sin(2 pi p / R)
+        const float c = w.x, sn = -w.y;
+        A.x += c * a.x;
+        A.y += c * a.y;
+        S.x += sn * b.x;
+        S.y += sn * b.y;
+      }
     }
-    dst[off + __umul24(unsigned(o), es)] = acc;
+    const int base = (j - k) * R + k;
+    if (q == 0) {
+      dst[off + __umul24(unsigned(base), es)] = A;
+    } else {
+      // forward: y_q = A - i S, y_{R-q} = A + i S (the inverse swaps them)
+      const float2 iS = make_float2(-S.y, S.x);
+      dst[off + __umul24(unsigned(base + q * Ns), es)] = INV ? cadd(A, iS) : csub(A, iS);
+      dst[off + __umul24(unsigned(base + (R - q) * Ns), es)] = INV ? csub(A, iS) : cadd(A, iS);
+    }
   }
 }
 
