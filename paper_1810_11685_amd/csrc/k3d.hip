@@ -257,10 +257,58 @@ __device__ __forceinline__ void stage_ct(const float2* __restrict__ src, float2*
   }
 }
 
+// stage_generic for a prime length N transformed in one stage (no input
+// twiddles, one butterfly per line) with N a compile-time constant: the pair
+// loop unrolls and the work split folds.  Same operations in the same order.
+template <bool INV, int N>
+__device__ __forceinline__ void stage_prime_ct(const float2* __restrict__ src, float2* __restrict__ dst,
+                                               const LineMap m, const float2* __restrict__ tw) {
+  constexpr int H = (N - 1) / 2, PER = H + 1;
+  constexpr float RPER = 1.0f / float(PER);
+  const int total = m.nlines * PER;
+  const unsigned es = unsigned(m.es);
+  const float rlpg = rcp(m.lpg);
+  for (int t = threadIdx.x; t < total; t += blockDim.x) {
+    const int L = udiv(t, RPER), q = t - L * PER;
+    const unsigned off = line_off(m, unsigned(L), rlpg);
+    const float2* s = src + off;
+    float2 A = s[0], S = make_float2(0.f, 0.f);
+    if (q == 0) {
+#pragma unroll
+      for (int r = 1; r <= H; ++r) A = cadd(A, cadd(s[unsigned(r) * es], s[unsigned(N - r) * es]));
+      dst[off] = A;
+    } else {
+      int p = 0;   // (r q) mod N
+#pragma unroll
+      for (int r = 1; r <= H; ++r) {
+        const float2 xr = s[unsigned(r) * es], xm = s[unsigned(N - r) * es];
+        const float2 a = cadd(xr, xm), b = csub(xr, xm);
+        p += q;
+        if (p >= N) p -= N;
+        const float2 w = tw[p];   // cos(2 pi p / N) - i sin(2 pi p / N)
+        const float c = w.x, sn = -w.y;
+        A.x += c * a.x;
+        A.y += c * a.y;
+        S.x += sn * b.x;
+        S.y += sn * b.y;
+      }
+      const float2 iS = make_float2(-S.y, S.x);
+      dst[off + __umul24(unsigned(q), es)] = INV ? cadd(A, iS) : csub(A, iS);
+      dst[off + __umul24(unsigned(N - q), es)] = INV ? csub(A, iS) : cadd(A, iS);
+    }
+  }
+}
+
 // All stages of one axis (barrier after each); returns the buffer holding the
 // result (a or b).
 template <bool INV>
 __device__ float2* fft_axis(float2* a, float2* b, const LineMap m, const AxisPlan P, const float2* tw) {
+  if (P.n == 53) {
+    // prime: the axes of the paper's 37^3-node grid with its 8-cell PML
+    stage_prime_ct<INV, 53>(a, b, m, tw);
+    __syncthreads();
+    return b;
+  }
   if (P.n == 49) {
     // 7 x 7: the axes of the paper's 33^3-node grid with its 8-cell PML
     stage_ct<7, INV, 49, 1>(a, b, m, tw);
