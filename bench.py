@@ -488,6 +488,37 @@ def main():
                         "runs": runs}
         del plan3
         torch.cuda.empty_cache()
+        # the paper's other 3-D grid: 37^3 nodes plus the PML (53^3, a prime
+        # axis length), for one vector and the three illuminations
+        c37 = qi.config3d("vol37")
+        p37 = c37["params"]
+        n37, nt37, ns37 = p37["nx"] * p37["ny"] * p37["nz"], p37["nt"], p37["sensor_xyz"].shape[0]
+        plan37 = q.Plan3D(p37, c37["c0"], c37["rho0"])
+        plan37.set_graph(args.graph == "on")
+        runs37 = {}
+        with torch.cuda.stream(stream):
+            for b in (1, 3):
+                x3 = T(np.stack([c37["p0"]] * b))
+                r3 = T(qi.gaussian_field((b, nt37, ns37), 3707))
+                plan37.forward(x3, stream=stream)
+                plan37.adjoint(r3, stream=stream)
+                sync()
+                t = time.perf_counter()
+                for _ in range(2):
+                    plan37.forward(x3, stream=stream)
+                    plan37.adjoint(r3, stream=stream)
+                sync()
+                dt3 = (time.perf_counter() - t) / 2
+                gps3 = 2.0 * n37 * nt37 * b / dt3
+                runs37[f"B{b}"] = {"batch": b, "ms": round(dt3 * 1e3, 2), "grid_point_steps_per_s": round(gps3, 1),
+                                   "algorithmic_GB_s": round(gps3 / 2 * bytes_3d_pair(p37["nx"]) / 1e9, 1)}
+                log(f"3-D 53^3 Nt={nt37} forward+adjoint B={b}: {dt3 * 1e3:.1f} ms -> {gps3:.3e} grid-point-steps/s")
+                del x3, r3
+        out["vol37"] = {"workload": "3-D: 37^3 nodes plus an 8-cell PML (53^3 grid, prime axis length), Nt=292, "
+                                    "2145 detectors on two faces, lossy, forward + adjoint",
+                        "bytes_per_point_per_iterate_pair": bytes_3d_pair(p37["nx"]), "runs": runs37}
+        del plan37
+        torch.cuda.empty_cache()
 
     # ------------------------------------------------------------ optical operators
     # The diffusion-approximation solve (FP64 Jacobi-CG on the grid-matched P1

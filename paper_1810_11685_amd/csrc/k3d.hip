@@ -300,22 +300,28 @@ __device__ __forceinline__ void stage_prime_ct(const float2* __restrict__ src, f
 }
 
 // All stages of one axis (barrier after each); returns the buffer holding the
-// result (a or b).
-template <bool INV>
+// result (a or b).  AX selects the compile-time stages a kernel instance
+// carries (49 or 53, else none): each instance holds only its own, so one
+// length's unrolled code does not weigh on another's.
+template <bool INV, int AX>
 __device__ float2* fft_axis(float2* a, float2* b, const LineMap m, const AxisPlan P, const float2* tw) {
-  if (P.n == 53) {
-    // prime: the axes of the paper's 37^3-node grid with its 8-cell PML
-    stage_prime_ct<INV, 53>(a, b, m, tw);
-    __syncthreads();
-    return b;
+  if constexpr (AX == 49) {
+    if (P.n == 49) {
+      // 7 x 7: the axes of the paper's 33^3-node grid with its 8-cell PML
+      stage_ct<7, INV, 49, 1>(a, b, m, tw);
+      __syncthreads();
+      stage_ct<7, INV, 49, 7>(b, a, m, tw);
+      __syncthreads();
+      return a;
+    }
   }
-  if (P.n == 49) {
-    // 7 x 7: the axes of the paper's 33^3-node grid with its 8-cell PML
-    stage_ct<7, INV, 49, 1>(a, b, m, tw);
-    __syncthreads();
-    stage_ct<7, INV, 49, 7>(b, a, m, tw);
-    __syncthreads();
-    return a;
+  if constexpr (AX == 53) {
+    if (P.n == 53) {
+      // prime: the axes of the paper's 37^3-node grid with its 8-cell PML
+      stage_prime_ct<INV, 53>(a, b, m, tw);
+      __syncthreads();
+      return b;
+    }
   }
   // radices packed 8 bits a stage: a dynamic index into P would put P in scratch
   unsigned long long rad = 0;
@@ -393,7 +399,7 @@ __device__ __forceinline__ float& pc(float2* buf, int hp, int nx, int f, int j2,
   return (j2 & 1) ? z.y : z.x;
 }
 
-template <int MODE>
+template <int MODE, int AX>
 __global__ void __launch_bounds__(kRowMax) row3_kernel(const Launch3 L, int ntile, int chunk, int n) {
   int item, tile;
   if (!locate(L.nitems, ntile, chunk, item, tile)) return;
@@ -440,7 +446,7 @@ __global__ void __launch_bounds__(kRowMax) row3_kernel(const Launch3 L, int ntil
   float2* R = bufA;
   if (nin > 0) {
     const LineMap lm{nin * hp, nin * hp, 0, nx, 1};
-    R = fft_axis<true>(bufA, bufB, lm, M.px, tw);
+    R = fft_axis<true, AX>(bufA, bufB, lm, M.px, tw);
   }
   float2* O = (R == bufA) ? bufB : bufA;
 
@@ -577,7 +583,7 @@ __global__ void __launch_bounds__(kRowMax) row3_kernel(const Launch3 L, int ntil
 
   // outgoing fields -> half spectra of each line
   const LineMap lm{nout * hp, nout * hp, 0, nx, 1};
-  float2* Z = fft_axis<false>(O, R, lm, M.px, tw);
+  float2* Z = fft_axis<false, AX>(O, R, lm, M.px, tw);
   for (int t = tid; t < nout * ncol * hp; t += B) {
     const int oc = udiv(t, rhp), j = t - oc * hp, o = udiv(oc, rncol), c = oc - o * ncol;
     const float2* Zl = Z + (o * hp + j) * nx;
@@ -617,7 +623,7 @@ __device__ __forceinline__ int plane_code(int f, int code) {
   }
 }
 
-template <int MODE>
+template <int MODE, int AX>
 __global__ void __launch_bounds__(kPlaneMax) plane3_kernel(const Launch3 L, int ntile, int chunk, int code, int n) {
   int item, tile;
   if (!locate(L.nitems, ntile, chunk, item, tile)) return;
@@ -647,12 +653,12 @@ __global__ void __launch_bounds__(kPlaneMax) plane3_kernel(const Launch3 L, int 
   const LineMap my{nz * ct, ct, ny * ct, 1, ct};
   const LineMap mz{ny * ct, ny * ct, 0, 1, ny * ct};
   auto fwd = [&](float2* a, float2* b) {
-    float2* r = fft_axis<false>(a, b, my, M.py, twy);
-    return fft_axis<false>(r, r == a ? b : a, mz, M.pz, twz);
+    float2* r = fft_axis<false, AX>(a, b, my, M.py, twy);
+    return fft_axis<false, AX>(r, r == a ? b : a, mz, M.pz, twz);
   };
   auto inv = [&](float2* a, float2* b) {
-    float2* r = fft_axis<true>(a, b, mz, M.pz, twz);
-    return fft_axis<true>(r, r == a ? b : a, my, M.py, twy);
+    float2* r = fft_axis<true, AX>(a, b, mz, M.pz, twz);
+    return fft_axis<true, AX>(r, r == a ? b : a, my, M.py, twy);
   };
   auto load = [&](int f, float2* dst) {
     const float2* src = chunk_of(f);
@@ -695,7 +701,13 @@ __global__ void combine3_kernel(const Launch3 L) {
 // ---------------------------------------------------------------- launchers
 template <int MODE>
 static hipError_t row_t(const Launch3& L, int ntile, int chunk, int n, size_t lds, hipStream_t st) {
-  hipLaunchKernelGGL(row3_kernel<MODE>, dim3(chunk * kXcds), dim3(L.m.rthr), lds, st, L, ntile, chunk, n);
+  const dim3 g(chunk * kXcds), t(L.m.rthr);
+  if (L.m.px.n == 49)
+    hipLaunchKernelGGL((row3_kernel<MODE, 49>), g, t, lds, st, L, ntile, chunk, n);
+  else if (L.m.px.n == 53)
+    hipLaunchKernelGGL((row3_kernel<MODE, 53>), g, t, lds, st, L, ntile, chunk, n);
+  else
+    hipLaunchKernelGGL((row3_kernel<MODE, 0>), g, t, lds, st, L, ntile, chunk, n);
   return hipGetLastError();
 }
 
@@ -718,7 +730,13 @@ hipError_t launch_row3(int mode, const Launch3& L, int ntile, int chunk, int n, 
 
 template <int MODE>
 static hipError_t plane_t(const Launch3& L, int ntile, int chunk, int code, int n, size_t lds, hipStream_t st) {
-  hipLaunchKernelGGL(plane3_kernel<MODE>, dim3(chunk * kXcds), dim3(L.m.pthr), lds, st, L, ntile, chunk, code, n);
+  const dim3 g(chunk * kXcds), t(L.m.pthr);
+  if (L.m.py.n == 49 || L.m.pz.n == 49)
+    hipLaunchKernelGGL((plane3_kernel<MODE, 49>), g, t, lds, st, L, ntile, chunk, code, n);
+  else if (L.m.py.n == 53 || L.m.pz.n == 53)
+    hipLaunchKernelGGL((plane3_kernel<MODE, 53>), g, t, lds, st, L, ntile, chunk, code, n);
+  else
+    hipLaunchKernelGGL((plane3_kernel<MODE, 0>), g, t, lds, st, L, ntile, chunk, code, n);
   return hipGetLastError();
 }
 
@@ -748,15 +766,27 @@ static hipError_t allow(K* k, size_t bytes) {
                              int(bytes));
 }
 
+template <int MODE>
+static hipError_t allow_row(size_t bytes) {
+  hipError_t e = allow(&row3_kernel<MODE, 0>, bytes);
+  if (e == hipSuccess) e = allow(&row3_kernel<MODE, 49>, bytes);
+  if (e == hipSuccess) e = allow(&row3_kernel<MODE, 53>, bytes);
+  return e;
+}
+template <int MODE>
+static hipError_t allow_plane(size_t bytes) {
+  hipError_t e = allow(&plane3_kernel<MODE, 0>, bytes);
+  if (e == hipSuccess) e = allow(&plane3_kernel<MODE, 49>, bytes);
+  if (e == hipSuccess) e = allow(&plane3_kernel<MODE, 53>, bytes);
+  return e;
+}
+
 hipError_t k3d_allow_lds(size_t bytes) {
-  const hipError_t es[] = {allow(&row3_kernel<R3_F1>, bytes),      allow(&row3_kernel<R3_F2>, bytes),
-                           allow(&row3_kernel<R3_F2L>, bytes),     allow(&row3_kernel<R3_F3>, bytes),
-                           allow(&row3_kernel<R3_A1>, bytes),      allow(&row3_kernel<R3_A1L>, bytes),
-                           allow(&row3_kernel<R3_A2>, bytes),      allow(&row3_kernel<R3_A3>, bytes),
-                           allow(&row3_kernel<R3_FWD1>, bytes),    allow(&row3_kernel<R3_INV1>, bytes),
-                           allow(&plane3_kernel<P3_GRADP1>, bytes), allow(&plane3_kernel<P3_GRADM2>, bytes),
-                           allow(&plane3_kernel<P3_FRAC>, bytes),   allow(&plane3_kernel<P3_GRADP2>, bytes),
-                           allow(&plane3_kernel<P3_APPLY>, bytes)};
+  const hipError_t es[] = {allow_row<R3_F1>(bytes),       allow_row<R3_F2>(bytes),        allow_row<R3_F2L>(bytes),
+                           allow_row<R3_F3>(bytes),       allow_row<R3_A1>(bytes),        allow_row<R3_A1L>(bytes),
+                           allow_row<R3_A2>(bytes),       allow_row<R3_A3>(bytes),        allow_row<R3_FWD1>(bytes),
+                           allow_row<R3_INV1>(bytes),     allow_plane<P3_GRADP1>(bytes),  allow_plane<P3_GRADM2>(bytes),
+                           allow_plane<P3_FRAC>(bytes),   allow_plane<P3_GRADP2>(bytes),  allow_plane<P3_APPLY>(bytes)};
   for (hipError_t e : es)
     if (e != hipSuccess) return e;
   return hipSuccess;
