@@ -273,20 +273,28 @@ __device__ __forceinline__ float2* fft_stages(float2* a, float2* b, int nlines, 
 // FFT of `nlines` lines: compile-time plan for the common lengths, the
 // runtime plan otherwise.  Same contract as fft_lines; row lines have stride
 // lstride(n), column lines (COL) col_lstride(n).
-template <bool COL>
+// NF != 0: a kernel instance for lines of length NF carries that compile-time
+// plan only (and the runtime plan as a fallback), so the other lengths'
+// unrolled code does not weigh on it.
+template <bool COL, int NF = 0>
 __device__ __forceinline__ float2* fft_any(float2* a, float2* b, int nlines, int n, int ls, uint32_t rad,
                                            int nst, const float2* tw) {
+  if constexpr (NF != 0) {
+    if (n == NF) return fft_c<NF, COL ? col_lstride(NF) : lstride(NF), 0, 1>(a, b, nlines, tw);
+    return fft_lines(a, b, nlines, n, ls, rad, nst, tw);
+  } else {
 #define QPAT_FFT_CASE(N) \
   case N: return fft_c<N, COL ? col_lstride(N) : lstride(N), 0, 1>(a, b, nlines, tw);
-  switch (n) {
-    QPAT_FFT_CASE(128)
-    QPAT_FFT_CASE(256)
-    QPAT_FFT_CASE(384)
-    QPAT_FFT_CASE(512)
-    QPAT_FFT_CASE(1024)
-    default: return fft_lines(a, b, nlines, n, ls, rad, nst, tw);
-  }
+    switch (n) {
+      QPAT_FFT_CASE(128)
+      QPAT_FFT_CASE(256)
+      QPAT_FFT_CASE(384)
+      QPAT_FFT_CASE(512)
+      QPAT_FFT_CASE(1024)
+      default: return fft_lines(a, b, nlines, n, ls, rad, nst, tw);
+    }
 #undef QPAT_FFT_CASE
+  }
 }
 
 // ---------------------------------------------------------------- packing
@@ -592,7 +600,7 @@ __device__ __forceinline__ Work shift_work(const Work& w, long long off) {
 // branch, so the loads of all iterations issue back to back.
 #define FOR_K_LD _Pragma("unroll") for (int k = 0; k < kMaxPer; ++k) if (k * B < tot)
 
-template <int MODE, bool U>
+template <int MODE, bool U, int NF>
 __global__ void __launch_bounds__(kMaxThreads)
 row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
   constexpr int BM = MODE & ~RM_X;
@@ -642,7 +650,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     put_pair(S, bufA, M);
     put_tw(TW, tw, nx);
     __syncthreads();
-    float2* r = fft_any<false>(bufA, bufB, rt, nx, LS, M.radx, M.nstx, tw);
+    float2* r = fft_any<false, NF>(bufA, bufB, rt, nx, LS, M.radx, M.nstx, tw);
     float2* o = other(r, bufA, bufB);
     FOR_K {
       const int it = threadIdx.x + k * B;
@@ -658,7 +666,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
       }
     }
     __syncthreads();
-    r = fft_any<false>(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
+    r = fft_any<false, NF>(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
     store_pair_spectra(r, M, W.s0, W.s1, tile);
   } else if constexpr (BM == RM_F2 || BM == RM_F2L) {
     // eq num-rho with the additive source of eq s1 (dt s = p0 / (2 d c^2), d = 2)
@@ -702,7 +710,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     float2* r = nullptr;
     float2* o = bufA;
     if (!skip) {
-      r = fft_any<false>(bufA, bufB, rt, nx, LS, M.radx, M.nstx, tw);
+      r = fft_any<false, NF>(bufA, bufB, rt, nx, LS, M.radx, M.nstx, tw);
       o = other(r, bufA, bufB);
     }
     FOR_K {
@@ -741,12 +749,12 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     if constexpr (BM == RM_F2L) taps_put(T, false);
     __syncthreads();
     if constexpr (BM == RM_F2) {
-      r = fft_any<false>(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
+      r = fft_any<false, NF>(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
       store_rowpair_spectra(r, M, W.s0, tile);
       store_rowpair_spectra(r + (rt / 2) * LS, M, W.s1, tile);
     } else {
       if (!(flags & FL_NO_SENSORS)) sensor_partials(M, T, o, y0, W.part, n + 1);
-      r = fft_any<false>(o, other(o, bufA, bufB), rt / 2, nx, LS, M.radx, M.nstx, tw);
+      r = fft_any<false, NF>(o, other(o, bufA, bufB), rt / 2, nx, LS, M.radx, M.nstx, tw);
       store_rowpair_spectra(r, M, W.s0, tile);
     }
   } else if constexpr (BM == RM_F3) {
@@ -776,7 +784,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     put_tw(TW, tw, nx);
     __syncthreads();
     taps_fetch(T, M, nullptr, 0);
-    float2* r = fft_any<false>(bufA, bufB, rt, nx, LS, M.radx, M.nstx, tw);
+    float2* r = fft_any<false, NF>(bufA, bufB, rt, nx, LS, M.radx, M.nstx, tw);
     float2* o = other(r, bufA, bufB);
     FOR_K {
       const int it = threadIdx.x + k * B;
@@ -798,7 +806,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     taps_put(T, false);
     __syncthreads();
     if (!(flags & FL_NO_SENSORS)) sensor_partials(M, T, o, y0, W.part, n + 1);
-    r = fft_any<false>(o, other(o, bufA, bufB), rt / 2, nx, LS, M.radx, M.nstx, tw);
+    r = fft_any<false, NF>(o, other(o, bufA, bufB), rt / 2, nx, LS, M.radx, M.nstx, tw);
     store_rowpair_spectra(r, M, W.s0, tile);
   } else if constexpr (BM == RM_A1 || BM == RM_A1L) {
     // transpose of eqs num-m and num-p: p* += M^T r_{n+1}; q = c^2 p*
@@ -860,7 +868,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     taps_fetch(T, M, W.part, n + 1);
     float2* r = bufA;
     if (!first) {
-      r = fft_any<false>(bufA, bufB, half, nx, LS, M.radx, M.nstx, tw);
+      r = fft_any<false, NF>(bufA, bufB, half, nx, LS, M.radx, M.nstx, tw);
       // p* = -(grad_x^- g_x + grad_y^- g_y): negate the (conjugated) inverse
       for (int it = threadIdx.x; it < half * LS; it += B) {
         const float2 z = r[it];
@@ -903,11 +911,11 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     }
     __syncthreads();
     if constexpr (BM == RM_A1) {
-      r = fft_any<false>(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
+      r = fft_any<false, NF>(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
       store_rowpair_spectra(r, M, W.s0, tile);
       store_rowpair_spectra(r + half * LS, M, W.s1, tile);
     } else if (n != -1) {
-      r = fft_any<false>(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
+      r = fft_any<false, NF>(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
       store_pair_spectra(r, M, W.s0, W.s1, tile);
     }
   } else if constexpr (BM == RM_A2) {
@@ -948,7 +956,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     put_rowpair(S1, bufA + (rt / 2) * LS, M);
     put_tw(TW, tw, nx);
     __syncthreads();
-    float2* r = fft_any<false>(bufA, bufB, rt, nx, LS, M.radx, M.nstx, tw);
+    float2* r = fft_any<false, NF>(bufA, bufB, rt, nx, LS, M.radx, M.nstx, tw);
     float2* o = other(r, bufA, bufB);
     FOR_K {
       const int it = threadIdx.x + k * B;
@@ -970,7 +978,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     }
     __syncthreads();
     if (n != -1) {
-      r = fft_any<false>(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
+      r = fft_any<false, NF>(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
       store_pair_spectra(r, M, W.s0, W.s1, tile);
     }
   } else if constexpr (BM == RM_A3) {
@@ -997,7 +1005,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     put_pair(S, bufA, M);
     put_tw(TW, tw, nx);
     __syncthreads();
-    float2* r = fft_any<false>(bufA, bufB, rt, nx, LS, M.radx, M.nstx, tw);
+    float2* r = fft_any<false, NF>(bufA, bufB, rt, nx, LS, M.radx, M.nstx, tw);
     float2* o = other(r, bufA, bufB);
     FOR_K {
       const int it = threadIdx.x + k * B;
@@ -1013,7 +1021,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
       }
     }
     __syncthreads();
-    r = fft_any<false>(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
+    r = fft_any<false, NF>(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
     store_pair_spectra(r, M, W.s0, W.s1, tile);
   } else if constexpr (BM == RM_FWD1) {
     const float* src = X.in;
@@ -1036,7 +1044,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     }
     put_tw(TW, tw, nx);
     __syncthreads();
-    float2* r = fft_any<false>(bufA, bufB, rt / 2, nx, LS, M.radx, M.nstx, tw);
+    float2* r = fft_any<false, NF>(bufA, bufB, rt / 2, nx, LS, M.radx, M.nstx, tw);
     store_rowpair_spectra(r, M, W.s0, tile);
   } else if constexpr (BM == RM_INV1) {
     RowPairRegs S0;
@@ -1046,7 +1054,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     put_rowpair(S0, bufA, M);
     put_tw(TW, tw, nx);
     __syncthreads();
-    float2* r = fft_any<false>(bufA, bufB, rt / 2, nx, LS, M.radx, M.nstx, tw);
+    float2* r = fft_any<false, NF>(bufA, bufB, rt / 2, nx, LS, M.radx, M.nstx, tw);
     float* dst = X.out;
     for (int it = threadIdx.x; it < tot; it += B) {
       const int j = fdiv(it, nx, rnx), x = it - j * nx;
@@ -1091,7 +1099,7 @@ __device__ constexpr int kColOut[kColModes] = {2, 2, 2, 2, 1, 1};
 
 // Column pass for any supported line length (runtime or compile-time FFT
 // plan): the tile goes through LDS between every phase.
-template <int CM>
+template <int CM, int NF>
 __device__ __forceinline__ void col_generic(const Medium& M, const Work& W, int tile, int mcode, float2* lds) {
   constexpr int nin = kColIn[CM], nout = kColOut[CM];
   const int ny = M.ny, nxh = M.nxh, ct = M.ct, ls = col_lstride(ny);
@@ -1167,7 +1175,7 @@ __device__ __forceinline__ void col_generic(const Medium& M, const Work& W, int 
   }
   put_tw(TW, tw, ny);
   __syncthreads();
-  float2* r = fft_any<true>(bufA, bufB, nin * ct, ny, ls, M.rady, M.nsty, tw);
+  float2* r = fft_any<true, NF>(bufA, bufB, nin * ct, ny, ls, M.rady, M.nsty, tw);
   float2* o = other(r, bufA, bufB);
   FOR_K {
     const int it = threadIdx.x + k * B;
@@ -1226,7 +1234,7 @@ __device__ __forceinline__ void col_generic(const Medium& M, const Work& W, int 
     }
   }
   __syncthreads();
-  r = fft_any<true>(o, other(o, bufA, bufB), nout * ct, ny, ls, M.rady, M.nsty, tw);
+  r = fft_any<true, NF>(o, other(o, bufA, bufB), nout * ct, ny, ls, M.rady, M.nsty, tw);
   for (unsigned it = threadIdx.x; it < nout * ncol; it += B) {
     const bool f = it >= ncol;
     const unsigned rem = f ? it - ncol : it, w = rem & (rc - 1), ty = rem >> lsh;
@@ -1485,7 +1493,7 @@ __device__ __forceinline__ void col_fused(const Medium& M, const Work& W, int ti
   }
 }
 
-template <bool U, int CM>
+template <bool U, int CM, int NF>
 __global__ void __launch_bounds__(kMaxThreads)
 col_kernel(const Launch L, int ntile, int chunk, int mcode_arg, int n) {
   const int mcode = CM == CM_APPLY ? mcode_arg : kColCode[CM];
@@ -1503,15 +1511,22 @@ col_kernel(const Launch L, int ntile, int chunk, int mcode_arg, int n) {
       return;                                                            \
     }                                                                    \
     break;
-  switch (M.ny) {
-    QPAT_COL_CASE(128)
-    QPAT_COL_CASE(256)
-    QPAT_COL_CASE(512)
-    QPAT_COL_CASE(1024)
-    default: break;
+  if constexpr (NF == 128 || NF == 256 || NF == 512 || NF == 1024) {
+    switch (M.ny) {
+      QPAT_COL_CASE(NF)
+      default: break;
+    }
+  } else if constexpr (NF == 0) {
+    switch (M.ny) {
+      QPAT_COL_CASE(128)
+      QPAT_COL_CASE(256)
+      QPAT_COL_CASE(512)
+      QPAT_COL_CASE(1024)
+      default: break;
+    }
   }
 #undef QPAT_COL_CASE
-  col_generic<CM>(M, W, tile, mcode, lds);
+  col_generic<CM, NF>(M, W, tile, mcode, lds);
 }
 
 // ---------------------------------------------------------------- sensor data
@@ -1589,15 +1604,28 @@ __global__ void __launch_bounds__(kBlock) dot_final(const double* __restrict__ p
 }
 
 // ---------------------------------------------------------------- launchers
+// Uniform launches pick the kernel instance for their row / column length
+// (lengths with a compile-time plan); mixed batches take the all-length one.
+// 1024-point columns stay on the all-length instance: the dedicated one
+// measured 5-10% slower at 1024^2 x 8.
+#define QPAT_FOR_LENGTHS(X) X(128) X(256) X(384) X(512) X(1024)
+#define QPAT_FOR_COL_LENGTHS(X) X(128) X(256) X(384) X(512)
+
 template <int MODE>
 static hipError_t launch_row_t(const Launch& L, bool uniform, int ntile, int chunk, int nblocks, int threads,
                                size_t lds, int n, int flags, hipStream_t st) {
-  if (uniform)
-    hipLaunchKernelGGL((row_kernel<MODE, true>), dim3(nblocks), dim3(threads), lds, st, L, ntile, chunk, n,
-                       flags);
-  else
-    hipLaunchKernelGGL((row_kernel<MODE, false>), dim3(nblocks), dim3(threads), lds, st, L, ntile, chunk, n,
-                       flags);
+  const dim3 g(nblocks), t(threads);
+  if (uniform) {
+#define QPAT_ROW_LEN(N) \
+  case N: hipLaunchKernelGGL((row_kernel<MODE, true, N>), g, t, lds, st, L, ntile, chunk, n, flags); break;
+    switch (L.m.nx) {
+      QPAT_FOR_LENGTHS(QPAT_ROW_LEN)
+      default: hipLaunchKernelGGL((row_kernel<MODE, true, 0>), g, t, lds, st, L, ntile, chunk, n, flags); break;
+    }
+#undef QPAT_ROW_LEN
+  } else {
+    hipLaunchKernelGGL((row_kernel<MODE, false, 0>), g, t, lds, st, L, ntile, chunk, n, flags);
+  }
   return hipGetLastError();
 }
 
@@ -1628,11 +1656,18 @@ hipError_t launch_row(int mode, const Launch& L, bool uniform, int ntile, int ch
 template <int CM>
 static hipError_t launch_col_t(int mcode, const Launch& L, bool uniform, int ntile, int chunk, int nblocks,
                                int threads, size_t lds, int n, hipStream_t st) {
-  if (uniform)
-    hipLaunchKernelGGL((col_kernel<true, CM>), dim3(nblocks), dim3(threads), lds, st, L, ntile, chunk, mcode, n);
-  else
-    hipLaunchKernelGGL((col_kernel<false, CM>), dim3(nblocks), dim3(threads), lds, st, L, ntile, chunk, mcode,
-                       n);
+  const dim3 g(nblocks), t(threads);
+  if (uniform) {
+#define QPAT_COL_LEN(N) \
+  case N: hipLaunchKernelGGL((col_kernel<true, CM, N>), g, t, lds, st, L, ntile, chunk, mcode, n); break;
+    switch (L.m.ny) {
+      QPAT_FOR_COL_LENGTHS(QPAT_COL_LEN)
+      default: hipLaunchKernelGGL((col_kernel<true, CM, 0>), g, t, lds, st, L, ntile, chunk, mcode, n); break;
+    }
+#undef QPAT_COL_LEN
+  } else {
+    hipLaunchKernelGGL((col_kernel<false, CM, 0>), g, t, lds, st, L, ntile, chunk, mcode, n);
+  }
   return hipGetLastError();
 }
 
@@ -1650,21 +1685,30 @@ hipError_t launch_col(int cm, int mcode, const Launch& L, bool uniform, int ntil
 }
 
 // Let every row / column pass kernel use up to `bytes` of dynamic LDS.
+template <typename K>
+static hipError_t allow_fn(K* k, size_t bytes) {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             int(bytes));
+}
 template <int MODE>
 static hipError_t allow_row(size_t bytes) {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&row_kernel<MODE, true>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&row_kernel<MODE, false>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
+  hipError_t e = allow_fn(&row_kernel<MODE, false, 0>, bytes);
+  if (e == hipSuccess) e = allow_fn(&row_kernel<MODE, true, 0>, bytes);
+#define QPAT_ALLOW_ROW(N) \
+  if (e == hipSuccess) e = allow_fn(&row_kernel<MODE, true, N>, bytes);
+  QPAT_FOR_LENGTHS(QPAT_ALLOW_ROW)
+#undef QPAT_ALLOW_ROW
+  return e;
 }
 template <int CM>
 static hipError_t allow_col(size_t bytes) {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&col_kernel<true, CM>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&col_kernel<false, CM>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
+  hipError_t e = allow_fn(&col_kernel<false, CM, 0>, bytes);
+  if (e == hipSuccess) e = allow_fn(&col_kernel<true, CM, 0>, bytes);
+#define QPAT_ALLOW_COL(N) \
+  if (e == hipSuccess) e = allow_fn(&col_kernel<true, CM, N>, bytes);
+  QPAT_FOR_COL_LENGTHS(QPAT_ALLOW_COL)
+#undef QPAT_ALLOW_COL
+  return e;
 }
 
 hipError_t kernels_allow_lds(size_t bytes) {
