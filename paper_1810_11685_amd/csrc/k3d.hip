@@ -299,30 +299,11 @@ __device__ __forceinline__ void stage_prime_ct(const float2* __restrict__ src, f
   }
 }
 
-// All stages of one axis (barrier after each); returns the buffer holding the
-// result (a or b).  AX selects the compile-time stages a kernel instance
-// carries (49 or 53, else none): each instance holds only its own, so one
-// length's unrolled code does not weigh on another's.
-template <bool INV, int AX>
-__device__ float2* fft_axis(float2* a, float2* b, const LineMap m, const AxisPlan P, const float2* tw) {
-  if constexpr (AX == 49) {
-    if (P.n == 49) {
-      // 7 x 7: the axes of the paper's 33^3-node grid with its 8-cell PML
-      stage_ct<7, INV, 49, 1>(a, b, m, tw);
-      __syncthreads();
-      stage_ct<7, INV, 49, 7>(b, a, m, tw);
-      __syncthreads();
-      return a;
-    }
-  }
-  if constexpr (AX == 53) {
-    if (P.n == 53) {
-      // prime: the axes of the paper's 37^3-node grid with its 8-cell PML
-      stage_prime_ct<INV, 53>(a, b, m, tw);
-      __syncthreads();
-      return b;
-    }
-  }
+// The runtime plan of an axis: every stage through stage_small or
+// stage_generic (barrier after each); returns the buffer holding the result.
+template <bool INV>
+__device__ __forceinline__ float2* fft_axis_rt(float2* a, float2* b, const LineMap m, const AxisPlan P,
+                                               const float2* tw) {
   // radices packed 8 bits a stage: a dynamic index into P would put P in scratch
   unsigned long long rad = 0;
 #pragma unroll
@@ -348,6 +329,31 @@ __device__ float2* fft_axis(float2* a, float2* b, const LineMap m, const AxisPla
     Ns *= R;
   }
   return s;
+}
+
+// All stages of one axis (barrier after each); returns the buffer holding the
+// result (a or b).  AX is the axis length of a kernel instance whose every
+// transformed axis has that length (49 or 53: compile-time stages only, no
+// runtime plan in the instance); AX = 0 runs the runtime plan.  The launchers
+// pick AX from the plan's axis lengths.
+template <bool INV, int AX>
+__device__ __forceinline__ float2* fft_axis(float2* a, float2* b, const LineMap m, const AxisPlan P,
+                                            const float2* tw) {
+  if constexpr (AX == 49) {
+    // 7 x 7: the axes of the paper's 33^3-node grid with its 8-cell PML
+    stage_ct<7, INV, 49, 1>(a, b, m, tw);
+    __syncthreads();
+    stage_ct<7, INV, 49, 7>(b, a, m, tw);
+    __syncthreads();
+    return a;
+  } else if constexpr (AX == 53) {
+    // prime: the axes of the paper's 37^3-node grid with its 8-cell PML
+    stage_prime_ct<INV, 53>(a, b, m, tw);
+    __syncthreads();
+    return b;
+  } else {
+    return fft_axis_rt<INV>(a, b, m, P, tw);
+  }
 }
 
 // ---------------------------------------------------------------- block -> (item, tile)
@@ -702,6 +708,7 @@ __global__ void combine3_kernel(const Launch3 L) {
 template <int MODE>
 static hipError_t row_t(const Launch3& L, int ntile, int chunk, int n, size_t lds, hipStream_t st) {
   const dim3 g(chunk * kXcds), t(L.m.rthr);
+  // an instance with compile-time stages only for its own x length
   if (L.m.px.n == 49)
     hipLaunchKernelGGL((row3_kernel<MODE, 49>), g, t, lds, st, L, ntile, chunk, n);
   else if (L.m.px.n == 53)
@@ -731,9 +738,10 @@ hipError_t launch_row3(int mode, const Launch3& L, int ntile, int chunk, int n, 
 template <int MODE>
 static hipError_t plane_t(const Launch3& L, int ntile, int chunk, int code, int n, size_t lds, hipStream_t st) {
   const dim3 g(chunk * kXcds), t(L.m.pthr);
-  if (L.m.py.n == 49 || L.m.pz.n == 49)
+  // an instance with compile-time stages only when both transformed axes have its length
+  if (L.m.py.n == 49 && L.m.pz.n == 49)
     hipLaunchKernelGGL((plane3_kernel<MODE, 49>), g, t, lds, st, L, ntile, chunk, code, n);
-  else if (L.m.py.n == 53 || L.m.pz.n == 53)
+  else if (L.m.py.n == 53 && L.m.pz.n == 53)
     hipLaunchKernelGGL((plane3_kernel<MODE, 53>), g, t, lds, st, L, ntile, chunk, code, n);
   else
     hipLaunchKernelGGL((plane3_kernel<MODE, 0>), g, t, lds, st, L, ntile, chunk, code, n);
