@@ -75,6 +75,9 @@ CASES = [
     (13, 7, 10, 30, 0.0, 1.5, 2, (6, 3)),     # lossless, prime 13 and 7
     (24, 20, 18, 40, 0.75, 1.5, 4, (16, 5)),
     (10, 15, 6, 25, 2.0, 1.5, 2, (2, 4)),      # radix 5
+    (10, 49, 49, 8, 0.75, 1.5, 4, None),       # compile-time 49-point plane passes, runtime-plan rows
+    (9, 53, 53, 6, 0.75, 1.5, 4, None),        # compile-time 53-point plane passes, runtime-plan rows
+    (49, 12, 10, 8, 0.75, 1.5, 3, None),       # compile-time 49-point rows, runtime-plan planes
 ]
 
 
