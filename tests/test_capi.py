@@ -149,3 +149,14 @@ def test_optical_create_checks(q):
     assert L.qpat_optical_create(4, 4, 1e-4, 65, ctypes.byref(h)) == 1
     assert L.qpat_optical_create(4, 4, 1e-4, 1, None) == 1
     assert L.qpat_optical_forward(None, None, None, None, None, 1, 1e-8, 10, None, None) == 1
+
+
+def test_build_lists_every_source_once():
+    """Every translation unit under csrc/ is compiled, each to its own object
+    (optical.hip and optical.cpp share a stem, so object names keep the
+    extension)."""
+    import os
+    from paper_1810_11685_amd import build as B
+    units = sorted(f for f in os.listdir(B.CSRC) if f.endswith((".hip", ".cpp")))
+    assert sorted(B.SOURCES) == units
+    assert len({s + ".o" for s in B.SOURCES}) == len(B.SOURCES)
