@@ -78,6 +78,7 @@ CASES = [
     (10, 49, 49, 8, 0.75, 1.5, 4, None),       # compile-time 49-point plane passes, runtime-plan rows
     (9, 53, 53, 6, 0.75, 1.5, 4, None),        # compile-time 53-point plane passes, runtime-plan rows
     (49, 12, 10, 8, 0.75, 1.5, 3, None),       # compile-time 49-point rows, runtime-plan planes
+    (53, 10, 9, 8, 0.75, 1.5, 3, None),        # compile-time 53-point rows, runtime-plan planes
 ]
 
 
