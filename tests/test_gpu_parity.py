@@ -73,6 +73,9 @@ CASES = [
     (48, 96, 100, 2.0, 1.5, 5),     # radix-3 rows and columns
     (64, 32, 80, 0.0, 1.5, 6),      # lossless
     (128, 128, 150, 0.75, 1.5, 20),
+    (128, 48, 80, 0.75, 1.5, 6),    # 128-point row instance, all-length column kernel
+    (48, 256, 60, 0.75, 1.5, 8),    # all-length row kernel, 256-point column instance
+    (384, 256, 340, 0.75, 1.5, 10), # 384-point rows, 256-point columns (the wave reaches the ring)
 ]
 
 
