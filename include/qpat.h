@@ -3,10 +3,10 @@
  *
  * The library computes the discrete acoustic forward operator H_a of
  * Javaherian & Holman, "Direct quantitative photoacoustic tomography for
- * realistic acoustic media" (arXiv 1810.11685), Section 3.3.3 and Definition 4
+ * realistic acoustic media" (arXiv 1810.11685), Section 3.2.3 and Definition 4
  * (k-space PSTD solve of eqs num-vel, num-rho, num-p, num-m with the two-step
  * additive source of eq s1), and its discretise-then-adjoint H_a^* (Section
- * 3.3.4, Lemma 2), on a 2-D grid, in FP32, with hand-written HIP kernels for
+ * 3.2.4, Lemma 2), on a 2-D grid, in FP32, with hand-written HIP kernels for
  * gfx950.
  *
  * Conventions shared by every entry point
@@ -84,7 +84,7 @@ typedef struct {
   const double* sensor_xy;
 } qpat_params;
 
-/* Spectral operators for qpat_apply (Section 3.3.2): k-space staggered
+/* Spectral operators for qpat_apply (Section 3.2.2): k-space staggered
  * gradients of eq grr and the fractional Laplacians Y_dis, Y_abs. */
 typedef enum {
   QPAT_OP_DX_PLUS = 0,  /* d/dx^+ : F^-1 { i kx e^{+i kx dx/2} sinc(c_ref k dt/2) F } */
@@ -265,8 +265,8 @@ qpat_status qpat_tv_value(qpat_tv tv, const float* x, double beta, int32_t batch
 /* y = a x + b y over n device floats (the vector updates of Algorithm 4). */
 qpat_status qpat_axpby(int64_t n, float a, const float* x, float b, float* y, qpat_stream stream);
 
-/* ---- 3-D solver (Section 3.3.3 with d = 3: velocity and density with three
- * components each, so the stacked state z_n of Section 3.3.4 holds 7N values,
+/* ---- 3-D solver (Section 3.2.3 with d = 3: velocity and density with three
+ * components each, so the stacked state z_n of Section 3.2.4 holds 7N values,
  * and the source of eq s1 puts p0 / (6 c0^2) into each density component at
  * n = -1 and 0).  Conventions follow the 2-D solver axis by axis: fields are
  * [nz][ny][nx] (x fastest), node (k, j, i) at ((i - nx/2) dx, (j - ny/2) dy,

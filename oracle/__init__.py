@@ -7,13 +7,13 @@ calls it, and this package imports nothing from the library.
 Paper: Javaherian & Holman, "Direct quantitative photoacoustic tomography for
 realistic acoustic media" (arXiv 1810.11685).
 
-* `kspace.forward`   - Section 3.3.3 ("Numerical computation of the acoustic
+* `kspace.forward`   - Section 3.2.3 ("Numerical computation of the acoustic
   forward operator"): the k-space PSTD loop (eqs num-vel, num-rho, num-p,
   num-m) with the additive source of eq s1, discretised operators of
-  Section 3.3.2 (eq grr, Y_abs, Y_dis, eq dis-pml).
+  Section 3.2.2 (eq grr, Y_abs, Y_dis, eq dis-pml).
 * `kspace.adjoint`   - exact transpose of `forward` (reverse mode, step by step).
 * `kspace.adjoint_paper` - the paper's own adjoint recursion, eq t41 with the
-  pairwise-summed adjoint source of eq adj_data (Section 3.3.4, Lemma 2).
+  pairwise-summed adjoint source of eq adj_data (Section 3.2.4, Lemma 2).
 * `dense`            - brute force on tiny grids: explicit DFT matrices, the
   block one-step matrix T of eq Tprod (with D, E, G of eqs D4, E, G4) and the
   dense H_a of Definition 4, for cross-checking the three routines above.

@@ -108,7 +108,7 @@ def sensor_taps(prm: dict):
 
 
 class Operators:
-    """All discretised operators and medium diagonals of Section 3.3.2."""
+    """All discretised operators and medium diagonals of Section 3.2.2."""
 
     def __init__(self, prm: dict, c0: np.ndarray, rho0: np.ndarray):
         nx, ny = prm["nx"], prm["ny"]
@@ -187,7 +187,7 @@ class Operators:
 
 def forward(prm: dict, c0, rho0, p0, *, ops: Operators | None = None, record=None,
             inject=(-1, 0), nsteps: int | None = None) -> np.ndarray:
-    """H_a p0: sensor data [nt, ns] (Section 3.3.3, steps 1-4).
+    """H_a p0: sensor data [nt, ns] (Section 3.2.3, steps 1-4).
 
     The initial pressure enters as the additive mass source of eq s1,
     dt * s = p0 / (2 d c0^2), at iterates n = -1 and 0 (`inject` can change the
@@ -234,7 +234,7 @@ def forward(prm: dict, c0, rho0, p0, *, ops: Operators | None = None, record=Non
 def adjoint(prm: dict, c0, rho0, r, *, ops: Operators | None = None, record=None) -> np.ndarray:
     """H_a^T r by reverse-mode transposition of `forward`, one linear
     operation at a time, under the unweighted Euclidean inner products of
-    R^N and R^{Ns Nt} (discretise-then-adjoint, Section 3.3.4).
+    R^N and R^{Ns Nt} (discretise-then-adjoint, Section 3.2.4).
 
     Transposes used: the medium, PML and source maps are diagonal;
     (F^-1 diag(m) F)^T = F^-1 diag(conj m) F for a real operator, hence

@@ -2,9 +2,9 @@
 
 TEST INFRASTRUCTURE (see the package docstring): slow, literal, FP64.
 
-The scheme is the one of Section 3.3.3 with d = 3: three velocity and three
+The scheme is the one of Section 3.2.3 with d = 3: three velocity and three
 density components, so the stacked state z_n of the paper holds 7N values
-(Section 3.3.4), and the additive source of eq s1 puts p0 / (2 d c^2) with
+(Section 3.2.4), and the additive source of eq s1 puts p0 / (2 d c^2) with
 d = 3 into each density component at iterates n = -1 and 0.
 
 The conventions of the 2-D oracle carry over axis by axis: fields are
@@ -65,7 +65,7 @@ def sensor_taps(prm: dict):
 
 
 class Operators:
-    """Discretised operators and medium diagonals of Section 3.3.2 in 3-D."""
+    """Discretised operators and medium diagonals of Section 3.2.2 in 3-D."""
 
     def __init__(self, prm: dict, c0: np.ndarray, rho0: np.ndarray):
         nx, ny, nz = prm["nx"], prm["ny"], prm["nz"]
@@ -137,7 +137,7 @@ class Operators:
 
 def forward(prm: dict, c0, rho0, p0, *, ops: Operators | None = None, record=None,
             nsteps: int | None = None) -> np.ndarray:
-    """H_a p0 in 3-D: sensor data [nt, ns] (Section 3.3.3, steps 1-4, d = 3).
+    """H_a p0 in 3-D: sensor data [nt, ns] (Section 3.2.3, steps 1-4, d = 3).
     `record(n, state)` receives v^{n+1/2} (list of 3), rho^{n+1} (list of 3)
     and p^{n+1} after every iterate."""
     op = Operators(prm, c0, rho0) if ops is None else ops
@@ -176,7 +176,7 @@ def forward(prm: dict, c0, rho0, p0, *, ops: Operators | None = None, record=Non
 
 def adjoint(prm: dict, c0, rho0, r, *, ops: Operators | None = None) -> np.ndarray:
     """H_a^T r in 3-D by reverse-mode transposition of `forward`, one linear
-    operation at a time (discretise-then-adjoint, Section 3.3.4), under the
+    operation at a time (discretise-then-adjoint, Section 3.2.4), under the
     unweighted inner products of R^N and R^{Ns Nt}."""
     op = Operators(prm, c0, rho0) if ops is None else ops
     nt, dt = prm["nt"], prm["dt"]

@@ -1,6 +1,6 @@
 """Oracle of the sound-speed gradient of the acoustic data: the derivative of
 <r, H_a[c0] p0> with respect to c0 at every node, by reverse mode through the
-recursion of Section 3.3.3, with the reference speed c_ref (which sets kappa
+recursion of Section 3.2.3, with the reference speed c_ref (which sets kappa
 and the PML) held fixed.
 
 Test infrastructure: only the tests, the smoke check and the benchmark's CPU

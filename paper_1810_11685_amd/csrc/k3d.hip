@@ -1,4 +1,4 @@
-// 3-D k-space PSTD passes for gfx950 (Section 3.3.3 with d = 3).
+// 3-D k-space PSTD passes for gfx950 (Section 3.2.3 with d = 3).
 //
 // One iterate is three (row pass, plane pass) pairs, as in 2-D:
 //   row pass   - rt consecutive x-lines: inverse x-FFT of the incoming half

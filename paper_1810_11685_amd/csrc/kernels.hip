@@ -1,6 +1,6 @@
 // HIP kernels of the k-space acoustic operator for gfx950 (MI355X).
 //
-// Every spectral operator F^-1 diag(m) F of Section 3.3.2 (staggered
+// Every spectral operator F^-1 diag(m) F of Section 3.2.2 (staggered
 // gradients of eq grr, fractional Laplacians Y_dis and Y_abs) is split into
 //   row pass  : inverse row FFTs of the previous spectra, the pointwise update
 //               of eqs num-vel / num-rho / num-p (or their transposes), and the

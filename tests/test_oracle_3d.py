@@ -175,3 +175,65 @@ def test_stability_bound_3d():
 
 def test_face_sensor_count():
     assert qi.face_sensors(33, 8, 3.125e-4, 49).shape == (2145, 3)
+
+
+def _pml_factor(pos, n, L, alpha, c_ref, d, dt):
+    xi = np.maximum(0.0, np.maximum(L - pos, pos - (n - 1 - L)))
+    return np.exp(-alpha * (c_ref / d) * (xi / L) ** 4 * dt / 2.0)
+
+
+def test_velocity_staggering_3d():
+    """Where each velocity component lives (Section 3.2.1, eq grr): after the
+    first two iterates v_i = -dt A_v,i grad_i^+ (P0/2) / rho_i.  For
+    P0 = sin(k1 x) + sin(k2 y) + sin(k3 z) the staggered gradient is exactly
+    k kappa(k) cos(k (r + d/2)), the density is the mean of the node and its
+    neighbour ahead along the axis, and the PML factor is taken at i + 1/2.
+    The expected fields are computed here from those statements, so a swap of
+    the +/- shifts, a wrong staggering axis or node-placed velocity PML fails."""
+    nz, ny, nx = 14, 18, 20
+    dx, dy, dz, c = 1e-4, 1.3e-4, 0.8e-4, 1500.0
+    dt = 0.3 * dz / c
+    zz, yy, xx = np.mgrid[0:nz, 0:ny, 0:nx].astype(float)
+    rho0 = (1000.0 + 120.0 * np.sin(2 * np.pi * xx / nx + 0.3) + 80.0 * np.cos(2 * np.pi * yy / ny)
+            + 60.0 * np.sin(2 * np.pi * 2 * zz / nz + 1.0))
+    c0 = np.full((nz, ny, nx), c)
+    L, alpha = 3, 2.0
+    prm = qi.make_params3d(nx, ny, nz, dx, dt, 3, c, off_node_sensors(nz, ny, nx, (dx, dy, dz), 2, 7),
+                           dy=dy, dz=dz, pml_size=L, pml_alpha=alpha, alpha0_db=0.0)
+    x, y, z = (xx - nx / 2) * dx, (yy - ny / 2) * dy, (zz - nz / 2) * dz
+    ks = (2 * np.pi * 3 / (nx * dx), 2 * np.pi * 2 / (ny * dy), 2 * np.pi * 1 / (nz * dz))
+    p0 = np.sin(ks[0] * x) + np.sin(ks[1] * y) + np.sin(ks[2] * z)
+    rec = {}
+    K3.forward(prm, c0, rho0, p0, record=lambda n, s: rec.__setitem__(n, [v.copy() for v in s["v"]]))
+    kap = lambda k: math.sin(c * k * dt / 2) / (c * k * dt / 2)
+    for i, (r, d, n, axis, shape) in enumerate(((x, dx, nx, 2, (1, 1, nx)), (y, dy, ny, 1, (1, ny, 1)),
+                                                (z, dz, nz, 0, (nz, 1, 1)))):
+        k = ks[i]
+        g = 0.5 * k * kap(k) * np.cos(k * (r + d / 2))
+        rho_half = 0.5 * (rho0 + np.roll(rho0, -1, axis=axis))
+        av = _pml_factor(np.arange(n) + 0.5, n, L, alpha, c, d, dt).reshape(shape)
+        want = -dt * av * g / rho_half
+        assert np.abs(rec[-1][i]).max() == 0.0
+        assert np.abs(rec[0][i] - want).max() <= 1e-12 * np.abs(want).max(), i
+
+
+def test_offnode_trilinear_measurement():
+    """M at sensors between nodes (eq num-m read as trilinear interpolation):
+    trilinear interpolation reproduces every field spanned by 1, x, y, z, xy,
+    yz, xz, xyz, so M applied to node values returns the field at the sensor.
+    Fractions far from any node and three different spacings make swapped
+    axis weights fail."""
+    nz, ny, nx = 9, 11, 13
+    dx, dy, dz = 1e-4, 1.4e-4, 0.7e-4
+    frac = [(3.3, 2.7, 1.25), (10.25, 8.85, 6.6), (0.7, 0.3, 0.15), (11.85, 9.25, 7.9), (6.5, 5.1, 4.35)]
+    pos = np.array([[(u - nx / 2) * dx, (v - ny / 2) * dy, (w - nz / 2) * dz] for u, v, w in frac])
+    prm = qi.make_params3d(nx, ny, nz, dx, 1e-8, 2, 1500.0, pos, dy=dy, dz=dz, pml_size=0)
+    c0, rho0 = homog(nz, ny, nx)
+    op = K3.Operators(prm, c0, rho0)
+    zz, yy, xx = np.mgrid[0:nz, 0:ny, 0:nx].astype(float)
+    X, Y, Z = (xx - nx / 2) * dx, (yy - ny / 2) * dy, (zz - nz / 2) * dz
+    f = lambda x, y, z: (0.4 - 2e3 * x + 3e3 * y + 5e3 * z + 2e7 * x * y - 3e7 * y * z + 4e7 * x * z
+                         + 6e10 * x * y * z)
+    got = op.measure(f(X, Y, Z))
+    want = f(pos[:, 0], pos[:, 1], pos[:, 2])
+    assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()

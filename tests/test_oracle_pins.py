@@ -351,3 +351,95 @@ def test_stability_limit_matches_oracle():
     assert grow[0.9] < 2.0
     assert grow[1.2] > 1e3
     assert math.isinf(K.stability_limit(c, c, dx, dx))
+
+
+# ----------------------------------------------------------------------------
+# P12: where the velocity lives on the staggered grid (Section 3.2.1, eq grr).
+# After the first two iterates the velocity is -dt A_v grad^+ (P0/2) / rho_i.
+# For P0 = sin(k1 x) + sin(k2 y) the staggered gradient of eq grr is exactly
+# k kappa(k) cos(k (r + d/2)): the derivative half a cell ahead.  The density
+# that divides it must be the one at that half node (the mean of the two
+# neighbouring nodes) and the PML factor the one at i + 1/2.  Everything
+# expected below is computed here from those statements, not from the
+# oracle's tables, so a consistent swap of the +/- shifts on both axes, a
+# density averaged towards the wrong neighbour or a velocity PML taken at the
+# nodes each fails.
+# ----------------------------------------------------------------------------
+def _pml_factor(pos, n, L, alpha, c_ref, d, dt):
+    xi = np.maximum(0.0, np.maximum(L - pos, pos - (n - 1 - L)))
+    return np.exp(-alpha * (c_ref / d) * (xi / L) ** 4 * dt / 2.0)
+
+
+def test_p12_velocity_staggering():
+    nx, ny, dx, dy, c = 40, 30, 1e-4, 1.3e-4, 1500.0
+    dt = 0.3 * dx / c
+    yy, xx = np.mgrid[0:ny, 0:nx].astype(float)
+    rho0 = 1000.0 + 150.0 * np.sin(2 * np.pi * xx / nx + 0.4) + 90.0 * np.cos(2 * np.pi * 2 * yy / ny)
+    c0 = np.full((ny, nx), c)
+    L, alpha = 5, 2.0
+    prm = qi.make_params(nx, ny, dx, dt, 4, c, qi.ring_sensors(3, 4.5, dx, dy=dy), dy=dy,
+                         pml_size=L, pml_alpha=alpha, alpha0_db=0.0)
+    k1 = 2 * np.pi * 3 / (nx * dx)
+    k2 = 2 * np.pi * 2 / (ny * dy)
+    x = (xx - nx / 2) * dx
+    y = (yy - ny / 2) * dy
+    p0 = np.sin(k1 * x) + np.sin(k2 * y)
+    rec = {}
+    K.forward(prm, c0, rho0, p0, record=lambda n, s: rec.__setitem__(n, {k: v.copy() for k, v in s.items()}))
+    # iterate n = -1 starts from p = 0, so v stays 0 and p becomes P0/2
+    assert np.abs(rec[-1]["vx"]).max() == 0.0 and np.abs(rec[-1]["vy"]).max() == 0.0
+    assert np.abs(rec[-1]["p"] - 0.5 * p0).max() <= 1e-13
+    kap = lambda k: math.sin(c * k * dt / 2) / (c * k * dt / 2)
+    gx = 0.5 * k1 * kap(k1) * np.cos(k1 * (x + dx / 2))
+    gy = 0.5 * k2 * kap(k2) * np.cos(k2 * (y + dy / 2))
+    rho_half_x = 0.5 * (rho0 + np.roll(rho0, -1, axis=1))
+    rho_half_y = 0.5 * (rho0 + np.roll(rho0, -1, axis=0))
+    avx = _pml_factor(np.arange(nx) + 0.5, nx, L, alpha, c, dx, dt)[None, :]
+    avy = _pml_factor(np.arange(ny) + 0.5, ny, L, alpha, c, dy, dt)[:, None]
+    vx = -dt * avx * gx / rho_half_x
+    vy = -dt * avy * gy / rho_half_y
+    assert np.abs(rec[0]["vx"] - vx).max() <= 1e-12 * np.abs(vx).max()
+    assert np.abs(rec[0]["vy"] - vy).max() <= 1e-12 * np.abs(vy).max()
+
+
+# ----------------------------------------------------------------------------
+# P13: the measurement operator at sensors between nodes (eq num-m, read as
+# bilinear interpolation from the four surrounding nodes).  Bilinear
+# interpolation reproduces every field a + b x + c y + e x y exactly, so M
+# applied to its node values must return the field at the sensor.  The
+# fractions 0.3 / 0.7 / 0.25 / 0.85 are far from any node, and the grid is
+# non-square with dx != dy, so swapped x / y weights, weights taken from the
+# wrong side or a wrong coordinate origin fail.
+# ----------------------------------------------------------------------------
+def test_p13_offnode_bilinear_measurement():
+    nx, ny, dx, dy = 24, 18, 1e-4, 1.7e-4
+    frac = [(3.3, 2.7), (10.25, 14.85), (0.7, 0.3), (22.85, 16.25), (12.5, 9.1), (5.0, 7.6)]
+    pos = np.array([[(u - nx / 2) * dx, (v - ny / 2) * dy] for u, v in frac])
+    prm = qi.make_params(nx, ny, dx, 1e-8, 2, 1500.0, pos, dy=dy, pml_size=0)
+    op = K.Operators(prm, np.full((ny, nx), 1500.0), np.full((ny, nx), 1000.0))
+    yy, xx = np.mgrid[0:ny, 0:nx].astype(float)
+    X, Y = (xx - nx / 2) * dx, (yy - ny / 2) * dy
+    f = lambda x, y: 0.7 - 3e3 * x + 5e3 * y + 4e7 * x * y
+    got = op.measure(f(X, Y))
+    want = f(pos[:, 0], pos[:, 1])
+    assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
+    # M^T is the scatter with the same weights: <M g, r> = <g, M^T r>
+    g = qi.gaussian_field((ny, nx), 5)
+    r = np.linspace(-1.0, 2.0, len(frac))
+    assert abs(np.sum(op.measure(g) * r) - np.sum(g * op.measure_T(r))) <= 1e-12 * np.abs(g).sum()
+    # and the forward samples its pressure through that operator
+    rec = {}
+    prm2 = dict(prm, nt=3)
+    d = K.forward(prm2, np.full((ny, nx), 1500.0), np.full((ny, nx), 1000.0), g,
+                  record=lambda n, s: rec.__setitem__(n + 1, s["p"].copy()))
+    for m in range(3):
+        p = rec[m]
+        i0 = np.floor(np.array(frac)[:, 0]).astype(int)
+        j0 = np.floor(np.array(frac)[:, 1]).astype(int)
+        fx = np.array(frac)[:, 0] - i0
+        fy = np.array(frac)[:, 1] - j0
+        i1 = np.minimum(i0 + 1, nx - 1)
+        j1 = np.minimum(j0 + 1, ny - 1)
+        want = ((1 - fy) * ((1 - fx) * p[j0, i0] + fx * p[j0, i1])
+                + fy * ((1 - fx) * p[j1, i0] + fx * p[j1, i1]))
+        assert np.abs(d[m] - want).max() <= 1e-12 * np.abs(p).max()
