@@ -226,7 +226,10 @@ qpat_status qpat_batch_set_graph(qpat_batch batch, int32_t enable);
 
 /* Inner product with FP64 accumulation of two device float vectors of length
  * n; the result is written to *out (device double).  Deterministic: a fixed
- * block partition reduced in a fixed order (wavefront shuffles, then LDS). */
+ * block partition reduced in a fixed order (wavefront shuffles, then LDS).
+ * The partial sums live in a library buffer per (device, stream), allocated
+ * on the first call on that pair: calls on different streams do not share
+ * one, calls on one stream are ordered by it. */
 qpat_status qpat_dot(const float* a, const float* b, int64_t n, double* out, qpat_stream stream);
 
 /* ---- Lagged-diffusivity TV priorconditioner of the inexact-Newton driver

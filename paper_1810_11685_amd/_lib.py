@@ -2,6 +2,8 @@
 from __future__ import annotations
 
 import ctypes
+import functools
+import inspect
 import os
 import threading
 
@@ -148,3 +150,42 @@ def check(status: int, where: str) -> None:
     if status != 0:
         msg = lib().qpat_last_error()
         raise QpatError(status, where, msg.decode() if msg else "")
+
+
+def _cuda_tensors(objs):
+    for o in objs:
+        if isinstance(o, torch.Tensor):
+            if o.is_cuda:
+                yield o
+        elif isinstance(o, (list, tuple)):
+            yield from _cuda_tensors(o)
+
+
+def on_stream(fn):
+    """Run a binding on the stream given as its `stream` argument.
+
+    The library enqueues its work on that stream; for a stream other than the
+    current one the wrapper first makes it wait for the work already queued
+    on the current stream (the inputs' producers), runs the binding with it
+    as the current stream (so outputs and temporaries are allocated on it)
+    and marks the tensor arguments as used by it (so the caching allocator
+    does not reuse their memory while it still reads them).  The results
+    then belong to that stream; a caller using them elsewhere synchronises
+    with it first."""
+    sig = inspect.signature(fn)
+
+    @functools.wraps(fn)
+    def wrapper(*args, **kw):
+        bound = sig.bind(*args, **kw)
+        stream = bound.arguments.get("stream")
+        cur = torch.cuda.current_stream()
+        if stream is None or stream == cur:
+            return fn(*args, **kw)
+        bound.arguments["stream"] = None
+        stream.wait_stream(cur)
+        for t in _cuda_tensors(list(bound.arguments.values())):
+            t.record_stream(stream)
+        with torch.cuda.stream(stream):
+            return fn(*bound.args, **bound.kwargs)
+
+    return wrapper

@@ -1427,24 +1427,24 @@ qpat_status qpat_dot(const float* a, const float* b, int64_t n, double* out, qpa
   if (!out) return fail(QPAT_E_INVALID, "out is NULL");
   if (n < 0) return fail(QPAT_E_INVALID, "n must be >= 0");
   if (n > 0 && (!a || !b)) return fail(QPAT_E_INVALID, "NULL input with n > 0");
+  // partial sums: one buffer per (device, stream), so calls on different
+  // streams never share one; calls on one stream are ordered by it
   static std::mutex mu;
-  static std::map<int, double*> partials;
-  constexpr int kNblk = 512;
+  static std::map<std::pair<int, void*>, double*> partials;
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
   double* part = nullptr;
   {
     std::lock_guard<std::mutex> g(mu);
-    auto it = partials.find(dev);
+    auto it = partials.find({dev, stream});
     if (it == partials.end()) {
-      HIPCHK(hipMalloc(&part, kNblk * sizeof(double)));
-      partials[dev] = part;
+      HIPCHK(hipMalloc(&part, kDotBlocks * sizeof(double)));
+      partials[{dev, stream}] = part;
     } else {
       part = it->second;
     }
   }
-  int nblk = int(std::min<int64_t>(kNblk, (n + kBlock - 1) / kBlock));
-  if (nblk < 1) nblk = 1;
+  const int nblk = dot_blocks(n);
   hipError_t e = launch_dot(a, b, n, part, nblk, out, (hipStream_t)stream);
   if (e != hipSuccess) return fail(QPAT_E_HIP, std::string("dot: ") + hipGetErrorString(e));
   return QPAT_OK;

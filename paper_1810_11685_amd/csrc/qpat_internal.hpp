@@ -130,6 +130,12 @@ hipError_t launch_grad_c(const float* c2, const float* p0, const float* g0, cons
                          int batch, long long gc_stride, float* out, hipStream_t st);
 hipError_t launch_dot(const float* a, const float* b, int64_t n, double* partial, int nblk,
                       double* out, hipStream_t st);
+// Blocks (and partial sums) of the inner product of length n: at most kDotBlocks.
+constexpr int kDotBlocks = 512;
+inline int dot_blocks(int64_t n) {
+  const int64_t b = (n + kBlock - 1) / kBlock;
+  return int(b < 1 ? 1 : (b > kDotBlocks ? kDotBlocks : b));
+}
 
 // LDS line layout: element e of a line sits at px(e) = e + e/8.  The pad slot
 // after every 8 elements spreads the strided writes of the early Stockham

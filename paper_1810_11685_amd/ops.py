@@ -11,7 +11,7 @@ import math
 import numpy as np
 import torch
 
-from ._lib import QpatParams, check, lib
+from ._lib import QpatParams, check, lib, on_stream
 
 OPS = {"dx+": 0, "dx-": 1, "dy+": 2, "dy-": 3, "ydis": 4, "yabs": 5}
 
@@ -70,6 +70,7 @@ class Plan:
         check(L.qpat_plan_create(ctypes.byref(p), c0.ctypes.data, rho0.ctypes.data, ctypes.byref(h)),
               "qpat_plan_create")
         self._h = h
+        self._c0 = c0.copy()
         self.params = dict(prm)
         self.nx, self.ny, self.nt = prm["nx"], prm["ny"], prm["nt"]
         self.ns = len(self._xy)
@@ -88,6 +89,10 @@ class Plan:
     def handle(self):
         return self._h
 
+    def sound_speed(self) -> np.ndarray:
+        """The FP64 sound speed [ny, nx] the plan was built from."""
+        return self._c0
+
     # ---- shapes
     def _fields(self, t, name):
         t = _need(t, (self.ny, self.nx), name)
@@ -98,6 +103,7 @@ class Plan:
         return t, (t.numel() // (self.nt * self.ns)), t.shape[:-2]
 
     # ---- operators
+    @on_stream
     def forward(self, p0: torch.Tensor, stream=None) -> torch.Tensor:
         """H_a p0: [..., ny, nx] -> [..., nt, ns]."""
         p0, b, lead = self._fields(p0, "p0")
@@ -107,6 +113,7 @@ class Plan:
 
     jv = forward
 
+    @on_stream
     def adjoint(self, res: torch.Tensor, stream=None) -> torch.Tensor:
         """H_a^* r: [..., nt, ns] -> [..., ny, nx]."""
         res, b, lead = self._data(res, "res")
@@ -114,6 +121,7 @@ class Plan:
         check(lib().qpat_adjoint(self._h, _ptr(res), _ptr(out), b, _stream(stream)), "qpat_adjoint")
         return out
 
+    @on_stream
     def jtjv(self, v: torch.Tensor, stream=None) -> torch.Tensor:
         """H_a^* H_a v: [..., ny, nx] -> [..., ny, nx]."""
         v, b, lead = self._fields(v, "v")
@@ -121,6 +129,7 @@ class Plan:
         check(lib().qpat_jtjv(self._h, _ptr(v), _ptr(out), b, _stream(stream)), "qpat_jtjv")
         return out
 
+    @on_stream
     def apply(self, op: str, x: torch.Tensor, stream=None) -> torch.Tensor:
         """One spectral operator ('dx+', 'dx-', 'dy+', 'dy-', 'ydis', 'yabs')."""
         x, b, lead = self._fields(x, "x")
@@ -134,6 +143,7 @@ class Plan:
         check(lib().qpat_ckpt_bytes(self._h, interval, batch, ctypes.byref(n)), "qpat_ckpt_bytes")
         return int(n.value)
 
+    @on_stream
     def forward_ckpt(self, p0: torch.Tensor, interval: int, stream=None):
         """(data, checkpoints): checkpoints [B, ceil(nt/K), 5, ny, nx]."""
         p0, b, lead = self._fields(p0, "p0")
@@ -144,6 +154,7 @@ class Plan:
               "qpat_forward_ckpt")
         return out, ck
 
+    @on_stream
     def replay(self, p0: torch.Tensor, ckpt: torch.Tensor, interval: int, seg: int, stream=None):
         """States z_m [B, cnt, 5, ny, nx] of segment `seg` recomputed from its checkpoint."""
         p0, b, _ = self._fields(p0, "p0")
@@ -160,6 +171,7 @@ class Plan:
         check(lib().qpat_medium_grad_bytes(self._h, interval, batch, ctypes.byref(n)), "qpat_medium_grad_bytes")
         return int(n.value)
 
+    @on_stream
     def medium_grad(self, p0: torch.Tensor, res: torch.Tensor, interval: int | None = None, work=None,
                     stream=None) -> tuple[torch.Tensor, torch.Tensor]:
         """(d<res, H_a[c0] p0>/dc0, H_a^* res) for p0 [..., ny, nx] and res
@@ -193,6 +205,7 @@ class Plan:
                                    ctypes.byref(ch)), "qpat_get_tiles")
         return int(r.value), int(c.value), int(rh.value), int(ch.value)
 
+    @on_stream
     def tune(self, batch: int = 1, stream=None) -> tuple[int, int, int, int]:
         check(lib().qpat_tune(self._h, batch, _stream(stream)), "qpat_tune")
         return self.tiles()
@@ -200,6 +213,7 @@ class Plan:
     def set_graph(self, enable: bool = True) -> None:
         check(lib().qpat_set_graph(self._h, int(bool(enable))), "qpat_set_graph")
 
+    @on_stream
     def time_pass(self, pass_id: int, batch: int = 1, reps: int = 20, stream=None) -> float:
         """Mean duration in ms of one launch of a pass kind (qpat_time_pass)."""
         ms = ctypes.c_float()
@@ -236,6 +250,7 @@ class Batch:
     def _arr(ts):
         return (ctypes.c_void_p * len(ts))(*[t.data_ptr() for t in ts])
 
+    @on_stream
     def forward(self, p0s, stream=None):
         ins = [_need(x, (p.ny, p.nx), "p0") for x, p in zip(p0s, self.plans)]
         outs = [torch.empty(p.nt, p.ns, device=x.device, dtype=torch.float32) for x, p in zip(ins, self.plans)]
@@ -243,6 +258,7 @@ class Batch:
               "qpat_batch_forward")
         return outs
 
+    @on_stream
     def adjoint(self, ress, stream=None):
         ins = [_need(x, (p.nt, p.ns), "res") for x, p in zip(ress, self.plans)]
         outs = [torch.empty(p.ny, p.nx, device=x.device, dtype=torch.float32) for x, p in zip(ins, self.plans)]
@@ -250,6 +266,7 @@ class Batch:
               "qpat_batch_adjoint")
         return outs
 
+    @on_stream
     def jtjv(self, vs, stream=None, out=None):
         ins = [_need(x, (p.ny, p.nx), "v") for x, p in zip(vs, self.plans)]
         outs = out if out is not None else [torch.empty_like(x) for x in ins]
@@ -261,6 +278,7 @@ class Batch:
         check(lib().qpat_batch_set_graph(self._h, int(bool(enable))), "qpat_batch_set_graph")
 
 
+@on_stream
 def dot(a: torch.Tensor, b: torch.Tensor, stream=None) -> torch.Tensor:
     """<a, b> with FP64 accumulation (qpat_dot); returns a 0-d float64 CUDA tensor."""
     a = a.contiguous()

@@ -7,7 +7,7 @@ import ctypes
 import numpy as np
 import torch
 
-from ._lib import QpatParams3d, check, lib
+from ._lib import QpatParams3d, check, lib, on_stream
 from .ops import _need, _ptr, _stream
 
 OPS3 = {"dx+": 0, "dx-": 1, "dy+": 2, "dy-": 3, "dz+": 4, "dz-": 5, "ydis": 6, "yabs": 7}
@@ -64,6 +64,7 @@ class Plan3D:
         t = _need(t, (self.nt, self.ns), name)
         return t, t.numel() // (self.nt * self.ns), t.shape[:-2]
 
+    @on_stream
     def forward(self, p0: torch.Tensor, stream=None) -> torch.Tensor:
         """H_a p0: [..., nz, ny, nx] -> [..., nt, ns]."""
         p0, b, lead = self._fields(p0, "p0")
@@ -73,6 +74,7 @@ class Plan3D:
 
     jv = forward
 
+    @on_stream
     def adjoint(self, res: torch.Tensor, stream=None) -> torch.Tensor:
         """H_a^* r: [..., nt, ns] -> [..., nz, ny, nx]."""
         res, b, lead = self._data(res, "res")
@@ -80,12 +82,14 @@ class Plan3D:
         check(lib().qpat3d_adjoint(self._h, _ptr(res), _ptr(out), b, _stream(stream)), "qpat3d_adjoint")
         return out
 
+    @on_stream
     def jtjv(self, v: torch.Tensor, stream=None) -> torch.Tensor:
         v, b, _ = self._fields(v, "v")
         out = torch.empty_like(v)
         check(lib().qpat3d_jtjv(self._h, _ptr(v), _ptr(out), b, _stream(stream)), "qpat3d_jtjv")
         return out
 
+    @on_stream
     def apply(self, op: str, x: torch.Tensor, stream=None) -> torch.Tensor:
         """One spectral operator ('dx+', 'dx-', 'dy+', 'dy-', 'dz+', 'dz-', 'ydis', 'yabs')."""
         x, b, _ = self._fields(x, "x")

@@ -10,7 +10,7 @@ import ctypes
 import numpy as np
 import torch
 
-from ._lib import check, lib
+from ._lib import check, lib, on_stream
 from .ops import Plan, _ptr, _stream
 
 
@@ -43,6 +43,7 @@ class Optical:
             raise ValueError(f"{name} must be float32 [..., {self.ne}]")
         return t, (1 if t.dim() == 1 else t.shape[0])
 
+    @on_stream
     def forward(self, kappa: torch.Tensor, mu: torch.Tensor, currents, stream=None) -> torch.Tensor:
         """H = mu o I Phi with A_o Phi = G; currents [batch][4] (bottom, top, left, right)."""
         kappa, b = self._el(kappa, "kappa")
@@ -56,6 +57,7 @@ class Optical:
         self.iters = int(it.value)
         return H
 
+    @on_stream
     def jv(self, dkappa: torch.Tensor, dmu: torch.Tensor, stream=None) -> torch.Tensor:
         dkappa, b = self._el(dkappa, "dkappa")
         dmu, _ = self._el(dmu, "dmu")
@@ -66,6 +68,7 @@ class Optical:
         self.iters = int(it.value)
         return out
 
+    @on_stream
     def jtv(self, H: torch.Tensor, stream=None) -> tuple[torch.Tensor, torch.Tensor]:
         H, b = self._el(H, "H")
         gk, gm = torch.empty_like(H), torch.empty_like(H)
@@ -75,6 +78,7 @@ class Optical:
         self.iters = int(it.value)
         return gk, gm
 
+    @on_stream
     def pixels(self, H: torch.Tensor, stream=None) -> torch.Tensor:
         """Initial pressure [.., ny, nx]: the mean of each pixel's two elements."""
         H, b = self._el(H, "H")
@@ -82,6 +86,7 @@ class Optical:
         check(lib().qpat_optical_pixels(self._h, _ptr(H), _ptr(p), 0, b, _stream(stream)), "qpat_optical_pixels")
         return p
 
+    @on_stream
     def pixels_T(self, p: torch.Tensor, stream=None) -> torch.Tensor:
         p = p.contiguous()
         if p.dtype != torch.float32 or p.shape[-2:] != (self.ny, self.nx):
@@ -102,14 +107,17 @@ class QPATJacobian:
             raise ValueError("the acoustic grid and the optical mesh must match")
         self.plan, self.optical = plan, optical
 
+    @on_stream
     def forward(self, kappa, mu, currents, stream=None) -> torch.Tensor:
         H = self.optical.forward(kappa, mu, currents, stream)
         return self.plan.forward(self.optical.pixels(H, stream), stream=stream)
 
+    @on_stream
     def jv(self, dkappa, dmu, stream=None) -> torch.Tensor:
         dH = self.optical.jv(dkappa, dmu, stream)
         return self.plan.jv(self.optical.pixels(dH, stream), stream=stream)
 
+    @on_stream
     def jtv(self, r, stream=None) -> tuple[torch.Tensor, torch.Tensor]:
         g = self.plan.adjoint(r, stream=stream)
         return self.optical.jtv(self.optical.pixels_T(g, stream), stream)

@@ -18,7 +18,7 @@ import math
 
 import torch
 
-from ._lib import check, lib
+from ._lib import check, lib, on_stream
 from .ops import Plan, _ptr, _stream, dot
 
 
@@ -49,16 +49,19 @@ class TV:
         b = 1 if x.dim() == 2 else x.shape[0]
         return x, b
 
+    @on_stream
     def set_weights(self, x: torch.Tensor, beta: float, stream=None) -> None:
         x, b = self._fields(x)
         check(lib().qpat_tv_set_weights(self._h, _ptr(x), float(beta), b, _stream(stream)), "qpat_tv_set_weights")
 
+    @on_stream
     def apply(self, x: torch.Tensor, gamma: float, stream=None) -> torch.Tensor:
         x, b = self._fields(x)
         y = torch.empty_like(x)
         check(lib().qpat_tv_apply(self._h, float(gamma), _ptr(x), _ptr(y), b, _stream(stream)), "qpat_tv_apply")
         return y
 
+    @on_stream
     def solve(self, r: torch.Tensor, gamma: float, tol: float = 1e-6, max_iter: int = 20000,
               stream=None) -> tuple[torch.Tensor, int]:
         r, b = self._fields(r)
@@ -68,6 +71,7 @@ class TV:
                                   ctypes.byref(it), _stream(stream)), "qpat_tv_solve")
         return z, int(it.value)
 
+    @on_stream
     def value(self, x: torch.Tensor, beta: float, stream=None) -> list[float]:
         x, b = self._fields(x)
         out = (ctypes.c_double * b)()
@@ -75,6 +79,7 @@ class TV:
         return list(out)
 
 
+@on_stream
 def axpby(a: float, x: torch.Tensor, b: float, y: torch.Tensor, stream=None) -> torch.Tensor:
     """y <- a x + b y in place (qpat_axpby); x and y contiguous float32 of one size."""
     if not (x.is_contiguous() and y.is_contiguous()) or x.numel() != y.numel():
@@ -83,10 +88,12 @@ def axpby(a: float, x: torch.Tensor, b: float, y: torch.Tensor, stream=None) -> 
     return y
 
 
+@on_stream
 def _dot(a: torch.Tensor, b: torch.Tensor, stream=None) -> float:
     return float(dot(a, b, stream).item())
 
 
+@on_stream
 def ld_reconstruct(plan: Plan, data: torch.Tensor, x0: torch.Tensor, *, beta: float, gamma: float,
                    i_max: int = 30, i_m: int = 5, tol_in: float = 0.0, tol_out: float = 1e-3,
                    outer_max: int = 30, solve_tol: float = 1e-6, solve_max_iter: int = 20000, stream=None):

@@ -123,6 +123,34 @@ def test_full_size_vol33_prefix(q, kind):
         assert rel(N(plan.adjoint(T(r))), K3.adjoint(short, c0, rho0, r[:Kp + 1], ops=ops)) <= TOL
 
 
+def test_full_length_vol33(q):
+    """The paper's 3-D reconstruction workload in full (49^3, Nt = 292, 2145
+    detectors; Definition 4, Lemma 2) in the benchmark's launch (automatic
+    shape, hipGraph replay on a non-default stream): data of the workload's
+    blobs over all 292 samples, once the wave has crossed to the detector
+    faces, and the gradient of 0.5 ||H_a p0 - d||^2 for data d of other
+    blobs, against the oracle."""
+    import torch
+    cfg = qi.config3d("vol33")
+    prm, c0, rho0, p0 = cfg["params"], cfg["c0"], cfg["rho0"], cfg["p0"]
+    ops = K3.Operators(prm, c0, rho0)
+    d_ref = K3.forward(prm, c0, rho0, p0, ops=ops)
+    p1 = qi.blobs3d(49, 49, 49, 3310, radius_cells=0.25 * 33, sigma_range=(1.5, 3.0))
+    dobs = K3.forward(prm, c0, rho0, p1, ops=ops)
+    g_ref = K3.adjoint(prm, c0, rho0, d_ref - dobs, ops=ops)
+    plan = q.Plan3D(prm, c0, rho0)
+    plan.set_graph(True)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        for rep in range(2):
+            d = plan.forward(T(p0))
+            g = plan.adjoint(d - T(dobs))
+            s.synchronize()
+            assert rel(N(d), d_ref) <= TOL
+            assert rel(N(g), g_ref) <= TOL
+    plan.set_graph(False)
+
+
 def test_vol37_generation_grid_prime_axes(q):
     """53^3 (37^3 plus the PML; 53 is prime, a direct DFT stage): a short
     prefix of the data against the oracle."""

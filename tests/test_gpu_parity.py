@@ -5,6 +5,7 @@ fields against the FP64 oracle on identical seeded inputs); bitwise equality
 where the same arithmetic is replayed (batching, checkpoint replay, graphs).
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -15,6 +16,7 @@ from oracle import kspace as K
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-4
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 def rel(a, b):
@@ -118,10 +120,56 @@ def test_small_config_full(q):
     assert abs(lhs - rhs) <= 1e-5 * np.linalg.norm(hx) * np.linalg.norm(yv)
 
 
+def test_headline_full_length_in_bench_launch(q):
+    """The headline workload in full (512^2, Nt = 2000, 256 ring sensors, lossy,
+    20-cell PML; Definition 4, Lemma 2) in the launch the benchmark times: the
+    launch shape picked by the tuner, hipGraph capture and replay, on a
+    non-default stream.  Against the FP64 oracle's stored results
+    (tests/golden/make_fwdadj512.py):
+      data       H_a p0 for the workload's blobs, every sample;
+      gradient   H_a^* r for the oracle's residual r = H_a p0 - dobs;
+      end to end H_a^* (d_gpu - dobs), the gradient of 0.5 ||H_a p0 - dobs||^2.
+    Also the default launch shape, the fixed shape (2, 1, 512, 128) and eager
+    launches give the same bits."""
+    import torch
+    gold = np.load(os.path.join(GOLD, "fwdadj512_oracle.npz"))
+    cfg = qi.config("fwdadj512")
+    prm, c0, rho0, p0 = cfg["params"], cfg["c0"], cfg["rho0"], cfg["p0"]
+    plan = q.Plan(prm, c0, rho0)
+    default = plan.tiles()
+    s = torch.cuda.Stream()
+    x = T(p0)
+    dobs = T(gold["dobs"])
+    r_or = T(gold["data"].astype(np.float64) - gold["dobs"].astype(np.float64))
+    with torch.cuda.stream(s):
+        plan.tune(1)
+        tuned = plan.tiles()
+        plan.set_graph(True)
+        outs = []
+        for rep in range(2):              # the capture run, then a replay
+            d = plan.forward(x)
+            g1 = plan.adjoint(r_or)
+            g2 = plan.adjoint(d - dobs)
+            s.synchronize()
+            outs.append((N(d), N(g1), N(g2)))
+        plan.set_graph(False)
+    print(f"headline parity: tuned shape {tuned}, default {default}")
+    for d, g1, g2 in outs:
+        assert d.shape == (2000, 256)
+        assert rel(d, gold["data"]) <= TOL
+        assert rel(g1, gold["grad"]) <= TOL
+        assert rel(g2, gold["grad"]) <= TOL
+    assert all(np.array_equal(a, b) for a, b in zip(outs[0], outs[1]))
+    for shape in {default, (2, 1, 512, 128)}:
+        plan.set_tiles(*shape)
+        assert np.array_equal(N(plan.forward(x)), outs[0][0]), shape
+        assert np.array_equal(N(plan.adjoint(r_or)), outs[0][1]), shape
+
+
 @pytest.mark.parametrize("kind", ["fields", "data", "adjoint"])
 def test_full_size_512_prefix(q, kind):
-    """512^2, Nt = 2000, 256 ring sensors (the headline workload) in the launch
-    configuration the benchmark uses.  The first K samples (and states) depend
+    """512^2, Nt = 2000, 256 ring sensors (the headline workload) with the
+    default launch shape and eager launches.  The first K samples (and states) depend
     only on the first K iterates, and a residual supported on the first K
     samples has an adjoint equal to the K-step adjoint, so the oracle can
     check the full-size run in seconds:
