@@ -8,8 +8,10 @@ that forward + adjoint pair; value = 2 * 512^2 * 2000 / step time, with inputs
 resident in HBM.
 
 Also reported on the same JSON line:
-  roofline      - the dominant pass kind: algorithmic bytes per launch / its
-                  mean launch time (HIP events, live), against 8 TB/s HBM;
+  roofline      - the kernel with the largest share of the step: algorithmic
+                  bytes per launch (the scope table's per-point figure times
+                  the grid points of one launch) / its mean launch time (HIP
+                  events, live, on the stream it runs on), against 8 TB/s HBM;
   cpu_baseline  - the FP64 oracle on the host cores, on a bounded sample;
   batched       - Gauss-Newton J^T J v on 8 Krylov vectors at 1024^2, Nt = 4000
                   (alpha0 = 0.5, y = 1.3): one batched call vs 8 plain calls;
@@ -23,6 +25,7 @@ import hashlib
 import json
 import math
 import os
+import statistics
 import sys
 import time
 
@@ -31,6 +34,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "grid-point-steps/s fwd+adjoint (512², FP32) and batched J^TJv/s vs plain"
 HBM_PEAK_GBS = 8000.0
+REPEATS = 5          # timed runs of each batched / uneven measurement (median reported)
 
 # Algorithmic HBM bytes per grid point moved by one launch of each pass kind
 # (FP32 fields 4 B/pt; a half spectrum [ny][nx/2] of complex64 is 4 B/pt; the
@@ -50,6 +54,18 @@ PASS_BYTES = {
     10: 8 + 8 + 8 + 8 + 8,   # adj row velocity
     11: 8 + 4 + 2,           # adj col div: 2 in, 1 out, kappa
 }
+
+
+# The same per grid point as the scope table of the hot path counts them
+# (fields and half spectra only, no multiplier tables): 152 B per forward
+# iterate.  Each adjoint pass is the transpose of one forward pass and is
+# given that pass's count (152 B per adjoint iterate).  These are the bytes
+# the roofline line uses.
+SCOPE_BYTES = {0: 12, 1: 40, 2: 16, 3: 36, 4: 16, 5: 32,
+               6: 32, 7: 16, 8: 36, 9: 16, 10: 40, 11: 12}
+# Passes served by one kernel (the fractional-Laplacian column pass is the
+# same kernel forward and adjoint); every other pass has a kernel of its own.
+KERNEL_OF_PASS = {4: "col_fraclap", 7: "col_fraclap"}
 
 
 # Algorithmic HBM bytes per FEM node of one conjugate-gradient iteration of
@@ -109,36 +125,81 @@ def pmc_traffic(pass_name: str):
     return None if k is None else k.get("bytes_per_launch")
 
 
+def dominant_kernel(passes: dict, npts: int, batch: int = 1) -> dict:
+    """Roofline entry of the kernel with the largest share of an iterate pair:
+    its launches per pair times their mean duration.  achieved = algorithmic
+    bytes per launch (scope-table bytes per point times the points of one
+    launch) / mean launch duration."""
+    names = [n for n, _ in PASSES_ORDER()]
+    kern = {}
+    for pid, name in enumerate(names):
+        k = KERNEL_OF_PASS.get(pid, name)
+        kern.setdefault(k, []).append(pid)
+    total = sum(v["ms"] for v in passes.values())
+    best = max(kern, key=lambda k: sum(passes[names[p]]["ms"] for p in kern[k]))
+    pids = kern[best]
+    ms = sum(passes[names[p]]["ms"] for p in pids) / len(pids)
+    byts = sum(SCOPE_BYTES[p] for p in pids) / len(pids) * npts * batch
+    gbs = byts / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "kernel": best,
+            "passes": [names[p] for p in pids], "bytes_per_launch": int(byts), "launch_ms": round(ms, 5),
+            "share_of_step": round(ms * len(pids) / total, 4)}
+
+
+def PASSES_ORDER():
+    from paper_1810_11685_amd.ops import PASSES
+    return PASSES
+
+
 def sync():
     import torch
     torch.cuda.synchronize()
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(cfg, budget_s: float):
     """FP64 oracle forward + adjoint on a bounded number of iterates of the same
-    512^2 workload; returns grid-point-steps/s and what was sampled."""
-    import numpy as np
+    512^2 workload, with every host thread for scipy.fft and with one; returns
+    grid-point-steps/s and what was sampled."""
     import qpat_inputs as qi
     from oracle import kspace as K
-    workers = min(os.cpu_count() or 1, 16)
-    K.set_workers(workers)
     prm, c0, rho0, p0 = cfg["params"], cfg["c0"], cfg["rho0"], cfg["p0"]
     ops = K.Operators(prm, c0, rho0)
     n_pts = prm["nx"] * prm["ny"]
-    t = time.perf_counter()
-    K.forward(prm, c0, rho0, p0, ops=ops, nsteps=3)
-    per = (time.perf_counter() - t) / 3
-    steps = int(max(5, min(prm["nt"], budget_s / (2.2 * per))))
-    short = dict(prm, nt=steps)
-    t0 = time.perf_counter()
-    d = K.forward(short, c0, rho0, p0, ops=ops)
-    t1 = time.perf_counter()
-    K.adjoint(short, c0, rho0, qi.gaussian_field(d.shape, 5), ops=ops)
-    t2 = time.perf_counter()
-    return {"value": 2 * n_pts * steps / (t2 - t0), "unit": "grid-point-steps/s", "cores": workers,
-            "kind": "oracle",
-            "sample": f"FP64 numpy/scipy.fft oracle, 512x512 workload, first {steps} of 2000 iterates: "
-                      f"forward {t1 - t0:.1f} s + adjoint {t2 - t1:.1f} s"}
+    ncpu = os.cpu_count() or 1
+    res = {}
+    for workers, share in ((ncpu, 0.6), (1, 0.4)):
+        K.set_workers(workers)
+        t = time.perf_counter()
+        K.forward(prm, c0, rho0, p0, ops=ops, nsteps=3)
+        per = (time.perf_counter() - t) / 3
+        steps = int(max(5, min(prm["nt"], share * budget_s / (2.2 * per))))
+        short = dict(prm, nt=steps)
+        t0 = time.perf_counter()
+        d = K.forward(short, c0, rho0, p0, ops=ops)
+        t1 = time.perf_counter()
+        K.adjoint(short, c0, rho0, qi.gaussian_field(d.shape, 5), ops=ops)
+        t2 = time.perf_counter()
+        res[workers] = (2 * n_pts * steps / (t2 - t0), steps, t1 - t0, t2 - t1)
+    K.set_workers(ncpu)
+    v, steps, tf, ta = res[ncpu]
+    v1, steps1, tf1, ta1 = res[1]
+    return {"value": v, "unit": "grid-point-steps/s", "cores": ncpu, "kind": "oracle",
+            "cpu_model": cpu_model(), "host_cpus": ncpu, "value_1_thread": v1,
+            "sample": f"FP64 numpy/scipy.fft oracle, 512x512 workload, forward + adjoint over the first "
+                      f"{steps} of 2000 iterates with {ncpu} scipy.fft threads ({tf:.1f} s + {ta:.1f} s), "
+                      f"and over the first {steps1} with 1 thread ({tf1:.1f} s + {ta1:.1f} s)"}
 
 
 def main():
@@ -216,20 +277,15 @@ def main():
     passes = {}
     with torch.cuda.stream(stream):
         for pid, (name, kind) in enumerate(PASSES):
-            t_ms = plan.time_pass(pid, batch=1, reps=50)
-            gbs = PASS_BYTES[pid] * nx * ny / (t_ms * 1e-3) / 1e9
-            passes[name] = {"kernel": kind, "ms": round(t_ms, 5), "bytes_per_pt": PASS_BYTES[pid],
-                            "GB_s": round(gbs, 1)}
-    dom = max(passes, key=lambda k: passes[k]["ms"])
-    dpid = [n for n, _ in PASSES].index(dom)
-    achieved = passes[dom]["GB_s"]
-    traffic = pmc_traffic(dom)
-    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": dom, "bytes_per_launch": PASS_BYTES[dpid] * nx * ny,
-                "launch_ms": passes[dom]["ms"]}
-    whole = value * 160.0 / 1e9
-    log(f"dominant pass {dom}: {passes[dom]['ms'] * 1e3:.1f} us, {achieved:.0f} GB/s; "
+            t_ms = plan.time_pass(pid, batch=1, reps=50, stream=stream)
+            gbs = SCOPE_BYTES[pid] * nx * ny / (t_ms * 1e-3) / 1e9
+            passes[name] = {"kernel": kind, "ms": round(t_ms, 5), "bytes_per_pt": SCOPE_BYTES[pid],
+                            "bytes_per_pt_with_tables": PASS_BYTES[pid], "GB_s": round(gbs, 1)}
+    roofline = dominant_kernel(passes, nx * ny)
+    roofline["traffic"] = pmc_traffic(roofline["kernel"])
+    whole = value * 152.0 / 1e9
+    log(f"dominant kernel {roofline['kernel']}: {roofline['launch_ms'] * 1e3:.1f} us per launch, "
+        f"{roofline['achieved']:.0f} GB/s, {roofline['share_of_step']:.1%} of the step; "
         f"whole solve {whole:.0f} GB/s algorithmic")
 
     out = {"metric": METRIC, "value": round(value, 1), "unit": "grid-point-steps/s", "n_gpus": 1,
@@ -262,45 +318,50 @@ def main():
             gplan.set_graph(False)
             gplan.jtjv(vs[0])                     # warm-up (plain)
             sync()
-            t = time.perf_counter()
+            t_single = []                         # each plain call timed on its own
             for j in range(B):
+                t = time.perf_counter()
                 gplan.jtjv(vs[j])
-            sync()
-            t_plain = time.perf_counter() - t
-            log(f"plain J^T J v x{B} (1024^2, Nt=4000): {t_plain:.2f} s")
+                sync()
+                t_single.append(time.perf_counter() - t)
+            t_plain = B * statistics.median(t_single)
+            log(f"plain J^T J v x{B} (1024^2, Nt=4000): {t_plain:.2f} s (8 x median of {B} single calls)")
             gplan.set_tiles(*tiles_b)
             gplan.set_graph(args.graph == "on")
             gplan.jtjv(vs)                        # warm-up (batched; captures the graph)
             sync()
-            t = time.perf_counter()
-            gplan.jtjv(vs)
-            sync()
-            t_batch = time.perf_counter() - t
-            log(f"batched J^T J v x{B}: {t_batch:.2f} s")
+            t_runs = []
+            for _ in range(REPEATS):
+                t = time.perf_counter()
+                gplan.jtjv(vs)
+                sync()
+                t_runs.append(time.perf_counter() - t)
+            t_batch = statistics.median(t_runs)
+            log(f"batched J^T J v x{B}: {t_batch:.2f} s (median of {REPEATS})")
             # per-pass bandwidth of the batched launches (in-sequence HIP-event timing)
             bpass = {}
             for pid, (name, kind) in enumerate(PASSES):
-                t_ms = gplan.time_pass(pid, batch=B, reps=5)
-                bpass[name] = {"kernel": kind, "ms": round(t_ms, 4),
-                               "GB_s": round(PASS_BYTES[pid] * 1024 * 1024 * B / (t_ms * 1e-3) / 1e9, 1)}
-            bdom = max(bpass, key=lambda k: bpass[k]["ms"])
+                t_ms = gplan.time_pass(pid, batch=B, reps=5, stream=stream)
+                bpass[name] = {"kernel": kind, "ms": round(t_ms, 4), "bytes_per_pt": SCOPE_BYTES[pid],
+                               "GB_s": round(SCOPE_BYTES[pid] * 1024 * 1024 * B / (t_ms * 1e-3) / 1e9, 1)}
+            broof = dominant_kernel(bpass, 1024 * 1024, B)
             bsum = sum(v["ms"] for v in bpass.values())
-            bavg = sum(PASS_BYTES.values()) * 1024 * 1024 * B / (bsum * 1e-3) / 1e9
-            log(f"batched passes: dominant {bdom} {bpass[bdom]['GB_s']:.0f} GB/s; "
+            bavg = sum(SCOPE_BYTES.values()) * 1024 * 1024 * B / (bsum * 1e-3) / 1e9
+            log(f"batched passes: dominant {broof['kernel']} {broof['achieved']:.0f} GB/s; "
                 f"iterate pair {bsum * 1e3:.0f} us = {bavg:.0f} GB/s algorithmic")
         pts = 2.0 * 1024 * 1024 * gp["nt"] * B
         out["batched"] = {"workload": "gn1024: J^T J v, 1024x1024, Nt=4000, 512 ring sensors, "
                                       "alpha0=0.5, y=1.3, 8 Krylov vectors",
                           "jtjv_per_s_plain": round(B / t_plain, 4), "jtjv_per_s_batched": round(B / t_batch, 4),
                           "speedup": round(t_plain / t_batch, 3),
+                          "timing": f"plain: {B} x the median of {B} single calls; batched: median of {REPEATS}",
+                          "batched_runs_s": [round(v, 4) for v in t_runs],
+                          "plain_single_s": [round(v, 4) for v in t_single],
                           "grid_point_steps_per_s_batched": round(pts / t_batch, 1),
                           "tiles_plain": list(tiles_1), "tiles_batched": list(tiles_b),
                           "passes": bpass,
-                          "roofline": {"bound": "hbm", "kernel": bdom, "achieved": bpass[bdom]["GB_s"],
-                                       "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                       "frac": round(bpass[bdom]["GB_s"] / HBM_PEAK_GBS, 4),
-                                       "iterate_pair_GB_s": round(bavg, 1),
-                                       "iterate_pair_frac": round(bavg / HBM_PEAK_GBS, 4)}}
+                          "roofline": dict(broof, iterate_pair_GB_s=round(bavg, 1),
+                                           iterate_pair_frac=round(bavg / HBM_PEAK_GBS, 4))}
         del gplan, vs
         torch.cuda.empty_cache()
 
@@ -330,24 +391,29 @@ def main():
             shape_b[n] = shared
         for pl, p in zip(plans, probs):
             pl.set_tiles(*shape_1[p["params"]["nx"]])
+        def timed(fn, reps):
+            out_t = []
+            for _ in range(reps):
+                t = time.perf_counter()
+                fn()
+                sync()
+                out_t.append(time.perf_counter() - t)
+            return statistics.median(out_t), out_t
+
+        def plain_jtjv():
+            for pl, x in zip(plans, xs):
+                pl.jtjv(x)
+
+        def plain_jv():                           # J v = H_a v: one forward solve per problem
+            for pl, x in zip(plans, xs):
+                pl.forward(x)
+
         with torch.cuda.stream(stream):
-            for pl, x in zip(plans, xs):          # warm-up
-                pl.jtjv(x)
+            plain_jtjv()                          # warm-up
+            plain_jv()
             sync()
-            t = time.perf_counter()
-            for pl, x in zip(plans, xs):
-                pl.jtjv(x)
-            sync()
-            t_plain = time.perf_counter() - t
-            # J v = H_a v (H_a is linear in p0): one forward solve per problem
-            for pl, x in zip(plans, xs):          # warm-up
-                pl.forward(x)
-            sync()
-            t = time.perf_counter()
-            for pl, x in zip(plans, xs):
-                pl.forward(x)
-            sync()
-            t_plain_jv = time.perf_counter() - t
+            t_plain, runs_plain = timed(plain_jtjv, REPEATS)
+            t_plain_jv, runs_plain_jv = timed(plain_jv, REPEATS)
             for pl, p in zip(plans, probs):
                 try:
                     pl.set_tiles(*shape_b[p["params"]["nx"]])
@@ -355,18 +421,11 @@ def main():
                     shape_b[p["params"]["nx"]] = pl.tiles()
             bat = q.Batch(plans)
             bat.set_graph(args.graph == "on")
-            bat.jtjv(xs)
-            sync()
-            t = time.perf_counter()
-            bat.jtjv(xs)
-            sync()
-            t_batch = time.perf_counter() - t
-            bat.forward(xs)                       # warm-up (captures the forward graph)
-            sync()
-            t = time.perf_counter()
+            bat.jtjv(xs)                          # warm-up (captures the graphs)
             bat.forward(xs)
             sync()
-            t_batch_jv = time.perf_counter() - t
+            t_batch, runs_batch = timed(lambda: bat.jtjv(xs), REPEATS)
+            t_batch_jv, runs_batch_jv = timed(lambda: bat.forward(xs), REPEATS)
         log(f"uneven batch of {len(probs)}: J^T J v plain {t_plain:.2f} s, batched {t_batch:.2f} s; "
             f"J v plain {t_plain_jv:.2f} s, batched {t_batch_jv:.2f} s")
         out["uneven"] = {"workload": "32 problems over 12x256^2 (Nt=1380), 10x384^2 (Nt=2069), "
@@ -378,6 +437,11 @@ def main():
                          "jtjv_per_s_plain": round(len(probs) / t_plain, 3),
                          "jtjv_per_s_batched": round(len(probs) / t_batch, 3),
                          "speedup": round(t_plain / t_batch, 3),
+                         "timing": f"median of {REPEATS} runs each",
+                         "runs_s": {"jtjv_plain": [round(v, 4) for v in runs_plain],
+                                    "jtjv_batched": [round(v, 4) for v in runs_batch],
+                                    "jv_plain": [round(v, 4) for v in runs_plain_jv],
+                                    "jv_batched": [round(v, 4) for v in runs_batch_jv]},
                          "grid_point_steps_per_s_batched": round(pts / t_batch, 1),
                          "tiles_plain": {str(n): list(shape_1[n]) for n in sizes},
                          "tiles_batched": {str(n): list(shape_b[n]) for n in sizes}}

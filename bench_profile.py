@@ -1,12 +1,12 @@
-"""Profiling helpers: a calibration copy kernel for rocprofv3 byte counters and
+"""Measurement helpers of the benchmark (not part of the library): a calibration copy kernel for rocprofv3 byte counters and
 summaries of rocprofv3 CSV output.
 
-    python -m paper_1810_11685_amd.profiling copy --mib 256
+    python bench_profile.py copy --mib 256
         runs a plain device-to-device copy of the given size (the reference
         for scaling FETCH_SIZE / WRITE_SIZE to bytes).
-    python -m paper_1810_11685_amd.profiling stats <kernel_stats.csv>
+    python bench_profile.py stats <kernel_stats.csv>
         prints a short per-kernel table from a --stats CSV.
-    python -m paper_1810_11685_amd.profiling pmc <dir_fetch> <dir_write> <dir_cfetch> <dir_cwrite> \
+    python bench_profile.py pmc <dir_fetch> <dir_write> <dir_cfetch> <dir_cwrite> \
             --copy-mib 256 --out profiles/pmc_traffic.json
         combines two counter runs of the benchmark with two of the copy kernel
         into per-pass HBM traffic per launch.
@@ -21,7 +21,7 @@ import json
 import os
 import sys
 
-HERE = os.path.dirname(os.path.abspath(__file__))
+HERE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1810_11685_amd")
 
 # kernel-name fragments of the pass kinds (row kernels by mode, template arg U)
 ROW_MODES = {0: "fwd_row_velocity", 1: "fwd_row_density", 2: "fwd_row_density", 3: "fwd_row_pressure",

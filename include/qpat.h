@@ -45,7 +45,8 @@ typedef enum {
   QPAT_E_UNSUPPORTED = 2, /* grid size not 2^a or 3*2^a in [8, 1024], y odd with loss, mixed batch */
   QPAT_E_UNSTABLE = 3,    /* dt above the k-space stability bound for c_ref < max(c0) */
   QPAT_E_HIP = 4,         /* a HIP runtime call failed (message has the HIP error) */
-  QPAT_E_OOM = 5          /* device or pinned host allocation failed */
+  QPAT_E_OOM = 5,         /* device or pinned host allocation failed */
+  QPAT_E_NONFINITE = 6    /* qpat_check: a checked output held NaN or Inf */
 } qpat_status;
 
 typedef struct qpat_plan_s* qpat_plan;
@@ -369,6 +370,17 @@ qpat_status qpat_optical_jtv(qpat_optical optical, const float* H, float* gkappa
                              double tol, int32_t max_iter, int32_t* iters, qpat_stream stream);
 qpat_status qpat_optical_pixels(qpat_optical optical, const float* in, float* out, int32_t transpose,
                                 int32_t batch, qpat_stream stream);
+
+/* Failure detection (opt-in).  With the check enabled, every qpat_forward /
+ * qpat_jv call also scans its sensor data, and every qpat_adjoint / qpat_jtjv
+ * call its gradient, for NaN or Inf values with one small kernel on the same
+ * stream after the solve (a plan-owned device flag, no host synchronisation).
+ * qpat_check synchronises `stream`, reads the flag and clears it: it returns
+ * QPAT_E_NONFINITE if any checked output since the last qpat_check held a
+ * non-finite value (an unstable medium or time step, or non-finite inputs),
+ * QPAT_OK otherwise.  Enabling allocates the 4-byte flag once. */
+qpat_status qpat_set_check(qpat_plan plan, int32_t enable);
+qpat_status qpat_check(qpat_plan plan, qpat_stream stream);
 
 /* Plan introspection: sizes and the device bytes the plan holds. */
 qpat_status qpat_plan_info(qpat_plan plan, int32_t* nx, int32_t* ny, int32_t* nt, int32_t* ns,

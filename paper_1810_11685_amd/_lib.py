@@ -50,7 +50,7 @@ class QpatParams3d(ctypes.Structure):
 
 
 STATUS = {0: "QPAT_OK", 1: "QPAT_E_INVALID", 2: "QPAT_E_UNSUPPORTED", 3: "QPAT_E_UNSTABLE",
-          4: "QPAT_E_HIP", 5: "QPAT_E_OOM"}
+          4: "QPAT_E_HIP", 5: "QPAT_E_OOM", 6: "QPAT_E_NONFINITE"}
 
 # name -> (restype, argtypes)
 _SIGS = {
@@ -110,6 +110,8 @@ _SIGS = {
     "qpat_optical_jtv": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_double, c_int32,
                                    ctypes.POINTER(c_int32), c_void_p]),
     "qpat_optical_pixels": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_void_p]),
+    "qpat_set_check": (c_int32, [c_void_p, c_int32]),
+    "qpat_check": (c_int32, [c_void_p, c_void_p]),
     "qpat_plan_info": (c_int32, [c_void_p, ctypes.POINTER(c_int32), ctypes.POINTER(c_int32),
                                  ctypes.POINTER(c_int32), ctypes.POINTER(c_int32), ctypes.POINTER(c_size_t)]),
     "qpat_status_string": (ctypes.c_char_p, [c_int32]),

@@ -1750,6 +1750,24 @@ hipError_t launch_grad_c(const float* c2, const float* p0, const float* g0, cons
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- output check
+// flag <- 1 if any of x[0 .. n) is NaN or infinite (every writer stores the
+// same value, so no atomics are needed; the host clears the flag).
+__global__ void __launch_bounds__(kBlock) finite_kernel(const float* __restrict__ x, int64_t n, int* flag) {
+  bool bad = false;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    bad |= !isfinite(x[i]);
+  if (bad) *flag = 1;
+}
+
+hipError_t launch_finite(const float* x, int64_t n, int* flag, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int64_t want = (n + kBlock - 1) / kBlock;
+  const int nblk = int(want < 1024 ? want : 1024);
+  hipLaunchKernelGGL(finite_kernel, dim3(nblk), dim3(kBlock), 0, st, x, n, flag);
+  return hipGetLastError();
+}
+
 hipError_t launch_dot(const float* a, const float* b, int64_t n, double* partial, int nblk, double* out,
                       hipStream_t st) {
   hipLaunchKernelGGL(dot_partial, dim3(nblk), dim3(kBlock), 0, st, a, b, n, partial);

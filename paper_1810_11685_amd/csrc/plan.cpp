@@ -424,6 +424,9 @@ struct qpat_plan_s {
   }
   bool graph = false;
   int rt = 2, ct = 1, rthr = kBlock, cthr = kBlock;
+  // opt-in output check: flag set by a kernel after each solve
+  bool check = false;
+  int* d_flag = nullptr;
 };
 
 struct qpat_batch_s {
@@ -813,7 +816,12 @@ qpat_status do_forward(qpat_plan P, const float* p0, float* data, int batch, hip
     io[i].out = internal_data ? P->datas[i] : data + data_elems(P) * i;
   }
   STCHK(exec_set_io(*E, io, st));
-  return exec_run(*E, OP_FWD, P->graph, st);
+  STCHK(exec_run(*E, OP_FWD, P->graph, st));
+  if (P->check && !internal_data) {
+    hipError_t e = launch_finite(data, int64_t(data_elems(P)) * batch, P->d_flag, st);
+    if (e != hipSuccess) return fail(QPAT_E_HIP, std::string("output check: ") + hipGetErrorString(e));
+  }
+  return QPAT_OK;
 }
 
 qpat_status do_adjoint(qpat_plan P, const float* res, float* grad, int batch, hipStream_t st,
@@ -826,7 +834,12 @@ qpat_status do_adjoint(qpat_plan P, const float* res, float* grad, int batch, hi
     io[i].out = grad + field_elems(P) * i;
   }
   STCHK(exec_set_io(*E, io, st));
-  return exec_run(*E, OP_ADJ, P->graph, st);
+  STCHK(exec_run(*E, OP_ADJ, P->graph, st));
+  if (P->check) {
+    hipError_t e = launch_finite(grad, int64_t(field_elems(P)) * batch, P->d_flag, st);
+    if (e != hipSuccess) return fail(QPAT_E_HIP, std::string("output check: ") + hipGetErrorString(e));
+  }
+  return QPAT_OK;
 }
 
 // ---- tuning cache
@@ -935,6 +948,7 @@ const char* qpat_status_string(qpat_status s) {
     case QPAT_E_UNSTABLE: return "time step above the stability bound";
     case QPAT_E_HIP: return "HIP runtime error";
     case QPAT_E_OOM: return "out of memory";
+    case QPAT_E_NONFINITE: return "non-finite output";
   }
   return "unknown status";
 }
@@ -967,7 +981,30 @@ void qpat_plan_destroy(qpat_plan P) {
   P->clear_execs();
   if (P->d_work) (void)hipFree(P->d_work);
   if (P->d_med) (void)hipFree(P->d_med);
+  if (P->d_flag) (void)hipFree(P->d_flag);
   delete P;
+}
+
+qpat_status qpat_set_check(qpat_plan P, int32_t enable) {
+  if (!P) return fail(QPAT_E_INVALID, "plan is NULL");
+  if (enable && !P->d_flag) {
+    HIPCHK(hipMalloc(&P->d_flag, sizeof(int)));
+    HIPCHK(hipMemset(P->d_flag, 0, sizeof(int)));
+  }
+  P->check = enable != 0;
+  return QPAT_OK;
+}
+
+qpat_status qpat_check(qpat_plan P, qpat_stream stream) {
+  if (!P) return fail(QPAT_E_INVALID, "plan is NULL");
+  if (!P->d_flag) return QPAT_OK;
+  hipStream_t st = (hipStream_t)stream;
+  int flag = 0;
+  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(hipMemcpy(&flag, P->d_flag, sizeof(int), hipMemcpyDeviceToHost));
+  if (!flag) return QPAT_OK;
+  HIPCHK(hipMemset(P->d_flag, 0, sizeof(int)));
+  return fail(QPAT_E_NONFINITE, "a solve output held NaN or Inf values");
 }
 
 qpat_status qpat_forward(qpat_plan P, const float* p0, float* data, int32_t batch, qpat_stream stream) {

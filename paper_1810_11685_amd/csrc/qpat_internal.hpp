@@ -130,6 +130,8 @@ hipError_t launch_grad_c(const float* c2, const float* p0, const float* g0, cons
                          int batch, long long gc_stride, float* out, hipStream_t st);
 hipError_t launch_dot(const float* a, const float* b, int64_t n, double* partial, int nblk,
                       double* out, hipStream_t st);
+// Sets *flag (device int) to 1 if any of the n floats at x is NaN or infinite.
+hipError_t launch_finite(const float* x, int64_t n, int* flag, hipStream_t st);
 // Blocks (and partial sums) of the inner product of length n: at most kDotBlocks.
 constexpr int kDotBlocks = 512;
 inline int dot_blocks(int64_t n) {

@@ -221,6 +221,20 @@ class Plan:
               "qpat_time_pass")
         return float(ms.value)
 
+    def set_check(self, enable: bool = True) -> None:
+        """Scan every solve's output for NaN / Inf (qpat_set_check)."""
+        check(lib().qpat_set_check(self._h, int(bool(enable))), "qpat_set_check")
+
+    @on_stream
+    def outputs_finite(self, stream=None) -> bool:
+        """Synchronise the stream; False if a checked output since the last
+        call held NaN or Inf (qpat_check returned QPAT_E_NONFINITE)."""
+        st = lib().qpat_check(self._h, _stream(stream))
+        if st == 6:
+            return False
+        check(st, "qpat_check")
+        return True
+
     def device_bytes(self) -> int:
         n = ctypes.c_size_t()
         check(lib().qpat_plan_info(self._h, None, None, None, None, ctypes.byref(n)), "qpat_plan_info")

@@ -64,8 +64,11 @@ def test_null_and_status_strings(q):
     L = q.lib()
     assert L.qpat_validate(None) == 1
     assert b"NULL" in L.qpat_last_error()
-    for s in range(6):
+    for s in range(7):
         assert L.qpat_status_string(s)
+    assert L.qpat_status_string(6) == b"non-finite output"
+    assert L.qpat_set_check(None, 1) == 1
+    assert L.qpat_check(None, None) == 1
     h = ctypes.c_void_p()
     p, _keep = q.make_params(good())
     assert L.qpat_plan_create(ctypes.byref(p), None, None, ctypes.byref(h)) == 1

@@ -334,3 +334,28 @@ def test_nt_one_and_two(q):
         assert rel(N(plan.forward(T(p0))), K.forward(prm, c0, rho0, p0, ops=ops)) <= TOL
         r = qi.gaussian_field((nt, 5), 3)
         assert rel(N(plan.adjoint(T(r))), K.adjoint(prm, c0, rho0, r, ops=ops)) <= TOL
+
+
+def test_output_check_flags_nonfinite(q):
+    """Opt-in failure detection: with the check on, a solve whose output holds
+    NaN / Inf (here from a NaN in p0, or in the residual) is reported by the
+    next check, which then clears the flag; clean solves report nothing."""
+    prm, c0, rho0, p0 = problem(64, 48, 40)
+    plan = q.Plan(prm, c0, rho0)
+    plan.set_check(True)
+    x = T(p0)
+    d = plan.forward(x)
+    plan.adjoint(d)
+    assert plan.outputs_finite()
+    bad = p0.copy()
+    bad[20, 30] = np.nan
+    plan.forward(T(bad))
+    assert not plan.outputs_finite()
+    assert plan.outputs_finite()          # cleared by the read
+    r = N(d)
+    r[5, 3] = np.inf
+    plan.adjoint(T(r))
+    assert not plan.outputs_finite()
+    plan.set_check(False)
+    plan.forward(T(bad))
+    assert plan.outputs_finite()          # not checked
