@@ -233,6 +233,18 @@ qpat_status qpat_batch_set_graph(qpat_batch batch, int32_t enable);
  * one, calls on one stream are ordered by it. */
 qpat_status qpat_dot(const float* a, const float* b, int64_t n, double* out, qpat_stream stream);
 
+/* qpat_dot for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and result bits, with the partial sums in a static device
+ * array of 512 doubles (4 KB) that the library holds on every device it runs
+ * on until the process ends.  The call allocates nothing; the first call on
+ * a device looks up the array's address there.  Lengths 0 .. 2^40 (the
+ * array holds one partial per block, at most 512 blocks, whatever n);
+ * QPAT_E_INVALID beyond.  Every call on one device shares that device's
+ * array: calls that overlap on one device (on different streams, or from
+ * different threads) race and must be ordered by the caller. */
+qpat_status qpat_dot_noalloc(const float* a, const float* b, int64_t n, double* out, qpat_stream stream);
+
 /* ---- Lagged-diffusivity TV priorconditioner of the inexact-Newton driver
  * (Section 5.2: the TV functional of eq tvm with D of eq dd, its gradient
  * M[x] x of eqs jm, m, m1, and M_gamma = M + gamma I of eq pre), for fields on

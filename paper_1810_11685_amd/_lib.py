@@ -81,6 +81,7 @@ _SIGS = {
     "qpat_batch_jtjv": (c_int32, [c_void_p, ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p), c_void_p]),
     "qpat_batch_set_graph": (c_int32, [c_void_p, c_int32]),
     "qpat_dot": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_void_p]),
+    "qpat_dot_noalloc": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_void_p]),
     "qpat_tv_create": (c_int32, [c_int32, c_int32, c_int32, ctypes.POINTER(c_void_p)]),
     "qpat_tv_destroy": (None, [c_void_p]),
     "qpat_tv_set_weights": (c_int32, [c_void_p, c_void_p, ctypes.c_double, c_int32, c_void_p]),

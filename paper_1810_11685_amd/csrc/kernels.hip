@@ -18,6 +18,9 @@
 // places consecutive tiles of one item on the same XCD.
 #include "qpat_internal.hpp"
 
+#include <map>
+#include <mutex>
+
 namespace qpat {
 
 // ---------------------------------------------------------------- complex
@@ -1766,6 +1769,31 @@ hipError_t launch_finite(const float* x, int64_t n, int* flag, hipStream_t st) {
   const int nblk = int(want < 1024 ? want : 1024);
   hipLaunchKernelGGL(finite_kernel, dim3(nblk), dim3(kBlock), 0, st, x, n, flag);
   return hipGetLastError();
+}
+
+// Partial sums of qpat_dot_noalloc: a static array that every device the
+// library runs on holds until the process ends, shared by all calls on that
+// device.  Host code never passes the array's name to a kernel; it uses the
+// device address looked up once per device below.
+static __device__ __align__(256) double scratch[kDotBlocks];
+
+hipError_t dot_scratch(double** ptr) {
+  static std::mutex mu;
+  static std::map<int, double*> addr;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> g(mu);
+  auto it = addr.find(dev);
+  if (it == addr.end()) {
+    double* p = nullptr;
+    e = hipGetSymbolAddress((void**)&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (p == nullptr) return hipErrorInvalidSymbol;
+    it = addr.emplace(dev, p).first;
+  }
+  *ptr = it->second;
+  return hipSuccess;
 }
 
 hipError_t launch_dot(const float* a, const float* b, int64_t n, double* partial, int nblk, double* out,

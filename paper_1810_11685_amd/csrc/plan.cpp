@@ -1487,4 +1487,17 @@ qpat_status qpat_dot(const float* a, const float* b, int64_t n, double* out, qpa
   return QPAT_OK;
 }
 
+qpat_status qpat_dot_noalloc(const float* a, const float* b, int64_t n, double* out, qpat_stream stream) {
+  if (!out) return fail(QPAT_E_INVALID, "out is NULL");
+  if (n < 0) return fail(QPAT_E_INVALID, "n must be >= 0");
+  if (n > kDotNoallocMaxN) return fail(QPAT_E_INVALID, "n exceeds 2^40, the largest length qpat_dot_noalloc takes");
+  if (n > 0 && (!a || !b)) return fail(QPAT_E_INVALID, "NULL input with n > 0");
+  double* part = nullptr;
+  hipError_t e = dot_scratch(&part);
+  if (e != hipSuccess) return fail(QPAT_E_HIP, std::string("dot_noalloc: symbol lookup: ") + hipGetErrorString(e));
+  e = launch_dot(a, b, n, part, dot_blocks(n), out, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(QPAT_E_HIP, std::string("dot_noalloc: ") + hipGetErrorString(e));
+  return QPAT_OK;
+}
+
 }  // extern "C"

@@ -134,6 +134,11 @@ hipError_t launch_dot(const float* a, const float* b, int64_t n, double* partial
 hipError_t launch_finite(const float* x, int64_t n, int* flag, hipStream_t st);
 // Blocks (and partial sums) of the inner product of length n: at most kDotBlocks.
 constexpr int kDotBlocks = 512;
+// Device address, on the current device, of the static partial-sum array of
+// qpat_dot_noalloc (kDotBlocks doubles), looked up once per device.
+hipError_t dot_scratch(double** ptr);
+// Largest length qpat_dot_noalloc accepts.
+constexpr int64_t kDotNoallocMaxN = int64_t(1) << 40;
 inline int dot_blocks(int64_t n) {
   const int64_t b = (n + kBlock - 1) / kBlock;
   return int(b < 1 ? 1 : (b > kDotBlocks ? kDotBlocks : b));
