@@ -215,6 +215,7 @@ def main():
     ap.add_argument("--no-medium", action="store_true", help="skip the sound-speed gradient measurement")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3-D solver measurement")
     ap.add_argument("--no-optical", action="store_true", help="skip the optical operator measurement")
+    ap.add_argument("--no-probe", action="store_true", help="skip the grid-barrier probe")
     ap.add_argument("--batches3d", default="1,3,8,16", help="batch sizes of the 3-D measurement")
     ap.add_argument("--tiles", default=None,
                     help="launch shape rows,cols,row_threads,col_threads of the headline plan (skips tuning)")
@@ -242,15 +243,15 @@ def main():
     nx, ny, nt, ns = prm["nx"], prm["ny"], prm["nt"], len(prm["sensor_xy"])
     plan = q.Plan(prm, cfg["c0"], cfg["rho0"])
     tiles_default = plan.tiles()
+    plan.set_graph(args.graph == "on")
+    stream = torch.cuda.Stream(device=dev)
     if args.tiles:
         plan.set_tiles(*[int(v) for v in args.tiles.split(",")])
         log(f"tiles {plan.tiles()} (given)")
     elif not args.no_tune:
         t = time.perf_counter()
-        plan.tune(1)
+        plan.tune(1, stream=stream)           # forward + adjoint candidates, in the launch mode timed below
         log(f"tuned tiles {plan.tiles()} (default {tiles_default}) in {time.perf_counter() - t:.1f} s")
-    plan.set_graph(args.graph == "on")
-    stream = torch.cuda.Stream(device=dev)
     p0 = T(cfg["p0"])
     res = T(qi.gaussian_field((nt, ns), 1823))
 
@@ -308,10 +309,12 @@ def main():
         gplan = q.Plan(gp, g["c0"], g["rho0"])
         tiles_1 = tiles_b = gplan.tiles()
         if not args.no_tune:                      # each path gets the launch shape tuned for its batch
-            gplan.tune(1)
+            gplan.tune(1, stream=stream)          # plain calls launch eagerly
             tiles_1 = gplan.tiles()
-            gplan.tune(B)
+            gplan.set_graph(args.graph == "on")
+            gplan.tune(B, stream=stream)          # the batched call in its launch mode
             tiles_b = gplan.tiles()
+            gplan.set_graph(False)
         vs = T(np.stack([qi.smooth_noise(1024, 1024, 8.0, 3000 + j) for j in range(B)]))
         with torch.cuda.stream(stream):
             gplan.set_tiles(*tiles_1)
@@ -369,26 +372,15 @@ def main():
         plans = [q.Plan(p["params"], p["c0"], p["rho0"]) for p in probs]
         xs = [T(p["p0"]) for p in probs]
         pts = sum(2.0 * p["params"]["nx"] * p["params"]["ny"] * p["params"]["nt"] for p in probs)
-        # launch shapes per grid size: tuned for one vector (plain) and for the
-        # number of problems of that size (batched)
-        # one shared launch shape for the mixed batch (a launch runs with the
-        # largest LDS and thread count of its items): tuned on the largest grid
-        # for the number of problems of that size, and applied to every plan
+        # plain path: every problem alone, with the launch shape tuned for one
+        # vector of its grid size
         sizes = sorted({p["params"]["nx"] for p in probs})
-        shape_1, shape_b = {}, {}
+        shape_1 = {}
         for n in sizes:
             group = [pl for pl, p in zip(plans, probs) if p["params"]["nx"] == n]
-            shape_1[n] = group[0].tiles()
             if not args.no_tune:
-                group[0].tune(1)
-                shape_1[n] = group[0].tiles()
-        big = [pl for pl, p in zip(plans, probs) if p["params"]["nx"] == sizes[-1]]
-        shared = big[0].tiles()
-        if not args.no_tune:
-            big[0].tune(len(big))
-            shared = big[0].tiles()
-        for n in sizes:
-            shape_b[n] = shared
+                group[0].tune(1, stream=stream)
+            shape_1[n] = group[0].tiles()
         for pl, p in zip(plans, probs):
             pl.set_tiles(*shape_1[p["params"]["nx"]])
         def timed(fn, reps):
@@ -414,13 +406,13 @@ def main():
             sync()
             t_plain, runs_plain = timed(plain_jtjv, REPEATS)
             t_plain_jv, runs_plain_jv = timed(plain_jv, REPEATS)
-            for pl, p in zip(plans, probs):
-                try:
-                    pl.set_tiles(*shape_b[p["params"]["nx"]])
-                except q.QpatError:               # not valid for this grid: keep its own
-                    shape_b[p["params"]["nx"]] = pl.tiles()
+            # batched path: launch shapes per grid size and the schedule (one
+            # launch set for all, or one per grid size on forked streams) from
+            # the batch tuner
             bat = q.Batch(plans)
             bat.set_graph(args.graph == "on")
+            sched = bat.tune(stream=stream) if not args.no_tune else bat.schedule()
+            shape_b = {n: next(pl for pl, p in zip(plans, probs) if p["params"]["nx"] == n).tiles() for n in sizes}
             bat.jtjv(xs)                          # warm-up (captures the graphs)
             bat.forward(xs)
             sync()
@@ -443,6 +435,8 @@ def main():
                                     "jv_plain": [round(v, 4) for v in runs_plain_jv],
                                     "jv_batched": [round(v, 4) for v in runs_batch_jv]},
                          "grid_point_steps_per_s_batched": round(pts / t_batch, 1),
+                         "schedule": ["one launch set for all problems",
+                                      "one launch sequence per grid size on forked streams"][sched],
                          "tiles_plain": {str(n): list(shape_1[n]) for n in sizes},
                          "tiles_batched": {str(n): list(shape_b[n]) for n in sizes}}
         del bat, plans, xs
@@ -621,6 +615,26 @@ def main():
         out["optical"] = {"workload": "P1-FEM diffusion approximation (Robin boundary) on the grid-matched mesh, "
                                       "4 illuminations, FP64 CG preconditioned by a multigrid V-cycle, to 1e-8",
                           "bytes_per_node_per_iteration": OPT_BYTES_PER_NODE_ITER, "runs": runs}
+
+    # ------------------------------------------------------------ persistent launch vs kernel boundaries
+    # One exchange step of a single-vector solve (every block writes its share
+    # of 2 MiB, the two spectra a 512^2 pass hands on, then reads another
+    # block's share) synchronised by a grid barrier inside one cooperative
+    # kernel (flat and hierarchical) or by a kernel boundary in a graph.
+    if not args.no_probe:
+        designs = {0: "barrier_flat", 1: "barrier_hierarchical", 2: "kernel_boundary_graph"}
+        probe = {}
+        with torch.cuda.stream(stream):
+            for nb in (256, 512):
+                for words_total in (0, 1 << 19):
+                    for d, name in designs.items():
+                        us, to = q.probe_barrier(d, nb, 256, 400, words_total // nb, stream=stream)
+                        probe[f"{name}_{nb}blocks_{'2MiB' if words_total else 'nodata'}"] = \
+                            {"us_per_step": round(us, 2), "timed_out": to}
+        log("grid barrier probe (us per exchange step): " +
+            ", ".join(f"{k} {v['us_per_step']}" for k, v in probe.items()))
+        out["persistent_probe"] = {"what": "one exchange step (write own slot, synchronise, read another block's "
+                                           "slot), 256 threads per block", "runs": probe}
 
     # ------------------------------------------------------------ CPU baseline (oracle)
     if not args.no_cpu:

@@ -180,9 +180,14 @@ qpat_status qpat_medium_grad(qpat_plan plan, const float* p0, const float* res, 
  * threads per block of each pass (64, 128, 256 or 512; rows*nx and cols*ny at
  * most 8 times the threads; a block's LDS within the 160 KB of a gfx950
  * work-group).  qpat_tune times the candidates on `stream` for
- * `batch` vectors (short forward solves, synchronising the stream) and keeps
- * the fastest; results are cached per (nx, ny, batch, lossy) in the file named
- * by QPAT_TUNE_CACHE, if set.  row_threads / col_threads may be NULL in
+ * `batch` vectors and keeps the fastest: each candidate runs 16 forward
+ * iterates and the 16 adjoint iterates that undo them (every pass kind of a
+ * forward + adjoint pair), launched the way the plan's calls launch them
+ * (captured and replayed as a hipGraph when graph mode is on; the stream is
+ * synchronised).  Results are cached per (nx, ny, batch, lossy, graph mode)
+ * in the file named by QPAT_TUNE_CACHE, if set, one line
+ * "nx ny batch lossy graph rows cols row_threads col_threads" per shape; a
+ * plan whose key is in the file takes that shape without timing.  row_threads / col_threads may be NULL in
  * qpat_get_tiles. */
 qpat_status qpat_set_tiles(qpat_plan plan, int32_t rows, int32_t cols, int32_t row_threads,
                            int32_t col_threads);
@@ -205,6 +210,25 @@ qpat_status qpat_tune(qpat_plan plan, int32_t batch, qpat_stream stream);
 qpat_status qpat_time_pass(qpat_plan plan, int32_t pass, int32_t batch, int32_t reps,
                            qpat_stream stream, float* ms_per_launch);
 
+/* Diagnostic probe of the persistent-launch alternative: the mean time of
+ * one exchange step of `nblocks` blocks of `threads` threads, each block
+ * writing `words` floats to its slot of a device buffer and then reading the
+ * slot of the next block, with the blocks synchronised in between by
+ *   design 0  a device-wide barrier in a cooperative launch (one arrival counter),
+ *   design 1  a hierarchical barrier in a cooperative launch (an arrival
+ *             counter per XCD group, then a global counter and a generation
+ *             word polled by one lane per block with back-off),
+ *   design 2  kernel boundaries: one launch per step, replayed from a hipGraph.
+ * Steps are timed with HIP events on `stream` (which is synchronised) as the
+ * difference of runs of `iters` and iters/10 steps, so launch costs cancel.
+ * Every wait is bounded: *timed_out is set when a block gave up waiting (the
+ * kernel then ends early and *us_per_step is meaningless).  Cooperative
+ * designs need every block resident (QPAT_E_UNSUPPORTED otherwise).  Limits:
+ * threads 64..1024 (multiple of 64), nblocks 1..4096, iters 2..100000, words
+ * 0..2^20.  The probe allocates and frees its own buffers. */
+qpat_status qpat_probe_barrier(int32_t design, int32_t nblocks, int32_t threads, int32_t iters, int32_t words,
+                               qpat_stream stream, float* us_per_step, int32_t* timed_out);
+
 /* hipGraph mode: when enabled, the kernel sequence of a forward / adjoint /
  * jtjv call is captured into a hipGraph on first use and replayed on later
  * calls with the same operation, batch and buffer addresses. */
@@ -224,6 +248,22 @@ qpat_status qpat_batch_adjoint(qpat_batch batch, const float* const* res, float*
 qpat_status qpat_batch_jtjv(qpat_batch batch, const float* const* v, float* const* out,
                             qpat_stream stream);
 qpat_status qpat_batch_set_graph(qpat_batch batch, int32_t enable);
+/* Schedule of a batch.  0: one launch per pass covers every problem (a
+ * launch runs with the largest LDS and thread count of its problems).  1: one
+ * launch sequence per grid size (nx, ny), each with the launch shape of its
+ * plans, the sequences running side by side on streams of the batch forked
+ * from and joined back into the caller's stream (inside the captured graph
+ * in graph mode).  Setting a schedule rebuilds the batch's launch state from
+ * the plans' current launch shapes (synchronising the device).  Results do
+ * not depend on the schedule. */
+qpat_status qpat_batch_set_schedule(qpat_batch batch, int32_t schedule);
+qpat_status qpat_batch_get_schedule(qpat_batch batch, int32_t* schedule);
+/* Autotune a batch: for every grid size, qpat_tune on its first plan for the
+ * number of problems of that size (in the batch's graph mode), that shape
+ * given to every plan of the size (the plans' launch shapes change); then
+ * both schedules timed on full forward + adjoint sweeps of the batch and the
+ * faster kept.  Synchronises `stream`; overwrites the batch's work buffers. */
+qpat_status qpat_batch_tune(qpat_batch batch, qpat_stream stream);
 
 /* Inner product with FP64 accumulation of two device float vectors of length
  * n; the result is written to *out (device double).  Deterministic: a fixed
@@ -280,6 +320,47 @@ qpat_status qpat_tv_value(qpat_tv tv, const float* x, double beta, int32_t batch
                           qpat_stream stream);
 /* y = a x + b y over n device floats (the vector updates of Algorithm 4). */
 qpat_status qpat_axpby(int64_t n, float a, const float* x, float b, float* y, qpat_stream stream);
+
+/* ---- Inexact-Newton reconstruction of p0 from acoustic data (Section 5.2.1:
+ * Algorithm 5, the lagged-diffusivity outer loop with step length 1, around
+ * Algorithm 4, PCG on the Gauss-Newton system J^T J d = -grad of eq apj with
+ * the TV priorconditioner M_gamma[X^k] of eq pre), for `batch` data sets of
+ * one plan solved side by side.  The unknown is p0 itself (J = H_a), the
+ * misfit eps = 0.5 |H_a X - data|^2, its gradient H_a^*(H_a X - data)
+ * (eq gr).  Every J^T J d is one batched qpat_jtjv call; the PCG scalars
+ * (r.z, d.J^T J d, alpha, beta) and the stopping ratio stay on the device as
+ * FP64 values; the host reads one flag per data set per PCG iteration (which
+ * data sets go on) and the misfits once per outer step.
+ *  beta, gamma   TV smoothing and preconditioner shift (> 0).
+ *  i_max, i_m, tol_in   PCG runs while i < i_max and (i < i_m or
+ *                1 - r_i.z_i / r_{i-i_m}.z_{i-i_m} > tol_in), as printed in Algorithm 4.
+ *  outer_max, tol_out   outer steps while k = 0 or 1 - eps^k / eps^{k-1} > tol_out,
+ *                at most outer_max (Algorithm 5; per data set).
+ *  solve_tol, solve_max_iter   the M_gamma solves (as qpat_tv_solve). */
+typedef struct {
+  double beta, gamma;
+  int32_t i_max, i_m;
+  double tol_in;
+  int32_t outer_max;
+  double tol_out;
+  double solve_tol;
+  int32_t solve_max_iter;
+} qpat_ld_params;
+typedef struct qpat_ld_s* qpat_ld;
+/* Work space (TV weights and solver, PCG vectors, FP64 scalars) for `batch`
+ * data sets of `plan` (batch in [1, 64]); the plan must outlive it. */
+qpat_status qpat_ld_create(qpat_plan plan, int32_t batch, qpat_ld* out);
+void qpat_ld_destroy(qpat_ld ld);
+/* data [batch][nt][ns] (device); x [batch][ny][nx] (device): the initial
+ * images on entry, the reconstructions on return.  eps_hist: host
+ * [batch][outer_max + 1] misfits eps^0 .. (entries past the last step repeat
+ * the last value); pcg_iters: host [batch][outer_max] PCG iterations of each
+ * outer step (-1 where a data set had already stopped); *outer_steps (may be
+ * NULL): outer steps run; *solve_iters (may be NULL): M_gamma solver
+ * iterations in all.  The gradient at the last iterate is not formed (no
+ * step uses it).  Synchronises `stream`. */
+qpat_status qpat_ld_run(qpat_ld ld, const float* data, float* x, const qpat_ld_params* p, double* eps_hist,
+                        int32_t* pcg_iters, int32_t* outer_steps, int32_t* solve_iters, qpat_stream stream);
 
 /* ---- 3-D solver (Section 3.2.3 with d = 3: velocity and density with three
  * components each, so the stacked state z_n of Section 3.2.4 holds 7N values,

@@ -49,6 +49,18 @@ class QpatParams3d(ctypes.Structure):
     ]
 
 
+class QpatLdParams(ctypes.Structure):
+    _fields_ = [
+        ("beta", c_double), ("gamma", c_double),
+        ("i_max", c_int32), ("i_m", c_int32),
+        ("tol_in", c_double),
+        ("outer_max", c_int32),
+        ("tol_out", c_double),
+        ("solve_tol", c_double),
+        ("solve_max_iter", c_int32),
+    ]
+
+
 STATUS = {0: "QPAT_OK", 1: "QPAT_E_INVALID", 2: "QPAT_E_UNSUPPORTED", 3: "QPAT_E_UNSTABLE",
           4: "QPAT_E_HIP", 5: "QPAT_E_OOM", 6: "QPAT_E_NONFINITE"}
 
@@ -73,6 +85,8 @@ _SIGS = {
                                  ctypes.POINTER(c_int32), ctypes.POINTER(c_int32)]),
     "qpat_tune": (c_int32, [c_void_p, c_int32, c_void_p]),
     "qpat_set_graph": (c_int32, [c_void_p, c_int32]),
+    "qpat_probe_barrier": (c_int32, [c_int32, c_int32, c_int32, c_int32, c_int32, c_void_p,
+                                     ctypes.POINTER(ctypes.c_float), ctypes.POINTER(c_int32)]),
     "qpat_time_pass": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_void_p, ctypes.POINTER(ctypes.c_float)]),
     "qpat_batch_create": (c_int32, [ctypes.POINTER(c_void_p), c_int32, ctypes.POINTER(c_void_p)]),
     "qpat_batch_destroy": (None, [c_void_p]),
@@ -80,6 +94,9 @@ _SIGS = {
     "qpat_batch_adjoint": (c_int32, [c_void_p, ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p), c_void_p]),
     "qpat_batch_jtjv": (c_int32, [c_void_p, ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p), c_void_p]),
     "qpat_batch_set_graph": (c_int32, [c_void_p, c_int32]),
+    "qpat_batch_set_schedule": (c_int32, [c_void_p, c_int32]),
+    "qpat_batch_get_schedule": (c_int32, [c_void_p, ctypes.POINTER(c_int32)]),
+    "qpat_batch_tune": (c_int32, [c_void_p, c_void_p]),
     "qpat_dot": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_void_p]),
     "qpat_dot_noalloc": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_void_p]),
     "qpat_tv_create": (c_int32, [c_int32, c_int32, c_int32, ctypes.POINTER(c_void_p)]),
@@ -91,6 +108,11 @@ _SIGS = {
     "qpat_tv_value": (c_int32, [c_void_p, c_void_p, ctypes.c_double, c_int32, ctypes.POINTER(ctypes.c_double),
                                 c_void_p]),
     "qpat_axpby": (c_int32, [c_int64, ctypes.c_float, c_void_p, ctypes.c_float, c_void_p, c_void_p]),
+    "qpat_ld_create": (c_int32, [c_void_p, c_int32, ctypes.POINTER(c_void_p)]),
+    "qpat_ld_destroy": (None, [c_void_p]),
+    "qpat_ld_run": (c_int32, [c_void_p, c_void_p, c_void_p, ctypes.POINTER(QpatLdParams),
+                              ctypes.POINTER(c_double), ctypes.POINTER(c_int32), ctypes.POINTER(c_int32),
+                              ctypes.POINTER(c_int32), c_void_p]),
     "qpat3d_validate": (c_int32, [ctypes.POINTER(QpatParams3d)]),
     "qpat3d_plan_create": (c_int32, [ctypes.POINTER(QpatParams3d), c_void_p, c_void_p, ctypes.POINTER(c_void_p)]),
     "qpat3d_plan_destroy": (None, [c_void_p]),

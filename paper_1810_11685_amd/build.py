@@ -14,7 +14,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqpat.so")
-SOURCES = ["kernels.hip", "plan.cpp", "recon.hip", "recon.cpp", "k3d.hip", "plan3d.cpp", "optical.hip", "optical.cpp"]
+SOURCES = ["kernels.hip", "plan.cpp", "recon.hip", "recon.cpp", "k3d.hip", "plan3d.cpp", "optical.hip", "optical.cpp", "probe.hip"]
 
 # -packed-fp32-ops keeps the compiler from emitting packed FP32 VALU ops.
 HIP_FLAGS = ["-O3", "--offload-arch=gfx950", "-mcode-object-version=5", "-fPIC", "-std=c++17",

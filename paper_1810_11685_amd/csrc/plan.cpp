@@ -434,10 +434,37 @@ struct qpat_batch_s {
   std::vector<void*> blocks;       // per-problem work allocations (owned)
   std::vector<Work> works;
   std::vector<float*> datas;
-  Exec exec;
+  // Schedule: the problems are split into groups, each advanced by one
+  // executor (one launch per pass for the group, with the launch shape of its
+  // plans).  Schedule 0 has one group; schedule 1 one group per grid size,
+  // the groups running side by side on streams forked from the caller's.
+  struct Group {
+    std::vector<int> members;
+    Exec exec;
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+  };
+  std::vector<std::unique_ptr<Group>> groups;
+  int schedule = 0;
+  hipEvent_t fork = nullptr;
   bool graph = false;
+  std::map<int, std::pair<hipGraph_t, hipGraphExec_t>> graphs;  // whole fork/join sequences, by operation
+  void release_groups() {
+    for (auto& g : graphs) {
+      if (g.second.second) (void)hipGraphExecDestroy(g.second.second);
+      if (g.second.first) (void)hipGraphDestroy(g.second.first);
+    }
+    graphs.clear();
+    for (auto& g : groups) {
+      g->exec.release();
+      if (g->stream) (void)hipStreamDestroy(g->stream);
+      if (g->done) (void)hipEventDestroy(g->done);
+    }
+    groups.clear();
+  }
   ~qpat_batch_s() {
-    exec.release();
+    release_groups();
+    if (fork) (void)hipEventDestroy(fork);
     for (void* b : blocks)
       if (b) (void)hipFree(b);
   }
@@ -845,7 +872,7 @@ qpat_status do_adjoint(qpat_plan P, const float* res, float* grad, int batch, hi
 // ---- tuning cache
 std::string tune_key(qpat_plan P, int batch) {
   char buf[128];
-  std::snprintf(buf, sizeof buf, "%d %d %d %d", P->prm.nx, P->prm.ny, batch, P->med.lossy);
+  std::snprintf(buf, sizeof buf, "%d %d %d %d %d", P->prm.nx, P->prm.ny, batch, P->med.lossy, int(P->graph));
   return buf;
 }
 
@@ -857,10 +884,10 @@ bool tune_lookup(const std::string& key, int* rt, int* ct, int* rthr, int* cthr)
   char line[256];
   bool found = false;
   while (std::fgets(line, sizeof line, f)) {
-    int a, b, c, d, r, co, rh, ch;
-    if (std::sscanf(line, "%d %d %d %d %d %d %d %d", &a, &b, &c, &d, &r, &co, &rh, &ch) == 8) {
+    int a, b, c, d, g, r, co, rh, ch;
+    if (std::sscanf(line, "%d %d %d %d %d %d %d %d %d", &a, &b, &c, &d, &g, &r, &co, &rh, &ch) == 9) {
       char k[128];
-      std::snprintf(k, sizeof k, "%d %d %d %d", a, b, c, d);
+      std::snprintf(k, sizeof k, "%d %d %d %d %d", a, b, c, d, g);
       if (key == k) {
         *rt = r;
         *ct = co;
@@ -904,33 +931,68 @@ qpat_status set_tiles(qpat_plan P, int rt, int ct, int rthr, int cthr) {
   return QPAT_OK;
 }
 
-// Time a short forward solve (first `steps` iterates) with the current tiles.
-qpat_status time_forward(qpat_plan P, int batch, int steps, hipStream_t st, float* ms) {
+// Time a short forward + adjoint with the current tiles: the first `steps`
+// forward iterates, then the adjoint iterates of the same span (every pass
+// kind of both sweeps), launched the way the plan's calls launch them -
+// captured in a hipGraph and replayed when graph mode is on.  Best of three.
+qpat_status time_pair(qpat_plan P, int batch, int steps, hipStream_t st, float* ms) {
   Exec* E = nullptr;
   STCHK(plan_exec(P, batch, &E));
+  // The adjoint writes its gradient, a field, through IO::out at iterates 0
+  // and -1: it needs a field-sized buffer of its own (the per-vector data
+  // buffer holds only nt * ns floats).  The forward iterates below do not
+  // write IO::out (no sensor-data combine).
+  float* gout = nullptr;
+  HIPCHK(hipMalloc(&gout, field_elems(P) * batch * sizeof(float)));
   std::vector<IO> io(batch);
   for (int i = 0; i < batch; ++i) {
     io[i].in = P->works[i].q;  // any field-sized buffer works as p0 for timing
-    io[i].out = P->datas[i];
+    io[i].out = gout + field_elems(P) * i;
   }
-  STCHK(exec_set_io(*E, io, st));
+  qpat_status rs = exec_set_io(*E, io, st);
+  if (rs != QPAT_OK) {
+    (void)hipFree(gout);
+    return rs;
+  }
   const int nl = std::min(P->prm.nt - 2, steps);
-  hipEvent_t a, b;
-  HIPCHK(hipEventCreate(&a));
-  HIPCHK(hipEventCreate(&b));
-  hipError_t e = seq_forward(*E, nl, st);  // warm-up
+  auto body = [&](hipStream_t s) -> hipError_t {
+    for (int n = -1; n <= nl; ++n) LCHK(fwd_iterate(*E, n, 0, s));
+    for (int n = nl; n >= -1; --n) LCHK(adj_iterate(*E, n, 0, s));
+    return hipSuccess;
+  };
+  hipGraph_t g = nullptr;
+  hipGraphExec_t ge = nullptr;
+  const bool use_graph = P->graph && st != nullptr;
+  hipEvent_t a = nullptr, b = nullptr;
+  hipError_t e = hipEventCreate(&a);
+  if (e == hipSuccess) e = hipEventCreate(&b);
+  if (e == hipSuccess && use_graph) {
+    e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      hipError_t e1 = body(st);
+      e = hipStreamEndCapture(st, &g);
+      if (e == hipSuccess) e = e1;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+  }
+  auto launch = [&]() -> hipError_t { return use_graph ? hipGraphLaunch(ge, st) : body(st); };
+  if (e == hipSuccess) e = launch();  // warm-up
   *ms = INFINITY;
   for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {  // best of three: the candidates differ by a few %
     float t = 0.f;
     e = hipEventRecord(a, st);
-    if (e == hipSuccess) e = seq_forward(*E, nl, st);
+    if (e == hipSuccess) e = launch();
     if (e == hipSuccess) e = hipEventRecord(b, st);
     if (e == hipSuccess) e = hipEventSynchronize(b);
     if (e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
     if (e == hipSuccess) *ms = std::min(*ms, t);
   }
-  (void)hipEventDestroy(a);
-  (void)hipEventDestroy(b);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);  // the launches are done with gout
+  if (ge) (void)hipGraphExecDestroy(ge);
+  if (g) (void)hipGraphDestroy(g);
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  (void)hipFree(gout);
   if (e != hipSuccess) return fail(QPAT_E_HIP, std::string("tune timing: ") + hipGetErrorString(e));
   return QPAT_OK;
 }
@@ -1281,7 +1343,7 @@ qpat_status qpat_tune(qpat_plan P, int32_t batch, qpat_stream stream) {
       if (!row_tile_ok(nx, ny, r, h)) continue;
       STCHK(set_tiles(P, r, bct, h, bch));
       float ms;
-      STCHK(time_forward(P, batch, steps, st, &ms));
+      STCHK(time_pair(P, batch, steps, st, &ms));
       if (ms < best) {
         best = ms;
         brt = r;
@@ -1294,7 +1356,7 @@ qpat_status qpat_tune(qpat_plan P, int32_t batch, qpat_stream stream) {
       if (!col_tile_ok(nx / 2, ny, c, h)) continue;
       STCHK(set_tiles(P, brt, c, brh, h));
       float ms;
-      STCHK(time_forward(P, batch, steps, st, &ms));
+      STCHK(time_pair(P, batch, steps, st, &ms));
       if (ms < best) {
         best = ms;
         bct = c;
@@ -1335,12 +1397,21 @@ qpat_status qpat_time_pass(qpat_plan P, int32_t pass, int32_t batch, int32_t rep
   hipStream_t st = (hipStream_t)stream;
   Exec* E = nullptr;
   STCHK(plan_exec(P, batch, &E));
+  // IO::out of an adjoint pass is a field (written at iterates 0 and -1),
+  // IO::in of a forward pass too (read at -1 and 0): field-sized buffers
+  float* fbuf = nullptr;
+  HIPCHK(hipMalloc(&fbuf, field_elems(P) * batch * sizeof(float)));
+  HIPCHK(hipMemset(fbuf, 0, field_elems(P) * batch * sizeof(float)));
   std::vector<IO> io(batch);
   for (int i = 0; i < batch; ++i) {
-    io[i].in = P->datas[i];
-    io[i].out = P->datas[i];
+    io[i].in = fbuf + field_elems(P) * i;
+    io[i].out = fbuf + field_elems(P) * i;
   }
-  STCHK(exec_set_io(*E, io, st));
+  qpat_status rs = exec_set_io(*E, io, st);
+  if (rs != QPAT_OK) {
+    (void)hipFree(fbuf);
+    return rs;
+  }
   const int n = std::min(1, P->prm.nt - 2);
   hipEvent_t a, b;
   HIPCHK(hipEventCreate(&a));
@@ -1352,8 +1423,10 @@ qpat_status qpat_time_pass(qpat_plan P, int32_t pass, int32_t batch, int32_t rep
   if (e == hipSuccess) e = hipEventSynchronize(b);
   float ms = 0.f;
   if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
+  (void)hipFree(fbuf);
   if (e != hipSuccess) return fail(QPAT_E_HIP, std::string("time_pass: ") + hipGetErrorString(e));
   *ms_per_launch = ms / reps;
   return QPAT_OK;
@@ -1376,6 +1449,45 @@ qpat_status qpat_plan_info(qpat_plan P, int32_t* nx, int32_t* ny, int32_t* nt, i
 }
 
 // ---- uneven batches
+// (Re)build the groups of a batch for its schedule from the plans' current
+// media and launch shapes.
+static qpat_status batch_build(qpat_batch B) {
+  B->release_groups();
+  const int count = int(B->plans.size());
+  std::vector<std::vector<int>> members;
+  if (B->schedule == 0) {
+    members.emplace_back();
+    for (int i = 0; i < count; ++i) members[0].push_back(i);
+  } else {
+    std::map<std::pair<int, int>, int> cls;
+    for (int i = 0; i < count; ++i) {
+      const auto key = std::make_pair(B->plans[i]->prm.nx, B->plans[i]->prm.ny);
+      auto it = cls.find(key);
+      if (it == cls.end()) {
+        it = cls.emplace(key, int(members.size())).first;
+        members.emplace_back();
+      }
+      members[it->second].push_back(i);
+    }
+  }
+  for (auto& mem : members) {
+    std::unique_ptr<qpat_batch_s::Group> g(new qpat_batch_s::Group());
+    g->members = mem;
+    std::vector<Item> items(mem.size());
+    for (size_t k = 0; k < mem.size(); ++k) {
+      items[k].m = B->plans[mem[k]]->med;
+      items[k].w = B->works[mem[k]];
+    }
+    STCHK(exec_build(g->exec, items));
+    if (members.size() > 1) {
+      HIPCHK(hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking));
+      HIPCHK(hipEventCreateWithFlags(&g->done, hipEventDisableTiming));
+    }
+    B->groups.push_back(std::move(g));
+  }
+  return QPAT_OK;
+}
+
 qpat_status qpat_batch_create(const qpat_plan* plans, int32_t count, qpat_batch* out) {
   if (!out) return fail(QPAT_E_INVALID, "out is NULL");
   *out = nullptr;
@@ -1387,31 +1499,21 @@ qpat_status qpat_batch_create(const qpat_plan* plans, int32_t count, qpat_batch*
     for (int j = 0; j < i; ++j)
       if (plans[j] == plans[i]) return fail(QPAT_E_INVALID, "a plan may appear only once in a batch");
   }
-  qpat_batch B = new qpat_batch_s();
+  std::unique_ptr<qpat_batch_s> B(new qpat_batch_s());
   B->plans.assign(plans, plans + count);
-  std::vector<Item> items(count);
   for (int i = 0; i < count; ++i) {
     void* blk = nullptr;
     size_t per = 0;
     std::vector<Work> w;
     std::vector<float*> dd;
-    qpat_status s = alloc_works(plans[i]->prm, 1, &blk, &per, w, dd);
-    if (s != QPAT_OK) {
-      delete B;
-      return s;
-    }
+    STCHK(alloc_works(plans[i]->prm, 1, &blk, &per, w, dd));
     B->blocks.push_back(blk);
     B->works.push_back(w[0]);
     B->datas.push_back(dd[0]);
-    items[i].m = plans[i]->med;
-    items[i].w = w[0];
   }
-  qpat_status s = exec_build(B->exec, items);
-  if (s != QPAT_OK) {
-    delete B;
-    return s;
-  }
-  *out = B;
+  HIPCHK(hipEventCreateWithFlags(&B->fork, hipEventDisableTiming));
+  STCHK(batch_build(B.get()));
+  *out = B.release();
   return QPAT_OK;
 }
 
@@ -1423,40 +1525,170 @@ void qpat_batch_destroy(qpat_batch B) {
 
 static qpat_status batch_io(qpat_batch B, const float* const* in, float* const* out, bool internal_in,
                             bool internal_out, hipStream_t st) {
-  std::vector<IO> io(B->plans.size());
-  for (size_t i = 0; i < B->plans.size(); ++i) {
-    io[i].in = internal_in ? B->datas[i] : in[i];
-    io[i].out = internal_out ? B->datas[i] : out[i];
-    if (!io[i].in || !io[i].out) return fail(QPAT_E_INVALID, "NULL pointer in batch arrays");
+  for (auto& g : B->groups) {
+    std::vector<IO> io(g->members.size());
+    for (size_t k = 0; k < g->members.size(); ++k) {
+      const int i = g->members[k];
+      io[k].in = internal_in ? B->datas[i] : in[i];
+      io[k].out = internal_out ? B->datas[i] : out[i];
+      if (!io[k].in || !io[k].out) return fail(QPAT_E_INVALID, "NULL pointer in batch arrays");
+    }
+    STCHK(exec_set_io(g->exec, io, st));
   }
-  return exec_set_io(B->exec, io, st);
+  return QPAT_OK;
+}
+
+// The forward or adjoint sweep of every group: on `st` for one group, else
+// forked onto the groups' streams and joined back into `st`.
+static hipError_t batch_body(qpat_batch B, int op, hipStream_t st) {
+  auto sweep = [&](Exec& E, hipStream_t s) {
+    return op == OP_FWD ? seq_forward(E, E.max_nt - 2, s) : seq_adjoint(E, s);
+  };
+  if (B->groups.size() == 1) return sweep(B->groups[0]->exec, st);
+  LCHK(hipEventRecord(B->fork, st));
+  for (auto& g : B->groups) {
+    LCHK(hipStreamWaitEvent(g->stream, B->fork, 0));
+    LCHK(sweep(g->exec, g->stream));
+    LCHK(hipEventRecord(g->done, g->stream));
+  }
+  for (auto& g : B->groups) LCHK(hipStreamWaitEvent(st, g->done, 0));
+  return hipSuccess;
+}
+
+static qpat_status batch_run(qpat_batch B, int op, hipStream_t st) {
+  if (!B->graph || st == nullptr) {
+    hipError_t e = batch_body(B, op, st);
+    if (e != hipSuccess) return fail(QPAT_E_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+    return QPAT_OK;
+  }
+  auto it = B->graphs.find(op);
+  if (it == B->graphs.end()) {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    hipError_t e = batch_body(B, op, st);
+    hipError_t e2 = hipStreamEndCapture(st, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return fail(QPAT_E_HIP, std::string("graph capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    HIPCHK(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+    it = B->graphs.emplace(op, std::make_pair(g, ge)).first;
+  }
+  HIPCHK(hipGraphLaunch(it->second.second, st));
+  return QPAT_OK;
 }
 
 qpat_status qpat_batch_forward(qpat_batch B, const float* const* p0, float* const* data, qpat_stream stream) {
   if (!B || !p0 || !data) return fail(QPAT_E_INVALID, "NULL argument");
   STCHK(batch_io(B, p0, data, false, false, (hipStream_t)stream));
-  return exec_run(B->exec, OP_FWD, B->graph, (hipStream_t)stream);
+  return batch_run(B, OP_FWD, (hipStream_t)stream);
 }
 
 qpat_status qpat_batch_adjoint(qpat_batch B, const float* const* res, float* const* grad, qpat_stream stream) {
   if (!B || !res || !grad) return fail(QPAT_E_INVALID, "NULL argument");
   STCHK(batch_io(B, res, grad, false, false, (hipStream_t)stream));
-  return exec_run(B->exec, OP_ADJ, B->graph, (hipStream_t)stream);
+  return batch_run(B, OP_ADJ, (hipStream_t)stream);
 }
 
 qpat_status qpat_batch_jtjv(qpat_batch B, const float* const* v, float* const* out, qpat_stream stream) {
   if (!B || !v || !out) return fail(QPAT_E_INVALID, "NULL argument");
   hipStream_t st = (hipStream_t)stream;
   STCHK(batch_io(B, v, nullptr, false, true, st));
-  STCHK(exec_run(B->exec, OP_FWD, B->graph, st));
+  STCHK(batch_run(B, OP_FWD, st));
   STCHK(batch_io(B, nullptr, out, true, false, st));
-  return exec_run(B->exec, OP_ADJ, B->graph, st);
+  return batch_run(B, OP_ADJ, st);
 }
 
 qpat_status qpat_batch_set_graph(qpat_batch B, int32_t enable) {
   if (!B) return fail(QPAT_E_INVALID, "batch is NULL");
   B->graph = enable != 0;
   return QPAT_OK;
+}
+
+qpat_status qpat_batch_set_schedule(qpat_batch B, int32_t schedule) {
+  if (!B) return fail(QPAT_E_INVALID, "batch is NULL");
+  if (schedule != 0 && schedule != 1) return fail(QPAT_E_INVALID, "schedule must be 0 or 1");
+  (void)hipDeviceSynchronize();  // the groups' buffers may still be in use
+  B->schedule = schedule;
+  return batch_build(B);
+}
+
+qpat_status qpat_batch_get_schedule(qpat_batch B, int32_t* schedule) {
+  if (!B || !schedule) return fail(QPAT_E_INVALID, "NULL argument");
+  *schedule = B->schedule;
+  return QPAT_OK;
+}
+
+qpat_status qpat_batch_tune(qpat_batch B, qpat_stream stream) {
+  if (!B) return fail(QPAT_E_INVALID, "batch is NULL");
+  hipStream_t st = (hipStream_t)stream;
+  // launch shapes: per grid size, tuned on its first plan for the number of
+  // problems of that size and given to every plan of that size
+  std::map<std::pair<int, int>, std::vector<qpat_plan>> cls;
+  for (qpat_plan P : B->plans) cls[{P->prm.nx, P->prm.ny}].push_back(P);
+  for (auto& c : cls) {
+    qpat_plan P0 = c.second[0];
+    const bool g0 = P0->graph;
+    P0->graph = B->graph;
+    qpat_status s = qpat_tune(P0, int32_t(c.second.size()), stream);
+    P0->graph = g0;
+    STCHK(s);
+    for (qpat_plan P : c.second) STCHK(set_tiles(P, P0->rt, P0->ct, P0->rthr, P0->cthr));
+  }
+  // schedule: a full forward + adjoint of the batch under each, best of two
+  std::vector<size_t> goff(B->plans.size());
+  size_t gtot = 0;
+  for (size_t i = 0; i < B->plans.size(); ++i) {
+    goff[i] = gtot;
+    gtot += size_t(B->plans[i]->prm.nx) * B->plans[i]->prm.ny;
+  }
+  float* gbuf = nullptr;
+  HIPCHK(hipMalloc(&gbuf, gtot * sizeof(float)));
+  float best = INFINITY;
+  int best_s = 0;
+  hipEvent_t a = nullptr, b = nullptr;
+  HIPCHK(hipEventCreate(&a));
+  HIPCHK(hipEventCreate(&b));
+  qpat_status rc = QPAT_OK;
+  for (int sch = 0; sch < 2 && rc == QPAT_OK; ++sch) {
+    B->schedule = sch;
+    (void)hipStreamSynchronize(st);
+    rc = batch_build(B);
+    if (rc != QPAT_OK) break;
+    std::vector<const float*> in(B->plans.size());
+    std::vector<float*> outp(B->plans.size());
+    for (size_t i = 0; i < B->plans.size(); ++i) {
+      in[i] = B->works[i].q;        // any field-sized buffer works as p0 for timing
+      outp[i] = gbuf + goff[i];     // gradients: field-sized buffers of their own
+    }
+    for (int rep = 0; rep < 3 && rc == QPAT_OK; ++rep) {  // warm-up (and graph capture), then two timed
+      float t = 0.f;
+      hipError_t e = hipEventRecord(a, st);
+      if (e == hipSuccess) {
+        rc = batch_io(B, in.data(), nullptr, false, true, st);
+        if (rc == QPAT_OK) rc = batch_run(B, OP_FWD, st);
+        if (rc == QPAT_OK) rc = batch_io(B, nullptr, outp.data(), true, false, st);
+        if (rc == QPAT_OK) rc = batch_run(B, OP_ADJ, st);
+      }
+      if (rc != QPAT_OK) break;
+      if (e == hipSuccess) e = hipEventRecord(b, st);
+      if (e == hipSuccess) e = hipEventSynchronize(b);
+      if (e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
+      if (e != hipSuccess) rc = fail(QPAT_E_HIP, std::string("batch tune timing: ") + hipGetErrorString(e));
+      if (rc == QPAT_OK && rep > 0 && t < best) {
+        best = t;
+        best_s = sch;
+      }
+    }
+  }
+  (void)hipStreamSynchronize(st);
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  (void)hipFree(gbuf);
+  STCHK(rc);
+  B->schedule = best_s;
+  return batch_build(B);
 }
 
 // ---- reductions

@@ -56,8 +56,9 @@ struct Work {
 
 // Per-call input / output pointers of one vector.
 struct IO {
-  const float* in;   // forward: p0 [ny][nx]; adjoint: residual [nt][ns]; apply: field
-  float* out;        // forward: data [nt][ns]; adjoint: gradient [ny][nx]; apply: field
+  const float* in;   // forward: p0 [ny][nx] (read at iterates -1, 0); adjoint: residual [nt][ns]; apply: field
+  float* out;        // forward: data [nt][ns] (sensor-data combine); adjoint: gradient [ny][nx] (written at
+                     // iterates 0 and -1); apply: field
   float* sens;       // sound-speed sensitivities dp^m/dc, [slots][ny][nx] (RM_X passes only)
   double* gc;        // adjoint: correlation sum_m p*^m dp^m/dc [ny][nx] (RM_X passes only)
 };

@@ -345,7 +345,110 @@ axpby_kernel(int64_t n, float a, const float* __restrict__ x, float b, float* __
     y[k] = a * x[k] + b * y[k];
 }
 
+// ---- PCG of Algorithm 4 with its scalars on the device, for `batch` fields
+// of n values ([batch][n]); rz is the history r_i.z_i, [batch][rzs]
+__global__ void __launch_bounds__(kRedThreads)
+ld_dot_kernel(const float* __restrict__ a, const float* __restrict__ b, size_t n, double* __restrict__ part) {
+  __shared__ double red[kRedThreads / 64];
+  const size_t base = size_t(blockIdx.y) * n;
+  double acc = 0.0;
+  for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < n; k += size_t(gridDim.x) * blockDim.x)
+    acc += double(a[base + k]) * double(b[base + k]);
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) part[size_t(blockIdx.y) * kRedBlocks + blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(kRedThreads)
+ld_total_kernel(const double* __restrict__ part, double* __restrict__ out, int ostride, double scale) {
+  __shared__ double red[kRedThreads / 64];
+  const double t = partial_total(part, blockIdx.x, red);
+  if (threadIdx.x == 0) out[size_t(blockIdx.x) * ostride] = scale * t;
+}
+
+// which fields run PCG iteration i: not finished, i < i_max and (i < i_m or
+// 1 - rz_i / rz_{i - i_m} > tol_in); a field that does not run is finished
+__global__ void ld_live_kernel(int batch, const double* __restrict__ rz, int rzs, int i, int i_max, int i_m,
+                               double tol_in, int* __restrict__ done, int* __restrict__ live) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= batch) return;
+  bool l = !done[f] && i < i_max;
+  if (l && i >= i_m) l = 1.0 - rz[size_t(f) * rzs + i] / rz[size_t(f) * rzs + i - i_m] > tol_in;
+  live[f] = l ? 1 : 0;
+  if (!l) done[f] = 1;
+}
+
+// alpha = rz_i / (d . H d);  sol += alpha d;  r -= alpha H d   (live fields)
+__global__ void __launch_bounds__(kRedThreads)
+ld_step_kernel(size_t n, const double* __restrict__ rz, int rzs, int i, const double* __restrict__ dhd,
+               const int* __restrict__ live, const float* __restrict__ d, const float* __restrict__ hd,
+               float* __restrict__ sol, float* __restrict__ r) {
+  const int f = blockIdx.y;
+  if (!live[f]) return;
+  const float a = float(rz[size_t(f) * rzs + i] / dhd[f]);
+  const size_t base = size_t(f) * n;
+  for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < n; k += size_t(gridDim.x) * blockDim.x) {
+    sol[base + k] = a * d[base + k] + sol[base + k];
+    r[base + k] = -a * hd[base + k] + r[base + k];
+  }
+}
+
+// d = z + (rz_{i+1} / rz_i) d   (live fields)
+__global__ void __launch_bounds__(kRedThreads)
+ld_dir_kernel(size_t n, const double* __restrict__ rz, int rzs, int i, const int* __restrict__ live,
+              const float* __restrict__ z, float* __restrict__ d) {
+  const int f = blockIdx.y;
+  if (!live[f]) return;
+  const float bt = float(rz[size_t(f) * rzs + i + 1] / rz[size_t(f) * rzs + i]);
+  const size_t base = size_t(f) * n;
+  for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < n; k += size_t(gridDim.x) * blockDim.x)
+    d[base + k] = 1.0f * z[base + k] + bt * d[base + k];
+}
+
+// x += sol for the fields whose flag is set (the outer step of Algorithm 5)
+__global__ void __launch_bounds__(kRedThreads)
+ld_add_kernel(size_t n, const int* __restrict__ flag, const float* __restrict__ sol, float* __restrict__ x) {
+  const int f = blockIdx.y;
+  if (!flag[f]) return;
+  const size_t base = size_t(f) * n;
+  for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < n; k += size_t(gridDim.x) * blockDim.x)
+    x[base + k] = 1.0f * sol[base + k] + 1.0f * x[base + k];
+}
+
 }  // namespace
+
+hipError_t launch_ld_dots(const float* a, const float* b, size_t n, int batch, double* part, double* out,
+                          int ostride, double scale, hipStream_t st) {
+  hipLaunchKernelGGL(ld_dot_kernel, dim3(kRedBlocks, batch), dim3(kRedThreads), 0, st, a, b, n, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(ld_total_kernel, dim3(batch), dim3(kRedThreads), 0, st, part, out, ostride, scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_ld_live(int batch, const double* rz, int rzs, int i, int i_max, int i_m, double tol_in, int* done,
+                          int* live, hipStream_t st) {
+  hipLaunchKernelGGL(ld_live_kernel, dim3((batch + 63) / 64), dim3(64), 0, st, batch, rz, rzs, i, i_max, i_m, tol_in,
+                     done, live);
+  return hipGetLastError();
+}
+
+hipError_t launch_ld_step(size_t n, int batch, const double* rz, int rzs, int i, const double* dhd, const int* live,
+                          const float* d, const float* hd, float* sol, float* r, hipStream_t st) {
+  hipLaunchKernelGGL(ld_step_kernel, dim3(kRedBlocks, batch), dim3(kRedThreads), 0, st, n, rz, rzs, i, dhd, live, d,
+                     hd, sol, r);
+  return hipGetLastError();
+}
+
+hipError_t launch_ld_dir(size_t n, int batch, const double* rz, int rzs, int i, const int* live, const float* z,
+                         float* d, hipStream_t st) {
+  hipLaunchKernelGGL(ld_dir_kernel, dim3(kRedBlocks, batch), dim3(kRedThreads), 0, st, n, rz, rzs, i, live, z, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_ld_add(size_t n, int batch, const int* flag, const float* sol, float* x, hipStream_t st) {
+  hipLaunchKernelGGL(ld_add_kernel, dim3(kRedBlocks, batch), dim3(kRedThreads), 0, st, n, flag, sol, x);
+  return hipGetLastError();
+}
 
 hipError_t launch_tv_weights(const float* x, int nx, int ny, int batch, double beta, double* wh, double* wv,
                              hipStream_t st) {

@@ -48,4 +48,18 @@ hipError_t launch_cg_iteration(const TvCg& c, const MgLevel* lv, int nlev, int n
 hipError_t launch_cg_finish(const TvCg& c, float* out, int nx, int ny, int batch, hipStream_t st);
 hipError_t launch_axpby(int64_t n, float a, const float* x, float b, float* y, hipStream_t st);
 
+// PCG of Algorithm 4 with device scalars, `batch` fields of n values:
+// out[f * ostride] = scale * a_f . b_f (FP64; part holds [batch][kRedBlocks]);
+// live / done flags of iteration i; the alpha step; the beta direction update;
+// x += sol for the flagged fields.
+hipError_t launch_ld_dots(const float* a, const float* b, size_t n, int batch, double* part, double* out,
+                          int ostride, double scale, hipStream_t st);
+hipError_t launch_ld_live(int batch, const double* rz, int rzs, int i, int i_max, int i_m, double tol_in, int* done,
+                          int* live, hipStream_t st);
+hipError_t launch_ld_step(size_t n, int batch, const double* rz, int rzs, int i, const double* dhd, const int* live,
+                          const float* d, const float* hd, float* sol, float* r, hipStream_t st);
+hipError_t launch_ld_dir(size_t n, int batch, const double* rz, int rzs, int i, const int* live, const float* z,
+                         float* d, hipStream_t st);
+hipError_t launch_ld_add(size_t n, int batch, const int* flag, const float* sol, float* x, hipStream_t st);
+
 }  // namespace qpat

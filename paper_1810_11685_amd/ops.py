@@ -291,6 +291,36 @@ class Batch:
     def set_graph(self, enable: bool = True) -> None:
         check(lib().qpat_batch_set_graph(self._h, int(bool(enable))), "qpat_batch_set_graph")
 
+    def set_schedule(self, schedule: int) -> None:
+        """0: one launch per pass for every problem; 1: one launch sequence per
+        grid size, side by side on forked streams (qpat_batch_set_schedule)."""
+        check(lib().qpat_batch_set_schedule(self._h, int(schedule)), "qpat_batch_set_schedule")
+
+    def schedule(self) -> int:
+        v = ctypes.c_int32()
+        check(lib().qpat_batch_get_schedule(self._h, ctypes.byref(v)), "qpat_batch_get_schedule")
+        return int(v.value)
+
+    @on_stream
+    def tune(self, stream=None) -> int:
+        """Launch shapes per grid size and the schedule (qpat_batch_tune); returns the schedule."""
+        check(lib().qpat_batch_tune(self._h, _stream(stream)), "qpat_batch_tune")
+        return self.schedule()
+
+
+@on_stream
+def probe_barrier(design: int, nblocks: int, threads: int = 256, iters: int = 400, words: int = 0,
+                  stream=None) -> tuple[float, bool]:
+    """Mean microseconds of one exchange step under a grid barrier (design 0:
+    one counter, 1: hierarchical, cooperative launches) or kernel boundaries
+    in a graph (design 2), and whether a bounded wait gave up
+    (qpat_probe_barrier)."""
+    us = ctypes.c_float()
+    to = ctypes.c_int32()
+    check(lib().qpat_probe_barrier(design, nblocks, threads, iters, words, _stream(stream), ctypes.byref(us),
+                                   ctypes.byref(to)), "qpat_probe_barrier")
+    return float(us.value), bool(to.value)
+
 
 @on_stream
 def dot(a: torch.Tensor, b: torch.Tensor, stream=None) -> torch.Tensor:

@@ -67,6 +67,15 @@ def test_null_and_status_strings(q):
     for s in range(7):
         assert L.qpat_status_string(s)
     assert L.qpat_status_string(6) == b"non-finite output"
+    f, t = ctypes.c_float(), ctypes.c_int32()
+    assert L.qpat_probe_barrier(3, 256, 256, 10, 0, None, ctypes.byref(f), ctypes.byref(t)) == 1
+    assert L.qpat_probe_barrier(0, 256, 100, 10, 0, None, ctypes.byref(f), ctypes.byref(t)) == 1
+    assert L.qpat_probe_barrier(0, 256, 256, 1, 0, None, ctypes.byref(f), ctypes.byref(t)) == 1
+    hh = ctypes.c_void_p()
+    assert L.qpat_ld_create(None, 1, ctypes.byref(hh)) == 1 and hh.value is None
+    assert L.qpat_ld_run(None, None, None, None, None, None, None, None, None) == 1
+    assert L.qpat_batch_set_schedule(None, 1) == 1
+    assert L.qpat_batch_tune(None, None) == 1
     assert L.qpat_set_check(None, 1) == 1
     assert L.qpat_check(None, None) == 1
     h = ctypes.c_void_p()

@@ -142,9 +142,9 @@ def test_headline_full_length_in_bench_launch(q):
     dobs = T(gold["dobs"])
     r_or = T(gold["data"].astype(np.float64) - gold["dobs"].astype(np.float64))
     with torch.cuda.stream(s):
+        plan.set_graph(True)
         plan.tune(1)
         tuned = plan.tiles()
-        plan.set_graph(True)
         outs = []
         for rep in range(2):              # the capture run, then a replay
             d = plan.forward(x)
@@ -308,11 +308,40 @@ def test_uneven_batch_matches_single(q):
         probs.append((q.Plan(prm, c0, rho0), p0))
     B = q.Batch([p for p, _ in probs])
     xs = [T(p0) for _, p0 in probs]
-    ds = B.forward(xs)
-    gs = B.jtjv(xs)
-    for (plan, _), x, d, g in zip(probs, xs, ds, gs):
-        assert np.array_equal(N(d), N(plan.forward(x)))
-        assert np.array_equal(N(g), N(plan.jtjv(x)))
+    refs = [(N(plan.forward(x)), N(plan.jtjv(x))) for (plan, _), x in zip(probs, xs)]
+    # one launch set for all problems, then one launch sequence per grid size
+    # on forked streams (eager and graph-replayed): the same bits
+    for schedule, graph in ((0, False), (1, False), (1, True), (1, True)):
+        B.set_schedule(schedule)
+        B.set_graph(graph)
+        assert B.schedule() == schedule
+        ds = B.forward(xs)
+        gs = B.jtjv(xs)
+        for (dref, gref), d, g in zip(refs, ds, gs):
+            assert np.array_equal(N(d), dref)
+            assert np.array_equal(N(g), gref)
+
+
+def test_uneven_batch_tuner(q):
+    """qpat_batch_tune picks launch shapes per grid size and a schedule; the
+    results stay those of the single plans."""
+    import torch
+    probs = []
+    for (nx, nt, seed) in [(64, 50, 3), (128, 40, 9), (64, 30, 11), (128, 60, 13)]:
+        prm, c0, rho0, p0 = problem(nx, nx, nt, seed=seed, ns=nx // 4)
+        probs.append((q.Plan(prm, c0, rho0), p0))
+    xs = [T(p0) for _, p0 in probs]
+    refs = [N(plan.jtjv(x)) for (plan, _), x in zip(probs, xs)]
+    B = q.Batch([p for p, _ in probs])
+    B.set_graph(True)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        sched = B.tune()
+        gs = B.jtjv(xs)
+        s.synchronize()
+    assert sched in (0, 1)
+    for ref, g in zip(refs, gs):
+        assert np.array_equal(N(g), ref)
 
 
 def test_dot_fp64_accumulation(q):

@@ -101,3 +101,53 @@ def test_uneven_batch_full_nt(q):
         zk = N(ck)[0, 1]
         for i, nm in enumerate(["vx", "vy", "rx", "ry", "p"]):
             assert rel(zk[i], rec[Kp][nm]) <= TOL, (p["params"]["nx"], nm)
+
+
+def test_barrier_probe_runs_and_ends(q):
+    """The persistent-launch probe: flat and hierarchical grid barriers in a
+    cooperative launch and kernel boundaries in a graph all finish (bounded
+    waits, no time-out) and report a positive time per exchange step."""
+    for d in (0, 1, 2):
+        us, timed_out = q.probe_barrier(d, 256, 256, 40, 512)
+        assert not timed_out, d
+        assert 0.0 < us < 1e4, (d, us)
+
+
+def test_tuner_shape_bitwise_and_cache_round_trip(q, tmp_path, monkeypatch):
+    """qpat_tune times forward + adjoint candidates in the plan's launch mode
+    (graph replay here) and returns a valid shape whose results equal the
+    default shape's bit for bit; it stores the shape in QPAT_TUNE_CACHE under
+    (nx, ny, batch, lossy, graph), and a later plan with that key takes the
+    stored shape without timing (a different valid shape written into the
+    file is returned as is)."""
+    import torch
+    c0, rho0 = qi.medium(128, 128, 31, 32, sigma_cells=6.0)
+    dx = 1e-4
+    prm = qi.make_params(128, 128, dx, 0.3 * dx / c0.max(), 60, c0.max(), qi.ring_sensors(32, 50, dx),
+                         pml_size=10)
+    x = torch.as_tensor(np.stack([qi.blobs(128, 128, 33, radius_cells=20), qi.gaussian_field((128, 128), 34)]),
+                        dtype=torch.float32, device="cuda")
+    plan = q.Plan(prm, c0, rho0)
+    d0 = plan.forward(x).cpu()
+    g0 = plan.adjoint(plan.forward(x)).cpu()
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("QPAT_TUNE_CACHE", str(cache))
+    plan.set_graph(True)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        shape = plan.tune(2)
+        d1 = plan.forward(x)
+        g1 = plan.adjoint(d1)
+        s.synchronize()
+    assert torch.equal(d1.cpu(), d0) and torch.equal(g1.cpu(), g0)
+    lines = cache.read_text().split("\n")
+    assert lines[0].split() == [str(v) for v in (128, 128, 2, 1, 1, *shape)]
+    other = (4, 2, 256, 256) if shape != (4, 2, 256, 256) else (2, 1, 128, 128)
+    cache.write_text(" ".join(str(v) for v in (128, 128, 2, 1, 1, *other)) + "\n")
+    plan2 = q.Plan(prm, c0, rho0)
+    plan2.set_graph(True)
+    with torch.cuda.stream(s):
+        assert plan2.tune(2) == other
+        d2 = plan2.forward(x)
+        s.synchronize()
+    assert torch.equal(d2.cpu(), d0)
