@@ -19,6 +19,10 @@ SOURCES = ["kernels.hip", "plan.cpp", "recon.hip", "recon.cpp", "k3d.hip", "plan
 # -packed-fp32-ops keeps the compiler from emitting packed FP32 VALU ops.
 HIP_FLAGS = ["-O3", "--offload-arch=gfx950", "-mcode-object-version=5", "-fPIC", "-std=c++17",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# Per-source compiler flags (none at present).
+SOURCE_FLAGS: dict[str, list[str]] = {}
+# roctx ranges around the entry points (shown by rocprofv3 --marker-trace)
+LINK_LIBS = ["-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx"]
 
 
 def hipcc() -> str:
@@ -43,12 +47,13 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
     jobs = jobs or min(len(SOURCES), max(1, min(os.cpu_count() or 1, 8)))
     with tempfile.TemporaryDirectory(prefix="qpat_build_") as tmpd:
         objs = [os.path.join(tmpd, src + ".o") for src in SOURCES]   # x.hip and x.cpp both exist
-        cmds = [[cc, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj] for src, obj in zip(SOURCES, objs)]
+        cmds = [[cc, *HIP_FLAGS, *SOURCE_FLAGS.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
+                for src, obj in zip(SOURCES, objs)]
         with ThreadPoolExecutor(max_workers=jobs) as ex:
             for f in [ex.submit(_run, c, verbose) for c in cmds]:
                 f.result()
         tmp = LIB + ".tmp"
-        _run([cc, *HIP_FLAGS, "-shared", *objs, "-o", tmp], verbose)
+        _run([cc, *HIP_FLAGS, "-shared", *objs, "-o", tmp, *LINK_LIBS], verbose)
         os.replace(tmp, LIB)
     return LIB
 

@@ -118,6 +118,14 @@ enum Flags : int {
 };
 constexpr int kSlotShift = 8;  // RM_X passes: flags >> kSlotShift is the sensitivity slot
 
+// roctx range for the lifetime of the object (plan.cpp).
+struct TraceRange {
+  explicit TraceRange(const char* name);
+  ~TraceRange();
+  TraceRange(const TraceRange&) = delete;
+  TraceRange& operator=(const TraceRange&) = delete;
+};
+
 // Launch helpers implemented in kernels.hip.
 hipError_t launch_row(int mode, const Launch& L, bool uniform, int ntile, int chunk, int nblocks,
                       int threads, size_t lds, int n, int flags, hipStream_t st);

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/qpat.h"
+#include "qpat_internal.hpp"
 #include "recon_internal.hpp"
 
 namespace qpat {
@@ -326,6 +327,7 @@ void qpat_ld_destroy(qpat_ld L) {
 
 qpat_status qpat_ld_run(qpat_ld L, const float* data, float* x, const qpat_ld_params* p, double* eps_hist,
                         int32_t* pcg_iters, int32_t* outer_steps, int32_t* solve_iters, qpat_stream stream) {
+  const TraceRange trace_("qpat_ld_run");
   if (!L || !p) return set_error(QPAT_E_INVALID, "NULL argument");
   if (!data || !x) return set_error(QPAT_E_INVALID, "data and x must not be NULL");
   if (!eps_hist || !pcg_iters) return set_error(QPAT_E_INVALID, "eps_hist and pcg_iters must not be NULL");
