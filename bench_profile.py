@@ -10,6 +10,12 @@ summaries of rocprofv3 CSV output.
             --copy-mib 256 --out profiles/pmc_traffic.json
         combines two counter runs of the benchmark with two of the copy kernel
         into per-pass HBM traffic per launch.
+    python bench_profile.py passes --cfg gn1024 --batch 8 --tiles 2,1,256,256
+        times every pass kind of one plan on its own (qpat_time_pass), for
+        counter runs that should see one pass kind per kernel name.
+    python bench_profile.py table <pmc_dir> [<pmc_dir> ...]
+        per-pass averages of every counter found in rocprofv3 --pmc CSV
+        directories.
 """
 from __future__ import annotations
 
@@ -124,6 +130,44 @@ def pmc_summary(dfetch, dwrite, dcf, dcw, copy_mib, out):
     print(json.dumps(rec, indent=1))
 
 
+def time_passes(cfg: str, batch: int, tiles: str, reps: int, nt: int) -> None:
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    import paper_1810_11685_amd as q
+    import qpat_inputs as qi
+    from paper_1810_11685_amd.ops import PASSES
+    from bench import SCOPE_BYTES
+    g = qi.config(cfg, nt=nt)
+    plan = q.Plan(g["params"], g["c0"], g["rho0"])
+    if tiles:
+        plan.set_tiles(*[int(v) for v in tiles.split(",")])
+    n = g["params"]["nx"] * g["params"]["ny"]
+    for pid in range(len(PASSES)):
+        t = plan.time_pass(pid, batch=batch, reps=reps)
+        print(f"{PASSES[pid][0]:18s} {t * 1e3:8.1f} us  {SCOPE_BYTES[pid] * n * batch / (t * 1e-3) / 1e9:7.0f} GB/s",
+              flush=True)
+
+
+def counter_table(dirs) -> str:
+    """Per-pass mean of every counter in the given --pmc directories."""
+    vals = {}
+    names = set()
+    for d in dirs:
+        files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+        for f in files:
+            for r in csv.DictReader(open(f)):
+                p = pass_of(r["Kernel_Name"])
+                if p is None:
+                    continue
+                names.add(r["Counter_Name"])
+                vals.setdefault(p, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    cols = sorted(names)
+    lines = [f"{'pass':18s} " + " ".join(f"{c[:22]:>22s}" for c in cols)]
+    for p in sorted(vals):
+        row = [sum(vals[p][c]) / len(vals[p][c]) if c in vals[p] else float("nan") for c in cols]
+        lines.append(f"{p:18s} " + " ".join(f"{v:22.1f}" for v in row))
+    return "\n".join(lines)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -138,11 +182,23 @@ def main(argv=None):
     p.add_argument("copy_write")
     p.add_argument("--copy-mib", type=int, default=256)
     p.add_argument("--out", required=True)
+    t = sub.add_parser("passes")
+    t.add_argument("--cfg", default="gn1024")
+    t.add_argument("--batch", type=int, default=8)
+    t.add_argument("--tiles", default="")
+    t.add_argument("--reps", type=int, default=5)
+    t.add_argument("--nt", type=int, default=64)
+    tb = sub.add_parser("table")
+    tb.add_argument("dirs", nargs="+")
     a = ap.parse_args(argv)
     if a.cmd == "copy":
         copy_kernel(a.mib)
     elif a.cmd == "stats":
         print(stats_table(a.csv))
+    elif a.cmd == "passes":
+        time_passes(a.cfg, a.batch, a.tiles, a.reps, a.nt)
+    elif a.cmd == "table":
+        print(counter_table(a.dirs))
     else:
         pmc_summary(a.fetch, a.write, a.copy_fetch, a.copy_write, a.copy_mib, a.out)
 

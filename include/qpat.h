@@ -129,6 +129,16 @@ qpat_status qpat_jv(qpat_plan plan, const float* v, float* data, int32_t batch,
 qpat_status qpat_jtjv(qpat_plan plan, const float* v, float* out, int32_t batch,
                       qpat_stream stream);
 
+/* qpat_jtjv that also hands back the intermediate J v = H_a v: v [B][ny][nx]
+ * -> jv [B][nt][ns] and out [B][ny][nx] (device, caller-owned, not
+ * overlapping).  The same launches as qpat_jv followed by qpat_adjoint on its
+ * output, so jv is bitwise qpat_jv's and out bitwise qpat_jtjv's.  A
+ * Gauss-Newton solver that keeps J d for each search direction d can form
+ * J (x + sum a_i d_i) - y from the residual at x without another forward
+ * solve (J is linear in p0). */
+qpat_status qpat_jtjv_data(qpat_plan plan, const float* v, float* jv, float* out, int32_t batch,
+                           qpat_stream stream);
+
 /* One spectral operator on B fields: in [B][ny][nx] -> out [B][ny][nx]. */
 qpat_status qpat_apply(qpat_plan plan, int32_t op, const float* in, float* out, int32_t batch,
                        qpat_stream stream);
@@ -213,7 +223,8 @@ qpat_status qpat_time_pass(qpat_plan plan, int32_t pass, int32_t batch, int32_t 
 /* Diagnostic probe of the persistent-launch alternative: the mean time of
  * one exchange step of `nblocks` blocks of `threads` threads, each block
  * writing `words` floats to its slot of a device buffer and then reading the
- * slot of the next block, with the blocks synchronised in between by
+ * slot of the next block (as float4 vectors, all of a thread's loads in
+ * flight together), with the blocks synchronised in between by
  *   design 0  a device-wide barrier in a cooperative launch (one arrival counter),
  *   design 1  a hierarchical barrier in a cooperative launch (an arrival
  *             counter per XCD group, then a global counter and a generation
@@ -225,7 +236,7 @@ qpat_status qpat_time_pass(qpat_plan plan, int32_t pass, int32_t batch, int32_t 
  * kernel then ends early and *us_per_step is meaningless).  Cooperative
  * designs need every block resident (QPAT_E_UNSUPPORTED otherwise).  Limits:
  * threads 64..1024 (multiple of 64), nblocks 1..4096, iters 2..100000, words
- * 0..2^20.  The probe allocates and frees its own buffers. */
+ * 0..2^20 and a multiple of 4.  The probe allocates and frees its own buffers. */
 qpat_status qpat_probe_barrier(int32_t design, int32_t nblocks, int32_t threads, int32_t iters, int32_t words,
                                qpat_stream stream, float* us_per_step, int32_t* timed_out);
 
@@ -327,10 +338,15 @@ qpat_status qpat_axpby(int64_t n, float a, const float* x, float b, float* y, qp
  * the TV priorconditioner M_gamma[X^k] of eq pre), for `batch` data sets of
  * one plan solved side by side.  The unknown is p0 itself (J = H_a), the
  * misfit eps = 0.5 |H_a X - data|^2, its gradient H_a^*(H_a X - data)
- * (eq gr).  Every J^T J d is one batched qpat_jtjv call; the PCG scalars
+ * (eq gr).  Every J^T J d is one batched qpat_jtjv_data call; the PCG scalars
  * (r.z, d.J^T J d, alpha, beta) and the stopping ratio stay on the device as
  * FP64 values; the host reads one flag per data set per PCG iteration (which
- * data sets go on) and the misfits once per outer step.
+ * data sets go on) and the misfits once per outer step.  Because H_a is
+ * linear, the residual at X^{k+1} = X^k + sum_i alpha_i d_i is formed as
+ * r^k + sum_i alpha_i (H_a d_i) from the data of the PCG's own products, so
+ * an outer step costs its PCG products plus one adjoint solve (the gradient
+ * for the next step) and no forward solve; the first step skips the forward
+ * solve too when every initial image is zero (H_a 0 = 0).
  *  beta, gamma   TV smoothing and preconditioner shift (> 0).
  *  i_max, i_m, tol_in   PCG runs while i < i_max and (i < i_m or
  *                1 - r_i.z_i / r_{i-i_m}.z_{i-i_m} > tol_in), as printed in Algorithm 4.

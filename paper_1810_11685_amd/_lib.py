@@ -73,6 +73,7 @@ _SIGS = {
     "qpat_adjoint": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_void_p]),
     "qpat_jv": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_void_p]),
     "qpat_jtjv": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_void_p]),
+    "qpat_jtjv_data": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_void_p]),
     "qpat_apply": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_int32, c_void_p]),
     "qpat_ckpt_bytes": (c_int32, [c_void_p, c_int32, c_int32, ctypes.POINTER(c_size_t)]),
     "qpat_forward_ckpt": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_int32, c_void_p]),

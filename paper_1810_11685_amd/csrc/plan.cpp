@@ -1099,6 +1099,14 @@ qpat_status qpat_jtjv(qpat_plan P, const float* v, float* out, int32_t batch, qp
   return do_adjoint(P, nullptr, out, batch, (hipStream_t)stream, true);
 }
 
+qpat_status qpat_jtjv_data(qpat_plan P, const float* v, float* jv, float* out, int32_t batch, qpat_stream stream) {
+  const TraceRange trace_("qpat_jtjv_data");
+  STCHK(check_plan_call(P, v, out, batch));
+  if (!jv) return fail(QPAT_E_INVALID, "jv is NULL");
+  STCHK(do_forward(P, v, jv, batch, (hipStream_t)stream, false));
+  return do_adjoint(P, jv, out, batch, (hipStream_t)stream, false);
+}
+
 qpat_status qpat_apply(qpat_plan P, int32_t op, const float* in, float* out, int32_t batch, qpat_stream stream) {
   STCHK(check_plan_call(P, in, out, batch));
   static const int codes[6] = {MC_DXP, MC_DXM, MC_DYP, MC_DYM, MC_LDIS, MC_LABS};

@@ -87,16 +87,25 @@ __device__ bool grid_barrier(BarrierState* st, int design, unsigned k, int spin_
 }
 
 // One exchange step k: write this block's slot of buffer k & 1, (barrier),
-// read the next block's slot of the same buffer.
+// read the next block's slot of the same buffer.  Slots are float4 vectors
+// (words is a multiple of 4) and a thread's loads are unrolled so that they
+// are all in flight together, as in the solver's passes.
 __device__ __forceinline__ void write_slot(float* buf, int words, int k) {
-  float* dst = buf + (size_t(k & 1) * gridDim.x + blockIdx.x) * words;
-  for (int i = threadIdx.x; i < words; i += blockDim.x) dst[i] = float(k + i);
+  float4* dst = reinterpret_cast<float4*>(buf + (size_t(k & 1) * gridDim.x + blockIdx.x) * words);
+  const int n4 = words >> 2;
+#pragma unroll 4
+  for (int i = threadIdx.x; i < n4; i += blockDim.x) dst[i] = make_float4(float(k + i), 0.f, 0.f, 0.f);
 }
 __device__ __forceinline__ float read_slot(const float* buf, int words, int k) {
   const unsigned nb = gridDim.x;
-  const float* src = buf + (size_t(k & 1) * nb + (blockIdx.x + 1) % nb) * words;
+  const float4* src = reinterpret_cast<const float4*>(buf + (size_t(k & 1) * nb + (blockIdx.x + 1) % nb) * words);
+  const int n4 = words >> 2;
   float acc = 0.f;
-  for (int i = threadIdx.x; i < words; i += blockDim.x) acc += src[i];
+#pragma unroll 4
+  for (int i = threadIdx.x; i < n4; i += blockDim.x) {
+    const float4 v = src[i];
+    acc += (v.x + v.y) + (v.z + v.w);
+  }
   return acc;
 }
 
@@ -126,7 +135,7 @@ qpat_status probe_barrier(int design, int nblocks, int threads, int iters, int w
   if (threads < 64 || threads > 1024 || (threads & 63)) return set_error(QPAT_E_INVALID, "threads: 64..1024, multiple of 64");
   if (nblocks < 1 || nblocks > 4096) return set_error(QPAT_E_INVALID, "nblocks must be in [1, 4096]");
   if (iters < 2 || iters > 100000) return set_error(QPAT_E_INVALID, "iters must be in [2, 100000]");
-  if (words < 0 || words > (1 << 20)) return set_error(QPAT_E_INVALID, "words must be in [0, 2^20]");
+  if (words < 0 || words > (1 << 20) || (words & 3)) return set_error(QPAT_E_INVALID, "words must be a multiple of 4 in [0, 2^20]");
   if (!us_per_step || !timed_out) return set_error(QPAT_E_INVALID, "output pointer is NULL");
   int dev = 0;
   hipDeviceProp_t prop;

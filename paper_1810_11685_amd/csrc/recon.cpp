@@ -222,6 +222,7 @@ struct qpat_ld_s {
   int rzs = 0;                       // row stride of the rz history (i_max + 2 of the last run)
   void* mem = nullptr;
   float *res = nullptr, *grad = nullptr, *r = nullptr, *z = nullptr, *d = nullptr, *sol = nullptr, *hd = nullptr;
+  float *jd = nullptr, *hsol = nullptr;  // data [B][nt][ns]: H_a d of the current direction, H_a sol
   double *part = nullptr, *rz = nullptr, *dhd = nullptr, *eps = nullptr;
   int *live = nullptr, *done = nullptr, *flag = nullptr;
   int* h_int = nullptr;              // pinned: flags to and from the device
@@ -247,15 +248,27 @@ qpat_status ld_reserve_rz(qpat_ld L, int i_max) {
   return QPAT_OK;
 }
 
-// res = H x - data, eps_f = 0.5 |res_f|^2 (device), and, with `grad`, grad = H^* res (eq gr)
-qpat_status ld_misfit(qpat_ld L, const float* data, const float* x, bool grad, hipStream_t st) {
+// res = H x - data, eps_f = 0.5 |res_f|^2 (device) and grad = H^* res (eq gr).
+// When every x_f is zero, H x = 0 exactly and the forward solve is skipped
+// (res = -data, the value the solve would give).
+qpat_status ld_misfit(qpat_ld L, const float* data, const float* x, hipStream_t st) {
   const int B = L->batch;
-  qpat_status s = qpat_forward(L->plan, x, L->res, B, st);
-  if (s != QPAT_OK) return s;
-  TVCHK(launch_axpby(int64_t(L->D) * B, -1.0f, data, 1.0f, L->res, st));
+  const int64_t nd = int64_t(L->D) * B;
+  TVCHK(launch_ld_dots(x, x, L->N, B, L->part, L->eps, 1, 1.0, st));
+  TVCHK(hipMemcpyAsync(L->h_eps, L->eps, sizeof(double) * B, hipMemcpyDeviceToHost, st));
+  TVCHK(hipStreamSynchronize(st));
+  bool zero = true;
+  for (int b = 0; b < B; ++b) zero = zero && L->h_eps[b] == 0.0;
+  if (zero) {
+    TVCHK(hipMemcpyAsync(L->res, data, sizeof(float) * nd, hipMemcpyDeviceToDevice, st));
+    TVCHK(launch_axpby(nd, 0.0f, data, -1.0f, L->res, st));
+  } else {
+    qpat_status s = qpat_forward(L->plan, x, L->res, B, st);
+    if (s != QPAT_OK) return s;
+    TVCHK(launch_axpby(nd, -1.0f, data, 1.0f, L->res, st));
+  }
   TVCHK(launch_ld_dots(L->res, L->res, L->D, B, L->part, L->eps, 1, 0.5, st));
-  if (grad) return qpat_adjoint(L->plan, L->res, L->grad, B, st);
-  return QPAT_OK;
+  return qpat_adjoint(L->plan, L->res, L->grad, B, st);
 }
 
 qpat_status ld_read_eps(qpat_ld L, hipStream_t st) {
@@ -294,6 +307,7 @@ qpat_status qpat_ld_create(qpat_plan plan, int32_t batch, qpat_ld* out) {
   };
   const size_t o_res = take(datas * 4), o_grad = take(fields * 4), o_r = take(fields * 4), o_z = take(fields * 4),
                o_d = take(fields * 4), o_sol = take(fields * 4), o_hd = take(fields * 4),
+               o_jd = take(datas * 4), o_hsol = take(datas * 4),
                o_part = take(sizeof(double) * kRedBlocks * batch), o_dhd = take(sizeof(double) * batch),
                o_eps = take(sizeof(double) * batch), o_live = take(sizeof(int) * batch),
                o_done = take(sizeof(int) * batch), o_flag = take(sizeof(int) * batch);
@@ -306,6 +320,8 @@ qpat_status qpat_ld_create(qpat_plan plan, int32_t batch, qpat_ld* out) {
   L->d = reinterpret_cast<float*>(m + o_d);
   L->sol = reinterpret_cast<float*>(m + o_sol);
   L->hd = reinterpret_cast<float*>(m + o_hd);
+  L->jd = reinterpret_cast<float*>(m + o_jd);
+  L->hsol = reinterpret_cast<float*>(m + o_hsol);
   L->part = reinterpret_cast<double*>(m + o_part);
   L->dhd = reinterpret_cast<double*>(m + o_dhd);
   L->eps = reinterpret_cast<double*>(m + o_eps);
@@ -349,7 +365,7 @@ qpat_status qpat_ld_run(qpat_ld L, const float* data, float* x, const qpat_ld_pa
     for (int k = 0; k < K; ++k) pcg_iters[size_t(b) * K + k] = -1;
   }
   // eps^0 and the gradient at X^0
-  STCHK(ld_misfit(L, data, x, true, st));
+  STCHK(ld_misfit(L, data, x, st));
   STCHK(ld_read_eps(L, st));
   for (int b = 0; b < B; ++b) eps_hist[size_t(b) * (K + 1)] = L->h_eps[b];
   std::vector<int> active(B, 1);
@@ -371,6 +387,7 @@ qpat_status qpat_ld_run(qpat_ld L, const float* data, float* x, const qpat_ld_pa
     solves += it;
     TVCHK(hipMemcpyAsync(L->d, L->z, sizeof(float) * N * B, hipMemcpyDeviceToDevice, st));
     TVCHK(hipMemsetAsync(L->sol, 0, sizeof(float) * N * B, st));
+    TVCHK(hipMemsetAsync(L->hsol, 0, sizeof(float) * L->D * B, st));
     TVCHK(launch_ld_dots(L->r, L->z, N, B, L->part, L->rz, rzs, 1.0, st));   // rz_0
     for (int b = 0; b < B; ++b) L->h_int[b] = active[b] ? 0 : 1;          // done = not active
     TVCHK(hipMemcpyAsync(L->done, L->h_int, sizeof(int) * B, hipMemcpyHostToDevice, st));
@@ -385,9 +402,10 @@ qpat_status qpat_ld_run(qpat_ld L, const float* data, float* x, const qpat_ld_pa
         count[b] += L->h_int[b] != 0;
       }
       if (!any) break;
-      STCHK(qpat_jtjv(L->plan, L->d, L->hd, B, stream));                  // H d, one batched call
+      STCHK(qpat_jtjv_data(L->plan, L->d, L->jd, L->hd, B, stream));     // H_a d and H d, one batched call
       TVCHK(launch_ld_dots(L->d, L->hd, N, B, L->part, L->dhd, 1, 1.0, st));
       TVCHK(launch_ld_step(N, B, L->rz, rzs, i, L->dhd, L->live, L->d, L->hd, L->sol, L->r, st));
+      TVCHK(launch_ld_data_step(L->D, B, L->rz, rzs, i, L->dhd, L->live, L->jd, L->hsol, st));
       STCHK(qpat_tv_solve(L->tv, p->gamma, L->r, L->z, B, p->solve_tol, p->solve_max_iter, &it, stream));
       solves += it;
       TVCHK(launch_ld_dots(L->r, L->z, N, B, L->part, L->rz + i + 1, rzs, 1.0, st));
@@ -399,8 +417,11 @@ qpat_status qpat_ld_run(qpat_ld L, const float* data, float* x, const qpat_ld_pa
     TVCHK(launch_ld_add(N, B, L->flag, L->sol, x, st));
     for (int b = 0; b < B; ++b)
       if (active[b]) pcg_iters[size_t(b) * K + k] = count[b];
-    // eps^{k+1}; the gradient only if another outer step can follow
-    STCHK(ld_misfit(L, data, x, false, st));
+    // eps^{k+1}: the residual H_a X^{k+1} - data = res + H_a sol (H_a linear), with
+    // H_a sol accumulated from the PCG's products; the gradient only if another
+    // outer step can follow
+    TVCHK(launch_ld_add(L->D, B, L->flag, L->hsol, L->res, st));
+    TVCHK(launch_ld_dots(L->res, L->res, L->D, B, L->part, L->eps, 1, 0.5, st));
     STCHK(ld_read_eps(L, st));
     for (int b = 0; b < B; ++b) {
       double* h = eps_hist + size_t(b) * (K + 1);

@@ -392,6 +392,19 @@ ld_step_kernel(size_t n, const double* __restrict__ rz, int rzs, int i, const do
   }
 }
 
+// hsol += alpha jd (live data sets): the data of the step that ld_step_kernel
+// adds to sol, with the same FP32 alpha
+__global__ void __launch_bounds__(kRedThreads)
+ld_data_step_kernel(size_t nd, const double* __restrict__ rz, int rzs, int i, const double* __restrict__ dhd,
+                    const int* __restrict__ live, const float* __restrict__ jd, float* __restrict__ hsol) {
+  const int f = blockIdx.y;
+  if (!live[f]) return;
+  const float a = float(rz[size_t(f) * rzs + i] / dhd[f]);
+  const size_t base = size_t(f) * nd;
+  for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < nd; k += size_t(gridDim.x) * blockDim.x)
+    hsol[base + k] = a * jd[base + k] + hsol[base + k];
+}
+
 // d = z + (rz_{i+1} / rz_i) d   (live fields)
 __global__ void __launch_bounds__(kRedThreads)
 ld_dir_kernel(size_t n, const double* __restrict__ rz, int rzs, int i, const int* __restrict__ live,
@@ -436,6 +449,13 @@ hipError_t launch_ld_step(size_t n, int batch, const double* rz, int rzs, int i,
                           const float* d, const float* hd, float* sol, float* r, hipStream_t st) {
   hipLaunchKernelGGL(ld_step_kernel, dim3(kRedBlocks, batch), dim3(kRedThreads), 0, st, n, rz, rzs, i, dhd, live, d,
                      hd, sol, r);
+  return hipGetLastError();
+}
+
+hipError_t launch_ld_data_step(size_t nd, int batch, const double* rz, int rzs, int i, const double* dhd,
+                               const int* live, const float* jd, float* hsol, hipStream_t st) {
+  hipLaunchKernelGGL(ld_data_step_kernel, dim3(kRedBlocks, batch), dim3(kRedThreads), 0, st, nd, rz, rzs, i, dhd, live,
+                     jd, hsol);
   return hipGetLastError();
 }
 

@@ -61,5 +61,8 @@ hipError_t launch_ld_step(size_t n, int batch, const double* rz, int rzs, int i,
 hipError_t launch_ld_dir(size_t n, int batch, const double* rz, int rzs, int i, const int* live, const float* z,
                          float* d, hipStream_t st);
 hipError_t launch_ld_add(size_t n, int batch, const int* flag, const float* sol, float* x, hipStream_t st);
+// hsol += alpha_i jd per live data set, alpha_i = rz_i / dhd (the step of launch_ld_step on data vectors)
+hipError_t launch_ld_data_step(size_t nd, int batch, const double* rz, int rzs, int i, const double* dhd,
+                               const int* live, const float* jd, float* hsol, hipStream_t st);
 
 }  // namespace qpat

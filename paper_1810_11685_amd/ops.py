@@ -130,6 +130,15 @@ class Plan:
         return out
 
     @on_stream
+    def jtjv_data(self, v: torch.Tensor, stream=None) -> tuple[torch.Tensor, torch.Tensor]:
+        """(H_a v, H_a^* H_a v) from one call (qpat_jtjv_data)."""
+        v, b, lead = self._fields(v, "v")
+        jv = torch.empty(*lead, self.nt, self.ns, device=v.device, dtype=torch.float32)
+        out = torch.empty_like(v)
+        check(lib().qpat_jtjv_data(self._h, _ptr(v), _ptr(jv), _ptr(out), b, _stream(stream)), "qpat_jtjv_data")
+        return jv, out
+
+    @on_stream
     def apply(self, op: str, x: torch.Tensor, stream=None) -> torch.Tensor:
         """One spectral operator ('dx+', 'dx-', 'dy+', 'dy-', 'ydis', 'yabs')."""
         x, b, lead = self._fields(x, "x")

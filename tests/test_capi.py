@@ -71,6 +71,8 @@ def test_null_and_status_strings(q):
     assert L.qpat_probe_barrier(3, 256, 256, 10, 0, None, ctypes.byref(f), ctypes.byref(t)) == 1
     assert L.qpat_probe_barrier(0, 256, 100, 10, 0, None, ctypes.byref(f), ctypes.byref(t)) == 1
     assert L.qpat_probe_barrier(0, 256, 256, 1, 0, None, ctypes.byref(f), ctypes.byref(t)) == 1
+    assert L.qpat_probe_barrier(2, 256, 256, 10, 6, None, ctypes.byref(f), ctypes.byref(t)) == 1
+    assert L.qpat_jtjv_data(None, None, None, None, 1, None) == 1
     hh = ctypes.c_void_p()
     assert L.qpat_ld_create(None, 1, ctypes.byref(hh)) == 1 and hh.value is None
     assert L.qpat_ld_run(None, None, None, None, None, None, None, None, None) == 1

@@ -214,6 +214,9 @@ def test_jtjv_is_adjoint_of_forward(q):
     ops = K.Operators(prm, c0, rho0)
     ref = K.adjoint(prm, c0, rho0, K.forward(prm, c0, rho0, N(v)[1], ops=ops), ops=ops)
     assert rel(a[1], ref) <= TOL
+    # qpat_jtjv_data hands back the intermediate H_a v as well: bitwise qpat_jv's and qpat_jtjv's
+    jv, c = plan.jtjv_data(v)
+    assert np.array_equal(N(jv), N(plan.forward(v))) and np.array_equal(N(c), a)
 
 
 def test_batch_equals_single_bitwise(q):
