@@ -352,10 +352,19 @@ struct TwRegs {
   float2 t[kMaxPer];
 };
 
+// Row length of a row-pass instance: the compile-time length NF when the
+// instance carries one (it is launched only for rows of that length), else
+// the plan's.  nxh = nx / 2 (half-spectrum columns).
+template <int NF>
+__device__ __forceinline__ int row_len(const Medium& M) { return NF > 0 ? NF : M.nx; }
+template <int NF>
+__device__ __forceinline__ int row_half(const Medium& M) { return NF > 0 ? NF / 2 : M.nxh; }
+
 // line j <- rows j of the row tile (s0, s1)
+template <int NF>
 __device__ __forceinline__ void fetch_pair(PairRegs& R, const Medium& M, const float2* __restrict__ s0,
                                            const float2* __restrict__ s1, int tile) {
-  const int tot = M.rt * M.nxh;
+  const int tot = M.rt * row_half<NF>(M);
   const unsigned base = mul24(tile, tot);
 #pragma unroll
   for (int k = 0; k < kPairIt; ++k) {
@@ -366,8 +375,9 @@ __device__ __forceinline__ void fetch_pair(PairRegs& R, const Medium& M, const f
     }
   }
 }
+template <int NF>
 __device__ __forceinline__ void put_pair(const PairRegs& R, float2* buf, const Medium& M) {
-  const int nx = M.nx, nxh = M.nxh, LS = lstride(nx), rc = M.rt * M.ct, tot = M.rt * nxh;
+  const int nx = row_len<NF>(M), nxh = row_half<NF>(M), LS = lstride(nx), rc = M.rt * M.ct, tot = M.rt * nxh;
 #pragma unroll
   for (int k = 0; k < kPairIt; ++k) {
     const int p = threadIdx.x + k * blockDim.x;
@@ -380,9 +390,10 @@ __device__ __forceinline__ void put_pair(const PairRegs& R, float2* buf, const M
 }
 
 // line l <- rows (2l, 2l+1) of the row tile of s0
+template <int NF>
 __device__ __forceinline__ void fetch_rowpair(RowPairRegs& R, const Medium& M, const float2* __restrict__ s0,
                                               int tile) {
-  const int nxh = M.nxh, hc = (M.rt >> 1) * M.ct, tot = (M.rt >> 1) * nxh;
+  const int nxh = row_half<NF>(M), hc = (M.rt >> 1) * M.ct, tot = (M.rt >> 1) * nxh;
   const unsigned base = mul24(tile, M.rt * nxh);
 #pragma unroll
   for (int k = 0; k < kRowPairIt; ++k) {
@@ -396,8 +407,10 @@ __device__ __forceinline__ void fetch_rowpair(RowPairRegs& R, const Medium& M, c
     }
   }
 }
+template <int NF>
 __device__ __forceinline__ void put_rowpair(const RowPairRegs& R, float2* buf, const Medium& M) {
-  const int nx = M.nx, nxh = M.nxh, LS = lstride(nx), hc = (M.rt >> 1) * M.ct, tot = (M.rt >> 1) * nxh;
+  const int nx = row_len<NF>(M), nxh = row_half<NF>(M), LS = lstride(nx), hc = (M.rt >> 1) * M.ct,
+            tot = (M.rt >> 1) * nxh;
 #pragma unroll
   for (int k = 0; k < kRowPairIt; ++k) {
     const int q = threadIdx.x + k * blockDim.x;
@@ -424,10 +437,14 @@ __device__ __forceinline__ void put_tw(const TwRegs& R, float2* dst, int n) {
   }
 }
 
+// (the store loops are unrolled so that the LDS reads of several iterations
+// are in flight together: the global stores in between cannot alias LDS)
+template <int NF>
 __device__ __forceinline__ void store_pair_spectra(const float2* buf, const Medium& M, float2* __restrict__ s0,
                                                    float2* __restrict__ s1, int tile) {
-  const int nx = M.nx, nxh = M.nxh, LS = lstride(nx), rc = M.rt * M.ct;
+  const int nx = row_len<NF>(M), nxh = row_half<NF>(M), LS = lstride(nx), rc = M.rt * M.ct;
   const unsigned base = mul24(tile, M.rt * nxh);
+#pragma unroll 4
   for (int p = threadIdx.x; p < M.rt * nxh; p += blockDim.x) {
     const int w = p & (rc - 1);
     const int j = w >> M.lct, k = ((p >> (M.lrt + M.lct)) << M.lct) + (w & (M.ct - 1));
@@ -438,10 +455,12 @@ __device__ __forceinline__ void store_pair_spectra(const float2* buf, const Medi
   }
 }
 
+template <int NF>
 __device__ __forceinline__ void store_rowpair_spectra(const float2* buf, const Medium& M, float2* __restrict__ s0,
                                                       int tile) {
-  const int nx = M.nx, nxh = M.nxh, LS = lstride(nx), hc = (M.rt >> 1) * M.ct;
+  const int nx = row_len<NF>(M), nxh = row_half<NF>(M), LS = lstride(nx), hc = (M.rt >> 1) * M.ct;
   const unsigned base = mul24(tile, M.rt * nxh);
+#pragma unroll 4
   for (int q = threadIdx.x; q < (M.rt >> 1) * nxh; q += blockDim.x) {
     const int tx = q >> (M.lrt - 1 + M.lct), w2 = q & (hc - 1);
     const int l = w2 >> M.lct, ix = w2 & (M.ct - 1);
@@ -615,7 +634,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
   const Work W = U ? shift_work(L.w0, item * L.wstride) : L.items[item].w;
   const IO& X = L.io[item];
   if (n > M.nt - 2) return;  // this problem has finished (uneven batches)
-  const int nx = M.nx, nxh = M.nxh, rt = M.rt;
+  const int nx = row_len<NF>(M), nxh = row_half<NF>(M), rt = M.rt;
   const int y0 = tile * rt;
   const int B = blockDim.x;
   const int LS = lstride(nx);
@@ -626,6 +645,16 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
   const int tot = rt * nx;
   const float dt = M.dt;
   const float rnx = 1.0f / static_cast<float>(nx);
+  // row j of element it of the tile, and the offset of grid row y (integer
+  // shifts / a constant divide when the instance has a compile-time length)
+  auto rowdiv = [&](int it) -> int {
+    if constexpr (NF > 0) return int(unsigned(it) / unsigned(NF));
+    else return fdiv(it, nx, rnx);
+  };
+  auto rowoff = [&](int y) -> unsigned {
+    if constexpr (NF > 0) return unsigned(y) * unsigned(NF);
+    else return mul24(y, nx);
+  };
   // RM_X variants: this iterate's slot of the sound-speed sensitivities
   float* const sens = XS ? X.sens + size_t(unsigned(flags) >> kSlotShift) * unsigned(nx * M.ny) : nullptr;
 
@@ -635,13 +664,13 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     float vxo[kMaxPer], vyo[kMaxPer], bx[kMaxPer], by[kMaxPer], ax[kMaxPer], ay[kMaxPer];
     PairRegs S;
     TwRegs TW;
-    fetch_pair(S, M, W.s0, W.s1, tile);
+    fetch_pair<NF>(S, M, W.s0, W.s1, tile);
     fetch_tw(TW, M.twx, nx);
     FOR_K_LD {
       const int it = min(int(threadIdx.x) + k * B, tot - 1);
       {
-        const int j = fdiv(it, nx, rnx), x = it - j * nx, y = y0 + j;
-        const unsigned idx = mul24(y, nx) + x;
+        const int j = rowdiv(it), x = it - j * nx, y = y0 + j;
+        const unsigned idx = rowoff(y) + x;
         vxo[k] = W.f0[idx];
         vyo[k] = W.f1[idx];
         bx[k] = M.bx[idx];
@@ -650,17 +679,27 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
         ay[k] = M.avy[y];
       }
     }
-    put_pair(S, bufA, M);
+    put_pair<NF>(S, bufA, M);
     put_tw(TW, tw, nx);
     __syncthreads();
     float2* r = fft_any<false, NF>(bufA, bufB, rt, nx, LS, M.radx, M.nstx, tw);
     float2* o = other(r, bufA, bufB);
+    // all LDS reads of the loop first: its LDS writes go to the other buffer,
+    // which the compiler cannot tell, so an interleaved loop waits per element
+    float2 zr[kMaxPer];
     FOR_K {
       const int it = threadIdx.x + k * B;
       if (it < tot) {
-        const int j = fdiv(it, nx, rnx), x = it - j * nx;
-        const unsigned idx = mul24(y0 + j, nx) + x;
-        const float2 z = r[j * LS + px(x)];
+        const int j = rowdiv(it), x = it - j * nx;
+        zr[k] = r[j * LS + px(x)];
+      }
+    }
+    FOR_K {
+      const int it = threadIdx.x + k * B;
+      if (it < tot) {
+        const int j = rowdiv(it), x = it - j * nx;
+        const unsigned idx = rowoff(y0 + j) + x;
+        const float2 z = zr[k];
         const float vx = ax[k] * (ax[k] * (first ? 0.f : vxo[k]) - bx[k] * z.x);
         const float vy = ay[k] * (ay[k] * (first ? 0.f : vyo[k]) + by[k] * z.y);
         W.f0[idx] = vx;
@@ -670,7 +709,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     }
     __syncthreads();
     r = fft_any<false, NF>(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
-    store_pair_spectra(r, M, W.s0, W.s1, tile);
+    store_pair_spectra<NF>(r, M, W.s0, W.s1, tile);
   } else if constexpr (BM == RM_F2 || BM == RM_F2L) {
     // eq num-rho with the additive source of eq s1 (dt s = p0 / (2 d c^2), d = 2)
     const bool skip = (n == -1);  // v^{-1/2} = 0 and rho^{-1} = 0
@@ -680,13 +719,13 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     TwRegs TW;
     TapStage T{};
     if constexpr (BM == RM_F2L) taps_range(T, M, tap_base, y0, rt);
-    if (!skip) fetch_pair(S, M, W.s0, W.s1, tile);
+    if (!skip) fetch_pair<NF>(S, M, W.s0, W.s1, tile);
     fetch_tw(TW, M.twx, nx);
     FOR_K_LD {
       const int it = min(int(threadIdx.x) + k * B, tot - 1);
       {
-        const int j = fdiv(it, nx, rnx), x = it - j * nx, y = y0 + j;
-        const unsigned idx = mul24(y, nx) + x;
+        const int j = rowdiv(it), x = it - j * nx, y = y0 + j;
+        const unsigned idx = rowoff(y) + x;
         rxo[k] = W.f2[idx];
         ryo[k] = W.f3[idx];
         r0[k] = M.rho0[idx];
@@ -699,14 +738,14 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
       FOR_K_LD {
         const int it = min(int(threadIdx.x) + k * B, tot - 1);
         {
-          const int j = fdiv(it, nx, rnx), x = it - j * nx;
-          const unsigned idx = mul24(y0 + j, nx) + x;
+          const int j = rowdiv(it), x = it - j * nx;
+          const unsigned idx = rowoff(y0 + j) + x;
           if constexpr (BM != RM_F2L) c2[k] = M.c2[idx];
           src[k] = X.in[idx];
         }
       }
     }
-    if (!skip) put_pair(S, bufA, M);
+    if (!skip) put_pair<NF>(S, bufA, M);
     put_tw(TW, tw, nx);
     __syncthreads();
     if constexpr (BM == RM_F2L) taps_fetch(T, M, nullptr, 0);
@@ -716,14 +755,24 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
       r = fft_any<false, NF>(bufA, bufB, rt, nx, LS, M.radx, M.nstx, tw);
       o = other(r, bufA, bufB);
     }
+    float2 zr[kMaxPer];
+    if (!skip) {
+      FOR_K {
+        const int it = threadIdx.x + k * B;
+        if (it < tot) {
+          const int j = rowdiv(it), x = it - j * nx;
+          zr[k] = r[j * LS + px(x)];
+        }
+      }
+    }
     FOR_K {
       const int it = threadIdx.x + k * B;
       if (it < tot) {
-        const int j = fdiv(it, nx, rnx), x = it - j * nx;
-        const unsigned idx = mul24(y0 + j, nx) + x;
+        const int j = rowdiv(it), x = it - j * nx;
+        const unsigned idx = rowoff(y0 + j) + x;
         float ex = 0.f, ey = 0.f;
         if (!skip) {
-          const float2 z = r[j * LS + px(x)];
+          const float2 z = zr[k];
           ex = z.x;
           ey = -z.y;
         } else {
@@ -753,12 +802,12 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     __syncthreads();
     if constexpr (BM == RM_F2) {
       r = fft_any<false, NF>(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
-      store_rowpair_spectra(r, M, W.s0, tile);
-      store_rowpair_spectra(r + (rt / 2) * LS, M, W.s1, tile);
+      store_rowpair_spectra<NF>(r, M, W.s0, tile);
+      store_rowpair_spectra<NF>(r + (rt / 2) * LS, M, W.s1, tile);
     } else {
       if (!(flags & FL_NO_SENSORS)) sensor_partials(M, T, o, y0, W.part, n + 1);
       r = fft_any<false, NF>(o, other(o, bufA, bufB), rt / 2, nx, LS, M.radx, M.nstx, tw);
-      store_rowpair_spectra(r, M, W.s0, tile);
+      store_rowpair_spectra<NF>(r, M, W.s0, tile);
     }
   } else if constexpr (BM == RM_F3) {
     // eq num-p: p = c^2 (S - eta Y_dis S + tau Y_abs u)
@@ -767,14 +816,14 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     taps_range(T, M, tap_base, y0, rt);
     RowPairRegs S0, S1;
     TwRegs TW;
-    fetch_rowpair(S0, M, W.s0, tile);
-    fetch_rowpair(S1, M, W.s1, tile);
+    fetch_rowpair<NF>(S0, M, W.s0, tile);
+    fetch_rowpair<NF>(S1, M, W.s1, tile);
     fetch_tw(TW, M.twx, nx);
     FOR_K_LD {
       const int it = min(int(threadIdx.x) + k * B, tot - 1);
       {
-        const int j = fdiv(it, nx, rnx), x = it - j * nx;
-        const unsigned idx = mul24(y0 + j, nx) + x;
+        const int j = rowdiv(it), x = it - j * nx;
+        const unsigned idx = rowoff(y0 + j) + x;
         rxo[k] = W.f2[idx];
         ryo[k] = W.f3[idx];
         c2[k] = M.c2[idx];
@@ -782,21 +831,30 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
         ctau[k] = M.c2tau[idx];
       }
     }
-    put_rowpair(S0, bufA, M);
-    put_rowpair(S1, bufA + (rt / 2) * LS, M);
+    put_rowpair<NF>(S0, bufA, M);
+    put_rowpair<NF>(S1, bufA + (rt / 2) * LS, M);
     put_tw(TW, tw, nx);
     __syncthreads();
     taps_fetch(T, M, nullptr, 0);
     float2* r = fft_any<false, NF>(bufA, bufB, rt, nx, LS, M.radx, M.nstx, tw);
     float2* o = other(r, bufA, bufB);
+    float ysr[kMaxPer], yur[kMaxPer];
     FOR_K {
       const int it = threadIdx.x + k * B;
       if (it < tot) {
-        const int j = fdiv(it, nx, rnx), x = it - j * nx;
-        const float ys = rowpair_val(r, j, x, nx), yu = rowpair_val(r + (rt / 2) * LS, j, x, nx);
+        const int j = rowdiv(it), x = it - j * nx;
+        ysr[k] = rowpair_val(r, j, x, nx);
+        yur[k] = rowpair_val(r + (rt / 2) * LS, j, x, nx);
+      }
+    }
+    FOR_K {
+      const int it = threadIdx.x + k * B;
+      if (it < tot) {
+        const int j = rowdiv(it), x = it - j * nx;
+        const float ys = ysr[k], yu = yur[k];
         const float p = c2[k] * (rxo[k] + ryo[k]) - ce[k] * ys + ctau[k] * yu;
         pcomp(o, j, x, nx) = p;
-        const unsigned idx = mul24(y0 + j, nx) + x;
+        const unsigned idx = rowoff(y0 + j) + x;
         if (flags & FL_STORE_P) W.q[idx] = p;
         if constexpr (XS) {
           // eq Twelve: c^2 eta ~ c^(y+2) and c^2 tau ~ c^(y+1), so each term of
@@ -810,7 +868,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     __syncthreads();
     if (!(flags & FL_NO_SENSORS)) sensor_partials(M, T, o, y0, W.part, n + 1);
     r = fft_any<false, NF>(o, other(o, bufA, bufB), rt / 2, nx, LS, M.radx, M.nstx, tw);
-    store_rowpair_spectra(r, M, W.s0, tile);
+    store_rowpair_spectra<NF>(r, M, W.s0, tile);
   } else if constexpr (BM == RM_A1 || BM == RM_A1L) {
     // transpose of eqs num-m and num-p: p* += M^T r_{n+1}; q = c^2 p*
     const bool first = (n == M.nt - 2);
@@ -821,13 +879,13 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     taps_range(T, M, tap_base, y0, rt);
     RowPairRegs S0;
     TwRegs TW;
-    if (!first) fetch_rowpair(S0, M, W.s0, tile);
+    if (!first) fetch_rowpair<NF>(S0, M, W.s0, tile);
     fetch_tw(TW, M.twx, nx);
     FOR_K_LD {
       const int it = min(int(threadIdx.x) + k * B, tot - 1);
       {
-        const int j = fdiv(it, nx, rnx), x = it - j * nx, y = y0 + j;
-        const unsigned idx = mul24(y, nx) + x;
+        const int j = rowdiv(it), x = it - j * nx, y = y0 + j;
+        const unsigned idx = rowoff(y) + x;
         c2[k] = M.c2[idx];
         if constexpr (BM == RM_A1) {
           ce[k] = M.c2eta[idx];
@@ -847,8 +905,8 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
       FOR_K_LD {
         const int it = min(int(threadIdx.x) + k * B, tot - 1);
         {
-          const int j = fdiv(it, nx, rnx), x = it - j * nx;
-          const unsigned idx = mul24(y0 + j, nx) + x;
+          const int j = rowdiv(it), x = it - j * nx;
+          const unsigned idx = rowoff(y0 + j) + x;
           sv[k] = sens[idx];
           gprev[k] = first ? 0.0 : X.gc[idx];
         }
@@ -859,13 +917,13 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
         FOR_K_LD {
           const int it = min(int(threadIdx.x) + k * B, tot - 1);
           {
-            const int j = fdiv(it, nx, rnx), x = it - j * nx;
-            gacc[k] = X.out[mul24(y0 + j, nx) + x];
+            const int j = rowdiv(it), x = it - j * nx;
+            gacc[k] = X.out[rowoff(y0 + j) + x];
           }
         }
       }
     }
-    if (!first) put_rowpair(S0, bufA, M);
+    if (!first) put_rowpair<NF>(S0, bufA, M);
     put_tw(TW, tw, nx);
     __syncthreads();
     taps_fetch(T, M, W.part, n + 1);
@@ -873,6 +931,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     if (!first) {
       r = fft_any<false, NF>(bufA, bufB, half, nx, LS, M.radx, M.nstx, tw);
       // p* = -(grad_x^- g_x + grad_y^- g_y): negate the (conjugated) inverse
+#pragma unroll 4
       for (int it = threadIdx.x; it < half * LS; it += B) {
         const float2 z = r[it];
         r[it] = make_float2(-z.x, z.y);
@@ -885,12 +944,20 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     sensor_scatter(M, T, r, y0, rt, W.part, n + 1);
     __syncthreads();
     float2* o = other(r, bufA, bufB);
+    float pbr[kMaxPer];
     FOR_K {
       const int it = threadIdx.x + k * B;
       if (it < tot) {
-        const int j = fdiv(it, nx, rnx), x = it - j * nx;
-        const unsigned idx = mul24(y0 + j, nx) + x;
-        const float pb = pcomp(r, j, x, nx);
+        const int j = rowdiv(it), x = it - j * nx;
+        pbr[k] = pcomp(r, j, x, nx);
+      }
+    }
+    FOR_K {
+      const int it = threadIdx.x + k * B;
+      if (it < tot) {
+        const int j = rowdiv(it), x = it - j * nx;
+        const unsigned idx = rowoff(y0 + j) + x;
+        const float pb = pbr[k];
         if constexpr (XS) X.gc[idx] = gprev[k] + double(pb) * double(sv[k]);
         if constexpr (BM == RM_A1) {
           // eta q and tau q, each with its own rows paired (see RM_F2)
@@ -915,11 +982,11 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     __syncthreads();
     if constexpr (BM == RM_A1) {
       r = fft_any<false, NF>(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
-      store_rowpair_spectra(r, M, W.s0, tile);
-      store_rowpair_spectra(r + half * LS, M, W.s1, tile);
+      store_rowpair_spectra<NF>(r, M, W.s0, tile);
+      store_rowpair_spectra<NF>(r + half * LS, M, W.s1, tile);
     } else if (n != -1) {
       r = fft_any<false, NF>(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
-      store_pair_spectra(r, M, W.s0, W.s1, tile);
+      store_pair_spectra<NF>(r, M, W.s0, W.s1, tile);
     }
   } else if constexpr (BM == RM_A2) {
     // transpose of the mass update and of the Y terms of eq num-p
@@ -928,14 +995,14 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     float c2[kMaxPer], gacc[kMaxPer];
     RowPairRegs S0, S1;
     TwRegs TW;
-    fetch_rowpair(S0, M, W.s0, tile);
-    fetch_rowpair(S1, M, W.s1, tile);
+    fetch_rowpair<NF>(S0, M, W.s0, tile);
+    fetch_rowpair<NF>(S1, M, W.s1, tile);
     fetch_tw(TW, M.twx, nx);
     FOR_K_LD {
       const int it = min(int(threadIdx.x) + k * B, tot - 1);
       {
-        const int j = fdiv(it, nx, rnx), x = it - j * nx, y = y0 + j;
-        const unsigned idx = mul24(y, nx) + x;
+        const int j = rowdiv(it), x = it - j * nx, y = y0 + j;
+        const unsigned idx = rowoff(y) + x;
         qv[k] = W.q[idx];
         rbx0[k] = W.f2[idx];
         rby0[k] = W.f3[idx];
@@ -948,25 +1015,34 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
       FOR_K_LD {
         const int it = min(int(threadIdx.x) + k * B, tot - 1);
         {
-          const int j = fdiv(it, nx, rnx), x = it - j * nx;
-          const unsigned idx = mul24(y0 + j, nx) + x;
+          const int j = rowdiv(it), x = it - j * nx;
+          const unsigned idx = rowoff(y0 + j) + x;
           c2[k] = M.c2[idx];
           gacc[k] = M.nt >= 2 ? X.out[idx] : 0.f;
         }
       }
     }
-    put_rowpair(S0, bufA, M);
-    put_rowpair(S1, bufA + (rt / 2) * LS, M);
+    put_rowpair<NF>(S0, bufA, M);
+    put_rowpair<NF>(S1, bufA + (rt / 2) * LS, M);
     put_tw(TW, tw, nx);
     __syncthreads();
     float2* r = fft_any<false, NF>(bufA, bufB, rt, nx, LS, M.radx, M.nstx, tw);
     float2* o = other(r, bufA, bufB);
+    float ydr[kMaxPer], yar[kMaxPer];
     FOR_K {
       const int it = threadIdx.x + k * B;
       if (it < tot) {
-        const int j = fdiv(it, nx, rnx), x = it - j * nx;
-        const unsigned idx = mul24(y0 + j, nx) + x;
-        const float yd = rowpair_val(r, j, x, nx), ya = rowpair_val(r + (rt / 2) * LS, j, x, nx);
+        const int j = rowdiv(it), x = it - j * nx;
+        ydr[k] = rowpair_val(r, j, x, nx);
+        yar[k] = rowpair_val(r + (rt / 2) * LS, j, x, nx);
+      }
+    }
+    FOR_K {
+      const int it = threadIdx.x + k * B;
+      if (it < tot) {
+        const int j = rowdiv(it), x = it - j * nx;
+        const unsigned idx = rowoff(y0 + j) + x;
+        const float yd = ydr[k], ya = yar[k];
         const float sb = qv[k] - yd;
         const float rbx = (first ? 0.f : rbx0[k]) + sb, rby = (first ? 0.f : rby0[k]) + sb;
         if (n == 0) X.out[idx] = rbx + rby;
@@ -982,7 +1058,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     __syncthreads();
     if (n != -1) {
       r = fft_any<false, NF>(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
-      store_pair_spectra(r, M, W.s0, W.s1, tile);
+      store_pair_spectra<NF>(r, M, W.s0, W.s1, tile);
     }
   } else if constexpr (BM == RM_A3) {
     // transpose of eq num-vel
@@ -990,13 +1066,13 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     float vbx0[kMaxPer], vby0[kMaxPer], bx[kMaxPer], by[kMaxPer], ax[kMaxPer], ay[kMaxPer];
     PairRegs S;
     TwRegs TW;
-    fetch_pair(S, M, W.s0, W.s1, tile);
+    fetch_pair<NF>(S, M, W.s0, W.s1, tile);
     fetch_tw(TW, M.twx, nx);
     FOR_K_LD {
       const int it = min(int(threadIdx.x) + k * B, tot - 1);
       {
-        const int j = fdiv(it, nx, rnx), x = it - j * nx, y = y0 + j;
-        const unsigned idx = mul24(y, nx) + x;
+        const int j = rowdiv(it), x = it - j * nx, y = y0 + j;
+        const unsigned idx = rowoff(y) + x;
         vbx0[k] = W.f0[idx];
         vby0[k] = W.f1[idx];
         bx[k] = M.bx[idx];
@@ -1005,17 +1081,25 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
         ay[k] = M.avy[y];
       }
     }
-    put_pair(S, bufA, M);
+    put_pair<NF>(S, bufA, M);
     put_tw(TW, tw, nx);
     __syncthreads();
     float2* r = fft_any<false, NF>(bufA, bufB, rt, nx, LS, M.radx, M.nstx, tw);
     float2* o = other(r, bufA, bufB);
+    float2 zr[kMaxPer];
     FOR_K {
       const int it = threadIdx.x + k * B;
       if (it < tot) {
-        const int j = fdiv(it, nx, rnx), x = it - j * nx;
-        const unsigned idx = mul24(y0 + j, nx) + x;
-        const float2 z = r[j * LS + px(x)];
+        const int j = rowdiv(it), x = it - j * nx;
+        zr[k] = r[j * LS + px(x)];
+      }
+    }
+    FOR_K {
+      const int it = threadIdx.x + k * B;
+      if (it < tot) {
+        const int j = rowdiv(it), x = it - j * nx;
+        const unsigned idx = rowoff(y0 + j) + x;
+        const float2 z = zr[k];
         const float vbx = (first ? 0.f : vbx0[k]) - z.x;
         const float vby = (first ? 0.f : vby0[k]) + z.y;
         o[j * LS + px(x)] = make_float2(-ax[k] * bx[k] * vbx, -ay[k] * by[k] * vby);
@@ -1025,7 +1109,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     }
     __syncthreads();
     r = fft_any<false, NF>(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
-    store_pair_spectra(r, M, W.s0, W.s1, tile);
+    store_pair_spectra<NF>(r, M, W.s0, W.s1, tile);
   } else if constexpr (BM == RM_FWD1) {
     const float* src = X.in;
     TwRegs TW;
@@ -1034,34 +1118,35 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     FOR_K_LD {
       const int it = min(int(threadIdx.x) + k * B, tot - 1);
       {
-        const int j = fdiv(it, nx, rnx), x = it - j * nx;
-        v[k] = src[mul24(y0 + j, nx) + x];
+        const int j = rowdiv(it), x = it - j * nx;
+        v[k] = src[rowoff(y0 + j) + x];
       }
     }
     FOR_K {
       const int it = threadIdx.x + k * B;
       if (it < tot) {
-        const int j = fdiv(it, nx, rnx), x = it - j * nx;
+        const int j = rowdiv(it), x = it - j * nx;
         pcomp(bufA, j, x, nx) = v[k];
       }
     }
     put_tw(TW, tw, nx);
     __syncthreads();
     float2* r = fft_any<false, NF>(bufA, bufB, rt / 2, nx, LS, M.radx, M.nstx, tw);
-    store_rowpair_spectra(r, M, W.s0, tile);
+    store_rowpair_spectra<NF>(r, M, W.s0, tile);
   } else if constexpr (BM == RM_INV1) {
     RowPairRegs S0;
     TwRegs TW;
-    fetch_rowpair(S0, M, W.s0, tile);
+    fetch_rowpair<NF>(S0, M, W.s0, tile);
     fetch_tw(TW, M.twx, nx);
-    put_rowpair(S0, bufA, M);
+    put_rowpair<NF>(S0, bufA, M);
     put_tw(TW, tw, nx);
     __syncthreads();
     float2* r = fft_any<false, NF>(bufA, bufB, rt / 2, nx, LS, M.radx, M.nstx, tw);
     float* dst = X.out;
+#pragma unroll 4
     for (int it = threadIdx.x; it < tot; it += B) {
-      const int j = fdiv(it, nx, rnx), x = it - j * nx;
-      dst[mul24(y0 + j, nx) + x] = rowpair_val(r, j, x, nx);
+      const int j = rowdiv(it), x = it - j * nx;
+      dst[rowoff(y0 + j) + x] = rowpair_val(r, j, x, nx);
     }
   }
 }
@@ -1607,16 +1692,17 @@ __global__ void __launch_bounds__(kBlock) dot_final(const double* __restrict__ p
 }
 
 // ---------------------------------------------------------------- launchers
-// Uniform launches pick the kernel instance for their row / column length
-// (lengths with a compile-time plan); mixed batches take the all-length one.
-// 1024-point columns stay on the all-length instance: the dedicated one
-// measured 5-10% slower at 1024^2 x 8.
+// Launches pick the kernel instance for their row / column length (lengths
+// with a compile-time plan): uniform launches by the plan's length, table
+// launches by the length all their items share (`len`, 0 when they differ:
+// then the all-length instance).  1024-point columns stay on the all-length
+// instance: the dedicated one measured 5-10% slower at 1024^2 x 8.
 #define QPAT_FOR_LENGTHS(X) X(128) X(256) X(384) X(512) X(1024)
 #define QPAT_FOR_COL_LENGTHS(X) X(128) X(256) X(384) X(512)
 
 template <int MODE>
-static hipError_t launch_row_t(const Launch& L, bool uniform, int ntile, int chunk, int nblocks, int threads,
-                               size_t lds, int n, int flags, hipStream_t st) {
+static hipError_t launch_row_t(const Launch& L, bool uniform, int len, int ntile, int chunk, int nblocks,
+                               int threads, size_t lds, int n, int flags, hipStream_t st) {
   const dim3 g(nblocks), t(threads);
   if (uniform) {
 #define QPAT_ROW_LEN(N) \
@@ -1627,15 +1713,21 @@ static hipError_t launch_row_t(const Launch& L, bool uniform, int ntile, int chu
     }
 #undef QPAT_ROW_LEN
   } else {
-    hipLaunchKernelGGL((row_kernel<MODE, false, 0>), g, t, lds, st, L, ntile, chunk, n, flags);
+#define QPAT_ROW_LEN(N) \
+  case N: hipLaunchKernelGGL((row_kernel<MODE, false, N>), g, t, lds, st, L, ntile, chunk, n, flags); break;
+    switch (len) {
+      QPAT_FOR_LENGTHS(QPAT_ROW_LEN)
+      default: hipLaunchKernelGGL((row_kernel<MODE, false, 0>), g, t, lds, st, L, ntile, chunk, n, flags); break;
+    }
+#undef QPAT_ROW_LEN
   }
   return hipGetLastError();
 }
 
-hipError_t launch_row(int mode, const Launch& L, bool uniform, int ntile, int chunk, int nblocks, int threads,
-                      size_t lds, int n, int flags, hipStream_t st) {
+hipError_t launch_row(int mode, const Launch& L, bool uniform, int len, int ntile, int chunk, int nblocks,
+                      int threads, size_t lds, int n, int flags, hipStream_t st) {
 #define QPAT_ROW_CASE(m) \
-  case m: return launch_row_t<m>(L, uniform, ntile, chunk, nblocks, threads, lds, n, flags, st);
+  case m: return launch_row_t<m>(L, uniform, len, ntile, chunk, nblocks, threads, lds, n, flags, st);
   switch (mode) {
     QPAT_ROW_CASE(RM_F1)
     QPAT_ROW_CASE(RM_F2)
@@ -1657,8 +1749,8 @@ hipError_t launch_row(int mode, const Launch& L, bool uniform, int ntile, int ch
 }
 
 template <int CM>
-static hipError_t launch_col_t(int mcode, const Launch& L, bool uniform, int ntile, int chunk, int nblocks,
-                               int threads, size_t lds, int n, hipStream_t st) {
+static hipError_t launch_col_t(int mcode, const Launch& L, bool uniform, int len, int ntile, int chunk,
+                               int nblocks, int threads, size_t lds, int n, hipStream_t st) {
   const dim3 g(nblocks), t(threads);
   if (uniform) {
 #define QPAT_COL_LEN(N) \
@@ -1669,22 +1761,31 @@ static hipError_t launch_col_t(int mcode, const Launch& L, bool uniform, int nti
     }
 #undef QPAT_COL_LEN
   } else {
-    hipLaunchKernelGGL((col_kernel<false, CM, 0>), g, t, lds, st, L, ntile, chunk, mcode, n);
+#define QPAT_COL_LEN(N) \
+  case N: hipLaunchKernelGGL((col_kernel<false, CM, N>), g, t, lds, st, L, ntile, chunk, mcode, n); break;
+    switch (len) {
+      QPAT_FOR_COL_LENGTHS(QPAT_COL_LEN)
+      default: hipLaunchKernelGGL((col_kernel<false, CM, 0>), g, t, lds, st, L, ntile, chunk, mcode, n); break;
+    }
+#undef QPAT_COL_LEN
   }
   return hipGetLastError();
 }
 
-hipError_t launch_col(int cm, int mcode, const Launch& L, bool uniform, int ntile, int chunk, int nblocks,
-                      int threads, size_t lds, int n, hipStream_t st) {
+hipError_t launch_col(int cm, int mcode, const Launch& L, bool uniform, int len, int ntile, int chunk,
+                      int nblocks, int threads, size_t lds, int n, hipStream_t st) {
+#define QPAT_COL_CASE(c) \
+  case c: return launch_col_t<c>(mcode, L, uniform, len, ntile, chunk, nblocks, threads, lds, n, st);
   switch (cm) {
-    case CM_GRADP1: return launch_col_t<CM_GRADP1>(mcode, L, uniform, ntile, chunk, nblocks, threads, lds, n, st);
-    case CM_GRADM2: return launch_col_t<CM_GRADM2>(mcode, L, uniform, ntile, chunk, nblocks, threads, lds, n, st);
-    case CM_FRAC: return launch_col_t<CM_FRAC>(mcode, L, uniform, ntile, chunk, nblocks, threads, lds, n, st);
-    case CM_GRADP2: return launch_col_t<CM_GRADP2>(mcode, L, uniform, ntile, chunk, nblocks, threads, lds, n, st);
-    case CM_DIVM: return launch_col_t<CM_DIVM>(mcode, L, uniform, ntile, chunk, nblocks, threads, lds, n, st);
-    case CM_APPLY: return launch_col_t<CM_APPLY>(mcode, L, uniform, ntile, chunk, nblocks, threads, lds, n, st);
+    QPAT_COL_CASE(CM_GRADP1)
+    QPAT_COL_CASE(CM_GRADM2)
+    QPAT_COL_CASE(CM_FRAC)
+    QPAT_COL_CASE(CM_GRADP2)
+    QPAT_COL_CASE(CM_DIVM)
+    QPAT_COL_CASE(CM_APPLY)
     default: return hipErrorInvalidValue;
   }
+#undef QPAT_COL_CASE
 }
 
 // Let every row / column pass kernel use up to `bytes` of dynamic LDS.
@@ -1697,8 +1798,9 @@ template <int MODE>
 static hipError_t allow_row(size_t bytes) {
   hipError_t e = allow_fn(&row_kernel<MODE, false, 0>, bytes);
   if (e == hipSuccess) e = allow_fn(&row_kernel<MODE, true, 0>, bytes);
-#define QPAT_ALLOW_ROW(N) \
-  if (e == hipSuccess) e = allow_fn(&row_kernel<MODE, true, N>, bytes);
+#define QPAT_ALLOW_ROW(N)                                                 \
+  if (e == hipSuccess) e = allow_fn(&row_kernel<MODE, true, N>, bytes); \
+  if (e == hipSuccess) e = allow_fn(&row_kernel<MODE, false, N>, bytes);
   QPAT_FOR_LENGTHS(QPAT_ALLOW_ROW)
 #undef QPAT_ALLOW_ROW
   return e;
@@ -1707,8 +1809,9 @@ template <int CM>
 static hipError_t allow_col(size_t bytes) {
   hipError_t e = allow_fn(&col_kernel<false, CM, 0>, bytes);
   if (e == hipSuccess) e = allow_fn(&col_kernel<true, CM, 0>, bytes);
-#define QPAT_ALLOW_COL(N) \
-  if (e == hipSuccess) e = allow_fn(&col_kernel<true, CM, N>, bytes);
+#define QPAT_ALLOW_COL(N)                                               \
+  if (e == hipSuccess) e = allow_fn(&col_kernel<true, CM, N>, bytes); \
+  if (e == hipSuccess) e = allow_fn(&col_kernel<false, CM, N>, bytes);
   QPAT_FOR_COL_LENGTHS(QPAT_ALLOW_COL)
 #undef QPAT_ALLOW_COL
   return e;

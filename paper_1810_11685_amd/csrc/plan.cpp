@@ -169,6 +169,7 @@ struct Exec {
   Launch L{};
   bool uniform = false;
   int row_ntile = 0, col_ntile = 0, row_chunk = 0, col_chunk = 0;
+  int tab_nx = 0, tab_ny = 0;  // table launches: the row / column length all items share (0: they differ)
   bool lossy = false;
   // pinned staging ring for the I/O table
   static constexpr int kRing = 16;
@@ -240,6 +241,12 @@ qpat_status exec_build(Exec& E, const std::vector<Item>& items) {
     E.rthr = std::max(E.rthr, m.rthr);
     E.cthr = std::max(E.cthr, m.cthr);
   }
+  E.tab_nx = items[0].m.nx;
+  E.tab_ny = items[0].m.ny;
+  for (int i = 1; i < ni; ++i) {
+    if (items[i].m.nx != E.tab_nx) E.tab_nx = 0;
+    if (items[i].m.ny != E.tab_ny) E.tab_ny = 0;
+  }
   const std::vector<int2> rm = xcd_map(rows), cm = xcd_map(cols);
   E.nrow = int(rm.size());
   E.ncol = int(cm.size());
@@ -304,19 +311,19 @@ qpat_status exec_set_io(Exec& E, const std::vector<IO>& io, hipStream_t st) {
 
 hipError_t row(Exec& E, int mode, int n, int flags, hipStream_t st) {
   if (E.uniform)
-    return launch_row(mode, E.L, true, E.row_ntile, E.row_chunk, E.row_chunk * kXcds, E.rthr, E.row_lds, n,
+    return launch_row(mode, E.L, true, 0, E.row_ntile, E.row_chunk, E.row_chunk * kXcds, E.rthr, E.row_lds, n,
                       flags, st);
   Launch L = E.L;
   L.map = E.d_rowmap;
-  return launch_row(mode, L, false, 0, 0, E.nrow, E.rthr, E.row_lds, n, flags, st);
+  return launch_row(mode, L, false, E.tab_nx, 0, 0, E.nrow, E.rthr, E.row_lds, n, flags, st);
 }
 hipError_t col(Exec& E, int cm, int n, hipStream_t st, int mcode = 0) {
   if (E.uniform)
-    return launch_col(cm, mcode, E.L, true, E.col_ntile, E.col_chunk, E.col_chunk * kXcds, E.cthr, E.col_lds, n,
-                      st);
+    return launch_col(cm, mcode, E.L, true, 0, E.col_ntile, E.col_chunk, E.col_chunk * kXcds, E.cthr, E.col_lds,
+                      n, st);
   Launch L = E.L;
   L.map = E.d_colmap;
-  return launch_col(cm, mcode, L, false, 0, 0, E.ncol, E.cthr, E.col_lds, n, st);
+  return launch_col(cm, mcode, L, false, E.tab_ny, 0, 0, E.ncol, E.cthr, E.col_lds, n, st);
 }
 
 #define LCHK(expr)                           \

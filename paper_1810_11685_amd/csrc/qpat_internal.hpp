@@ -127,10 +127,12 @@ struct TraceRange {
 };
 
 // Launch helpers implemented in kernels.hip.
-hipError_t launch_row(int mode, const Launch& L, bool uniform, int ntile, int chunk, int nblocks,
+// `len`: for table launches (uniform false), the row (column) length every
+// item shares, or 0 when the items' lengths differ.
+hipError_t launch_row(int mode, const Launch& L, bool uniform, int len, int ntile, int chunk, int nblocks,
                       int threads, size_t lds, int n, int flags, hipStream_t st);
-hipError_t launch_col(int cm, int mcode, const Launch& L, bool uniform, int ntile, int chunk, int nblocks,
-                      int threads, size_t lds, int n, hipStream_t st);
+hipError_t launch_col(int cm, int mcode, const Launch& L, bool uniform, int len, int ntile, int chunk,
+                      int nblocks, int threads, size_t lds, int n, hipStream_t st);
 hipError_t launch_combine(const Item* items, const IO* io, int nitems, int max_count,
                           hipStream_t st);
 hipError_t kernels_allow_lds(size_t bytes);
