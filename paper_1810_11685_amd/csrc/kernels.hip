@@ -622,7 +622,12 @@ __device__ __forceinline__ Work shift_work(const Work& w, long long off) {
 // branch, so the loads of all iterations issue back to back.
 #define FOR_K_LD _Pragma("unroll") for (int k = 0; k < kMaxPer; ++k) if (k * B < tot)
 
-template <int MODE, bool U, int NF>
+// TG: the FFT stages read their twiddles from the plan's table in global
+// memory (L1/L2 resident) instead of a copy staged in LDS.  That takes the
+// table load and its LDS writes off a block's critical path, which pays when
+// a launch has about one block per CU; with several blocks per CU the LDS
+// copy (and the occupancy it costs) is the better trade.
+template <int MODE, bool U, int NF, bool TG = false>
 __global__ void __launch_bounds__(kMaxThreads)
 row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
   constexpr int BM = MODE & ~RM_X;
@@ -640,8 +645,9 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
   const int LS = lstride(nx);
   float2* bufA = lds;
   float2* bufB = lds + rt * LS;
-  float2* tw = lds + 2 * rt * LS;
-  void* tap_base = lds + 2 * rt * LS + nx;
+  float2* const twl = lds + 2 * rt * LS;
+  const float2* const tw = TG ? static_cast<const float2*>(M.twx) : twl;
+  void* tap_base = lds + 2 * rt * LS + (TG ? 0 : nx);
   const int tot = rt * nx;
   const float dt = M.dt;
   const float rnx = 1.0f / static_cast<float>(nx);
@@ -665,7 +671,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     PairRegs S;
     TwRegs TW;
     fetch_pair<NF>(S, M, W.s0, W.s1, tile);
-    fetch_tw(TW, M.twx, nx);
+    if constexpr (!TG) fetch_tw(TW, M.twx, nx);
     FOR_K_LD {
       const int it = min(int(threadIdx.x) + k * B, tot - 1);
       {
@@ -680,7 +686,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
       }
     }
     put_pair<NF>(S, bufA, M);
-    put_tw(TW, tw, nx);
+    if constexpr (!TG) put_tw(TW, twl, nx);
     __syncthreads();
     float2* r = fft_any<false, NF>(bufA, bufB, rt, nx, LS, M.radx, M.nstx, tw);
     float2* o = other(r, bufA, bufB);
@@ -720,7 +726,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     TapStage T{};
     if constexpr (BM == RM_F2L) taps_range(T, M, tap_base, y0, rt);
     if (!skip) fetch_pair<NF>(S, M, W.s0, W.s1, tile);
-    fetch_tw(TW, M.twx, nx);
+    if constexpr (!TG) fetch_tw(TW, M.twx, nx);
     FOR_K_LD {
       const int it = min(int(threadIdx.x) + k * B, tot - 1);
       {
@@ -746,7 +752,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
       }
     }
     if (!skip) put_pair<NF>(S, bufA, M);
-    put_tw(TW, tw, nx);
+    if constexpr (!TG) put_tw(TW, twl, nx);
     __syncthreads();
     if constexpr (BM == RM_F2L) taps_fetch(T, M, nullptr, 0);
     float2* r = nullptr;
@@ -818,7 +824,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     TwRegs TW;
     fetch_rowpair<NF>(S0, M, W.s0, tile);
     fetch_rowpair<NF>(S1, M, W.s1, tile);
-    fetch_tw(TW, M.twx, nx);
+    if constexpr (!TG) fetch_tw(TW, M.twx, nx);
     FOR_K_LD {
       const int it = min(int(threadIdx.x) + k * B, tot - 1);
       {
@@ -833,7 +839,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     }
     put_rowpair<NF>(S0, bufA, M);
     put_rowpair<NF>(S1, bufA + (rt / 2) * LS, M);
-    put_tw(TW, tw, nx);
+    if constexpr (!TG) put_tw(TW, twl, nx);
     __syncthreads();
     taps_fetch(T, M, nullptr, 0);
     float2* r = fft_any<false, NF>(bufA, bufB, rt, nx, LS, M.radx, M.nstx, tw);
@@ -880,7 +886,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     RowPairRegs S0;
     TwRegs TW;
     if (!first) fetch_rowpair<NF>(S0, M, W.s0, tile);
-    fetch_tw(TW, M.twx, nx);
+    if constexpr (!TG) fetch_tw(TW, M.twx, nx);
     FOR_K_LD {
       const int it = min(int(threadIdx.x) + k * B, tot - 1);
       {
@@ -924,7 +930,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
       }
     }
     if (!first) put_rowpair<NF>(S0, bufA, M);
-    put_tw(TW, tw, nx);
+    if constexpr (!TG) put_tw(TW, twl, nx);
     __syncthreads();
     taps_fetch(T, M, W.part, n + 1);
     float2* r = bufA;
@@ -997,7 +1003,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     TwRegs TW;
     fetch_rowpair<NF>(S0, M, W.s0, tile);
     fetch_rowpair<NF>(S1, M, W.s1, tile);
-    fetch_tw(TW, M.twx, nx);
+    if constexpr (!TG) fetch_tw(TW, M.twx, nx);
     FOR_K_LD {
       const int it = min(int(threadIdx.x) + k * B, tot - 1);
       {
@@ -1024,7 +1030,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     }
     put_rowpair<NF>(S0, bufA, M);
     put_rowpair<NF>(S1, bufA + (rt / 2) * LS, M);
-    put_tw(TW, tw, nx);
+    if constexpr (!TG) put_tw(TW, twl, nx);
     __syncthreads();
     float2* r = fft_any<false, NF>(bufA, bufB, rt, nx, LS, M.radx, M.nstx, tw);
     float2* o = other(r, bufA, bufB);
@@ -1067,7 +1073,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     PairRegs S;
     TwRegs TW;
     fetch_pair<NF>(S, M, W.s0, W.s1, tile);
-    fetch_tw(TW, M.twx, nx);
+    if constexpr (!TG) fetch_tw(TW, M.twx, nx);
     FOR_K_LD {
       const int it = min(int(threadIdx.x) + k * B, tot - 1);
       {
@@ -1082,7 +1088,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
       }
     }
     put_pair<NF>(S, bufA, M);
-    put_tw(TW, tw, nx);
+    if constexpr (!TG) put_tw(TW, twl, nx);
     __syncthreads();
     float2* r = fft_any<false, NF>(bufA, bufB, rt, nx, LS, M.radx, M.nstx, tw);
     float2* o = other(r, bufA, bufB);
@@ -1114,7 +1120,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     const float* src = X.in;
     TwRegs TW;
     float v[kMaxPer];
-    fetch_tw(TW, M.twx, nx);
+    if constexpr (!TG) fetch_tw(TW, M.twx, nx);
     FOR_K_LD {
       const int it = min(int(threadIdx.x) + k * B, tot - 1);
       {
@@ -1129,7 +1135,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
         pcomp(bufA, j, x, nx) = v[k];
       }
     }
-    put_tw(TW, tw, nx);
+    if constexpr (!TG) put_tw(TW, twl, nx);
     __syncthreads();
     float2* r = fft_any<false, NF>(bufA, bufB, rt / 2, nx, LS, M.radx, M.nstx, tw);
     store_rowpair_spectra<NF>(r, M, W.s0, tile);
@@ -1137,9 +1143,9 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     RowPairRegs S0;
     TwRegs TW;
     fetch_rowpair<NF>(S0, M, W.s0, tile);
-    fetch_tw(TW, M.twx, nx);
+    if constexpr (!TG) fetch_tw(TW, M.twx, nx);
     put_rowpair<NF>(S0, bufA, M);
-    put_tw(TW, tw, nx);
+    if constexpr (!TG) put_tw(TW, twl, nx);
     __syncthreads();
     float2* r = fft_any<false, NF>(bufA, bufB, rt / 2, nx, LS, M.radx, M.nstx, tw);
     float* dst = X.out;
@@ -1187,7 +1193,7 @@ __device__ constexpr int kColOut[kColModes] = {2, 2, 2, 2, 1, 1};
 
 // Column pass for any supported line length (runtime or compile-time FFT
 // plan): the tile goes through LDS between every phase.
-template <int CM, int NF>
+template <int CM, int NF, bool TG>
 __device__ __forceinline__ void col_generic(const Medium& M, const Work& W, int tile, int mcode, float2* lds) {
   constexpr int nin = kColIn[CM], nout = kColOut[CM];
   const int ny = M.ny, nxh = M.nxh, ct = M.ct, ls = col_lstride(ny);
@@ -1196,7 +1202,8 @@ __device__ __forceinline__ void col_generic(const Medium& M, const Work& W, int 
   const int nsl = 2;
   float2* bufA = lds;
   float2* bufB = lds + nsl * ct * ls;
-  float2* tw = lds + 2 * nsl * ct * ls;
+  float2* const twl = lds + 2 * nsl * ct * ls;
+  const float2* const tw = TG ? static_cast<const float2*>(M.twy) : twl;
   // which tables this launch uses
   int xcode = 0, ycode = 0;
   bool frac = false, labs = false;
@@ -1231,7 +1238,7 @@ __device__ __forceinline__ void col_generic(const Medium& M, const Work& W, int 
     }
   }
   TwRegs TW;
-  fetch_tw(TW, M.twy, ny);
+  if constexpr (!TG) fetch_tw(TW, M.twy, ny);
   const int tot = ct * ny;
   MultPre P[kMaxPer];
   FOR_K {
@@ -1261,7 +1268,7 @@ __device__ __forceinline__ void col_generic(const Medium& M, const Work& W, int 
       bufA[mul24((f ? ct : 0) + c, ls) + px(ky)] = tv[k];
     }
   }
-  put_tw(TW, tw, ny);
+  if constexpr (!TG) put_tw(TW, twl, ny);
   __syncthreads();
   float2* r = fft_any<true, NF>(bufA, bufB, nin * ct, ny, ls, M.rady, M.nsty, tw);
   float2* o = other(r, bufA, bufB);
@@ -1427,7 +1434,7 @@ __device__ __forceinline__ void col_mult_lds(const Medium& M, int tile, int mcod
 // transform's last stage, the multipliers and the inverse transform's first
 // stage stay in registers.  The tile with the packed DC / Nyquist column
 // (tile 0) takes its multiply phase through LDS.
-template <int CM, int N>
+template <int CM, int N, bool TG>
 __device__ __forceinline__ void col_fused(const Medium& M, const Work& W, int tile, int mcode, float2* lds) {
   constexpr int nin = kColIn[CM], nout = kColOut[CM];
   constexpr int NST = plan_nst(N), LS = col_lstride(N);
@@ -1442,8 +1449,9 @@ __device__ __forceinline__ void col_fused(const Medium& M, const Work& W, int ti
   const int tid = threadIdx.x;
   float2* bufA = lds;
   float2* bufB = lds + 2 * ct * LS;
-  float2* tw = lds + 4 * ct * LS;  // forward-plan twiddles
-  float2* twr = tw + N;            // reversed-plan twiddles
+  float2* const twl = lds + 4 * ct * LS;  // LDS copies: forward-plan twiddles, then reversed-plan ones
+  const float2* const tw = TG ? static_cast<const float2*>(M.twy) : twl;
+  const float2* const twr = TG ? static_cast<const float2*>(M.twyr) : twl + N;
   int xcode = 0, ycode = 0;
   bool frac = false, labs = false;
   for (int e = 0; e < 4; ++e) {
@@ -1476,8 +1484,10 @@ __device__ __forceinline__ void col_fused(const Medium& M, const Work& W, int ti
     }
   }
   TwRegs TW, TWR;
-  fetch_tw(TW, M.twy, N);
-  fetch_tw(TWR, M.twyr, N);
+  if constexpr (!TG) {
+    fetch_tw(TW, M.twy, N);
+    fetch_tw(TWR, M.twyr, N);
+  }
   const unsigned np = unsigned(ct) * NBS;
   const unsigned tstep = unsigned(NBS);   // tables are [kx][ky]: a column's entries are contiguous
   float ma[kP][RS], mb[kP][RS];
@@ -1507,8 +1517,10 @@ __device__ __forceinline__ void col_fused(const Medium& M, const Work& W, int ti
       stage_store<R1, 1>(v1[i], bufA + l * LS, j);
     }
   }
-  put_tw(TW, tw, N);
-  put_tw(TWR, twr, N);
+  if constexpr (!TG) {
+    put_tw(TW, twl, N);
+    put_tw(TWR, twl + N, N);
+  }
   __syncthreads();
   // ---- forward stages 2 .. NST-1
   float2* r = fft_stages<N, false, LS, 1, NST - 1, R1>(bufA, bufB, nin * ct, tw);
@@ -1581,7 +1593,7 @@ __device__ __forceinline__ void col_fused(const Medium& M, const Work& W, int ti
   }
 }
 
-template <bool U, int CM, int NF>
+template <bool U, int CM, int NF, bool TG = false>
 __global__ void __launch_bounds__(kMaxThreads)
 col_kernel(const Launch L, int ntile, int chunk, int mcode_arg, int n) {
   const int mcode = CM == CM_APPLY ? mcode_arg : kColCode[CM];
@@ -1595,7 +1607,7 @@ col_kernel(const Launch L, int ntile, int chunk, int mcode_arg, int n) {
 #define QPAT_COL_CASE(N)                                                 \
   case N:                                                                \
     if ((N / radix_of<N, false>(0)) % M.rt == 0) {                       \
-      col_fused<CM, N>(M, W, tile, mcode, lds);                          \
+      col_fused<CM, N, TG>(M, W, tile, mcode, lds);                      \
       return;                                                            \
     }                                                                    \
     break;
@@ -1614,7 +1626,7 @@ col_kernel(const Launch L, int ntile, int chunk, int mcode_arg, int n) {
     }
   }
 #undef QPAT_COL_CASE
-  col_generic<CM, NF>(M, W, tile, mcode, lds);
+  col_generic<CM, NF, TG>(M, W, tile, mcode, lds);
 }
 
 // ---------------------------------------------------------------- sensor data
@@ -1701,10 +1713,18 @@ __global__ void __launch_bounds__(kBlock) dot_final(const double* __restrict__ p
 #define QPAT_FOR_COL_LENGTHS(X) X(128) X(256) X(384) X(512)
 
 template <int MODE>
-static hipError_t launch_row_t(const Launch& L, bool uniform, int len, int ntile, int chunk, int nblocks,
+static hipError_t launch_row_t(const Launch& L, bool uniform, int len, bool tg, int ntile, int chunk, int nblocks,
                                int threads, size_t lds, int n, int flags, hipStream_t st) {
   const dim3 g(nblocks), t(threads);
-  if (uniform) {
+  if (uniform && tg) {
+#define QPAT_ROW_LEN(N) \
+  case N: hipLaunchKernelGGL((row_kernel<MODE, true, N, true>), g, t, lds, st, L, ntile, chunk, n, flags); break;
+    switch (L.m.nx) {
+      QPAT_FOR_LENGTHS(QPAT_ROW_LEN)
+      default: return hipErrorInvalidValue;  // global-twiddle instances exist for these lengths only
+    }
+#undef QPAT_ROW_LEN
+  } else if (uniform) {
 #define QPAT_ROW_LEN(N) \
   case N: hipLaunchKernelGGL((row_kernel<MODE, true, N>), g, t, lds, st, L, ntile, chunk, n, flags); break;
     switch (L.m.nx) {
@@ -1713,6 +1733,7 @@ static hipError_t launch_row_t(const Launch& L, bool uniform, int len, int ntile
     }
 #undef QPAT_ROW_LEN
   } else {
+    if (tg) return hipErrorInvalidValue;
 #define QPAT_ROW_LEN(N) \
   case N: hipLaunchKernelGGL((row_kernel<MODE, false, N>), g, t, lds, st, L, ntile, chunk, n, flags); break;
     switch (len) {
@@ -1724,10 +1745,10 @@ static hipError_t launch_row_t(const Launch& L, bool uniform, int len, int ntile
   return hipGetLastError();
 }
 
-hipError_t launch_row(int mode, const Launch& L, bool uniform, int len, int ntile, int chunk, int nblocks,
+hipError_t launch_row(int mode, const Launch& L, bool uniform, int len, bool tg, int ntile, int chunk, int nblocks,
                       int threads, size_t lds, int n, int flags, hipStream_t st) {
 #define QPAT_ROW_CASE(m) \
-  case m: return launch_row_t<m>(L, uniform, len, ntile, chunk, nblocks, threads, lds, n, flags, st);
+  case m: return launch_row_t<m>(L, uniform, len, tg, ntile, chunk, nblocks, threads, lds, n, flags, st);
   switch (mode) {
     QPAT_ROW_CASE(RM_F1)
     QPAT_ROW_CASE(RM_F2)
@@ -1749,10 +1770,18 @@ hipError_t launch_row(int mode, const Launch& L, bool uniform, int len, int ntil
 }
 
 template <int CM>
-static hipError_t launch_col_t(int mcode, const Launch& L, bool uniform, int len, int ntile, int chunk,
+static hipError_t launch_col_t(int mcode, const Launch& L, bool uniform, int len, bool tg, int ntile, int chunk,
                                int nblocks, int threads, size_t lds, int n, hipStream_t st) {
   const dim3 g(nblocks), t(threads);
-  if (uniform) {
+  if (uniform && tg) {
+#define QPAT_COL_LEN(N) \
+  case N: hipLaunchKernelGGL((col_kernel<true, CM, N, true>), g, t, lds, st, L, ntile, chunk, mcode, n); break;
+    switch (L.m.ny) {
+      QPAT_FOR_COL_LENGTHS(QPAT_COL_LEN)
+      default: return hipErrorInvalidValue;
+    }
+#undef QPAT_COL_LEN
+  } else if (uniform) {
 #define QPAT_COL_LEN(N) \
   case N: hipLaunchKernelGGL((col_kernel<true, CM, N>), g, t, lds, st, L, ntile, chunk, mcode, n); break;
     switch (L.m.ny) {
@@ -1761,6 +1790,7 @@ static hipError_t launch_col_t(int mcode, const Launch& L, bool uniform, int len
     }
 #undef QPAT_COL_LEN
   } else {
+    if (tg) return hipErrorInvalidValue;
 #define QPAT_COL_LEN(N) \
   case N: hipLaunchKernelGGL((col_kernel<false, CM, N>), g, t, lds, st, L, ntile, chunk, mcode, n); break;
     switch (len) {
@@ -1772,10 +1802,10 @@ static hipError_t launch_col_t(int mcode, const Launch& L, bool uniform, int len
   return hipGetLastError();
 }
 
-hipError_t launch_col(int cm, int mcode, const Launch& L, bool uniform, int len, int ntile, int chunk,
+hipError_t launch_col(int cm, int mcode, const Launch& L, bool uniform, int len, bool tg, int ntile, int chunk,
                       int nblocks, int threads, size_t lds, int n, hipStream_t st) {
 #define QPAT_COL_CASE(c) \
-  case c: return launch_col_t<c>(mcode, L, uniform, len, ntile, chunk, nblocks, threads, lds, n, st);
+  case c: return launch_col_t<c>(mcode, L, uniform, len, tg, ntile, chunk, nblocks, threads, lds, n, st);
   switch (cm) {
     QPAT_COL_CASE(CM_GRADP1)
     QPAT_COL_CASE(CM_GRADM2)
@@ -1788,6 +1818,17 @@ hipError_t launch_col(int cm, int mcode, const Launch& L, bool uniform, int len,
 #undef QPAT_COL_CASE
 }
 
+bool kernels_have_length(int n, bool col) {
+#define QPAT_HAVE(N) if (n == N) return true;
+  if (col) {
+    QPAT_FOR_COL_LENGTHS(QPAT_HAVE)
+  } else {
+    QPAT_FOR_LENGTHS(QPAT_HAVE)
+  }
+#undef QPAT_HAVE
+  return false;
+}
+
 // Let every row / column pass kernel use up to `bytes` of dynamic LDS.
 template <typename K>
 static hipError_t allow_fn(K* k, size_t bytes) {
@@ -1798,8 +1839,9 @@ template <int MODE>
 static hipError_t allow_row(size_t bytes) {
   hipError_t e = allow_fn(&row_kernel<MODE, false, 0>, bytes);
   if (e == hipSuccess) e = allow_fn(&row_kernel<MODE, true, 0>, bytes);
-#define QPAT_ALLOW_ROW(N)                                                 \
-  if (e == hipSuccess) e = allow_fn(&row_kernel<MODE, true, N>, bytes); \
+#define QPAT_ALLOW_ROW(N)                                                       \
+  if (e == hipSuccess) e = allow_fn(&row_kernel<MODE, true, N>, bytes);       \
+  if (e == hipSuccess) e = allow_fn(&row_kernel<MODE, true, N, true>, bytes); \
   if (e == hipSuccess) e = allow_fn(&row_kernel<MODE, false, N>, bytes);
   QPAT_FOR_LENGTHS(QPAT_ALLOW_ROW)
 #undef QPAT_ALLOW_ROW
@@ -1809,8 +1851,9 @@ template <int CM>
 static hipError_t allow_col(size_t bytes) {
   hipError_t e = allow_fn(&col_kernel<false, CM, 0>, bytes);
   if (e == hipSuccess) e = allow_fn(&col_kernel<true, CM, 0>, bytes);
-#define QPAT_ALLOW_COL(N)                                               \
-  if (e == hipSuccess) e = allow_fn(&col_kernel<true, CM, N>, bytes); \
+#define QPAT_ALLOW_COL(N)                                                     \
+  if (e == hipSuccess) e = allow_fn(&col_kernel<true, CM, N>, bytes);       \
+  if (e == hipSuccess) e = allow_fn(&col_kernel<true, CM, N, true>, bytes); \
   if (e == hipSuccess) e = allow_fn(&col_kernel<false, CM, N>, bytes);
   QPAT_FOR_COL_LENGTHS(QPAT_ALLOW_COL)
 #undef QPAT_ALLOW_COL

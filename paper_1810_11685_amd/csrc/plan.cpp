@@ -170,6 +170,7 @@ struct Exec {
   bool uniform = false;
   int row_ntile = 0, col_ntile = 0, row_chunk = 0, col_chunk = 0;
   int tab_nx = 0, tab_ny = 0;  // table launches: the row / column length all items share (0: they differ)
+  bool row_tg = false, col_tg = false;  // uniform launches: FFT twiddles read from global memory
   bool lossy = false;
   // pinned staging ring for the I/O table
   static constexpr int kRing = 16;
@@ -277,6 +278,17 @@ qpat_status exec_build(Exec& E, const std::vector<Item>& items) {
     E.col_ntile = m0.nxh / m0.ct;
     E.row_chunk = (ni * E.row_ntile + kXcds - 1) / kXcds;
     E.col_chunk = (ni * E.col_ntile + kXcds - 1) / kXcds;
+    // Twiddles from global memory when a pass has at most about two blocks
+    // per CU (latency-bound: the LDS staging of the table is on the critical
+    // path); with more blocks the LDS copy is kept.
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      cus = 0;
+    E.row_tg = u && cus > 0 && kernels_have_length(m0.nx, false) && ni * E.row_ntile <= 2 * cus;
+    E.col_tg = u && cus > 0 && kernels_have_length(m0.ny, true) && ni * E.col_ntile <= 2 * cus;
+    if (E.row_tg) E.row_lds = row_lds_bytes(m0.nx, m0.rt, true);
+    if (E.col_tg) E.col_lds = col_lds_bytes(m0.ny, m0.ct, true);
   }
   HIPCHK(hipMalloc(&E.d_items, sizeof(Item) * ni));
   HIPCHK(hipMalloc(&E.d_io, sizeof(IO) * ni));
@@ -311,19 +323,19 @@ qpat_status exec_set_io(Exec& E, const std::vector<IO>& io, hipStream_t st) {
 
 hipError_t row(Exec& E, int mode, int n, int flags, hipStream_t st) {
   if (E.uniform)
-    return launch_row(mode, E.L, true, 0, E.row_ntile, E.row_chunk, E.row_chunk * kXcds, E.rthr, E.row_lds, n,
-                      flags, st);
+    return launch_row(mode, E.L, true, 0, E.row_tg, E.row_ntile, E.row_chunk, E.row_chunk * kXcds, E.rthr,
+                      E.row_lds, n, flags, st);
   Launch L = E.L;
   L.map = E.d_rowmap;
-  return launch_row(mode, L, false, E.tab_nx, 0, 0, E.nrow, E.rthr, E.row_lds, n, flags, st);
+  return launch_row(mode, L, false, E.tab_nx, false, 0, 0, E.nrow, E.rthr, E.row_lds, n, flags, st);
 }
 hipError_t col(Exec& E, int cm, int n, hipStream_t st, int mcode = 0) {
   if (E.uniform)
-    return launch_col(cm, mcode, E.L, true, 0, E.col_ntile, E.col_chunk, E.col_chunk * kXcds, E.cthr, E.col_lds,
-                      n, st);
+    return launch_col(cm, mcode, E.L, true, 0, E.col_tg, E.col_ntile, E.col_chunk, E.col_chunk * kXcds, E.cthr,
+                      E.col_lds, n, st);
   Launch L = E.L;
   L.map = E.d_colmap;
-  return launch_col(cm, mcode, L, false, E.tab_ny, 0, 0, E.ncol, E.cthr, E.col_lds, n, st);
+  return launch_col(cm, mcode, L, false, E.tab_ny, false, 0, 0, E.ncol, E.cthr, E.col_lds, n, st);
 }
 
 #define LCHK(expr)                           \

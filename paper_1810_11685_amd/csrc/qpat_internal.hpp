@@ -128,11 +128,16 @@ struct TraceRange {
 
 // Launch helpers implemented in kernels.hip.
 // `len`: for table launches (uniform false), the row (column) length every
-// item shares, or 0 when the items' lengths differ.
-hipError_t launch_row(int mode, const Launch& L, bool uniform, int len, int ntile, int chunk, int nblocks,
+// item shares, or 0 when the items' lengths differ.  `tg`: uniform launches
+// only, FFT twiddles read from global memory (the LDS size then excludes the
+// twiddle tables, see row_lds_bytes / col_lds_bytes); the line length must be
+// one of kernels_have_length's.
+hipError_t launch_row(int mode, const Launch& L, bool uniform, int len, bool tg, int ntile, int chunk, int nblocks,
                       int threads, size_t lds, int n, int flags, hipStream_t st);
-hipError_t launch_col(int cm, int mcode, const Launch& L, bool uniform, int len, int ntile, int chunk,
+hipError_t launch_col(int cm, int mcode, const Launch& L, bool uniform, int len, bool tg, int ntile, int chunk,
                       int nblocks, int threads, size_t lds, int n, hipStream_t st);
+// Row (col false) or column lengths with compile-time kernel instances.
+bool kernels_have_length(int n, bool col);
 hipError_t launch_combine(const Item* items, const IO* io, int nitems, int max_count,
                           hipStream_t st);
 hipError_t kernels_allow_lds(size_t bytes);
@@ -164,12 +169,13 @@ __host__ __device__ constexpr int lstride(int n) { return n + (n >> 3); }
 __host__ __device__ constexpr int col_lstride(int ny) { return lstride(ny) + 1; }
 
 // LDS bytes of one block of each pass: ping-pong line buffers, the twiddle
-// tables (columns: the plan and its reverse), and (rows) the staged sensor taps.
-inline size_t row_lds_bytes(int nx, int rt) {
-  return size_t(2 * rt * lstride(nx) + nx) * sizeof(float2) + kTapCap * (sizeof(Tap) + sizeof(float));
+// tables unless they are read from global memory (tg; columns: the plan and
+// its reverse), and (rows) the staged sensor taps.
+inline size_t row_lds_bytes(int nx, int rt, bool tg = false) {
+  return size_t(2 * rt * lstride(nx) + (tg ? 0 : nx)) * sizeof(float2) + kTapCap * (sizeof(Tap) + sizeof(float));
 }
-inline size_t col_lds_bytes(int ny, int ct) {
-  return (size_t(2) * 2 * ct * col_lstride(ny) + 2 * size_t(ny)) * sizeof(float2);
+inline size_t col_lds_bytes(int ny, int ct, bool tg = false) {
+  return (size_t(2) * 2 * ct * col_lstride(ny) + (tg ? 0 : 2 * size_t(ny))) * sizeof(float2);
 }
 
 }  // namespace qpat
