@@ -246,6 +246,43 @@ __device__ __forceinline__ float2* fft_c(float2* a, float2* b, int nlines, const
   }
 }
 
+// In-place version: every thread gathers and transforms all its butterflies
+// of a stage, the block synchronises, then every thread scatters its outputs
+// into the same buffer.  A thread holds at most kMaxPer values per stage
+// (the host bounds a tile to kMaxPer elements per thread).
+template <int N, int LS, int S, int NS>
+__device__ __forceinline__ float2* fft_c_ip(float2* a, int nlines, const float2* tw) {
+  if constexpr (S == plan_nst(N)) {
+    return a;
+  } else {
+    constexpr int R = plan_radix(N, S), NB = N / R, OFF = NS - plan_radix(N, 0);
+    constexpr int MB = (kMaxPer + R - 1) / R;
+    const unsigned total = unsigned(nlines) * NB;
+    float2 v[MB][R];
+#pragma unroll
+    for (int i = 0; i < MB; ++i) {
+      const unsigned it = threadIdx.x + i * blockDim.x;
+      if (it < total) {
+        const unsigned line = it / NB, j = it % NB;
+        static_assert(stage_folds(R, NS, NB), "stage offsets do not fold");
+        stage_load<R, NB>(v[i], a + line * LS, j);
+        stage_regs<R, NS, OFF>(v[i], j, tw);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < MB; ++i) {
+      const unsigned it = threadIdx.x + i * blockDim.x;
+      if (it < total) {
+        const unsigned line = it / NB, j = it % NB;
+        stage_store<R, NS>(v[i], a + line * LS, j);
+      }
+    }
+    __syncthreads();
+    return fft_c_ip<N, LS, S + 1, NS * R>(a, nlines, tw);
+  }
+}
+
 // Radix of stage s of the compile-time plan of length N, or of that plan in
 // reverse order (REV).  A power-of-two plan reversed still has power-of-two
 // Ns in every stage; its per-stage twiddles form their own table.
@@ -275,14 +312,16 @@ __device__ __forceinline__ float2* fft_stages(float2* a, float2* b, int nlines, 
 
 // FFT of `nlines` lines: compile-time plan for the common lengths, the
 // runtime plan otherwise.  Same contract as fft_lines; row lines have stride
-// lstride(n), column lines (COL) col_lstride(n).
+// lstride(n), column lines (COL) col_lstride(n).  IP (instances with a
+// compile-time length only, n == NF): the stages run in place in a (b unused).
 // NF != 0: a kernel instance for lines of length NF carries that compile-time
 // plan only (and the runtime plan as a fallback), so the other lengths'
 // unrolled code does not weigh on it.
-template <bool COL, int NF = 0>
+template <bool COL, int NF = 0, bool IP = false>
 __device__ __forceinline__ float2* fft_any(float2* a, float2* b, int nlines, int n, int ls, uint32_t rad,
                                            int nst, const float2* tw) {
   if constexpr (NF != 0) {
+    if constexpr (IP) return fft_c_ip<NF, COL ? col_lstride(NF) : lstride(NF), 0, 1>(a, nlines, tw);
     if (n == NF) return fft_c<NF, COL ? col_lstride(NF) : lstride(NF), 0, 1>(a, b, nlines, tw);
     return fft_lines(a, b, nlines, n, ls, rad, nst, tw);
   } else {
@@ -643,11 +682,17 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
   const int y0 = tile * rt;
   const int B = blockDim.x;
   const int LS = lstride(nx);
+  // IP: instances with a compile-time length run their FFT stages in place in
+  // one LDS buffer unless they read global twiddles (TG, launches of about
+  // one block per CU, where the extra barriers would cost): the freed LDS lets
+  // more blocks share a CU.
+  constexpr bool IP = NF > 0 && !TG;
+  constexpr int NBUF = IP ? 1 : 2;
   float2* bufA = lds;
-  float2* bufB = lds + rt * LS;
-  float2* const twl = lds + 2 * rt * LS;
+  float2* bufB = IP ? lds : lds + rt * LS;
+  float2* const twl = lds + NBUF * rt * LS;
   const float2* const tw = TG ? static_cast<const float2*>(M.twx) : twl;
-  void* tap_base = lds + 2 * rt * LS + (TG ? 0 : nx);
+  void* tap_base = lds + NBUF * rt * LS + (TG ? 0 : nx);
   const int tot = rt * nx;
   const float dt = M.dt;
   const float rnx = 1.0f / static_cast<float>(nx);
@@ -688,7 +733,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     put_pair<NF>(S, bufA, M);
     if constexpr (!TG) put_tw(TW, twl, nx);
     __syncthreads();
-    float2* r = fft_any<false, NF>(bufA, bufB, rt, nx, LS, M.radx, M.nstx, tw);
+    float2* r = fft_any<false, NF, IP>(bufA, bufB, rt, nx, LS, M.radx, M.nstx, tw);
     float2* o = other(r, bufA, bufB);
     // all LDS reads of the loop first: its LDS writes go to the other buffer,
     // which the compiler cannot tell, so an interleaved loop waits per element
@@ -700,6 +745,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
         zr[k] = r[j * LS + px(x)];
       }
     }
+    if constexpr (IP) __syncthreads();  // the loop below writes the buffer just read
     FOR_K {
       const int it = threadIdx.x + k * B;
       if (it < tot) {
@@ -714,7 +760,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
       }
     }
     __syncthreads();
-    r = fft_any<false, NF>(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
+    r = fft_any<false, NF, IP>(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
     store_pair_spectra<NF>(r, M, W.s0, W.s1, tile);
   } else if constexpr (BM == RM_F2 || BM == RM_F2L) {
     // eq num-rho with the additive source of eq s1 (dt s = p0 / (2 d c^2), d = 2)
@@ -758,7 +804,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     float2* r = nullptr;
     float2* o = bufA;
     if (!skip) {
-      r = fft_any<false, NF>(bufA, bufB, rt, nx, LS, M.radx, M.nstx, tw);
+      r = fft_any<false, NF, IP>(bufA, bufB, rt, nx, LS, M.radx, M.nstx, tw);
       o = other(r, bufA, bufB);
     }
     float2 zr[kMaxPer];
@@ -771,6 +817,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
         }
       }
     }
+    if constexpr (IP) __syncthreads();  // the loop below writes the buffer just read
     FOR_K {
       const int it = threadIdx.x + k * B;
       if (it < tot) {
@@ -807,12 +854,12 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     if constexpr (BM == RM_F2L) taps_put(T, false);
     __syncthreads();
     if constexpr (BM == RM_F2) {
-      r = fft_any<false, NF>(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
+      r = fft_any<false, NF, IP>(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
       store_rowpair_spectra<NF>(r, M, W.s0, tile);
       store_rowpair_spectra<NF>(r + (rt / 2) * LS, M, W.s1, tile);
     } else {
       if (!(flags & FL_NO_SENSORS)) sensor_partials(M, T, o, y0, W.part, n + 1);
-      r = fft_any<false, NF>(o, other(o, bufA, bufB), rt / 2, nx, LS, M.radx, M.nstx, tw);
+      r = fft_any<false, NF, IP>(o, other(o, bufA, bufB), rt / 2, nx, LS, M.radx, M.nstx, tw);
       store_rowpair_spectra<NF>(r, M, W.s0, tile);
     }
   } else if constexpr (BM == RM_F3) {
@@ -842,7 +889,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     if constexpr (!TG) put_tw(TW, twl, nx);
     __syncthreads();
     taps_fetch(T, M, nullptr, 0);
-    float2* r = fft_any<false, NF>(bufA, bufB, rt, nx, LS, M.radx, M.nstx, tw);
+    float2* r = fft_any<false, NF, IP>(bufA, bufB, rt, nx, LS, M.radx, M.nstx, tw);
     float2* o = other(r, bufA, bufB);
     float ysr[kMaxPer], yur[kMaxPer];
     FOR_K {
@@ -853,6 +900,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
         yur[k] = rowpair_val(r + (rt / 2) * LS, j, x, nx);
       }
     }
+    if constexpr (IP) __syncthreads();  // the loop below writes the buffer just read
     FOR_K {
       const int it = threadIdx.x + k * B;
       if (it < tot) {
@@ -873,7 +921,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     taps_put(T, false);
     __syncthreads();
     if (!(flags & FL_NO_SENSORS)) sensor_partials(M, T, o, y0, W.part, n + 1);
-    r = fft_any<false, NF>(o, other(o, bufA, bufB), rt / 2, nx, LS, M.radx, M.nstx, tw);
+    r = fft_any<false, NF, IP>(o, other(o, bufA, bufB), rt / 2, nx, LS, M.radx, M.nstx, tw);
     store_rowpair_spectra<NF>(r, M, W.s0, tile);
   } else if constexpr (BM == RM_A1 || BM == RM_A1L) {
     // transpose of eqs num-m and num-p: p* += M^T r_{n+1}; q = c^2 p*
@@ -935,7 +983,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     taps_fetch(T, M, W.part, n + 1);
     float2* r = bufA;
     if (!first) {
-      r = fft_any<false, NF>(bufA, bufB, half, nx, LS, M.radx, M.nstx, tw);
+      r = fft_any<false, NF, IP>(bufA, bufB, half, nx, LS, M.radx, M.nstx, tw);
       // p* = -(grad_x^- g_x + grad_y^- g_y): negate the (conjugated) inverse
 #pragma unroll 4
       for (int it = threadIdx.x; it < half * LS; it += B) {
@@ -958,6 +1006,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
         pbr[k] = pcomp(r, j, x, nx);
       }
     }
+    if constexpr (IP) __syncthreads();  // the loop below writes the buffer just read
     FOR_K {
       const int it = threadIdx.x + k * B;
       if (it < tot) {
@@ -987,11 +1036,11 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     }
     __syncthreads();
     if constexpr (BM == RM_A1) {
-      r = fft_any<false, NF>(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
+      r = fft_any<false, NF, IP>(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
       store_rowpair_spectra<NF>(r, M, W.s0, tile);
       store_rowpair_spectra<NF>(r + half * LS, M, W.s1, tile);
     } else if (n != -1) {
-      r = fft_any<false, NF>(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
+      r = fft_any<false, NF, IP>(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
       store_pair_spectra<NF>(r, M, W.s0, W.s1, tile);
     }
   } else if constexpr (BM == RM_A2) {
@@ -1032,7 +1081,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     put_rowpair<NF>(S1, bufA + (rt / 2) * LS, M);
     if constexpr (!TG) put_tw(TW, twl, nx);
     __syncthreads();
-    float2* r = fft_any<false, NF>(bufA, bufB, rt, nx, LS, M.radx, M.nstx, tw);
+    float2* r = fft_any<false, NF, IP>(bufA, bufB, rt, nx, LS, M.radx, M.nstx, tw);
     float2* o = other(r, bufA, bufB);
     float ydr[kMaxPer], yar[kMaxPer];
     FOR_K {
@@ -1043,6 +1092,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
         yar[k] = rowpair_val(r + (rt / 2) * LS, j, x, nx);
       }
     }
+    if constexpr (IP) __syncthreads();  // the loop below writes the buffer just read
     FOR_K {
       const int it = threadIdx.x + k * B;
       if (it < tot) {
@@ -1063,7 +1113,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     }
     __syncthreads();
     if (n != -1) {
-      r = fft_any<false, NF>(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
+      r = fft_any<false, NF, IP>(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
       store_pair_spectra<NF>(r, M, W.s0, W.s1, tile);
     }
   } else if constexpr (BM == RM_A3) {
@@ -1090,7 +1140,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     put_pair<NF>(S, bufA, M);
     if constexpr (!TG) put_tw(TW, twl, nx);
     __syncthreads();
-    float2* r = fft_any<false, NF>(bufA, bufB, rt, nx, LS, M.radx, M.nstx, tw);
+    float2* r = fft_any<false, NF, IP>(bufA, bufB, rt, nx, LS, M.radx, M.nstx, tw);
     float2* o = other(r, bufA, bufB);
     float2 zr[kMaxPer];
     FOR_K {
@@ -1100,6 +1150,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
         zr[k] = r[j * LS + px(x)];
       }
     }
+    if constexpr (IP) __syncthreads();  // the loop below writes the buffer just read
     FOR_K {
       const int it = threadIdx.x + k * B;
       if (it < tot) {
@@ -1114,7 +1165,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
       }
     }
     __syncthreads();
-    r = fft_any<false, NF>(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
+    r = fft_any<false, NF, IP>(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
     store_pair_spectra<NF>(r, M, W.s0, W.s1, tile);
   } else if constexpr (BM == RM_FWD1) {
     const float* src = X.in;
@@ -1137,7 +1188,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     }
     if constexpr (!TG) put_tw(TW, twl, nx);
     __syncthreads();
-    float2* r = fft_any<false, NF>(bufA, bufB, rt / 2, nx, LS, M.radx, M.nstx, tw);
+    float2* r = fft_any<false, NF, IP>(bufA, bufB, rt / 2, nx, LS, M.radx, M.nstx, tw);
     store_rowpair_spectra<NF>(r, M, W.s0, tile);
   } else if constexpr (BM == RM_INV1) {
     RowPairRegs S0;
@@ -1147,7 +1198,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     put_rowpair<NF>(S0, bufA, M);
     if constexpr (!TG) put_tw(TW, twl, nx);
     __syncthreads();
-    float2* r = fft_any<false, NF>(bufA, bufB, rt / 2, nx, LS, M.radx, M.nstx, tw);
+    float2* r = fft_any<false, NF, IP>(bufA, bufB, rt / 2, nx, LS, M.radx, M.nstx, tw);
     float* dst = X.out;
 #pragma unroll 4
     for (int it = threadIdx.x; it < tot; it += B) {

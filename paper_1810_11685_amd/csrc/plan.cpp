@@ -287,8 +287,15 @@ qpat_status exec_build(Exec& E, const std::vector<Item>& items) {
       cus = 0;
     E.row_tg = u && cus > 0 && kernels_have_length(m0.nx, false) && ni * E.row_ntile <= 2 * cus;
     E.col_tg = u && cus > 0 && kernels_have_length(m0.ny, true) && ni * E.col_ntile <= 2 * cus;
-    if (E.row_tg) E.row_lds = row_lds_bytes(m0.nx, m0.rt, true);
+    // row instances with a compile-time length run in place unless they read
+    // global twiddles (one LDS line buffer instead of two)
+    if (u) E.row_lds = row_lds_bytes(m0.nx, m0.rt, E.row_tg, kernels_have_length(m0.nx, false) && !E.row_tg);
     if (E.col_tg) E.col_lds = col_lds_bytes(m0.ny, m0.ct, true);
+  }
+  if (!E.uniform && E.tab_nx && kernels_have_length(E.tab_nx, false)) {
+    E.row_lds = 0;
+    for (int i = 0; i < ni; ++i)
+      E.row_lds = std::max(E.row_lds, row_lds_bytes(items[i].m.nx, items[i].m.rt, false, true));
   }
   HIPCHK(hipMalloc(&E.d_items, sizeof(Item) * ni));
   HIPCHK(hipMalloc(&E.d_io, sizeof(IO) * ni));
