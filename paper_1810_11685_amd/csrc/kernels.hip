@@ -529,19 +529,41 @@ __device__ __forceinline__ float rowpair_val(const float2* buf, int j, int x, in
 // a block; the taps themselves are fetched after the first barrier (thread i
 // holds tap e0 + i, blockDim.x >= kTapCap) and written to LDS only where the
 // sensors are used, so their latency hides behind the first FFT.
+constexpr int kConRegs = 4;  // scatter contributions of a node held in registers
+
 struct TapStage {
   Tap* tl;     // [kTapCap]
   float* rv;   // [kTapCap]
   int e0, e1;  // CSR range of the tile
   int w[8];    // this thread's tap, word by word
   float r;     // and its residual sample
+  int n0, n1;  // adjoint: CSR range of the tile's scatter nodes
+  int4 nd;     // this thread's node (y, x, c0, c1)
+  int con[kConRegs];  // and its first contributions
 };
 
-__device__ __forceinline__ void taps_range(TapStage& T, const Medium& M, void* base, int y0, int rt) {
+__device__ __forceinline__ void taps_range(TapStage& T, const Medium& M, void* base, int y0, int rt,
+                                           bool nodes = false) {
   T.tl = reinterpret_cast<Tap*>(base);
   T.rv = reinterpret_cast<float*>(T.tl + kTapCap);
   T.e0 = M.tap_off[y0];
   T.e1 = M.tap_off[y0 + rt];
+  if (nodes) {
+    T.n0 = M.node_off[y0];
+    T.n1 = M.node_off[y0 + rt];
+  }
+}
+
+// Adjoint: this thread's scatter node and its first contributions (issued
+// early, consumed after the inverse FFT).
+__device__ __forceinline__ void nodes_fetch(TapStage& T, const Medium& M) {
+  const int i = threadIdx.x;
+  if (i < T.n1 - T.n0) {
+    T.nd = M.nodes[T.n0 + i];
+#pragma unroll
+    for (int k = 0; k < kConRegs; ++k)
+      if (T.nd.z + k < T.nd.w) T.con[k] = M.scon[T.nd.z + k];
+  }
 }
 
 // rtap: residual samples in tap order for sample m ([nt][ntap]), or null
@@ -591,19 +613,33 @@ __device__ __forceinline__ void sensor_partials(const Medium& M, const TapStage&
   }
 }
 
-// Adjoint sensor scatter M^T r for rows y0 .. y0+rt-1, one thread per row so
-// taps hitting the same node are added in a fixed order.
+// Adjoint sensor scatter M^T r for rows y0 .. y0+rt-1 as a gather: one thread
+// per grid node a tap touches adds that node's contributions in increasing
+// tap index, the order of a serial scatter over the row's taps, so the result
+// does not depend on the thread count.
+__device__ __forceinline__ float scatter_term(const Medium& M, const TapStage& T, const float* __restrict__ rtap,
+                                              int m, float acc, int code) {
+  const int e = code >> 1;
+  const bool staged = e - T.e0 < kTapCap;
+  const Tap* src = staged ? T.tl + (e - T.e0) : M.taps + e;
+  const float w = (code & 1) ? src->wr : src->wl;
+  const float rv = staged ? T.rv[e - T.e0] : rtap[unsigned(m) * unsigned(2 * M.ns) + e];
+  return acc + w * rv;
+}
+
 __device__ __forceinline__ void sensor_scatter(const Medium& M, const TapStage& T, float2* buf, int y0,
-                                               int rt, const float* __restrict__ rtap, int m) {
-  const int r = threadIdx.x;
-  if (r < rt) {
-    const int a = M.tap_off[y0 + r], b = M.tap_off[y0 + r + 1];
-    for (int e = a; e < b; ++e) {
-      const Tap t = tap_at(M, T, e);
-      const float rv = (e - T.e0 < kTapCap) ? T.rv[e - T.e0] : rtap[unsigned(m) * unsigned(2 * M.ns) + e];
-      pcomp(buf, r, t.ixl, M.nx) += t.wl * rv;
-      pcomp(buf, r, t.ixr, M.nx) += t.wr * rv;
-    }
+                                               const float* __restrict__ rtap, int m) {
+  const int nn = T.n1 - T.n0;
+  for (int i = threadIdx.x; i < nn; i += blockDim.x) {
+    const bool pre = i == int(threadIdx.x);  // the first round's node was fetched early
+    const int4 nd = pre ? T.nd : M.nodes[T.n0 + i];
+    float& v = pcomp(buf, nd.x - y0, nd.y, M.nx);
+    float acc = v;
+#pragma unroll
+    for (int k = 0; k < kConRegs; ++k)
+      if (nd.z + k < nd.w) acc = scatter_term(M, T, rtap, m, acc, pre ? T.con[k] : M.scon[nd.z + k]);
+    for (int c = nd.z + kConRegs; c < nd.w; ++c) acc = scatter_term(M, T, rtap, m, acc, M.scon[c]);
+    v = acc;
   }
 }
 
@@ -676,10 +712,10 @@ __device__ __forceinline__ void row_args_batch(const Launch& L, int ntile, int c
                  "s"(m.tap_off));
   } else if constexpr (BM == RM_A1) {
     asm volatile("" ::"s"(w.s0), "s"(w.part), "s"(m.c2), "s"(m.c2eta), "s"(m.c2tau), "s"(m.tap_off),
-                 "s"(m.taps), "s"(m.ny), "s"(m.ns));
+                 "s"(m.taps), "s"(m.ny), "s"(m.ns), "s"(m.node_off), "s"(m.nodes), "s"(m.scon));
   } else if constexpr (BM == RM_A1L) {
     asm volatile("" ::"s"(w.s0), "s"(w.f2), "s"(w.f3), "s"(m.c2), "s"(m.rho0), "s"(m.arx), "s"(m.ary),
-                 "s"(m.tap_off));
+                 "s"(m.tap_off), "s"(m.node_off), "s"(m.nodes));
   } else if constexpr (BM == RM_A2) {
     asm volatile("" ::"s"(w.s0), "s"(w.s1), "s"(w.q), "s"(w.f2), "s"(w.f3), "s"(m.rho0), "s"(m.arx), "s"(m.ary));
   } else {
@@ -982,7 +1018,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     float c2[kMaxPer], ce[kMaxPer], ctau[kMaxPer], rbx0[kMaxPer], rby0[kMaxPer], r0[kMaxPer];
     float ax[kMaxPer], ay[kMaxPer], gacc[kMaxPer];
     TapStage T;
-    taps_range(T, M, tap_base, y0, rt);
+    taps_range(T, M, tap_base, y0, rt, true);
     RowPairRegs S0;
     TwRegs TW;
     if (!first) fetch_rowpair<NF>(S0, M, W.s0, tile);
@@ -1033,6 +1069,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     if constexpr (!TG) put_tw(TW, twl, nx);
     __syncthreads();
     taps_fetch(T, M, W.part, n + 1);
+    nodes_fetch(T, M);
     float2* r = bufA;
     if (!first) {
       r = fft_any<false, NF, IP>(bufA, bufB, half, nx, LS, M.radx, M.nstx, tw);
@@ -1047,7 +1084,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     }
     taps_put(T, true);
     __syncthreads();
-    sensor_scatter(M, T, r, y0, rt, W.part, n + 1);
+    sensor_scatter(M, T, r, y0, W.part, n + 1);
     __syncthreads();
     float2* o = other(r, bufA, bufB);
     float pbr[kMaxPer];

@@ -566,6 +566,30 @@ void build_taps(const qpat_params& p, std::vector<Tap>& taps, std::vector<int>& 
   off[p.ny] = int(taps.size());
 }
 
+// The adjoint of the tap gather as a gather per grid node: for every node a
+// tap touches, its contributions (tap e, left / right weight) in increasing e,
+// the order in which a serial scatter over the taps of its row adds them.
+void build_scatter(const qpat_params& p, const std::vector<Tap>& taps, const std::vector<int>& toff,
+                   std::vector<int4>& nodes, std::vector<int>& noff, std::vector<int>& scon) {
+  nodes.clear();
+  scon.clear();
+  noff.assign(p.ny + 1, 0);
+  for (int y = 0; y < p.ny; ++y) {
+    noff[y] = int(nodes.size());
+    std::map<int, std::vector<int>> byx;   // x -> contributions in tap order
+    for (int e = toff[y]; e < toff[y + 1]; ++e) {
+      byx[taps[e].ixl].push_back(e << 1);
+      byx[taps[e].ixr].push_back((e << 1) | 1);
+    }
+    for (const auto& kv : byx) {
+      const int c0 = int(scon.size());
+      for (int c : kv.second) scon.push_back(c);
+      nodes.push_back(make_int4(y, kv.first, c0, int(scon.size())));
+    }
+  }
+  noff[p.ny] = int(nodes.size());
+}
+
 // Carve aligned sub-buffers out of one allocation.
 struct Carver {
   size_t off = 0;
@@ -695,7 +719,12 @@ qpat_status plan_build(qpat_plan P, const double* c0, const double* rho0) {
   std::vector<Tap> taps;
   std::vector<int> toff;
   build_taps(p, taps, toff);
+  std::vector<int4> snodes;
+  std::vector<int> snoff, scon;
+  build_scatter(p, taps, toff, snodes, snoff, scon);
   if (taps.empty()) taps.push_back(Tap{});
+  if (snodes.empty()) snodes.push_back(make_int4(0, 0, 0, 0));
+  if (scon.empty()) scon.push_back(0);
 
   // ---- upload (host checks are done; from here on a device is needed)
   {
@@ -712,6 +741,8 @@ qpat_status plan_build(qpat_plan P, const double* c0, const double* rho0) {
   const size_t o_kap = cv.take<float>(nt2), o_ldis = cv.take<float>(nt2), o_labs = cv.take<float>(nt2);
   const size_t o_twx = cv.take<float2>(nx), o_twy = cv.take<float2>(ny), o_twyr = cv.take<float2>(ny);
   const size_t o_toff = cv.take<int>(toff.size()), o_taps = cv.take<Tap>(taps.size());
+  const size_t o_snoff = cv.take<int>(snoff.size()), o_snodes = cv.take<int4>(snodes.size()),
+               o_scon = cv.take<int>(scon.size());
   const size_t total = cv.off;
   std::vector<char> host(total, 0);
   auto put = [&](size_t o, const void* src, size_t bytes) { std::memcpy(host.data() + o, src, bytes); };
@@ -737,6 +768,9 @@ qpat_status plan_build(qpat_plan P, const double* c0, const double* rho0) {
   put(o_twyr, twyr.data(), ny * 8);
   put(o_toff, toff.data(), toff.size() * 4);
   put(o_taps, taps.data(), taps.size() * sizeof(Tap));
+  put(o_snoff, snoff.data(), snoff.size() * 4);
+  put(o_snodes, snodes.data(), snodes.size() * sizeof(int4));
+  put(o_scon, scon.data(), scon.size() * 4);
   char* d = nullptr;
   HIPCHK(hipMalloc(&d, total));
   P->d_med = d;
@@ -776,6 +810,9 @@ qpat_status plan_build(qpat_plan P, const double* c0, const double* rho0) {
   M.twyr = (const float2*)(d + o_twyr);
   M.tap_off = (const int*)(d + o_toff);
   M.taps = (const Tap*)(d + o_taps);
+  M.node_off = (const int*)(d + o_snoff);
+  M.nodes = (const int4*)(d + o_snodes);
+  M.scon = (const int*)(d + o_scon);
   default_tiles(nx, ny, &P->rt, &P->ct, &P->rthr, &P->cthr);
   M.rt = P->rt;
   M.ct = P->ct;

@@ -44,6 +44,12 @@ struct Medium {
   const float2* twyr;                                 // the same for the reversed ny plan
   const int* tap_off;                                 // [ny+1] CSR offsets into taps
   const Tap* taps;
+  // Adjoint scatter M^T r as a gather per grid node: node_off [ny+1] CSR
+  // offsets into nodes (y, x, c0, c1), whose contributions scon[c0..c1) are
+  // (tap index << 1 | right weight), in increasing tap index.
+  const int* node_off;
+  const int4* nodes;
+  const int* scon;
 };
 
 // Per-vector work buffers (owned by the plan).
