@@ -310,6 +310,86 @@ __device__ __forceinline__ float2* fft_stages(float2* a, float2* b, int nlines, 
   }
 }
 
+// Stages S .. S1-1 of the forward plan of length N in place (see fft_c_ip).
+template <int N, int LS, int S, int S1, int NS>
+__device__ __forceinline__ float2* fft_range_ip(float2* a, int nlines, const float2* tw) {
+  if constexpr (S == S1) {
+    return a;
+  } else {
+    constexpr int R = plan_radix(N, S), NB = N / R, OFF = NS - plan_radix(N, 0);
+    constexpr int MB = (kMaxPer + R - 1) / R;
+    const unsigned total = unsigned(nlines) * NB;
+    float2 v[MB][R];
+#pragma unroll
+    for (int i = 0; i < MB; ++i) {
+      const unsigned it = threadIdx.x + i * blockDim.x;
+      if (it < total) {
+        const unsigned line = it / NB, j = it % NB;
+        stage_load<R, NB>(v[i], a + line * LS, j);
+        stage_regs<R, NS, OFF>(v[i], j, tw);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < MB; ++i) {
+      const unsigned it = threadIdx.x + i * blockDim.x;
+      if (it < total) {
+        const unsigned line = it / NB, j = it % NB;
+        stage_store<R, NS>(v[i], a + line * LS, j);
+      }
+    }
+    __syncthreads();
+    return fft_range_ip<N, LS, S + 1, S1, NS * R>(a, nlines, tw);
+  }
+}
+
+// Row lines whose plan starts and ends with the same radix (512 = 8 8 8):
+// the two FFTs of a row pass around a pointwise update share their boundary
+// stage in registers.  The last stage of the first FFT leaves butterfly jj of
+// a line with the values at jj + r N/R, exactly the inputs of butterfly jj in
+// the first stage of the second FFT, so one thread per (line, jj) runs that
+// last stage, the update `pw(line, jj, v)` on its R values, and that first
+// stage, skipping an LDS round trip and a barrier on each side of the
+// update.  The arithmetic is the unfused sequence's.  Ends synchronised with
+// the second FFT's result in the returned buffer.
+template <int N>
+__host__ __device__ constexpr bool row_fusable() {
+  return N > 0 && (N & (N - 1)) == 0 && plan_radix(N, 0) == plan_radix(N, plan_nst(N) - 1) && plan_nst(N) >= 2;
+}
+template <int N, bool IP, class PW>
+__device__ __forceinline__ float2* fft_fused(float2* a, float2* b, int nlines, const float2* tw, PW pw) {
+  constexpr int LS = lstride(N), NST = plan_nst(N), R = plan_radix(N, 0), NB = N / R;
+  constexpr int OFFL = NB - R;  // twiddles of the last stage (Ns = N / R)
+  float2* r;
+  if constexpr (IP) r = fft_range_ip<N, LS, 0, NST - 1, 1>(a, nlines, tw);
+  else r = fft_stages<N, false, LS, 0, NST - 1, 1>(a, b, nlines, tw);
+  float2* o = IP ? r : (r == a ? b : a);
+  const unsigned it = threadIdx.x, total = unsigned(nlines) * NB;  // host bound: total <= blockDim.x
+  const bool act = it < total;
+  const unsigned line = act ? it / NB : 0, jj = it % NB;
+  float2 v[R];
+  if (act) {
+    stage_load<R, NB>(v, r + line * LS, jj);
+    stage_regs<R, NB, OFFL>(v, jj, tw);
+  }
+  if constexpr (IP) __syncthreads();
+  if (act) {
+    // The values pass an LDS store and load in the unfused sequence; the
+    // empty asm statements keep them opaque here too, so no multiply of one
+    // side is contracted with an add of the other (same rounding, same bits).
+#pragma unroll
+    for (int q = 0; q < R; ++q) asm volatile("" : "+v"(v[q].x), "+v"(v[q].y));
+    pw(int(line), int(jj), v);
+#pragma unroll
+    for (int q = 0; q < R; ++q) asm volatile("" : "+v"(v[q].x), "+v"(v[q].y));
+    stage_regs<R, 1, 0>(v, jj, tw);
+    stage_store<R, 1>(v, o + line * LS, jj);
+  }
+  __syncthreads();
+  if constexpr (IP) return fft_range_ip<N, LS, 1, NST, R>(o, nlines, tw);
+  else return fft_stages<N, false, LS, 1, NST, R>(o, r, nlines, tw);
+}
+
 // FFT of `nlines` lines: compile-time plan for the common lengths, the
 // runtime plan otherwise.  Same contract as fft_lines; row lines have stride
 // lstride(n), column lines (COL) col_lstride(n).  IP (instances with a
@@ -797,7 +877,59 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
   // RM_X variants: this iterate's slot of the sound-speed sensitivities
   float* const sens = XS ? X.sens + size_t(unsigned(flags) >> kSlotShift) * unsigned(nx * M.ny) : nullptr;
 
-  if constexpr (BM == RM_F1) {
+  if constexpr ((BM == RM_F1 || BM == RM_A3) && row_fusable<NF>()) {
+    // eq num-vel (RM_F1: v_i = A_i (A_i v_i - dt/rho_i d/dr_i^+ p)) and its
+    // transpose (RM_A3) with the update between the two FFTs in registers:
+    // one thread per (row, butterfly jj) of the boundary stage, which holds
+    // the row's values at x = jj + r N/R
+    constexpr int R = plan_radix(NF, 0), NB = NF / R;
+    const bool first = BM == RM_F1 ? (n == 0) : (n == M.nt - 2);  // the state starts at zero
+    float v0x[R], v0y[R], bx[R], by[R], ax[R];
+    float ay = 0.f;
+    PairRegs S;
+    TwRegs TW;
+    fetch_pair<NF>(S, M, W.s0, W.s1, tile);
+    if constexpr (!TG) fetch_tw(TW, M.twx, nx);
+    {
+      const unsigned it = min(unsigned(threadIdx.x), unsigned(rt * NB) - 1u);
+      const int j = int(it / NB), jj = int(it % NB), y = y0 + j;
+      const unsigned base = rowoff(y) + jj;
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        v0x[q] = W.f0[base + q * NB];
+        v0y[q] = W.f1[base + q * NB];
+        bx[q] = M.bx[base + q * NB];
+        by[q] = M.by[base + q * NB];
+        ax[q] = M.avx[jj + q * NB];
+      }
+      ay = M.avy[y];
+    }
+    put_pair<NF>(S, bufA, M);
+    if constexpr (!TG) put_tw(TW, twl, nx);
+    __syncthreads();
+    auto pw = [&](int j, int jj, float2* v) {
+      const unsigned base = rowoff(y0 + j) + jj;
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const float2 z = v[q];
+        if constexpr (BM == RM_F1) {
+          const float vx = ax[q] * (ax[q] * (first ? 0.f : v0x[q]) - bx[q] * z.x);
+          const float vy = ay * (ay * (first ? 0.f : v0y[q]) + by[q] * z.y);
+          W.f0[base + q * NB] = vx;
+          W.f1[base + q * NB] = vy;
+          v[q] = make_float2(vx, vy);
+        } else {
+          const float vbx = (first ? 0.f : v0x[q]) - z.x;
+          const float vby = (first ? 0.f : v0y[q]) + z.y;
+          W.f0[base + q * NB] = ax[q] * ax[q] * vbx;
+          W.f1[base + q * NB] = ay * ay * vby;
+          v[q] = make_float2(-ax[q] * bx[q] * vbx, -ay * by[q] * vby);
+        }
+      }
+    };
+    float2* r = fft_fused<NF, IP>(bufA, bufB, rt, tw, pw);
+    store_pair_spectra<NF>(r, M, W.s0, W.s1, tile);
+  } else if constexpr (BM == RM_F1) {
     // eq num-vel: v_i = A_i (A_i v_i - dt/rho_i d/dr_i^+ p)
     const bool first = (n == 0);  // v^{-1/2} = 0
     float vxo[kMaxPer], vyo[kMaxPer], bx[kMaxPer], by[kMaxPer], ax[kMaxPer], ay[kMaxPer];
