@@ -231,6 +231,26 @@ def test_batch_equals_single_bitwise(q):
         assert np.array_equal(gb[i], N(plan.adjoint(rb[i])))
 
 
+@pytest.mark.parametrize("n,a0", [(512, 0.75), (512, 0.0), (256, 0.75), (384, 0.75), (1024, 0.75)])
+def test_launch_variants_bitwise_at_compiled_lengths(q, n, a0):
+    """Lengths with compile-time kernel instances run different code by block
+    count: about one block per CU takes global twiddles and ping-pong stages
+    (at 512 the velocity passes share their FFTs' boundary stage in
+    registers), several blocks per CU take LDS twiddles and in-place row
+    stages.  One vector and a batch of eight (which crosses that line) must
+    agree bit for bit, forward and adjoint, lossy and lossless."""
+    nt = 24 if n >= 1024 else 40
+    prm, c0, rho0, _ = problem(n, n, nt, alpha0_db=a0, ns=32)
+    plan = q.Plan(prm, c0, rho0)
+    plan.set_tiles(2, 1, 512 if n <= 512 else 256, 128 if n <= 512 else 256)
+    x = T(np.stack([qi.smooth_noise(n, n, 3.0, 70 + b) for b in range(8)]))
+    r = T(qi.gaussian_field((8, nt, 32), 71))
+    db, gb = N(plan.forward(x)), N(plan.adjoint(r))
+    for i in (0, 5):
+        assert np.array_equal(db[i], N(plan.forward(x[i])))
+        assert np.array_equal(gb[i], N(plan.adjoint(r[i])))
+
+
 def test_tiles_do_not_change_results(q):
     prm, c0, rho0, p0 = problem(64, 64, 50)
     plan = q.Plan(prm, c0, rho0)
