@@ -157,7 +157,7 @@ __device__ float2* fft_lines(float2* a, float2* b, int nlines, int n, int ls, ui
   return a;
 }
 
-// Compile-time versions of the same radix plans ([2|4] 8 ... 8 [3]) for the
+// Compile-time versions of the same radix plans (see plan_radix) for the
 // common line lengths: every stage's radix, stride and twiddle step is a
 // constant, so index arithmetic folds into shifts and LDS immediate offsets.
 __host__ __device__ constexpr int ilog2c(int v) {
@@ -170,16 +170,20 @@ __host__ __device__ constexpr int plan_nst(int n) {
   const int a = ilog2c(three ? n / 3 : n);
   return (a % 3 ? 1 : 0) + a / 3 + (three ? 1 : 0);
 }
+// Power-of-two part 2^a: radix 8 stages, with the remainder as two radix-4
+// stages at both ends (a = 3q + 1: 4 8..8 4) or one radix-4 second stage
+// (a = 3q + 2: 8 4 8..8), so that a plan of two or more stages starts and
+// ends with the same radix where it can (the row passes fuse the boundary
+// stage of two FFTs); then the radix-3 stage, if any.
 __host__ __device__ constexpr int plan_radix(int n, int s) {
   const bool three = n % 3 == 0;
   const int a = ilog2c(three ? n / 3 : n);
   const int rem = a % 3, q = a / 3;
-  int idx = 0;
-  if (rem) {
-    if (s == 0) return rem == 1 ? 2 : 4;
-    idx = 1;
-  }
-  return s < idx + q ? 8 : 3;
+  const int np2 = (rem ? 1 : 0) + q;  // power-of-two stages
+  if (s >= np2) return 3;
+  if (rem == 0) return 8;
+  if (rem == 1) return q == 0 ? 2 : ((s == 0 || s == np2 - 1) ? 4 : 8);
+  return q == 0 ? 4 : (s == 1 ? 4 : 8);
 }
 
 // Padded offset of a displacement d from a base position b when b + d stays
@@ -356,34 +360,48 @@ template <int N>
 __host__ __device__ constexpr bool row_fusable() {
   return N > 0 && (N & (N - 1)) == 0 && plan_radix(N, 0) == plan_radix(N, plan_nst(N) - 1) && plan_nst(N) >= 2;
 }
+template <int N>
+__host__ __device__ constexpr int fused_slots() { return (kMaxPer + plan_radix(N, 0) - 1) / plan_radix(N, 0); }
+// pw(i, line, jj, v): the update of butterfly slot i (0 <= i < fused_slots)
+// of this thread, (line, jj), on its R values v.  A thread has at most
+// fused_slots butterflies (the host bounds a tile to kMaxPer elements per
+// thread), slot i being butterfly threadIdx.x + i blockDim.x.
 template <int N, bool IP, class PW>
 __device__ __forceinline__ float2* fft_fused(float2* a, float2* b, int nlines, const float2* tw, PW pw) {
-  constexpr int LS = lstride(N), NST = plan_nst(N), R = plan_radix(N, 0), NB = N / R;
+  constexpr int LS = lstride(N), NST = plan_nst(N), R = plan_radix(N, 0), NB = N / R, MB = fused_slots<N>();
   constexpr int OFFL = NB - R;  // twiddles of the last stage (Ns = N / R)
   float2* r;
   if constexpr (IP) r = fft_range_ip<N, LS, 0, NST - 1, 1>(a, nlines, tw);
   else r = fft_stages<N, false, LS, 0, NST - 1, 1>(a, b, nlines, tw);
   float2* o = IP ? r : (r == a ? b : a);
-  const unsigned it = threadIdx.x, total = unsigned(nlines) * NB;  // host bound: total <= blockDim.x
-  const bool act = it < total;
-  const unsigned line = act ? it / NB : 0, jj = it % NB;
-  float2 v[R];
-  if (act) {
-    stage_load<R, NB>(v, r + line * LS, jj);
-    stage_regs<R, NB, OFFL>(v, jj, tw);
+  const unsigned total = unsigned(nlines) * NB;
+  float2 v[MB][R];
+#pragma unroll
+  for (int i = 0; i < MB; ++i) {
+    const unsigned it = threadIdx.x + i * blockDim.x;
+    if (it < total) {
+      const unsigned line = it / NB, jj = it % NB;
+      stage_load<R, NB>(v[i], r + line * LS, jj);
+      stage_regs<R, NB, OFFL>(v[i], jj, tw);
+    }
   }
   if constexpr (IP) __syncthreads();
-  if (act) {
-    // The values pass an LDS store and load in the unfused sequence; the
-    // empty asm statements keep them opaque here too, so no multiply of one
-    // side is contracted with an add of the other (same rounding, same bits).
 #pragma unroll
-    for (int q = 0; q < R; ++q) asm volatile("" : "+v"(v[q].x), "+v"(v[q].y));
-    pw(int(line), int(jj), v);
+  for (int i = 0; i < MB; ++i) {
+    const unsigned it = threadIdx.x + i * blockDim.x;
+    if (it < total) {
+      const unsigned line = it / NB, jj = it % NB;
+      // The values pass an LDS store and load in the unfused sequence; the
+      // empty asm statements keep them opaque here too, so no multiply of
+      // one side is contracted with an add of the other (same rounding).
 #pragma unroll
-    for (int q = 0; q < R; ++q) asm volatile("" : "+v"(v[q].x), "+v"(v[q].y));
-    stage_regs<R, 1, 0>(v, jj, tw);
-    stage_store<R, 1>(v, o + line * LS, jj);
+      for (int q = 0; q < R; ++q) asm volatile("" : "+v"(v[i][q].x), "+v"(v[i][q].y));
+      pw(i, int(line), int(jj), v[i]);
+#pragma unroll
+      for (int q = 0; q < R; ++q) asm volatile("" : "+v"(v[i][q].x), "+v"(v[i][q].y));
+      stage_regs<R, 1, 0>(v[i], jj, tw);
+      stage_store<R, 1>(v[i], o + line * LS, jj);
+    }
   }
   __syncthreads();
   if constexpr (IP) return fft_range_ip<N, LS, 1, NST, R>(o, nlines, tw);
@@ -880,50 +898,52 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
   if constexpr ((BM == RM_F1 || BM == RM_A3) && row_fusable<NF>()) {
     // eq num-vel (RM_F1: v_i = A_i (A_i v_i - dt/rho_i d/dr_i^+ p)) and its
     // transpose (RM_A3) with the update between the two FFTs in registers:
-    // one thread per (row, butterfly jj) of the boundary stage, which holds
-    // the row's values at x = jj + r N/R
-    constexpr int R = plan_radix(NF, 0), NB = NF / R;
+    // butterfly (row j, jj) of the boundary stage holds the row's values at
+    // x = jj + q N/R
+    constexpr int R = plan_radix(NF, 0), NB = NF / R, MB = fused_slots<NF>();
     const bool first = BM == RM_F1 ? (n == 0) : (n == M.nt - 2);  // the state starts at zero
-    float v0x[R], v0y[R], bx[R], by[R], ax[R];
-    float ay = 0.f;
+    float v0x[MB][R], v0y[MB][R], bx[MB][R], by[MB][R], ax[MB][R], ay[MB];
     PairRegs S;
     TwRegs TW;
     fetch_pair<NF>(S, M, W.s0, W.s1, tile);
     if constexpr (!TG) fetch_tw(TW, M.twx, nx);
-    {
-      const unsigned it = min(unsigned(threadIdx.x), unsigned(rt * NB) - 1u);
-      const int j = int(it / NB), jj = int(it % NB), y = y0 + j;
-      const unsigned base = rowoff(y) + jj;
 #pragma unroll
-      for (int q = 0; q < R; ++q) {
-        v0x[q] = W.f0[base + q * NB];
-        v0y[q] = W.f1[base + q * NB];
-        bx[q] = M.bx[base + q * NB];
-        by[q] = M.by[base + q * NB];
-        ax[q] = M.avx[jj + q * NB];
+    for (int i = 0; i < MB; ++i) {
+      if (i * B < rt * NB) {
+        const unsigned it = min(unsigned(threadIdx.x + i * B), unsigned(rt * NB) - 1u);
+        const int j = int(it / NB), jj = int(it % NB), y = y0 + j;
+        const unsigned base = rowoff(y) + jj;
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+          v0x[i][q] = W.f0[base + q * NB];
+          v0y[i][q] = W.f1[base + q * NB];
+          bx[i][q] = M.bx[base + q * NB];
+          by[i][q] = M.by[base + q * NB];
+          ax[i][q] = M.avx[jj + q * NB];
+        }
+        ay[i] = M.avy[y];
       }
-      ay = M.avy[y];
     }
     put_pair<NF>(S, bufA, M);
     if constexpr (!TG) put_tw(TW, twl, nx);
     __syncthreads();
-    auto pw = [&](int j, int jj, float2* v) {
+    auto pw = [&](int i, int j, int jj, float2* v) {
       const unsigned base = rowoff(y0 + j) + jj;
 #pragma unroll
       for (int q = 0; q < R; ++q) {
         const float2 z = v[q];
         if constexpr (BM == RM_F1) {
-          const float vx = ax[q] * (ax[q] * (first ? 0.f : v0x[q]) - bx[q] * z.x);
-          const float vy = ay * (ay * (first ? 0.f : v0y[q]) + by[q] * z.y);
+          const float vx = ax[i][q] * (ax[i][q] * (first ? 0.f : v0x[i][q]) - bx[i][q] * z.x);
+          const float vy = ay[i] * (ay[i] * (first ? 0.f : v0y[i][q]) + by[i][q] * z.y);
           W.f0[base + q * NB] = vx;
           W.f1[base + q * NB] = vy;
           v[q] = make_float2(vx, vy);
         } else {
-          const float vbx = (first ? 0.f : v0x[q]) - z.x;
-          const float vby = (first ? 0.f : v0y[q]) + z.y;
-          W.f0[base + q * NB] = ax[q] * ax[q] * vbx;
-          W.f1[base + q * NB] = ay * ay * vby;
-          v[q] = make_float2(-ax[q] * bx[q] * vbx, -ay * by[q] * vby);
+          const float vbx = (first ? 0.f : v0x[i][q]) - z.x;
+          const float vby = (first ? 0.f : v0y[i][q]) + z.y;
+          W.f0[base + q * NB] = ax[i][q] * ax[i][q] * vbx;
+          W.f1[base + q * NB] = ay[i] * ay[i] * vby;
+          v[q] = make_float2(-ax[i][q] * bx[i][q] * vbx, -ay[i] * by[i][q] * vby);
         }
       }
     };

@@ -63,8 +63,9 @@ constexpr int kMaxN = 1024;
 constexpr int kMinN = 8;
 
 // n = 2^a or 3 * 2^a: radix plan with radices up to `maxr` (8 or 4), 4 bits
-// per stage, first stage lowest; the radix-3 stage comes last so that the
-// sub-transform length before every stage is a power of two.
+// per stage, first stage lowest (the kernels' compile-time plans, plan_radix,
+// are the same); the radix-3 stage comes last so that the sub-transform
+// length before every stage is a power of two.
 bool radix_plan(int n, uint32_t* rad, int* nst, int maxr = 8) {
   if (n < kMinN || n > kMaxN || (n & 1)) return false;
   std::vector<int> r;
@@ -75,10 +76,28 @@ bool radix_plan(int n, uint32_t* rad, int* nst, int maxr = 8) {
   int a = 0;
   while ((1 << a) < m) ++a;
   if (maxr == 8) {
+    // radix 8, the remainder as 4 .. 4 (a = 3q + 1) or a radix-4 second stage
+    // (a = 3q + 2), so that the plan starts and ends with the same radix
     const int q = a / 3, rem = a % 3;
-    if (rem == 1) r.push_back(2);
-    if (rem == 2) r.push_back(4);
-    for (int i = 0; i < q; ++i) r.push_back(8);
+    if (rem == 0) {
+      for (int i = 0; i < q; ++i) r.push_back(8);
+    } else if (rem == 1) {
+      if (q == 0) {
+        r.push_back(2);
+      } else {
+        r.push_back(4);
+        for (int i = 0; i < q - 1; ++i) r.push_back(8);
+        r.push_back(4);
+      }
+    } else {
+      if (q == 0) {
+        r.push_back(4);
+      } else {
+        r.push_back(8);
+        r.push_back(4);
+        for (int i = 0; i < q - 1; ++i) r.push_back(8);
+      }
+    }
   } else {
     const int q = a / 2, rem = a % 2;
     if (rem == 1) r.push_back(2);
