@@ -26,8 +26,11 @@ namespace qpat {
 // ---------------------------------------------------------------- complex
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+// Complex product with its two fused multiply-adds written out: left to the
+// compiler, which product of each part it fuses depends on the surrounding
+// code, so two inlined copies of one FFT stage could round differently.
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
-  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+  return make_float2(__builtin_fmaf(a.x, b.x, -(a.y * b.y)), __builtin_fmaf(a.y, b.x, a.x * b.y));
 }
 __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
 __device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
@@ -67,17 +70,19 @@ template <> __device__ __forceinline__ void bfly<8>(float2* v) {
   float2 o[4] = {v[1], v[3], v[5], v[7]};
   bfly<4>(e);
   bfly<4>(o);
-  const float2 o1 = make_float2(c * (o[1].x + o[1].y), c * (o[1].y - o[1].x));   // W8^1
-  const float2 o2 = mul_mi(o[2]);                                               // W8^2
-  const float2 o3 = make_float2(c * (o[3].y - o[3].x), -c * (o[3].x + o[3].y)); // W8^3
+  // W8^1 o1 = c (s1 + i d1) and W8^3 o3 = c (d3 - i s3), each scaling fused
+  // into the adds and subtracts that use it (written out, as in cmul)
+  const float s1 = o[1].x + o[1].y, d1 = o[1].y - o[1].x;
+  const float s3 = o[3].x + o[3].y, d3 = o[3].y - o[3].x;
+  const float2 o2 = mul_mi(o[2]);  // W8^2
   v[0] = cadd(e[0], o[0]);
   v[4] = csub(e[0], o[0]);
-  v[1] = cadd(e[1], o1);
-  v[5] = csub(e[1], o1);
+  v[1] = make_float2(__builtin_fmaf(c, s1, e[1].x), __builtin_fmaf(c, d1, e[1].y));
+  v[5] = make_float2(__builtin_fmaf(-c, s1, e[1].x), __builtin_fmaf(-c, d1, e[1].y));
   v[2] = cadd(e[2], o2);
   v[6] = csub(e[2], o2);
-  v[3] = cadd(e[3], o3);
-  v[7] = csub(e[3], o3);
+  v[3] = make_float2(__builtin_fmaf(c, d3, e[3].x), __builtin_fmaf(-c, s3, e[3].y));
+  v[7] = make_float2(__builtin_fmaf(-c, d3, e[3].x), __builtin_fmaf(c, s3, e[3].y));
 }
 
 // 24-bit unsigned product (full-rate multiply); every grid and spectrum
@@ -401,6 +406,65 @@ __device__ __forceinline__ float2* fft_fused(float2* a, float2* b, int nlines, c
       for (int q = 0; q < R; ++q) asm volatile("" : "+v"(v[i][q].x), "+v"(v[i][q].y));
       stage_regs<R, 1, 0>(v[i], jj, tw);
       stage_store<R, 1>(v[i], o + line * LS, jj);
+    }
+  }
+  __syncthreads();
+  if constexpr (IP) return fft_range_ip<N, LS, 1, NST, R>(o, nlines, tw);
+  else return fft_stages<N, false, LS, 1, NST, R>(o, r, nlines, tw);
+}
+
+// The same fusion for updates that read two lines and write two lines per
+// position (rows 2l and 2l+1 packed as one complex line on one side of the
+// update, each row its own line on the other): work item (l, jj) runs the
+// last stage on lines inl(l, 0) and inl(l, 1), `pw(i, l, jj, va, vb)` on their
+// values, and the first stage on lines outl(l, 0) and outl(l, 1).
+template <int N>
+__host__ __device__ constexpr int fused2_slots() { return (kMaxPer / 2 + plan_radix(N, 0) - 1) / plan_radix(N, 0); }
+template <int N, bool IP, class IL, class OL, class PW>
+__device__ __forceinline__ float2* fft_fused2(float2* a, float2* b, int nlines, const float2* tw, IL inl, OL outl,
+                                              PW pw) {
+  constexpr int LS = lstride(N), NST = plan_nst(N), R = plan_radix(N, 0), NB = N / R, MB = fused2_slots<N>();
+  constexpr int OFFL = NB - R;
+  float2* r;
+  if constexpr (IP) r = fft_range_ip<N, LS, 0, NST - 1, 1>(a, nlines, tw);
+  else r = fft_stages<N, false, LS, 0, NST - 1, 1>(a, b, nlines, tw);
+  float2* o = IP ? r : (r == a ? b : a);
+  const unsigned total = unsigned(nlines / 2) * NB;
+  float2 va[MB][R], vb[MB][R];
+#pragma unroll
+  for (int i = 0; i < MB; ++i) {
+    const unsigned it = threadIdx.x + i * blockDim.x;
+    if (it < total) {
+      const int l = int(it / NB);
+      const unsigned jj = it % NB;
+      stage_load<R, NB>(va[i], r + inl(l, 0) * LS, jj);
+      stage_regs<R, NB, OFFL>(va[i], jj, tw);
+      stage_load<R, NB>(vb[i], r + inl(l, 1) * LS, jj);
+      stage_regs<R, NB, OFFL>(vb[i], jj, tw);
+    }
+  }
+  if constexpr (IP) __syncthreads();
+#pragma unroll
+  for (int i = 0; i < MB; ++i) {
+    const unsigned it = threadIdx.x + i * blockDim.x;
+    if (it < total) {
+      const int l = int(it / NB);
+      const unsigned jj = it % NB;
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        asm volatile("" : "+v"(va[i][q].x), "+v"(va[i][q].y));
+        asm volatile("" : "+v"(vb[i][q].x), "+v"(vb[i][q].y));
+      }
+      pw(i, l, int(jj), va[i], vb[i]);
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        asm volatile("" : "+v"(va[i][q].x), "+v"(va[i][q].y));
+        asm volatile("" : "+v"(vb[i][q].x), "+v"(vb[i][q].y));
+      }
+      stage_regs<R, 1, 0>(va[i], jj, tw);
+      stage_store<R, 1>(va[i], o + outl(l, 0) * LS, jj);
+      stage_regs<R, 1, 0>(vb[i], jj, tw);
+      stage_store<R, 1>(vb[i], o + outl(l, 1) * LS, jj);
     }
   }
   __syncthreads();
@@ -928,6 +992,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     if constexpr (!TG) put_tw(TW, twl, nx);
     __syncthreads();
     auto pw = [&](int i, int j, int jj, float2* v) {
+#pragma clang fp contract(off)  // the same rounding fused or not (no cross-path contraction choices)
       const unsigned base = rowoff(y0 + j) + jj;
 #pragma unroll
       for (int q = 0; q < R; ++q) {
@@ -989,6 +1054,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     FOR_K {
       const int it = threadIdx.x + k * B;
       if (it < tot) {
+#pragma clang fp contract(off)  // the same rounding fused or not (no cross-path contraction choices)
         const int j = rowdiv(it), x = it - j * nx;
         const unsigned idx = rowoff(y0 + j) + x;
         const float2 z = zr[k];
@@ -1004,6 +1070,69 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     store_pair_spectra<NF>(r, M, W.s0, W.s1, tile);
   } else if constexpr (BM == RM_F2 || BM == RM_F2L) {
     // eq num-rho with the additive source of eq s1 (dt s = p0 / (2 d c^2), d = 2)
+    if constexpr (BM == RM_F2 && row_fusable<NF>() && !TG) {
+      if (n >= 1) {
+        // iterates past the source: the update between the two FFTs in
+        // registers, rows 2l and 2l+1 of each position together (their S and
+        // u values share one complex line each on the output side)
+        constexpr int R = plan_radix(NF, 0), NB = NF / R, MB = fused2_slots<NF>();
+        const int half = rt / 2;
+        float rxa[MB][R], rya[MB][R], r0a[MB][R], rxb[MB][R], ryb[MB][R], r0b[MB][R], ax[MB][R];
+        float aya[MB], ayb[MB];
+        PairRegs S;
+        TwRegs TW;
+        fetch_pair<NF>(S, M, W.s0, W.s1, tile);
+        if constexpr (!TG) fetch_tw(TW, M.twx, nx);
+#pragma unroll
+        for (int i = 0; i < MB; ++i) {
+          if (i * B < half * NB) {
+            const unsigned it = min(unsigned(threadIdx.x + i * B), unsigned(half * NB) - 1u);
+            const int l = int(it / NB), jj = int(it % NB), ya = y0 + 2 * l;
+            const unsigned ba = rowoff(ya) + jj, bb = ba + nx;
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+              rxa[i][q] = W.f2[ba + q * NB];
+              rya[i][q] = W.f3[ba + q * NB];
+              r0a[i][q] = M.rho0[ba + q * NB];
+              rxb[i][q] = W.f2[bb + q * NB];
+              ryb[i][q] = W.f3[bb + q * NB];
+              r0b[i][q] = M.rho0[bb + q * NB];
+              ax[i][q] = M.arx[jj + q * NB];
+            }
+            aya[i] = M.ary[ya];
+            ayb[i] = M.ary[ya + 1];
+          }
+        }
+        put_pair<NF>(S, bufA, M);
+        if constexpr (!TG) put_tw(TW, twl, nx);
+        __syncthreads();
+        auto inl = [&](int l, int sd) { return 2 * l + sd; };
+        auto outl = [&](int l, int sd) { return sd * half + l; };
+        auto pw = [&](int i, int l, int jj, float2* va, float2* vb) {
+#pragma clang fp contract(off)  // the same rounding fused or not (no cross-path contraction choices)
+          const unsigned ba = rowoff(y0 + 2 * l) + jj, bb = ba + nx;
+          const float s = 0.f;
+#pragma unroll
+          for (int q = 0; q < R; ++q) {
+            const float exa = va[q].x, eya = -va[q].y, exb = vb[q].x, eyb = -vb[q].y;
+            const float rxA = ax[i][q] * (ax[i][q] * rxa[i][q] - dt * r0a[i][q] * exa) + s;
+            const float ryA = aya[i] * (aya[i] * rya[i][q] - dt * r0a[i][q] * eya) + s;
+            const float rxB = ax[i][q] * (ax[i][q] * rxb[i][q] - dt * r0b[i][q] * exb) + s;
+            const float ryB = ayb[i] * (ayb[i] * ryb[i][q] - dt * r0b[i][q] * eyb) + s;
+            W.f2[ba + q * NB] = rxA;
+            W.f3[ba + q * NB] = ryA;
+            W.f2[bb + q * NB] = rxB;
+            W.f3[bb + q * NB] = ryB;
+            va[q] = make_float2(rxA + ryA, rxB + ryB);
+            vb[q] = make_float2(r0a[i][q] * (ax[i][q] * exa + aya[i] * eya), r0b[i][q] * (ax[i][q] * exb + ayb[i] * eyb));
+          }
+        };
+        float2* r = fft_fused2<NF, IP>(bufA, bufB, rt, tw, inl, outl, pw);
+        store_rowpair_spectra<NF>(r, M, W.s0, tile);
+        store_rowpair_spectra<NF>(r + half * LS, M, W.s1, tile);
+        return;
+      }
+    }
     const bool skip = (n == -1);  // v^{-1/2} = 0 and rho^{-1} = 0
     const bool inject = (n <= 0);
     float rxo[kMaxPer], ryo[kMaxPer], r0[kMaxPer], ax[kMaxPer], ay[kMaxPer], src[kMaxPer], c2[kMaxPer];
@@ -1061,6 +1190,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     FOR_K {
       const int it = threadIdx.x + k * B;
       if (it < tot) {
+#pragma clang fp contract(off)  // the same rounding fused or not (no cross-path contraction choices)
         const int j = rowdiv(it), x = it - j * nx;
         const unsigned idx = rowoff(y0 + j) + x;
         float ex = 0.f, ey = 0.f;
@@ -1287,6 +1417,70 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
   } else if constexpr (BM == RM_A2) {
     // transpose of the mass update and of the Y terms of eq num-p
     const bool first = (n == M.nt - 2);
+    if constexpr (row_fusable<NF>() && !TG) {
+      if (n >= 1) {
+        // the update between the two FFTs in registers: rows 2l and 2l+1 of
+        // each position together (they share the input lines)
+        constexpr int R = plan_radix(NF, 0), NB = NF / R, MB = fused2_slots<NF>();
+        const int half = rt / 2;
+        float qa[MB][R], xa[MB][R], ya0[MB][R], r0a[MB][R], qb[MB][R], xb[MB][R], yb0[MB][R], r0b[MB][R];
+        float ax[MB][R], aya[MB], ayb[MB];
+        RowPairRegs S0, S1;
+        TwRegs TW;
+        fetch_rowpair<NF>(S0, M, W.s0, tile);
+        fetch_rowpair<NF>(S1, M, W.s1, tile);
+        if constexpr (!TG) fetch_tw(TW, M.twx, nx);
+#pragma unroll
+        for (int i = 0; i < MB; ++i) {
+          if (i * B < half * NB) {
+            const unsigned it = min(unsigned(threadIdx.x + i * B), unsigned(half * NB) - 1u);
+            const int l = int(it / NB), jj = int(it % NB), y = y0 + 2 * l;
+            const unsigned ba = rowoff(y) + jj, bb = ba + nx;
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+              qa[i][q] = W.q[ba + q * NB];
+              xa[i][q] = W.f2[ba + q * NB];
+              ya0[i][q] = W.f3[ba + q * NB];
+              r0a[i][q] = M.rho0[ba + q * NB];
+              qb[i][q] = W.q[bb + q * NB];
+              xb[i][q] = W.f2[bb + q * NB];
+              yb0[i][q] = W.f3[bb + q * NB];
+              r0b[i][q] = M.rho0[bb + q * NB];
+              ax[i][q] = M.arx[jj + q * NB];
+            }
+            aya[i] = M.ary[y];
+            ayb[i] = M.ary[y + 1];
+          }
+        }
+        put_rowpair<NF>(S0, bufA, M);
+        put_rowpair<NF>(S1, bufA + half * LS, M);
+        if constexpr (!TG) put_tw(TW, twl, nx);
+        __syncthreads();
+        auto inl = [&](int l, int sd) { return sd * half + l; };
+        auto outl = [&](int l, int sd) { return 2 * l + sd; };
+        auto pw = [&](int i, int l, int jj, float2* va, float2* vb) {
+#pragma clang fp contract(off)  // the same rounding fused or not (no cross-path contraction choices)
+          const unsigned ba = rowoff(y0 + 2 * l) + jj, bb = ba + nx;
+#pragma unroll
+          for (int q = 0; q < R; ++q) {
+            // rows 2l and 2l+1 of the (conjugated) inverse transforms
+            const float yda = va[q].x, ydb = -va[q].y, yaa = vb[q].x, yab = -vb[q].y;
+            const float sba = qa[i][q] - yda, sbb = qb[i][q] - ydb;
+            const float rbxa = (first ? 0.f : xa[i][q]) + sba, rbya = (first ? 0.f : ya0[i][q]) + sba;
+            const float rbxb = (first ? 0.f : xb[i][q]) + sbb, rbyb = (first ? 0.f : yb0[i][q]) + sbb;
+            va[q] = make_float2(r0a[i][q] * ax[i][q] * (yaa - dt * rbxa), r0a[i][q] * aya[i] * (yaa - dt * rbya));
+            vb[q] = make_float2(r0b[i][q] * ax[i][q] * (yab - dt * rbxb), r0b[i][q] * ayb[i] * (yab - dt * rbyb));
+            W.f2[ba + q * NB] = ax[i][q] * ax[i][q] * rbxa;
+            W.f3[ba + q * NB] = aya[i] * aya[i] * rbya;
+            W.f2[bb + q * NB] = ax[i][q] * ax[i][q] * rbxb;
+            W.f3[bb + q * NB] = ayb[i] * ayb[i] * rbyb;
+          }
+        };
+        float2* r = fft_fused2<NF, IP>(bufA, bufB, rt, tw, inl, outl, pw);
+        store_pair_spectra<NF>(r, M, W.s0, W.s1, tile);
+        return;
+      }
+    }
     float qv[kMaxPer], rbx0[kMaxPer], rby0[kMaxPer], r0[kMaxPer], ax[kMaxPer], ay[kMaxPer];
     float c2[kMaxPer], gacc[kMaxPer];
     RowPairRegs S0, S1;
@@ -1337,6 +1531,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     FOR_K {
       const int it = threadIdx.x + k * B;
       if (it < tot) {
+#pragma clang fp contract(off)  // the same rounding fused or not (no cross-path contraction choices)
         const int j = rowdiv(it), x = it - j * nx;
         const unsigned idx = rowoff(y0 + j) + x;
         const float yd = ydr[k], ya = yar[k];
@@ -1395,6 +1590,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     FOR_K {
       const int it = threadIdx.x + k * B;
       if (it < tot) {
+#pragma clang fp contract(off)  // the same rounding fused or not (no cross-path contraction choices)
         const int j = rowdiv(it), x = it - j * nx;
         const unsigned idx = rowoff(y0 + j) + x;
         const float2 z = zr[k];
