@@ -187,8 +187,8 @@ qpat_status qpat_medium_grad(qpat_plan plan, const float* p0, const float* res, 
 /* Launch shape of the FFT passes: rows per row-pass block, spectrum columns
  * per column-pass block (powers of two dividing ny and nx/2; rows even, and at
  * most ny/8 when ny is a power of two of 128 or more) and
- * threads per block of each pass (64, 128, 256 or 512; rows*nx and cols*ny at
- * most 8 times the threads; a block's LDS within the 160 KB of a gfx950
+ * threads per block of each pass (64, 128, 256 or 512; rows*nx at most 8 and
+ * cols*ny at most 4 times the threads; a block's LDS within the 160 KB of a gfx950
  * work-group).  qpat_tune times the candidates on `stream` for
  * `batch` vectors and keeps the fastest: each candidate runs 16 forward
  * iterates and the 16 adjoint iterates that undo them (every pass kind of a

@@ -549,9 +549,11 @@ struct PairRegs {
 struct RowPairRegs {
   float2 a[kRowPairIt], b[kRowPairIt];
 };
-struct TwRegs {
-  float2 t[kMaxPer];
+template <int K>
+struct TwRegsK {
+  float2 t[K];
 };
+using TwRegs = TwRegsK<kMaxPer>;
 
 // Row length of a row-pass instance: the compile-time length NF when the
 // instance carries one (it is launched only for rows of that length), else
@@ -623,16 +625,18 @@ __device__ __forceinline__ void put_rowpair(const RowPairRegs& R, float2* buf, c
   }
 }
 
-__device__ __forceinline__ void fetch_tw(TwRegs& R, const float2* __restrict__ tw, int n) {
+template <int K>
+__device__ __forceinline__ void fetch_tw(TwRegsK<K>& R, const float2* __restrict__ tw, int n) {
 #pragma unroll
-  for (int k = 0; k < kMaxPer; ++k) {
+  for (int k = 0; k < K; ++k) {
     const int i = threadIdx.x + k * blockDim.x;
     if (i < n) R.t[k] = tw[i];
   }
 }
-__device__ __forceinline__ void put_tw(const TwRegs& R, float2* dst, int n) {
+template <int K>
+__device__ __forceinline__ void put_tw(const TwRegsK<K>& R, float2* dst, int n) {
 #pragma unroll
-  for (int k = 0; k < kMaxPer; ++k) {
+  for (int k = 0; k < K; ++k) {
     const int i = threadIdx.x + k * blockDim.x;
     if (i < n) dst[i] = R.t[k];
   }
@@ -1931,8 +1935,8 @@ __device__ __forceinline__ void col_fused(const Medium& M, const Work& W, int ti
   static_assert(RS == radix_of<N, true>(0) && R1 == radix_of<N, true>(NST - 1), "plan reversal");
   constexpr int OFFS = NBS - R1;  // twiddles of the last forward stage (Ns = NBS)
   constexpr int OFFL = NB1 - RS;  // twiddles of the last inverse stage (Ns = NB1)
-  constexpr int kQ = nin * kMaxPer / R1;          // first-stage butterflies per thread (bound)
-  constexpr int kP = kMaxPer / RS > 0 ? kMaxPer / RS : 1;  // middle butterflies per thread (bound)
+  constexpr int kQ = (nin * kColPer + R1 - 1) / R1;  // first-stage butterflies per thread (bound)
+  constexpr int kP = (kColPer + RS - 1) / RS;         // middle butterflies per thread (bound)
   const int nxh = M.nxh, ct = M.ct, c0 = tile * ct, B = blockDim.x, lct = M.lct, lrt = M.lrt;
   const int tid = threadIdx.x;
   float2* bufA = lds;
@@ -1971,7 +1975,7 @@ __device__ __forceinline__ void col_fused(const Medium& M, const Work& W, int ti
       for (int r = 0; r < R1; ++r) v1[i][r] = src[r * step1];
     }
   }
-  TwRegs TW, TWR;
+  TwRegsK<kColPer> TW, TWR;  // N <= kColPer * B (ct >= 1)
   if constexpr (!TG) {
     fetch_tw(TW, M.twy, N);
     fetch_tw(TWR, M.twyr, N);
@@ -2199,7 +2203,7 @@ __global__ void __launch_bounds__(kBlock) dot_final(const double* __restrict__ p
 // then the all-length instance).  1024-point columns stay on the all-length
 // instance: the dedicated one measured 5-10% slower at 1024^2 x 8.
 #define QPAT_FOR_LENGTHS(X) X(128) X(256) X(384) X(512) X(1024)
-#define QPAT_FOR_COL_LENGTHS(X) X(128) X(256) X(384) X(512)
+#define QPAT_FOR_COL_LENGTHS(X) X(128) X(256) X(384) X(512) X(1024)
 
 template <int MODE>
 static hipError_t launch_row_t(const Launch& L, bool uniform, int len, bool tg, int ntile, int chunk, int nblocks,

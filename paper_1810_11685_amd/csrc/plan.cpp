@@ -146,9 +146,13 @@ bool row_tile_ok(int nx, int ny, int rt, int thr) {
   return rt >= 2 && (rt & (rt - 1)) == 0 && ny % rt == 0 && row_lds_bytes(nx, rt) <= kMaxLds &&
          threads_ok(thr) && rt * nx <= kMaxPer * thr && (!fused_cols || rt <= ny / 8);
 }
+// A column tile of ct spectrum columns fits the LDS limit and leaves at most
+// kColPer elements of each field per thread (a column pass holds its input
+// fields' first-stage values, multipliers and twiddles in registers together;
+// the tighter bound keeps those under 128 VGPRs).
 bool col_tile_ok(int nxh, int ny, int ct, int thr) {
   return ct >= 1 && (ct & (ct - 1)) == 0 && nxh % ct == 0 && col_lds_bytes(ny, ct) <= kMaxLds &&
-         threads_ok(thr) && ct * ny <= kMaxPer * thr;
+         threads_ok(thr) && ct * ny <= kColPer * thr;
 }
 
 // Defaults: small tiles (many blocks) with enough threads to keep every
@@ -1006,7 +1010,7 @@ qpat_status set_tiles(qpat_plan P, int rt, int ct, int rthr, int cthr) {
                                 "the LDS limit");
   if (!col_tile_ok(P->prm.nx / 2, P->prm.ny, ct, cthr))
     return fail(QPAT_E_INVALID, "column tile: columns must be a power of two dividing nx/2, threads "
-                                "64/128/256/512, columns*ny <= 8*threads, within the LDS limit");
+                                "64/128/256/512, columns*ny <= 4*threads, within the LDS limit");
   if (rt != P->rt || ct != P->ct || rthr != P->rthr || cthr != P->cthr) {
     P->rt = P->med.rt = rt;
     P->ct = P->med.ct = ct;

@@ -13,6 +13,7 @@ constexpr int kBlock = 256;   // threads per block of the helper kernels (defaul
 constexpr int kMaxThreads = 512;  // maximum threads per block of a row / column pass
 constexpr size_t kMaxLds = 163840;  // gfx950: LDS bytes available to one work-group
 constexpr int kMaxPer = 8;    // pointwise elements per thread held in registers
+constexpr int kColPer = 4;    // spectrum elements of one field per thread in a column pass
 constexpr int kTapCap = 64;   // sensor taps of one row tile staged in LDS
 constexpr int kXcds = 8;      // MI355X: 8 XCDs, work-groups dispatched round-robin
 
