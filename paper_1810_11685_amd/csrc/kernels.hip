@@ -1713,9 +1713,9 @@ __device__ __forceinline__ void col_generic(const Medium& M, const Work& W, int 
   // memory order: field, tile row ty, element (iy, c) of the rt x ct tile
   const float rny = 1.0f / static_cast<float>(ny);
   const int rc = M.rt * ct;
-  // (a tile holds nin*ct*ny <= nin*kMaxPer*B elements: all loads are issued
+  // (a tile holds nin*ct*ny <= nin*kColPer*B elements: all loads are issued
   // into registers before the first LDS write)
-  constexpr int kIt = nin * kMaxPer;
+  constexpr int kIt = nin * kColPer;
   const unsigned ncol = unsigned(ct) * ny, ntot = nin * ncol;     // elements per field / tile
   const unsigned rowstep = unsigned(nxh) * M.rt, tbase = unsigned(tile) * rc;  // tile row ty at ty * rowstep
   const int lsh = M.lrt + M.lct;
@@ -1729,11 +1729,12 @@ __device__ __forceinline__ void col_generic(const Medium& M, const Work& W, int 
       tv[k] = (f ? W.s1 : W.s0)[mul24(rem >> lsh, rowstep) + tbase + (rem & (rc - 1))];
     }
   }
-  TwRegs TW;
+  TwRegsK<kColPer> TW;  // ny <= kColPer * B
   if constexpr (!TG) fetch_tw(TW, M.twy, ny);
   const int tot = ct * ny;
-  MultPre P[kMaxPer];
-  FOR_K {
+  MultPre P[kColPer];
+#pragma unroll
+  for (int k = 0; k < kColPer; ++k) {
     const int it = threadIdx.x + k * B;
     if (it < tot) {
       const int c = ct == 1 ? 0 : fdiv(it, ny, rny), ky = it - c * ny, kx = c0 + c;
@@ -1764,7 +1765,8 @@ __device__ __forceinline__ void col_generic(const Medium& M, const Work& W, int 
   __syncthreads();
   float2* r = fft_any<true, NF>(bufA, bufB, nin * ct, ny, ls, M.rady, M.nsty, tw);
   float2* o = other(r, bufA, bufB);
-  FOR_K {
+#pragma unroll
+  for (int k = 0; k < kColPer; ++k) {
     const int it = threadIdx.x + k * B;
     if (it < tot) {
       const int c = ct == 1 ? 0 : fdiv(it, ny, rny), ky = it - c * ny;
@@ -2096,7 +2098,14 @@ col_kernel(const Launch L, int ntile, int chunk, int mcode_arg, int n) {
   const Medium& M = medium_of<U>(L, item);
   const Work W = U ? shift_work(L.w0, item * L.wstride) : L.items[item].w;
   if (n > M.nt - 2) return;  // this problem has finished (uneven batches)
-  // fused path: power-of-two lengths whose first-stage stride is a whole number of tile rows
+  // fused path: power-of-two lengths whose first-stage stride is a whole number
+  // of tile rows.  An instance with a compile-time power-of-two length takes it
+  // unconditionally: a row tile of a power-of-two grid of 128+ rows has at most
+  // ny / 8 rows (a power of two), and N / R1 >= N / 8, so the condition holds;
+  // the generic pass is not compiled into such instances.
+  if constexpr (NF == 128 || NF == 256 || NF == 512 || NF == 1024) {
+    col_fused<CM, NF, TG>(M, W, tile, mcode, lds);
+  } else {
 #define QPAT_COL_CASE(N)                                                 \
   case N:                                                                \
     if ((N / radix_of<N, false>(0)) % M.rt == 0) {                       \
@@ -2104,22 +2113,18 @@ col_kernel(const Launch L, int ntile, int chunk, int mcode_arg, int n) {
       return;                                                            \
     }                                                                    \
     break;
-  if constexpr (NF == 128 || NF == 256 || NF == 512 || NF == 1024) {
-    switch (M.ny) {
-      QPAT_COL_CASE(NF)
-      default: break;
+    if constexpr (NF == 0) {
+      switch (M.ny) {
+        QPAT_COL_CASE(128)
+        QPAT_COL_CASE(256)
+        QPAT_COL_CASE(512)
+        QPAT_COL_CASE(1024)
+        default: break;
+      }
     }
-  } else if constexpr (NF == 0) {
-    switch (M.ny) {
-      QPAT_COL_CASE(128)
-      QPAT_COL_CASE(256)
-      QPAT_COL_CASE(512)
-      QPAT_COL_CASE(1024)
-      default: break;
-    }
-  }
 #undef QPAT_COL_CASE
-  col_generic<CM, NF, TG>(M, W, tile, mcode, lds);
+    col_generic<CM, NF, TG>(M, W, tile, mcode, lds);
+  }
 }
 
 // ---------------------------------------------------------------- sensor data
