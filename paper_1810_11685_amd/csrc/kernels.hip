@@ -319,13 +319,14 @@ __device__ __forceinline__ float2* fft_stages(float2* a, float2* b, int nlines, 
   }
 }
 
-// Stages S .. S1-1 of the forward plan of length N in place (see fft_c_ip).
-template <int N, int LS, int S, int S1, int NS>
+// Stages S .. S1-1 of the plan of length N (REV: the plan in reverse order)
+// in place (see fft_c_ip).
+template <int N, int LS, int S, int S1, int NS, bool REV = false>
 __device__ __forceinline__ float2* fft_range_ip(float2* a, int nlines, const float2* tw) {
   if constexpr (S == S1) {
     return a;
   } else {
-    constexpr int R = plan_radix(N, S), NB = N / R, OFF = NS - plan_radix(N, 0);
+    constexpr int R = radix_of<N, REV>(S), NB = N / R, OFF = NS - radix_of<N, REV>(0);
     constexpr int MB = (kMaxPer + R - 1) / R;
     const unsigned total = unsigned(nlines) * NB;
     float2 v[MB][R];
@@ -348,7 +349,7 @@ __device__ __forceinline__ float2* fft_range_ip(float2* a, int nlines, const flo
       }
     }
     __syncthreads();
-    return fft_range_ip<N, LS, S + 1, S1, NS * R>(a, nlines, tw);
+    return fft_range_ip<N, LS, S + 1, S1, NS * R, REV>(a, nlines, tw);
   }
 }
 
@@ -1846,6 +1847,42 @@ __device__ __forceinline__ float2 mult_apply(int code, float a, float b, float2 
   }
 }
 
+// Conjugated products of the packed DC / Nyquist column at row ky: z[f] is
+// field f's forward spectrum there, zm[f] the conjugate at the mirror row
+// ny - ky; the two real columns are separated, multiplied with their own
+// tables (a, b at kx = 0; an, bn at the Nyquist column) and packed again.
+template <int CM>
+__device__ __forceinline__ void packed_products(int mcode, float a, float b, float an, float bn, float2 sx,
+                                                float2 sxn, float2 sy, const float2* z, const float2* zm,
+                                                float2* g) {
+  constexpr int nin = kColIn[CM], nout = kColOut[CM];
+  float2 f0[2], fn[2];
+#pragma unroll
+  for (int f = 0; f < 2; ++f) {
+    if (f < nin) {
+      f0[f] = cscale(cadd(z[f], zm[f]), 0.5f);
+      fn[f] = mul_mi(cscale(csub(z[f], zm[f]), 0.5f));
+    } else {
+      f0[f] = fn[f] = make_float2(0.f, 0.f);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    if (q < nout) {
+      float2 g0 = make_float2(0.f, 0.f), gn = make_float2(0.f, 0.f);
+#pragma unroll
+      for (int f = 0; f < 2; ++f) {
+        const int code = (mcode >> (4 * (2 * q + f))) & 15;
+        if (code) {
+          g0 = cadd(g0, mult_apply(code, a, b, sx, sy, f0[f]));
+          gn = cadd(gn, mult_apply(code, an, bn, sxn, sy, fn[f]));
+        }
+      }
+      g[q] = cconj(make_float2(g0.x - gn.y, g0.y + gn.x));
+    }
+  }
+}
+
 // Multiply phase through LDS for the first `ncols` columns of the tile
 // (including the packed DC / Nyquist column, whose two real columns are
 // separated with the mirror element ny - ky): r holds the forward spectra, o
@@ -1877,32 +1914,16 @@ __device__ __forceinline__ void col_mult_lds(const Medium& M, int tile, int mcod
       const float an = tabA[tn], bn = labs ? M.labs[tn] : 0.f;
       const float2 sxn = xcode ? symx[nxh] : make_float2(0.f, 0.f);
       const int km = ky ? ny - ky : 0;
-      float2 f0[2], fn[2];
+      float2 z[2], zm[2], g[2];
 #pragma unroll
       for (int f = 0; f < 2; ++f) {
-        if (f < nin) {
-          const float2 z = r[mul24(f * ct + c, ls) + px(ky)], zm = cconj(r[mul24(f * ct + c, ls) + px(km)]);
-          f0[f] = cscale(cadd(z, zm), 0.5f);
-          fn[f] = mul_mi(cscale(csub(z, zm), 0.5f));
-        } else {
-          f0[f] = fn[f] = make_float2(0.f, 0.f);
-        }
+        z[f] = f < nin ? r[mul24(f * ct + c, ls) + px(ky)] : make_float2(0.f, 0.f);
+        zm[f] = f < nin ? cconj(r[mul24(f * ct + c, ls) + px(km)]) : make_float2(0.f, 0.f);
       }
+      packed_products<CM>(mcode, a, b, an, bn, sx, sxn, sy, z, zm, g);
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        if (q < nout) {
-          float2 g0 = make_float2(0.f, 0.f), gn = make_float2(0.f, 0.f);
-#pragma unroll
-          for (int f = 0; f < 2; ++f) {
-            const int code = (mcode >> (4 * (2 * q + f))) & 15;
-            if (code) {
-              g0 = cadd(g0, mult_apply(code, a, b, sx, sy, f0[f]));
-              gn = cadd(gn, mult_apply(code, an, bn, sxn, sy, fn[f]));
-            }
-          }
-          o[mul24(q * ct + c, ls) + px(ky)] = cconj(make_float2(g0.x - gn.y, g0.y + gn.x));
-        }
-      }
+      for (int q = 0; q < 2; ++q)
+        if (q < nout) o[mul24(q * ct + c, ls) + px(ky)] = g[q];
     } else {
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
@@ -1920,6 +1941,85 @@ __device__ __forceinline__ void col_mult_lds(const Medium& M, int tile, int mcod
   }
 }
 
+// The multiply phase of the packed column (column 0 of tile 0) in place: lines
+// f ct hold the forward spectra, lines q ct receive the conjugated products.
+// Every thread reads its rows and their mirrors before any is overwritten.
+template <int CM>
+__device__ __forceinline__ void col_mult_packed_ip(const Medium& M, int mcode, int ls, float2* a) {
+  constexpr int nin = kColIn[CM], nout = kColOut[CM];
+  const int ny = M.ny, nxh = M.nxh, ct = M.ct, B = blockDim.x, tid = threadIdx.x;
+  int xcode = 0, ycode = 0;
+  bool frac = false, labs = false;
+  for (int e = 0; e < 4; ++e) {
+    const int c = (mcode >> (4 * e)) & 15;
+    if (c == MC_DXP || c == MC_DXM) xcode = c;
+    if (c == MC_DYP || c == MC_DYM) ycode = c;
+    if (c == MC_LDIS) frac = true;
+    if (c == MC_LABS) { frac = true; labs = true; }
+  }
+  const float* tabA = frac ? M.ldis : M.kap;
+  const float2* symx = xcode == MC_DXP ? M.dxp : M.dxm;
+  const float2* symy = ycode == MC_DYP ? M.dyp : M.dym;
+  float2 z[kColPer][2], zm[kColPer][2];  // ny <= kColPer * B
+#pragma unroll
+  for (int k = 0; k < kColPer; ++k) {
+    const int ky = tid + k * B;
+    if (ky < ny) {
+      const int km = ky ? ny - ky : 0;
+#pragma unroll
+      for (int f = 0; f < 2; ++f) {
+        z[k][f] = f < nin ? a[mul24(f * ct, ls) + px(ky)] : make_float2(0.f, 0.f);
+        zm[k][f] = f < nin ? cconj(a[mul24(f * ct, ls) + px(km)]) : make_float2(0.f, 0.f);
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kColPer; ++k) {
+    const int ky = tid + k * B;
+    if (ky < ny) {
+      const unsigned tn = mul24(nxh, ny) + ky;   // tables are [kx][ky]; kx = 0 here
+      const float va = tabA[ky], vb = labs ? M.labs[ky] : 0.f;
+      const float an = tabA[tn], bn = labs ? M.labs[tn] : 0.f;
+      const float2 sx = xcode ? symx[0] : make_float2(0.f, 0.f), sxn = xcode ? symx[nxh] : make_float2(0.f, 0.f);
+      const float2 sy = ycode ? symy[ky] : make_float2(0.f, 0.f);
+      float2 g[2];
+      packed_products<CM>(mcode, va, vb, an, bn, sx, sxn, sy, z[k], zm[k], g);
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+        if (q < nout) a[mul24(q * ct, ls) + px(ky)] = g[q];
+    }
+  }
+}
+
+// One Stockham stage in place on `nlines` lines a + l lstep (at most two
+// lines of N <= kColPer B points): all butterflies are read and transformed
+// in registers, then the block synchronises and writes them back.
+template <int R, int NS, int NB, int OFF>
+__device__ __forceinline__ void stage_ip(float2* a, int nlines, int lstep, const float2* tw) {
+  constexpr int MB = (2 * kColPer + R - 1) / R;
+  const unsigned total = unsigned(nlines) * NB;
+  float2 v[MB][R];
+#pragma unroll
+  for (int i = 0; i < MB; ++i) {
+    const unsigned it = threadIdx.x + i * blockDim.x;
+    if (it < total) {
+      const unsigned line = it / NB, j = it % NB;
+      stage_load<R, NB>(v[i], a + line * lstep, j);
+      stage_regs<R, NS, OFF>(v[i], j, tw);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < MB; ++i) {
+    const unsigned it = threadIdx.x + i * blockDim.x;
+    if (it < total) {
+      const unsigned line = it / NB, j = it % NB;
+      stage_store<R, NS>(v[i], a + line * lstep, j);
+    }
+  }
+}
+
 // Column pass for power-of-two line lengths N with a compile-time plan.  The
 // forward transform's first stage is computed straight from the global loads
 // and the inverse transform (the same plan in reverse order, so that its
@@ -1928,7 +2028,10 @@ __device__ __forceinline__ void col_mult_lds(const Medium& M, int tile, int mcod
 // transform's last stage, the multipliers and the inverse transform's first
 // stage stay in registers.  The tile with the packed DC / Nyquist column
 // (tile 0) takes its multiply phase through LDS.
-template <int CM, int N, bool TG>
+// IP: the FFT stages run in place in one LDS line buffer (each exchange
+// stage gathers its butterflies into registers, synchronises, scatters), which
+// halves the block's LDS and lets more blocks share a CU.
+template <int CM, int N, bool TG, bool IP = false>
 __device__ __forceinline__ void col_fused(const Medium& M, const Work& W, int tile, int mcode, float2* lds) {
   constexpr int nin = kColIn[CM], nout = kColOut[CM];
   constexpr int NST = plan_nst(N), LS = col_lstride(N);
@@ -1942,8 +2045,8 @@ __device__ __forceinline__ void col_fused(const Medium& M, const Work& W, int ti
   const int nxh = M.nxh, ct = M.ct, c0 = tile * ct, B = blockDim.x, lct = M.lct, lrt = M.lrt;
   const int tid = threadIdx.x;
   float2* bufA = lds;
-  float2* bufB = lds + 2 * ct * LS;
-  float2* const twl = lds + 4 * ct * LS;  // LDS copies: forward-plan twiddles, then reversed-plan ones
+  float2* bufB = IP ? lds : lds + 2 * ct * LS;
+  float2* const twl = lds + (IP ? 2 : 4) * ct * LS;  // LDS copies: forward-plan twiddles, then reversed-plan ones
   const float2* const tw = TG ? static_cast<const float2*>(M.twy) : twl;
   const float2* const twr = TG ? static_cast<const float2*>(M.twyr) : twl + N;
   int xcode = 0, ycode = 0;
@@ -2017,32 +2120,46 @@ __device__ __forceinline__ void col_fused(const Medium& M, const Work& W, int ti
   }
   __syncthreads();
   // ---- forward stages 2 .. NST-1
-  float2* r = fft_stages<N, false, LS, 1, NST - 1, R1>(bufA, bufB, nin * ct, tw);
-  float2* o = other(r, bufA, bufB);
+  float2* r;
+  if constexpr (IP) r = fft_range_ip<N, LS, 1, NST - 1, R1>(bufA, nin * ct, tw);
+  else r = fft_stages<N, false, LS, 1, NST - 1, R1>(bufA, bufB, nin * ct, tw);
+  float2* o = IP ? r : other(r, bufA, bufB);
   // column 0 of tile 0 holds the packed DC / Nyquist column: its last forward
   // stage goes to LDS (into its own lines of o) for the mirror-element
   // multiply; every other column stays in registers.  A column takes the
   // same path whatever the tile shape, so results do not depend on it.
   const bool packed = c0 == 0;
   if (packed) {
-    for (unsigned it = tid; it < unsigned(nin) * NBS; it += B) {
-      const unsigned f = it / NBS, j = it % NBS;
-      stockham_c<RS, NBS, NBS, OFFS>(r + f * ct * LS, o + f * ct * LS, j, tw);
+    if constexpr (IP) {
+      stage_ip<RS, NBS, NBS, OFFS>(r, nin, ct * LS, tw);  // lines f ct; the loop below reads other lines
+    } else {
+      for (unsigned it = tid; it < unsigned(nin) * NBS; it += B) {
+        const unsigned f = it / NBS, j = it % NBS;
+        stockham_c<RS, NBS, NBS, OFFS>(r + f * ct * LS, o + f * ct * LS, j, tw);
+      }
     }
   }
   {
     // last forward stage, multipliers, first inverse stage: registers only
+    float2 z[kP][nin][RS];
 #pragma unroll
     for (int i = 0; i < kP; ++i) {
       const unsigned pp = tid + i * B;
       if (pp < np && !(packed && pp < NBS)) {
         const unsigned c = pp / NBS, j = pp % NBS;
-        float2 z[nin][RS];
 #pragma unroll
         for (int f = 0; f < nin; ++f) {
-          stage_load<RS, NBS>(z[f], r + (f * ct + c) * LS, j);
-          stage_regs<RS, NBS, OFFS>(z[f], j, tw);
+          stage_load<RS, NBS>(z[i][f], r + (f * ct + c) * LS, j);
+          stage_regs<RS, NBS, OFFS>(z[i][f], j, tw);
         }
+      }
+    }
+    if constexpr (IP) __syncthreads();  // the stores below overwrite lines just read
+#pragma unroll
+    for (int i = 0; i < kP; ++i) {
+      const unsigned pp = tid + i * B;
+      if (pp < np && !(packed && pp < NBS)) {
+        const unsigned c = pp / NBS, j = pp % NBS;
 #pragma unroll
         for (int q = 0; q < nout; ++q) {
           float2 w[RS];
@@ -2052,7 +2169,7 @@ __device__ __forceinline__ void col_fused(const Medium& M, const Work& W, int ti
 #pragma unroll
             for (int f = 0; f < nin; ++f) {
               const int code = (mcode >> (4 * (2 * q + f))) & 15;
-              if (code) acc = cadd(acc, mult_apply(code, ma[i][rr], mb[i][rr], msx[i], msy[i][rr], z[f][rr]));
+              if (code) acc = cadd(acc, mult_apply(code, ma[i][rr], mb[i][rr], msx[i], msy[i][rr], z[i][f][rr]));
             }
             w[rr] = cconj(acc);
           }
@@ -2064,17 +2181,26 @@ __device__ __forceinline__ void col_fused(const Medium& M, const Work& W, int ti
     __syncthreads();
   }
   if (packed) {
-    // column 0 lines: o (f ct) -> products r (q ct) -> first inverse stage o (q ct)
-    col_mult_lds<CM>(M, tile, mcode, LS, 1, o, r);
-    __syncthreads();
-    for (unsigned it = tid; it < unsigned(nout) * NBS; it += B) {
-      const unsigned q = it / NBS, j = it % NBS;
-      stockham_c<RS, 1, NBS, 1 - RS>(r + q * ct * LS, o + q * ct * LS, j, twr);
+    if constexpr (IP) {
+      // column 0 lines, in place: products (q ct), then the first inverse stage
+      col_mult_packed_ip<CM>(M, mcode, LS, o);
+      __syncthreads();
+      stage_ip<RS, 1, NBS, 1 - RS>(o, nout, ct * LS, twr);
+    } else {
+      // column 0 lines: o (f ct) -> products r (q ct) -> first inverse stage o (q ct)
+      col_mult_lds<CM>(M, tile, mcode, LS, 1, o, r);
+      __syncthreads();
+      for (unsigned it = tid; it < unsigned(nout) * NBS; it += B) {
+        const unsigned q = it / NBS, j = it % NBS;
+        stockham_c<RS, 1, NBS, 1 - RS>(r + q * ct * LS, o + q * ct * LS, j, twr);
+      }
     }
     __syncthreads();
   }
   // ---- inverse stages 2 .. NST-1, then the last one straight to global memory
-  float2* r2 = fft_stages<N, true, LS, 1, NST - 1, RS>(o, other(o, bufA, bufB), nout * ct, twr);
+  float2* r2;
+  if constexpr (IP) r2 = fft_range_ip<N, LS, 1, NST - 1, RS, true>(o, nout * ct, twr);
+  else r2 = fft_stages<N, true, LS, 1, NST - 1, RS>(o, other(o, bufA, bufB), nout * ct, twr);
   const unsigned nq2 = unsigned(nout * ct) * NB1;
   for (unsigned q = tid; q < nq2; q += B) {
     const unsigned l = q / NB1, j = q % NB1, f = l >> lct, c = l & (ct - 1);
@@ -2104,7 +2230,7 @@ col_kernel(const Launch L, int ntile, int chunk, int mcode_arg, int n) {
   // ny / 8 rows (a power of two), and N / R1 >= N / 8, so the condition holds;
   // the generic pass is not compiled into such instances.
   if constexpr (NF == 128 || NF == 256 || NF == 512 || NF == 1024) {
-    col_fused<CM, NF, TG>(M, W, tile, mcode, lds);
+    col_fused<CM, NF, TG, !TG>(M, W, tile, mcode, lds);  // in place unless twiddles are read from global memory
   } else {
 #define QPAT_COL_CASE(N)                                                 \
   case N:                                                                \

@@ -137,6 +137,10 @@ int ilog2(int v) {
 
 bool threads_ok(int t) { return t == 64 || t == 128 || t == 256 || t == 512; }
 
+// Column launches at these lengths take an instance whose FFT stages run in
+// place (a compile-time power-of-two plan).
+bool col_in_place(int ny) { return kernels_have_length(ny, true) && (ny & (ny - 1)) == 0; }
+
 // A row tile of rt rows (rt even, dividing ny) fits the LDS limit and leaves
 // at most kMaxPer pointwise elements per thread.
 bool row_tile_ok(int nx, int ny, int rt, int thr) {
@@ -310,15 +314,21 @@ qpat_status exec_build(Exec& E, const std::vector<Item>& items) {
       cus = 0;
     E.row_tg = u && cus > 0 && kernels_have_length(m0.nx, false) && ni * E.row_ntile <= 2 * cus;
     E.col_tg = u && cus > 0 && kernels_have_length(m0.ny, true) && ni * E.col_ntile <= 2 * cus;
-    // row instances with a compile-time length run in place unless they read
-    // global twiddles (one LDS line buffer instead of two)
+    // row instances with a compile-time length, and column instances with a
+    // compile-time power-of-two length, run in place unless they read global
+    // twiddles (one LDS line buffer instead of two)
     if (u) E.row_lds = row_lds_bytes(m0.nx, m0.rt, E.row_tg, kernels_have_length(m0.nx, false) && !E.row_tg);
-    if (E.col_tg) E.col_lds = col_lds_bytes(m0.ny, m0.ct, true);
+    if (u) E.col_lds = col_lds_bytes(m0.ny, m0.ct, E.col_tg, col_in_place(m0.ny) && !E.col_tg);
   }
   if (!E.uniform && E.tab_nx && kernels_have_length(E.tab_nx, false)) {
     E.row_lds = 0;
     for (int i = 0; i < ni; ++i)
       E.row_lds = std::max(E.row_lds, row_lds_bytes(items[i].m.nx, items[i].m.rt, false, true));
+  }
+  if (!E.uniform && E.tab_ny && col_in_place(E.tab_ny)) {
+    E.col_lds = 0;
+    for (int i = 0; i < ni; ++i)
+      E.col_lds = std::max(E.col_lds, col_lds_bytes(items[i].m.ny, items[i].m.ct, false, true));
   }
   HIPCHK(hipMalloc(&E.d_items, sizeof(Item) * ni));
   HIPCHK(hipMalloc(&E.d_io, sizeof(IO) * ni));

@@ -176,15 +176,15 @@ __host__ __device__ constexpr int lstride(int n) { return n + (n >> 3); }
 __host__ __device__ constexpr int col_lstride(int ny) { return lstride(ny) + 1; }
 
 // LDS bytes of one block of each pass: ping-pong line buffers (one buffer
-// for rows transformed in place, ip), the twiddle tables unless they are read
+// for lines transformed in place, ip), the twiddle tables unless they are read
 // from global memory (tg; columns: the plan and its reverse), and (rows) the
 // staged sensor taps.
 inline size_t row_lds_bytes(int nx, int rt, bool tg = false, bool ip = false) {
   return size_t((ip ? 1 : 2) * rt * lstride(nx) + (tg ? 0 : nx)) * sizeof(float2) +
          kTapCap * (sizeof(Tap) + sizeof(float));
 }
-inline size_t col_lds_bytes(int ny, int ct, bool tg = false) {
-  return (size_t(2) * 2 * ct * col_lstride(ny) + (tg ? 0 : 2 * size_t(ny))) * sizeof(float2);
+inline size_t col_lds_bytes(int ny, int ct, bool tg = false, bool ip = false) {
+  return (size_t(ip ? 1 : 2) * 2 * ct * col_lstride(ny) + (tg ? 0 : 2 * size_t(ny))) * sizeof(float2);
 }
 
 }  // namespace qpat
