@@ -449,7 +449,11 @@ def main():
     if not args.no_recon:
         nq, its = 4, 10
         p0s = T(np.stack([qi.blobs(ny, nx, 1900 + j, count=5, radius_cells=0.2 * 220) for j in range(nq)]))
+        tiles_step = plan.tiles()
         with torch.cuda.stream(stream):
+            if not args.no_tune:
+                plan.tune(nq, stream=stream)      # the driver's calls carry nq vectors each
+            tiles_recon = plan.tiles()
             datas = plan.forward(p0s)
             v = torch.zeros_like(p0s)
             plan.jtjv(v)                          # warm-up of the batched graph
@@ -474,8 +478,9 @@ def main():
                         "jtjv_batched_seconds": round(t_h, 4),
                         "jtjv_fraction": round(its * t_h / t_r, 3), "mgamma_solver_iterations": solves,
                         "misfit_reduction": [round(h[-1] / h[0], 6) for h in hist],
-                        "rel_error_vs_p0": [round(e, 4) for e in rel_err]}
+                        "rel_error_vs_p0": [round(e, 4) for e in rel_err], "tiles": list(tiles_recon)}
         del p0s, datas, v, x
+        plan.set_tiles(*tiles_step)
         torch.cuda.empty_cache()
 
     # ------------------------------------------------------------ sound-speed gradient

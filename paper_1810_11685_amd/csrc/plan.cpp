@@ -1453,6 +1453,11 @@ qpat_status qpat_tune(qpat_plan P, int32_t batch, qpat_stream stream) {
   hipStream_t st = (hipStream_t)stream;
   const int steps = 16;
   int brt = P->rt, bct = P->ct, brh = P->rthr, bch = P->cthr;
+  struct Cand {
+    float ms;
+    int rt, ct, rh, ch;
+  };
+  std::vector<Cand> seen;
   float best = INFINITY;
   // row shapes first (column shape fixed), then column shapes with the best row shape
   for (int r = 2; r <= 32; r *= 2)
@@ -1461,6 +1466,7 @@ qpat_status qpat_tune(qpat_plan P, int32_t batch, qpat_stream stream) {
       STCHK(set_tiles(P, r, bct, h, bch));
       float ms;
       STCHK(time_pair(P, batch, steps, st, &ms));
+      seen.push_back({ms, r, bct, h, bch});
       if (ms < best) {
         best = ms;
         brt = r;
@@ -1474,12 +1480,36 @@ qpat_status qpat_tune(qpat_plan P, int32_t batch, qpat_stream stream) {
       STCHK(set_tiles(P, brt, c, brh, h));
       float ms;
       STCHK(time_pair(P, batch, steps, st, &ms));
+      seen.push_back({ms, brt, c, brh, h});
       if (ms < best) {
         best = ms;
         bct = c;
         bch = h;
       }
     }
+  // the sweeps' short runs separate shapes only to a few percent: the three
+  // fastest distinct shapes are timed again over three times the iterates
+  std::sort(seen.begin(), seen.end(), [](const Cand& a, const Cand& b) { return a.ms < b.ms; });
+  std::vector<Cand> top;
+  for (const Cand& c : seen) {
+    bool dup = false;
+    for (const Cand& t : top) dup = dup || (t.rt == c.rt && t.ct == c.ct && t.rh == c.rh && t.ch == c.ch);
+    if (!dup) top.push_back(c);
+    if (top.size() == 3) break;
+  }
+  best = INFINITY;
+  for (const Cand& c : top) {
+    STCHK(set_tiles(P, c.rt, c.ct, c.rh, c.ch));
+    float ms;
+    STCHK(time_pair(P, batch, 3 * steps, st, &ms));
+    if (ms < best) {
+      best = ms;
+      brt = c.rt;
+      bct = c.ct;
+      brh = c.rh;
+      bch = c.ch;
+    }
+  }
   STCHK(set_tiles(P, brt, bct, brh, bch));
   tune_store(key, brt, bct, brh, bch);
   return QPAT_OK;
