@@ -923,7 +923,8 @@ __device__ __forceinline__ void col_args_batch(const Launch& L, int ntile, int c
 template <int MODE, bool U, int NF, bool TG = false>
 __global__ void __launch_bounds__(kMaxThreads)
 row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
-  constexpr int BM = MODE & ~RM_X;
+  constexpr int BM = MODE & ~(RM_X | RM_FZ);
+  constexpr bool FZ = (MODE & RM_FZ) != 0;
   constexpr bool XS = (MODE & RM_X) != 0;
   extern __shared__ float2 lds[];
   if constexpr (U) row_args_batch<BM>(L, ntile, chunk, n, flags);
@@ -1073,71 +1074,135 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     __syncthreads();
     r = fft_any<false, NF, IP>(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
     store_pair_spectra<NF>(r, M, W.s0, W.s1, tile);
-  } else if constexpr (BM == RM_F2 || BM == RM_F2L) {
-    // eq num-rho with the additive source of eq s1 (dt s = p0 / (2 d c^2), d = 2)
+  } else if constexpr (FZ) {
+    // RM_FZ instances of the lossy density passes (forward eq num-rho and its
+    // transpose) at iterates n >= 1, past the source and the zero initial
+    // state: only the fused path is compiled, so the first iterates' code does
+    // not set these kernels' register count.  The host launches them only for
+    // compile-time lengths whose plan fuses and twiddles staged in LDS.
     if constexpr (BM == RM_F2 && row_fusable<NF>() && !TG) {
-      if (n >= 1) {
-        // iterates past the source: the update between the two FFTs in
-        // registers, rows 2l and 2l+1 of each position together (their S and
-        // u values share one complex line each on the output side)
-        constexpr int R = plan_radix(NF, 0), NB = NF / R, MB = fused2_slots<NF>();
-        const int half = rt / 2;
-        float rxa[MB][R], rya[MB][R], r0a[MB][R], rxb[MB][R], ryb[MB][R], r0b[MB][R], ax[MB][R];
-        float aya[MB], ayb[MB];
-        PairRegs S;
-        TwRegs TW;
-        fetch_pair<NF>(S, M, W.s0, W.s1, tile);
-        if constexpr (!TG) fetch_tw(TW, M.twx, nx);
+      // iterates past the source: the update between the two FFTs in
+      // registers, rows 2l and 2l+1 of each position together (their S and
+      // u values share one complex line each on the output side)
+      constexpr int R = plan_radix(NF, 0), NB = NF / R, MB = fused2_slots<NF>();
+      const int half = rt / 2;
+      float rxa[MB][R], rya[MB][R], r0a[MB][R], rxb[MB][R], ryb[MB][R], r0b[MB][R], ax[MB][R];
+      float aya[MB], ayb[MB];
+      PairRegs S;
+      TwRegs TW;
+      fetch_pair<NF>(S, M, W.s0, W.s1, tile);
+      if constexpr (!TG) fetch_tw(TW, M.twx, nx);
 #pragma unroll
-        for (int i = 0; i < MB; ++i) {
-          if (i * B < half * NB) {
-            const unsigned it = min(unsigned(threadIdx.x + i * B), unsigned(half * NB) - 1u);
-            const int l = int(it / NB), jj = int(it % NB), ya = y0 + 2 * l;
-            const unsigned ba = rowoff(ya) + jj, bb = ba + nx;
-#pragma unroll
-            for (int q = 0; q < R; ++q) {
-              rxa[i][q] = W.f2[ba + q * NB];
-              rya[i][q] = W.f3[ba + q * NB];
-              r0a[i][q] = M.rho0[ba + q * NB];
-              rxb[i][q] = W.f2[bb + q * NB];
-              ryb[i][q] = W.f3[bb + q * NB];
-              r0b[i][q] = M.rho0[bb + q * NB];
-              ax[i][q] = M.arx[jj + q * NB];
-            }
-            aya[i] = M.ary[ya];
-            ayb[i] = M.ary[ya + 1];
-          }
-        }
-        put_pair<NF>(S, bufA, M);
-        if constexpr (!TG) put_tw(TW, twl, nx);
-        __syncthreads();
-        auto inl = [&](int l, int sd) { return 2 * l + sd; };
-        auto outl = [&](int l, int sd) { return sd * half + l; };
-        auto pw = [&](int i, int l, int jj, float2* va, float2* vb) {
-#pragma clang fp contract(off)  // the same rounding fused or not (no cross-path contraction choices)
-          const unsigned ba = rowoff(y0 + 2 * l) + jj, bb = ba + nx;
-          const float s = 0.f;
+      for (int i = 0; i < MB; ++i) {
+        if (i * B < half * NB) {
+          const unsigned it = min(unsigned(threadIdx.x + i * B), unsigned(half * NB) - 1u);
+          const int l = int(it / NB), jj = int(it % NB), ya = y0 + 2 * l;
+          const unsigned ba = rowoff(ya) + jj, bb = ba + nx;
 #pragma unroll
           for (int q = 0; q < R; ++q) {
-            const float exa = va[q].x, eya = -va[q].y, exb = vb[q].x, eyb = -vb[q].y;
-            const float rxA = ax[i][q] * (ax[i][q] * rxa[i][q] - dt * r0a[i][q] * exa) + s;
-            const float ryA = aya[i] * (aya[i] * rya[i][q] - dt * r0a[i][q] * eya) + s;
-            const float rxB = ax[i][q] * (ax[i][q] * rxb[i][q] - dt * r0b[i][q] * exb) + s;
-            const float ryB = ayb[i] * (ayb[i] * ryb[i][q] - dt * r0b[i][q] * eyb) + s;
-            W.f2[ba + q * NB] = rxA;
-            W.f3[ba + q * NB] = ryA;
-            W.f2[bb + q * NB] = rxB;
-            W.f3[bb + q * NB] = ryB;
-            va[q] = make_float2(rxA + ryA, rxB + ryB);
-            vb[q] = make_float2(r0a[i][q] * (ax[i][q] * exa + aya[i] * eya), r0b[i][q] * (ax[i][q] * exb + ayb[i] * eyb));
+            rxa[i][q] = W.f2[ba + q * NB];
+            rya[i][q] = W.f3[ba + q * NB];
+            r0a[i][q] = M.rho0[ba + q * NB];
+            rxb[i][q] = W.f2[bb + q * NB];
+            ryb[i][q] = W.f3[bb + q * NB];
+            r0b[i][q] = M.rho0[bb + q * NB];
+            ax[i][q] = M.arx[jj + q * NB];
           }
-        };
-        float2* r = fft_fused2<NF, IP>(bufA, bufB, rt, tw, inl, outl, pw);
-        store_rowpair_spectra<NF>(r, M, W.s0, tile);
-        store_rowpair_spectra<NF>(r + half * LS, M, W.s1, tile);
-        return;
+          aya[i] = M.ary[ya];
+          ayb[i] = M.ary[ya + 1];
+        }
       }
+      put_pair<NF>(S, bufA, M);
+      if constexpr (!TG) put_tw(TW, twl, nx);
+      __syncthreads();
+      auto inl = [&](int l, int sd) { return 2 * l + sd; };
+      auto outl = [&](int l, int sd) { return sd * half + l; };
+      auto pw = [&](int i, int l, int jj, float2* va, float2* vb) {
+#pragma clang fp contract(off)  // the same rounding fused or not (no cross-path contraction choices)
+        const unsigned ba = rowoff(y0 + 2 * l) + jj, bb = ba + nx;
+        const float s = 0.f;
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+          const float exa = va[q].x, eya = -va[q].y, exb = vb[q].x, eyb = -vb[q].y;
+          const float rxA = ax[i][q] * (ax[i][q] * rxa[i][q] - dt * r0a[i][q] * exa) + s;
+          const float ryA = aya[i] * (aya[i] * rya[i][q] - dt * r0a[i][q] * eya) + s;
+          const float rxB = ax[i][q] * (ax[i][q] * rxb[i][q] - dt * r0b[i][q] * exb) + s;
+          const float ryB = ayb[i] * (ayb[i] * ryb[i][q] - dt * r0b[i][q] * eyb) + s;
+          W.f2[ba + q * NB] = rxA;
+          W.f3[ba + q * NB] = ryA;
+          W.f2[bb + q * NB] = rxB;
+          W.f3[bb + q * NB] = ryB;
+          va[q] = make_float2(rxA + ryA, rxB + ryB);
+          vb[q] = make_float2(r0a[i][q] * (ax[i][q] * exa + aya[i] * eya), r0b[i][q] * (ax[i][q] * exb + ayb[i] * eyb));
+        }
+      };
+      float2* r = fft_fused2<NF, IP>(bufA, bufB, rt, tw, inl, outl, pw);
+      store_rowpair_spectra<NF>(r, M, W.s0, tile);
+      store_rowpair_spectra<NF>(r + half * LS, M, W.s1, tile);
+    } else if constexpr (BM == RM_A2 && row_fusable<NF>() && !TG) {
+      const bool first = (n == M.nt - 2);
+      // the update between the two FFTs in registers: rows 2l and 2l+1 of
+      // each position together (they share the input lines)
+      constexpr int R = plan_radix(NF, 0), NB = NF / R, MB = fused2_slots<NF>();
+      const int half = rt / 2;
+      float qa[MB][R], xa[MB][R], ya0[MB][R], r0a[MB][R], qb[MB][R], xb[MB][R], yb0[MB][R], r0b[MB][R];
+      float ax[MB][R], aya[MB], ayb[MB];
+      RowPairRegs S0, S1;
+      TwRegs TW;
+      fetch_rowpair<NF>(S0, M, W.s0, tile);
+      fetch_rowpair<NF>(S1, M, W.s1, tile);
+      if constexpr (!TG) fetch_tw(TW, M.twx, nx);
+#pragma unroll
+      for (int i = 0; i < MB; ++i) {
+        if (i * B < half * NB) {
+          const unsigned it = min(unsigned(threadIdx.x + i * B), unsigned(half * NB) - 1u);
+          const int l = int(it / NB), jj = int(it % NB), y = y0 + 2 * l;
+          const unsigned ba = rowoff(y) + jj, bb = ba + nx;
+#pragma unroll
+          for (int q = 0; q < R; ++q) {
+            qa[i][q] = W.q[ba + q * NB];
+            xa[i][q] = W.f2[ba + q * NB];
+            ya0[i][q] = W.f3[ba + q * NB];
+            r0a[i][q] = M.rho0[ba + q * NB];
+            qb[i][q] = W.q[bb + q * NB];
+            xb[i][q] = W.f2[bb + q * NB];
+            yb0[i][q] = W.f3[bb + q * NB];
+            r0b[i][q] = M.rho0[bb + q * NB];
+            ax[i][q] = M.arx[jj + q * NB];
+          }
+          aya[i] = M.ary[y];
+          ayb[i] = M.ary[y + 1];
+        }
+      }
+      put_rowpair<NF>(S0, bufA, M);
+      put_rowpair<NF>(S1, bufA + half * LS, M);
+      if constexpr (!TG) put_tw(TW, twl, nx);
+      __syncthreads();
+      auto inl = [&](int l, int sd) { return sd * half + l; };
+      auto outl = [&](int l, int sd) { return 2 * l + sd; };
+      auto pw = [&](int i, int l, int jj, float2* va, float2* vb) {
+#pragma clang fp contract(off)  // the same rounding fused or not (no cross-path contraction choices)
+        const unsigned ba = rowoff(y0 + 2 * l) + jj, bb = ba + nx;
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+          // rows 2l and 2l+1 of the (conjugated) inverse transforms
+          const float yda = va[q].x, ydb = -va[q].y, yaa = vb[q].x, yab = -vb[q].y;
+          const float sba = qa[i][q] - yda, sbb = qb[i][q] - ydb;
+          const float rbxa = (first ? 0.f : xa[i][q]) + sba, rbya = (first ? 0.f : ya0[i][q]) + sba;
+          const float rbxb = (first ? 0.f : xb[i][q]) + sbb, rbyb = (first ? 0.f : yb0[i][q]) + sbb;
+          va[q] = make_float2(r0a[i][q] * ax[i][q] * (yaa - dt * rbxa), r0a[i][q] * aya[i] * (yaa - dt * rbya));
+          vb[q] = make_float2(r0b[i][q] * ax[i][q] * (yab - dt * rbxb), r0b[i][q] * ayb[i] * (yab - dt * rbyb));
+          W.f2[ba + q * NB] = ax[i][q] * ax[i][q] * rbxa;
+          W.f3[ba + q * NB] = aya[i] * aya[i] * rbya;
+          W.f2[bb + q * NB] = ax[i][q] * ax[i][q] * rbxb;
+          W.f3[bb + q * NB] = ayb[i] * ayb[i] * rbyb;
+        }
+      };
+      float2* r = fft_fused2<NF, IP>(bufA, bufB, rt, tw, inl, outl, pw);
+      store_pair_spectra<NF>(r, M, W.s0, W.s1, tile);
     }
+  } else if constexpr (BM == RM_F2 || BM == RM_F2L) {
+    // eq num-rho with the additive source of eq s1 (dt s = p0 / (2 d c^2), d = 2)
     const bool skip = (n == -1);  // v^{-1/2} = 0 and rho^{-1} = 0
     const bool inject = (n <= 0);
     float rxo[kMaxPer], ryo[kMaxPer], r0[kMaxPer], ax[kMaxPer], ay[kMaxPer], src[kMaxPer], c2[kMaxPer];
@@ -1422,70 +1487,6 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
   } else if constexpr (BM == RM_A2) {
     // transpose of the mass update and of the Y terms of eq num-p
     const bool first = (n == M.nt - 2);
-    if constexpr (row_fusable<NF>() && !TG) {
-      if (n >= 1) {
-        // the update between the two FFTs in registers: rows 2l and 2l+1 of
-        // each position together (they share the input lines)
-        constexpr int R = plan_radix(NF, 0), NB = NF / R, MB = fused2_slots<NF>();
-        const int half = rt / 2;
-        float qa[MB][R], xa[MB][R], ya0[MB][R], r0a[MB][R], qb[MB][R], xb[MB][R], yb0[MB][R], r0b[MB][R];
-        float ax[MB][R], aya[MB], ayb[MB];
-        RowPairRegs S0, S1;
-        TwRegs TW;
-        fetch_rowpair<NF>(S0, M, W.s0, tile);
-        fetch_rowpair<NF>(S1, M, W.s1, tile);
-        if constexpr (!TG) fetch_tw(TW, M.twx, nx);
-#pragma unroll
-        for (int i = 0; i < MB; ++i) {
-          if (i * B < half * NB) {
-            const unsigned it = min(unsigned(threadIdx.x + i * B), unsigned(half * NB) - 1u);
-            const int l = int(it / NB), jj = int(it % NB), y = y0 + 2 * l;
-            const unsigned ba = rowoff(y) + jj, bb = ba + nx;
-#pragma unroll
-            for (int q = 0; q < R; ++q) {
-              qa[i][q] = W.q[ba + q * NB];
-              xa[i][q] = W.f2[ba + q * NB];
-              ya0[i][q] = W.f3[ba + q * NB];
-              r0a[i][q] = M.rho0[ba + q * NB];
-              qb[i][q] = W.q[bb + q * NB];
-              xb[i][q] = W.f2[bb + q * NB];
-              yb0[i][q] = W.f3[bb + q * NB];
-              r0b[i][q] = M.rho0[bb + q * NB];
-              ax[i][q] = M.arx[jj + q * NB];
-            }
-            aya[i] = M.ary[y];
-            ayb[i] = M.ary[y + 1];
-          }
-        }
-        put_rowpair<NF>(S0, bufA, M);
-        put_rowpair<NF>(S1, bufA + half * LS, M);
-        if constexpr (!TG) put_tw(TW, twl, nx);
-        __syncthreads();
-        auto inl = [&](int l, int sd) { return sd * half + l; };
-        auto outl = [&](int l, int sd) { return 2 * l + sd; };
-        auto pw = [&](int i, int l, int jj, float2* va, float2* vb) {
-#pragma clang fp contract(off)  // the same rounding fused or not (no cross-path contraction choices)
-          const unsigned ba = rowoff(y0 + 2 * l) + jj, bb = ba + nx;
-#pragma unroll
-          for (int q = 0; q < R; ++q) {
-            // rows 2l and 2l+1 of the (conjugated) inverse transforms
-            const float yda = va[q].x, ydb = -va[q].y, yaa = vb[q].x, yab = -vb[q].y;
-            const float sba = qa[i][q] - yda, sbb = qb[i][q] - ydb;
-            const float rbxa = (first ? 0.f : xa[i][q]) + sba, rbya = (first ? 0.f : ya0[i][q]) + sba;
-            const float rbxb = (first ? 0.f : xb[i][q]) + sbb, rbyb = (first ? 0.f : yb0[i][q]) + sbb;
-            va[q] = make_float2(r0a[i][q] * ax[i][q] * (yaa - dt * rbxa), r0a[i][q] * aya[i] * (yaa - dt * rbya));
-            vb[q] = make_float2(r0b[i][q] * ax[i][q] * (yab - dt * rbxb), r0b[i][q] * ayb[i] * (yab - dt * rbyb));
-            W.f2[ba + q * NB] = ax[i][q] * ax[i][q] * rbxa;
-            W.f3[ba + q * NB] = aya[i] * aya[i] * rbya;
-            W.f2[bb + q * NB] = ax[i][q] * ax[i][q] * rbxb;
-            W.f3[bb + q * NB] = ayb[i] * ayb[i] * rbyb;
-          }
-        };
-        float2* r = fft_fused2<NF, IP>(bufA, bufB, rt, tw, inl, outl, pw);
-        store_pair_spectra<NF>(r, M, W.s0, W.s1, tile);
-        return;
-      }
-    }
     float qv[kMaxPer], rbx0[kMaxPer], rby0[kMaxPer], r0[kMaxPer], ax[kMaxPer], ay[kMaxPer];
     float c2[kMaxPer], gacc[kMaxPer];
     RowPairRegs S0, S1;
@@ -2336,37 +2337,55 @@ __global__ void __launch_bounds__(kBlock) dot_final(const double* __restrict__ p
 #define QPAT_FOR_LENGTHS(X) X(128) X(256) X(384) X(512) X(1024)
 #define QPAT_FOR_COL_LENGTHS(X) X(128) X(256) X(384) X(512) X(1024)
 
+// Compile-time row lengths whose plan fuses the boundary stage (RM_FZ instances).
+#define QPAT_FOR_FUSED_LENGTHS(X) X(128) X(256) X(512) X(1024)
+
 template <int MODE>
 static hipError_t launch_row_t(const Launch& L, bool uniform, int len, bool tg, int ntile, int chunk, int nblocks,
                                int threads, size_t lds, int n, int flags, hipStream_t st) {
   const dim3 g(nblocks), t(threads);
-  if (uniform && tg) {
+  if constexpr ((MODE & RM_FZ) != 0) {
+    if (tg) return hipErrorInvalidValue;
+#define QPAT_ROW_LEN(N)                                                                                   \
+  case N:                                                                                                 \
+    if (uniform) hipLaunchKernelGGL((row_kernel<MODE, true, N>), g, t, lds, st, L, ntile, chunk, n, flags); \
+    else hipLaunchKernelGGL((row_kernel<MODE, false, N>), g, t, lds, st, L, ntile, chunk, n, flags);       \
+    break;
+    switch (uniform ? L.m.nx : len) {
+      QPAT_FOR_FUSED_LENGTHS(QPAT_ROW_LEN)
+      default: return hipErrorInvalidValue;
+    }
+#undef QPAT_ROW_LEN
+    return hipGetLastError();
+  } else {
+    if (uniform && tg) {
 #define QPAT_ROW_LEN(N) \
   case N: hipLaunchKernelGGL((row_kernel<MODE, true, N, true>), g, t, lds, st, L, ntile, chunk, n, flags); break;
-    switch (L.m.nx) {
-      QPAT_FOR_LENGTHS(QPAT_ROW_LEN)
-      default: return hipErrorInvalidValue;  // global-twiddle instances exist for these lengths only
-    }
+      switch (L.m.nx) {
+        QPAT_FOR_LENGTHS(QPAT_ROW_LEN)
+        default: return hipErrorInvalidValue;  // global-twiddle instances exist for these lengths only
+      }
 #undef QPAT_ROW_LEN
-  } else if (uniform) {
+    } else if (uniform) {
 #define QPAT_ROW_LEN(N) \
   case N: hipLaunchKernelGGL((row_kernel<MODE, true, N>), g, t, lds, st, L, ntile, chunk, n, flags); break;
-    switch (L.m.nx) {
-      QPAT_FOR_LENGTHS(QPAT_ROW_LEN)
-      default: hipLaunchKernelGGL((row_kernel<MODE, true, 0>), g, t, lds, st, L, ntile, chunk, n, flags); break;
-    }
+      switch (L.m.nx) {
+        QPAT_FOR_LENGTHS(QPAT_ROW_LEN)
+        default: hipLaunchKernelGGL((row_kernel<MODE, true, 0>), g, t, lds, st, L, ntile, chunk, n, flags); break;
+      }
 #undef QPAT_ROW_LEN
-  } else {
-    if (tg) return hipErrorInvalidValue;
+    } else {
+      if (tg) return hipErrorInvalidValue;
 #define QPAT_ROW_LEN(N) \
   case N: hipLaunchKernelGGL((row_kernel<MODE, false, N>), g, t, lds, st, L, ntile, chunk, n, flags); break;
-    switch (len) {
-      QPAT_FOR_LENGTHS(QPAT_ROW_LEN)
-      default: hipLaunchKernelGGL((row_kernel<MODE, false, 0>), g, t, lds, st, L, ntile, chunk, n, flags); break;
-    }
+      switch (len) {
+        QPAT_FOR_LENGTHS(QPAT_ROW_LEN)
+        default: hipLaunchKernelGGL((row_kernel<MODE, false, 0>), g, t, lds, st, L, ntile, chunk, n, flags); break;
+      }
 #undef QPAT_ROW_LEN
+    }
+    return hipGetLastError();
   }
-  return hipGetLastError();
 }
 
 hipError_t launch_row(int mode, const Launch& L, bool uniform, int len, bool tg, int ntile, int chunk, int nblocks,
@@ -2388,6 +2407,8 @@ hipError_t launch_row(int mode, const Launch& L, bool uniform, int len, bool tg,
     QPAT_ROW_CASE(RM_F3 | RM_X)
     QPAT_ROW_CASE(RM_A1 | RM_X)
     QPAT_ROW_CASE(RM_A1L | RM_X)
+    QPAT_ROW_CASE(RM_F2 | RM_FZ)
+    QPAT_ROW_CASE(RM_A2 | RM_FZ)
     default: return hipErrorInvalidValue;
   }
 #undef QPAT_ROW_CASE
@@ -2442,6 +2463,13 @@ hipError_t launch_col(int cm, int mcode, const Launch& L, bool uniform, int len,
 #undef QPAT_COL_CASE
 }
 
+bool kernels_row_fused(int n) {
+#define QPAT_HAVE(N) if (n == N) return row_fusable<N>();
+  QPAT_FOR_FUSED_LENGTHS(QPAT_HAVE)
+#undef QPAT_HAVE
+  return false;
+}
+
 bool kernels_have_length(int n, bool col) {
 #define QPAT_HAVE(N) if (n == N) return true;
   if (col) {
@@ -2471,6 +2499,16 @@ static hipError_t allow_row(size_t bytes) {
 #undef QPAT_ALLOW_ROW
   return e;
 }
+template <int MODE>
+static hipError_t allow_row_fused(size_t bytes) {
+  hipError_t e = hipSuccess;
+#define QPAT_ALLOW_ROW(N)                                                 \
+  if (e == hipSuccess) e = allow_fn(&row_kernel<MODE, true, N>, bytes); \
+  if (e == hipSuccess) e = allow_fn(&row_kernel<MODE, false, N>, bytes);
+  QPAT_FOR_FUSED_LENGTHS(QPAT_ALLOW_ROW)
+#undef QPAT_ALLOW_ROW
+  return e;
+}
 template <int CM>
 static hipError_t allow_col(size_t bytes) {
   hipError_t e = allow_fn(&col_kernel<false, CM, 0>, bytes);
@@ -2490,6 +2528,7 @@ hipError_t kernels_allow_lds(size_t bytes) {
                            allow_row<RM_A2>(bytes),      allow_row<RM_A3>(bytes),     allow_row<RM_FWD1>(bytes),
                            allow_row<RM_INV1>(bytes),    allow_row<RM_F2L | RM_X>(bytes), allow_row<RM_F3 | RM_X>(bytes),
                            allow_row<RM_A1 | RM_X>(bytes), allow_row<RM_A1L | RM_X>(bytes),
+                           allow_row_fused<RM_F2 | RM_FZ>(bytes), allow_row_fused<RM_A2 | RM_FZ>(bytes),
                            allow_col<CM_GRADP1>(bytes), allow_col<CM_GRADM2>(bytes),
                            allow_col<CM_FRAC>(bytes),    allow_col<CM_GRADP2>(bytes), allow_col<CM_DIVM>(bytes),
                            allow_col<CM_APPLY>(bytes)};
