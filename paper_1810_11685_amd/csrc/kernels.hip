@@ -473,6 +473,67 @@ __device__ __forceinline__ float2* fft_fused2(float2* a, float2* b, int nlines, 
   else return fft_stages<N, false, LS, 1, NST, R>(o, r, nlines, tw);
 }
 
+// The value x of the adjacent lane (lane ^ 1): a DPP quad permutation
+// [1, 0, 3, 2], a VALU move (no LDS round trip).  Both lanes of a pair must
+// be active.
+__device__ __forceinline__ float lane_pair_swap(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xB1, 0xF, 0xF, false));
+}
+
+// The same fusion for updates that pair rows 2l and 2l+1 as one complex line
+// on one side of the update and keep each row its own line on the other.
+// Work item (l, sd, jj) runs the last stage on line inl(l, sd), the update
+// `pw(i, l, sd, jj, v, active)` of row 2l + sd, and the first stage on line
+// outl(l, sd).  Consecutive work items hold the two rows of a pair, so the
+// two lanes of a pair trade the half of a packed line each needs with one
+// lane shuffle per value inside pw; pw therefore runs on every lane (lanes
+// without a work item hold zeros and `active` false).
+template <int N, bool IP, class IL, class OL, class PW>
+__device__ __forceinline__ float2* fft_fused_pairs(float2* a, float2* b, int nlines, const float2* tw, IL inl,
+                                                   OL outl, PW pw) {
+  constexpr int LS = lstride(N), NST = plan_nst(N), R = plan_radix(N, 0), NB = N / R, MB = fused_slots<N>();
+  constexpr int OFFL = NB - R;
+  float2* r;
+  if constexpr (IP) r = fft_range_ip<N, LS, 0, NST - 1, 1>(a, nlines, tw);
+  else r = fft_stages<N, false, LS, 0, NST - 1, 1>(a, b, nlines, tw);
+  float2* o = IP ? r : (r == a ? b : a);
+  const unsigned total = unsigned(nlines) * NB;  // even: pairs are both in range or both out
+  float2 v[MB][R];
+#pragma unroll
+  for (int i = 0; i < MB; ++i) {
+    const unsigned it = threadIdx.x + i * blockDim.x;
+    const unsigned p = it >> 1, sd = it & 1u, l = p / NB, jj = p % NB;
+    if (it < total) {
+      stage_load<R, NB>(v[i], r + inl(int(l), int(sd)) * LS, jj);
+      stage_regs<R, NB, OFFL>(v[i], jj, tw);
+    } else {
+#pragma unroll
+      for (int q = 0; q < R; ++q) v[i][q] = make_float2(0.f, 0.f);
+    }
+  }
+  if constexpr (IP) __syncthreads();
+#pragma unroll
+  for (int i = 0; i < MB; ++i) {
+    if (i * blockDim.x < total) {  // block-uniform: the shuffles see whole waves
+      const unsigned it = threadIdx.x + i * blockDim.x;
+      const unsigned p = it >> 1, sd = it & 1u, l = p / NB, jj = p % NB;
+      const bool active = it < total;
+#pragma unroll
+      for (int q = 0; q < R; ++q) asm volatile("" : "+v"(v[i][q].x), "+v"(v[i][q].y));
+      pw(i, int(l), int(sd), int(jj), v[i], active);
+#pragma unroll
+      for (int q = 0; q < R; ++q) asm volatile("" : "+v"(v[i][q].x), "+v"(v[i][q].y));
+      if (active) {
+        stage_regs<R, 1, 0>(v[i], jj, tw);
+        stage_store<R, 1>(v[i], o + outl(int(l), int(sd)) * LS, jj);
+      }
+    }
+  }
+  __syncthreads();
+  if constexpr (IP) return fft_range_ip<N, LS, 1, NST, R>(o, nlines, tw);
+  else return fft_stages<N, false, LS, 1, NST, R>(o, r, nlines, tw);
+}
+
 // FFT of `nlines` lines: compile-time plan for the common lengths, the
 // runtime plan otherwise.  Same contract as fft_lines; row lines have stride
 // lstride(n), column lines (COL) col_lstride(n).  IP (instances with a
@@ -1079,8 +1140,66 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     // transpose) at iterates n >= 1, past the source and the zero initial
     // state: only the fused path is compiled, so the first iterates' code does
     // not set these kernels' register count.  The host launches them only for
-    // compile-time lengths whose plan fuses and twiddles staged in LDS.
-    if constexpr (BM == RM_F2 && row_fusable<NF>() && !TG) {
+    // compile-time lengths whose plan fuses.  Work item (l, sd, jj): row
+    // 2l + sd at butterfly jj, the two rows of a pair in adjacent lanes.
+    // plans whose boundary stage has radix 8 hold one row per work item (rows
+    // 2l, 2l+1 in adjacent lanes); radix-4 ones (1024, 128) two rows per work
+    // item, which is faster there but only where the twiddles sit in LDS
+    constexpr bool PAIRS = plan_radix(NF > 0 ? NF : 8, 0) > 4;
+    if constexpr (BM == RM_F2 && row_fusable<NF>() && PAIRS) {
+      // each row's inverse line in, S and u lines (rows 2l, 2l+1 packed) out
+      constexpr int R = plan_radix(NF, 0), NB = NF / R, MB = fused_slots<NF>();
+      const int half = rt / 2;
+      float rxo[MB][R], ryo[MB][R], r0[MB][R], ax[MB][R], ay[MB];
+      PairRegs S;
+      TwRegs TW;
+      fetch_pair<NF>(S, M, W.s0, W.s1, tile);
+      if constexpr (!TG) fetch_tw(TW, M.twx, nx);
+#pragma unroll
+      for (int i = 0; i < MB; ++i) {
+        if (i * B < rt * NB) {
+          const unsigned it = min(unsigned(threadIdx.x + i * B), unsigned(rt * NB) - 1u);
+          const unsigned p = it >> 1, l = p / NB, jj = p % NB;
+          const int y = y0 + 2 * int(l) + int(it & 1u);
+          const unsigned base = rowoff(y) + jj;
+#pragma unroll
+          for (int q = 0; q < R; ++q) {
+            rxo[i][q] = W.f2[base + q * NB];
+            ryo[i][q] = W.f3[base + q * NB];
+            r0[i][q] = M.rho0[base + q * NB];
+            ax[i][q] = M.arx[jj + q * NB];
+          }
+          ay[i] = M.ary[y];
+        }
+      }
+      put_pair<NF>(S, bufA, M);
+      if constexpr (!TG) put_tw(TW, twl, nx);
+      __syncthreads();
+      auto inl = [&](int l, int sd) { return 2 * l + sd; };
+      auto outl = [&](int l, int sd) { return sd * half + l; };
+      auto pw = [&](int i, int l, int sd, int jj, float2* v, bool active) {
+#pragma clang fp contract(off)  // the same rounding fused or not (no cross-path contraction choices)
+        const unsigned base = rowoff(y0 + 2 * l + sd) + jj;
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+          const float ex = v[q].x, ey = -v[q].y;
+          const float s = 0.f;
+          const float rx = ax[i][q] * (ax[i][q] * rxo[i][q] - dt * r0[i][q] * ex) + s;
+          const float ry = ay[i] * (ay[i] * ryo[i][q] - dt * r0[i][q] * ey) + s;
+          if (active) {
+            W.f2[base + q * NB] = rx;
+            W.f3[base + q * NB] = ry;
+          }
+          const float sum = rx + ry, u = r0[i][q] * (ax[i][q] * ex + ay[i] * ey);
+          // row 2l keeps S and sends u; row 2l+1 keeps u and sends S
+          const float got = lane_pair_swap(sd ? sum : u);
+          v[q] = sd ? make_float2(got, u) : make_float2(sum, got);
+        }
+      };
+      float2* r = fft_fused_pairs<NF, IP>(bufA, bufB, rt, tw, inl, outl, pw);
+      store_rowpair_spectra<NF>(r, M, W.s0, tile);
+      store_rowpair_spectra<NF>(r + half * LS, M, W.s1, tile);
+    } else if constexpr (BM == RM_F2 && row_fusable<NF>() && !TG) {
       // iterates past the source: the update between the two FFTs in
       // registers, rows 2l and 2l+1 of each position together (their S and
       // u values share one complex line each on the output side)
@@ -1139,6 +1258,61 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
       float2* r = fft_fused2<NF, IP>(bufA, bufB, rt, tw, inl, outl, pw);
       store_rowpair_spectra<NF>(r, M, W.s0, tile);
       store_rowpair_spectra<NF>(r + half * LS, M, W.s1, tile);
+    } else if constexpr (BM == RM_A2 && row_fusable<NF>() && PAIRS) {
+      // the eta / tau lines (rows 2l, 2l+1 packed) in, each row's line out
+      const bool first = (n == M.nt - 2);
+      constexpr int R = plan_radix(NF, 0), NB = NF / R, MB = fused_slots<NF>();
+      const int half = rt / 2;
+      float qv[MB][R], x0[MB][R], y0v[MB][R], r0[MB][R], ax[MB][R], ay[MB];
+      RowPairRegs S0, S1;
+      TwRegs TW;
+      fetch_rowpair<NF>(S0, M, W.s0, tile);
+      fetch_rowpair<NF>(S1, M, W.s1, tile);
+      if constexpr (!TG) fetch_tw(TW, M.twx, nx);
+#pragma unroll
+      for (int i = 0; i < MB; ++i) {
+        if (i * B < rt * NB) {
+          const unsigned it = min(unsigned(threadIdx.x + i * B), unsigned(rt * NB) - 1u);
+          const unsigned p = it >> 1, l = p / NB, jj = p % NB;
+          const int y = y0 + 2 * int(l) + int(it & 1u);
+          const unsigned base = rowoff(y) + jj;
+#pragma unroll
+          for (int q = 0; q < R; ++q) {
+            qv[i][q] = W.q[base + q * NB];
+            x0[i][q] = W.f2[base + q * NB];
+            y0v[i][q] = W.f3[base + q * NB];
+            r0[i][q] = M.rho0[base + q * NB];
+            ax[i][q] = M.arx[jj + q * NB];
+          }
+          ay[i] = M.ary[y];
+        }
+      }
+      put_rowpair<NF>(S0, bufA, M);
+      put_rowpair<NF>(S1, bufA + half * LS, M);
+      if constexpr (!TG) put_tw(TW, twl, nx);
+      __syncthreads();
+      auto inl = [&](int l, int sd) { return sd * half + l; };
+      auto outl = [&](int l, int sd) { return 2 * l + sd; };
+      auto pw = [&](int i, int l, int sd, int jj, float2* v, bool active) {
+#pragma clang fp contract(off)  // the same rounding fused or not (no cross-path contraction choices)
+        const unsigned base = rowoff(y0 + 2 * l + sd) + jj;
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+          // row 2l holds the eta line (yd of rows 2l, 2l+1), row 2l+1 the tau
+          // line (ya of rows 2l, 2l+1): each sends the value the other's row needs
+          const float got = lane_pair_swap(sd ? v[q].x : -v[q].y);
+          const float yd = sd ? got : v[q].x, ya = sd ? -v[q].y : got;
+          const float sb = qv[i][q] - yd;
+          const float rbx = (first ? 0.f : x0[i][q]) + sb, rby = (first ? 0.f : y0v[i][q]) + sb;
+          v[q] = make_float2(r0[i][q] * ax[i][q] * (ya - dt * rbx), r0[i][q] * ay[i] * (ya - dt * rby));
+          if (active) {
+            W.f2[base + q * NB] = ax[i][q] * ax[i][q] * rbx;
+            W.f3[base + q * NB] = ay[i] * ay[i] * rby;
+          }
+        }
+      };
+      float2* r = fft_fused_pairs<NF, IP>(bufA, bufB, rt, tw, inl, outl, pw);
+      store_pair_spectra<NF>(r, M, W.s0, W.s1, tile);
     } else if constexpr (BM == RM_A2 && row_fusable<NF>() && !TG) {
       const bool first = (n == M.nt - 2);
       // the update between the two FFTs in registers: rows 2l and 2l+1 of
@@ -2345,11 +2519,12 @@ static hipError_t launch_row_t(const Launch& L, bool uniform, int len, bool tg, 
                                int threads, size_t lds, int n, int flags, hipStream_t st) {
   const dim3 g(nblocks), t(threads);
   if constexpr ((MODE & RM_FZ) != 0) {
-    if (tg) return hipErrorInvalidValue;
-#define QPAT_ROW_LEN(N)                                                                                   \
-  case N:                                                                                                 \
-    if (uniform) hipLaunchKernelGGL((row_kernel<MODE, true, N>), g, t, lds, st, L, ntile, chunk, n, flags); \
-    else hipLaunchKernelGGL((row_kernel<MODE, false, N>), g, t, lds, st, L, ntile, chunk, n, flags);       \
+    if (tg && !uniform) return hipErrorInvalidValue;
+#define QPAT_ROW_LEN(N)                                                                                        \
+  case N:                                                                                                      \
+    if (tg) hipLaunchKernelGGL((row_kernel<MODE, true, N, true>), g, t, lds, st, L, ntile, chunk, n, flags);  \
+    else if (uniform) hipLaunchKernelGGL((row_kernel<MODE, true, N>), g, t, lds, st, L, ntile, chunk, n, flags); \
+    else hipLaunchKernelGGL((row_kernel<MODE, false, N>), g, t, lds, st, L, ntile, chunk, n, flags);            \
     break;
     switch (uniform ? L.m.nx : len) {
       QPAT_FOR_FUSED_LENGTHS(QPAT_ROW_LEN)
@@ -2463,8 +2638,8 @@ hipError_t launch_col(int cm, int mcode, const Launch& L, bool uniform, int len,
 #undef QPAT_COL_CASE
 }
 
-bool kernels_row_fused(int n) {
-#define QPAT_HAVE(N) if (n == N) return row_fusable<N>();
+bool kernels_row_fused(int n, bool tg) {
+#define QPAT_HAVE(N) if (n == N) return row_fusable<N>() && (plan_radix(N, 0) > 4 || !tg);
   QPAT_FOR_FUSED_LENGTHS(QPAT_HAVE)
 #undef QPAT_HAVE
   return false;
@@ -2502,8 +2677,9 @@ static hipError_t allow_row(size_t bytes) {
 template <int MODE>
 static hipError_t allow_row_fused(size_t bytes) {
   hipError_t e = hipSuccess;
-#define QPAT_ALLOW_ROW(N)                                                 \
-  if (e == hipSuccess) e = allow_fn(&row_kernel<MODE, true, N>, bytes); \
+#define QPAT_ALLOW_ROW(N)                                                       \
+  if (e == hipSuccess) e = allow_fn(&row_kernel<MODE, true, N>, bytes);       \
+  if (e == hipSuccess) e = allow_fn(&row_kernel<MODE, true, N, true>, bytes); \
   if (e == hipSuccess) e = allow_fn(&row_kernel<MODE, false, N>, bytes);
   QPAT_FOR_FUSED_LENGTHS(QPAT_ALLOW_ROW)
 #undef QPAT_ALLOW_ROW

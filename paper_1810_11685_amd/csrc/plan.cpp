@@ -365,7 +365,7 @@ hipError_t row(Exec& E, int mode, int n, int flags, hipStream_t st) {
   // the lossy density passes past the first iterates take the instances that
   // hold only the fused-boundary-stage path, where one exists
   if ((mode == RM_F2 || mode == RM_A2) && n >= 1 &&
-      (E.uniform ? !E.row_tg && kernels_row_fused(E.L.m.nx) : kernels_row_fused(E.tab_nx)))
+      (E.uniform ? kernels_row_fused(E.L.m.nx, E.row_tg) : kernels_row_fused(E.tab_nx, false)))
     mode |= RM_FZ;
   if (E.uniform)
     return launch_row(mode, E.L, true, 0, E.row_tg, E.row_ntile, E.row_chunk, E.row_chunk * kXcds, E.rthr,

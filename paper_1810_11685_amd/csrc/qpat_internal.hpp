@@ -118,7 +118,7 @@ enum RowMode : int {
   RM_X = 16,
   // Modifier of RM_F2 / RM_A2 at iterates n >= 1: the instance holds only the
   // path with the two FFTs' boundary stage fused (compile-time lengths whose
-  // plan allows it, twiddles staged in LDS; see kernels_row_fused).
+  // plan allows it; see kernels_row_fused).
   RM_FZ = 32
 };
 
@@ -147,9 +147,9 @@ hipError_t launch_row(int mode, const Launch& L, bool uniform, int len, bool tg,
                       int threads, size_t lds, int n, int flags, hipStream_t st);
 hipError_t launch_col(int cm, int mcode, const Launch& L, bool uniform, int len, bool tg, int ntile, int chunk,
                       int nblocks, int threads, size_t lds, int n, hipStream_t st);
-// Row lengths whose RM_FZ instances exist (uniform launches without global
-// twiddles, and table launches of that length).
-bool kernels_row_fused(int n);
+// Row lengths whose RM_FZ instances exist (uniform launches, and table
+// launches of that length), for launches reading global twiddles (tg) or not.
+bool kernels_row_fused(int n, bool tg);
 // Row (col false) or column lengths with compile-time kernel instances.
 bool kernels_have_length(int n, bool col);
 hipError_t launch_combine(const Item* items, const IO* io, int nitems, int max_count,
