@@ -345,6 +345,27 @@ def test_uneven_batch_matches_single(q):
             assert np.array_equal(N(g), gref)
 
 
+def test_mixed_batch_matches_fused_single_plans(q):
+    """A batch mixing 256^2 and 512^2 grids launches the all-length kernels
+    (runtime plans, density updates between two separate FFTs); single plans
+    of those sizes launch the compile-time instances whose density passes fuse
+    the FFTs' boundary stage (one row per work item, lane pairs exchanging
+    their packed-line halves). The same bits."""
+    probs = []
+    for (nx, nt, seed) in [(256, 14, 21), (512, 10, 23)]:
+        prm, c0, rho0, p0 = problem(nx, nx, nt, seed=seed, ns=nx // 8)
+        probs.append((q.Plan(prm, c0, rho0), p0))
+    B = q.Batch([p for p, _ in probs])
+    B.set_schedule(0)
+    xs = [T(p0) for _, p0 in probs]
+    refs = [(N(plan.forward(x)), N(plan.jtjv(x))) for (plan, _), x in zip(probs, xs)]
+    ds = B.forward(xs)
+    gs = B.jtjv(xs)
+    for (dref, gref), d, g in zip(refs, ds, gs):
+        assert np.array_equal(N(d), dref)
+        assert np.array_equal(N(g), gref)
+
+
 def test_uneven_batch_tuner(q):
     """qpat_batch_tune picks launch shapes per grid size and a schedule; the
     results stay those of the single plans."""
