@@ -704,9 +704,27 @@ __device__ __forceinline__ void put_tw(const TwRegsK<K>& R, float2* dst, int n) 
   }
 }
 
+// Spectrum store; NT (launches of about one block per CU): non-temporal, so
+// the kernel's end has fewer dirty L2 lines to write back before the next
+// pass, on other XCDs, reads them.  With many blocks per CU the plain store is
+// the faster one (measured: one 512^2 vector 154.0 -> 152.0 ms non-temporal,
+// 1024^2 x 8 pass sum 554 -> 661 us).
+typedef float f2v_t __attribute__((ext_vector_type(2)));
+template <bool NT>
+__device__ __forceinline__ void st_spec(float2* p, float2 v) {
+  if constexpr (NT) {
+    f2v_t x;
+    x.x = v.x;
+    x.y = v.y;
+    __builtin_nontemporal_store(x, reinterpret_cast<f2v_t*>(p));
+  } else {
+    *p = v;
+  }
+}
+
 // (the store loops are unrolled so that the LDS reads of several iterations
 // are in flight together: the global stores in between cannot alias LDS)
-template <int NF>
+template <int NF, bool NT = false>
 __device__ __forceinline__ void store_pair_spectra(const float2* buf, const Medium& M, float2* __restrict__ s0,
                                                    float2* __restrict__ s1, int tile) {
   const int nx = row_len<NF>(M), nxh = row_half<NF>(M), LS = lstride(nx), rc = M.rt * M.ct;
@@ -717,12 +735,12 @@ __device__ __forceinline__ void store_pair_spectra(const float2* buf, const Medi
     const int j = w >> M.lct, k = ((p >> (M.lrt + M.lct)) << M.lct) + (w & (M.ct - 1));
     float2 A, B;
     unpack(buf + j * LS, k, nx, nxh, A, B);
-    s0[base + p] = A;
-    s1[base + p] = B;
+    st_spec<NT>(s0 + base + p, A);
+    st_spec<NT>(s1 + base + p, B);
   }
 }
 
-template <int NF>
+template <int NF, bool NT = false>
 __device__ __forceinline__ void store_rowpair_spectra(const float2* buf, const Medium& M, float2* __restrict__ s0,
                                                       int tile) {
   const int nx = row_len<NF>(M), nxh = row_half<NF>(M), LS = lstride(nx), hc = (M.rt >> 1) * M.ct;
@@ -734,8 +752,8 @@ __device__ __forceinline__ void store_rowpair_spectra(const float2* buf, const M
     const unsigned off = base + (unsigned(tx) << (M.lrt + M.lct)) + (2 * l) * M.ct + ix;
     float2 A, B;
     unpack(buf + l * LS, k_of(tx, ix, M.lct), nx, nxh, A, B);
-    s0[off] = A;
-    s0[off + M.ct] = B;
+    st_spec<NT>(s0 + off, A);
+    st_spec<NT>(s0 + off + M.ct, B);
   }
 }
 
@@ -1080,7 +1098,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
       }
     };
     float2* r = fft_fused<NF, IP>(bufA, bufB, rt, tw, pw);
-    store_pair_spectra<NF>(r, M, W.s0, W.s1, tile);
+    store_pair_spectra<NF, TG>(r, M, W.s0, W.s1, tile);
   } else if constexpr (BM == RM_F1) {
     // eq num-vel: v_i = A_i (A_i v_i - dt/rho_i d/dr_i^+ p)
     const bool first = (n == 0);  // v^{-1/2} = 0
@@ -1134,7 +1152,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     }
     __syncthreads();
     r = fft_any<false, NF, IP>(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
-    store_pair_spectra<NF>(r, M, W.s0, W.s1, tile);
+    store_pair_spectra<NF, TG>(r, M, W.s0, W.s1, tile);
   } else if constexpr (FZ) {
     // RM_FZ instances of the lossy density passes (forward eq num-rho and its
     // transpose) at iterates n >= 1, past the source and the zero initial
@@ -1197,8 +1215,8 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
         }
       };
       float2* r = fft_fused_pairs<NF, IP>(bufA, bufB, rt, tw, inl, outl, pw);
-      store_rowpair_spectra<NF>(r, M, W.s0, tile);
-      store_rowpair_spectra<NF>(r + half * LS, M, W.s1, tile);
+      store_rowpair_spectra<NF, TG>(r, M, W.s0, tile);
+      store_rowpair_spectra<NF, TG>(r + half * LS, M, W.s1, tile);
     } else if constexpr (BM == RM_F2 && row_fusable<NF>() && !TG) {
       // iterates past the source: the update between the two FFTs in
       // registers, rows 2l and 2l+1 of each position together (their S and
@@ -1256,8 +1274,8 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
         }
       };
       float2* r = fft_fused2<NF, IP>(bufA, bufB, rt, tw, inl, outl, pw);
-      store_rowpair_spectra<NF>(r, M, W.s0, tile);
-      store_rowpair_spectra<NF>(r + half * LS, M, W.s1, tile);
+      store_rowpair_spectra<NF, TG>(r, M, W.s0, tile);
+      store_rowpair_spectra<NF, TG>(r + half * LS, M, W.s1, tile);
     } else if constexpr (BM == RM_A2 && row_fusable<NF>() && PAIRS) {
       // the eta / tau lines (rows 2l, 2l+1 packed) in, each row's line out
       const bool first = (n == M.nt - 2);
@@ -1312,7 +1330,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
         }
       };
       float2* r = fft_fused_pairs<NF, IP>(bufA, bufB, rt, tw, inl, outl, pw);
-      store_pair_spectra<NF>(r, M, W.s0, W.s1, tile);
+      store_pair_spectra<NF, TG>(r, M, W.s0, W.s1, tile);
     } else if constexpr (BM == RM_A2 && row_fusable<NF>() && !TG) {
       const bool first = (n == M.nt - 2);
       // the update between the two FFTs in registers: rows 2l and 2l+1 of
@@ -1373,7 +1391,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
         }
       };
       float2* r = fft_fused2<NF, IP>(bufA, bufB, rt, tw, inl, outl, pw);
-      store_pair_spectra<NF>(r, M, W.s0, W.s1, tile);
+      store_pair_spectra<NF, TG>(r, M, W.s0, W.s1, tile);
     }
   } else if constexpr (BM == RM_F2 || BM == RM_F2L) {
     // eq num-rho with the additive source of eq s1 (dt s = p0 / (2 d c^2), d = 2)
@@ -1469,12 +1487,12 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     __syncthreads();
     if constexpr (BM == RM_F2) {
       r = fft_any<false, NF, IP>(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
-      store_rowpair_spectra<NF>(r, M, W.s0, tile);
-      store_rowpair_spectra<NF>(r + (rt / 2) * LS, M, W.s1, tile);
+      store_rowpair_spectra<NF, TG>(r, M, W.s0, tile);
+      store_rowpair_spectra<NF, TG>(r + (rt / 2) * LS, M, W.s1, tile);
     } else {
       if (!(flags & FL_NO_SENSORS)) sensor_partials(M, T, o, y0, W.part, n + 1);
       r = fft_any<false, NF, IP>(o, other(o, bufA, bufB), rt / 2, nx, LS, M.radx, M.nstx, tw);
-      store_rowpair_spectra<NF>(r, M, W.s0, tile);
+      store_rowpair_spectra<NF, TG>(r, M, W.s0, tile);
     }
   } else if constexpr (BM == RM_F3) {
     // eq num-p: p = c^2 (S - eta Y_dis S + tau Y_abs u)
@@ -1536,7 +1554,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     __syncthreads();
     if (!(flags & FL_NO_SENSORS)) sensor_partials(M, T, o, y0, W.part, n + 1);
     r = fft_any<false, NF, IP>(o, other(o, bufA, bufB), rt / 2, nx, LS, M.radx, M.nstx, tw);
-    store_rowpair_spectra<NF>(r, M, W.s0, tile);
+    store_rowpair_spectra<NF, TG>(r, M, W.s0, tile);
   } else if constexpr (BM == RM_A1 || BM == RM_A1L) {
     // transpose of eqs num-m and num-p: p* += M^T r_{n+1}; q = c^2 p*
     const bool first = (n == M.nt - 2);
@@ -1652,11 +1670,11 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     __syncthreads();
     if constexpr (BM == RM_A1) {
       r = fft_any<false, NF, IP>(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
-      store_rowpair_spectra<NF>(r, M, W.s0, tile);
-      store_rowpair_spectra<NF>(r + half * LS, M, W.s1, tile);
+      store_rowpair_spectra<NF, TG>(r, M, W.s0, tile);
+      store_rowpair_spectra<NF, TG>(r + half * LS, M, W.s1, tile);
     } else if (n != -1) {
       r = fft_any<false, NF, IP>(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
-      store_pair_spectra<NF>(r, M, W.s0, W.s1, tile);
+      store_pair_spectra<NF, TG>(r, M, W.s0, W.s1, tile);
     }
   } else if constexpr (BM == RM_A2) {
     // transpose of the mass update and of the Y terms of eq num-p
@@ -1730,7 +1748,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     __syncthreads();
     if (n != -1) {
       r = fft_any<false, NF, IP>(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
-      store_pair_spectra<NF>(r, M, W.s0, W.s1, tile);
+      store_pair_spectra<NF, TG>(r, M, W.s0, W.s1, tile);
     }
   } else if constexpr (BM == RM_A3) {
     // transpose of eq num-vel
@@ -1783,7 +1801,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     }
     __syncthreads();
     r = fft_any<false, NF, IP>(o, other(o, bufA, bufB), rt, nx, LS, M.radx, M.nstx, tw);
-    store_pair_spectra<NF>(r, M, W.s0, W.s1, tile);
+    store_pair_spectra<NF, TG>(r, M, W.s0, W.s1, tile);
   } else if constexpr (BM == RM_FWD1) {
     const float* src = X.in;
     TwRegs TW;
@@ -1806,7 +1824,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     if constexpr (!TG) put_tw(TW, twl, nx);
     __syncthreads();
     float2* r = fft_any<false, NF, IP>(bufA, bufB, rt / 2, nx, LS, M.radx, M.nstx, tw);
-    store_rowpair_spectra<NF>(r, M, W.s0, tile);
+    store_rowpair_spectra<NF, TG>(r, M, W.s0, tile);
   } else if constexpr (BM == RM_INV1) {
     RowPairRegs S0;
     TwRegs TW;
@@ -2384,7 +2402,7 @@ __device__ __forceinline__ void col_fused(const Medium& M, const Work& W, int ti
     stage_regs<R1, NB1, OFFL>(v, j, twr);
     float2* dst = (f ? W.s1 : W.s0) + elem(j, c);
 #pragma unroll
-    for (int rr = 0; rr < R1; ++rr) dst[rr * step1] = cconj(v[rr]);
+    for (int rr = 0; rr < R1; ++rr) st_spec<TG>(dst + rr * step1, cconj(v[rr]));
   }
 }
 
