@@ -29,7 +29,7 @@ import sys
 
 HERE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1810_11685_amd")
 
-# kernel-name fragments of the pass kinds (row kernels by mode, template arg U)
+# kernel-name fragments of the pass kinds (row kernels by mode without its modifier bits, template arg U)
 ROW_MODES = {0: "fwd_row_velocity", 1: "fwd_row_density", 2: "fwd_row_density", 3: "fwd_row_pressure",
              4: "adj_row_pressure", 5: "adj_row_pressure", 6: "adj_row_density", 7: "adj_row_velocity"}
 
@@ -65,6 +65,7 @@ def pass_of(name: str):
         return COL_MODES.get(mode, f"col_mode_{mode}")
     if "row_kernel<" in name:
         mode = int(name.split("row_kernel<")[1].split(",")[0].split(">")[0])
+        mode &= ~(16 | 32)  # modifiers: sensitivity store (16), fused-only density instance (32)
         return ROW_MODES.get(mode, f"row_mode_{mode}")
     return None
 
@@ -107,16 +108,21 @@ def pmc_summary(dfetch, dwrite, dcf, dcw, copy_mib, out):
     sf = expected_kib / copy_val(cf) if copy_val(cf) else None
     sw = expected_kib / copy_val(cw) if copy_val(cw) else None
     per = {}
-    for name in set(fetch) | set(write):
+    vals = {}
+    for name in sorted(set(fetch) | set(write)):
         p = pass_of(name)
         if p is None:
             continue
-        f = fetch.get(name, [])
-        w = write.get(name, [])
-        fk = sum(f) / len(f) if f else None
-        wk = sum(w) / len(w) if w else None
-        e = per.setdefault(p, {"kernels": []})
-        e["kernels"].append(name[:80])
+        v = vals.setdefault(p, {"f": [], "w": []})
+        v["f"] += fetch.get(name, [])
+        v["w"] += write.get(name, [])
+        per.setdefault(p, {"kernels": []})["kernels"].append(name[:80])
+    for p, v in vals.items():
+        # a pass kind may run as several instances (first iterates apart):
+        # averages over all its dispatches
+        fk = sum(v["f"]) / len(v["f"]) if v["f"] else None
+        wk = sum(v["w"]) / len(v["w"]) if v["w"] else None
+        e = per[p]
         e["fetch_KiB_per_launch"] = fk
         e["write_KiB_per_launch"] = wk
         if fk is not None and wk is not None and sf and sw:
