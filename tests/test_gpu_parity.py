@@ -366,6 +366,22 @@ def test_mixed_batch_matches_fused_single_plans(q):
         assert np.array_equal(N(g), gref)
 
 
+def test_batch_of_16_at_128_matches_single_calls(q):
+    """128^2 with 16 vectors per launch is a many-block launch: its density
+    passes fuse the FFTs' boundary stage with two rows per work item (the
+    radix-4 boundary form); one vector per launch takes the unfused passes.
+    Each vector of the batch equals its single call bit for bit."""
+    import torch
+    prm, c0, rho0, p0 = problem(128, 128, 24, seed=31, ns=32)
+    plan = q.Plan(prm, c0, rho0)
+    plan.set_tiles(2, 1, 64, 64)  # 64 row blocks per vector: 16 vectors are 1024 blocks, one vector 64
+    vs = torch.stack([T(p0)] + [T(qi.gaussian_field((128, 128), 40 + j)) for j in range(15)])
+    d16, g16 = N(plan.forward(vs)), N(plan.jtjv(vs))
+    for j in (0, 7, 15):
+        assert np.array_equal(N(plan.forward(vs[j])), d16[j])
+        assert np.array_equal(N(plan.jtjv(vs[j])), g16[j])
+
+
 def test_uneven_batch_tuner(q):
     """qpat_batch_tune picks launch shapes per grid size and a schedule; the
     results stay those of the single plans."""
