@@ -775,7 +775,6 @@ __device__ __forceinline__ float rowpair_val(const float2* buf, int j, int x, in
 // a block; the taps themselves are fetched after the first barrier (thread i
 // holds tap e0 + i, blockDim.x >= kTapCap) and written to LDS only where the
 // sensors are used, so their latency hides behind the first FFT.
-constexpr int kConRegs = 4;  // scatter contributions of a node held in registers
 
 struct TapStage {
   Tap* tl;     // [kTapCap]
@@ -800,15 +799,18 @@ __device__ __forceinline__ void taps_range(TapStage& T, const Medium& M, void* b
   }
 }
 
-// Adjoint: this thread's scatter node and its first contributions (issued
-// early, consumed after the inverse FFT).
+// Adjoint: this thread's scatter node and its first contributions, one record
+// (issued early, consumed after the inverse FFT).
 __device__ __forceinline__ void nodes_fetch(TapStage& T, const Medium& M) {
   const int i = threadIdx.x;
   if (i < T.n1 - T.n0) {
-    T.nd = M.nodes[T.n0 + i];
-#pragma unroll
-    for (int k = 0; k < kConRegs; ++k)
-      if (T.nd.z + k < T.nd.w) T.con[k] = M.scon[T.nd.z + k];
+    const int4* rec = M.nodes + 2 * (T.n0 + i);
+    T.nd = rec[0];
+    const int4 c = rec[1];
+    T.con[0] = c.x;
+    T.con[1] = c.y;
+    T.con[2] = c.z;
+    T.con[3] = c.w;
   }
 }
 
@@ -878,7 +880,7 @@ __device__ __forceinline__ void sensor_scatter(const Medium& M, const TapStage& 
   const int nn = T.n1 - T.n0;
   for (int i = threadIdx.x; i < nn; i += blockDim.x) {
     const bool pre = i == int(threadIdx.x);  // the first round's node was fetched early
-    const int4 nd = pre ? T.nd : M.nodes[T.n0 + i];
+    const int4 nd = pre ? T.nd : M.nodes[2 * (T.n0 + i)];
     float& v = pcomp(buf, nd.x - y0, nd.y, M.nx);
     float acc = v;
 #pragma unroll

@@ -613,7 +613,7 @@ void build_scatter(const qpat_params& p, const std::vector<Tap>& taps, const std
   scon.clear();
   noff.assign(p.ny + 1, 0);
   for (int y = 0; y < p.ny; ++y) {
-    noff[y] = int(nodes.size());
+    noff[y] = int(nodes.size() / 2);  // offsets count records (two int4 each)
     std::map<int, std::vector<int>> byx;   // x -> contributions in tap order
     for (int e = toff[y]; e < toff[y + 1]; ++e) {
       byx[taps[e].ixl].push_back(e << 1);
@@ -622,10 +622,16 @@ void build_scatter(const qpat_params& p, const std::vector<Tap>& taps, const std
     for (const auto& kv : byx) {
       const int c0 = int(scon.size());
       for (int c : kv.second) scon.push_back(c);
-      nodes.push_back(make_int4(y, kv.first, c0, int(scon.size())));
+      const int c1 = int(scon.size());
+      // the record: (y, x, c0, c1), then the first kConRegs contributions
+      // inline (the kernel reads them with the record, not after it)
+      nodes.push_back(make_int4(y, kv.first, c0, c1));
+      int in[kConRegs] = {0, 0, 0, 0};
+      for (int k = 0; k < kConRegs && c0 + k < c1; ++k) in[k] = scon[c0 + k];
+      nodes.push_back(make_int4(in[0], in[1], in[2], in[3]));
     }
   }
-  noff[p.ny] = int(nodes.size());
+  noff[p.ny] = int(nodes.size() / 2);
 }
 
 // Carve aligned sub-buffers out of one allocation.
@@ -761,7 +767,7 @@ qpat_status plan_build(qpat_plan P, const double* c0, const double* rho0) {
   std::vector<int> snoff, scon;
   build_scatter(p, taps, toff, snodes, snoff, scon);
   if (taps.empty()) taps.push_back(Tap{});
-  if (snodes.empty()) snodes.push_back(make_int4(0, 0, 0, 0));
+  if (snodes.empty()) snodes.assign(2, make_int4(0, 0, 0, 0));
   if (scon.empty()) scon.push_back(0);
 
   // ---- upload (host checks are done; from here on a device is needed)

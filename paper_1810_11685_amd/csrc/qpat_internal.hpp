@@ -14,6 +14,7 @@ constexpr int kMaxThreads = 512;  // maximum threads per block of a row / column
 constexpr size_t kMaxLds = 163840;  // gfx950: LDS bytes available to one work-group
 constexpr int kMaxPer = 8;    // pointwise elements per thread held in registers
 constexpr int kColPer = 4;    // spectrum elements of one field per thread in a column pass
+constexpr int kConRegs = 4;   // adjoint scatter: contributions of a node held inline in its record
 constexpr int kTapCap = 64;   // sensor taps of one row tile staged in LDS
 constexpr int kXcds = 8;      // MI355X: 8 XCDs, work-groups dispatched round-robin
 
@@ -46,8 +47,9 @@ struct Medium {
   const int* tap_off;                                 // [ny+1] CSR offsets into taps
   const Tap* taps;
   // Adjoint scatter M^T r as a gather per grid node: node_off [ny+1] CSR
-  // offsets into nodes (y, x, c0, c1), whose contributions scon[c0..c1) are
-  // (tap index << 1 | right weight), in increasing tap index.
+  // offsets (in records) into nodes, two int4 per node: (y, x, c0, c1) and the
+  // first kConRegs of its contributions scon[c0..c1) (tap index << 1 | right
+  // weight, in increasing tap index; zero-padded).
   const int* node_off;
   const int4* nodes;
   const int* scon;
