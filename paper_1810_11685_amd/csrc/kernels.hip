@@ -1160,11 +1160,11 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     // transpose) at iterates n >= 1, past the source and the zero initial
     // state: only the fused path is compiled, so the first iterates' code does
     // not set these kernels' register count.  The host launches them only for
-    // compile-time lengths whose plan fuses.  Work item (l, sd, jj): row
-    // 2l + sd at butterfly jj, the two rows of a pair in adjacent lanes.
-    // plans whose boundary stage has radix 8 hold one row per work item (rows
-    // 2l, 2l+1 in adjacent lanes); radix-4 ones (1024, 128) two rows per work
-    // item, which is faster there but only where the twiddles sit in LDS
+    // compile-time lengths whose plan fuses (kernels_row_fused).  Plans whose
+    // boundary stage has radix 8 (256, 512) hold one row per work item, the
+    // rows 2l and 2l+1 of a pair in adjacent lanes (fft_fused_pairs); radix-4
+    // ones (128, 1024) two rows per work item (fft_fused2), which is faster
+    // there, and only where the twiddles sit in LDS.
     constexpr bool PAIRS = plan_radix(NF > 0 ? NF : 8, 0) > 4;
     if constexpr (BM == RM_F2 && row_fusable<NF>() && PAIRS) {
       // each row's inverse line in, S and u lines (rows 2l, 2l+1 packed) out
