@@ -473,6 +473,12 @@ __device__ __forceinline__ float2* fft_fused2(float2* a, float2* b, int nlines, 
   else return fft_stages<N, false, LS, 1, NST, R>(o, r, nlines, tw);
 }
 
+// First thread index of this thread's wavefront as a scalar, so that tests on
+// it compile to scalar branches: a wave whose lanes have no work item skips a
+// fused section (and its operand loads) as a whole, while the lanes of a wave
+// with work stay together for the lane exchanges.
+__device__ __forceinline__ unsigned wave_base() { return __builtin_amdgcn_readfirstlane(threadIdx.x) & ~63u; }
+
 // The value x of the adjacent lane (lane ^ 1): a DPP quad permutation
 // [1, 0, 3, 2], a VALU move (no LDS round trip).  Both lanes of a pair must
 // be active.
@@ -514,7 +520,7 @@ __device__ __forceinline__ float2* fft_fused_pairs(float2* a, float2* b, int nli
   if constexpr (IP) __syncthreads();
 #pragma unroll
   for (int i = 0; i < MB; ++i) {
-    if (i * blockDim.x < total) {  // block-uniform: the shuffles see whole waves
+    if (wave_base() + i * blockDim.x < total) {  // wave-uniform: the exchanges see whole waves
       const unsigned it = threadIdx.x + i * blockDim.x;
       const unsigned p = it >> 1, sd = it & 1u, l = p / NB, jj = p % NB;
       const bool active = it < total;
@@ -1060,7 +1066,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
     if constexpr (!TG) fetch_tw(TW, M.twx, nx);
 #pragma unroll
     for (int i = 0; i < MB; ++i) {
-      if (i * B < rt * NB) {
+      if (wave_base() + i * B < rt * NB) {
         const unsigned it = min(unsigned(threadIdx.x + i * B), unsigned(rt * NB) - 1u);
         const int j = int(it / NB), jj = int(it % NB), y = y0 + j;
         const unsigned base = rowoff(y) + jj;
@@ -1177,7 +1183,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
       if constexpr (!TG) fetch_tw(TW, M.twx, nx);
 #pragma unroll
       for (int i = 0; i < MB; ++i) {
-        if (i * B < rt * NB) {
+        if (wave_base() + i * B < rt * NB) {
           const unsigned it = min(unsigned(threadIdx.x + i * B), unsigned(rt * NB) - 1u);
           const unsigned p = it >> 1, l = p / NB, jj = p % NB;
           const int y = y0 + 2 * int(l) + int(it & 1u);
@@ -1233,7 +1239,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
       if constexpr (!TG) fetch_tw(TW, M.twx, nx);
 #pragma unroll
       for (int i = 0; i < MB; ++i) {
-        if (i * B < half * NB) {
+        if (wave_base() + i * B < half * NB) {
           const unsigned it = min(unsigned(threadIdx.x + i * B), unsigned(half * NB) - 1u);
           const int l = int(it / NB), jj = int(it % NB), ya = y0 + 2 * l;
           const unsigned ba = rowoff(ya) + jj, bb = ba + nx;
@@ -1291,7 +1297,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
       if constexpr (!TG) fetch_tw(TW, M.twx, nx);
 #pragma unroll
       for (int i = 0; i < MB; ++i) {
-        if (i * B < rt * NB) {
+        if (wave_base() + i * B < rt * NB) {
           const unsigned it = min(unsigned(threadIdx.x + i * B), unsigned(rt * NB) - 1u);
           const unsigned p = it >> 1, l = p / NB, jj = p % NB;
           const int y = y0 + 2 * int(l) + int(it & 1u);
@@ -1348,7 +1354,7 @@ row_kernel(const Launch L, int ntile, int chunk, int n, int flags) {
       if constexpr (!TG) fetch_tw(TW, M.twx, nx);
 #pragma unroll
       for (int i = 0; i < MB; ++i) {
-        if (i * B < half * NB) {
+        if (wave_base() + i * B < half * NB) {
           const unsigned it = min(unsigned(threadIdx.x + i * B), unsigned(half * NB) - 1u);
           const int l = int(it / NB), jj = int(it % NB), y = y0 + 2 * l;
           const unsigned ba = rowoff(y) + jj, bb = ba + nx;
