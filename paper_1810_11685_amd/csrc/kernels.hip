@@ -2273,7 +2273,7 @@ __device__ __forceinline__ void col_fused(const Medium& M, const Work& W, int ti
   float2 v1[kQ][R1];
 #pragma unroll
   for (int i = 0; i < kQ; ++i) {
-    if (i * B < int(nq)) {
+    if (wave_base() + i * B < nq) {
       const unsigned q = min(unsigned(tid + i * B), nq - 1);
       const unsigned l = q / NB1, j = q % NB1, f = l >> lct, c = l & (ct - 1);
       const float2* src = (f ? W.s1 : W.s0) + elem(j, c);
@@ -2292,7 +2292,7 @@ __device__ __forceinline__ void col_fused(const Medium& M, const Work& W, int ti
   float2 msy[kP][RS], msx[kP];
 #pragma unroll
   for (int i = 0; i < kP; ++i) {
-    if (i * B < int(np)) {
+    if (wave_base() + i * B < np) {
       const unsigned pp = min(unsigned(tid + i * B), np - 1);
       const unsigned c = pp / NBS, j = pp % NBS, kx = c0 + c;
       const unsigned t0 = mul24(kx, N) + j;
