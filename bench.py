@@ -102,7 +102,7 @@ def log(*a):
 
 def kernel_hash() -> str:
     h = hashlib.sha256()
-    for f in ("kernels.hip", "qpat_internal.hpp"):
+    for f in ("kernels.hip", "qpat_internal.hpp", "plan.cpp"):   # plan.cpp fixes the spectrum layout
         with open(os.path.join(ROOT, "paper_1810_11685_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

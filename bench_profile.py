@@ -36,7 +36,7 @@ ROW_MODES = {0: "fwd_row_velocity", 1: "fwd_row_density", 2: "fwd_row_density", 
 
 def kernel_hash() -> str:
     h = hashlib.sha256()
-    for f in ("kernels.hip", "qpat_internal.hpp"):
+    for f in ("kernels.hip", "qpat_internal.hpp", "plan.cpp"):   # plan.cpp fixes the spectrum layout
         with open(os.path.join(HERE, "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

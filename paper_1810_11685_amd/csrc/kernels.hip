@@ -631,18 +631,35 @@ __device__ __forceinline__ int row_len(const Medium& M) { return NF > 0 ? NF : M
 template <int NF>
 __device__ __forceinline__ int row_half(const Medium& M) { return NF > 0 ? NF / 2 : M.nxh; }
 
+// Spectra are stored in tiles of srt rows x ct columns (row tiles of srt
+// rows one after another, the column tiles of one row tile one after another,
+// each tile row-major).  A row block's rt rows (srt a multiple of rt) are rows
+// r0 .. r0 + rt - 1 of one storage row tile.  The block enumerates its
+// elements p in the order of an rt x ct tiling (column tile major); element p
+// sits at spec_row_base + spec_row_off(p).  With srt = rt that is base + p.
+template <int NF>
+__device__ __forceinline__ unsigned spec_row_base(const Medium& M, int tile) {
+  const unsigned y0 = unsigned(tile) << M.lrt;
+  return mul24(y0 >> M.lsrt, unsigned(M.srt * row_half<NF>(M))) + ((y0 & unsigned(M.srt - 1)) << M.lct);
+}
+__device__ __forceinline__ unsigned spec_row_off(const Medium& M, unsigned p) {
+  const int s = M.lrt + M.lct;
+  return ((p >> s) << (M.lsrt + M.lct)) + (p & ((1u << s) - 1u));
+}
+
 // line j <- rows j of the row tile (s0, s1)
 template <int NF>
 __device__ __forceinline__ void fetch_pair(PairRegs& R, const Medium& M, const float2* __restrict__ s0,
                                            const float2* __restrict__ s1, int tile) {
   const int tot = M.rt * row_half<NF>(M);
-  const unsigned base = mul24(tile, tot);
+  const unsigned base = spec_row_base<NF>(M, tile);
 #pragma unroll
   for (int k = 0; k < kPairIt; ++k) {
     const int p = threadIdx.x + k * blockDim.x;
     if (p < tot) {
-      R.a[k] = s0[base + p];
-      R.b[k] = s1[base + p];
+      const unsigned o = base + spec_row_off(M, p);
+      R.a[k] = s0[o];
+      R.b[k] = s1[o];
     }
   }
 }
@@ -665,14 +682,14 @@ template <int NF>
 __device__ __forceinline__ void fetch_rowpair(RowPairRegs& R, const Medium& M, const float2* __restrict__ s0,
                                               int tile) {
   const int nxh = row_half<NF>(M), hc = (M.rt >> 1) * M.ct, tot = (M.rt >> 1) * nxh;
-  const unsigned base = mul24(tile, M.rt * nxh);
+  const unsigned base = spec_row_base<NF>(M, tile);
 #pragma unroll
   for (int k = 0; k < kRowPairIt; ++k) {
     const int q = threadIdx.x + k * blockDim.x;
     if (q < tot) {
       const int tx = q >> (M.lrt - 1 + M.lct), w2 = q & (hc - 1);
       const int l = w2 >> M.lct, ix = w2 & (M.ct - 1);
-      const unsigned off = base + (unsigned(tx) << (M.lrt + M.lct)) + (2 * l) * M.ct + ix;
+      const unsigned off = base + (unsigned(tx) << (M.lsrt + M.lct)) + (2 * l) * M.ct + ix;
       R.a[k] = s0[off];
       R.b[k] = s0[off + M.ct];
     }
@@ -734,15 +751,16 @@ template <int NF, bool NT = false>
 __device__ __forceinline__ void store_pair_spectra(const float2* buf, const Medium& M, float2* __restrict__ s0,
                                                    float2* __restrict__ s1, int tile) {
   const int nx = row_len<NF>(M), nxh = row_half<NF>(M), LS = lstride(nx), rc = M.rt * M.ct;
-  const unsigned base = mul24(tile, M.rt * nxh);
+  const unsigned base = spec_row_base<NF>(M, tile);
 #pragma unroll 4
   for (int p = threadIdx.x; p < M.rt * nxh; p += blockDim.x) {
     const int w = p & (rc - 1);
     const int j = w >> M.lct, k = ((p >> (M.lrt + M.lct)) << M.lct) + (w & (M.ct - 1));
     float2 A, B;
     unpack(buf + j * LS, k, nx, nxh, A, B);
-    st_spec<NT>(s0 + base + p, A);
-    st_spec<NT>(s1 + base + p, B);
+    const unsigned o = base + spec_row_off(M, p);
+    st_spec<NT>(s0 + o, A);
+    st_spec<NT>(s1 + o, B);
   }
 }
 
@@ -750,12 +768,12 @@ template <int NF, bool NT = false>
 __device__ __forceinline__ void store_rowpair_spectra(const float2* buf, const Medium& M, float2* __restrict__ s0,
                                                       int tile) {
   const int nx = row_len<NF>(M), nxh = row_half<NF>(M), LS = lstride(nx), hc = (M.rt >> 1) * M.ct;
-  const unsigned base = mul24(tile, M.rt * nxh);
+  const unsigned base = spec_row_base<NF>(M, tile);
 #pragma unroll 4
   for (int q = threadIdx.x; q < (M.rt >> 1) * nxh; q += blockDim.x) {
     const int tx = q >> (M.lrt - 1 + M.lct), w2 = q & (hc - 1);
     const int l = w2 >> M.lct, ix = w2 & (M.ct - 1);
-    const unsigned off = base + (unsigned(tx) << (M.lrt + M.lct)) + (2 * l) * M.ct + ix;
+    const unsigned off = base + (unsigned(tx) << (M.lsrt + M.lct)) + (2 * l) * M.ct + ix;
     float2 A, B;
     unpack(buf + l * LS, k_of(tx, ix, M.lct), nx, nxh, A, B);
     st_spec<NT>(s0 + off, A);
@@ -956,6 +974,7 @@ __device__ __forceinline__ void row_args_batch(const Launch& L, int ntile, int c
   const Work& w = L.w0;
   asm volatile("" ::"s"(ntile), "s"(chunk), "s"(n), "s"(flags), "s"(L.nitems), "s"(L.wstride), "s"(m.nx),
                "s"(m.nxh), "s"(m.nt), "s"(m.rt), "s"(m.ct), "s"(m.lrt), "s"(m.lct), "s"(m.twx), "s"(blockDim.x));
+  asm volatile("" ::"s"(m.srt), "s"(m.lsrt));
   if constexpr (BM == RM_F1 || BM == RM_A3) {
     asm volatile("" ::"s"(w.s0), "s"(w.s1), "s"(w.f0), "s"(w.f1), "s"(m.bx), "s"(m.by), "s"(m.avx), "s"(m.avy));
   } else if constexpr (BM == RM_F2 || BM == RM_F2L) {
@@ -981,7 +1000,7 @@ template <int CM>
 __device__ __forceinline__ void col_args_batch(const Launch& L, int ntile, int chunk, int n) {
   const Medium& m = L.m;
   asm volatile("" ::"s"(ntile), "s"(chunk), "s"(n), "s"(L.nitems), "s"(L.wstride), "s"(m.ny), "s"(m.nxh),
-               "s"(m.nt), "s"(m.rt), "s"(m.ct), "s"(m.lrt), "s"(m.lct), "s"(L.w0.s0), "s"(L.w0.s1), "s"(m.twy),
+               "s"(m.nt), "s"(m.srt), "s"(m.ct), "s"(m.lsrt), "s"(m.lct), "s"(L.w0.s0), "s"(L.w0.s1), "s"(m.twy),
                "s"(m.twyr), "s"(blockDim.x));
   if constexpr (CM == CM_FRAC) {
     asm volatile("" ::"s"(m.ldis), "s"(m.labs));
@@ -1912,15 +1931,15 @@ __device__ __forceinline__ void col_generic(const Medium& M, const Work& W, int 
   const float2* symx = xcode == MC_DXP ? M.dxp : M.dxm;
   const float2* symy = ycode == MC_DYP ? M.dyp : M.dym;
   // load phase: the tile (transposed into lines), twiddles, multiplier values
-  // memory order: field, tile row ty, element (iy, c) of the rt x ct tile
+  // memory order: field, tile row ty, element (iy, c) of the srt x ct tile
   const float rny = 1.0f / static_cast<float>(ny);
-  const int rc = M.rt * ct;
+  const int rc = M.srt * ct;
   // (a tile holds nin*ct*ny <= nin*kColPer*B elements: all loads are issued
   // into registers before the first LDS write)
   constexpr int kIt = nin * kColPer;
   const unsigned ncol = unsigned(ct) * ny, ntot = nin * ncol;     // elements per field / tile
-  const unsigned rowstep = unsigned(nxh) * M.rt, tbase = unsigned(tile) * rc;  // tile row ty at ty * rowstep
-  const int lsh = M.lrt + M.lct;
+  const unsigned rowstep = unsigned(nxh) * M.srt, tbase = unsigned(tile) * rc;  // tile row ty at ty * rowstep
+  const int lsh = M.lsrt + M.lct;
   float2 tv[kIt];
 #pragma unroll
   for (int k = 0; k < kIt; ++k) {
@@ -1959,7 +1978,7 @@ __device__ __forceinline__ void col_generic(const Medium& M, const Work& W, int 
     if (it < ntot) {
       const bool f = it >= ncol;
       const unsigned rem = f ? it - ncol : it, w = rem & (rc - 1);
-      const unsigned ky = ((rem >> lsh) << M.lrt) + (w >> M.lct), c = w & (ct - 1);
+      const unsigned ky = ((rem >> lsh) << M.lsrt) + (w >> M.lct), c = w & (ct - 1);
       bufA[mul24((f ? ct : 0) + c, ls) + px(ky)] = tv[k];
     }
   }
@@ -2029,7 +2048,7 @@ __device__ __forceinline__ void col_generic(const Medium& M, const Work& W, int 
   for (unsigned it = threadIdx.x; it < nout * ncol; it += B) {
     const bool f = it >= ncol;
     const unsigned rem = f ? it - ncol : it, w = rem & (rc - 1), ty = rem >> lsh;
-    const unsigned ky = (ty << M.lrt) + (w >> M.lct), c = w & (ct - 1);
+    const unsigned ky = (ty << M.lsrt) + (w >> M.lct), c = w & (ct - 1);
     (f ? W.s1 : W.s0)[mul24(ty, rowstep) + tbase + w] = cconj(r[mul24((f ? ct : 0) + c, ls) + px(ky)]);
   }
 }
@@ -2243,7 +2262,7 @@ __device__ __forceinline__ void col_fused(const Medium& M, const Work& W, int ti
   constexpr int OFFL = NB1 - RS;  // twiddles of the last inverse stage (Ns = NB1)
   constexpr int kQ = (nin * kColPer + R1 - 1) / R1;  // first-stage butterflies per thread (bound)
   constexpr int kP = (kColPer + RS - 1) / RS;         // middle butterflies per thread (bound)
-  const int nxh = M.nxh, ct = M.ct, c0 = tile * ct, B = blockDim.x, lct = M.lct, lrt = M.lrt;
+  const int nxh = M.nxh, ct = M.ct, c0 = tile * ct, B = blockDim.x, lct = M.lct, lsrt = M.lsrt;
   const int tid = threadIdx.x;
   float2* bufA = lds;
   float2* bufB = IP ? lds : lds + 2 * ct * LS;
@@ -2262,11 +2281,11 @@ __device__ __forceinline__ void col_fused(const Medium& M, const Work& W, int ti
   const float* tabA = frac ? M.ldis : M.kap;
   const float2* symx = xcode == MC_DXP ? M.dxp : M.dxm;
   const float2* symy = ycode == MC_DYP ? M.dyp : M.dym;
-  // element ky of column c of the tile: (ky / rt) rowstep + tbase + (ky mod rt) ct + c;
-  // inputs r and r + 1 of a first-stage butterfly are step1 apart (rt divides NB1)
-  const unsigned rowstep = unsigned(nxh) * M.rt, tbase = unsigned(tile) * (M.rt * ct);
-  const unsigned step1 = mul24(NB1 >> lrt, rowstep);
-  auto elem = [&](unsigned j, unsigned c) { return mul24(j >> lrt, rowstep) + tbase + ((j & (M.rt - 1)) << lct) + c; };
+  // element ky of column c of the tile: (ky / srt) rowstep + tbase + (ky mod srt) ct + c;
+  // inputs r and r + 1 of a first-stage butterfly are step1 apart (srt divides NB1)
+  const unsigned rowstep = unsigned(nxh) * M.srt, tbase = unsigned(tile) * (M.srt * ct);
+  const unsigned step1 = mul24(NB1 >> lsrt, rowstep);
+  auto elem = [&](unsigned j, unsigned c) { return mul24(j >> lsrt, rowstep) + tbase + ((j & (M.srt - 1)) << lct) + c; };
 
   // ---- load phase: first-stage inputs, both twiddle tables, middle multipliers
   const unsigned nq = unsigned(nin * ct) * NB1;
@@ -2435,7 +2454,7 @@ col_kernel(const Launch L, int ntile, int chunk, int mcode_arg, int n) {
   } else {
 #define QPAT_COL_CASE(N)                                                 \
   case N:                                                                \
-    if ((N / radix_of<N, false>(0)) % M.rt == 0) {                       \
+    if ((N / radix_of<N, false>(0)) % M.srt == 0) {                      \
       col_fused<CM, N, TG>(M, W, tile, mcode, lds);                      \
       return;                                                            \
     }                                                                    \

@@ -159,6 +159,22 @@ bool col_tile_ok(int nxh, int ny, int ct, int thr) {
          threads_ok(thr) && ct * ny <= kColPer * thr;
 }
 
+// Rows of the spectrum's storage tiles for row tiles of rt rows: at least
+// kStorageRows where the grid allows it (a power of two, a multiple of rt,
+// dividing ny and the first-stage stride of the fused column pass).  Row
+// blocks of two rows then write 16-byte pieces of 32-byte tile rows, and
+// column blocks read 32-byte runs instead of 16-byte ones.  Measured
+// (1024^2 x 8, tiles 2,1,256,512): column passes 251 -> 208 us per iterate
+// pair, row passes 307 -> 317 us; 8 or 16 rows cost the row passes more than
+// the column passes gain.
+constexpr int kStorageRows = 4;
+int storage_rows(int ny, int rt) {
+  const bool fused_cols = ny >= 128 && (ny & (ny - 1)) == 0;
+  int s = rt;
+  while (2 * s <= kStorageRows && ny % (2 * s) == 0 && (!fused_cols || 2 * s <= ny / 8)) s *= 2;
+  return s;
+}
+
 // Defaults: small tiles (many blocks) with enough threads to keep every
 // thread busy in the radix-8 stages.
 void default_tiles(int nx, int ny, int* rt, int* ct, int* rthr, int* cthr) {
@@ -287,7 +303,7 @@ qpat_status exec_build(Exec& E, const std::vector<Item>& items) {
     for (int i = 0; i < ni && u; ++i) {
       const Medium& m = items[i].m;
       u = m.c2 == m0.c2 && m.nx == m0.nx && m.ny == m0.ny && m.nt == m0.nt && m.rt == m0.rt &&
-          m.ct == m0.ct && m.rthr == m0.rthr && m.cthr == m0.cthr;
+          m.srt == m0.srt && m.ct == m0.ct && m.rthr == m0.rthr && m.cthr == m0.cthr;
       const Work& w = items[i].w;
       const Work& w0 = items[0].w;
       auto d = [&](const void* a, const void* b) { return (long long)((const char*)a - (const char*)b); };
@@ -864,6 +880,8 @@ qpat_status plan_build(qpat_plan P, const double* c0, const double* rho0) {
   M.cthr = P->cthr;
   M.lrt = ilog2(P->rt);
   M.lct = ilog2(P->ct);
+  M.srt = storage_rows(ny, P->rt);
+  M.lsrt = ilog2(M.srt);
   return QPAT_OK;
 }
 
@@ -1037,6 +1055,8 @@ qpat_status set_tiles(qpat_plan P, int rt, int ct, int rthr, int cthr) {
     P->ct = P->med.ct = ct;
     P->med.lrt = ilog2(rt);
     P->med.lct = ilog2(ct);
+    P->med.srt = storage_rows(P->prm.ny, rt);
+    P->med.lsrt = ilog2(P->med.srt);
     P->rthr = P->med.rthr = rthr;
     P->cthr = P->med.cthr = cthr;
     HIPCHK(hipDeviceSynchronize());

@@ -33,7 +33,8 @@ struct Medium {
   float dt;
   float ypow;             // power-law exponent y of the absorption
   int rt, ct;             // rows per row-pass tile, spectrum columns per column-pass tile
-  int lrt, lct;           // log2(rt), log2(ct); spectra are stored in rt x ct tiles
+  int lrt, lct;           // log2(rt), log2(ct)
+  int srt, lsrt;          // spectra are stored in srt x ct tiles (srt a multiple of rt); log2(srt)
   int rthr, cthr;         // threads per block of the row / column passes
   uint32_t radx, rady;    // radix plans (max radix 8), 4 bits per stage, first stage lowest
   int nstx, nsty;
