@@ -194,8 +194,9 @@ qpat_status qpat_medium_grad(qpat_plan plan, const float* p0, const float* res, 
  * iterates and the 16 adjoint iterates that undo them (every pass kind of a
  * forward + adjoint pair), launched the way the plan's calls launch them
  * (captured and replayed as a hipGraph when graph mode is on; the stream is
- * synchronised); the three fastest are then timed again over 48 + 48
- * iterates.  Results are cached per (nx, ny, batch, lossy, graph mode)
+ * synchronised); the three fastest are then timed again, each over the same
+ * number of iterates each way: 48, or more where 16 took under ~7 ms, so that
+ * each timing covers ~20 ms of work (at most 4096, and at most nt - 2).  Results are cached per (nx, ny, batch, lossy, graph mode)
  * in the file named by QPAT_TUNE_CACHE, if set, one line
  * "nx ny batch lossy graph rows cols row_threads col_threads" per shape; a
  * plan whose key is in the file takes that shape without timing.  row_threads / col_threads may be NULL in

@@ -1519,7 +1519,9 @@ qpat_status qpat_tune(qpat_plan P, int32_t batch, qpat_stream stream) {
       }
     }
   // the sweeps' short runs separate shapes only to a few percent: the three
-  // fastest distinct shapes are timed again over three times the iterates
+  // fastest distinct shapes are timed again over at least three times the
+  // iterates and at least ~20 ms of work each (at 512^2, one vector, 48
+  // iterates are 3.5 ms, too short to order shapes 0.7% apart)
   std::sort(seen.begin(), seen.end(), [](const Cand& a, const Cand& b) { return a.ms < b.ms; });
   std::vector<Cand> top;
   for (const Cand& c : seen) {
@@ -1529,10 +1531,12 @@ qpat_status qpat_tune(qpat_plan P, int32_t batch, qpat_stream stream) {
     if (top.size() == 3) break;
   }
   best = INFINITY;
+  const float ms0 = top.empty() ? 0.f : top[0].ms;
+  const int steps2 = ms0 > 0.f ? std::max(3 * steps, int(std::min(4096.f, std::ceil(steps * 20.f / ms0)))) : 3 * steps;
   for (const Cand& c : top) {
     STCHK(set_tiles(P, c.rt, c.ct, c.rh, c.ch));
     float ms;
-    STCHK(time_pair(P, batch, 3 * steps, st, &ms));
+    STCHK(time_pair(P, batch, steps2, st, &ms));
     if (ms < best) {
       best = ms;
       brt = c.rt;
