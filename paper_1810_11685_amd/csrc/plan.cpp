@@ -161,9 +161,10 @@ bool col_tile_ok(int nxh, int ny, int ct, int thr) {
 
 // Rows of the spectrum's storage tiles for row tiles of rt rows: at least
 // kStorageRows where the grid allows it (a power of two, a multiple of rt,
-// dividing ny and the first-stage stride of the fused column pass).  Row
-// blocks of two rows then write 16-byte pieces of 32-byte tile rows, and
-// column blocks read 32-byte runs instead of 16-byte ones.  Measured
+// dividing ny and the first-stage stride of the fused column pass).  At one
+// column per tile, row blocks of two rows then write and read 16-byte halves
+// of 32-byte tiles, and column blocks read 32-byte runs instead of 16-byte
+// ones.  Measured
 // (1024^2 x 8, tiles 2,1,256,512): column passes 251 -> 208 us per iterate
 // pair, row passes 307 -> 317 us; 8 or 16 rows cost the row passes more than
 // the column passes gain.

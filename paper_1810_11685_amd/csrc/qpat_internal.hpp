@@ -60,7 +60,7 @@ struct Medium {
 struct Work {
   float *f0, *f1, *f2, *f3;   // forward: v_x v_y rho_x rho_y;  adjoint: their adjoints
   float* q;                   // forward: p snapshot (checkpoints); adjoint: q = c^2 p*
-  float2 *s0, *s1;            // half spectra, ny x nx/2 in rt x ct tiles (DC / Nyquist packed in column 0)
+  float2 *s0, *s1;            // half spectra, ny x nx/2 in srt x ct tiles (DC / Nyquist packed in column 0)
   float* part;                // forward: sensor partials [nt][ns][2]; adjoint: residual in tap order [nt][2 ns]
 };
 
