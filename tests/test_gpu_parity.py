@@ -280,6 +280,30 @@ def test_large_lds_tiles_do_not_change_results(q):
         assert np.array_equal(N(plan.adjoint(r)), g0)
 
 
+@pytest.mark.parametrize("n", [256, 512])
+def test_storage_tile_heights_bitwise(q, n):
+    """Spectra are stored in tiles of max(rows per row tile, 4) rows: row
+    blocks of two rows write and read half of every tile, blocks of four or
+    eight rows whole tiles, and the column passes read runs of four or eight
+    rows.  Forward and adjoint results do not depend on it, for a batch of
+    four and for one vector (about one block per CU)."""
+    nt = 30
+    prm, c0, rho0, _ = problem(n, n, nt, ns=32)
+    plan = q.Plan(prm, c0, rho0)
+    x = T(np.stack([qi.smooth_noise(n, n, 3.0, 90 + b) for b in range(4)]))
+    r = T(qi.gaussian_field((4, nt, 32), 91))
+    ref = None
+    for shape in [(2, 1, 512, 512), (4, 1, 512, 256), (8, 2, 512, 256), (2, 2, 256, 512), (8, 1, 512, 128)]:
+        plan.set_tiles(*shape)
+        assert plan.tiles() == shape
+        out = (N(plan.forward(x)), N(plan.adjoint(r)), N(plan.forward(x[1])), N(plan.adjoint(r[2])))
+        if ref is None:
+            ref = out
+            assert np.array_equal(out[2], out[0][1]) and np.array_equal(out[3], out[1][2])
+        else:
+            assert all(np.array_equal(a, b) for a, b in zip(out, ref)), shape
+
+
 def test_graph_mode_replays_match(q):
     """Captured hipGraph replays equal direct launches bit for bit, on every
     replay, with eager work and synchronisation in between."""
