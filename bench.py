@@ -108,16 +108,19 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def pmc_traffic(pass_name: str):
-    """HBM traffic per launch from the committed rocprofv3 counter summary, if it
-    was taken with the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "fwdadj512_pmc_traffic.json")
+def pmc_traffic(pass_name: str, record: str = "fwdadj512_pmc_traffic.json", tiles=None):
+    """HBM traffic per launch from a committed rocprofv3 counter summary, if it
+    was taken with the current kernel source (and, where the record names its
+    launch shape, with the same rows and columns per tile); else None."""
+    path = os.path.join(ROOT, "profiles", record)
     try:
         with open(path) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
     if rec.get("kernel_hash") != kernel_hash():
+        return None
+    if tiles is not None and rec.get("tiles") is not None and list(rec["tiles"])[:2] != list(tiles)[:2]:
         return None
     if pass_name in ("fwd_col_fraclap", "adj_col_fraclap"):
         pass_name = "col_fraclap"      # one kernel serves both
@@ -363,7 +366,9 @@ def main():
                           "grid_point_steps_per_s_batched": round(pts / t_batch, 1),
                           "tiles_plain": list(tiles_1), "tiles_batched": list(tiles_b),
                           "passes": bpass,
-                          "roofline": dict(broof, iterate_pair_GB_s=round(bavg, 1),
+                          "roofline": dict(broof, traffic=pmc_traffic(broof["kernel"], "gn1024x8_pmc_traffic.json",
+                                                                      tiles_b),
+                                           iterate_pair_GB_s=round(bavg, 1),
                                            iterate_pair_frac=round(bavg / HBM_PEAK_GBS, 4))}
         del gplan, vs
         torch.cuda.empty_cache()

@@ -92,7 +92,7 @@ def stats_table(path: str) -> str:
     return "\n".join(lines)
 
 
-def pmc_summary(dfetch, dwrite, dcf, dcw, copy_mib, out):
+def pmc_summary(dfetch, dwrite, dcf, dcw, copy_mib, out, tiles=""):
     fetch, write = read_counters(dfetch, "FETCH_SIZE"), read_counters(dwrite, "WRITE_SIZE")
     cf, cw = read_counters(dcf, "FETCH_SIZE"), read_counters(dcw, "WRITE_SIZE")
 
@@ -131,6 +131,8 @@ def pmc_summary(dfetch, dwrite, dcf, dcw, copy_mib, out):
            "note": "HBM-side bytes per launch = FETCH_SIZE*scale_fetch + WRITE_SIZE*scale_write (KiB -> B); "
                    "scales make a plain copy of known size read and write exactly its size",
            "per_pass": per}
+    if tiles:
+        rec["tiles"] = [int(v) for v in tiles.split(",")]
     with open(out, "w") as fh:
         json.dump(rec, fh, indent=1)
     print(json.dumps(rec, indent=1))
@@ -188,6 +190,7 @@ def main(argv=None):
     p.add_argument("copy_write")
     p.add_argument("--copy-mib", type=int, default=256)
     p.add_argument("--out", required=True)
+    p.add_argument("--tiles", default="", help="launch shape the counters were taken with (recorded)")
     t = sub.add_parser("passes")
     t.add_argument("--cfg", default="gn1024")
     t.add_argument("--batch", type=int, default=8)
@@ -206,7 +209,7 @@ def main(argv=None):
     elif a.cmd == "table":
         print(counter_table(a.dirs))
     else:
-        pmc_summary(a.fetch, a.write, a.copy_fetch, a.copy_write, a.copy_mib, a.out)
+        pmc_summary(a.fetch, a.write, a.copy_fetch, a.copy_write, a.copy_mib, a.out, a.tiles)
 
 
 if __name__ == "__main__":
